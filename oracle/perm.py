@@ -1,0 +1,252 @@
+"""Permutation matrix P0 in the free-WP lattice basis (Appendix; Sec. II.B.3, eq. perm).
+
+Oracle: test-only.
+
+(i) THE RULE (what the product library must reproduce). The Appendix reduces eq. perm, after
+the p and p' integrations against the delta functions and the polar substitution
+q = Q cos(phi), q' = Q sin(phi) with the analytic Q integration, to
+
+  [P0]^{gg'}_{ij,i'j'} = sum_{l1,l1',k} g^{l1 l1' k}_{gg'} / sqrt(d_i dq_j d_i' dq_j')
+        * int_{-1}^{1} dx P_k(x) int_{phi1}^{phi2} dphi F(phi, x)
+          cos(phi)^(a+1) sin(phi)^(b+1) / (zeta1^(l'+1) zeta2^(l+1)),
+
+  zeta1 = sqrt(cos^2 + sin^2/4 + x cos sin),  zeta2 = sqrt(cos^2/4 + sin^2 + x cos sin),
+  phi1 = atan(q'_{j'-1} / q_j),  phi2 = atan(q'_{j'} / q_{j-1}),
+  F = 1/2 U^2 - 1/2 L^2 with U = min(q_j/cos, q'_{j'}/sin, p'_{i'}/zeta1, p_i/zeta2),
+                          L = max(q_{j-1}/cos, q'_{j'-1}/sin, p'_{i'-1}/zeta1, p_{i-1}/zeta2),
+
+evaluated with an n_x-point Gauss-Legendre rule in x on [-1, 1] and an n_phi-point rule on
+[phi1, phi2]. Readings: F is taken as 0 where U <= L (the printed difference would be negative
+on an empty Q range) and written 0.5 (U - L)(U + L); (a, b) = (l1 + l1', l2 + l2') (pinned by
+the m-scheme evaluation of G in ``mscheme``); atan of x/0 is pi/2.
+
+(ii) SEMI-ANALYTIC (s-wave, l = l' = 0): the 3D (q, q', x) form before the polar substitution
+with x traded for pi1 (dx = 2 pi1 dpi1 / (q q'), pi2^2 = pi1^2 + 3/4 (q'^2 - q^2)); the inner
+integral is 2 ln(pi1 + pi2) on one exact pi1 interval and the (q, q') box is done adaptively.
+
+(iii) BRUTE FORCE: midpoint sums of the 3D theta form on tiny lattices.
+
+Layout used by the oracle: a lattice row/column index is (j, i) -> j * M + i.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from numpy.polynomial import legendre as _leg
+from scipy import integrate
+
+from .recoupling import exponents
+
+
+# --------------------------------------------------------------------------- nodes per box
+
+def box_nodes(q_edges, j, jp, n_x, n_phi):
+    """Quadrature nodes of the (x, phi) rule for the q-box (j, j'), 0-based bins."""
+    qa, qb = q_edges[j], q_edges[j + 1]        # q_{j-1}, q_j
+    qpa, qpb = q_edges[jp], q_edges[jp + 1]    # q'_{j'-1}, q'_{j'}
+    phi1 = np.arctan2(qpa, qb)
+    phi2 = np.arctan2(qpb, qa)
+    xg, xw = _leg.leggauss(n_x)
+    tg, tw = _leg.leggauss(n_phi)
+    phi = 0.5 * (phi1 + phi2) + 0.5 * (phi2 - phi1) * tg
+    wphi = 0.5 * (phi2 - phi1) * tw
+    X = np.repeat(xg, n_phi)
+    PHI = np.tile(phi, n_x)
+    W = np.repeat(xw, n_phi) * np.tile(wphi, n_x)
+    c, s = np.cos(PHI), np.sin(PHI)
+    z1 = np.sqrt(c * c + 0.25 * s * s + X * c * s)
+    z2 = np.sqrt(0.25 * c * c + s * s + X * c * s)
+    Q1 = np.maximum(qa / c, qpa / s)
+    Q2 = np.minimum(qb / c, qpb / s)
+    return dict(x=X, c=c, s=s, z1=z1, z2=z2, Q1=Q1, Q2=Q2, w=W)
+
+
+def moment_weight(nodes, key):
+    """Node weight of moment key = (k, a, b, l, l'): w P_k(x) c^(a+1) s^(b+1) / (z1^(l'+1) z2^(l+1))."""
+    k, a, b, l, lp = key
+    Pk = _leg.legval(nodes["x"], [0.0] * k + [1.0])
+    return (nodes["w"] * Pk * nodes["c"] ** (a + 1) * nodes["s"] ** (b + 1)
+            / (nodes["z1"] ** (lp + 1) * nodes["z2"] ** (l + 1)))
+
+
+def F_values(p_edges, nodes, ii, iip):
+    """F at every node for the cell pairs (i, i') given as index arrays -> (npairs, nnodes)."""
+    z1 = nodes["z1"][None, :]
+    z2 = nodes["z2"][None, :]
+    U = np.minimum(np.minimum(nodes["Q2"][None, :], p_edges[iip + 1][:, None] / z1),
+                   p_edges[ii + 1][:, None] / z2)
+    L = np.maximum(np.maximum(nodes["Q1"][None, :], p_edges[iip][:, None] / z1),
+                   p_edges[ii][:, None] / z2)
+    return np.where(U > L, 0.5 * (U - L) * (U + L), 0.0)
+
+
+def candidate_pairs(p_edges, nodes):
+    """All (i, i') for which some node has F > 0 (widened by one bin each side).
+
+    For one node and row i, F > 0 needs A < B with A = max(Q1, p_{i-1}/z2), B = min(Q2, p_i/z2)
+    and p'_{i'-1} < B z1, p'_{i'} > A z1: a contiguous i' range. The union over nodes is
+    covered by its hull.
+    """
+    M = len(p_edges) - 1
+    pa, pb = p_edges[:-1], p_edges[1:]
+    A = np.maximum(nodes["Q1"][None, :], pa[:, None] / nodes["z2"][None, :])
+    B = np.minimum(nodes["Q2"][None, :], pb[:, None] / nodes["z2"][None, :])
+    ok = A < B
+    lo = np.searchsorted(p_edges, (A * nodes["z1"][None, :]).ravel(), side="right").reshape(A.shape) - 1
+    hi = np.searchsorted(p_edges, (B * nodes["z1"][None, :]).ravel(), side="left").reshape(B.shape) - 1
+    lo = np.where(ok, lo, M + 10)
+    hi = np.where(ok, hi, -10)
+    lo_i = np.clip(lo.min(axis=1) - 1, 0, M - 1)
+    hi_i = np.clip(hi.max(axis=1) + 1, 0, M - 1)
+    ii, iip = [], []
+    for i in range(M):
+        if hi.max(axis=1)[i] < 0:
+            continue
+        r = np.arange(lo_i[i], hi_i[i] + 1)
+        ii.append(np.full(len(r), i))
+        iip.append(r)
+    if not ii:
+        return np.zeros(0, int), np.zeros(0, int)
+    return np.concatenate(ii), np.concatenate(iip)
+
+
+# --------------------------------------------------------------------------- channel terms
+
+def channel_terms(chans, gtabs):
+    """Distinct moment keys and the coefficient array C[g, g', m] (g summed over terms)."""
+    keys = []
+    index = {}
+    n = len(chans)
+    entries = []
+    for a, ca in enumerate(chans):
+        for b, cb in enumerate(chans):
+            for (l1, l1p, k), gv in gtabs[(a, b)].items():
+                ea, eb = exponents(ca, cb, l1, l1p)
+                key = (k, ea, eb, ca[0], cb[0])
+                if key not in index:
+                    index[key] = len(keys)
+                    keys.append(key)
+                entries.append((a, b, index[key], gv))
+    C = np.zeros((n, n, len(keys)))
+    for a, b, m, gv in entries:
+        C[a, b, m] += gv
+    return keys, C
+
+
+# --------------------------------------------------------------------------- P0 build
+
+class P0Lattice:
+    """Geometric P0 data: for every q-box, the stored cell pairs and their moment integrals."""
+
+    def __init__(self, p_edges, q_edges, keys, n_x=8, n_phi=8, exhaustive=False):
+        self.p_edges = np.asarray(p_edges, float)
+        self.q_edges = np.asarray(q_edges, float)
+        self.M = len(p_edges) - 1
+        self.N = len(q_edges) - 1
+        self.keys = list(keys)
+        self.n_x, self.n_phi = n_x, n_phi
+        dp = np.diff(self.p_edges)
+        dq = np.diff(self.q_edges)
+        rows, cols, moms = [], [], []
+        M, N = self.M, self.N
+        for j in range(N):
+            for jp in range(N):
+                nodes = box_nodes(self.q_edges, j, jp, n_x, n_phi)
+                if exhaustive:
+                    ii, iip = np.meshgrid(np.arange(M), np.arange(M), indexing="ij")
+                    ii, iip = ii.ravel(), iip.ravel()
+                else:
+                    ii, iip = candidate_pairs(self.p_edges, nodes)
+                if len(ii) == 0:
+                    continue
+                F = F_values(self.p_edges, nodes, ii, iip)
+                Wm = np.stack([moment_weight(nodes, key) for key in self.keys], axis=1)
+                mom = F @ Wm
+                norm = 1.0 / np.sqrt(dp[ii] * dq[j] * dp[iip] * dq[jp])
+                mom *= norm[:, None]
+                keep = np.any(mom != 0.0, axis=1)
+                rows.append(j * M + ii[keep])
+                cols.append(jp * M + iip[keep])
+                moms.append(mom[keep])
+        self.rows = np.concatenate(rows) if rows else np.zeros(0, int)
+        self.cols = np.concatenate(cols) if cols else np.zeros(0, int)
+        self.moms = np.concatenate(moms) if moms else np.zeros((0, len(keys)))
+        order = np.lexsort((self.cols, self.rows))
+        self.rows, self.cols, self.moms = self.rows[order], self.cols[order], self.moms[order]
+
+    @property
+    def geo_nnz(self):
+        return len(self.rows)
+
+    def channel_block(self, C, a, b):
+        """Sparse (M N x M N) block P0^{ab} = sum_m C[a, b, m] moment_m, exact zeros dropped."""
+        v = self.moms @ C[a, b]
+        keep = v != 0.0
+        D = self.M * self.N
+        return sp.csr_matrix((v[keep], (self.rows[keep], self.cols[keep])), shape=(D, D))
+
+    def full(self, C):
+        """Full P0 in the channel-major layout (g, j, i) -> (g N + j) M + i."""
+        n = C.shape[0]
+        blocks = [[self.channel_block(C, a, b) for b in range(n)] for a in range(n)]
+        return sp.bmat(blocks, format="csr")
+
+
+def element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi):
+    """One moment integral of one cell pair by the rule (for sampled checks at full size)."""
+    nodes = box_nodes(np.asarray(q_edges, float), j, jp, n_x, n_phi)
+    F = F_values(np.asarray(p_edges, float), nodes, np.array([i]), np.array([ip]))[0]
+    dp = np.diff(p_edges)
+    dq = np.diff(q_edges)
+    return float(F @ moment_weight(nodes, key)) / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
+
+
+# --------------------------------------------------------------------------- pins (s-wave)
+
+def element_semianalytic_s(p_edges, q_edges, i, j, ip, jp, epsabs=1e-13, epsrel=1e-11):
+    """Exact s-wave moment (l = l' = k = 0) of one cell pair, adaptive 2D integration.
+
+    int_{Dq_j} dq int_{Dq_j'} dq' int dx q q' / (pi1 pi2) theta(pi1 in D_i') theta(pi2 in D_i)
+    with x -> pi1: inner = 2 [ln(pi1 + pi2)] over
+    [|q - q'/2|, q + q'/2] cap [p'_{i'-1}, p'_{i'}] cap {pi1^2 in [p_{i-1}^2 - c, p_i^2 - c]},
+    c = 3/4 (q'^2 - q^2).
+    """
+    pa, pb = p_edges[i], p_edges[i + 1]
+    ppa, ppb = p_edges[ip], p_edges[ip + 1]
+
+    def inner(qp, q):
+        c = 0.75 * (qp * qp - q * q)
+        lo = max(abs(q - 0.5 * qp), ppa, np.sqrt(max(0.0, pa * pa - c)))
+        if pb * pb - c <= 0.0:
+            return 0.0
+        hi = min(q + 0.5 * qp, ppb, np.sqrt(pb * pb - c))
+        if hi <= lo:
+            return 0.0
+        f = lambda r: np.log(r + np.sqrt(max(0.0, r * r + c)))
+        return 2.0 * (f(hi) - f(lo))
+
+    qa, qb = q_edges[j], q_edges[j + 1]
+    qpa, qpb = q_edges[jp], q_edges[jp + 1]
+    val, _ = integrate.dblquad(inner, qa, qb, qpa, qpb, epsabs=epsabs, epsrel=epsrel)
+    dp = np.diff(p_edges)
+    dq = np.diff(q_edges)
+    return val / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
+
+
+def element_bruteforce_s(p_edges, q_edges, i, j, ip, jp, n):
+    """Midpoint sum with n^3 points of the 3D (q, q', x) theta form, s-wave."""
+    qa, qb = q_edges[j], q_edges[j + 1]
+    qpa, qpb = q_edges[jp], q_edges[jp + 1]
+    t = (np.arange(n) + 0.5) / n
+    q = qa + (qb - qa) * t
+    qp = qpa + (qpb - qpa) * t
+    x = -1.0 + 2.0 * t
+    Q, QP, X = np.meshgrid(q, qp, x, indexing="ij")
+    pi1 = np.sqrt(Q * Q + 0.25 * QP * QP + Q * QP * X)
+    pi2 = np.sqrt(0.25 * Q * Q + QP * QP + Q * QP * X)
+    th = ((pi1 > p_edges[ip]) & (pi1 <= p_edges[ip + 1]) & (pi2 > p_edges[i]) & (pi2 <= p_edges[i + 1]))
+    f = np.where(th, Q * QP / (pi1 * pi2), 0.0)
+    vol = (qb - qa) * (qpb - qpa) * 2.0 / n ** 3
+    dp = np.diff(p_edges)
+    dq = np.diff(q_edges)
+    return f.sum() * vol / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])

@@ -1,0 +1,37 @@
+"""Two-body pseudostates: h1 = h0 + v1 diagonalised in the free WP basis (eq. exp_z).
+
+Oracle: test-only.
+
+  * eigenpairs of diag(e) + v (numpy.linalg.eigh), ascending energies eps_k;
+  * O has the eigenvectors as ROWS: |z_k> ~ sum_i O_ki |p_i>;
+  * negative energies are bound states; continuum pseudostates carry the momenta
+    p*_k = sqrt(eps_k / H2M).
+
+Scattering-WP bins Delta_k (the paper never states how they are built): momentum bins with
+edges p^_0 = 0, p^_k = (p*_k + p*_{k+1})/2 between neighbours and p^_K = 2 p*_K - p^_{K-1} at
+the top, widths d*_k. The amplitude is independent of the partition as the basis grows
+(Sec. III.B, after eq. dg1b).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lattice import H2M, h0_diagonal
+
+
+def diagonalize(edges, v, h2m=H2M):
+    eps, vec = np.linalg.eigh(np.diag(h0_diagonal(edges, h2m)) + v)
+    return eps, vec.T.copy()
+
+
+def scattering_bins(eps_cont, h2m=H2M):
+    """Edges of the momentum bins around the continuum pseudostates (ascending eps > 0)."""
+    if np.any(eps_cont <= 0):
+        raise ValueError("continuum pseudostate with non-positive energy")
+    ps = np.sqrt(eps_cont / h2m)
+    K = len(ps)
+    e = np.empty(K + 1)
+    e[0] = 0.0
+    e[1:K] = 0.5 * (ps[:-1] + ps[1:])
+    e[K] = 2.0 * ps[-1] - e[K - 1]
+    return e

@@ -1,0 +1,94 @@
+"""Diagonal channel resolvent G1(E) in the three-body SWP basis (Sec. III.B, eqs. dg1, dg1a, dg1b).
+
+Oracle: test-only. Unit momentum weights (the same weights as the P0 Appendix and the
+amplitude formula; the paper's closed formulas quoted in a footnote are for energy weights):
+
+  bound-continuum  G_0j = (1/dq_j) int_{Dq_j} dq / (E + i0 - eps0 - b3 q^2),
+  continuum        G_kj = (1/(d*_k dq_j)) int_{Delta_k} dp int_{Dq_j} dq / (E + i0 - h p^2 - b3 q^2),
+
+h = H2M, b3 = (3/4) H2M.
+
+G_0j: with E - eps0 = b3 q0^2 the q integral is elementary,
+  PV -> (1/(2 b3 q0)) [ln|(q0 + q)/(q0 - q)|],  imaginary part -i pi / (2 b3 q0) if q0 in bin j.
+G_kj: the p integral is done in closed form for fixed q (log or arctangent), the q integral by
+adaptive quadrature with breakpoints at the singular points; for E > 0 the imaginary part is
+-(pi / (d*_k dq_j)) (1 / (2 sqrt(h b3))) times the polar angle of the energy ellipse inside the
+rectangle (p = sqrt(E/h) cos t, q = sqrt(E/b3) sin t).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import integrate
+
+from .lattice import H2M
+
+
+def bound_continuum(q_edges, E, eps0, h2m=H2M):
+    b3 = 0.75 * h2m
+    q0 = np.sqrt((E - eps0) / b3)
+    qa, qb = q_edges[:-1], q_edges[1:]
+    f = lambda q: np.log(np.abs((q0 + q) / (q0 - q)))
+    re = (f(qb) - f(qa)) / (2.0 * b3 * q0)
+    im = np.where((q0 > qa) & (q0 <= qb), -np.pi / (2.0 * b3 * q0), 0.0)
+    d = qb - qa
+    return (re + 1j * im) / d
+
+
+def _inner_p(q, pa, pb, E, h, b3):
+    """PV int_{pa}^{pb} dp / (E - b3 q^2 - h p^2)."""
+    c2 = E - b3 * q * q
+    sh = np.sqrt(h)
+    if c2 > 0.0:
+        c = np.sqrt(c2)
+        g = lambda p: np.log(abs((c + sh * p) / (c - sh * p))) if p != c / sh else np.inf
+        return (g(pb) - g(pa)) / (2.0 * c * sh)
+    if c2 < 0.0:
+        k = np.sqrt(-c2)
+        return -(np.arctan(sh * pb / k) - np.arctan(sh * pa / k)) / (sh * k)
+    return 1.0 / (h * pb) - (1.0 / (h * pa) if pa > 0 else np.inf)
+
+
+def _arc_inside(pa, pb, qa, qb, E, h, b3):
+    """Polar angle t in [0, pi/2] with (sqrt(E/h) cos t, sqrt(E/b3) sin t) inside the box."""
+    if E <= 0.0:
+        return 0.0
+    P, Q = np.sqrt(E / h), np.sqrt(E / b3)
+    # p in [pa, pb] <=> cos t in [pa/P, pb/P]; q in [qa, qb] <=> sin t in [qa/Q, qb/Q]
+    lo_p = np.arccos(min(1.0, pb / P))
+    hi_p = np.arccos(min(1.0, pa / P))
+    lo_q = np.arcsin(min(1.0, qa / Q))
+    hi_q = np.arcsin(min(1.0, qb / Q))
+    return max(0.0, min(hi_p, hi_q) - max(lo_p, lo_q))
+
+
+def continuum_element(pa, pb, qa, qb, E, h2m=H2M, epsabs=1e-15, epsrel=1e-13):
+    h = h2m
+    b3 = 0.75 * h2m
+    pts = []
+    for c2 in (E, E - h * pa * pa, E - h * pb * pb):
+        if c2 > 0:
+            qs = np.sqrt(c2 / b3)
+            if qa < qs < qb:
+                pts.append(qs)
+    f = lambda q: _inner_p(q, pa, pb, E, h, b3)
+    re, _ = integrate.quad(f, qa, qb, points=sorted(pts) or None, epsabs=epsabs, epsrel=epsrel, limit=400)
+    im = -np.pi / (2.0 * np.sqrt(h * b3)) * _arc_inside(pa, pb, qa, qb, E, h, b3)
+    return (re + 1j * im) / ((pb - pa) * (qb - qa))
+
+
+def channel_diagonal(q_edges, E, eps_bound, cont_bins, h2m=H2M):
+    """G1 over (k, j) for one pair channel: bound rows first (if any), then continuum bins.
+
+    eps_bound: list of bound-state energies of this pair channel (the deuteron in 3S1).
+    cont_bins: momentum edges of the continuum pseudostate bins.
+    Returns complex array (K, N).
+    """
+    N = len(q_edges) - 1
+    rows = []
+    for eb in eps_bound:
+        rows.append(bound_continuum(q_edges, E, eb, h2m))
+    for k in range(len(cont_bins) - 1):
+        pa, pb = cont_bins[k], cont_bins[k + 1]
+        rows.append(np.array([continuum_element(pa, pb, q_edges[j], q_edges[j + 1], E, h2m)
+                              for j in range(N)]))
+    return np.array(rows)
