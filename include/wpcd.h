@@ -1,0 +1,225 @@
+/*
+ * wpcd.h - C ABI of libwpcd: the wave-packet continuum discretisation (WPCD) hot path for the
+ * three-nucleon Faddeev equation on one AMD MI355X (gfx950) GPU.
+ *
+ * Method: Pomerantsev, Kukulin, Rubtsova, "New general approach in few-body scattering
+ * calculations: Solving discretized Faddeev equations on a graphics processing unit".
+ * The calls follow the five-step scheme of its Sec. V.A:
+ *   (1) lattice, two-body pseudostates, recoupling coefficients   wp_lattice_build,
+ *                                                                 twobody_pseudostates
+ *   (2)+(3) selection and evaluation of the nonzero P0 elements     perm_matrix_build
+ *   (4) channel resolvent G1(E) and (5) iteration + Pade            faddeev_solve
+ *   on-shell amplitude (Sec. II.B.4)                                amplitude
+ * plus a continuous-batching step API (faddeev_batch_*) for serving many energies against
+ * one resident P0.
+ *
+ * Conventions for every call:
+ *   - returns wp_status (WP_OK = 0); never aborts, never throws across the ABI; on failure
+ *     wp_last_error() returns a thread-local message describing it;
+ *   - handles are created by the library and released by the caller with the matching *_free;
+ *   - input arrays are copied (the caller keeps ownership); output arrays are caller-allocated
+ *     host memory whose sizes come from the documented query;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream); calls on one handle
+ *     are not thread-safe, different handles may be used concurrently on different streams;
+ *   - device memory comes from the allocator given to wp_lattice_build (NULL = hipMalloc);
+ *     P0 and the per-lattice tables stay resident until wp_lattice_free;
+ *   - call order on a lattice: wp_lattice_build -> twobody_pseudostates ->
+ *     perm_matrix_build -> faddeev_solve / faddeev_batch_*; anything else is WP_ENOTREADY;
+ *   - units: momenta fm^-1, energies MeV; E_lab is the neutron lab energy on a deuteron at
+ *     rest, the three-body energy is E = eps0 + (2/3) E_lab.
+ */
+#ifndef WPCD_H
+#define WPCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int wp_status;
+enum {
+  WP_OK = 0,
+  WP_EINVAL = 1,      /* invalid argument (sizes, ranges, NULL where not allowed) */
+  WP_ENOMEM = 2,      /* host or device allocation failed */
+  WP_EDEVICE = 3,     /* a HIP runtime call or kernel launch failed */
+  WP_ENOTREADY = 4,   /* call made out of order on this handle */
+  WP_ENOCONV = 5,     /* iteration / Pade summation did not reach the accepted accuracy */
+  WP_EBUDGET = 6,     /* request does not fit the device-memory budget of a batch */
+  WP_EINTERNAL = 7
+};
+
+/* Message of the last failure on the calling thread ("" if none). Valid until the next call. */
+const char* wp_last_error(void);
+
+/* Optional device allocator (e.g. backed by a framework's caching allocator). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);   /* returns device memory or NULL */
+  void (*release)(void* ptr, void* ctx);
+  void* ctx;
+} wp_allocator;
+
+typedef struct wp_lattice wp_lattice;
+typedef struct wp_solution wp_solution;
+typedef struct wp_batch wp_batch;
+
+/*
+ * Lattice of free wave packets (Sec. II.B.1, eqs. pq and xij): M bins D_i in the pair
+ * momentum p and N bins in the spectator momentum q, unit momentum weights (Appendix:
+ * <p,q|p_i q_j> = theta(p in D_i) theta(q in D_j) / (p q sqrt(d_i d_j))), times the jj-coupled
+ * three-body channels gamma = (l, s, j, lam, I) of one block Gamma = (J, pi, T) (eq. qnum).
+ *   grid_kind 0: tangent map p_i = alpha tan(i atan(p_max/alpha)/M) (same for q with q_max);
+ *   grid_kind 1: explicit edges p_edges[M+1], q_edges[N+1], [0] = 0, strictly increasing.
+ * Channels: l + s + t odd, T = 1/2 (two_T must be 1), (-1)^(l+lam) = parity, j <= j_max;
+ * swave_only keeps l = lam = 0. Canonical order: sorted by (j, l, s, lam, 2I).
+ * n_x, n_phi: Gauss-Legendre points of the (x, phi) rule of the P0 elements, 1..32 each.
+ * Limits: 2 <= M, N <= 1024; at most 32 channels.
+ */
+typedef struct {
+  int M, N;
+  int grid_kind;
+  double alpha, p_max, q_max;
+  const double* p_edges;
+  const double* q_edges;
+  int two_J, parity, two_T, j_max, swave_only;
+  int n_x, n_phi;
+  double hbar2_over_m; /* hbar^2 / m_N in MeV fm^2, e.g. 41.471 */
+} wp_lattice_desc;
+
+wp_status wp_lattice_build(const wp_lattice_desc* desc, const wp_allocator* alloc, wp_lattice** out);
+
+/* Channel table: *n_ch always set; if table != NULL it receives n_ch rows of
+ * (l, s, j, lam, 2I, t) as int[6]. */
+wp_status wp_lattice_channels(const wp_lattice* lat, int* n_ch, int* table);
+
+/* Lattice edges (host copies): p_edges[M+1], q_edges[N+1]; either may be NULL. */
+wp_status wp_lattice_edges(const wp_lattice* lat, double* p_edges, double* q_edges);
+
+/*
+ * Step-1 results for one channel's pair wave (after twobody_pseudostates): number of bound
+ * states, pseudostate energies eps[M] (ascending), O[M*M] (row k = eigenvector k in the free WP
+ * basis, eq. exp_z) and the continuum bin edges bins[M - n_bound + 1]. Pointers may be NULL.
+ */
+wp_status wp_lattice_pseudostates(const wp_lattice* lat, int channel, int* n_bound, double* eps, double* O,
+                                  double* bins);
+
+/*
+ * Step-4 result: the diagonal of G1(E) (eqs. dg1a, dg1b) for one channel at E = eps0 + (2/3) E_lab,
+ * G[2*(k*N + j) + {0,1}] = re/im of G_kj, k = pseudostate (bound states first), j = q bin;
+ * G holds 2*M*N doubles. Host FP64 only (no device work).
+ */
+wp_status wp_lattice_resolvent(const wp_lattice* lat, double E_lab, int channel, double* G);
+
+void wp_lattice_free(wp_lattice* lat);
+
+/*
+ * Two-body input and pseudostates (Sec. II.B.2, eq. exp_z): the NN potential v1 in the free
+ * WP basis, h1 = h0 + v1 diagonalised for every pair wave (l, s) present, O with the
+ * eigenvectors as rows, continuum pseudostate bins around p*_k = sqrt(eps_k / (hbar^2/m)) with
+ * edges 0, midpoints between neighbours, and a mirrored last edge.
+ *   kind 0: separable Yamaguchi v = -lambda g(p) g(p'), g = 1/(p^2 + beta^2), 3S1 only;
+ *   kind 1: Malfliet-Tjon form V_R e^{-mu_R r}/r - V_A e^{-mu_A r}/r in every pair wave,
+ *           singlet (s = 0) waves with V_A * singlet_ratio.
+ * tune != 0: lambda (kind 0) or V_A (kind 1) is tuned so the lowest 3S1 eigenvalue equals
+ * -target_BE. Exactly one bound state (in 3S1) is required; otherwise WP_EINVAL.
+ * Outputs (may be NULL): eps0 (deuteron energy), strength (the tuned lambda or V_A).
+ */
+typedef struct {
+  int kind;
+  double beta, lambda;
+  double V_R, mu_R, V_A, mu_A, singlet_ratio;
+  double target_BE;
+  int tune;
+} wp_potential_desc;
+
+wp_status twobody_pseudostates(wp_lattice* lat, const wp_potential_desc* pot, double* eps0,
+                               double* strength);
+
+/*
+ * Permutation matrix P0 in the lattice basis (Sec. II.B.3, eq. perm; Appendix, final
+ * formula): steps 2 (selection of the nonzero cell pairs) and 3 (their (x, phi) Gauss
+ * quadrature with the analytic Q integral F) of Sec. V.A, on the GPU. The result stays
+ * resident as block-CSR: block rows and columns are lattice cells r = j*M + i (q bin j, p bin i),
+ * each stored block holds the n_ch x n_ch channel values (row-major in (gamma, gamma')).
+ * Values are computed in FP64 and stored in FP64 (WP_P_FP64) or rounded to FP32 (WP_P_FP32).
+ * Blocks whose values are all exactly zero are omitted. Energy independent: build once.
+ * stats (may be NULL): blocks = stored cell pairs, nnz = stored scalar entries (blocks times
+ * channel pairs with a nonzero coefficient), candidates = selected cell pairs before
+ * compaction, bytes = device bytes of the stored matrix, device_ms = GPU time of the build.
+ */
+enum { WP_P_FP64 = 0, WP_P_FP32 = 1 };
+typedef struct {
+  int64_t nnz, blocks, candidates;
+  int64_t bytes;
+  double device_ms;
+} wp_perm_stats;
+
+wp_status perm_matrix_build(wp_lattice* lat, int precision, void* stream, wp_perm_stats* stats);
+
+/* Host copy of the resident P0: row_ptr[N*M + 1] (block offsets), col[blocks], val[blocks *
+ * n_ch * n_ch] (FP32 storage is widened). Any pointer may be NULL to skip it. */
+wp_status perm_matrix_export(const wp_lattice* lat, int64_t* row_ptr, int32_t* col, double* val);
+
+/*
+ * Elastic transition operator (Sec. II.A, eq. Ueq; Sec. II.B.4, eq. m_pvg) for each E_lab:
+ * G1(E) diagonal in the SWP basis (eqs. dg1a, dg1b; FP64, host), the factorised kernel
+ * K = P0 (v O^T) G1 O applied by the GPU, Neumann iteration of y = b + K y with
+ * b = P0 (v O^T) e0, and the on-shell series a_n = e0^T O y_n summed with Wynn's epsilon
+ * algorithm in FP64. One solve per (energy, open channel), all energies of a call batched.
+ *   mode WP_SOLVE_FP64:  P0 as built, blocks and vectors FP64.
+ *   mode WP_SOLVE_MIXED: P0 rounded to FP32 (a second resident copy), v1/O blocks in BF16 on
+ *                        MFMA with FP32 accumulation, vectors FP32; outer FP64 residual
+ *                        refinement every refine_every terms (see faddeev_solve in the
+ *                        library for the scheme).
+ * tol: relative stop tolerance of the Pade estimates (e.g. 1e-12); accept: accepted relative
+ * error estimate when the estimates reach a rounding plateau (e.g. 1e-7); max_iter: terms per
+ * solve (<= 1000). Returns WP_ENOCONV (solution still returned) if any solve was not accepted.
+ */
+enum { WP_SOLVE_FP64 = 0, WP_SOLVE_MIXED = 1 };
+typedef struct {
+  int mode;
+  double tol;
+  double accept;
+  int max_iter;
+  int refine_every;
+} wp_solve_opts;
+
+wp_status faddeev_solve(wp_lattice* lat, int n_E, const double* E_lab, const wp_solve_opts* opts,
+                        void* stream, wp_solution** out);
+
+/*
+ * On-shell amplitude of energy e_idx (Sec. II.B.4): A_ab = (2/(3 (hbar^2/m) q0)) U_ab / dq_j0
+ * over the n_open open deuteron channels (j0: the q bin (q_{j-1}, q_j] holding q0),
+ * S = 1 - 2 pi i A, delta = arg(S_aa)/2 in degrees, eta = |S_aa|.
+ * A and S: n_open^2 complex numbers, row-major, re/im interleaved (2 n_open^2 doubles);
+ * delta_deg, eta, err_est: n_open doubles (err_est = relative error estimate of U).
+ * Call with A == NULL first to query n_open (<= 4). Pointers other than n_open may be NULL.
+ * Also reports iterations used (n_iter, may be NULL).
+ */
+wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, double* A, double* S,
+                    double* delta_deg, double* eta, double* err_est, int* n_iter);
+
+void wp_solution_free(wp_solution* sol);
+
+/*
+ * Continuous batching (serving): up to max_slots energies of one lattice share every kernel
+ * launch of a step. faddeev_batch_admit takes a free slot (or WP_EBUDGET when none is free or
+ * the slot's vectors would exceed hbm_budget bytes); faddeev_batch_step advances every live
+ * slot by `terms` Neumann terms (one batched launch sequence) and reports the slots whose
+ * Pade estimate was accepted; faddeev_batch_take moves a finished slot's result out and frees
+ * the slot. Each slot's arithmetic is independent of the other slots (column-wise kernels,
+ * fixed reduction order), so a result does not depend on its batch-mates.
+ */
+wp_status faddeev_batch_create(wp_lattice* lat, int max_slots, size_t hbm_budget,
+                               const wp_solve_opts* opts, wp_batch** out);
+wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot);
+wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, int* n_done, int* done_slots);
+wp_status faddeev_batch_take(wp_batch* b, int slot, wp_solution** out);
+wp_status faddeev_batch_live(const wp_batch* b, int* n_live);
+void faddeev_batch_free(wp_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WPCD_H */

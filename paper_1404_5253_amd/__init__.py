@@ -1,0 +1,291 @@
+"""Python binding of libwpcd (include/wpcd.h): argument marshalling only.
+
+Every step of the hot path runs inside the library (host FP64 C++ and gfx950 HIP kernels).
+PyTorch provides device memory (a caching-allocator-backed ``wp_allocator``) and streams
+(``torch.cuda.current_stream()``). If ``libwpcd.so`` is missing this module raises on import:
+there is no fallback.
+
+The module-level functions carry the names of the C entry points:
+``wp_lattice_build``, ``twobody_pseudostates``, ``perm_matrix_build``, ``perm_matrix_export``,
+``faddeev_solve``, ``amplitude`` and the ``faddeev_batch_*`` step API. ``Lattice`` wraps them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwpcd.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "or `python paper_1404_5253_amd/build.py`")
+_lib = C.CDLL(LIB_PATH)
+
+WP_OK, WP_EINVAL, WP_ENOMEM, WP_EDEVICE, WP_ENOTREADY, WP_ENOCONV, WP_EBUDGET, WP_EINTERNAL = range(8)
+WP_P_FP64, WP_P_FP32 = 0, 1
+WP_SOLVE_FP64, WP_SOLVE_MIXED = 0, 1
+H2M = 41.471
+
+
+class WpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"wpcd status {status}: {msg}")
+        self.status = status
+
+
+class _Alloc(C.Structure):
+    _fields_ = [("alloc", C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)),
+                ("release", C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)),
+                ("ctx", C.c_void_p)]
+
+
+class _LatDesc(C.Structure):
+    _fields_ = [("M", C.c_int), ("N", C.c_int), ("grid_kind", C.c_int),
+                ("alpha", C.c_double), ("p_max", C.c_double), ("q_max", C.c_double),
+                ("p_edges", C.POINTER(C.c_double)), ("q_edges", C.POINTER(C.c_double)),
+                ("two_J", C.c_int), ("parity", C.c_int), ("two_T", C.c_int), ("j_max", C.c_int),
+                ("swave_only", C.c_int), ("n_x", C.c_int), ("n_phi", C.c_int),
+                ("hbar2_over_m", C.c_double)]
+
+
+class _PotDesc(C.Structure):
+    _fields_ = [("kind", C.c_int), ("beta", C.c_double), ("lambda_", C.c_double),
+                ("V_R", C.c_double), ("mu_R", C.c_double), ("V_A", C.c_double), ("mu_A", C.c_double),
+                ("singlet_ratio", C.c_double), ("target_BE", C.c_double), ("tune", C.c_int)]
+
+
+class _PermStats(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("blocks", C.c_int64), ("candidates", C.c_int64),
+                ("bytes", C.c_int64), ("device_ms", C.c_double)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("accept", C.c_double),
+                ("max_iter", C.c_int), ("refine_every", C.c_int)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int)
+
+_SIGS = {
+    "wp_last_error": (C.c_char_p, []),
+    "wp_lattice_build": (C.c_int, [C.POINTER(_LatDesc), C.POINTER(_Alloc), C.POINTER(_P)]),
+    "wp_lattice_channels": (C.c_int, [_P, _I, _I]),
+    "wp_lattice_edges": (C.c_int, [_P, _D, _D]),
+    "wp_lattice_pseudostates": (C.c_int, [_P, C.c_int, _I, _D, _D, _D]),
+    "wp_lattice_resolvent": (C.c_int, [_P, C.c_double, C.c_int, _D]),
+    "wp_lattice_free": (None, [_P]),
+    "twobody_pseudostates": (C.c_int, [_P, C.POINTER(_PotDesc), _D, _D]),
+    "perm_matrix_build": (C.c_int, [_P, C.c_int, _P, C.POINTER(_PermStats)]),
+    "perm_matrix_export": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _D]),
+    "faddeev_solve": (C.c_int, [_P, C.c_int, _D, C.POINTER(_SolveOpts), _P, C.POINTER(_P)]),
+    "amplitude": (C.c_int, [_P, C.c_int, _I, _D, _D, _D, _D, _D, _I]),
+    "wp_solution_free": (None, [_P]),
+    "faddeev_batch_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_SolveOpts), C.POINTER(_P)]),
+    "faddeev_batch_admit": (C.c_int, [_P, C.c_double, _I]),
+    "faddeev_batch_step": (C.c_int, [_P, _P, C.c_int, _I, _I]),
+    "faddeev_batch_take": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
+    "faddeev_batch_live": (C.c_int, [_P, _I]),
+    "faddeev_batch_free": (None, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(st):
+    if st != WP_OK:
+        raise WpError(st, _lib.wp_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def exported_symbols():
+    """Names of the C entry points this binding resolves (all must exist in the library)."""
+    return sorted(_SIGS)
+
+
+# ---------------------------------------------------------------- torch plumbing
+
+class TorchAllocator:
+    """wp_allocator backed by torch's caching allocator (device memory stays torch-owned)."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self._a = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)(self._alloc)
+        self._r = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)(self._release)
+        self.struct = _Alloc(self._a, self._r, None)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _release(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+
+def current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- C entry points
+
+def wp_lattice_build(M, N, two_J=1, parity=1, j_max=1, swave_only=True, n_x=8, n_phi=8, alpha=1.0,
+                     p_max=10.0, q_max=10.0, hbar2_over_m=H2M, p_edges=None, q_edges=None, allocator=None):
+    pe = None if p_edges is None else np.ascontiguousarray(p_edges, dtype=np.float64)
+    qe = None if q_edges is None else np.ascontiguousarray(q_edges, dtype=np.float64)
+    d = _LatDesc(M, N, 1 if pe is not None else 0, alpha, p_max, q_max, _dptr(pe), _dptr(qe),
+                 two_J, parity, 1, j_max, 1 if swave_only else 0, n_x, n_phi, hbar2_over_m)
+    h = _P()
+    _check(_lib.wp_lattice_build(C.byref(d), C.byref(allocator.struct) if allocator else None, C.byref(h)))
+    return h
+
+
+def twobody_pseudostates(lat, kind="mt", beta=1.394, lam=0.0, V_R=1438.72, mu_R=3.11, V_A=0.0, mu_A=1.55,
+                         singlet_ratio=0.82, target_BE=2.2246, tune=True):
+    k = {"yamaguchi": 0, "mt": 1}[kind]
+    p = _PotDesc(k, beta, lam, V_R, mu_R, V_A, mu_A, singlet_ratio, target_BE, 1 if tune else 0)
+    eps0, strength = C.c_double(), C.c_double()
+    _check(_lib.twobody_pseudostates(lat, C.byref(p), C.byref(eps0), C.byref(strength)))
+    return eps0.value, strength.value
+
+
+def perm_matrix_build(lat, precision=WP_P_FP64, stream=None):
+    st = _PermStats()
+    _check(_lib.perm_matrix_build(lat, precision, stream, C.byref(st)))
+    return dict(nnz=st.nnz, blocks=st.blocks, candidates=st.candidates, bytes=st.bytes, device_ms=st.device_ms)
+
+
+def faddeev_solve(lat, E_lab, mode=WP_SOLVE_FP64, tol=1e-12, accept=1e-7, max_iter=200, refine_every=0,
+                  stream=None, allow_noconv=False):
+    E = np.ascontiguousarray(np.atleast_1d(E_lab), dtype=np.float64)
+    o = _SolveOpts(mode, tol, accept, max_iter, refine_every)
+    h = _P()
+    st = _lib.faddeev_solve(lat, len(E), _dptr(E), C.byref(o), stream, C.byref(h))
+    if st == WP_ENOCONV and allow_noconv and h.value:
+        return h, False
+    _check(st)
+    return h, True
+
+
+def amplitude(sol, e_idx):
+    n = C.c_int()
+    _check(_lib.amplitude(sol, e_idx, C.byref(n), None, None, None, None, None, None))
+    n = n.value
+    A = np.zeros(2 * n * n)
+    S = np.zeros(2 * n * n)
+    dl, et, er = np.zeros(n), np.zeros(n), np.zeros(n)
+    it = (C.c_int * n)()
+    nn = C.c_int()
+    _check(_lib.amplitude(sol, e_idx, C.byref(nn), _dptr(A), _dptr(S), _dptr(dl), _dptr(et), _dptr(er), it))
+    return dict(A=(A[0::2] + 1j * A[1::2]).reshape(n, n), S=(S[0::2] + 1j * S[1::2]).reshape(n, n),
+                delta=dl, eta=et, err=er, iters=np.array(list(it)))
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Solution:
+    def __init__(self, handle, n_E, converged=True):
+        self.h = handle
+        self.n_E = n_E
+        self.converged = converged
+
+    def amplitude(self, e_idx=0):
+        return amplitude(self.h, e_idx)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.wp_solution_free(self.h)
+            self.h = None
+
+
+class Lattice:
+    """One lattice: channels, pseudostates, resident P0 (device memory from torch)."""
+
+    def __init__(self, M, N, two_J=1, parity=1, j_max=1, swave_only=True, n_x=8, n_phi=8, alpha=1.0,
+                 p_max=10.0, q_max=10.0, hbar2_over_m=H2M, p_edges=None, q_edges=None, torch_alloc=True):
+        self.alloc = None
+        if torch_alloc:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    self.alloc = TorchAllocator()
+            except Exception:
+                self.alloc = None
+        self.M, self.N = M, N
+        self.h = wp_lattice_build(M, N, two_J, parity, j_max, swave_only, n_x, n_phi, alpha, p_max, q_max,
+                                  hbar2_over_m, p_edges, q_edges, self.alloc)
+        n = C.c_int()
+        _check(_lib.wp_lattice_channels(self.h, C.byref(n), None))
+        tab = (C.c_int * (6 * n.value))()
+        _check(_lib.wp_lattice_channels(self.h, C.byref(n), tab))
+        self.channels = [tuple(tab[6 * a: 6 * a + 6]) for a in range(n.value)]
+        self.nch = n.value
+        self.perm_stats = None
+
+    def edges(self):
+        pe, qe = np.zeros(self.M + 1), np.zeros(self.N + 1)
+        _check(_lib.wp_lattice_edges(self.h, _dptr(pe), _dptr(qe)))
+        return pe, qe
+
+    def pseudostates(self, **kw):
+        self.eps0, self.strength = twobody_pseudostates(self.h, **kw)
+        return self.eps0, self.strength
+
+    def pseudostate_data(self, channel):
+        nb = C.c_int()
+        eps = np.zeros(self.M)
+        O = np.zeros(self.M * self.M)
+        _check(_lib.wp_lattice_pseudostates(self.h, channel, C.byref(nb), _dptr(eps), _dptr(O), None))
+        bins = np.zeros(self.M - nb.value + 1)
+        _check(_lib.wp_lattice_pseudostates(self.h, channel, None, None, None, _dptr(bins)))
+        return nb.value, eps, O.reshape(self.M, self.M), bins
+
+    def resolvent(self, E_lab, channel):
+        G = np.zeros(2 * self.M * self.N)
+        _check(_lib.wp_lattice_resolvent(self.h, E_lab, channel, _dptr(G)))
+        return (G[0::2] + 1j * G[1::2]).reshape(self.M, self.N)
+
+    def build_perm(self, precision="fp64", stream=None):
+        p = {"fp64": WP_P_FP64, "fp32": WP_P_FP32}[precision]
+        self.perm_stats = perm_matrix_build(self.h, p, stream if stream is not None else current_stream())
+        return self.perm_stats
+
+    def export_perm(self):
+        st = self.perm_stats
+        R = self.M * self.N
+        rp = np.zeros(R + 1, dtype=np.int64)
+        col = np.zeros(max(st["blocks"], 1), dtype=np.int32)
+        val = np.zeros(max(st["blocks"], 1) * self.nch * self.nch)
+        _check(_lib.perm_matrix_export(self.h, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       col.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(val)))
+        nb = st["blocks"]
+        return rp, col[:nb], val[:nb * self.nch * self.nch].reshape(nb, self.nch, self.nch)
+
+    def solve(self, E_lab, mode="fp64", tol=1e-12, accept=1e-7, max_iter=200, refine_every=0, stream=None,
+              allow_noconv=False):
+        m = {"fp64": WP_SOLVE_FP64, "mixed": WP_SOLVE_MIXED}[mode]
+        E = np.atleast_1d(E_lab)
+        h, ok = faddeev_solve(self.h, E, m, tol, accept, max_iter, refine_every,
+                              stream if stream is not None else current_stream(), allow_noconv)
+        return Solution(h, len(E), ok)
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _lib.wp_lattice_free(self.h)
+            self.h = None

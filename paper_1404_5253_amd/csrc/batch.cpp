@@ -1,0 +1,218 @@
+// Continuous batching of faddeev solves against one resident P0 (serving).
+//
+// A batch owns max_slots energy slots; slot s uses the columns s*n_open .. s*n_open + n_open - 1
+// of the solve vectors (one column per open initial channel). Admission computes the slot's G1
+// on the host (FP64), uploads it into the slot's columns and builds the slot's right-hand side
+// b = P0 (v O^T) e0 with column-range kernels, so live slots are not disturbed. A step advances
+// every column by `terms` Neumann terms with the same launches as faddeev_solve. The kernels
+// are column-wise with a fixed reduction order, so a slot's numbers do not depend on which
+// other slots are live. Finished or free slots get G1 = 0, which keeps their vectors at zero.
+#include <algorithm>
+#include <memory>
+
+#include "wpcd_objects.h"
+
+struct wp_batch {
+  wp_lattice* L = nullptr;
+  wp_solve_opts o{};
+  int slots = 0, nfin = 0, B = 0, max_terms = 0;
+  int64_t D = 0;
+  DBuf<double2> dG, dy, dt, ds, dacap;
+  DBuf<int> dj0, dg0, dfin;
+  std::vector<int> j0, g0;
+  struct Slot {
+    bool live = false, done = false;
+    EnergyResult r;
+    std::vector<ColState> cs;
+  };
+  std::vector<Slot> s;
+  std::vector<double2> hcap;
+};
+
+extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t hbm_budget, const wp_solve_opts* o,
+                                          wp_batch** out) {
+  if (!L || !o || !out || max_slots < 1) return fail(WP_EINVAL, "faddeev_batch_create: bad argument");
+  *out = nullptr;
+  if (!L->pseudo || !L->have_P) return fail(WP_ENOTREADY, "lattice needs pseudostates and P0");
+  if (o->mode != WP_SOLVE_FP64) return fail(WP_EINVAL, "batches run the FP64 path");
+  if (!L->d_val64.p) return fail(WP_ENOTREADY, "batch needs P0 built with WP_P_FP64");
+  if (o->tol <= 0 || o->accept <= 0 || o->max_iter < 4) return fail(WP_EINVAL, "bad solve options");
+  if (wp_status st = upload_waves(L)) return st;
+  std::unique_ptr<wp_batch> b(new wp_batch());
+  b->L = L;
+  b->o = *o;
+  b->nfin = (int)L->opens.size();
+  b->D = (int64_t)L->M * L->N * L->nch;
+  b->max_terms = 64;
+  const size_t per_slot = (size_t)b->nfin * (4 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
+  int cap = (int)std::min<size_t>((size_t)max_slots, hbm_budget / std::max<size_t>(per_slot, 1));
+  if (cap < 1) return fail(WP_EBUDGET, "hbm_budget smaller than one slot");
+  b->slots = cap;
+  b->B = cap * b->nfin;
+  const int B = b->B;
+  DevAlloc* al = &L->al;
+  if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
+      !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
+      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin))
+    return fail(WP_ENOMEM, "device allocation (batch)");
+  for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
+  b->j0.assign(B, 0);
+  b->g0.assign(B, 0);
+  for (int c = 0; c < B; ++c) b->g0[c] = L->opens[c % b->nfin];
+  HIPCHECK(hipMemcpy(b->dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(b->dg0.p, b->g0.data(), B * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(b->dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(hipDeviceSynchronize());
+  b->s.resize(cap);
+  b->hcap.resize((size_t)b->max_terms * B * b->nfin);
+  *out = b.release();
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_batch_live(const wp_batch* b, int* n) {
+  if (!b || !n) return fail(WP_EINVAL, "NULL argument");
+  int c = 0;
+  for (auto& s : b->s) c += s.live;
+  *n = c;
+  return WP_OK;
+}
+
+// Set G1 of a slot's columns (host values, or zeros when gw is null) on stream st.
+static wp_status put_slot_g1(wp_batch* b, int slot, const std::vector<std::vector<cplx>>* gw, hipStream_t st) {
+  const wp_lattice* L = b->L;
+  const int M = L->M, N = L->N, nch = L->nch, nf = b->nfin, B = b->B;
+  std::vector<double2> h((size_t)b->D * nf);
+  for (int j = 0; j < N; ++j)
+    for (int k = 0; k < M; ++k)
+      for (int g = 0; g < nch; ++g) {
+        double2 v = make_double2(0.0, 0.0);
+        if (gw) {
+          cplx z = (*gw)[L->wave_of[g]][(size_t)k * N + j];
+          v = make_double2(z.real(), z.imag());
+        }
+        for (int f = 0; f < nf; ++f) h[(((size_t)j * M + k) * nch + g) * nf + f] = v;
+      }
+  // rows of the [D][B] array, the slot's nf consecutive columns
+  HIPCHECK(hipStreamSynchronize(st));
+  HIPCHECK(hipMemcpy2D(b->dG.p + (size_t)slot * nf, B * sizeof(double2), h.data(), nf * sizeof(double2),
+                       nf * sizeof(double2), b->D, hipMemcpyHostToDevice));
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
+  if (!b || !slot) return fail(WP_EINVAL, "NULL argument");
+  if (!(E_lab > 0)) return fail(WP_EINVAL, "E_lab must be positive");
+  int sl = -1;
+  for (int k = 0; k < b->slots; ++k)
+    if (!b->s[k].live) {
+      sl = k;
+      break;
+    }
+  if (sl < 0) return fail(WP_EBUDGET, "no free slot within the batch's device-memory budget");
+  wp_lattice* L = b->L;
+  auto& S = b->s[sl];
+  S = wp_batch::Slot();
+  if (!kinematics(L, E_lab, S.r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
+  std::vector<std::vector<cplx>> gw(L->waves.size());
+  try {
+    for (size_t w = 0; w < L->waves.size(); ++w) g1_wave(L, L->waves[w], S.r.E, gw[w]);
+  } catch (const std::exception& e) {
+    return fail(WP_EINTERNAL, e.what());
+  }
+  const int nf = b->nfin, c0 = sl * nf;
+  hipStream_t st = nullptr;
+  if (wp_status e = put_slot_g1(b, sl, &gw, st)) return e;
+  for (int f = 0; f < nf; ++f) b->j0[c0 + f] = S.r.j0;
+  HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, b->B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
+                             c0 + nf));
+  HIPCHECK(launch_spmv64((int64_t)L->M * L->N, L->nch, b->B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
+                         b->dy.p, st, c0, c0 + nf));
+  HIPCHECK(hipStreamSynchronize(st));
+  S.cs.resize(nf);
+  for (auto& c : S.cs) {
+    c.w.resize(nf);
+    c.S.assign(nf, cplx(0, 0));
+  }
+  S.live = true;
+  *slot = sl;
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, int* n_done, int* done_slots) {
+  if (!b || !n_done) return fail(WP_EINVAL, "NULL argument");
+  if (terms < 1 || terms > b->max_terms) return fail(WP_EINVAL, "terms must be in [1, 64]");
+  hipStream_t st = (hipStream_t)stream;
+  wp_lattice* L = b->L;
+  const int M = L->M, N = L->N, nch = L->nch, B = b->B, nf = b->nfin;
+  *n_done = 0;
+  bool any = false;
+  for (auto& s : b->s) any |= (s.live && !s.done);
+  if (!any) return WP_OK;
+  for (int t = 0; t < terms; ++t) {
+    RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
+    HIPCHECK(launch_rot64(ro, b->dy.p, b->dt.p, st));
+    RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, b->dj0.p, b->dfin.p, nf, 0};
+    HIPCHECK(launch_rot64(rw, b->dt.p, b->ds.p, st));
+    HIPCHECK(launch_spmv64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
+  }
+  HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
+                          st));
+  HIPCHECK(hipStreamSynchronize(st));
+  for (int sl = 0; sl < b->slots; ++sl) {
+    auto& S = b->s[sl];
+    if (!S.live || S.done) continue;
+    bool all = true;
+    for (int f0 = 0; f0 < nf; ++f0) {
+      ColState& cs = S.cs[f0];
+      const int c = sl * nf + f0;
+      for (int t = 0; t < terms && !cs.done; ++t) {
+        if (cs.n >= b->o.max_iter) {
+          cs.done = true;
+          cs.ok = cs.best_r <= b->o.accept;
+          cs.err = cs.best_r;
+          break;
+        }
+        std::vector<cplx> a(nf);
+        for (int f = 0; f < nf; ++f) {
+          double2 v = b->hcap[((size_t)t * B + c) * nf + f];
+          a[f] = cplx(v.x, v.y);
+        }
+        column_push(cs, a.data(), nf, b->o.tol, b->o.accept);
+      }
+      all &= cs.done;
+    }
+    if (all) {
+      S.done = true;
+      for (int f0 = 0; f0 < nf; ++f0) {
+        ColState& cs = S.cs[f0];
+        const std::vector<cplx>& est = cs.best.empty() ? cs.last : cs.best;
+        for (int f = 0; f < nf; ++f) S.r.U[f * nf + f0] = est[f];
+        S.r.err[f0] = cs.err;
+        S.r.iters[f0] = cs.n;
+        S.r.ok &= cs.ok;
+      }
+      if (wp_status e = put_slot_g1(b, sl, nullptr, st)) return e;
+      if (done_slots) done_slots[*n_done] = sl;
+      ++*n_done;
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(st));
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_batch_take(wp_batch* b, int slot, wp_solution** out) {
+  if (!b || !out || slot < 0 || slot >= b->slots) return fail(WP_EINVAL, "bad argument");
+  *out = nullptr;
+  auto& S = b->s[slot];
+  if (!S.live || !S.done) return fail(WP_ENOTREADY, "slot has no finished result");
+  std::unique_ptr<wp_solution> sol(new wp_solution());
+  sol->h2m = b->L->h2m;
+  sol->res.push_back(S.r);
+  const bool ok = S.r.ok;
+  S = wp_batch::Slot();
+  *out = sol.release();
+  return ok ? WP_OK : fail(WP_ENOCONV, "slot's Pade summation was not accepted (result still returned)");
+}
+
+extern "C" void faddeev_batch_free(wp_batch* b) { delete b; }

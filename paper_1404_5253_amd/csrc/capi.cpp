@@ -1,0 +1,636 @@
+// C ABI of libwpcd (include/wpcd.h): handles, call order, device memory and the host side of
+// the hot path (P0 build orchestration and the iteration / Pade loop).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <thread>
+#include <tuple>
+
+#include "wpcd_objects.h"
+
+using namespace wpcd;
+
+static thread_local std::string g_err;
+
+wp_status wpcd::fail(wp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+
+extern "C" const char* wp_last_error(void) { return g_err.c_str(); }
+
+void* DevAlloc::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (custom) return a.alloc(bytes, a.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+void DevAlloc::release(void* p) {
+  if (!p) return;
+  if (custom)
+    a.release(p, a.ctx);
+  else
+    (void)hipFree(p);
+}
+
+// ------------------------------------------------------------------ lattice
+
+extern "C" wp_status wp_lattice_build(const wp_lattice_desc* d, const wp_allocator* alloc, wp_lattice** out) {
+  if (!d || !out) return fail(WP_EINVAL, "wp_lattice_build: NULL argument");
+  *out = nullptr;
+  if (d->M < 2 || d->M > 1024 || d->N < 2 || d->N > 1024) return fail(WP_EINVAL, "M, N must be in [2, 1024]");
+  if (d->two_T != 1) return fail(WP_EINVAL, "only T = 1/2 (two_T = 1) is supported");
+  if (d->n_x < 1 || d->n_x > 16 || d->n_phi < 1 || d->n_phi > 16)
+    return fail(WP_EINVAL, "n_x, n_phi must be in [1, 16]");
+  if (d->hbar2_over_m <= 0) return fail(WP_EINVAL, "hbar2_over_m must be positive");
+  if (d->two_J < 1 || d->two_J % 2 == 0) return fail(WP_EINVAL, "two_J must be odd and positive");
+  std::unique_ptr<wp_lattice> L(new (std::nothrow) wp_lattice());
+  if (!L) return fail(WP_ENOMEM, "host allocation");
+  if (alloc) {
+    if (!alloc->alloc || !alloc->release) return fail(WP_EINVAL, "allocator needs alloc and release");
+    L->al.a = *alloc;
+    L->al.custom = true;
+  }
+  L->M = d->M;
+  L->N = d->N;
+  L->two_J = d->two_J;
+  L->n_x = d->n_x;
+  L->n_phi = d->n_phi;
+  L->h2m = d->hbar2_over_m;
+  if (d->grid_kind == 0) {
+    if (d->alpha <= 0 || d->p_max <= 0 || d->q_max <= 0) return fail(WP_EINVAL, "alpha, p_max, q_max must be > 0");
+    L->pe = tangent_edges(d->M, d->alpha, d->p_max);
+    L->qe = tangent_edges(d->N, d->alpha, d->q_max);
+  } else if (d->grid_kind == 1) {
+    if (!d->p_edges || !d->q_edges) return fail(WP_EINVAL, "explicit grid needs p_edges and q_edges");
+    L->pe.assign(d->p_edges, d->p_edges + d->M + 1);
+    L->qe.assign(d->q_edges, d->q_edges + d->N + 1);
+    for (auto* e : {&L->pe, &L->qe}) {
+      if ((*e)[0] != 0.0) return fail(WP_EINVAL, "edges must start at 0");
+      for (size_t i = 1; i < e->size(); ++i)
+        if (!((*e)[i] > (*e)[i - 1])) return fail(WP_EINVAL, "edges must be strictly increasing");
+    }
+  } else {
+    return fail(WP_EINVAL, "grid_kind must be 0 or 1");
+  }
+  L->ch = enumerate_channels(d->two_J, d->parity >= 0 ? 1 : -1, d->j_max, d->swave_only != 0);
+  L->nch = (int)L->ch.size();
+  if (L->nch < 1 || L->nch > 32) return fail(WP_EINVAL, "channel count must be in [1, 32]");
+  // coefficient table C[g][g'][m] over distinct moments (k, a, b, l, l'), exponents a = l1 + l1'
+  // (powers of q) and b = l2 + l2' (powers of q')
+  std::map<std::tuple<int, int, int, int, int>, int> kidx;
+  std::vector<std::tuple<int, int, int, double>> ent;
+  for (int a = 0; a < L->nch; ++a)
+    for (int b = 0; b < L->nch; ++b)
+      for (const GTerm& t : g_table(L->ch[a], L->ch[b], d->two_J)) {
+        auto key = std::make_tuple(t.k, t.l1 + t.l1p, (L->ch[a].l - t.l1) + (L->ch[b].l - t.l1p), L->ch[a].l, L->ch[b].l);
+        auto it = kidx.find(key);
+        int m;
+        if (it == kidx.end()) {
+          m = (int)L->keys.size();
+          kidx[key] = m;
+          L->keys.push_back({std::get<0>(key), std::get<1>(key), std::get<2>(key), std::get<3>(key), std::get<4>(key)});
+        } else {
+          m = it->second;
+        }
+        ent.emplace_back(a, b, m, t.g);
+      }
+  int nm = std::max<int>(1, (int)L->keys.size());
+  if (L->keys.empty()) L->keys.push_back({0, 0, 0, 0, 0});
+  L->C.assign((size_t)L->nch * L->nch * nm, 0.0);
+  for (auto& e : ent) L->C[((size_t)std::get<0>(e) * L->nch + std::get<1>(e)) * nm + std::get<2>(e)] += std::get<3>(e);
+  for (int p = 0; p < L->nch * L->nch; ++p) {
+    bool nz = false;
+    for (int m = 0; m < nm; ++m) nz |= L->C[(size_t)p * nm + m] != 0.0;
+    L->nz_pairs += nz;
+  }
+  *out = L.release();
+  return WP_OK;
+}
+
+extern "C" wp_status wp_lattice_channels(const wp_lattice* L, int* n_ch, int* table) {
+  if (!L || !n_ch) return fail(WP_EINVAL, "NULL argument");
+  *n_ch = L->nch;
+  if (table)
+    for (int a = 0; a < L->nch; ++a) {
+      const Chan& c = L->ch[a];
+      int* r = table + 6 * a;
+      r[0] = c.l; r[1] = c.s; r[2] = c.j; r[3] = c.lam; r[4] = c.two_I; r[5] = c.t;
+    }
+  return WP_OK;
+}
+
+extern "C" wp_status wp_lattice_edges(const wp_lattice* L, double* p, double* q) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (p) std::copy(L->pe.begin(), L->pe.end(), p);
+  if (q) std::copy(L->qe.begin(), L->qe.end(), q);
+  return WP_OK;
+}
+
+extern "C" void wp_lattice_free(wp_lattice* L) { delete L; }
+
+// ------------------------------------------------------------------ pseudostates
+
+static double ground_energy(const std::vector<double>& h0, const std::vector<double>& v, int M) {
+  std::vector<double> A(v);
+  for (int i = 0; i < M; ++i) A[(size_t)i * M + i] += h0[i];
+  std::vector<double> d;
+  sym_eigen(M, A, d, nullptr);
+  return d[0];
+}
+
+static std::vector<double> wave_potential(const wp_lattice* L, const wp_potential_desc* p, int l, int s, double strength) {
+  const int M = L->M;
+  std::vector<double> v((size_t)M * M, 0.0);
+  if (p->kind == 0) {
+    if (l == 0 && s == 1) {
+      auto G = yamaguchi_form(L->pe, p->beta);
+      for (int i = 0; i < M; ++i)
+        for (int k = 0; k < M; ++k) v[(size_t)i * M + k] = -strength * G[i] * G[k];
+    }
+    return v;
+  }
+  auto YR = yukawa_wp(L->pe, l, p->mu_R);
+  auto YA = yukawa_wp(L->pe, l, p->mu_A);
+  double VA = s == 1 ? strength : p->singlet_ratio * strength;
+  for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];
+  return v;
+}
+
+// root of f on [a, b] (f(a) f(b) < 0) by bisection safeguarded secant (Illinois variant)
+template <class F>
+static double find_root(F f, double a, double b, double tol) {
+  double fa = f(a), fb = f(b);
+  if (fa * fb > 0) throw std::runtime_error("strength tuning: target not bracketed");
+  int side = 0;
+  for (int it = 0; it < 200; ++it) {
+    double c = (a * fb - b * fa) / (fb - fa);
+    if (!(c > std::min(a, b) && c < std::max(a, b))) c = 0.5 * (a + b);
+    double fc = f(c);
+    if (fc == 0.0 || std::fabs(b - a) < tol * std::fabs(c)) return c;
+    if (fc * fb > 0) {
+      b = c;
+      fb = fc;
+      if (side == -1) fa *= 0.5;
+      side = -1;
+    } else {
+      a = c;
+      fa = fc;
+      if (side == +1) fb *= 0.5;
+      side = +1;
+    }
+  }
+  return 0.5 * (a + b);
+}
+
+extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc* p, double* eps0, double* strength) {
+  if (!L || !p) return fail(WP_EINVAL, "NULL argument");
+  if (p->kind != 0 && p->kind != 1) return fail(WP_EINVAL, "potential kind must be 0 (Yamaguchi) or 1 (MT)");
+  try {
+    const int M = L->M;
+    auto h0 = h0_diagonal(L->pe, L->h2m);
+    double str = p->kind == 0 ? p->lambda : p->V_A;
+    if (p->tune) {
+      if (p->target_BE <= 0) return fail(WP_EINVAL, "target_BE must be positive");
+      if (p->kind == 0) {
+        auto G = yamaguchi_form(L->pe, p->beta);
+        auto f = [&](double lam) {
+          std::vector<double> v((size_t)M * M);
+          for (int i = 0; i < M; ++i)
+            for (int k = 0; k < M; ++k) v[(size_t)i * M + k] = -lam * G[i] * G[k];
+          return ground_energy(h0, v, M) + p->target_BE;
+        };
+        str = find_root(f, 1.0, 2000.0, 1e-15);
+      } else {
+        auto YR = yukawa_wp(L->pe, 0, p->mu_R);
+        auto YA = yukawa_wp(L->pe, 0, p->mu_A);
+        auto f = [&](double VA) {
+          std::vector<double> v(YR.size());
+          for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];
+          return ground_energy(h0, v, M) + p->target_BE;
+        };
+        str = find_root(f, 10.0, 5000.0, 1e-15);
+      }
+    }
+    L->waves.clear();
+    L->wave_of.assign(L->nch, -1);
+    int nbound = 0;
+    for (int a = 0; a < L->nch; ++a) {
+      int w = -1;
+      for (size_t k = 0; k < L->waves.size(); ++k)
+        if (L->waves[k].l == L->ch[a].l && L->waves[k].s == L->ch[a].s) w = (int)k;
+      if (w < 0) {
+        PairWave pw;
+        pw.l = L->ch[a].l;
+        pw.s = L->ch[a].s;
+        pw.v = wave_potential(L, p, pw.l, pw.s, str);
+        std::vector<double> A(pw.v);
+        for (int i = 0; i < M; ++i) A[(size_t)i * M + i] += h0[i];
+        sym_eigen(M, A, pw.eps, &pw.O);
+        pw.nb = 0;
+        while (pw.nb < M && pw.eps[pw.nb] < 0.0) ++pw.nb;
+        nbound += pw.nb;
+        // continuum bins: 0, midpoints of neighbouring p*_k, mirrored last edge
+        int K = M - pw.nb;
+        pw.bins.assign(K + 1, 0.0);
+        std::vector<double> ps(K);
+        for (int k = 0; k < K; ++k) ps[k] = std::sqrt(pw.eps[pw.nb + k] / L->h2m);
+        for (int k = 1; k < K; ++k) pw.bins[k] = 0.5 * (ps[k - 1] + ps[k]);
+        pw.bins[K] = 2.0 * ps[K - 1] - pw.bins[K - 1];
+        // W = v O^T
+        pw.W.assign((size_t)M * M, 0.0);
+        for (int i = 0; i < M; ++i)
+          for (int k = 0; k < M; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < M; ++q) s += pw.v[(size_t)i * M + q] * pw.O[(size_t)k * M + q];
+            pw.W[(size_t)i * M + k] = s;
+          }
+        L->waves.push_back(std::move(pw));
+        w = (int)L->waves.size() - 1;
+      }
+      L->wave_of[a] = w;
+    }
+    int deut = -1;
+    for (size_t k = 0; k < L->waves.size(); ++k)
+      if (L->waves[k].l == 0 && L->waves[k].s == 1) deut = (int)k;
+    if (deut < 0 || L->waves[deut].nb != 1 || nbound != 1)
+      return fail(WP_EINVAL, "expected exactly one two-body bound state, in 3S1");
+    L->eps0 = L->waves[deut].eps[0];
+    L->strength = str;
+    L->opens.clear();
+    for (int a = 0; a < L->nch; ++a)
+      if (L->ch[a].l == 0 && L->ch[a].s == 1 && L->ch[a].j == 1) L->opens.push_back(a);
+    if (L->opens.empty() || L->opens.size() > 4) return fail(WP_EINVAL, "1..4 open deuteron channels required");
+    L->d_O.reset();
+    L->d_W.reset();
+    L->d_wave.reset();
+    L->pseudo = true;
+    if (eps0) *eps0 = L->eps0;
+    if (strength) *strength = str;
+  } catch (const std::exception& e) {
+    return fail(WP_EINTERNAL, std::string("twobody_pseudostates: ") + e.what());
+  }
+  return WP_OK;
+}
+
+// device copies of O and W of every pair wave and the channel -> wave map (first GPU use)
+wp_status wpcd::upload_waves(wp_lattice* L) {
+  if (L->d_O.p) return WP_OK;
+  const size_t MM = (size_t)L->M * L->M;
+  std::vector<double> O(MM * L->waves.size()), W(MM * L->waves.size());
+  for (size_t k = 0; k < L->waves.size(); ++k) {
+    std::copy(L->waves[k].O.begin(), L->waves[k].O.end(), O.begin() + k * MM);
+    std::copy(L->waves[k].W.begin(), L->waves[k].W.end(), W.begin() + k * MM);
+  }
+  if (!L->d_O.make(&L->al, O.size()) || !L->d_W.make(&L->al, W.size()) || !L->d_wave.make(&L->al, L->nch))
+    return fail(WP_ENOMEM, "device allocation (pseudostates)");
+  HIPCHECK(hipMemcpy(L->d_O.p, O.data(), O.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_W.p, W.data(), W.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_wave.p, L->wave_of.data(), L->nch * sizeof(int), hipMemcpyHostToDevice));
+  return WP_OK;
+}
+
+extern "C" wp_status wp_lattice_pseudostates(const wp_lattice* L, int channel, int* n_bound, double* eps, double* O,
+                                             double* bins) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (!L->pseudo) return fail(WP_ENOTREADY, "twobody_pseudostates has not run");
+  if (channel < 0 || channel >= L->nch) return fail(WP_EINVAL, "channel out of range");
+  const PairWave& w = L->waves[L->wave_of[channel]];
+  if (n_bound) *n_bound = w.nb;
+  if (eps) std::copy(w.eps.begin(), w.eps.end(), eps);
+  if (O) std::copy(w.O.begin(), w.O.end(), O);
+  if (bins) std::copy(w.bins.begin(), w.bins.end(), bins);
+  return WP_OK;
+}
+
+
+extern "C" wp_status wp_lattice_resolvent(const wp_lattice* L, double E_lab, int channel, double* G) {
+  if (!L || !G) return fail(WP_EINVAL, "NULL argument");
+  if (!L->pseudo) return fail(WP_ENOTREADY, "twobody_pseudostates has not run");
+  if (channel < 0 || channel >= L->nch) return fail(WP_EINVAL, "channel out of range");
+  if (!(E_lab > 0)) return fail(WP_EINVAL, "E_lab must be positive");
+  std::vector<cplx> g;
+  try {
+    g1_wave(L, L->waves[L->wave_of[channel]], L->eps0 + 2.0 * E_lab / 3.0, g);
+  } catch (const std::exception& e) {
+    return fail(WP_EINTERNAL, e.what());
+  }
+  for (size_t e = 0; e < g.size(); ++e) {
+    G[2 * e] = g[e].real();
+    G[2 * e + 1] = g[e].imag();
+  }
+  return WP_OK;
+}
+
+// ------------------------------------------------------------------ P0 build
+
+static wp_status upload_tables(wp_lattice* L) {
+  if (L->d_pe.p) return WP_OK;
+  std::vector<double> gx(L->n_x), gwx(L->n_x), gp(L->n_phi), gwp(L->n_phi);
+  gauss_legendre(L->n_x, gx.data(), gwx.data());
+  gauss_legendre(L->n_phi, gp.data(), gwp.data());
+  std::vector<int> keys;
+  for (auto& k : L->keys) keys.insert(keys.end(), {k.k, k.a, k.b, k.l, k.lp});
+  if (!L->d_pe.make(&L->al, L->pe.size()) || !L->d_qe.make(&L->al, L->qe.size()) ||
+      !L->d_gx.make(&L->al, L->n_x) || !L->d_gwx.make(&L->al, L->n_x) || !L->d_gp.make(&L->al, L->n_phi) ||
+      !L->d_gwp.make(&L->al, L->n_phi) || !L->d_C.make(&L->al, L->C.size()) || !L->d_keys.make(&L->al, keys.size()))
+    return fail(WP_ENOMEM, "device allocation (lattice tables)");
+  HIPCHECK(hipMemcpy(L->d_pe.p, L->pe.data(), L->pe.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_qe.p, L->qe.data(), L->qe.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gx.p, gx.data(), gx.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gwx.p, gwx.data(), gwx.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gp.p, gp.data(), gp.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gwp.p, gwp.data(), gwp.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_C.p, L->C.data(), L->C.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_keys.p, keys.data(), keys.size() * sizeof(int), hipMemcpyHostToDevice));
+  return WP_OK;
+}
+
+extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* stream, wp_perm_stats* stats) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (precision != WP_P_FP64 && precision != WP_P_FP32) return fail(WP_EINVAL, "precision must be FP64 or FP32");
+  if ((int)L->keys.size() > 8) return fail(WP_EINVAL, "more than 8 distinct moments: partial waves beyond this build");
+  hipStream_t s = (hipStream_t)stream;
+  wp_status st = upload_tables(L);
+  if (st) return st;
+  const int M = L->M, N = L->N, nch = L->nch, nc2 = nch * nch;
+  const int64_t R = (int64_t)M * N;
+  PBuildArgs a{M, N, nch, (int)L->keys.size(), L->n_x, L->n_phi, L->d_pe.p, L->d_qe.p, L->d_gx.p,
+               L->d_gwx.p, L->d_gp.p, L->d_gwp.p, L->d_keys.p, L->d_C.p};
+  DBuf<int> cnt, lo, segoff;
+  DBuf<int64_t> rowcnt, rowptr_c, tmp, rowptr;
+  size_t nbox = (size_t)N * N * M;
+  if (!cnt.make(&L->al, nbox) || !lo.make(&L->al, nbox) || !segoff.make(&L->al, nbox) || !rowcnt.make(&L->al, R) ||
+      !rowptr_c.make(&L->al, R + 1) || !tmp.make(&L->al, scan_tmp_size(R)) || !rowptr.make(&L->al, R + 1))
+    return fail(WP_ENOMEM, "device allocation (selection)");
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  HIPCHECK(hipEventRecord(e0, s));
+  HIPCHECK(launch_select(a, cnt.p, lo.p, s));
+  HIPCHECK(launch_rowseg(M, N, cnt.p, segoff.p, rowcnt.p, s));
+  HIPCHECK(launch_scan(rowcnt.p, rowptr_c.p, R, tmp.p, s));
+  int64_t ncand = 0;
+  HIPCHECK(hipMemcpyAsync(&ncand, rowptr_c.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  DBuf<int32_t> col_c;
+  DBuf<double> val_c;
+  DBuf<uint8_t> flag;
+  if (!col_c.make(&L->al, std::max<int64_t>(ncand, 1)) || !val_c.make(&L->al, std::max<int64_t>(ncand, 1) * nc2) ||
+      !flag.make(&L->al, std::max<int64_t>(ncand, 1)))
+    return fail(WP_ENOMEM, "device allocation (candidates)");
+  if (ncand > 0) HIPCHECK(launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
+  if (ncand > 0) {
+    HIPCHECK(launch_rowcount(R, rowptr_c.p, flag.p, rowcnt.p, s));
+  } else {
+    HIPCHECK(hipMemsetAsync(rowcnt.p, 0, R * sizeof(int64_t), s));
+  }
+  HIPCHECK(launch_scan(rowcnt.p, rowptr.p, R, tmp.p, s));
+  int64_t nblk = 0;
+  HIPCHECK(hipMemcpyAsync(&nblk, rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  L->d_col.reset();
+  L->d_val64.reset();
+  L->d_val32.reset();
+  if (!L->d_col.make(&L->al, std::max<int64_t>(nblk, 1))) return fail(WP_ENOMEM, "device allocation (P0 columns)");
+  if (precision == WP_P_FP64) {
+    if (!L->d_val64.make(&L->al, std::max<int64_t>(nblk, 1) * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+  } else {
+    if (!L->d_val32.make(&L->al, std::max<int64_t>(nblk, 1) * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+  }
+  if (ncand > 0)
+    HIPCHECK(launch_compact(R, nch, rowptr_c.p, col_c.p, val_c.p, flag.p, rowptr.p, L->d_col.p, L->d_val64.p,
+                            L->d_val32.p, s));
+  HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::swap(L->d_rowptr.p, rowptr.p);
+  std::swap(L->d_rowptr.n, rowptr.n);
+  L->d_rowptr.al = &L->al;
+  L->blocks = nblk;
+  L->prec = precision;
+  L->have_P = true;
+  L->stats.blocks = nblk;
+  L->stats.nnz = nblk * L->nz_pairs;
+  L->stats.candidates = ncand;
+  L->stats.bytes = (R + 1) * 8 + nblk * 4 + nblk * nc2 * (precision == WP_P_FP64 ? 8 : 4);
+  L->stats.device_ms = ms;
+  if (stats) *stats = L->stats;
+  return WP_OK;
+}
+
+extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, int32_t* col, double* val) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (!L->have_P) return fail(WP_ENOTREADY, "perm_matrix_build has not run");
+  const int64_t R = (int64_t)L->M * L->N;
+  const int nc2 = L->nch * L->nch;
+  if (rowptr) HIPCHECK(hipMemcpy(rowptr, L->d_rowptr.p, (R + 1) * 8, hipMemcpyDeviceToHost));
+  if (col) HIPCHECK(hipMemcpy(col, L->d_col.p, L->blocks * 4, hipMemcpyDeviceToHost));
+  if (val) {
+    if (L->prec == WP_P_FP64) {
+      HIPCHECK(hipMemcpy(val, L->d_val64.p, L->blocks * nc2 * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> f(L->blocks * nc2);
+      HIPCHECK(hipMemcpy(f.data(), L->d_val32.p, f.size() * 4, hipMemcpyDeviceToHost));
+      for (size_t e = 0; e < f.size(); ++e) val[e] = f[e];
+    }
+  }
+  return WP_OK;
+}
+
+// ------------------------------------------------------------------ G1 (host, FP64)
+
+// G1 over (k, j) for pair wave w at energy E: row k = 0 is the bound state (if any).
+void wpcd::g1_wave(const wp_lattice* L, const PairWave& pw, double E, std::vector<cplx>& out) {
+  const int M = L->M, N = L->N;
+  out.assign((size_t)M * N, cplx(0, 0));
+  const int nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto work = [&](int t0) {
+    for (int k = t0; k < M; k += nthreads) {
+      for (int j = 0; j < N; ++j) {
+        cplx g;
+        if (k < pw.nb)
+          g = g1_bound_continuum(L->qe[j], L->qe[j + 1], E, pw.eps[k], L->h2m);
+        else
+          g = g1_continuum(pw.bins[k - pw.nb], pw.bins[k - pw.nb + 1], L->qe[j], L->qe[j + 1], E, L->h2m);
+        out[(size_t)k * N + j] = g;
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);
+  work(0);
+  for (auto& x : th) x.join();
+}
+
+// ------------------------------------------------------------------ solve (FP64 path)
+
+
+static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
+                            wp_solution* sol) {
+  const int M = L->M, N = L->N, nch = L->nch;
+  const int nfin = (int)L->opens.size();
+  const int nE = (int)Elab.size();
+  const int B = nE * nfin;  // columns: (energy, initial channel)
+  const int64_t D = (int64_t)M * N * nch;
+  const int64_t R = (int64_t)M * N;
+  // per-energy kinematics and G1
+  std::vector<int> j0(B), g0(B);
+  std::vector<double2> Gh((size_t)D * B);
+  sol->res.resize(nE);
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    if (!kinematics(L, Elab[e], r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
+    const int jj = r.j0;
+    std::vector<std::vector<cplx>> gw(L->waves.size());
+    for (size_t w = 0; w < L->waves.size(); ++w) g1_wave(L, L->waves[w], r.E, gw[w]);
+    for (int b = 0; b < nfin; ++b) {
+      int c = e * nfin + b;
+      j0[c] = jj;
+      g0[c] = L->opens[b];
+      for (int j = 0; j < N; ++j)
+        for (int k = 0; k < M; ++k)
+          for (int g = 0; g < nch; ++g) {
+            cplx v = gw[L->wave_of[g]][(size_t)k * N + j];
+            Gh[(((size_t)j * M + k) * nch + g) * B + c] = make_double2(v.real(), v.imag());
+          }
+    }
+  }
+  const int max_iter = std::max(4, std::min(1000, o.max_iter));
+  const int chunk = 8;
+  DBuf<double2> dG, dy, dt, ds, dacap;
+  DBuf<int> dj0, dg0, dfin;
+  if (!dG.make(&L->al, D * B) || !dy.make(&L->al, D * B) || !dt.make(&L->al, D * B) || !ds.make(&L->al, D * B) ||
+      !dacap.make(&L->al, (size_t)(max_iter + chunk) * B * nfin) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
+      !dfin.make(&L->al, nfin))
+    return fail(WP_ENOMEM, "device allocation (solve vectors)");
+  HIPCHECK(hipMemcpyAsync(dG.p, Gh.data(), Gh.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
+  const double* val = L->d_val64.p;
+  if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
+  if (wp_status us = upload_waves(L)) return us;
+  HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
+  HIPCHECK(launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+  std::vector<ColState> cs(B);
+  for (auto& c : cs) {
+    c.w.resize(nfin);
+    c.S.assign(nfin, cplx(0, 0));
+  }
+  std::vector<double2> hcap((size_t)chunk * B * nfin);
+  int n = 0;
+  bool all_done = false;
+  while (n < max_iter && !all_done) {
+    int T = std::min(chunk, max_iter - n);
+    for (int t = 0; t < T; ++t) {
+      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin, (int64_t)(n + t) * B * nfin};
+      HIPCHECK(launch_rot64(ro, dy.p, dt.p, s));
+      RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, dj0.p, dfin.p, nfin, 0};
+      HIPCHECK(launch_rot64(rw, dt.p, ds.p, s));
+      HIPCHECK(launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+    }
+    HIPCHECK(hipMemcpyAsync(hcap.data(), dacap.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(double2),
+                            hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    all_done = true;
+    for (int c = 0; c < B; ++c) {
+      for (int t = 0; t < T && !cs[c].done; ++t) {
+        std::vector<cplx> a(nfin);
+        for (int f = 0; f < nfin; ++f) {
+          double2 v = hcap[((size_t)t * B + c) * nfin + f];
+          a[f] = cplx(v.x, v.y);
+        }
+        column_push(cs[c], a.data(), nfin, o.tol, o.accept);
+      }
+      all_done &= cs[c].done;
+    }
+    n += T;
+  }
+  bool allok = true;
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    for (int b = 0; b < nfin; ++b) {
+      ColState& c = cs[e * nfin + b];
+      if (!c.done) {
+        c.ok = c.best_r <= o.accept;
+        c.err = c.best_r;
+      }
+      const std::vector<cplx>& est = c.best.empty() ? c.last : c.best;
+      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = est[f];
+      r.err[b] = c.err;
+      r.iters[b] = c.n;
+      r.ok &= c.ok;
+    }
+    allok &= r.ok;
+  }
+  return allok ? WP_OK : fail(WP_ENOCONV, "Pade summation did not reach the accepted accuracy for some energy");
+}
+
+extern "C" wp_status faddeev_solve(wp_lattice* L, int n_E, const double* E_lab, const wp_solve_opts* opts, void* stream,
+                                   wp_solution** out) {
+  if (!L || !E_lab || !opts || !out || n_E < 1) return fail(WP_EINVAL, "faddeev_solve: bad argument");
+  *out = nullptr;
+  if (!L->pseudo) return fail(WP_ENOTREADY, "twobody_pseudostates has not run");
+  if (!L->have_P) return fail(WP_ENOTREADY, "perm_matrix_build has not run");
+  if (opts->tol <= 0 || opts->accept <= 0 || opts->max_iter < 4) return fail(WP_EINVAL, "bad solve options");
+  for (int e = 0; e < n_E; ++e)
+    if (!(E_lab[e] > 0)) return fail(WP_EINVAL, "E_lab must be positive");
+  std::unique_ptr<wp_solution> sol(new wp_solution());
+  sol->h2m = L->h2m;
+  std::vector<double> E(E_lab, E_lab + n_E);
+  wp_status st;
+  try {
+    if (opts->mode == WP_SOLVE_FP64)
+      st = solve_fp64(L, E, *opts, (hipStream_t)stream, sol.get());
+    else
+      return fail(WP_EINVAL, "unknown solve mode");
+  } catch (const std::exception& e) {
+    return fail(WP_EINTERNAL, std::string("faddeev_solve: ") + e.what());
+  }
+  if (st == WP_OK || st == WP_ENOCONV) *out = sol.release();
+  return st;
+}
+
+extern "C" wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, double* A, double* S, double* delta,
+                               double* eta, double* err, int* n_iter) {
+  if (!sol || !n_open) return fail(WP_EINVAL, "NULL argument");
+  if (e_idx < 0 || e_idx >= (int)sol->res.size()) return fail(WP_EINVAL, "energy index out of range");
+  const EnergyResult& r = sol->res[e_idx];
+  const int n = r.n_open;
+  *n_open = n;
+  if (!A && !S && !delta && !eta && !err && !n_iter) return WP_OK;
+  // A = (2 / (3 h2m q0)) U / dq_j0,  S = 1 - 2 pi i A
+  const double fac = 2.0 / (3.0 * sol->h2m * r.q0) / r.dq0;
+  std::vector<cplx> Am(n * n), Sm(n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      Am[a * n + b] = fac * r.U[a * n + b];
+      Sm[a * n + b] = (a == b ? 1.0 : 0.0) - cplx(0.0, 2.0 * M_PI) * Am[a * n + b];
+    }
+  for (int e = 0; e < n * n; ++e) {
+    if (A) { A[2 * e] = Am[e].real(); A[2 * e + 1] = Am[e].imag(); }
+    if (S) { S[2 * e] = Sm[e].real(); S[2 * e + 1] = Sm[e].imag(); }
+  }
+  for (int a = 0; a < n; ++a) {
+    if (delta) delta[a] = 0.5 * std::arg(Sm[a * n + a]) * 180.0 / M_PI;
+    if (eta) eta[a] = std::abs(Sm[a * n + a]);
+    if (err) err[a] = r.err[a];
+    if (n_iter) n_iter[a] = r.iters[a];
+  }
+  return WP_OK;
+}
+
+extern "C" void wp_solution_free(wp_solution* s) { delete s; }

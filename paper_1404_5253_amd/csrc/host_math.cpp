@@ -1,0 +1,609 @@
+// Host FP64 numerics of the WPCD pipeline: lattice, NN potentials in the WP basis, symmetric
+// eigenproblem, recoupling coefficients and the channel resolvent. These are the "negligible"
+// steps 1 and 4 of the paper's Sec. V.A, kept on the CPU in FP64.
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <queue>
+#include <stdexcept>
+#include <tuple>
+
+#include "wpcd_internal.h"
+
+namespace wpcd {
+
+// ------------------------------------------------------------------ quadrature nodes
+
+void gauss_legendre(int n, double* x, double* w) {
+  // Roots of P_n by Newton's method from the Tricomi-type initial guess; weights
+  // 2 / ((1 - x^2) P_n'(x)^2). Nodes ascending.
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      if (n == 0) break;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pnm1 = (n == 1) ? 1.0 : p0;
+      pp = n * (z * pn - pnm1) / (z * z - 1.0);
+      double dz = pn / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        // one more evaluation of the derivative at the converged root
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        pn = (n == 1) ? z : p1;
+        pnm1 = (n == 1) ? 1.0 : p0;
+        pp = n * (z * pn - pnm1) / (z * z - 1.0);
+        break;
+      }
+    }
+    double wt = 2.0 / ((1.0 - z * z) * pp * pp);
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = wt;
+    w[n - 1 - i] = wt;
+  }
+  if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// ------------------------------------------------------------------ lattice
+
+std::vector<double> tangent_edges(int n, double alpha, double pmax) {
+  // p_i = alpha tan(i theta_max / n), theta_max = atan(pmax / alpha): dense bins near 0.
+  std::vector<double> e(n + 1);
+  double th = std::atan(pmax / alpha);
+  for (int i = 0; i <= n; ++i) e[i] = alpha * std::tan(i * th / n);
+  e[0] = 0.0;
+  e[n] = pmax;
+  return e;
+}
+
+std::vector<double> h0_diagonal(const std::vector<double>& e, double h2m) {
+  // <p_i | h2m p^2 | p_i> for unit-weight packets: (h2m / d_i) int_{D_i} p^2 dp.
+  size_t M = e.size() - 1;
+  std::vector<double> h(M);
+  for (size_t i = 0; i < M; ++i) {
+    double a = e[i], b = e[i + 1];
+    h[i] = h2m * (a * a + a * b + b * b) / 3.0;
+  }
+  return h;
+}
+
+// ------------------------------------------------------------------ potentials
+
+std::vector<double> yamaguchi_form(const std::vector<double>& e, double beta) {
+  // G_i = d_i^{-1/2} int_{D_i} p / (p^2 + beta^2) dp; v_ii' = -lambda G_i G_i'.
+  size_t M = e.size() - 1;
+  std::vector<double> G(M);
+  double b2 = beta * beta;
+  for (size_t i = 0; i < M; ++i) {
+    double a = e[i], b = e[i + 1];
+    G[i] = 0.5 * std::log((b * b + b2) / (a * a + b2)) / std::sqrt(b - a);
+  }
+  return G;
+}
+
+static double legendre_q(int l, double z) {
+  // Q_l(z), z > 1. For z >= 2 the hypergeometric series in 1/z^2; below, upward recurrence
+  // from Q_0 = atanh(1/z), Q_1 = z Q_0 - 1.
+  if (z < 2.0) {
+    double q0 = 0.5 * std::log((z + 1.0) / (z - 1.0));
+    if (l == 0) return q0;
+    double qm = q0, qc = z * q0 - 1.0;
+    for (int n = 1; n < l; ++n) {
+      double qn = ((2.0 * n + 1.0) * z * qc - n * qm) / (n + 1.0);
+      qm = qc;
+      qc = qn;
+    }
+    return qc;
+  }
+  // sqrt(pi) l! / Gamma(l + 3/2) = l! / prod_{m=0}^{l} (m + 1/2)
+  double pref = 1.0;
+  for (int m = 1; m <= l; ++m) pref *= m;
+  for (int m = 0; m <= l; ++m) pref /= (m + 0.5);
+  double x = 1.0 / (z * z);
+  double a = 0.5 * (l + 1), b = 0.5 * (l + 2), c = l + 1.5;
+  double term = 1.0, sum = 1.0;
+  for (int n = 0; n < 200; ++n) {
+    term *= (a + n) * (b + n) / ((c + n) * (n + 1.0)) * x;
+    sum += term;
+    if (std::fabs(term) < 1e-18 * std::fabs(sum)) break;
+  }
+  return pref * sum / std::pow(2.0 * z, l + 1);
+}
+
+std::vector<double> yukawa_wp(const std::vector<double>& e, int l, double mu) {
+  // Unit-strength Yukawa e^{-mu r}/r in partial wave l, free WP basis:
+  // v_ii' = (d_i d_i')^{-1/2} int int p p' v_l(p,p') dp dp',  p p' v_l = Q_l(z) / pi,
+  // z = (p^2 + p'^2 + mu^2) / (2 p p').
+  size_t M = e.size() - 1;
+  std::vector<double> v(M * M);
+  if (l == 0) {
+    // closed form from the second antiderivative of ln(u^2 + mu^2)
+    auto L2 = [mu](double u) {
+      return 0.5 * (u * u - mu * mu) * std::log(u * u + mu * mu) - 1.5 * u * u + 2.0 * mu * u * std::atan(u / mu);
+    };
+    for (size_t i = 0; i < M; ++i)
+      for (size_t k = 0; k < M; ++k) {
+        double A = e[i], B = e[i + 1], C = e[k], D = e[k + 1];
+        double plus = L2(B + D) - L2(B + C) - L2(A + D) + L2(A + C);
+        double minus = L2(B - C) - L2(B - D) - L2(A - C) + L2(A - D);
+        v[i * M + k] = (plus - minus) / (2.0 * M_PI) / std::sqrt((B - A) * (D - C));
+      }
+    return v;
+  }
+  const int ng = 32;
+  double gx[ng], gw[ng];
+  gauss_legendre(ng, gx, gw);
+  std::vector<double> P(M * ng), W(M * ng);
+  for (size_t i = 0; i < M; ++i) {
+    double h = 0.5 * (e[i + 1] - e[i]), m = 0.5 * (e[i + 1] + e[i]);
+    for (int a = 0; a < ng; ++a) {
+      P[i * ng + a] = m + h * gx[a];
+      W[i * ng + a] = h * gw[a];
+    }
+  }
+  for (size_t i = 0; i < M; ++i)
+    for (size_t k = i; k < M; ++k) {
+      double s = 0.0;
+      for (int a = 0; a < ng; ++a) {
+        double p = P[i * ng + a];
+        double acc = 0.0;
+        for (int b = 0; b < ng; ++b) {
+          double pp = P[k * ng + b];
+          double z = (p * p + pp * pp + mu * mu) / (2.0 * p * pp);
+          acc += W[k * ng + b] * legendre_q(l, z);
+        }
+        s += W[i * ng + a] * acc;
+      }
+      s /= M_PI * std::sqrt((e[i + 1] - e[i]) * (e[k + 1] - e[k]));
+      v[i * M + k] = s;
+      v[k * M + i] = s;
+    }
+  return v;
+}
+
+// ------------------------------------------------------------------ symmetric eigenproblem
+
+void sym_eigen(int n, std::vector<double>& A, std::vector<double>& d, std::vector<double>* Zout) {
+  // Householder reduction to tridiagonal form T = Q^T A Q, then implicit QR steps with the
+  // Wilkinson shift (bulge chasing with Givens rotations) accumulated into Q.
+  const bool vec = Zout != nullptr;
+  std::vector<double> Q;
+  if (vec) {
+    Q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  }
+  std::vector<double> v(n), p(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    int m = n - k - 1;  // length of x = A[k+1.., k]
+    double alpha = 0.0;
+    for (int r = 0; r < m; ++r) alpha += A[(size_t)(k + 1 + r) * n + k] * A[(size_t)(k + 1 + r) * n + k];
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    double x0 = A[(size_t)(k + 1) * n + k];
+    double sgn = x0 >= 0.0 ? 1.0 : -1.0;
+    for (int r = 0; r < m; ++r) v[r] = A[(size_t)(k + 1 + r) * n + k];
+    v[0] += sgn * alpha;
+    double vv = 0.0;
+    for (int r = 0; r < m; ++r) vv += v[r] * v[r];
+    if (vv == 0.0) continue;
+    double beta = 2.0 / vv;
+    // p = beta A22 v
+    for (int r = 0; r < m; ++r) {
+      double s = 0.0;
+      const double* row = &A[(size_t)(k + 1 + r) * n + (k + 1)];
+      for (int c = 0; c < m; ++c) s += row[c] * v[c];
+      p[r] = beta * s;
+    }
+    double pv = 0.0;
+    for (int r = 0; r < m; ++r) pv += p[r] * v[r];
+    double K = 0.5 * beta * pv;
+    for (int r = 0; r < m; ++r) w[r] = p[r] - K * v[r];
+    for (int r = 0; r < m; ++r) {
+      double* row = &A[(size_t)(k + 1 + r) * n + (k + 1)];
+      for (int c = 0; c < m; ++c) row[c] -= v[r] * w[c] + w[r] * v[c];
+    }
+    A[(size_t)(k + 1) * n + k] = -sgn * alpha;
+    A[(size_t)k * n + (k + 1)] = -sgn * alpha;
+    for (int r = 1; r < m; ++r) {
+      A[(size_t)(k + 1 + r) * n + k] = 0.0;
+      A[(size_t)k * n + (k + 1 + r)] = 0.0;
+    }
+    if (vec) {
+      // Q <- Q (I - beta v v^T) on columns k+1..n-1
+      for (int r = 0; r < n; ++r) {
+        double* row = &Q[(size_t)r * n + (k + 1)];
+        double s = 0.0;
+        for (int c = 0; c < m; ++c) s += row[c] * v[c];
+        s *= beta;
+        for (int c = 0; c < m; ++c) row[c] -= s * v[c];
+      }
+    }
+  }
+  d.assign(n, 0.0);
+  std::vector<double> e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];
+
+  const double eps = 2.2e-16;
+  int m = n - 1;
+  int guard = 0;
+  while (m > 0) {
+    if (std::fabs(e[m - 1]) <= eps * (std::fabs(d[m - 1]) + std::fabs(d[m]))) {
+      e[m - 1] = 0.0;
+      --m;
+      continue;
+    }
+    int l = m - 1;
+    while (l > 0 && std::fabs(e[l - 1]) > eps * (std::fabs(d[l - 1]) + std::fabs(d[l]))) --l;
+    if (++guard > 60 * n) throw std::runtime_error("symmetric eigensolver did not converge");
+    // Wilkinson shift from the trailing 2x2 block
+    double delta = 0.5 * (d[m - 1] - d[m]);
+    double em = e[m - 1];
+    double den = delta + (delta >= 0.0 ? 1.0 : -1.0) * std::hypot(delta, em);
+    double mu = d[m] - em * em / den;
+    double x = d[l] - mu, z = e[l];
+    for (int k = l; k < m; ++k) {
+      double r = std::hypot(x, z);
+      double c = x / r, s = z / r;
+      if (k > l) e[k - 1] = r;
+      double a = d[k], b = e[k], cc = d[k + 1];
+      d[k] = c * c * a + 2.0 * c * s * b + s * s * cc;
+      d[k + 1] = s * s * a - 2.0 * c * s * b + c * c * cc;
+      e[k] = c * s * (cc - a) + (c * c - s * s) * b;
+      if (k + 1 < m) {
+        x = e[k];
+        z = s * e[k + 1];
+        e[k + 1] = c * e[k + 1];
+      }
+      if (vec) {
+        for (int r2 = 0; r2 < n; ++r2) {
+          double qk = Q[(size_t)r2 * n + k], qk1 = Q[(size_t)r2 * n + k + 1];
+          Q[(size_t)r2 * n + k] = c * qk + s * qk1;
+          Q[(size_t)r2 * n + k + 1] = -s * qk + c * qk1;
+        }
+      }
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  std::vector<double> ds(n);
+  for (int i = 0; i < n; ++i) ds[i] = d[idx[i]];
+  if (vec) {
+    Zout->assign((size_t)n * n, 0.0);
+    for (int r = 0; r < n; ++r)
+      for (int i = 0; i < n; ++i) (*Zout)[(size_t)r * n + i] = Q[(size_t)i * n + idx[r]];
+  }
+  d = ds;
+}
+
+// ------------------------------------------------------------------ angular momentum algebra
+// All arguments are doubled (2j) integers.
+
+static long double fact(int n) {
+  static std::vector<long double> f;
+  if (f.empty()) {
+    f.resize(171);
+    f[0] = 1.0L;
+    for (int i = 1; i < 171; ++i) f[i] = f[i - 1] * i;
+  }
+  return f.at(n);
+}
+
+static bool tri2(int a, int b, int c) {
+  return c >= std::abs(a - b) && c <= a + b && ((a + b + c) % 2 == 0);
+}
+
+static long double delta2(int a, int b, int c) {
+  return std::sqrt(fact((a + b - c) / 2) * fact((a - b + c) / 2) * fact((-a + b + c) / 2) / fact((a + b + c) / 2 + 1));
+}
+
+static double cg2(int j1, int m1, int j2, int m2, int J, int M) {
+  // <j1 m1 j2 m2 | J M> by the Racah formula.
+  if (m1 + m2 != M || !tri2(j1, j2, J)) return 0.0;
+  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(M) > J) return 0.0;
+  if ((j1 + m1) % 2 || (j2 + m2) % 2 || (J + M) % 2) return 0.0;
+  long double pre = std::sqrt((J + 1) * fact((J + j1 - j2) / 2) * fact((J - j1 + j2) / 2) * fact((j1 + j2 - J) / 2) /
+                              fact((j1 + j2 + J) / 2 + 1));
+  pre *= std::sqrt(fact((J + M) / 2) * fact((J - M) / 2) * fact((j1 - m1) / 2) * fact((j1 + m1) / 2) *
+                   fact((j2 - m2) / 2) * fact((j2 + m2) / 2));
+  long double s = 0.0L;
+  for (int k = 0; k <= 200; ++k) {
+    int a1 = (j1 + j2 - J) / 2 - k, a2 = (j1 - m1) / 2 - k, a3 = (j2 + m2) / 2 - k;
+    int a4 = (J - j2 + m1) / 2 + k, a5 = (J - j1 - m2) / 2 + k;
+    if (a1 < 0 || a2 < 0 || a3 < 0) break;
+    if (a4 < 0 || a5 < 0) continue;
+    long double t = 1.0L / (fact(k) * fact(a1) * fact(a2) * fact(a3) * fact(a4) * fact(a5));
+    s += (k % 2 ? -t : t);
+  }
+  return (double)(pre * s);
+}
+
+static double sixj2(int a, int b, int c, int d, int e, int f) {
+  // {a b c; d e f} by the Racah formula.
+  if (!tri2(a, b, c) || !tri2(a, e, f) || !tri2(d, b, f) || !tri2(d, e, c)) return 0.0;
+  long double pre = delta2(a, b, c) * delta2(a, e, f) * delta2(d, b, f) * delta2(d, e, c);
+  int t1 = (a + b + c) / 2, t2 = (a + e + f) / 2, t3 = (d + b + f) / 2, t4 = (d + e + c) / 2;
+  int u1 = (a + b + d + e) / 2, u2 = (b + c + e + f) / 2, u3 = (c + a + f + d) / 2;
+  int tmin = std::max(std::max(t1, t2), std::max(t3, t4));
+  int tmax = std::min(u1, std::min(u2, u3));
+  long double s = 0.0L;
+  for (int t = tmin; t <= tmax; ++t) {
+    long double v = fact(t + 1) / (fact(t - t1) * fact(t - t2) * fact(t - t3) * fact(t - t4) * fact(u1 - t) *
+                                   fact(u2 - t) * fact(u3 - t));
+    s += (t % 2 ? -v : v);
+  }
+  return (double)(pre * s);
+}
+
+static double ninej2(int j1, int j2, int j3, int j4, int j5, int j6, int j7, int j8, int j9) {
+  // {j1 j2 j3; j4 j5 j6; j7 j8 j9} = sum_x (-1)^{2x} (2x+1) {j1 j4 j7; j8 j9 x}{j2 j5 j8; j4 x j6}{j3 j6 j9; x j1 j2}
+  int xmin = std::max(std::max(std::abs(j1 - j9), std::abs(j4 - j8)), std::abs(j2 - j6));
+  int xmax = std::min(std::min(j1 + j9, j4 + j8), j2 + j6);
+  double s = 0.0;
+  for (int x = xmin; x <= xmax; x += 2) {
+    double v = sixj2(j1, j4, j7, j8, j9, x) * sixj2(j2, j5, j8, j4, x, j6) * sixj2(j3, j6, j9, x, j1, j2);
+    s += (x % 2 ? -1.0 : 1.0) * (x + 1) * v;
+  }
+  return s;
+}
+
+std::vector<Chan> enumerate_channels(int two_J, int parity, int j_max, bool swave_only) {
+  std::vector<Chan> out;
+  for (int j = 0; j <= j_max; ++j)
+    for (int s = 0; s <= 1; ++s)
+      for (int l = std::abs(j - s); l <= j + s; ++l) {
+        int t = (l + s + 1) % 2;
+        for (int two_I = 1; two_I <= 2 * j + two_J + 1; two_I += 2) {
+          if (!(std::abs(2 * j - two_I) <= two_J && two_J <= 2 * j + two_I)) continue;
+          for (int lam : {(two_I - 1) / 2, (two_I + 1) / 2}) {
+            if (((l + lam) % 2 == 0 ? 1 : -1) != parity) continue;
+            if (swave_only && (l != 0 || lam != 0)) continue;
+            out.push_back({l, s, j, lam, two_I, t});
+          }
+        }
+      }
+  std::sort(out.begin(), out.end(), [](const Chan& a, const Chan& b) {
+    return std::make_tuple(a.j, a.l, a.s, a.lam, a.two_I) < std::make_tuple(b.j, b.l, b.s, b.lam, b.two_I);
+  });
+  out.erase(std::unique(out.begin(), out.end(),
+                        [](const Chan& a, const Chan& b) {
+                          return a.l == b.l && a.s == b.s && a.j == b.j && a.lam == b.lam && a.two_I == b.two_I;
+                        }),
+            out.end());
+  return out;
+}
+
+std::vector<GTerm> g_table(const Chan& c, const Chan& cp, int two_J) {
+  // Eq. gal with the factor (1/2)^{l2' + l1}; all angular momenta doubled internally.
+  auto hat = [](int two_x) { return (double)(two_x + 1); };
+  const int H = 1;  // 2 * (1/2)
+  int l = 2 * c.l, s = 2 * c.s, j = 2 * c.j, lam = 2 * c.lam, I = c.two_I, t = 2 * c.t;
+  int lp = 2 * cp.l, sp = 2 * cp.s, jp = 2 * cp.j, lamp = 2 * cp.lam, Ip = cp.two_I, tp = 2 * cp.t;
+  int J = two_J, T = 1;
+  double pref = -std::sqrt(hat(l) * hat(s) * hat(j) * hat(t) * hat(lam) * hat(I) * hat(lp) * hat(sp) * hat(jp) *
+                           hat(tp) * hat(lamp) * hat(Ip));
+  pref *= sixj2(H, H, tp, H, T, t);
+  std::map<std::tuple<int, int, int>, double> acc;
+  if (pref == 0.0) return {};
+  auto fct = [](int n) { return (double)fact(n); };
+  for (int L = 0; L <= 2 * std::max(c.l + c.lam, cp.l + cp.lam); L += 2) {
+    if (!tri2(l, lam, L) || !tri2(lp, lamp, L)) continue;
+    for (int S : {1, 3}) {
+      double a = hat(L) * hat(S) * sixj2(H, H, sp, H, S, s);
+      if (a == 0.0) continue;
+      a *= ninej2(l, s, j, lam, H, I, L, S, J) * ninej2(lp, sp, jp, lamp, H, Ip, L, S, J);
+      if (a == 0.0) continue;
+      for (int l1 = 0; l1 <= c.l; ++l1) {
+        int l2 = c.l - l1;
+        for (int l1p = 0; l1p <= cp.l; ++l1p) {
+          int l2p = cp.l - l1p;
+          double cc = std::pow(0.5, l2p + l1) *
+                      std::sqrt(fct(2 * c.l + 1) / (fct(2 * l1) * fct(2 * l2))) *
+                      std::sqrt(fct(2 * cp.l + 1) / (fct(2 * l1p) * fct(2 * l2p)));
+          int kmax = l1p + l2 + c.lam + cp.lam + L / 2 + 2;
+          for (int k = 0; k <= kmax; ++k) {
+            double sum = 0.0;
+            for (int f = std::abs(l1 - c.lam); f <= l1 + c.lam; ++f) {
+              double cf = cg2(2 * l1, 0, lam, 0, 2 * f, 0);
+              if (cf == 0.0) continue;
+              double ck = cg2(2 * k, 0, 2 * l1p, 0, 2 * f, 0);
+              if (ck == 0.0) continue;
+              double w6b = sixj2(2 * l2, 2 * l1, l, lam, L, 2 * f);
+              if (w6b == 0.0) continue;
+              for (int fp = std::abs(l2p - cp.lam); fp <= l2p + cp.lam; ++fp) {
+                double cfp = cg2(2 * l2p, 0, lamp, 0, 2 * fp, 0);
+                if (cfp == 0.0) continue;
+                double ck2 = cg2(2 * k, 0, 2 * l2, 0, 2 * fp, 0);
+                if (ck2 == 0.0) continue;
+                sum += sixj2(2 * l1p, 2 * l2p, lp, lamp, L, 2 * fp) * w6b * cfp * cf *
+                       sixj2(2 * fp, 2 * l1p, L, 2 * f, 2 * l2, 2 * k) * ck * ck2;
+              }
+            }
+            if (sum != 0.0) acc[{l1, l1p, k}] += pref * a * (2 * k + 1) * cc * sum;
+          }
+        }
+      }
+    }
+  }
+  std::vector<GTerm> out;
+  for (auto& kv : acc)
+    if (std::fabs(kv.second) > 1e-15) out.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second});
+  return out;
+}
+
+// ------------------------------------------------------------------ channel resolvent G1
+
+cplx g1_bound_continuum(double qa, double qb, double E, double eps0, double h2m) {
+  // (1/dq) int dq / (E + i0 - eps0 - b3 q^2), b3 = 3/4 h2m, E - eps0 = b3 q0^2.
+  double b3 = 0.75 * h2m;
+  double q0 = std::sqrt((E - eps0) / b3);
+  auto f = [q0](double q) { return std::log(std::fabs((q0 + q) / (q0 - q))); };
+  double re = (f(qb) - f(qa)) / (2.0 * b3 * q0);
+  double im = (q0 > qa && q0 <= qb) ? -M_PI / (2.0 * b3 * q0) : 0.0;
+  return cplx(re, im) / (qb - qa);
+}
+
+// ln|(x + c)/(x - c)| for x, c >= 0 without cancellation when c << x or x << c.
+static double loglog_ratio(double x, double c) {
+  if (x == c) return INFINITY;
+  if (c < x) return std::log1p(2.0 * c / (x - c));
+  return std::log1p(2.0 * x / (c - x));
+}
+
+static double inner_p(double q, double pa, double pb, double E, double h, double b3) {
+  // PV int_{pa}^{pb} dp / (E - b3 q^2 - h p^2)
+  double c2 = E - b3 * q * q;
+  double sh = std::sqrt(h);
+  if (c2 > 0.0) {
+    double c = std::sqrt(c2);
+    return (loglog_ratio(sh * pb, c) - loglog_ratio(sh * pa, c)) / (2.0 * c * sh);
+  }
+  if (c2 < 0.0) {
+    double k = std::sqrt(-c2);
+    // atan(u) - atan(v), u = sh pb / k, v = sh pa / k (both >= 0)
+    double d = std::atan2(sh * (pb - pa) * k, k * k + h * pa * pb);
+    return -d / (sh * k);
+  }
+  return (pa > 0.0) ? (1.0 / (h * pb) - 1.0 / (h * pa)) : -INFINITY;
+}
+
+static double adaptive_gl(const std::function<double(double)>& f, double a, double b, double tol) {
+  // Globally adaptive Gauss-Legendre: each interval is integrated with 10 and 20 points, the
+  // difference is its error estimate; the interval with the largest error is bisected until
+  // the summed error is below tol or 600 intervals exist (bounded work for singular integrands).
+  struct Rules {
+    double x10[10], w10[10], x20[20], w20[20];
+    Rules() {
+      gauss_legendre(10, x10, w10);
+      gauss_legendre(20, x20, w20);
+    }
+  };
+  static const Rules R;  // thread-safe one-time initialisation
+  const double *x10 = R.x10, *w10 = R.w10, *x20 = R.x20, *w20 = R.w20;
+  struct Iv {
+    double a, b, val, err;
+    bool operator<(const Iv& o) const { return err < o.err; }
+  };
+  // A node that lands exactly on an integrable (log) singularity is skipped: that only happens
+  // on intervals a few ulps wide, whose share of the integral is below rounding.
+  auto fin = [](double v) { return std::isfinite(v) ? v : 0.0; };
+  const double min_width = 1e-13 * (b - a);
+  auto eval = [&](double lo, double hi) {
+    double m = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    double s10 = 0.0, s20 = 0.0;
+    for (int i = 0; i < 10; ++i) s10 += w10[i] * fin(f(m + h * x10[i]));
+    for (int i = 0; i < 20; ++i) s20 += w20[i] * fin(f(m + h * x20[i]));
+    double e = (hi - lo) < min_width ? 0.0 : std::fabs(s20 - s10) * h;
+    return Iv{lo, hi, s20 * h, e};
+  };
+  std::priority_queue<Iv> pq;
+  Iv first = eval(a, b);
+  double total = first.val, err = first.err;
+  pq.push(first);
+  int n = 1;
+  while (err > tol && n < 600) {
+    Iv w = pq.top();
+    pq.pop();
+    double m = 0.5 * (w.a + w.b);
+    if (!(m > w.a && m < w.b)) {  // interval exhausted at double precision
+      pq.push(Iv{w.a, w.b, w.val, 0.0});
+      err -= w.err;
+      continue;
+    }
+    Iv l = eval(w.a, m), r = eval(m, w.b);
+    total += l.val + r.val - w.val;
+    err += l.err + r.err - w.err;
+    pq.push(l);
+    pq.push(r);
+    ++n;
+  }
+  return total;
+}
+
+static double arc_inside(double pa, double pb, double qa, double qb, double E, double h, double b3) {
+  if (E <= 0.0) return 0.0;
+  double P = std::sqrt(E / h), Q = std::sqrt(E / b3);
+  double lo_p = std::acos(std::min(1.0, pb / P));
+  double hi_p = std::acos(std::min(1.0, pa / P));
+  double lo_q = std::asin(std::min(1.0, qa / Q));
+  double hi_q = std::asin(std::min(1.0, qb / Q));
+  return std::max(0.0, std::min(hi_p, hi_q) - std::max(lo_p, lo_q));
+}
+
+cplx g1_continuum(double pa, double pb, double qa, double qb, double E, double h2m) {
+  // (1/(dp dq)) int_{pa}^{pb} dp int_{qa}^{qb} dq / (E + i0 - h p^2 - b3 q^2): p integral in
+  // closed form, q integral adaptive with breakpoints where the integrand is singular
+  // (ellipse meeting p = pa, p = pb, and E - b3 q^2 = 0); imaginary part = -pi/(2 sqrt(h b3))
+  // times the polar angle of the energy ellipse inside the box.
+  double h = h2m, b3 = 0.75 * h2m;
+  std::vector<double> pts{qa};
+  for (double c2 : {E, E - h * pa * pa, E - h * pb * pb}) {
+    if (c2 > 0.0) {
+      double qs = std::sqrt(c2 / b3);
+      if (qs > qa && qs < qb) pts.push_back(qs);
+    }
+  }
+  pts.push_back(qb);
+  std::sort(pts.begin(), pts.end());
+  auto f = [&](double q) { return inner_p(q, pa, pb, E, h, b3); };
+  double scale = 1.0 / (h * std::max(pb, 1e-3) * std::max(pb, 1e-3) + std::fabs(E) + 1e-3);
+  // For pa = 0 the p integral behaves like 1/sqrt(q - q*) just above q* = sqrt(E/b3)
+  // (E - b3 q^2 -> 0-); that segment is integrated in u with q = q* + u^2.
+  const double qstar = E > 0.0 ? std::sqrt(E / b3) : -1.0;
+  double re = 0.0;
+  for (size_t i = 0; i + 1 < pts.size(); ++i) {
+    double lo = pts[i], hi = pts[i + 1];
+    if (!(hi > lo)) continue;
+    if (pa == 0.0 && lo == qstar) {
+      // with pa = 0 the p integral is -atan(sqrt(h) pb / k) / (sqrt(h) k), k^2 = b3 (q^2 - q*^2);
+      // in u, k = u sqrt(b3 (2 q* + u^2)) without cancellation and the 2u dq/du cancels 1/k.
+      const double sh = std::sqrt(h);
+      auto g = [&](double u) {
+        double r = std::sqrt(b3 * (2.0 * qstar + u * u));
+        return -2.0 * std::atan2(sh * pb, u * r) / (sh * r);
+      };
+      re += adaptive_gl(g, 0.0, std::sqrt(hi - lo), 1e-15 * scale * (qb - qa));
+    } else {
+      re += adaptive_gl(f, lo, hi, 1e-15 * scale * (qb - qa));
+    }
+  }
+  double im = -M_PI / (2.0 * std::sqrt(h * b3)) * arc_inside(pa, pb, qa, qb, E, h, b3);
+  return cplx(re, im) / ((pb - pa) * (qb - qa));
+}
+
+// ------------------------------------------------------------------ Wynn epsilon
+
+cplx Wynn::push(cplx S) {
+  // New anti-diagonal eps_k^{(n-k)}, k = 0..n, from the previous one:
+  // eps_{k+1}^{(n-1-k)} = eps_{k-1}^{(n-k)} + 1 / (eps_k^{(n-k)} - eps_k^{(n-1-k)}).
+  std::vector<cplx> nw;
+  nw.reserve(diag.size() + 1);
+  nw.push_back(S);
+  for (size_t k = 0; k < diag.size(); ++k) {
+    cplx d = nw[k] - diag[k];
+    cplx inv = (std::abs(d) < 1e-300) ? cplx(1e300, 0.0) : 1.0 / d;
+    cplx lower = k >= 1 ? diag[k - 1] : cplx(0.0, 0.0);
+    nw.push_back(lower + inv);
+  }
+  diag.swap(nw);
+  for (long k = (long)(diag.size() - 1) / 2 * 2; k >= 0; k -= 2)
+    if (std::abs(diag[k]) < 1e200) return diag[k];
+  return diag[0];
+}
+
+}  // namespace wpcd

@@ -1,0 +1,618 @@
+// gfx950 kernels of the WPCD hot path.
+//
+// P0 build (steps 2 and 3 of the paper's Sec. V.A; Appendix, final formula):
+//   k_select   one workgroup per q-box (j, j'): every lane owns one (x, phi) quadrature node
+//              and walks the p rows i with two monotone pointers over the p' edges; the
+//              per-node ranges of p' bins with F > 0 are merged across the wavefront with
+//              shuffles and across wavefronts with LDS atomics into one hull per (box, i).
+//   k_rowseg   per lattice row (j, i): offsets of the box segments and the row total.
+//   k_scan_*   exclusive scans (row offsets of the candidate and of the final block-CSR).
+//   k_pbuild   one wavefront per q-box: node tables and moment weights in LDS, one candidate
+//              cell pair per lane, F and the moments accumulated in registers, channel values
+//              sum_m C[g][g'][m] mom_m written straight into the candidate block-CSR.
+//   k_rowcount / k_compact  ballot + popcount compaction of the nonzero blocks into the
+//              final block-CSR (deterministic, no atomics on the output path).
+// Solve (step 5):
+//   k_rot64    t = A y for every (channel, q bin, column) with A = O or v O^T (M x M per pair
+//              wave): LDS-tiled FP64 GEMM, optional G1 scaling and capture of e0^T O y.
+//   k_spmv64   block-CSR P0 times complex vectors, one wavefront per block row.
+#include <hip/hip_runtime.h>
+
+#include "wpcd_internal.h"
+
+namespace wpcd {
+
+#define WARP 64
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WARP);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WARP));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WARP));
+  return v;
+}
+
+struct Node {
+  double r1, r2, z1, Q1, Q2, w, x, c, s;
+};
+
+// Quadrature node nd of q-box (j, jp): x_a on [-1, 1], phi_b on [phi1, phi2] with
+// phi1 = atan(q'_{j'-1}/q_j), phi2 = atan(q'_{j'}/q_{j-1}); zeta1, zeta2 and the Q range of the box.
+__device__ Node box_node(const PBuildArgs& a, int j, int jp, int nd) {
+  Node n;
+  int ia = nd / a.n_phi, ib = nd - ia * a.n_phi;
+  double qa = a.qe[j], qb = a.qe[j + 1], qpa = a.qe[jp], qpb = a.qe[jp + 1];
+  double phi1 = atan2(qpa, qb), phi2 = atan2(qpb, qa);
+  double hphi = 0.5 * (phi2 - phi1);
+  double phi = 0.5 * (phi1 + phi2) + hphi * a.gp[ib];
+  n.w = a.gwx[ia] * hphi * a.gwp[ib];
+  n.x = a.gx[ia];
+  sincos(phi, &n.s, &n.c);
+  double cs = n.c * n.s;
+  n.z1 = sqrt(n.c * n.c + 0.25 * n.s * n.s + n.x * cs);
+  double z2 = sqrt(0.25 * n.c * n.c + n.s * n.s + n.x * cs);
+  n.r1 = 1.0 / n.z1;
+  n.r2 = 1.0 / z2;
+  n.Q1 = fmax(qa / n.c, qpa / n.s);
+  n.Q2 = fmin(qb / n.c, qpb / n.s);
+  return n;
+}
+
+// ------------------------------------------------------------------ step 2: selection
+
+__global__ void __launch_bounds__(256) k_select(PBuildArgs a, int* __restrict__ cnt, int* __restrict__ lo_out) {
+  extern __shared__ double sh[];
+  const int M = a.M;
+  double* spe = sh;                                   // M + 1
+  int* slo = reinterpret_cast<int*>(spe + M + 1);     // M
+  int* shi = slo + M;                                 // M
+  const int box = blockIdx.x;
+  const int j = box / a.N, jp = box - j * a.N;
+  const int nn = a.n_x * a.n_phi;
+  const int t = threadIdx.x, lane = t & 63;
+  for (int i = t; i <= M; i += blockDim.x) spe[i] = a.pe[i];
+  for (int i = t; i < M; i += blockDim.x) {
+    slo[i] = 0x7fffffff;
+    shi[i] = -1;
+  }
+  __syncthreads();
+  const bool valid = t < nn;
+  Node n{};
+  if (valid) n = box_node(a, j, jp, t);
+  int lp = 0, hp = 0;  // monotone pointers over p' bins
+  for (int i = 0; i < M; ++i) {
+    int mylo = 0x7fffffff, myhi = -1;
+    if (valid) {
+      double A = fmax(n.Q1, spe[i] * n.r2);
+      double B = fmin(n.Q2, spe[i + 1] * n.r2);
+      if (A < B) {
+        double Az = A * n.z1, Bz = B * n.z1;
+        while (lp < M - 1 && spe[lp + 1] <= Az) ++lp;   // first bin with upper edge > A zeta1
+        while (hp < M - 1 && spe[hp + 1] < Bz) ++hp;    // last bin with lower edge < B zeta1
+        mylo = lp;
+        myhi = hp;
+      }
+    }
+    mylo = wave_min(mylo);
+    myhi = wave_max(myhi);
+    if (lane == 0 && myhi >= 0) {
+      atomicMin(&slo[i], mylo);
+      atomicMax(&shi[i], myhi);
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < M; i += blockDim.x) {
+    int l = slo[i], h = shi[i];
+    int c = 0, l2 = 0;
+    if (h >= 0 && h >= l) {
+      l2 = max(0, l - 1);
+      int h2 = min(M - 1, h + 1);
+      c = h2 - l2 + 1;
+    }
+    cnt[(size_t)box * M + i] = c;
+    lo_out[(size_t)box * M + i] = l2;
+  }
+}
+
+hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) {
+  int nn = a.n_x * a.n_phi;
+  if (nn < 1 || nn > 256 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
+  int threads = ((nn + 63) / 64) * 64;
+  size_t shmem = (a.M + 1) * sizeof(double) + 2 * a.M * sizeof(int);
+  hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(threads), shmem, s, a, cnt, lo);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ row segments
+
+__global__ void k_rowseg(int M, int N, const int* __restrict__ cnt, int* __restrict__ segoff,
+                         int64_t* __restrict__ rowcnt) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;   // r = j*M + i
+  if (r >= M * N) return;
+  int j = r / M, i = r - j * M;
+  int64_t run = 0;
+  for (int jp = 0; jp < N; ++jp) {
+    size_t idx = ((size_t)j * N + jp) * M + i;
+    segoff[idx] = (int)run;
+    run += cnt[idx];
+  }
+  rowcnt[r] = run;
+}
+
+hipError_t launch_rowseg(int M, int N, const int* cnt, int* segoff, int64_t* rowcnt, hipStream_t s) {
+  int R = M * N;
+  hipLaunchKernelGGL(k_rowseg, dim3((R + 255) / 256), dim3(256), 0, s, M, N, cnt, segoff, rowcnt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ exclusive scan (int64)
+
+#define SCAN_T 256
+#define SCAN_E 4
+#define SCAN_CHUNK (SCAN_T * SCAN_E)
+
+__device__ int64_t block_exclusive(int64_t v, int64_t* sbuf, int64_t* total) {
+  // block-wide exclusive scan of one value per thread (SCAN_T threads)
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int64_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(x, o, WARP);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sbuf[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+      int64_t tmp = sbuf[w];
+      sbuf[w] = run;
+      run += tmp;
+    }
+    sbuf[SCAN_T / 64] = run;
+  }
+  __syncthreads();
+  int64_t res = x - v + sbuf[wv];
+  *total = sbuf[SCAN_T / 64];
+  __syncthreads();
+  return res;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_local(const int64_t* __restrict__ in, int64_t* __restrict__ out,
+                                                       int64_t n, int64_t* __restrict__ bsum) {
+  __shared__ int64_t sbuf[SCAN_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_E;
+  int64_t v[SCAN_E];
+  int64_t loc = 0;
+  for (int e = 0; e < SCAN_E; ++e) {
+    v[e] = (base + e < n) ? in[base + e] : 0;
+    loc += v[e];
+  }
+  int64_t tot;
+  int64_t off = block_exclusive(loc, sbuf, &tot);
+  for (int e = 0; e < SCAN_E; ++e) {
+    if (base + e < n) out[base + e] = off;
+    off += v[e];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_sums(int64_t* __restrict__ bsum, int nb, int64_t* __restrict__ total_out) {
+  __shared__ int64_t sbuf[SCAN_T / 64 + 1];
+  int64_t carry = 0;
+  for (int base = 0; base < nb; base += SCAN_T) {
+    int idx = base + threadIdx.x;
+    int64_t v = idx < nb ? bsum[idx] : 0;
+    int64_t tot;
+    int64_t off = block_exclusive(v, sbuf, &tot);
+    if (idx < nb) bsum[idx] = off + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ bsum) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += bsum[i / SCAN_CHUNK];
+}
+
+size_t scan_tmp_size(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1); }
+
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+  if (n <= 0) return hipErrorInvalidValue;
+  int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_T), 0, s, in, out, n, tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, tmp, nb, out + n);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, tmp);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ step 3: quadrature
+
+#define PB_MAXNODES 256
+#define PB_MAXMOM 8
+
+// Moment weight of key (k, a, b, l, l') at a node: w P_k(x) c^(a+1) s^(b+1) / (z1^(l'+1) z2^(l+1)).
+__device__ double moment_weight(const Node& n, const int* key) {
+  int k = key[0], ea = key[1], eb = key[2], l = key[3], lp = key[4];
+  double p0 = 1.0, p1 = n.x, pk = (k == 0) ? 1.0 : n.x;
+  for (int m = 2; m <= k; ++m) {
+    double p2 = ((2.0 * m - 1.0) * n.x * p1 - (m - 1.0) * p0) / m;
+    p0 = p1;
+    p1 = p2;
+    pk = p2;
+  }
+  double v = n.w * pk;
+  for (int e = 0; e <= ea; ++e) v *= n.c;
+  for (int e = 0; e <= eb; ++e) v *= n.s;
+  for (int e = 0; e <= lp; ++e) v *= n.r1;
+  for (int e = 0; e <= l; ++e) v *= n.r2;
+  return v;
+}
+
+template <int NMOM>
+__global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
+                                               const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
+                                               int32_t* __restrict__ col_c, double* __restrict__ val_c,
+                                               uint8_t* __restrict__ flag) {
+  extern __shared__ double sh[];
+  const int M = a.M, N = a.N;
+  const int nn = a.n_x * a.n_phi;
+  const int box = blockIdx.x;
+  const int j = box / N, jp = box - j * N;
+  const int t = threadIdx.x;
+  // LDS: r1, r2, Q1, Q2 [nn], weights [NMOM][nn], pe [M+1], pref [M+1] (int), lo [M] (int)
+  double* s_r1 = sh;
+  double* s_r2 = s_r1 + nn;
+  double* s_Q1 = s_r2 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_w = s_Q2 + nn;
+  double* s_pe = s_w + NMOM * nn;
+  int* s_pref = reinterpret_cast<int*>(s_pe + M + 1);
+  int* s_lo = s_pref + M + 1;
+
+  // exclusive prefix of the candidate counts over p rows i (wave scan in chunks of 64)
+  int run = 0;
+  for (int base = 0; base < M; base += 64) {
+    int i = base + t;
+    int c = (i < M) ? cnt[(size_t)box * M + i] : 0;
+    int x = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(x, o, WARP);
+      if (t >= o) x += y;
+    }
+    if (i < M) {
+      s_pref[i] = run + x - c;
+      s_lo[i] = lo[(size_t)box * M + i];
+    }
+    run += __shfl(x, 63, WARP);
+  }
+  const int total = run;
+  if (total == 0) return;
+  if (t == 0) s_pref[M] = total;
+  for (int i = t; i <= M; i += 64) s_pe[i] = a.pe[i];
+  for (int nd = t; nd < nn; nd += 64) {
+    Node n = box_node(a, j, jp, nd);
+    s_r1[nd] = n.r1;
+    s_r2[nd] = n.r2;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
+    for (int m = 0; m < a.nmom; ++m) s_w[m * nn + nd] = moment_weight(n, a.keys + 5 * m);
+  }
+  __syncthreads();
+
+  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  const int nc = a.nch, nc2 = nc * nc;
+  for (int e = t; e < total; e += 64) {
+    // row i: last i with pref[i] <= e
+    int lo_i = 0, hi_i = M - 1;
+    while (lo_i < hi_i) {
+      int mid = (lo_i + hi_i + 1) >> 1;
+      if (s_pref[mid] <= e) lo_i = mid;
+      else hi_i = mid - 1;
+    }
+    const int i = lo_i;
+    const int ip = s_lo[i] + (e - s_pref[i]);
+    const double pa = s_pe[i], pb = s_pe[i + 1], ppa = s_pe[ip], ppb = s_pe[ip + 1];
+    double mom[NMOM];
+#pragma unroll
+    for (int m = 0; m < NMOM; ++m) mom[m] = 0.0;
+    for (int nd = 0; nd < nn; ++nd) {
+      const double r1 = s_r1[nd], r2 = s_r2[nd];
+      const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
+      const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
+      const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+#pragma unroll
+      for (int m = 0; m < NMOM; ++m)
+        if (m < a.nmom) mom[m] = fma(s_w[m * nn + nd], F, mom[m]);
+    }
+    const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+    const int64_t blk = rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] + (ip - s_lo[i]);
+    col_c[blk] = jp * M + ip;
+    bool nz = false;
+    for (int gg = 0; gg < nc2; ++gg) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < NMOM; ++m)
+        if (m < a.nmom) v = fma(a.C[(size_t)gg * a.nmom + m], mom[m], v);
+      v *= norm;
+      val_c[blk * nc2 + gg] = v;
+      nz |= (v != 0.0);
+    }
+    flag[blk] = nz ? 1 : 0;
+  }
+}
+
+hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
+                         const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag, hipStream_t s) {
+  int nn = a.n_x * a.n_phi;
+  if (nn < 1 || nn > PB_MAXNODES || a.nmom < 1 || a.nmom > PB_MAXMOM || a.nch < 1) return hipErrorInvalidValue;
+  size_t shmem = (size_t)nn * (4 + (a.nmom <= 1 ? 1 : (a.nmom <= 2 ? 2 : (a.nmom <= 4 ? 4 : 8)))) * sizeof(double) +
+                 (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
+  dim3 g(a.N * a.N), b(64);
+  if (a.nmom <= 1)
+    hipLaunchKernelGGL(k_pbuild<1>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+  else if (a.nmom <= 2)
+    hipLaunchKernelGGL(k_pbuild<2>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+  else if (a.nmom <= 4)
+    hipLaunchKernelGGL(k_pbuild<4>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+  else
+    hipLaunchKernelGGL(k_pbuild<8>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ compaction
+
+__global__ void __launch_bounds__(256) k_rowcount(int64_t rows, const int64_t* __restrict__ rowptr_c,
+                                                  const uint8_t* __restrict__ flag, int64_t* __restrict__ rowcnt) {
+  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  int64_t b0 = rowptr_c[row], b1 = rowptr_c[row + 1];
+  int64_t c = 0;
+  for (int64_t e = b0 + lane; e < b1; e += 64) c += flag[e];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, WARP);
+  if (lane == 0) rowcnt[row] = c;
+}
+
+hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowcount, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, rowptr_c, flag, rowcnt);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const int64_t* __restrict__ rowptr_c,
+                                                 const int32_t* __restrict__ col_c, const double* __restrict__ val_c,
+                                                 const uint8_t* __restrict__ flag, const int64_t* __restrict__ rowptr,
+                                                 int32_t* __restrict__ col, double* __restrict__ val64,
+                                                 float* __restrict__ val32) {
+  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int nc2 = nch * nch;
+  int64_t b0 = rowptr_c[row], b1 = rowptr_c[row + 1];
+  int64_t out = rowptr[row];
+  for (int64_t base = b0; base < b1; base += 64) {
+    int64_t e = base + lane;
+    bool f = (e < b1) && flag[e];
+    unsigned long long mask = __ballot(f);
+    int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (f) {
+      int64_t d = out + before;
+      col[d] = col_c[e];
+      for (int g = 0; g < nc2; ++g) {
+        double v = val_c[e * nc2 + g];
+        if (val64) val64[d * nc2 + g] = v;
+        if (val32) val32[d * nc2 + g] = (float)v;
+      }
+    }
+    out += __popcll(mask);
+  }
+}
+
+hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c, const double* val_c,
+                          const uint8_t* flag, const int64_t* rowptr, int32_t* col, double* val64, float* val32,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, rowptr_c, col_c, val_c,
+                     flag, rowptr, col, val64, val32);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ solve: block rotation GEMM (FP64)
+
+#define RT 32
+
+template <bool SCALE>
+__global__ void __launch_bounds__(256) k_rot64(RotArgs r, const double2* __restrict__ in, double2* __restrict__ out) {
+  __shared__ double As[RT][RT + 1];
+  __shared__ double2 Is[RT][RT + 1];
+  const int M = r.M, B = r.B, nch = r.nch;
+  const int ncol = r.N * B;
+  const int g = blockIdx.z;
+  const double* A = r.A + (size_t)r.wave[g] * M * M;
+  const int k0 = blockIdx.x * RT, c0 = blockIdx.y * RT;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const bool cfast = B >= RT;
+  double2 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int i0 = 0; i0 < M; i0 += RT) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int rr = e >> 5, cc = e & 31;
+      int k = k0 + rr, i = i0 + cc;
+      As[rr][cc] = (k < M && i < M) ? A[(size_t)k * M + i] : 0.0;
+      int ii, col;
+      if (cfast) {
+        ii = e >> 5;
+        col = c0 + (e & 31);
+      } else {
+        ii = e & 31;
+        col = c0 + (e >> 5);
+      }
+      int iv = i0 + ii;
+      double2 v = make_double2(0.0, 0.0);
+      if (iv < M && col < ncol) {
+        int jj = col / B, cb = col - jj * B;
+        v = in[(((size_t)jj * M + iv) * nch + g) * B + cb];
+      }
+      Is[ii][col - c0] = v;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int ii = 0; ii < RT; ++ii) {
+      double2 x = Is[ii][tx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double av = As[ty + 8 * q][ii];
+        acc[q].x = fma(av, x.x, acc[q].x);
+        acc[q].y = fma(av, x.y, acc[q].y);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue: capture, scale, stage through LDS for coalesced stores
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int k = k0 + ty + 8 * q, col = c0 + tx;
+    double2 v = acc[q];
+    if (k < M && col < ncol) {
+      int jj = col / B, cb = col - jj * B;
+      if (r.acap && k == 0 && jj == r.j0[cb]) {
+        for (int f = 0; f < r.nfin; ++f)
+          if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = v;
+      }
+      if (SCALE) {
+        double2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
+        v = make_double2(v.x * gv.x - v.y * gv.y, v.x * gv.y + v.y * gv.x);
+      }
+    }
+    Is[ty + 8 * q][tx] = v;   // Is reused as [k][col]
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    int e = tid + 256 * q;
+    int kk, col;
+    if (cfast) {
+      kk = e >> 5;
+      col = c0 + (e & 31);
+    } else {
+      kk = e & 31;
+      col = c0 + (e >> 5);
+    }
+    int k = k0 + kk;
+    if (k < M && col < ncol) {
+      int jj = col / B, cb = col - jj * B;
+      out[(((size_t)jj * M + k) * nch + g) * B + cb] = Is[kk][col - c0];
+    }
+  }
+}
+
+hipError_t launch_rot64(const RotArgs& r, const double2* in, double2* out, hipStream_t s) {
+  if (r.M < 1 || r.N < 1 || r.B < 1 || r.nch < 1) return hipErrorInvalidValue;
+  if (r.G == nullptr && r.acap != nullptr) return hipErrorInvalidValue;
+  dim3 grid((r.M + RT - 1) / RT, (r.N * r.B + RT - 1) / RT, r.nch);
+  if (r.G)
+    hipLaunchKernelGGL(k_rot64<true>, grid, dim3(256), 0, s, r, in, out);
+  else
+    hipLaunchKernelGGL(k_rot64<false>, grid, dim3(256), 0, s, r, in, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ solve: block-CSR SpMV (FP64)
+
+template <int NC>
+__global__ void __launch_bounds__(256) k_spmv64(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
+                                                const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                const double2* __restrict__ x, double2* __restrict__ y) {
+  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  for (int c = cb0; c < cb1; ++c) {
+    double ar[NC], ai[NC];
+#pragma unroll
+    for (int g = 0; g < NC; ++g) ar[g] = ai[g] = 0.0;
+    for (int64_t e = b0 + lane; e < b1; e += 64) {
+      const int cc = col[e];
+      const double* v = val + e * NC * NC;
+#pragma unroll
+      for (int gp = 0; gp < NC; ++gp) {
+        double2 xv = x[((size_t)cc * NC + gp) * B + c];
+#pragma unroll
+        for (int g = 0; g < NC; ++g) {
+          ar[g] = fma(v[g * NC + gp], xv.x, ar[g]);
+          ai[g] = fma(v[g * NC + gp], xv.y, ai[g]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
+      if (lane == g) y[((size_t)row * NC + g) * B + c] = make_double2(sr, si);
+    }
+  }
+}
+
+hipError_t launch_spmv64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
+                         const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
+  if (cb1 < 0) cb1 = B;
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((rows + 3) / 4)), blk(256);
+  switch (nch) {
+    case 1: hipLaunchKernelGGL(k_spmv64<1>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
+    case 2: hipLaunchKernelGGL(k_spmv64<2>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
+    case 3: hipLaunchKernelGGL(k_spmv64<3>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
+    case 4: hipLaunchKernelGGL(k_spmv64<4>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ solve: right-hand side
+
+__global__ void k_fill0(double2* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_set_rhs(int M, int nch, int B, int cb0, const double* __restrict__ W, const int* __restrict__ wave,
+                          const int* __restrict__ j0, const int* __restrict__ g0, double2* __restrict__ s0) {
+  int c = cb0 + blockIdx.x;
+  int g = g0[c];
+  const double* Wg = W + (size_t)wave[g] * M * M;
+  for (int i = threadIdx.x; i < M; i += blockDim.x)
+    s0[(((size_t)j0[c] * M + i) * nch + g) * B + c] = make_double2(Wg[(size_t)i * M + 0], 0.0);
+}
+
+__global__ void k_fill0_cols(double2* __restrict__ p, int64_t rows, int B, int cb0, int cb1) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int w = cb1 - cb0;
+  if (i >= rows * w) return;
+  int64_t r = i / w;
+  int c = cb0 + (int)(i - r * w);
+  p[r * B + c] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, const int* wave, const int* j0,
+                             const int* g0, double2* s0, hipStream_t st, int cb0, int cb1) {
+  if (cb1 < 0) cb1 = B;
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1) return hipErrorInvalidValue;
+  int64_t rows = (int64_t)M * N * nch;
+  int64_t n = rows * (cb1 - cb0);
+  hipLaunchKernelGGL(k_fill0_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s0, rows, B, cb0, cb1);
+  hipLaunchKernelGGL(k_set_rhs, dim3(cb1 - cb0), dim3(128), 0, st, M, nch, B, cb0, W, wave, j0, g0, s0);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace wpcd

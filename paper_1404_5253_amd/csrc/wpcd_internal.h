@@ -1,0 +1,163 @@
+// Internal declarations shared by the host numerics (host_math.cpp), the C ABI (capi.cpp) and
+// the gfx950 kernels (kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wpcd.h"
+
+namespace wpcd {
+
+using cplx = std::complex<double>;
+
+// ------------------------------------------------------------------ host numerics
+// Gauss-Legendre nodes/weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, double* x, double* w);
+
+std::vector<double> tangent_edges(int n, double alpha, double pmax);
+std::vector<double> h0_diagonal(const std::vector<double>& edges, double h2m);
+
+// NN potential in the free WP basis (M x M, row-major).
+std::vector<double> yamaguchi_form(const std::vector<double>& edges, double beta);
+std::vector<double> yukawa_wp(const std::vector<double>& edges, int l, double mu);
+
+// Symmetric eigenproblem: Householder tridiagonalisation + implicit QL.
+// a (n x n row-major, destroyed) -> eigenvalues ascending in d, eigenvectors as ROWS of z.
+void sym_eigen(int n, std::vector<double>& a, std::vector<double>& d, std::vector<double>* z);
+
+// Recoupling
+struct Chan { int l, s, j, lam, two_I, t; };
+std::vector<Chan> enumerate_channels(int two_J, int parity, int j_max, bool swave_only);
+struct MomKey { int k, a, b, l, lp; };
+// g table of eq. gal for a channel pair: list of (l1, l1p, k, value)
+struct GTerm { int l1, l1p, k; double g; };
+std::vector<GTerm> g_table(const Chan& c, const Chan& cp, int two_J);
+
+// Channel resolvent elements (FP64)
+cplx g1_bound_continuum(double qa, double qb, double E, double eps0, double h2m);
+cplx g1_continuum(double pa, double pb, double qa, double qb, double E, double h2m);
+
+// Wynn epsilon accumulator with the stop rule of faddeev_solve.
+struct Wynn {
+  std::vector<cplx> diag;
+  cplx push(cplx S);
+};
+
+// ------------------------------------------------------------------ device helpers
+struct DevAlloc {
+  wp_allocator a{};
+  bool custom = false;
+  void* alloc(size_t bytes);
+  void release(void* p);
+};
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevAlloc* al = nullptr;
+  void reset() {
+    if (p && al) al->release(p);
+    p = nullptr;
+    n = 0;
+  }
+  bool make(DevAlloc* a, size_t count) {
+    reset();
+    al = a;
+    n = count;
+    if (count == 0) return true;
+    p = static_cast<T*>(a->alloc(count * sizeof(T)));
+    return p != nullptr;
+  }
+  ~DBuf() { reset(); }
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+};
+
+// ------------------------------------------------------------------ kernel launchers
+// (defined in kernels.hip; every launcher checks its shapes and returns hipError_t)
+struct PBuildArgs {
+  int M, N, nch, nmom, n_x, n_phi;
+  const double* pe;    // device [M+1]
+  const double* qe;    // device [N+1]
+  const double* gx;    // device Gauss nodes x [n_x]
+  const double* gwx;   // weights [n_x]
+  const double* gp;    // Gauss nodes phi [n_phi]
+  const double* gwp;   // weights [n_phi]
+  const int* keys;     // device [nmom][5]
+  const double* C;     // device [nch][nch][nmom]
+};
+
+// Selection (step 2): per q-box and p-row the hull [lo, lo + cnt) of possibly nonzero p' bins.
+hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s);
+// Per lattice row, offsets of each box segment and the row total.
+hipError_t launch_rowseg(int M, int N, const int* cnt, int* segoff, int64_t* rowcnt, hipStream_t s);
+// Exclusive scan of n int64 values into out[n+1] (tmp: scan_tmp_size(n) int64).
+size_t scan_tmp_size(int64_t n);
+hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+// Quadrature (step 3) into the candidate block-CSR (values in FP64, per-block nonzero flag).
+hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
+                         const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag,
+                         hipStream_t s);
+hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt,
+                           hipStream_t s);
+hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c,
+                          const double* val_c, const uint8_t* flag, const int64_t* rowptr,
+                          int32_t* col, double* val64, float* val32, hipStream_t s);
+
+// Solve kernels. Vector layout: x[((j*M + i)*nch + g)*B + c] complex (double2 / float2).
+struct RotArgs {
+  int M, N, nch, B;
+  const double* A;       // [nwave][M][M] row-major
+  const int* wave;       // [nch] pair wave of each channel
+  const double2* G;      // scaling [j][k][g][c] or nullptr
+  double2* acap;         // captured e^T O y entries or nullptr
+  const int* j0;         // [B] on-shell bin per column
+  const int* finals;     // [nfin] channels captured
+  int nfin;
+  int64_t acap_off;      // offset (in double2) of this term's capture row: acap[acap_off + c*nfin + f]
+};
+hipError_t launch_rot64(const RotArgs& r, const double2* in, double2* out, hipStream_t s);
+// y = P0 x for the columns [cb0, cb1) (cb1 < 0: all B columns)
+hipError_t launch_spmv64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
+                         const double* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
+                         int cb1 = -1);
+// s0 = (v O^T) e0 on the columns [cb0, cb1): the deuteron column W[:, 0] of channel g0[c] at q bin j0[c]
+hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, const int* wave,
+                             const int* j0, const int* g0, double2* s0, hipStream_t st, int cb0 = 0,
+                             int cb1 = -1);
+hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st);
+
+// Mixed precision (FP32 P0, BF16 blocks on MFMA, FP32 vectors)
+struct RotArgsMixed {
+  int M, N, nch, B;
+  const uint16_t* A;     // bf16 [nwave][Mp][Mp] (padded to multiple of 16, zero fill)
+  int Mp;
+  const int* wave;
+  const float2* G;       // scaling [j][k][g][c] or nullptr
+  float2* acap;
+  const int* j0;
+  const int* finals;
+  int nfin;
+  int64_t acap_off;
+};
+hipError_t launch_rot_bf16(const RotArgsMixed& r, const float2* in, float2* out, hipStream_t s);
+hipError_t launch_spmv32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
+                         const float* val, const float2* x, float2* y, hipStream_t s);
+hipError_t launch_spmv32acc64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
+                              const float* val, const double2* x, double2* y, hipStream_t s);
+hipError_t launch_cvt_d2f(int64_t n, const double2* in, float2* out, hipStream_t s);
+hipError_t launch_axpy_f2d(int64_t n, const float2* in, double2* out, double alpha, hipStream_t s);
+hipError_t launch_residual(int64_t n, const double2* b, const double2* y, const double2* Ky, double2* r,
+                           hipStream_t s);
+hipError_t launch_lincomb(int64_t n, int B, int nv, const float2* vecs, int64_t vstride,
+                          const double2* coef, double2* out, hipStream_t s);
+
+}  // namespace wpcd

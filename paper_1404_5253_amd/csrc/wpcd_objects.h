@@ -1,0 +1,142 @@
+// Handle objects of libwpcd shared by the C-ABI translation units (capi.cpp, batch.cpp).
+#pragma once
+
+#include <cmath>
+#include <string>
+
+#include "wpcd_internal.h"
+
+using namespace wpcd;
+
+#define HIPCHECK(expr)                                                                                     \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess) return wpcd::fail(WP_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct PairWave {
+  int l, s;
+  std::vector<double> eps, O, v, W;  // O rows = eigenvectors; W = v O^T
+  int nb = 0;
+  std::vector<double> bins;          // continuum pseudostate momentum bins
+};
+
+struct wp_lattice {
+  DevAlloc al;
+  int M = 0, N = 0, nch = 0, two_J = 1, n_x = 8, n_phi = 8;
+  double h2m = 41.471;
+  std::vector<double> pe, qe;
+  std::vector<Chan> ch;
+  std::vector<MomKey> keys;
+  std::vector<double> C;          // [nch][nch][nmom]
+  int nz_pairs = 0;
+  // pseudostates
+  bool pseudo = false;
+  std::vector<PairWave> waves;
+  std::vector<int> wave_of;
+  std::vector<int> opens;
+  double eps0 = 0.0, strength = 0.0;
+  // device tables
+  DBuf<double> d_pe, d_qe, d_gx, d_gwx, d_gp, d_gwp, d_C, d_O, d_W;
+  DBuf<int> d_keys, d_wave;
+  // P0
+  bool have_P = false;
+  int prec = WP_P_FP64;
+  int64_t blocks = 0;
+  DBuf<int64_t> d_rowptr;
+  DBuf<int32_t> d_col;
+  DBuf<double> d_val64;
+  DBuf<float> d_val32;
+  wp_perm_stats stats{};
+};
+
+struct EnergyResult {
+  double E_lab, E, q0, dq0;
+  int j0;
+  int n_open;
+  std::vector<cplx> U;      // [final][initial]
+  std::vector<double> err;  // per initial column
+  std::vector<int> iters;
+  bool ok = true;
+};
+
+struct wp_solution {
+  double h2m;
+  std::vector<EnergyResult> res;
+};
+
+
+namespace wpcd {
+
+wp_status fail(wp_status st, const std::string& msg);
+wp_status upload_waves(wp_lattice* L);
+// G1 over (k, j) of one pair wave at three-body energy E (host FP64, threaded over k)
+void g1_wave(const wp_lattice* L, const PairWave& pw, double E, std::vector<cplx>& out);
+
+// Kinematics of one energy: E, q0, on-shell bin j0 ((q_{j-1}, q_j] convention), its width.
+inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {
+  r.E_lab = E_lab;
+  r.E = L->eps0 + 2.0 * E_lab / 3.0;
+  r.q0 = std::sqrt(4.0 * (2.0 * E_lab / 3.0) / (3.0 * L->h2m));
+  int jj = -1;
+  for (int j = 0; j < L->N; ++j)
+    if (L->qe[j] < r.q0 && r.q0 <= L->qe[j + 1]) jj = j;
+  if (jj < 0) return false;
+  r.j0 = jj;
+  r.dq0 = L->qe[jj + 1] - L->qe[jj];
+  r.n_open = (int)L->opens.size();
+  r.U.assign(r.n_open * r.n_open, cplx(0, 0));
+  r.err.assign(r.n_open, 0.0);
+  r.iters.assign(r.n_open, 0);
+  r.ok = true;
+  return true;
+}
+
+// Pade (Wynn epsilon) state of one column (energy x initial channel) over its final channels,
+// with the stop rule: two successive relative changes <= tol, or a rounding plateau (no new
+// minimum of the change for PLATEAU terms, or partial sums above 1e250) accepted when the
+// smallest change <= accept.
+struct ColState {
+  std::vector<Wynn> w;      // per final
+  std::vector<cplx> S, last, best;
+  double best_r = INFINITY;
+  int best_n = 0, streak = 0, n = 0;
+  bool done = false, ok = false;
+  double err = 0.0;
+};
+constexpr int PLATEAU = 24;
+
+// One term of the on-shell series of every final for a column; returns true when finished.
+inline bool column_push(ColState& cs, const cplx* a, int nfin, double tol, double accept) {
+  std::vector<cplx> est(nfin);
+  double Smax = 0.0;
+  for (int f = 0; f < nfin; ++f) {
+    cs.S[f] += a[f];
+    est[f] = cs.w[f].push(cs.S[f]);
+    Smax = std::max(Smax, std::abs(cs.S[f]));
+  }
+  if (cs.n > 0) {
+    double r = 0.0;
+    for (int f = 0; f < nfin; ++f) r = std::max(r, std::abs(est[f] - cs.last[f]) / std::max(std::abs(est[f]), 1e-300));
+    if (r < cs.best_r) {
+      cs.best_r = r;
+      cs.best = est;
+      cs.best_n = cs.n;
+    }
+    cs.streak = (r <= tol) ? cs.streak + 1 : 0;
+    if (cs.streak >= 2) {
+      cs.best = est;
+      cs.err = r;
+      cs.done = cs.ok = true;
+    } else if (cs.n - cs.best_n >= PLATEAU || Smax > 1e250) {
+      cs.done = true;
+      cs.ok = cs.best_r <= accept;
+      cs.err = cs.best_r;
+    }
+  }
+  cs.last = est;
+  cs.n++;
+  return cs.done;
+}
+
+}  // namespace wpcd

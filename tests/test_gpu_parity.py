@@ -1,0 +1,179 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by element.
+
+Tolerances (FP64 path):
+  * P0: |dP| <= 1e-12 * max|P0| on the union of both patterns (the oracle divides by zeta where
+    the kernel multiplies by 1/zeta; pairs whose value is below that bound may differ in
+    whether they are stored, nothing else may);
+  * amplitudes of a convergent series (quartet): |dA| <= 1e-10 |A|;
+  * divergent series (doublet): Pade stops on a rounding plateau; |dA| <= 1e-10 |A| + 30 x the
+    larger of the two error estimates, and the HIP result must also agree with the oracle's
+    dense LU solve within that bound.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import paper_1404_5253_amd as wp
+
+from oracle import pipeline
+from oracle.perm import P0Lattice
+
+
+def _lib_lattice(spec, precision="fp64"):
+    L = wp.Lattice(spec.M, spec.N, two_J=spec.two_J, j_max=spec.j_max, swave_only=spec.swave_only,
+                   n_x=spec.n_x, n_phi=spec.n_phi)
+    if spec.pot == "yamaguchi":
+        L.pseudostates(kind="yamaguchi", beta=spec.beta)
+    else:
+        L.pseudostates(kind="mt", V_R=spec.V_R, mu_R=spec.mu_R, mu_A=spec.mu_A, singlet_ratio=spec.singlet_ratio)
+    L.build_perm(precision)
+    return L
+
+
+def _lib_dense_P0(L):
+    """Block-CSR export -> dict {(row cell, col cell): block}."""
+    rp, col, val = L.export_perm()
+    out = {}
+    for r in range(len(rp) - 1):
+        for b in range(rp[r], rp[r + 1]):
+            out[(r, int(col[b]))] = val[b]
+    return out
+
+
+def _oracle_blocks(s):
+    P = s.P0geo
+    vals = np.einsum("abm,nm->nab", s.C, P.moms)
+    return {(int(r), int(c)): vals[k] for k, (r, c) in enumerate(zip(P.rows, P.cols))}
+
+
+SPECS = {
+    "quartet_yam_24": pipeline.Spec(M=24, N=24, two_J=3, pot="yamaguchi"),
+    "doublet_mt_20": pipeline.Spec(M=20, N=20, two_J=1, pot="mt"),
+    "quartet_yam_ragged_17x13": pipeline.Spec(M=17, N=13, two_J=3, pot="yamaguchi", n_x=6, n_phi=10),
+}
+
+
+@pytest.fixture(scope="module")
+def systems():
+    return {k: pipeline.build_system(v) for k, v in SPECS.items()}
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_p0_fp64_matches_oracle(systems, name):
+    s = systems[name]
+    L = _lib_lattice(SPECS[name])
+    got = _lib_dense_P0(L)
+    ref = _oracle_blocks(s)
+    scale = max(np.abs(v).max() for v in ref.values())
+    keys = set(got) | set(ref)
+    nch = len(s.chans)
+    worst = 0.0
+    for k in keys:
+        a = got.get(k, np.zeros((nch, nch)))
+        b = ref.get(k, np.zeros((nch, nch)))
+        worst = max(worst, np.abs(a - b).max())
+    assert worst <= 1e-12 * scale, (name, worst / scale)
+    only = (set(got) ^ set(ref))
+    for k in only:
+        v = got.get(k, ref.get(k))
+        assert np.abs(v).max() <= 1e-12 * scale
+    assert L.perm_stats["blocks"] == len(got)
+    # CSR validity: sorted-unique columns per row and monotone row pointer
+    rp, col, _ = L.export_perm()
+    assert np.all(np.diff(rp) >= 0) and rp[0] == 0 and rp[-1] == len(col)
+    for r in range(len(rp) - 1):
+        c = col[rp[r]:rp[r + 1]]
+        assert len(np.unique(c)) == len(c)
+
+
+def test_p0_fp32_is_rounded_fp64(systems):
+    spec = SPECS["doublet_mt_20"]
+    L64 = _lib_lattice(spec, "fp64")
+    L32 = _lib_lattice(spec, "fp32")
+    r64, c64, v64 = L64.export_perm()
+    r32, c32, v32 = L32.export_perm()
+    assert np.array_equal(r64, r32) and np.array_equal(c64, c32)
+    assert np.array_equal(v32, v64.astype(np.float32).astype(np.float64))
+
+
+def test_p0_rebuild_is_bit_identical():
+    spec = SPECS["quartet_yam_24"]
+    L = _lib_lattice(spec)
+    a = L.export_perm()
+    L.build_perm("fp64")
+    b = L.export_perm()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,E", [("quartet_yam_24", 1.0), ("quartet_yam_24", 3.0), ("quartet_yam_24", 10.0),
+                                    ("doublet_mt_20", 3.0), ("doublet_mt_20", 14.1),
+                                    ("quartet_yam_ragged_17x13", 10.0)])
+def test_solve_fp64_matches_oracle(systems, name, E):
+    s = systems[name]
+    L = _lib_lattice(SPECS[name])
+    sol = L.solve([E], "fp64")
+    got = sol.amplitude(0)
+    ref = pipeline.solve_energy(s, E)
+    a, b = got["A"][0, 0], ref["A"][0, 0]
+    bound = 1e-10 * abs(b) + 30 * max(got["err"][0], ref["rel_err"]) * abs(b)
+    if name.startswith("quartet"):
+        bound = 1e-10 * abs(b)
+    assert abs(a - b) <= bound, (abs(a - b) / abs(b), got["err"], ref["rel_err"])
+    if SPECS[name].M * SPECS[name].N * len(s.chans) <= 1000:
+        d = pipeline.solve_energy(s, E, direct=True)
+        assert abs(a - d["A"][0, 0]) <= 1e-10 * abs(b) + 30 * got["err"][0] * abs(b)
+    if E < 1.5 * 2.2246:   # below breakup: |S| = 1 for the discrete system
+        assert abs(abs(got["S"][0, 0]) - 1.0) < 1e-9
+
+
+def test_batched_energies_equal_single():
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    Es = [2.0, 7.5, 14.1, 31.0]
+    many = L.solve(Es, "fp64")
+    for k, E in enumerate(Es):
+        one = L.solve([E], "fp64").amplitude(0)
+        assert np.array_equal(many.amplitude(k)["A"], one["A"])
+
+
+def test_batch_api_matches_solve():
+    """Continuous batching: results equal the solo solve, whatever the batch-mates."""
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    import ctypes as C
+    o = wp._SolveOpts(wp.WP_SOLVE_FP64, 1e-12, 1e-7, 200, 0)
+    b = C.c_void_p()
+    wp._check(wp._lib.faddeev_batch_create(L.h, 3, 1 << 30, C.byref(o), C.byref(b)))
+    queue = [5.0, 14.1, 2.5, 40.0, 9.0]
+    results = {}
+    slot_E = {}
+    n_done = C.c_int()
+    done = (C.c_int * 8)()
+    stream = wp.current_stream()
+    steps = 0
+    while (queue or slot_E) and steps < 500:
+        while queue:
+            sl = C.c_int()
+            st = wp._lib.faddeev_batch_admit(b, queue[0], C.byref(sl))
+            if st == wp.WP_EBUDGET:
+                break
+            wp._check(st)
+            slot_E[sl.value] = queue.pop(0)
+        wp._check(wp._lib.faddeev_batch_step(b, stream, 4, C.byref(n_done), done))
+        for k in range(n_done.value):
+            sl = done[k]
+            h = C.c_void_p()
+            wp._check(wp._lib.faddeev_batch_take(b, sl, C.byref(h)))
+            results[slot_E.pop(sl)] = wp.amplitude(h, 0)
+            wp._lib.wp_solution_free(h)
+        steps += 1
+    wp._lib.faddeev_batch_free(b)
+    assert len(results) == 5
+    for E, r in results.items():
+        solo = L.solve([E], "fp64").amplitude(0)
+        assert np.array_equal(r["A"], solo["A"]), E
