@@ -73,7 +73,7 @@ typedef struct wp_batch wp_batch;
  *   grid_kind 1: explicit edges p_edges[M+1], q_edges[N+1], [0] = 0, strictly increasing.
  * Channels: l + s + t odd, T = 1/2 (two_T must be 1), (-1)^(l+lam) = parity, j <= j_max;
  * swave_only keeps l = lam = 0. Canonical order: sorted by (j, l, s, lam, 2I).
- * n_x, n_phi: Gauss-Legendre points of the (x, phi) rule of the P0 elements, 1..32 each.
+ * n_x, n_phi: Gauss-Legendre points of the (x, phi) rule of the P0 elements, 1..16 each.
  * Limits: 2 <= M, N <= 1024; at most 32 channels.
  */
 typedef struct {
@@ -218,6 +218,17 @@ wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, int* n_done, 
 wp_status faddeev_batch_take(wp_batch* b, int slot, wp_solution** out);
 wp_status faddeev_batch_live(const wp_batch* b, int* n_live);
 void faddeev_batch_free(wp_batch* b);
+
+/*
+ * Measurement: when enabled, every kernel launch of the library is bracketed by HIP events
+ * recorded on the stream it is launched on. wp_profile_read aggregates the records (waiting on
+ * their events) by kernel name: with i < 0 it only reports n_kernels; for 0 <= i < n_kernels it
+ * fills name (>= 64 bytes), launches and total_ms (sum of the event-measured durations).
+ * wp_profile_reset drops all records. Process-wide; not for use from several threads at once.
+ */
+wp_status wp_profile_enable(int on);
+wp_status wp_profile_read(int i, int* n_kernels, char* name, int64_t* launches, double* total_ms);
+wp_status wp_profile_reset(void);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,9 @@ _SIGS = {
     "faddeev_batch_take": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     "faddeev_batch_live": (C.c_int, [_P, _I]),
     "faddeev_batch_free": (None, [_P]),
+    "wp_profile_enable": (C.c_int, [C.c_int]),
+    "wp_profile_read": (C.c_int, [C.c_int, _I, C.c_char_p, C.POINTER(C.c_int64), _D]),
+    "wp_profile_reset": (C.c_int, []),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -139,7 +142,10 @@ class TorchAllocator:
 
 
 def current_stream():
+    """torch's current HIP stream as a void* (None when no GPU is visible)."""
     import torch
+    if not torch.cuda.is_available():
+        return None
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
@@ -197,6 +203,28 @@ def amplitude(sol, e_idx):
                 delta=dl, eta=et, err=er, iters=np.array(list(it)))
 
 
+def wp_profile_enable(on=True):
+    _check(_lib.wp_profile_enable(1 if on else 0))
+
+
+def wp_profile_reset():
+    _check(_lib.wp_profile_reset())
+
+
+def wp_profile_read():
+    """{kernel name: (launches, total ms)} from the HIP events recorded around each launch."""
+    n = C.c_int()
+    _check(_lib.wp_profile_read(-1, C.byref(n), None, None, None))
+    out = {}
+    for i in range(n.value):
+        buf = C.create_string_buffer(64)
+        cnt = C.c_int64()
+        ms = C.c_double()
+        _check(_lib.wp_profile_read(i, None, buf, C.byref(cnt), C.byref(ms)))
+        out[buf.value.decode()] = (cnt.value, ms.value)
+    return out
+
+
 # ---------------------------------------------------------------- convenience wrapper
 
 class Solution:
@@ -208,7 +236,7 @@ class Solution:
     def amplitude(self, e_idx=0):
         return amplitude(self.h, e_idx)
 
-    def __del__(self):
+    def __del__(self, _lib=_lib):
         if getattr(self, "h", None) is not None and self.h.value:
             _lib.wp_solution_free(self.h)
             self.h = None
@@ -285,7 +313,7 @@ class Lattice:
                               stream if stream is not None else current_stream(), allow_noconv)
         return Solution(h, len(E), ok)
 
-    def __del__(self):
+    def __del__(self, _lib=_lib):
         if getattr(self, "h", None) is not None and self.h.value:
             _lib.wp_lattice_free(self.h)
             self.h = None

@@ -151,10 +151,10 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
   if (!any) return WP_OK;
   for (int t = 0; t < terms; ++t) {
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
-    HIPCHECK(launch_rot64(ro, b->dy.p, b->dt.p, st));
+    WP_LAUNCH("rot64_O", st, launch_rot64(ro, b->dy.p, b->dt.p, st));
     RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, b->dj0.p, b->dfin.p, nf, 0};
-    HIPCHECK(launch_rot64(rw, b->dt.p, b->ds.p, st));
-    HIPCHECK(launch_spmv64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
+    WP_LAUNCH("rot64_W", st, launch_rot64(rw, b->dt.p, b->ds.p, st));
+    WP_LAUNCH("spmv64", st, launch_spmv64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
   }
   HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
                           st));

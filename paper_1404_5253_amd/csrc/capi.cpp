@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <thread>
@@ -26,6 +27,106 @@ wp_status wpcd::fail(wp_status st, const std::string& msg) {
 
 
 extern "C" const char* wp_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ launch profiling
+
+namespace {
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<std::string, std::pair<int64_t, double>>> agg;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+}  // namespace
+
+wpcd::ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+  Profiler& p = prof();
+  if (!p.on) return;
+  std::lock_guard<std::mutex> g(p.mu);
+  a = p.get();
+  if (a) (void)hipEventRecord(a, st);
+}
+
+wpcd::ProfScope::~ProfScope() {
+  if (!a) return;
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  hipEvent_t b = p.get();
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  p.recs.push_back({name, a, b});
+}
+
+extern "C" wp_status wp_profile_enable(int on) {
+  prof().on = on != 0;
+  return WP_OK;
+}
+
+extern "C" wp_status wp_profile_reset(void) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  for (auto& r : p.recs) {
+    p.pool.push_back(r.a);
+    p.pool.push_back(r.b);
+  }
+  p.recs.clear();
+  p.agg.clear();
+  return WP_OK;
+}
+
+extern "C" wp_status wp_profile_read(int i, int* n, char* name, int64_t* launches, double* total_ms) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> g(p.mu);
+  if (!p.recs.empty()) {
+    std::map<std::string, std::pair<int64_t, double>> m;
+    for (auto& r : p.recs) {
+      HIPCHECK(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      auto& e = m[r.name];
+      e.first += 1;
+      e.second += ms;
+      p.pool.push_back(r.a);
+      p.pool.push_back(r.b);
+    }
+    p.recs.clear();
+    for (auto& kv : p.agg) {
+      auto& e = m[kv.first];
+      e.first += kv.second.first;
+      e.second += kv.second.second;
+    }
+    p.agg.assign(m.begin(), m.end());
+  }
+  if (n) *n = (int)p.agg.size();
+  if (i < 0) return WP_OK;
+  if (i >= (int)p.agg.size()) return fail(WP_EINVAL, "profile index out of range");
+  if (name) {
+    std::strncpy(name, p.agg[i].first.c_str(), 63);
+    name[63] = 0;
+  }
+  if (launches) *launches = p.agg[i].second.first;
+  if (total_ms) *total_ms = p.agg[i].second.second;
+  return WP_OK;
+}
 
 void* DevAlloc::alloc(size_t bytes) {
   if (bytes == 0) bytes = 1;
@@ -376,9 +477,9 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, s));
-  HIPCHECK(launch_select(a, cnt.p, lo.p, s));
-  HIPCHECK(launch_rowseg(M, N, cnt.p, segoff.p, rowcnt.p, s));
-  HIPCHECK(launch_scan(rowcnt.p, rowptr_c.p, R, tmp.p, s));
+  WP_LAUNCH("select", s, launch_select(a, cnt.p, lo.p, s));
+  WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt.p, segoff.p, rowcnt.p, s));
+  WP_LAUNCH("scan", s, launch_scan(rowcnt.p, rowptr_c.p, R, tmp.p, s));
   int64_t ncand = 0;
   HIPCHECK(hipMemcpyAsync(&ncand, rowptr_c.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -388,13 +489,13 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   if (!col_c.make(&L->al, std::max<int64_t>(ncand, 1)) || !val_c.make(&L->al, std::max<int64_t>(ncand, 1) * nc2) ||
       !flag.make(&L->al, std::max<int64_t>(ncand, 1)))
     return fail(WP_ENOMEM, "device allocation (candidates)");
-  if (ncand > 0) HIPCHECK(launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
+  if (ncand > 0) WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
   if (ncand > 0) {
-    HIPCHECK(launch_rowcount(R, rowptr_c.p, flag.p, rowcnt.p, s));
+    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c.p, flag.p, rowcnt.p, s));
   } else {
     HIPCHECK(hipMemsetAsync(rowcnt.p, 0, R * sizeof(int64_t), s));
   }
-  HIPCHECK(launch_scan(rowcnt.p, rowptr.p, R, tmp.p, s));
+  WP_LAUNCH("scan", s, launch_scan(rowcnt.p, rowptr.p, R, tmp.p, s));
   int64_t nblk = 0;
   HIPCHECK(hipMemcpyAsync(&nblk, rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -408,8 +509,8 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     if (!L->d_val32.make(&L->al, std::max<int64_t>(nblk, 1) * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
   }
   if (ncand > 0)
-    HIPCHECK(launch_compact(R, nch, rowptr_c.p, col_c.p, val_c.p, flag.p, rowptr.p, L->d_col.p, L->d_val64.p,
-                            L->d_val32.p, s));
+    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c.p, col_c.p, val_c.p, flag.p, rowptr.p, L->d_col.p,
+                                           L->d_val64.p, L->d_val32.p, s));
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -537,10 +638,10 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
     int T = std::min(chunk, max_iter - n);
     for (int t = 0; t < T; ++t) {
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin, (int64_t)(n + t) * B * nfin};
-      HIPCHECK(launch_rot64(ro, dy.p, dt.p, s));
+      WP_LAUNCH("rot64_O", s, launch_rot64(ro, dy.p, dt.p, s));
       RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, dj0.p, dfin.p, nfin, 0};
-      HIPCHECK(launch_rot64(rw, dt.p, ds.p, s));
-      HIPCHECK(launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+      WP_LAUNCH("rot64_W", s, launch_rot64(rw, dt.p, ds.p, s));
+      WP_LAUNCH("spmv64", s, launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
     }
     HIPCHECK(hipMemcpyAsync(hcap.data(), dacap.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(double2),
                             hipMemcpyDeviceToHost, s));

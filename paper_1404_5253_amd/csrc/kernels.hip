@@ -1,10 +1,9 @@
 // gfx950 kernels of the WPCD hot path.
 //
 // P0 build (steps 2 and 3 of the paper's Sec. V.A; Appendix, final formula):
-//   k_select   one workgroup per q-box (j, j'): every lane owns one (x, phi) quadrature node
-//              and walks the p rows i with two monotone pointers over the p' edges; the
-//              per-node ranges of p' bins with F > 0 are merged across the wavefront with
-//              shuffles and across wavefronts with LDS atomics into one hull per (box, i).
+//   k_select   one workgroup per q-box (j, j'): node tables in LDS, lanes over p rows i; the
+//              p' range with F > 0 at any node is bracketed by the extreme node bounds and
+//              located by binary search: one hull [lo, lo + cnt) per (box, i).
 //   k_rowseg   per lattice row (j, i): offsets of the box segments and the row total.
 //   k_scan_*   exclusive scans (row offsets of the candidate and of the final block-CSR).
 //   k_pbuild   one wavefront per q-box: node tables and moment weights in LDS, one candidate
@@ -65,54 +64,67 @@ __device__ Node box_node(const PBuildArgs& a, int j, int jp, int nd) {
 
 // ------------------------------------------------------------------ step 2: selection
 
-__global__ void __launch_bounds__(256) k_select(PBuildArgs a, int* __restrict__ cnt, int* __restrict__ lo_out) {
+__global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ cnt, int* __restrict__ lo_out) {
+  // One workgroup per q-box (j, j'); lanes over p rows i. For row i and node n, F > 0 needs
+  // A_n < B_n with A_n = max(Q1_n, p_{i-1}/zeta2_n), B_n = min(Q2_n, p_i/zeta2_n) and p' in
+  // (A_n zeta1_n, B_n zeta1_n). The union over nodes is covered by the p' bins meeting
+  // (min_n A_n zeta1_n, max_n B_n zeta1_n), found by two binary searches, widened by one bin.
   extern __shared__ double sh[];
   const int M = a.M;
-  double* spe = sh;                                   // M + 1
-  int* slo = reinterpret_cast<int*>(spe + M + 1);     // M
-  int* shi = slo + M;                                 // M
+  const int nn = a.n_x * a.n_phi;
+  double* spe = sh;              // M + 1
+  double* s_r2 = spe + M + 1;    // nn
+  double* s_z1 = s_r2 + nn;
+  double* s_Q1 = s_z1 + nn;
+  double* s_Q2 = s_Q1 + nn;
   const int box = blockIdx.x;
   const int j = box / a.N, jp = box - j * a.N;
-  const int nn = a.n_x * a.n_phi;
-  const int t = threadIdx.x, lane = t & 63;
+  const int t = threadIdx.x;
   for (int i = t; i <= M; i += blockDim.x) spe[i] = a.pe[i];
-  for (int i = t; i < M; i += blockDim.x) {
-    slo[i] = 0x7fffffff;
-    shi[i] = -1;
+  for (int nd = t; nd < nn; nd += blockDim.x) {
+    Node n = box_node(a, j, jp, nd);
+    s_r2[nd] = n.r2;
+    s_z1[nd] = n.z1;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
   }
   __syncthreads();
-  const bool valid = t < nn;
-  Node n{};
-  if (valid) n = box_node(a, j, jp, t);
-  int lp = 0, hp = 0;  // monotone pointers over p' bins
-  for (int i = 0; i < M; ++i) {
-    int mylo = 0x7fffffff, myhi = -1;
-    if (valid) {
-      double A = fmax(n.Q1, spe[i] * n.r2);
-      double B = fmin(n.Q2, spe[i + 1] * n.r2);
+  for (int i = t; i < M; i += blockDim.x) {
+    const double pa = spe[i], pb = spe[i + 1];
+    double xlo = INFINITY, xhi = -INFINITY;
+    for (int nd = 0; nd < nn; ++nd) {
+      const double r2 = s_r2[nd];
+      const double A = fmax(s_Q1[nd], pa * r2);
+      const double B = fmin(s_Q2[nd], pb * r2);
       if (A < B) {
-        double Az = A * n.z1, Bz = B * n.z1;
-        while (lp < M - 1 && spe[lp + 1] <= Az) ++lp;   // first bin with upper edge > A zeta1
-        while (hp < M - 1 && spe[hp + 1] < Bz) ++hp;    // last bin with lower edge < B zeta1
-        mylo = lp;
-        myhi = hp;
+        xlo = fmin(xlo, A * s_z1[nd]);
+        xhi = fmax(xhi, B * s_z1[nd]);
       }
     }
-    mylo = wave_min(mylo);
-    myhi = wave_max(myhi);
-    if (lane == 0 && myhi >= 0) {
-      atomicMin(&slo[i], mylo);
-      atomicMax(&shi[i], myhi);
-    }
-  }
-  __syncthreads();
-  for (int i = t; i < M; i += blockDim.x) {
-    int l = slo[i], h = shi[i];
     int c = 0, l2 = 0;
-    if (h >= 0 && h >= l) {
-      l2 = max(0, l - 1);
-      int h2 = min(M - 1, h + 1);
-      c = h2 - l2 + 1;
+    if (xlo < xhi) {
+      // lo: first bin i' with p'_{i'} (upper edge spe[i'+1]) > xlo
+      int lo = 0, hi = M;   // search smallest e in [1, M] with spe[e] > xlo
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (spe[mid] > xlo) hi = mid;
+        else lo = mid + 1;
+      }
+      int blo = max(lo - 1, 0);
+      // hi: last bin i' with lower edge spe[i'] < xhi
+      lo = 0;
+      hi = M;
+      while (lo < hi) {  // smallest e in [0, M] with spe[e] >= xhi
+        int mid = (lo + hi) >> 1;
+        if (spe[mid] >= xhi) hi = mid;
+        else lo = mid + 1;
+      }
+      int bhi = min(lo - 1, M - 1);
+      if (bhi >= blo) {
+        l2 = max(0, blo - 1);
+        int h2 = min(M - 1, bhi + 1);
+        c = h2 - l2 + 1;
+      }
     }
     cnt[(size_t)box * M + i] = c;
     lo_out[(size_t)box * M + i] = l2;
@@ -122,9 +134,8 @@ __global__ void __launch_bounds__(256) k_select(PBuildArgs a, int* __restrict__ 
 hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) {
   int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > 256 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
-  int threads = ((nn + 63) / 64) * 64;
-  size_t shmem = (a.M + 1) * sizeof(double) + 2 * a.M * sizeof(int);
-  hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(threads), shmem, s, a, cnt, lo);
+  size_t shmem = (a.M + 1) * sizeof(double) + 4 * nn * sizeof(double);
+  hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(128), shmem, s, a, cnt, lo);
   return hipGetLastError();
 }
 

@@ -68,6 +68,20 @@ struct wp_solution {
 
 namespace wpcd {
 
+// Launch profiling (wp_profile_*): records a pair of events around a launch on its stream.
+struct ProfScope {
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t s);
+  ~ProfScope();
+};
+#define WP_LAUNCH(name, stream, expr)        \
+  do {                                       \
+    wpcd::ProfScope ps_(name, stream);       \
+    HIPCHECK(expr);                          \
+  } while (0)
+
 wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
 // G1 over (k, j) of one pair wave at three-body energy E (host FP64, threaded over k)

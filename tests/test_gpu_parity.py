@@ -6,8 +6,8 @@ Tolerances (FP64 path):
     whether they are stored, nothing else may);
   * amplitudes of a convergent series (quartet): |dA| <= 1e-10 |A|;
   * divergent series (doublet): Pade stops on a rounding plateau; |dA| <= 1e-10 |A| + 30 x the
-    larger of the two error estimates, and the HIP result must also agree with the oracle's
-    dense LU solve within that bound.
+    larger of the two error estimates against the oracle's Pade, and <= 1e-8 |A| against the
+    oracle's dense LU solve of the same discrete system (the measured Pade floor is ~1e-9).
 """
 import numpy as np
 import pytest
@@ -125,8 +125,11 @@ def test_solve_fp64_matches_oracle(systems, name, E):
         bound = 1e-10 * abs(b)
     assert abs(a - b) <= bound, (abs(a - b) / abs(b), got["err"], ref["rel_err"])
     if SPECS[name].M * SPECS[name].N * len(s.chans) <= 1000:
+        # against the exact discrete solution (dense LU): Pade on the divergent doublet series
+        # reaches about 1e-9 relative (measured), the convergent quartet series 1e-12
         d = pipeline.solve_energy(s, E, direct=True)
-        assert abs(a - d["A"][0, 0]) <= 1e-10 * abs(b) + 30 * got["err"][0] * abs(b)
+        lim = 1e-10 if name.startswith("quartet") else 1e-8
+        assert abs(a - d["A"][0, 0]) <= lim * abs(d["A"][0, 0])
     if E < 1.5 * 2.2246:   # below breakup: |S| = 1 for the discrete system
         assert abs(abs(got["S"][0, 0]) - 1.0) < 1e-9
 

@@ -1,0 +1,81 @@
+"""CPU tests of libwpcd: symbol exports, argument checking, call order and the host FP64 steps
+(channels, pseudostates, strength tuning, G1) against the oracle. No GPU work is started."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1404_5253_amd as wp
+from oracle import channels, lattice as olat, pipeline, resolvent
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "wpcd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert "perm_matrix_build" in names and "faddeev_solve" in names and "amplitude" in names
+    lib = C.CDLL(wp.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(wp.exported_symbols())
+
+
+def test_argument_errors_and_call_order():
+    with pytest.raises(wp.WpError) as e:
+        wp.wp_lattice_build(1, 10)
+    assert e.value.status == wp.WP_EINVAL
+    with pytest.raises(wp.WpError):
+        wp.wp_lattice_build(10, 10, n_x=40)
+    with pytest.raises(wp.WpError):
+        wp.wp_lattice_build(10, 10, p_edges=np.array([0.0] + [1.0] * 10), q_edges=np.linspace(0, 1, 11))
+    L = wp.Lattice(8, 8, two_J=3, torch_alloc=False)
+    with pytest.raises(wp.WpError) as e:
+        L.solve([10.0])
+    assert e.value.status == wp.WP_ENOTREADY
+    with pytest.raises(wp.WpError) as e:
+        L.resolvent(10.0, 0)
+    assert e.value.status == wp.WP_ENOTREADY
+    assert wp._lib.perm_matrix_export(L.h, None, None, None) == wp.WP_ENOTREADY
+    assert b"perm_matrix_build" in wp._lib.wp_last_error()
+
+
+@pytest.mark.parametrize("two_J,j_max,swave", [(1, 2, False), (1, 1, True), (3, 1, True), (3, 2, False)])
+def test_channels_match_oracle(two_J, j_max, swave):
+    L = wp.Lattice(6, 6, two_J=two_J, j_max=j_max, swave_only=swave, torch_alloc=False)
+    ref = channels.enumerate_channels(two_J, +1, j_max)
+    if swave:
+        ref = [c for c in ref if c[0] == 0 and c[3] == 0]
+    assert L.channels == ref
+
+
+@pytest.mark.parametrize("pot,two_J", [("yamaguchi", 3), ("mt", 1)])
+def test_pseudostates_and_g1_match_oracle(pot, two_J):
+    M = 20
+    L = wp.Lattice(M, M, two_J=two_J, torch_alloc=False)
+    eps0, strength = L.pseudostates(kind=pot)
+    s = pipeline.build_system(pipeline.Spec(M=M, N=M, two_J=two_J, pot=pot))
+    assert strength == pytest.approx(s.strength, rel=1e-12)
+    assert eps0 == pytest.approx(-2.2246, abs=1e-12)
+    pe, qe = L.edges()
+    assert np.allclose(pe, s.p_edges, rtol=1e-15, atol=0) and np.allclose(qe, s.q_edges, rtol=1e-15, atol=0)
+    for a, ch in enumerate(L.channels):
+        nb, eps, O, bins = L.pseudostate_data(a)
+        d = s.pair[(ch[0], ch[1])]
+        assert nb == d["nb"]
+        assert np.allclose(eps, d["eps"], rtol=1e-11, atol=1e-11)
+        assert np.allclose(np.abs(O), np.abs(d["O"]), atol=1e-10)      # eigenvector signs are free
+        assert np.allclose(O @ O.T, np.eye(M), atol=1e-13)
+        assert np.allclose(bins, d["bins"], rtol=1e-12)
+        for E_lab in (2.0, 14.1):
+            G = L.resolvent(E_lab, a)
+            Go = resolvent.channel_diagonal(s.q_edges, olat.total_energy(E_lab, s.eps0),
+                                            list(d["eps"][:d["nb"]]), d["bins"])
+            assert np.max(np.abs(G - Go)) <= 1e-10 * np.max(np.abs(Go))
