@@ -2,7 +2,7 @@
 //
 // A batch owns max_slots energy slots; slot s uses the columns s*n_open .. s*n_open + n_open - 1
 // of the solve vectors (one column per open initial channel). Admission computes the slot's G1
-// on the host (FP64), uploads it into the slot's columns and builds the slot's right-hand side
+// on the device (FP64) straight into the slot's columns and builds the slot's right-hand side
 // b = P0 (v O^T) e0 with column-range kernels, so live slots are not disturbed. A step advances
 // every column by `terms` Neumann terms with the same launches as faddeev_solve. The kernels
 // are column-wise with a fixed reduction order, so a slot's numbers do not depend on which
@@ -19,6 +19,7 @@ struct wp_batch {
   int64_t D = 0;
   DBuf<double2> dG, dy, dt, ds, dacap;
   DBuf<int> dj0, dg0, dfin;
+  DBuf<double> dE;   // three-body energy of each slot
   std::vector<int> j0, g0;
   struct Slot {
     bool live = false, done = false;
@@ -53,7 +54,7 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   DevAlloc* al = &L->al;
   if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
       !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
-      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin))
+      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin) || !b->dE.make(al, cap))
     return fail(WP_ENOMEM, "device allocation (batch)");
   for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
   b->j0.assign(B, 0);
@@ -77,28 +78,6 @@ extern "C" wp_status faddeev_batch_live(const wp_batch* b, int* n) {
   return WP_OK;
 }
 
-// Set G1 of a slot's columns (host values, or zeros when gw is null) on stream st.
-static wp_status put_slot_g1(wp_batch* b, int slot, const std::vector<std::vector<cplx>>* gw, hipStream_t st) {
-  const wp_lattice* L = b->L;
-  const int M = L->M, N = L->N, nch = L->nch, nf = b->nfin, B = b->B;
-  std::vector<double2> h((size_t)b->D * nf);
-  for (int j = 0; j < N; ++j)
-    for (int k = 0; k < M; ++k)
-      for (int g = 0; g < nch; ++g) {
-        double2 v = make_double2(0.0, 0.0);
-        if (gw) {
-          cplx z = (*gw)[L->wave_of[g]][(size_t)k * N + j];
-          v = make_double2(z.real(), z.imag());
-        }
-        for (int f = 0; f < nf; ++f) h[(((size_t)j * M + k) * nch + g) * nf + f] = v;
-      }
-  // rows of the [D][B] array, the slot's nf consecutive columns
-  HIPCHECK(hipStreamSynchronize(st));
-  HIPCHECK(hipMemcpy2D(b->dG.p + (size_t)slot * nf, B * sizeof(double2), h.data(), nf * sizeof(double2),
-                       nf * sizeof(double2), b->D, hipMemcpyHostToDevice));
-  return WP_OK;
-}
-
 extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   if (!b || !slot) return fail(WP_EINVAL, "NULL argument");
   if (!(E_lab > 0)) return fail(WP_EINVAL, "E_lab must be positive");
@@ -113,20 +92,15 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   auto& S = b->s[sl];
   S = wp_batch::Slot();
   if (!kinematics(L, E_lab, S.r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
-  std::vector<std::vector<cplx>> gw(L->waves.size());
-  try {
-    for (size_t w = 0; w < L->waves.size(); ++w) g1_wave(L, L->waves[w], S.r.E, gw[w]);
-  } catch (const std::exception& e) {
-    return fail(WP_EINTERNAL, e.what());
-  }
   const int nf = b->nfin, c0 = sl * nf;
   hipStream_t st = nullptr;
-  if (wp_status e = put_slot_g1(b, sl, &gw, st)) return e;
+  HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
+  WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, b->B, b->dG.p), st));
   for (int f = 0; f < nf; ++f) b->j0[c0 + f] = S.r.j0;
   HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, b->B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
                              c0 + nf));
-  HIPCHECK(launch_spmv64((int64_t)L->M * L->N, L->nch, b->B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
+  HIPCHECK(launch_spmv_f64((int64_t)L->M * L->N, L->nch, b->B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
                          b->dy.p, st, c0, c0 + nf));
   HIPCHECK(hipStreamSynchronize(st));
   S.cs.resize(nf);
@@ -151,10 +125,8 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
   if (!any) return WP_OK;
   for (int t = 0; t < terms; ++t) {
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
-    WP_LAUNCH("rot64_O", st, launch_rot64(ro, b->dy.p, b->dt.p, st));
-    RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, b->dj0.p, b->dfin.p, nf, 0};
-    WP_LAUNCH("rot64_W", st, launch_rot64(rw, b->dt.p, b->ds.p, st));
-    WP_LAUNCH("spmv64", st, launch_spmv64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
+    WP_LAUNCH("step64", st, launch_step64(ro, L->d_W.p, b->dy.p, b->ds.p, st));
+    WP_LAUNCH("spmv64", st, launch_spmv_f64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
   }
   HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
                           st));
@@ -192,7 +164,8 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
         S.r.iters[f0] = cs.n;
         S.r.ok &= cs.ok;
       }
-      if (wp_status e = put_slot_g1(b, sl, nullptr, st)) return e;
+      // finished: G1 = 0 on the slot's columns keeps its vectors at zero until it is reused
+      HIPCHECK(launch_fill0_cols(b->dG.p, b->D, b->B, sl * nf, sl * nf + nf, st));
       if (done_slots) done_slots[*n_done] = sl;
       ++*n_done;
     }

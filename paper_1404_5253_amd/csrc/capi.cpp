@@ -383,6 +383,8 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
   return WP_OK;
 }
 
+static wp_status upload_tables(wp_lattice* L);
+
 // device copies of O and W of every pair wave and the channel -> wave map (first GPU use)
 wp_status wpcd::upload_waves(wp_lattice* L) {
   if (L->d_O.p) return WP_OK;
@@ -397,7 +399,72 @@ wp_status wpcd::upload_waves(wp_lattice* L) {
   HIPCHECK(hipMemcpy(L->d_O.p, O.data(), O.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_W.p, W.data(), W.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_wave.p, L->wave_of.data(), L->nch * sizeof(int), hipMemcpyHostToDevice));
+  // G1 tables
+  const int nw = (int)L->waves.size(), M = L->M;
+  std::vector<double> bins((size_t)nw * (M + 1), 0.0), epsb(nw, 0.0);
+  std::vector<int> nb(nw);
+  for (int w = 0; w < nw; ++w) {
+    std::copy(L->waves[w].bins.begin(), L->waves[w].bins.end(), bins.begin() + (size_t)w * (M + 1));
+    nb[w] = L->waves[w].nb;
+    epsb[w] = L->waves[w].nb ? L->waves[w].eps[0] : 0.0;
+  }
+  // tanh-sinh rule on [-1, 1]: t = k h, x = tanh(pi/2 sinh t), with the node position kept as a
+  // fraction of the interval measured from the nearer end
+  const double hts = 1.0 / 12.0;
+  const int K = 41;
+  std::vector<double> tu, tv, tw;
+  for (int k = -K; k <= K; ++k) {
+    double t = k * hts, sarg = 0.5 * M_PI * std::sinh(t);
+    tu.push_back(1.0 / (1.0 + std::exp(-2.0 * sarg)));
+    tv.push_back(1.0 / (1.0 + std::exp(2.0 * sarg)));
+    double ch = std::cosh(sarg);
+    tw.push_back(hts * 0.5 * M_PI * std::cosh(t) / (ch * ch));
+  }
+  std::vector<double> glx(20), glw(20);
+  gauss_legendre(20, glx.data(), glw.data());
+  L->nts = (int)tu.size();
+  L->ngl = 20;
+  if (!L->d_bins.make(&L->al, bins.size()) || !L->d_epsb.make(&L->al, nw) || !L->d_nb.make(&L->al, nw) ||
+      !L->d_ts_u.make(&L->al, tu.size()) || !L->d_ts_v.make(&L->al, tv.size()) || !L->d_ts_w.make(&L->al, tw.size()) ||
+      !L->d_gl_x.make(&L->al, 20) || !L->d_gl_w.make(&L->al, 20))
+    return fail(WP_ENOMEM, "device allocation (G1 tables)");
+  HIPCHECK(hipMemcpy(L->d_bins.p, bins.data(), bins.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_epsb.p, epsb.data(), nw * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_nb.p, nb.data(), nw * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_ts_u.p, tu.data(), tu.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_ts_v.p, tv.data(), tv.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_ts_w.p, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gl_x.p, glx.data(), 20 * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gl_w.p, glw.data(), 20 * 8, hipMemcpyHostToDevice));
   return WP_OK;
+}
+
+G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G) {
+  G1Args g{};
+  g.M = L->M;
+  g.N = L->N;
+  g.nch = L->nch;
+  g.B = B;
+  g.nwave = (int)L->waves.size();
+  g.nE = nE;
+  g.nrep = nrep;
+  g.col0 = col0;
+  g.qe = L->d_qe.p;
+  g.bins = L->d_bins.p;
+  g.nb = L->d_nb.p;
+  g.eps_b = L->d_epsb.p;
+  g.wave = L->d_wave.p;
+  g.E = dE;
+  g.ts_u = L->d_ts_u.p;
+  g.ts_v = L->d_ts_v.p;
+  g.ts_w = L->d_ts_w.p;
+  g.nts = L->nts;
+  g.gl_x = L->d_gl_x.p;
+  g.gl_w = L->d_gl_w.p;
+  g.ngl = L->ngl;
+  g.h2m = L->h2m;
+  g.G = G;
+  return g;
 }
 
 extern "C" wp_status wp_lattice_pseudostates(const wp_lattice* L, int channel, int* n_bound, double* eps, double* O,
@@ -414,21 +481,29 @@ extern "C" wp_status wp_lattice_pseudostates(const wp_lattice* L, int channel, i
 }
 
 
-extern "C" wp_status wp_lattice_resolvent(const wp_lattice* L, double E_lab, int channel, double* G) {
+extern "C" wp_status wp_lattice_resolvent(const wp_lattice* Lc, double E_lab, int channel, double* G) {
+  wp_lattice* L = const_cast<wp_lattice*>(Lc);
   if (!L || !G) return fail(WP_EINVAL, "NULL argument");
   if (!L->pseudo) return fail(WP_ENOTREADY, "twobody_pseudostates has not run");
   if (channel < 0 || channel >= L->nch) return fail(WP_EINVAL, "channel out of range");
   if (!(E_lab > 0)) return fail(WP_EINVAL, "E_lab must be positive");
-  std::vector<cplx> g;
-  try {
-    g1_wave(L, L->waves[L->wave_of[channel]], L->eps0 + 2.0 * E_lab / 3.0, g);
-  } catch (const std::exception& e) {
-    return fail(WP_EINTERNAL, e.what());
-  }
-  for (size_t e = 0; e < g.size(); ++e) {
-    G[2 * e] = g[e].real();
-    G[2 * e + 1] = g[e].imag();
-  }
+  if (wp_status st = upload_tables(L)) return st;
+  if (wp_status st = upload_waves(L)) return st;
+  const int64_t rows = (int64_t)L->M * L->N * L->nch;
+  DBuf<double2> dG;
+  DBuf<double> dE;
+  if (!dG.make(&L->al, rows) || !dE.make(&L->al, 1)) return fail(WP_ENOMEM, "device allocation (resolvent)");
+  const double E = L->eps0 + 2.0 * E_lab / 3.0;
+  HIPCHECK(hipMemcpy(dE.p, &E, 8, hipMemcpyHostToDevice));
+  WP_LAUNCH("g1", nullptr, launch_g1(g1_args(L, dE.p, 1, 1, 0, 1, dG.p), nullptr));
+  std::vector<double2> h(rows);
+  HIPCHECK(hipMemcpy(h.data(), dG.p, rows * sizeof(double2), hipMemcpyDeviceToHost));
+  for (int k = 0; k < L->M; ++k)
+    for (int j = 0; j < L->N; ++j) {
+      double2 v = h[((size_t)j * L->M + k) * L->nch + channel];
+      G[2 * ((size_t)k * L->N + j)] = v.x;
+      G[2 * ((size_t)k * L->N + j) + 1] = v.y;
+    }
   return WP_OK;
 }
 
@@ -551,31 +626,6 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
   return WP_OK;
 }
 
-// ------------------------------------------------------------------ G1 (host, FP64)
-
-// G1 over (k, j) for pair wave w at energy E: row k = 0 is the bound state (if any).
-void wpcd::g1_wave(const wp_lattice* L, const PairWave& pw, double E, std::vector<cplx>& out) {
-  const int M = L->M, N = L->N;
-  out.assign((size_t)M * N, cplx(0, 0));
-  const int nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  auto work = [&](int t0) {
-    for (int k = t0; k < M; k += nthreads) {
-      for (int j = 0; j < N; ++j) {
-        cplx g;
-        if (k < pw.nb)
-          g = g1_bound_continuum(L->qe[j], L->qe[j + 1], E, pw.eps[k], L->h2m);
-        else
-          g = g1_continuum(pw.bins[k - pw.nb], pw.bins[k - pw.nb + 1], L->qe[j], L->qe[j + 1], E, L->h2m);
-        out[(size_t)k * N + j] = g;
-      }
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);
-  work(0);
-  for (auto& x : th) x.join();
-}
-
 // ------------------------------------------------------------------ solve (FP64 path)
 
 
@@ -587,45 +637,38 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const int B = nE * nfin;  // columns: (energy, initial channel)
   const int64_t D = (int64_t)M * N * nch;
   const int64_t R = (int64_t)M * N;
-  // per-energy kinematics and G1
+  // per-energy kinematics; G1 is computed on the device
   std::vector<int> j0(B), g0(B);
-  std::vector<double2> Gh((size_t)D * B);
+  std::vector<double> Etot(nE);
   sol->res.resize(nE);
   for (int e = 0; e < nE; ++e) {
     EnergyResult& r = sol->res[e];
     if (!kinematics(L, Elab[e], r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
-    const int jj = r.j0;
-    std::vector<std::vector<cplx>> gw(L->waves.size());
-    for (size_t w = 0; w < L->waves.size(); ++w) g1_wave(L, L->waves[w], r.E, gw[w]);
+    Etot[e] = r.E;
     for (int b = 0; b < nfin; ++b) {
-      int c = e * nfin + b;
-      j0[c] = jj;
-      g0[c] = L->opens[b];
-      for (int j = 0; j < N; ++j)
-        for (int k = 0; k < M; ++k)
-          for (int g = 0; g < nch; ++g) {
-            cplx v = gw[L->wave_of[g]][(size_t)k * N + j];
-            Gh[(((size_t)j * M + k) * nch + g) * B + c] = make_double2(v.real(), v.imag());
-          }
+      j0[e * nfin + b] = r.j0;
+      g0[e * nfin + b] = L->opens[b];
     }
   }
   const int max_iter = std::max(4, std::min(1000, o.max_iter));
   const int chunk = 8;
+  if (wp_status us = upload_waves(L)) return us;
   DBuf<double2> dG, dy, dt, ds, dacap;
   DBuf<int> dj0, dg0, dfin;
+  DBuf<double> dE;
   if (!dG.make(&L->al, D * B) || !dy.make(&L->al, D * B) || !dt.make(&L->al, D * B) || !ds.make(&L->al, D * B) ||
       !dacap.make(&L->al, (size_t)(max_iter + chunk) * B * nfin) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
-      !dfin.make(&L->al, nfin))
+      !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");
-  HIPCHECK(hipMemcpyAsync(dG.p, Gh.data(), Gh.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p), s));
   HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
   const double* val = L->d_val64.p;
   if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
-  if (wp_status us = upload_waves(L)) return us;
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
-  HIPCHECK(launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
   std::vector<ColState> cs(B);
   for (auto& c : cs) {
     c.w.resize(nfin);
@@ -638,10 +681,8 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
     int T = std::min(chunk, max_iter - n);
     for (int t = 0; t < T; ++t) {
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin, (int64_t)(n + t) * B * nfin};
-      WP_LAUNCH("rot64_O", s, launch_rot64(ro, dy.p, dt.p, s));
-      RotArgs rw{M, N, nch, B, L->d_W.p, L->d_wave.p, nullptr, nullptr, dj0.p, dfin.p, nfin, 0};
-      WP_LAUNCH("rot64_W", s, launch_rot64(rw, dt.p, ds.p, s));
-      WP_LAUNCH("spmv64", s, launch_spmv64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
+      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
     }
     HIPCHECK(hipMemcpyAsync(hcap.data(), dacap.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(double2),
                             hipMemcpyDeviceToHost, s));
@@ -680,6 +721,259 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   return allok ? WP_OK : fail(WP_ENOCONV, "Pade summation did not reach the accepted accuracy for some energy");
 }
 
+
+// ------------------------------------------------------------------ solve (mixed path)
+
+static uint16_t host_bf16(double d) {
+  float f = (float)d;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
+  if (wp_status st = upload_waves(L)) return st;
+  const int M = L->M;
+  if (!L->d_Ob.p) {
+    const int Mp = (M + 15) / 16 * 16;
+    const size_t MM = (size_t)Mp * Mp;
+    std::vector<uint16_t> Ob(MM * L->waves.size(), 0), Wb(MM * L->waves.size(), 0);
+    for (size_t w = 0; w < L->waves.size(); ++w)
+      for (int r = 0; r < M; ++r)
+        for (int c = 0; c < M; ++c) {
+          Ob[w * MM + (size_t)r * Mp + c] = host_bf16(L->waves[w].O[(size_t)r * M + c]);
+          Wb[w * MM + (size_t)r * Mp + c] = host_bf16(L->waves[w].W[(size_t)r * M + c]);
+        }
+    if (!L->d_Ob.make(&L->al, Ob.size()) || !L->d_Wb.make(&L->al, Wb.size()))
+      return fail(WP_ENOMEM, "device allocation (bf16 blocks)");
+    HIPCHECK(hipMemcpy(L->d_Ob.p, Ob.data(), Ob.size() * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Wb.p, Wb.data(), Wb.size() * 2, hipMemcpyHostToDevice));
+    L->Mp = Mp;
+  }
+  if (!L->d_val32.p) {
+    const int64_t n = L->blocks * L->nch * L->nch;
+    if (!L->d_val32.make(&L->al, std::max<int64_t>(n, 1))) return fail(WP_ENOMEM, "device allocation (FP32 P0)");
+    if (n > 0) HIPCHECK(launch_cvt_scalar(n, L->d_val64.p, L->d_val32.p, s));
+  }
+  return WP_OK;
+}
+
+// [L/M] Pade of sum a_n: denominator q (q_0 = 1) from sum_{i=0}^{M} q_i a_{n-i} = 0, n = L+1..L+M
+// (complex Gaussian elimination with partial pivoting). Returns false if singular.
+static bool pade_denominator(const std::vector<cplx>& a, int Lp, int Mq, std::vector<cplx>& q) {
+  q.assign(Mq + 1, cplx(0, 0));
+  q[0] = 1.0;
+  if (Mq == 0) return true;
+  std::vector<cplx> H((size_t)Mq * (Mq + 1));
+  for (int r = 0; r < Mq; ++r) {
+    for (int i = 1; i <= Mq; ++i) {
+      int idx = Lp + 1 + r - i;
+      H[(size_t)r * (Mq + 1) + (i - 1)] = idx >= 0 ? a[idx] : cplx(0, 0);
+    }
+    H[(size_t)r * (Mq + 1) + Mq] = -a[Lp + 1 + r];
+  }
+  for (int c = 0; c < Mq; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < Mq; ++r)
+      if (std::abs(H[(size_t)r * (Mq + 1) + c]) > std::abs(H[(size_t)piv * (Mq + 1) + c])) piv = r;
+    if (std::abs(H[(size_t)piv * (Mq + 1) + c]) == 0.0) return false;
+    if (piv != c)
+      for (int k = 0; k <= Mq; ++k) std::swap(H[(size_t)c * (Mq + 1) + k], H[(size_t)piv * (Mq + 1) + k]);
+    for (int r = c + 1; r < Mq; ++r) {
+      cplx f = H[(size_t)r * (Mq + 1) + c] / H[(size_t)c * (Mq + 1) + c];
+      for (int k = c; k <= Mq; ++k) H[(size_t)r * (Mq + 1) + k] -= f * H[(size_t)c * (Mq + 1) + k];
+    }
+  }
+  for (int c = Mq - 1; c >= 0; --c) {
+    cplx v = H[(size_t)c * (Mq + 1) + Mq];
+    for (int k = c + 1; k < Mq; ++k) v -= H[(size_t)c * (Mq + 1) + k] * q[k + 1];
+    q[c + 1] = v / H[(size_t)c * (Mq + 1) + c];
+  }
+  for (auto& x : q)
+    if (!std::isfinite(x.real()) || !std::isfinite(x.imag())) return false;
+  return true;
+}
+
+// Weights w_m (m = 0..Lp) of the vector [Lp/Mq] approximant y = sum_m w_m v_m, whose projection
+// sum_m w_m a_m is the scalar Pade value P(1)/Q(1).
+static void pade_weights(const std::vector<cplx>& q, int Lp, std::vector<cplx>& w) {
+  const int Mq = (int)q.size() - 1;
+  cplx Q1 = 0.0;
+  for (auto& x : q) Q1 += x;
+  w.assign(Lp + 1, cplx(0, 0));
+  for (int m = 0; m <= Lp; ++m) {
+    cplx s = 0.0;
+    for (int i = 0; i <= std::min(Mq, Lp - m); ++i) s += q[i];
+    w[m] = s / Q1;
+  }
+}
+
+static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
+                             wp_solution* sol) {
+  const int M = L->M, N = L->N, nch = L->nch;
+  const int nfin = (int)L->opens.size();
+  const int nE = (int)Elab.size();
+  const int B = nE * nfin;
+  const int64_t D = (int64_t)M * N * nch;
+  const int64_t R = (int64_t)M * N;
+  const int64_t DB = D * B;
+  std::vector<int> j0(B), g0(B);
+  std::vector<double> Etot(nE);
+  sol->res.resize(nE);
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    if (!kinematics(L, Elab[e], r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
+    Etot[e] = r.E;
+    for (int b = 0; b < nfin; ++b) {
+      j0[e * nfin + b] = r.j0;
+      g0[e * nfin + b] = L->opens[b];
+    }
+  }
+  if (wp_status st = ensure_mixed(L, s)) return st;
+  const int Lmax = std::max(8, std::min(200, o.refine_every > 0 ? o.refine_every : 48));
+  const int max_outer = 8;
+  const int chunk = 8;
+  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dacap64, dcoef;
+  DBuf<float2> dG32, V, dt32, dacap32;
+  DBuf<int> dj0, dg0, dfin;
+  DBuf<double> dE;
+  if (!dG64.make(&L->al, DB) || !db.make(&L->al, DB) || !dy.make(&L->al, DB) || !dr.make(&L->al, DB) ||
+      !dKy.make(&L->al, DB) || !ds64.make(&L->al, DB) || !dacap64.make(&L->al, (size_t)B * nfin) ||
+      !dcoef.make(&L->al, (size_t)(Lmax + 1) * B) || !dG32.make(&L->al, DB) || !V.make(&L->al, (size_t)(Lmax + 1) * DB) ||
+      !dt32.make(&L->al, DB) || !dacap32.make(&L->al, (size_t)(Lmax + chunk) * B * nfin) || !dj0.make(&L->al, B) ||
+      !dg0.make(&L->al, B) || !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
+    return fail(WP_ENOMEM, "device allocation (mixed solve)");
+  HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG64.p), s));
+  HIPCHECK(launch_cvt_d2f(DB, dG64.p, dG32.p, s));
+  // b = P0 (v O^T) e0 with the FP32-stored P0, FP64 vectors and accumulation
+  HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds64.p, s));
+  WP_LAUNCH("spmv_f32v_f64x", s, launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s));
+  HIPCHECK(launch_fill0(dy.p, DB, s));
+  std::vector<cplx> U((size_t)B * nfin, cplx(0, 0)), Uy((size_t)B * nfin, cplx(0, 0));
+  std::vector<double> err(B, 1.0);
+  std::vector<int> iters(B, 0);
+  std::vector<bool> done(B, false);
+  std::vector<float2> hcap((size_t)chunk * B * nfin);
+  std::vector<double2> hcap64((size_t)B * nfin);
+  const double outer_tol = std::max(o.tol, 1e-14);
+  for (int outer = 0; outer < max_outer; ++outer) {
+    // FP64 residual r = b - (I - K) y and e^T O y of the current y
+    if (outer == 0) {
+      HIPCHECK(launch_cvt_d2f(DB, db.p, V.p, s));
+    } else {
+      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, dacap64.p, dj0.p, dfin.p, nfin, 0};
+      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
+      WP_LAUNCH("spmv_f32v_f64x", s, launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
+      HIPCHECK(launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
+      HIPCHECK(launch_cvt_d2f(DB, dr.p, V.p, s));
+      HIPCHECK(hipMemcpyAsync(hcap64.data(), dacap64.p, hcap64.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (size_t e = 0; e < Uy.size(); ++e) Uy[e] = cplx(hcap64[e].x, hcap64[e].y);
+    }
+    // mixed-precision Neumann terms of the correction, stored for the vector Pade
+    std::vector<ColState> cs(B);
+    std::vector<std::vector<std::vector<cplx>>> terms(B, std::vector<std::vector<cplx>>(nfin));
+    for (auto& c : cs) {
+      c.w.resize(nfin);
+      c.S.assign(nfin, cplx(0, 0));
+      c.plateau = 8;
+    }
+    int n = 0;
+    bool all = false;
+    while (n < Lmax && !all) {
+      const int T = std::min(chunk, Lmax - n);
+      for (int t = 0; t < T; ++t) {
+        RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, L->Mp, L->d_wave.p, dG32.p, dacap32.p, dj0.p, dfin.p, nfin,
+                        (int64_t)(n + t) * B * nfin};
+        WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, L->d_Wb.p, V.p + (size_t)(n + t) * DB, dt32.p, s));
+        WP_LAUNCH("spmv32", s, launch_spmv_f32(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, dt32.p,
+                                               V.p + (size_t)(n + t + 1) * DB, s));
+      }
+      HIPCHECK(hipMemcpyAsync(hcap.data(), dacap32.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(float2),
+                              hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      all = true;
+      for (int c = 0; c < B; ++c) {
+        for (int t = 0; t < T; ++t) {
+          std::vector<cplx> a(nfin);
+          for (int f = 0; f < nfin; ++f) {
+            float2 v = hcap[((size_t)t * B + c) * nfin + f];
+            a[f] = cplx(v.x, v.y);
+            terms[c][f].push_back(a[f]);
+          }
+          if (!cs[c].done) column_push(cs[c], a.data(), nfin, 1e-6, 1.0);
+        }
+        all &= cs[c].done || done[c];
+      }
+      n += T;
+    }
+    // vector Pade per column: the [L/M] (M <= 8, L = n - 1 - M) closest to Wynn's best estimate
+    std::vector<double2> coef((size_t)(Lmax + 1) * B, make_double2(0.0, 0.0));
+    bool any_active = false;
+    for (int c = 0; c < B; ++c) {
+      if (done[c]) continue;
+      any_active = true;
+      const int fi = c % nfin;  // the column's own initial channel defines the denominator
+      const std::vector<cplx>& a = terms[c][fi];
+      const cplx target = cs[c].best.empty() ? cs[c].last[fi] : cs[c].best[fi];
+      std::vector<cplx> bestw;
+      double bestd = INFINITY;
+      for (int Mq = 0; Mq <= 8 && 2 * Mq + 1 <= n; ++Mq) {
+        const int Lp = n - 1 - Mq;
+        std::vector<cplx> q, w;
+        if (!pade_denominator(a, Lp, Mq, q)) continue;
+        pade_weights(q, Lp, w);
+        cplx val = 0.0;
+        for (int m = 0; m <= Lp; ++m) val += w[m] * a[m];
+        double d = std::abs(val - target);
+        if (d < bestd) {
+          bestd = d;
+          bestw = w;
+        }
+      }
+      if (bestw.empty()) {
+        bestw.assign(n, cplx(1.0, 0.0));   // plain partial sum
+      }
+      double maxrel = 0.0;
+      for (int f = 0; f < nfin; ++f) {
+        cplx corr = 0.0;
+        for (size_t m = 0; m < bestw.size(); ++m) corr += bestw[m] * terms[c][f][m];
+        U[(size_t)c * nfin + f] = Uy[(size_t)c * nfin + f] + corr;
+        maxrel = std::max(maxrel, std::abs(corr) / std::max(std::abs(U[(size_t)c * nfin + f]), 1e-300));
+      }
+      for (size_t m = 0; m < bestw.size(); ++m) coef[m * B + c] = make_double2(bestw[m].real(), bestw[m].imag());
+      err[c] = maxrel;
+      iters[c] += n;
+      if (maxrel <= outer_tol) done[c] = true;
+    }
+    if (!any_active) break;
+    HIPCHECK(hipMemcpyAsync(dcoef.p, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+    HIPCHECK(launch_lincomb(D, B, Lmax + 1, V.p, DB, dcoef.p, dy.p, s));
+    bool alldone = true;
+    for (int c = 0; c < B; ++c) alldone &= done[c];
+    if (alldone) break;
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  bool allok = true;
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    for (int b = 0; b < nfin; ++b) {
+      const int c = e * nfin + b;
+      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = U[(size_t)c * nfin + f];
+      r.err[b] = err[c];
+      r.iters[b] = iters[c];
+      r.ok &= err[c] <= o.accept;
+    }
+    allok &= r.ok;
+  }
+  return allok ? WP_OK : fail(WP_ENOCONV, "mixed refinement did not reach the accepted accuracy for some energy");
+}
+
 extern "C" wp_status faddeev_solve(wp_lattice* L, int n_E, const double* E_lab, const wp_solve_opts* opts, void* stream,
                                    wp_solution** out) {
   if (!L || !E_lab || !opts || !out || n_E < 1) return fail(WP_EINVAL, "faddeev_solve: bad argument");
@@ -696,6 +990,8 @@ extern "C" wp_status faddeev_solve(wp_lattice* L, int n_E, const double* E_lab, 
   try {
     if (opts->mode == WP_SOLVE_FP64)
       st = solve_fp64(L, E, *opts, (hipStream_t)stream, sol.get());
+    else if (opts->mode == WP_SOLVE_MIXED)
+      st = solve_mixed(L, E, *opts, (hipStream_t)stream, sol.get());
     else
       return fail(WP_EINVAL, "unknown solve mode");
   } catch (const std::exception& e) {

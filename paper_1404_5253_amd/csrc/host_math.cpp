@@ -1,6 +1,6 @@
 // Host FP64 numerics of the WPCD pipeline: lattice, NN potentials in the WP basis, symmetric
-// eigenproblem, recoupling coefficients and the channel resolvent. These are the "negligible"
-// steps 1 and 4 of the paper's Sec. V.A, kept on the CPU in FP64.
+// eigenproblem, recoupling coefficients and Wynn's epsilon table. These are the "negligible"
+// step 1 of the paper's Sec. V.A and the scalar Pade step, kept on the CPU in FP64.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -444,146 +444,6 @@ std::vector<GTerm> g_table(const Chan& c, const Chan& cp, int two_J) {
   for (auto& kv : acc)
     if (std::fabs(kv.second) > 1e-15) out.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second});
   return out;
-}
-
-// ------------------------------------------------------------------ channel resolvent G1
-
-cplx g1_bound_continuum(double qa, double qb, double E, double eps0, double h2m) {
-  // (1/dq) int dq / (E + i0 - eps0 - b3 q^2), b3 = 3/4 h2m, E - eps0 = b3 q0^2.
-  double b3 = 0.75 * h2m;
-  double q0 = std::sqrt((E - eps0) / b3);
-  auto f = [q0](double q) { return std::log(std::fabs((q0 + q) / (q0 - q))); };
-  double re = (f(qb) - f(qa)) / (2.0 * b3 * q0);
-  double im = (q0 > qa && q0 <= qb) ? -M_PI / (2.0 * b3 * q0) : 0.0;
-  return cplx(re, im) / (qb - qa);
-}
-
-// ln|(x + c)/(x - c)| for x, c >= 0 without cancellation when c << x or x << c.
-static double loglog_ratio(double x, double c) {
-  if (x == c) return INFINITY;
-  if (c < x) return std::log1p(2.0 * c / (x - c));
-  return std::log1p(2.0 * x / (c - x));
-}
-
-static double inner_p(double q, double pa, double pb, double E, double h, double b3) {
-  // PV int_{pa}^{pb} dp / (E - b3 q^2 - h p^2)
-  double c2 = E - b3 * q * q;
-  double sh = std::sqrt(h);
-  if (c2 > 0.0) {
-    double c = std::sqrt(c2);
-    return (loglog_ratio(sh * pb, c) - loglog_ratio(sh * pa, c)) / (2.0 * c * sh);
-  }
-  if (c2 < 0.0) {
-    double k = std::sqrt(-c2);
-    // atan(u) - atan(v), u = sh pb / k, v = sh pa / k (both >= 0)
-    double d = std::atan2(sh * (pb - pa) * k, k * k + h * pa * pb);
-    return -d / (sh * k);
-  }
-  return (pa > 0.0) ? (1.0 / (h * pb) - 1.0 / (h * pa)) : -INFINITY;
-}
-
-static double adaptive_gl(const std::function<double(double)>& f, double a, double b, double tol) {
-  // Globally adaptive Gauss-Legendre: each interval is integrated with 10 and 20 points, the
-  // difference is its error estimate; the interval with the largest error is bisected until
-  // the summed error is below tol or 600 intervals exist (bounded work for singular integrands).
-  struct Rules {
-    double x10[10], w10[10], x20[20], w20[20];
-    Rules() {
-      gauss_legendre(10, x10, w10);
-      gauss_legendre(20, x20, w20);
-    }
-  };
-  static const Rules R;  // thread-safe one-time initialisation
-  const double *x10 = R.x10, *w10 = R.w10, *x20 = R.x20, *w20 = R.w20;
-  struct Iv {
-    double a, b, val, err;
-    bool operator<(const Iv& o) const { return err < o.err; }
-  };
-  // A node that lands exactly on an integrable (log) singularity is skipped: that only happens
-  // on intervals a few ulps wide, whose share of the integral is below rounding.
-  auto fin = [](double v) { return std::isfinite(v) ? v : 0.0; };
-  const double min_width = 1e-13 * (b - a);
-  auto eval = [&](double lo, double hi) {
-    double m = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-    double s10 = 0.0, s20 = 0.0;
-    for (int i = 0; i < 10; ++i) s10 += w10[i] * fin(f(m + h * x10[i]));
-    for (int i = 0; i < 20; ++i) s20 += w20[i] * fin(f(m + h * x20[i]));
-    double e = (hi - lo) < min_width ? 0.0 : std::fabs(s20 - s10) * h;
-    return Iv{lo, hi, s20 * h, e};
-  };
-  std::priority_queue<Iv> pq;
-  Iv first = eval(a, b);
-  double total = first.val, err = first.err;
-  pq.push(first);
-  int n = 1;
-  while (err > tol && n < 600) {
-    Iv w = pq.top();
-    pq.pop();
-    double m = 0.5 * (w.a + w.b);
-    if (!(m > w.a && m < w.b)) {  // interval exhausted at double precision
-      pq.push(Iv{w.a, w.b, w.val, 0.0});
-      err -= w.err;
-      continue;
-    }
-    Iv l = eval(w.a, m), r = eval(m, w.b);
-    total += l.val + r.val - w.val;
-    err += l.err + r.err - w.err;
-    pq.push(l);
-    pq.push(r);
-    ++n;
-  }
-  return total;
-}
-
-static double arc_inside(double pa, double pb, double qa, double qb, double E, double h, double b3) {
-  if (E <= 0.0) return 0.0;
-  double P = std::sqrt(E / h), Q = std::sqrt(E / b3);
-  double lo_p = std::acos(std::min(1.0, pb / P));
-  double hi_p = std::acos(std::min(1.0, pa / P));
-  double lo_q = std::asin(std::min(1.0, qa / Q));
-  double hi_q = std::asin(std::min(1.0, qb / Q));
-  return std::max(0.0, std::min(hi_p, hi_q) - std::max(lo_p, lo_q));
-}
-
-cplx g1_continuum(double pa, double pb, double qa, double qb, double E, double h2m) {
-  // (1/(dp dq)) int_{pa}^{pb} dp int_{qa}^{qb} dq / (E + i0 - h p^2 - b3 q^2): p integral in
-  // closed form, q integral adaptive with breakpoints where the integrand is singular
-  // (ellipse meeting p = pa, p = pb, and E - b3 q^2 = 0); imaginary part = -pi/(2 sqrt(h b3))
-  // times the polar angle of the energy ellipse inside the box.
-  double h = h2m, b3 = 0.75 * h2m;
-  std::vector<double> pts{qa};
-  for (double c2 : {E, E - h * pa * pa, E - h * pb * pb}) {
-    if (c2 > 0.0) {
-      double qs = std::sqrt(c2 / b3);
-      if (qs > qa && qs < qb) pts.push_back(qs);
-    }
-  }
-  pts.push_back(qb);
-  std::sort(pts.begin(), pts.end());
-  auto f = [&](double q) { return inner_p(q, pa, pb, E, h, b3); };
-  double scale = 1.0 / (h * std::max(pb, 1e-3) * std::max(pb, 1e-3) + std::fabs(E) + 1e-3);
-  // For pa = 0 the p integral behaves like 1/sqrt(q - q*) just above q* = sqrt(E/b3)
-  // (E - b3 q^2 -> 0-); that segment is integrated in u with q = q* + u^2.
-  const double qstar = E > 0.0 ? std::sqrt(E / b3) : -1.0;
-  double re = 0.0;
-  for (size_t i = 0; i + 1 < pts.size(); ++i) {
-    double lo = pts[i], hi = pts[i + 1];
-    if (!(hi > lo)) continue;
-    if (pa == 0.0 && lo == qstar) {
-      // with pa = 0 the p integral is -atan(sqrt(h) pb / k) / (sqrt(h) k), k^2 = b3 (q^2 - q*^2);
-      // in u, k = u sqrt(b3 (2 q* + u^2)) without cancellation and the 2u dq/du cancels 1/k.
-      const double sh = std::sqrt(h);
-      auto g = [&](double u) {
-        double r = std::sqrt(b3 * (2.0 * qstar + u * u));
-        return -2.0 * std::atan2(sh * pb, u * r) / (sh * r);
-      };
-      re += adaptive_gl(g, 0.0, std::sqrt(hi - lo), 1e-15 * scale * (qb - qa));
-    } else {
-      re += adaptive_gl(f, lo, hi, 1e-15 * scale * (qb - qa));
-    }
-  }
-  double im = -M_PI / (2.0 * std::sqrt(h * b3)) * arc_inside(pa, pb, qa, qb, E, h, b3);
-  return cplx(re, im) / ((pb - pa) * (qb - qa));
 }
 
 // ------------------------------------------------------------------ Wynn epsilon

@@ -621,9 +621,364 @@ hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, cons
   return hipGetLastError();
 }
 
+hipError_t launch_fill0_cols(double2* p, int64_t rows, int B, int cb0, int cb1, hipStream_t st) {
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1) return hipErrorInvalidValue;
+  int64_t n = rows * (cb1 - cb0);
+  hipLaunchKernelGGL(k_fill0_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, rows, B, cb0, cb1);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
+}
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+// ------------------------------------------------------------------ step 4: channel resolvent G1
+
+// Continuum element (1/(dp dq)) int int dp dq / (E + i0 - h p^2 - b3 q^2) (eq. dg1b, unit weights).
+// E < 0: p integral in closed form (arctangent), q integral by two 20-point Gauss panels.
+// E > 0: p = P r cos t, q = Q r sin t (P = sqrt(E/h), Q = sqrt(E/b3)) gives
+//   Re = (1/sqrt(h b3)) int dt [-1/2 ln|1 - r^2|]_{r_lo(t)}^{r_hi(t)},
+// split at the box corners and where the energy shell r = 1 crosses a box edge (log
+// singularities), each piece by tanh-sinh; Im = -(pi / (2 sqrt(h b3))) x (angle of the shell
+// inside the box).
+__device__ double2 g1_continuum_dev(const G1Args& g, double pa, double pb, double qa, double qb, double E) {
+  const double h = g.h2m, b3 = 0.75 * g.h2m;
+  double re = 0.0, im = 0.0;
+  if (E <= 0.0) {
+    const double sh = sqrt(h);
+    const double mid = 0.5 * (qa + qb);
+    for (int panel = 0; panel < 2; ++panel) {
+      const double a = panel ? mid : qa, b = panel ? qb : mid;
+      const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
+      double s = 0.0;
+      for (int n = 0; n < g.ngl; ++n) {
+        const double q = c + hw * g.gl_x[n];
+        const double k = sqrt(b3 * q * q - E);
+        s += g.gl_w[n] * (-atan2(sh * (pb - pa) * k, k * k + h * pa * pb) / (sh * k));
+      }
+      re += hw * s;
+    }
+  } else {
+    const double P = sqrt(E / h), Q = sqrt(E / b3);
+    const double t0 = atan2(qa / Q, pb / P), t1 = atan2(qb / Q, pa / P);
+    double pts[8];
+    int np = 0;
+    pts[np++] = t0;
+    pts[np++] = t1;
+    double cand[6] = {atan2(qa / Q, pa / P), atan2(qb / Q, pb / P), -1, -1, -1, -1};
+    if (pa / P < 1.0) cand[2] = acos(pa / P);
+    if (pb / P < 1.0) cand[3] = acos(pb / P);
+    if (qa / Q < 1.0) cand[4] = asin(qa / Q);
+    if (qb / Q < 1.0) cand[5] = asin(qb / Q);
+    for (int c = 0; c < 6; ++c)
+      if (cand[c] > t0 && cand[c] < t1) pts[np++] = cand[c];
+    for (int x = 1; x < np; ++x)  // insertion sort (np <= 8)
+      for (int y = x; y > 0 && pts[y - 1] > pts[y]; --y) {
+        double tmp = pts[y];
+        pts[y] = pts[y - 1];
+        pts[y - 1] = tmp;
+      }
+    for (int sgi = 0; sgi + 1 < np; ++sgi) {
+      const double a = pts[sgi], b = pts[sgi + 1];
+      if (!(b > a)) continue;
+      double s = 0.0;
+      for (int n = 0; n < g.nts; ++n) {
+        const double u = g.ts_u[n];
+        const double t = (u <= 0.5) ? a + (b - a) * u : b - (b - a) * g.ts_v[n];
+        double st, ct;
+        sincos(t, &st, &ct);
+        double rlo = 0.0;
+        if (pa > 0.0) rlo = pa / (P * ct);
+        if (qa > 0.0) rlo = fmax(rlo, qa / (Q * st));
+        const double rhi = fmin(pb / (P * ct), qb / (Q * st));
+        if (rhi > rlo) {
+          double f = -0.5 * log(fabs(1.0 - rhi * rhi)) + 0.5 * log(fabs(1.0 - rlo * rlo));
+          if (isfinite(f)) s += g.ts_w[n] * f;   // a node on the shell itself carries no weight
+        }
+      }
+      re += 0.5 * (b - a) * s;
+    }
+    re /= sqrt(h * b3);
+    const double lo_p = acos(fmin(1.0, pb / P)), hi_p = acos(fmin(1.0, pa / P));
+    const double lo_q = asin(fmin(1.0, qa / Q)), hi_q = asin(fmin(1.0, qb / Q));
+    im = -M_PI / (2.0 * sqrt(h * b3)) * fmax(0.0, fmin(hi_p, hi_q) - fmax(lo_p, lo_q));
+  }
+  const double d = (pb - pa) * (qb - qa);
+  return make_double2(re / d, im / d);
+}
+
+// Bound-continuum element (eq. dg1a): (1/dq) int dq / (E + i0 - eps0 - b3 q^2), E - eps0 = b3 q0^2.
+__device__ double2 g1_bound_dev(double qa, double qb, double E, double eps0, double h2m) {
+  const double b3 = 0.75 * h2m;
+  const double q0 = sqrt((E - eps0) / b3);
+  const double re = (log(fabs((q0 + qb) / (q0 - qb))) - log(fabs((q0 + qa) / (q0 - qa)))) / (2.0 * b3 * q0);
+  const double im = (q0 > qa && q0 <= qb) ? -M_PI / (2.0 * b3 * q0) : 0.0;
+  return make_double2(re / (qb - qa), im / (qb - qa));
+}
+
+__global__ void __launch_bounds__(256) k_g1(G1Args g) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_e = (int64_t)g.nwave * g.M * g.N;
+  if (tid >= per_e * g.nE) return;
+  const int e = (int)(tid / per_e);
+  int64_t r = tid - (int64_t)e * per_e;
+  const int w = (int)(r / ((int64_t)g.M * g.N));
+  r -= (int64_t)w * g.M * g.N;
+  const int k = (int)(r / g.N), j = (int)(r - (int64_t)k * g.N);
+  const double E = g.E[e];
+  const int nb = g.nb[w];
+  double2 v;
+  if (k < nb) {
+    v = g1_bound_dev(g.qe[j], g.qe[j + 1], E, g.eps_b[w], g.h2m);
+  } else {
+    const double* bins = g.bins + (size_t)w * (g.M + 1);
+    v = g1_continuum_dev(g, bins[k - nb], bins[k - nb + 1], g.qe[j], g.qe[j + 1], E);
+  }
+  for (int ch = 0; ch < g.nch; ++ch) {
+    if (g.wave[ch] != w) continue;
+    const size_t row = ((size_t)j * g.M + k) * g.nch + ch;
+    for (int f = 0; f < g.nrep; ++f) g.G[row * g.B + g.col0 + (size_t)e * g.nrep + f] = v;
+  }
+}
+
+hipError_t launch_g1(const G1Args& g, hipStream_t s) {
+  if (g.M < 1 || g.N < 1 || g.nE < 1 || g.nwave < 1 || g.nrep < 1) return hipErrorInvalidValue;
+  if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
+  hipLaunchKernelGGL(k_g1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+// ------------------------------------------------------------------ solve: fused block step (FP64)
+// For one channel g (pair wave w) and TC columns (j, c): y tile [M][TC] in LDS,
+// t = O_w y (capture e0^T O y at k = 0, j = j0[c]), t *= G1, s = (v O^T)_w t, written out.
+// Each column's sums run over i (then k) in a fixed order, independent of the tiling.
+template <int TC>
+__global__ void __launch_bounds__(256) k_step64(RotArgs r, const double* __restrict__ Wm,
+                                                const double2* __restrict__ y, double2* __restrict__ s_out) {
+  extern __shared__ double2 shc[];
+  const int M = r.M, B = r.B, nch = r.nch;
+  const int ncol = r.N * B;
+  const int g = blockIdx.y;
+  const size_t woff = (size_t)r.wave[g] * M * M;
+  const double* O = r.A + woff;
+  const double* W = Wm + woff;
+  const int col0 = blockIdx.x * TC;
+  double2* Xs = shc;            // [M][TC]
+  double2* Ts = shc + M * TC;   // [M][TC]
+  const int tid = threadIdx.x;
+  const bool cfast = B >= TC;
+  for (int e = tid; e < M * TC; e += 256) {
+    int i, cc;
+    if (cfast) {
+      i = e / TC;
+      cc = e - i * TC;
+    } else {
+      cc = e / M;
+      i = e - cc * M;
+    }
+    const int col = col0 + cc;
+    double2 v = make_double2(0.0, 0.0);
+    if (col < ncol) {
+      const int jj = col / B, cb = col - jj * B;
+      v = y[(((size_t)jj * M + i) * nch + g) * B + cb];
+    }
+    Xs[i * TC + cc] = v;
+  }
+  __syncthreads();
+  const int cc = tid % TC, rg = tid / TC, nrg = 256 / TC;
+  const int col = col0 + cc;
+  const bool live = col < ncol;
+  const int jj = live ? col / B : 0, cb = live ? col - jj * B : 0;
+  for (int k = rg; k < M; k += nrg) {
+    double ar = 0.0, ai = 0.0;
+    const double* Ok = O + (size_t)k * M;
+    for (int i = 0; i < M; ++i) {
+      const double a = Ok[i];
+      const double2 x = Xs[i * TC + cc];
+      ar = fma(a, x.x, ar);
+      ai = fma(a, x.y, ai);
+    }
+    double2 v = make_double2(ar, ai);
+    if (live) {
+      if (r.acap && k == 0 && jj == r.j0[cb]) {
+        for (int f = 0; f < r.nfin; ++f)
+          if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = v;
+      }
+      const double2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
+      v = make_double2(ar * gv.x - ai * gv.y, ar * gv.y + ai * gv.x);
+    }
+    Ts[k * TC + cc] = v;
+  }
+  __syncthreads();
+  for (int i = rg; i < M; i += nrg) {
+    double sr = 0.0, si = 0.0;
+    const double* Wi = W + (size_t)i * M;
+    for (int k = 0; k < M; ++k) {
+      const double a = Wi[k];
+      const double2 t = Ts[k * TC + cc];
+      sr = fma(a, t.x, sr);
+      si = fma(a, t.y, si);
+    }
+    if (live) s_out[(((size_t)jj * M + i) * nch + g) * B + cb] = make_double2(sr, si);
+  }
+}
+
+hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s) {
+  if (r.M < 1 || r.N < 1 || r.B < 1 || r.nch < 1 || !r.G) return hipErrorInvalidValue;
+  const int ncol = r.N * r.B;
+  int tc = 16;
+  while (tc > 2 && ((size_t)2 * r.M * tc * sizeof(double2) > 64 * 1024 || ncol / tc < 64)) tc >>= 1;
+  const size_t shmem = (size_t)2 * r.M * tc * sizeof(double2);
+  if (shmem > 64 * 1024) return hipErrorInvalidValue;
+  dim3 grid((ncol + tc - 1) / tc, r.nch);
+  switch (tc) {
+    case 16: hipLaunchKernelGGL(k_step64<16>, grid, dim3(256), shmem, s, r, W, y, s_out); break;
+    case 8: hipLaunchKernelGGL(k_step64<8>, grid, dim3(256), shmem, s, r, W, y, s_out); break;
+    case 4: hipLaunchKernelGGL(k_step64<4>, grid, dim3(256), shmem, s, r, W, y, s_out); break;
+    default: hipLaunchKernelGGL(k_step64<2>, grid, dim3(256), shmem, s, r, W, y, s_out); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+// ------------------------------------------------------------------ block-CSR products, any precision
+// VT: stored P0 value type (double / float); XT: vector element (double2 / float2); AT: accumulator.
+
+template <typename XT> struct Acc;
+template <> struct Acc<double2> { using T = double; };
+template <> struct Acc<float2> { using T = float; };
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WARP);
+  return v;
+}
+
+template <typename XT, typename AT>
+__device__ __forceinline__ XT make_x(AT re, AT im) {
+  XT v;
+  v.x = re;
+  v.y = im;
+  return v;
+}
+
+// Lanes over the columns (energies): block values and column index are wave-uniform, the
+// vector gathers are contiguous over c. For B >= 16.
+template <typename VT, typename XT, typename AT, int NC>
+__global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                              const XT* __restrict__ x, XT* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = cb0 + blockIdx.y * 64 + (threadIdx.x & 63);
+  if (row >= rows || c >= cb1) return;
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  AT ar[NC], ai[NC];
+#pragma unroll
+  for (int g = 0; g < NC; ++g) ar[g] = ai[g] = AT(0);
+  for (int64_t e = b0; e < b1; ++e) {
+    const int cc = col[e];
+    const VT* v = val + e * NC * NC;
+#pragma unroll
+    for (int gp = 0; gp < NC; ++gp) {
+      const XT xv = x[((size_t)cc * NC + gp) * B + c];
+#pragma unroll
+      for (int g = 0; g < NC; ++g) {
+        const AT a = (AT)v[g * NC + gp];
+        ar[g] = fma(a, (AT)xv.x, ar[g]);
+        ai[g] = fma(a, (AT)xv.y, ai[g]);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NC; ++g) y[((size_t)row * NC + g) * B + c] = make_x<XT, AT>(ar[g], ai[g]);
+}
+
+// Lanes over the blocks of a row, wave reduction; for few columns.
+template <typename VT, typename XT, typename AT, int NC>
+__global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                              const XT* __restrict__ x, XT* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  for (int c = cb0; c < cb1; ++c) {
+    AT ar[NC], ai[NC];
+#pragma unroll
+    for (int g = 0; g < NC; ++g) ar[g] = ai[g] = AT(0);
+    for (int64_t e = b0 + lane; e < b1; e += 64) {
+      const int cc = col[e];
+      const VT* v = val + e * NC * NC;
+#pragma unroll
+      for (int gp = 0; gp < NC; ++gp) {
+        const XT xv = x[((size_t)cc * NC + gp) * B + c];
+#pragma unroll
+        for (int g = 0; g < NC; ++g) {
+          const AT a = (AT)v[g * NC + gp];
+          ar[g] = fma(a, (AT)xv.x, ar[g]);
+          ai[g] = fma(a, (AT)xv.y, ai[g]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      const AT sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
+      if (lane == g) y[((size_t)row * NC + g) * B + c] = make_x<XT, AT>(sr, si);
+    }
+  }
+}
+
+template <typename VT, typename XT, typename AT, int NC>
+static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* rowptr, const int32_t* col,
+                          const VT* val, const XT* x, XT* y, hipStream_t s) {
+  // the choice depends on B only, so every launch on a given batch width sums in one order
+  if (B >= 16) {
+    dim3 grid((unsigned)((rows + 3) / 4), (cb1 - cb0 + 63) / 64);
+    hipLaunchKernelGGL((k_spmm<VT, XT, AT, NC>), grid, dim3(256), 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y);
+  } else {
+    hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, B, cb0, cb1,
+                       rowptr, col, val, x, y);
+  }
+}
+
+template <typename VT, typename XT, typename AT>
+static hipError_t spmv_any(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1) {
+  if (cb1 < 0) cb1 = B;
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1) return hipErrorInvalidValue;
+  switch (nch) {
+    case 1: spmv_dispatch<VT, XT, AT, 1>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
+    case 2: spmv_dispatch<VT, XT, AT, 2>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
+    case 3: spmv_dispatch<VT, XT, AT, 3>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
+    case 4: spmv_dispatch<VT, XT, AT, 4>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
+                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
+  return spmv_any<double, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+}
+hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
+                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1) {
+  return spmv_any<float, float2, float>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+}
+hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
+                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
+  return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
 }
 
 }  // namespace wpcd

@@ -39,10 +39,6 @@ struct MomKey { int k, a, b, l, lp; };
 struct GTerm { int l1, l1p, k; double g; };
 std::vector<GTerm> g_table(const Chan& c, const Chan& cp, int two_J);
 
-// Channel resolvent elements (FP64)
-cplx g1_bound_continuum(double qa, double qb, double E, double eps0, double h2m);
-cplx g1_continuum(double pa, double pb, double qa, double qb, double E, double h2m);
-
 // Wynn epsilon accumulator with the stop rule of faddeev_solve.
 struct Wynn {
   std::vector<cplx> diag;
@@ -125,6 +121,8 @@ struct RotArgs {
   int64_t acap_off;      // offset (in double2) of this term's capture row: acap[acap_off + c*nfin + f]
 };
 hipError_t launch_rot64(const RotArgs& r, const double2* in, double2* out, hipStream_t s);
+// fused s = W (G1 * (O y)) with capture; r.A = O, W = v O^T (same wave layout), r.G required
+hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s);
 // y = P0 x for the columns [cb0, cb1) (cb1 < 0: all B columns)
 hipError_t launch_spmv64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
                          const double* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
@@ -134,30 +132,61 @@ hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, cons
                              const int* j0, const int* g0, double2* s0, hipStream_t st, int cb0 = 0,
                              int cb1 = -1);
 hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st);
+// Block-CSR products for any storage/vector precision: lanes over columns when all B >= 16
+// columns are requested, else lanes over blocks with a wave reduction.
+hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
+                           const double2* x, double2* y, hipStream_t s, int cb0 = 0, int cb1 = -1);
+hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
+                           const float2* x, float2* y, hipStream_t s, int cb0 = 0, int cb1 = -1);
+hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
+                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
+                                 int cb1 = -1);
+// zero the columns [cb0, cb1) of a rows x B array
+hipError_t launch_fill0_cols(double2* p, int64_t rows, int B, int cb0, int cb1, hipStream_t st);
 
-// Mixed precision (FP32 P0, BF16 blocks on MFMA, FP32 vectors)
+// Channel resolvent G1 on the device (FP64). One thread per (wave, k, j, energy); the value is
+// written to every channel of that pair wave and to the nrep columns of the energy:
+// G[((j*M + k)*nch + g)*B + col0 + e*nrep + f].
+struct G1Args {
+  int M, N, nch, B, nwave, nE, nrep, col0;
+  const double* qe;     // [N+1]
+  const double* bins;   // [nwave][M+1] continuum bin edges (first M - nb + 1 used)
+  const int* nb;        // [nwave] bound states (0 or 1)
+  const double* eps_b;  // [nwave] bound-state energy
+  const int* wave;      // [nch]
+  const double* E;      // [nE] three-body energies
+  const double* ts_u;   // tanh-sinh node fractions from the left end
+  const double* ts_v;   //   ... and from the right end
+  const double* ts_w;   //   weights on [-1, 1]
+  int nts;
+  const double* gl_x;   // Gauss-Legendre nodes / weights on [-1, 1]
+  const double* gl_w;
+  int ngl;
+  double h2m;
+  double2* G;
+};
+hipError_t launch_g1(const G1Args& g, hipStream_t s);
+
+// Mixed precision (FP32 P0, BF16 blocks on MFMA with FP32 accumulation, FP32 vectors)
 struct RotArgsMixed {
   int M, N, nch, B;
-  const uint16_t* A;     // bf16 [nwave][Mp][Mp] (padded to multiple of 16, zero fill)
-  int Mp;
+  const uint16_t* A;     // O in bf16: [nwave][Mp][Mp] row-major, zero padded
+  int Mp;                // M rounded up to a multiple of 16
   const int* wave;
-  const float2* G;       // scaling [j][k][g][c] or nullptr
-  float2* acap;
+  const float2* G;       // G1 in FP32 [j][k][g][c]
+  float2* acap;          // captured e^T O y (FP32) or nullptr
   const int* j0;
   const int* finals;
   int nfin;
   int64_t acap_off;
 };
-hipError_t launch_rot_bf16(const RotArgsMixed& r, const float2* in, float2* out, hipStream_t s);
-hipError_t launch_spmv32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
-                         const float* val, const float2* x, float2* y, hipStream_t s);
-hipError_t launch_spmv32acc64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
-                              const float* val, const double2* x, double2* y, hipStream_t s);
+// s = W (G1 * (O y)) on MFMA (W = v O^T in bf16, same layout as A)
+hipError_t launch_step_bf16(const RotArgsMixed& r, const uint16_t* W, const float2* y, float2* s_out, hipStream_t s);
 hipError_t launch_cvt_d2f(int64_t n, const double2* in, float2* out, hipStream_t s);
-hipError_t launch_axpy_f2d(int64_t n, const float2* in, double2* out, double alpha, hipStream_t s);
+hipError_t launch_cvt_scalar(int64_t n, const double* in, float* out, hipStream_t s);
 hipError_t launch_residual(int64_t n, const double2* b, const double2* y, const double2* Ky, double2* r,
                            hipStream_t s);
-hipError_t launch_lincomb(int64_t n, int B, int nv, const float2* vecs, int64_t vstride,
-                          const double2* coef, double2* out, hipStream_t s);
+hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64_t vstride, const double2* coef,
+                          double2* out, hipStream_t s);
 
 }  // namespace wpcd

@@ -39,6 +39,13 @@ struct wp_lattice {
   // device tables
   DBuf<double> d_pe, d_qe, d_gx, d_gwx, d_gp, d_gwp, d_C, d_O, d_W;
   DBuf<int> d_keys, d_wave;
+  // G1 tables: continuum bins per wave, bound states, quadrature rules
+  DBuf<double> d_bins, d_epsb, d_ts_u, d_ts_v, d_ts_w, d_gl_x, d_gl_w;
+  DBuf<int> d_nb;
+  int nts = 0, ngl = 0;
+  // mixed precision: bf16 copies of O and v O^T (padded to Mp), FP32 P0 values
+  int Mp = 0;
+  DBuf<uint16_t> d_Ob, d_Wb;
   // P0
   bool have_P = false;
   int prec = WP_P_FP64;
@@ -84,8 +91,9 @@ struct ProfScope {
 
 wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
-// G1 over (k, j) of one pair wave at three-body energy E (host FP64, threaded over k)
-void g1_wave(const wp_lattice* L, const PairWave& pw, double E, std::vector<cplx>& out);
+wp_status ensure_mixed(wp_lattice* L, hipStream_t s);   // bf16 blocks + FP32 copy of P0
+// G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns)
+G1Args g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G);
 
 // Kinematics of one energy: E, q0, on-shell bin j0 ((q_{j-1}, q_j] convention), its width.
 inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {
@@ -114,7 +122,7 @@ struct ColState {
   std::vector<Wynn> w;      // per final
   std::vector<cplx> S, last, best;
   double best_r = INFINITY;
-  int best_n = 0, streak = 0, n = 0;
+  int best_n = 0, streak = 0, n = 0, plateau = 24;
   bool done = false, ok = false;
   double err = 0.0;
 };
@@ -142,7 +150,7 @@ inline bool column_push(ColState& cs, const cplx* a, int nfin, double tol, doubl
       cs.best = est;
       cs.err = r;
       cs.done = cs.ok = true;
-    } else if (cs.n - cs.best_n >= PLATEAU || Smax > 1e250) {
+    } else if (cs.n - cs.best_n >= cs.plateau || Smax > 1e250) {
       cs.done = true;
       cs.ok = cs.best_r <= accept;
       cs.err = cs.best_r;

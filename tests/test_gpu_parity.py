@@ -62,6 +62,21 @@ def systems():
     return {k: pipeline.build_system(v) for k, v in SPECS.items()}
 
 
+@pytest.mark.parametrize("name", ["quartet_yam_24", "doublet_mt_20"])
+@pytest.mark.parametrize("E_lab", [1.0, 3.0, 3.4, 14.1, 45.0])
+def test_g1_matches_oracle(systems, name, E_lab):
+    """Device G1 (eqs. dg1a, dg1b) against the oracle's adaptive quadrature, every element."""
+    from oracle import lattice as olat, resolvent
+    s = systems[name]
+    L = _lib_lattice(SPECS[name])
+    for a, ch in enumerate(L.channels):
+        d = s.pair[(ch[0], ch[1])]
+        G = L.resolvent(E_lab, a)
+        Go = resolvent.channel_diagonal(s.q_edges, olat.total_energy(E_lab, s.eps0), list(d["eps"][:d["nb"]]),
+                                        d["bins"])
+        assert np.max(np.abs(G - Go)) <= 1e-10 * np.max(np.abs(Go)), (ch, np.max(np.abs(G - Go)))
+
+
 @pytest.mark.parametrize("name", list(SPECS))
 def test_p0_fp64_matches_oracle(systems, name):
     s = systems[name]
@@ -180,3 +195,78 @@ def test_batch_api_matches_solve():
     for E, r in results.items():
         solo = L.solve([E], "fp64").amplitude(0)
         assert np.array_equal(r["A"], solo["A"]), E
+
+
+def _run_batch(L, energies, slots, terms=4):
+    """Drive the continuous-batching API until every energy is done; returns {E: amplitude}."""
+    import ctypes as C
+    o = wp._SolveOpts(wp.WP_SOLVE_FP64, 1e-12, 1e-7, 200, 0)
+    b = C.c_void_p()
+    wp._check(wp._lib.faddeev_batch_create(L.h, slots, 1 << 33, C.byref(o), C.byref(b)))
+    queue = list(energies)
+    results, slot_E = {}, {}
+    n_done = C.c_int()
+    done = (C.c_int * max(slots, 1))()
+    stream = wp.current_stream()
+    for _ in range(2000):
+        if not queue and not slot_E:
+            break
+        while queue:
+            sl = C.c_int()
+            st = wp._lib.faddeev_batch_admit(b, queue[0], C.byref(sl))
+            if st == wp.WP_EBUDGET:
+                break
+            wp._check(st)
+            slot_E[sl.value] = queue.pop(0)
+        wp._check(wp._lib.faddeev_batch_step(b, stream, terms, C.byref(n_done), done))
+        for k in range(n_done.value):
+            h = C.c_void_p()
+            wp._check(wp._lib.faddeev_batch_take(b, done[k], C.byref(h)))
+            results[slot_E.pop(done[k])] = wp.amplitude(h, 0)
+            wp._lib.wp_solution_free(h)
+    wp._lib.faddeev_batch_free(b)
+    return results
+
+
+def test_serving_result_alone_equals_in_mix():
+    """A request gives bit-identical numbers alone or among 23 others in a 24-slot batch (the
+    lane-per-energy product path), and agrees with the plain solve to the Pade tolerance."""
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    rng = np.random.default_rng(4)
+    mix = list(rng.uniform(1.0, 50.0, 40))
+    probe = [mix[3], mix[17], mix[31]]
+    together = _run_batch(L, mix, slots=24)
+    for E in probe:
+        alone = _run_batch(L, [E], slots=24)[E]
+        assert np.array_equal(alone["A"], together[E]["A"])
+        solo = L.solve([E], "fp64").amplitude(0)
+        ref = abs(solo["A"][0, 0])
+        assert abs(alone["A"][0, 0] - solo["A"][0, 0]) <= 1e-10 * ref + 30 * max(alone["err"][0], solo["err"][0]) * ref
+
+
+def test_wide_batch_matches_single():
+    """faddeev_solve over 20 energies (lane-per-energy SpMM) against single-energy solves."""
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    Es = list(np.random.default_rng(9).uniform(1.0, 50.0, 20))
+    many = L.solve(Es, "fp64")
+    for k, E in enumerate(Es):
+        one = L.solve([E], "fp64").amplitude(0)
+        a, b = many.amplitude(k), one
+        ref = abs(b["A"][0, 0])
+        assert abs(a["A"][0, 0] - b["A"][0, 0]) <= 1e-10 * ref + 30 * max(a["err"][0], b["err"][0]) * ref
+
+
+@pytest.mark.parametrize("name", ["quartet_yam_24", "doublet_mt_20"])
+def test_mixed_matches_fp64(name):
+    """Mixed path (FP32 P0, BF16 blocks on MFMA, FP64 residual refinement): |dA| <= 1e-6
+    against the FP64 path for every energy of a batch (the amplitude itself is at most 1/pi)."""
+    spec = SPECS[name]
+    L = _lib_lattice(spec)
+    Es = [1.5, 3.0, 9.0, 14.1, 33.0]
+    ref = L.solve(Es, "fp64")
+    mix = L.solve(Es, "mixed", tol=1e-9)
+    for k in range(len(Es)):
+        a, b = mix.amplitude(k), ref.amplitude(k)
+        assert abs(a["A"][0, 0] - b["A"][0, 0]) <= 1e-6, (Es[k], abs(a["A"][0, 0] - b["A"][0, 0]), a["err"], a["iters"])
