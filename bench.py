@@ -45,7 +45,72 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched-energy and serving measurements")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--sweep", action="store_true", help="also time the s-wave P0 build for M = N in 40..400")
     return ap.parse_args()
+
+
+def batched_energies_section(wp, torch, L, reps=3):
+    """64 energies U[1, 50] MeV (seed 1234) on the resident doublet lattice: FP64 vs mixed."""
+    Es = workloads.batched_energies()
+    out = {}
+    amps = {}
+    for mode in ("fp64", "mixed"):
+        L.solve(Es, mode, tol=1e-12 if mode == "fp64" else 1e-9, allow_noconv=True)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sol = L.solve(Es, mode, tol=1e-12 if mode == "fp64" else 1e-9, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        amps[mode] = np.array([sol.amplitude(k)["A"][0, 0] for k in range(len(Es))])
+        out[f"solves_per_s_{mode}"] = len(Es) / dt
+        out[f"ms_per_batch_{mode}"] = dt * 1e3
+    out["n_energies"] = len(Es)
+    out["max_abs_dA_mixed_vs_fp64"] = float(np.max(np.abs(amps["mixed"] - amps["fp64"])))
+    out["speedup_mixed_over_fp64"] = out["solves_per_s_mixed"] / out["solves_per_s_fp64"]
+    return out
+
+
+def serving_section(wp, torch, lats, seconds):
+    """Poisson stream (200 req/s, seed 2026) over the resident lattices, continuous batching."""
+    from paper_1404_5253_amd.serve import BatchBackend, run_stream
+    backs = []
+    for L in lats:
+        st = torch.cuda.Stream()
+        backs.append(BatchBackend(L, slots=32, hbm_budget=8 << 30, terms=4,
+                                  stream=wp.C.c_void_p(st.cuda_stream)))
+        backs[-1]._torch_stream = st
+    reqs = workloads.serving_requests(len(lats), rate=200.0, duration=seconds)
+    done, stats = run_stream(backs, reqs)
+    for b in backs:
+        b.close()
+    stats["requests"] = len(reqs)
+    stats["accepted"] = sum(1 for r in done if r.result.get("accepted", True))
+    stats["lattices"] = [f"M=N={L.M}, {L.nch} ch" for L in lats]
+    return stats
+
+
+def sweep_section(wp, torch, V_R, sizes=(40, 100, 200, 400), reps=3):
+    """P0 build of the s-wave quartet lattice (one channel) against M = N: the paper's scaling axis
+    (its headline point is M = N = 400 with about 256 million P0 elements)."""
+    out = {}
+    for M in sizes:
+        L = wp.Lattice(M, M, two_J=3, swave_only=True)
+        L.pseudostates(kind="mt", V_R=V_R)
+        L.build_perm("fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = L.build_perm("fp64")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[str(M)] = dict(P_elements=st["nnz"], candidates=st["candidates"], build_ms=dt * 1e3,
+                           device_ms=st["device_ms"], P_elements_per_s=st["nnz"] / dt,
+                           fill=st["nnz"] / float(M * M) ** 2)
+        del L
+    return out
 
 
 def cpu_baseline(V_R, M, N, budget_s=25.0):
@@ -177,6 +242,11 @@ def main():
         "kernels_ms_per_step": {k: round(v[1] / K, 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    if not args.no_extras:
+        out["batched_64_energies"] = batched_energies_section(wp, torch, lats[0])
+        out["serving"] = serving_section(wp, torch, lats, args.serve_seconds)
+    if args.sweep:
+        out["swave_sweep"] = sweep_section(wp, torch, V_R)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V_R, M, N)
     print(json.dumps(out))

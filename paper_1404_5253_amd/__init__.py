@@ -22,6 +22,7 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
                       "or `python paper_1404_5253_amd/build.py`")
 _lib = C.CDLL(LIB_PATH)
+C = C   # ctypes, re-exported for callers that pass raw stream handles
 
 WP_OK, WP_EINVAL, WP_ENOMEM, WP_EDEVICE, WP_ENOTREADY, WP_ENOCONV, WP_EBUDGET, WP_EINTERNAL = range(8)
 WP_P_FP64, WP_P_FP32 = 0, 1

@@ -534,7 +534,6 @@ static wp_status upload_tables(wp_lattice* L) {
 extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* stream, wp_perm_stats* stats) {
   if (!L) return fail(WP_EINVAL, "NULL lattice");
   if (precision != WP_P_FP64 && precision != WP_P_FP32) return fail(WP_EINVAL, "precision must be FP64 or FP32");
-  if ((int)L->keys.size() > 8) return fail(WP_EINVAL, "more than 8 distinct moments: partial waves beyond this build");
   hipStream_t s = (hipStream_t)stream;
   wp_status st = upload_tables(L);
   if (st) return st;
@@ -564,7 +563,22 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   if (!col_c.make(&L->al, std::max<int64_t>(ncand, 1)) || !val_c.make(&L->al, std::max<int64_t>(ncand, 1) * nc2) ||
       !flag.make(&L->al, std::max<int64_t>(ncand, 1)))
     return fail(WP_ENOMEM, "device allocation (candidates)");
-  if (ncand > 0) WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
+  const bool general = L->keys.size() > 8;
+  DBuf<double> mom, nrm, Ct;
+  if (ncand > 0 && general) {
+    // transposed coefficient table [nmom][nch*nch] for the combine contraction
+    const int nm = (int)L->keys.size();
+    std::vector<double> ct((size_t)nm * nc2);
+    for (int gg = 0; gg < nc2; ++gg)
+      for (int m = 0; m < nm; ++m) ct[(size_t)m * nc2 + gg] = L->C[(size_t)gg * nm + m];
+    if (!mom.make(&L->al, (size_t)ncand * nm) || !nrm.make(&L->al, ncand) || !Ct.make(&L->al, ct.size()))
+      return fail(WP_ENOMEM, "device allocation (moments)");
+    HIPCHECK(hipMemcpyAsync(Ct.p, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
+    WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct.p, cnt.p, lo.p, segoff.p, rowptr_c.p, ncand, col_c.p,
+                                                         mom.p, nrm.p, val_c.p, flag.p, s));
+  } else if (ncand > 0) {
+    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
+  }
   if (ncand > 0) {
     WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c.p, flag.p, rowcnt.p, s));
   } else {

@@ -12,9 +12,11 @@
 //   k_rowcount / k_compact  ballot + popcount compaction of the nonzero blocks into the
 //              final block-CSR (deterministic, no atomics on the output path).
 // Solve (step 5):
-//   k_rot64    t = A y for every (channel, q bin, column) with A = O or v O^T (M x M per pair
-//              wave): LDS-tiled FP64 GEMM, optional G1 scaling and capture of e0^T O y.
-//   k_spmv64   block-CSR P0 times complex vectors, one wavefront per block row.
+//   k_g1       G1(E) (eqs. dg1a, dg1b) in FP64, straight into the iteration layout.
+//   k_step64   per channel and column tile: t = O y, capture of e0^T O y, t *= G1,
+//              s = (v O^T) t (FP64; the mixed-precision MFMA version is in kernels_mixed.hip).
+//   k_spmm / k_spmv / k_spmv_gen  block-CSR P0 times complex vectors (lanes over energies,
+//              over blocks, or over channel rows for large blocks).
 #include <hip/hip_runtime.h>
 
 #include "wpcd_internal.h"
@@ -432,159 +434,6 @@ hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const 
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ solve: block rotation GEMM (FP64)
-
-#define RT 32
-
-template <bool SCALE>
-__global__ void __launch_bounds__(256) k_rot64(RotArgs r, const double2* __restrict__ in, double2* __restrict__ out) {
-  __shared__ double As[RT][RT + 1];
-  __shared__ double2 Is[RT][RT + 1];
-  const int M = r.M, B = r.B, nch = r.nch;
-  const int ncol = r.N * B;
-  const int g = blockIdx.z;
-  const double* A = r.A + (size_t)r.wave[g] * M * M;
-  const int k0 = blockIdx.x * RT, c0 = blockIdx.y * RT;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  const bool cfast = B >= RT;
-  double2 acc[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int i0 = 0; i0 < M; i0 += RT) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
-      int rr = e >> 5, cc = e & 31;
-      int k = k0 + rr, i = i0 + cc;
-      As[rr][cc] = (k < M && i < M) ? A[(size_t)k * M + i] : 0.0;
-      int ii, col;
-      if (cfast) {
-        ii = e >> 5;
-        col = c0 + (e & 31);
-      } else {
-        ii = e & 31;
-        col = c0 + (e >> 5);
-      }
-      int iv = i0 + ii;
-      double2 v = make_double2(0.0, 0.0);
-      if (iv < M && col < ncol) {
-        int jj = col / B, cb = col - jj * B;
-        v = in[(((size_t)jj * M + iv) * nch + g) * B + cb];
-      }
-      Is[ii][col - c0] = v;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int ii = 0; ii < RT; ++ii) {
-      double2 x = Is[ii][tx];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double av = As[ty + 8 * q][ii];
-        acc[q].x = fma(av, x.x, acc[q].x);
-        acc[q].y = fma(av, x.y, acc[q].y);
-      }
-    }
-    __syncthreads();
-  }
-  // epilogue: capture, scale, stage through LDS for coalesced stores
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int k = k0 + ty + 8 * q, col = c0 + tx;
-    double2 v = acc[q];
-    if (k < M && col < ncol) {
-      int jj = col / B, cb = col - jj * B;
-      if (r.acap && k == 0 && jj == r.j0[cb]) {
-        for (int f = 0; f < r.nfin; ++f)
-          if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = v;
-      }
-      if (SCALE) {
-        double2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
-        v = make_double2(v.x * gv.x - v.y * gv.y, v.x * gv.y + v.y * gv.x);
-      }
-    }
-    Is[ty + 8 * q][tx] = v;   // Is reused as [k][col]
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int e = tid + 256 * q;
-    int kk, col;
-    if (cfast) {
-      kk = e >> 5;
-      col = c0 + (e & 31);
-    } else {
-      kk = e & 31;
-      col = c0 + (e >> 5);
-    }
-    int k = k0 + kk;
-    if (k < M && col < ncol) {
-      int jj = col / B, cb = col - jj * B;
-      out[(((size_t)jj * M + k) * nch + g) * B + cb] = Is[kk][col - c0];
-    }
-  }
-}
-
-hipError_t launch_rot64(const RotArgs& r, const double2* in, double2* out, hipStream_t s) {
-  if (r.M < 1 || r.N < 1 || r.B < 1 || r.nch < 1) return hipErrorInvalidValue;
-  if (r.G == nullptr && r.acap != nullptr) return hipErrorInvalidValue;
-  dim3 grid((r.M + RT - 1) / RT, (r.N * r.B + RT - 1) / RT, r.nch);
-  if (r.G)
-    hipLaunchKernelGGL(k_rot64<true>, grid, dim3(256), 0, s, r, in, out);
-  else
-    hipLaunchKernelGGL(k_rot64<false>, grid, dim3(256), 0, s, r, in, out);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ solve: block-CSR SpMV (FP64)
-
-template <int NC>
-__global__ void __launch_bounds__(256) k_spmv64(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
-                                                const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                const double2* __restrict__ x, double2* __restrict__ y) {
-  int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  int lane = threadIdx.x & 63;
-  if (row >= rows) return;
-  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
-  for (int c = cb0; c < cb1; ++c) {
-    double ar[NC], ai[NC];
-#pragma unroll
-    for (int g = 0; g < NC; ++g) ar[g] = ai[g] = 0.0;
-    for (int64_t e = b0 + lane; e < b1; e += 64) {
-      const int cc = col[e];
-      const double* v = val + e * NC * NC;
-#pragma unroll
-      for (int gp = 0; gp < NC; ++gp) {
-        double2 xv = x[((size_t)cc * NC + gp) * B + c];
-#pragma unroll
-        for (int g = 0; g < NC; ++g) {
-          ar[g] = fma(v[g * NC + gp], xv.x, ar[g]);
-          ai[g] = fma(v[g * NC + gp], xv.y, ai[g]);
-        }
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < NC; ++g) {
-      double sr = wave_sum(ar[g]), si = wave_sum(ai[g]);
-      if (lane == g) y[((size_t)row * NC + g) * B + c] = make_double2(sr, si);
-    }
-  }
-}
-
-hipError_t launch_spmv64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
-                         const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
-  if (cb1 < 0) cb1 = B;
-  if (cb0 < 0 || cb1 > B || cb0 >= cb1) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((rows + 3) / 4)), blk(256);
-  switch (nch) {
-    case 1: hipLaunchKernelGGL(k_spmv64<1>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
-    case 2: hipLaunchKernelGGL(k_spmv64<2>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
-    case 3: hipLaunchKernelGGL(k_spmv64<3>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
-    case 4: hipLaunchKernelGGL(k_spmv64<4>, grid, blk, 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 // ------------------------------------------------------------------ solve: right-hand side
 
 __global__ void k_fill0(double2* __restrict__ p, int64_t n) {
@@ -954,10 +803,15 @@ static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* 
 }
 
 template <typename VT, typename XT, typename AT>
+hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1);
+
+template <typename VT, typename XT, typename AT>
 static hipError_t spmv_any(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
                            const XT* x, XT* y, hipStream_t s, int cb0, int cb1) {
   if (cb1 < 0) cb1 = B;
   if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1) return hipErrorInvalidValue;
+  if (nch > 4) return launch_spmv_gen<VT, XT, AT>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
   switch (nch) {
     case 1: spmv_dispatch<VT, XT, AT, 1>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
     case 2: spmv_dispatch<VT, XT, AT, 2>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
@@ -980,5 +834,207 @@ hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* ro
                                  const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
   return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
 }
+
+}  // namespace wpcd
+
+namespace wpcd {
+
+// ------------------------------------------------------------------ step 3 for many channels
+// With many channel pairs the P0 value of a cell pair is sum_m C[g][g'][m] I_m over the distinct
+// moments I_m = int dx dphi F w_m (Appendix, final formula, one term per (k, l1, l1')). The
+// moments of every candidate pair are computed first (node weights in LDS in chunks of MCH,
+// F recomputed per chunk), then combined with C in a second, dense contraction.
+#define MCH 32
+
+__global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
+                                                    const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
+                                                    int32_t* __restrict__ col_c, double* __restrict__ mom,
+                                                    double* __restrict__ norm) {
+  extern __shared__ double sh[];
+  const int M = a.M, N = a.N;
+  const int nn = a.n_x * a.n_phi;
+  const int box = blockIdx.x;
+  const int j = box / N, jp = box - j * N;
+  const int t = threadIdx.x;
+  double* s_r1 = sh;
+  double* s_r2 = s_r1 + nn;
+  double* s_Q1 = s_r2 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_w = s_Q2 + nn;            // [MCH][nn]
+  double* s_pe = s_w + MCH * nn;      // M + 1
+  int* s_pref = reinterpret_cast<int*>(s_pe + M + 1);
+  int* s_lo = s_pref + M + 1;
+  __shared__ int s_total;
+  if (t == 0) {
+    int run = 0;
+    for (int i = 0; i < M; ++i) {
+      s_pref[i] = run;
+      s_lo[i] = lo[(size_t)box * M + i];
+      run += cnt[(size_t)box * M + i];
+    }
+    s_pref[M] = run;
+    s_total = run;
+  }
+  __syncthreads();
+  const int total = s_total;
+  if (total == 0) return;
+  for (int i = t; i <= M; i += blockDim.x) s_pe[i] = a.pe[i];
+  for (int nd = t; nd < nn; nd += blockDim.x) {
+    Node n = box_node(a, j, jp, nd);
+    s_r1[nd] = n.r1;
+    s_r2[nd] = n.r2;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
+  }
+  __syncthreads();
+  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  for (int m0 = 0; m0 < a.nmom; m0 += MCH) {
+    const int mc = min(MCH, a.nmom - m0);
+    __syncthreads();
+    for (int e = t; e < mc * nn; e += blockDim.x) {
+      const int m = e / nn, nd = e - m * nn;
+      Node n = box_node(a, j, jp, nd);
+      s_w[m * nn + nd] = moment_weight(n, a.keys + 5 * (m0 + m));
+    }
+    __syncthreads();
+    for (int e = t; e < total; e += blockDim.x) {
+      int lo_i = 0, hi_i = M - 1;
+      while (lo_i < hi_i) {
+        int mid = (lo_i + hi_i + 1) >> 1;
+        if (s_pref[mid] <= e) lo_i = mid;
+        else hi_i = mid - 1;
+      }
+      const int i = lo_i;
+      const int ip = s_lo[i] + (e - s_pref[i]);
+      const double pa = s_pe[i], pb = s_pe[i + 1], ppa = s_pe[ip], ppb = s_pe[ip + 1];
+      double acc[MCH];
+#pragma unroll
+      for (int m = 0; m < MCH; ++m) acc[m] = 0.0;
+      for (int nd = 0; nd < nn; ++nd) {
+        const double r1 = s_r1[nd], r2 = s_r2[nd];
+        const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
+        const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
+        const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+        if (F != 0.0) {
+#pragma unroll
+          for (int m = 0; m < MCH; ++m) acc[m] = fma(s_w[m * nn + nd], F, acc[m]);
+        }
+      }
+      const int64_t blk = rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] + (ip - s_lo[i]);
+      for (int m = 0; m < mc; ++m) mom[blk * a.nmom + m0 + m] = acc[m];
+      if (m0 == 0) {
+        col_c[blk] = jp * M + ip;
+        norm[blk] = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+      }
+    }
+  }
+}
+
+// val[blk][gg] = norm[blk] * sum_m Ct[m][gg] mom[blk][m]; NBT candidate blocks per workgroup
+// with their moments in LDS, threads over the channel pairs gg.
+#define NBT 16
+__global__ void __launch_bounds__(256) k_combine(int64_t nblk, int nmom, int nc2, const double* __restrict__ Ct,
+                                                 const double* __restrict__ mom, const double* __restrict__ norm,
+                                                 double* __restrict__ val, uint8_t* __restrict__ flag) {
+  extern __shared__ double smom[];   // [NBT][nmom]
+  __shared__ int snz[NBT];
+  const int64_t b0 = (int64_t)blockIdx.x * NBT;
+  const int nb = (int)min((int64_t)NBT, nblk - b0);
+  for (int e = threadIdx.x; e < NBT * nmom; e += blockDim.x) {
+    const int b = e / nmom, m = e - b * nmom;
+    smom[e] = (b < nb) ? mom[(b0 + b) * nmom + m] : 0.0;
+  }
+  if (threadIdx.x < NBT) snz[threadIdx.x] = 0;
+  __syncthreads();
+  for (int gg = threadIdx.x; gg < nc2; gg += blockDim.x) {
+    double acc[NBT];
+#pragma unroll
+    for (int b = 0; b < NBT; ++b) acc[b] = 0.0;
+    for (int m = 0; m < nmom; ++m) {
+      const double c = Ct[(size_t)m * nc2 + gg];
+      if (c == 0.0) continue;
+#pragma unroll
+      for (int b = 0; b < NBT; ++b) acc[b] = fma(c, smom[b * nmom + m], acc[b]);
+    }
+    for (int b = 0; b < nb; ++b) {
+      const double v = acc[b] * norm[b0 + b];
+      val[(b0 + b) * nc2 + gg] = v;
+      if (v != 0.0) snz[b] = 1;   // benign race: every writer stores 1
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nb) flag[b0 + threadIdx.x] = (uint8_t)snz[threadIdx.x];
+}
+
+hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const int* cnt, const int* lo, const int* segoff,
+                                 const int64_t* rowptr_c, int64_t ncand, int32_t* col_c, double* mom, double* norm,
+                                 double* val_c, uint8_t* flag, hipStream_t s) {
+  const int nn = a.n_x * a.n_phi;
+  if (nn < 1 || nn > PB_MAXNODES || a.nmom < 1 || a.nch < 1) return hipErrorInvalidValue;
+  const size_t sh1 = (size_t)nn * (4 + MCH) * sizeof(double) + (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
+  if (sh1 > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pbuild_mom, dim3(a.N * a.N), dim3(256), sh1, s, a, cnt, lo, segoff, rowptr_c, col_c, mom, norm);
+  const size_t sh2 = (size_t)NBT * a.nmom * sizeof(double);
+  if (sh2 > 64 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)((ncand + NBT - 1) / NBT)), dim3(256), sh2, s, ncand, a.nmom,
+                     a.nch * a.nch, Ct, mom, norm, val_c, flag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ block-CSR product, many channels
+// One wavefront per block row; lanes over (g, c) outputs (NC x cols), looping over g' per block.
+template <typename VT, typename XT, typename AT>
+__global__ void __launch_bounds__(256) k_spmv_gen(int64_t rows, int NC, int B, int cb0, int cb1,
+                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int ncols = cb1 - cb0;
+  const int nout = NC * ncols;
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  const int nc2 = NC * NC;
+  for (int o0 = 0; o0 < nout; o0 += 64) {
+    const int o = o0 + lane;
+    const bool act = o < nout;
+    const int g = act ? o / ncols : 0;
+    const int c = cb0 + (act ? o - g * ncols : 0);
+    AT ar = 0, ai = 0;
+    if (act) {
+      for (int64_t e = b0; e < b1; ++e) {
+        const int cc = col[e];
+        const VT* v = val + e * nc2 + g * NC;
+        const XT* xr = x + (size_t)cc * NC * B + c;
+        for (int gp = 0; gp < NC; ++gp) {
+          const AT a = (AT)v[gp];
+          const XT xv = xr[(size_t)gp * B];
+          ar = fma(a, (AT)xv.x, ar);
+          ai = fma(a, (AT)xv.y, ai);
+        }
+      }
+      XT out;
+      out.x = ar;
+      out.y = ai;
+      y[((size_t)row * NC + g) * B + c] = out;
+    }
+  }
+}
+
+template <typename VT, typename XT, typename AT>
+hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1) {
+  if (cb1 < 0) cb1 = B;
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B, cb0, cb1,
+                     rowptr, col, val, x, y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_spmv_gen<double, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
+                                                             const double*, const double2*, double2*, hipStream_t, int, int);
+template hipError_t launch_spmv_gen<float, float2, float>(int64_t, int, int, const int64_t*, const int32_t*,
+                                                          const float*, const float2*, float2*, hipStream_t, int, int);
+template hipError_t launch_spmv_gen<float, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
+                                                            const float*, const double2*, double2*, hipStream_t, int, int);
 
 }  // namespace wpcd

@@ -102,6 +102,11 @@ hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp,
 hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
                          const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag,
                          hipStream_t s);
+// Many moments: moments of every candidate pair, then values = norm * (moments x C^T).
+// Ct is [nmom][nch*nch]; mom [ncand][nmom] and norm [ncand] are scratch.
+hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const int* cnt, const int* lo, const int* segoff,
+                                 const int64_t* rowptr_c, int64_t ncand, int32_t* col_c, double* mom, double* norm,
+                                 double* val_c, uint8_t* flag, hipStream_t s);
 hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt,
                            hipStream_t s);
 hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c,
@@ -120,13 +125,8 @@ struct RotArgs {
   int nfin;
   int64_t acap_off;      // offset (in double2) of this term's capture row: acap[acap_off + c*nfin + f]
 };
-hipError_t launch_rot64(const RotArgs& r, const double2* in, double2* out, hipStream_t s);
 // fused s = W (G1 * (O y)) with capture; r.A = O, W = v O^T (same wave layout), r.G required
 hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s);
-// y = P0 x for the columns [cb0, cb1) (cb1 < 0: all B columns)
-hipError_t launch_spmv64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
-                         const double* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
-                         int cb1 = -1);
 // s0 = (v O^T) e0 on the columns [cb0, cb1): the deuteron column W[:, 0] of channel g0[c] at q bin j0[c]
 hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, const int* wave,
                              const int* j0, const int* g0, double2* s0, hipStream_t st, int cb0 = 0,

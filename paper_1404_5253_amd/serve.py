@@ -1,0 +1,178 @@
+"""Continuous-batching serving loop over resident lattices (faddeev_batch_* of libwpcd).
+
+Each resident lattice owns one batch (a fixed number of energy slots sized by a device-memory
+budget) and one worker thread with its own HIP stream, so the steps of different lattices
+overlap on the GPU (ctypes releases the GIL inside library calls). A request
+(arrival time, lattice, E_lab) waits in its lattice's queue until a slot is free, is admitted
+between two steps of that batch, advances with every step of the batch and retires as soon as
+its Pade estimate is accepted; latency = retirement time - arrival time.
+
+The scheduler only talks to a backend object with admit(E) -> slot | None, step() -> list of
+(slot, result) and live(), so it is tested on the CPU with a fake backend and a virtual clock.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+
+@dataclass
+class Request:
+    rid: int
+    t_arrival: float
+    lattice: int
+    E_lab: float
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    result: dict = field(default=None)
+
+
+class BatchBackend:
+    """One lattice's continuous batch on the GPU (FP64 path)."""
+
+    def __init__(self, lattice, slots, hbm_budget, terms=4, tol=1e-12, accept=1e-7, max_iter=200, stream=None):
+        import paper_1404_5253_amd as wp
+        self.wp = wp
+        self.L = lattice
+        self.terms = terms
+        o = wp._SolveOpts(wp.WP_SOLVE_FP64, tol, accept, max_iter, 0)
+        self.h = C.c_void_p()
+        wp._check(wp._lib.faddeev_batch_create(lattice.h, slots, hbm_budget, C.byref(o), C.byref(self.h)))
+        self.slots = slots
+        self.stream = stream
+        self._done = (C.c_int * slots)()
+
+    def admit(self, E_lab):
+        sl = C.c_int()
+        st = self.wp._lib.faddeev_batch_admit(self.h, E_lab, C.byref(sl))
+        if st == self.wp.WP_EBUDGET:
+            return None
+        self.wp._check(st)
+        return sl.value
+
+    def live(self):
+        n = C.c_int()
+        self.wp._check(self.wp._lib.faddeev_batch_live(self.h, C.byref(n)))
+        return n.value
+
+    def step(self):
+        n = C.c_int()
+        self.wp._check(self.wp._lib.faddeev_batch_step(self.h, self.stream, self.terms, C.byref(n), self._done))
+        out = []
+        for k in range(n.value):
+            sl = self._done[k]
+            hs = C.c_void_p()
+            st = self.wp._lib.faddeev_batch_take(self.h, sl, C.byref(hs))
+            if st not in (self.wp.WP_OK, self.wp.WP_ENOCONV):
+                self.wp._check(st)
+            res = self.wp.amplitude(hs, 0)
+            res["accepted"] = st == self.wp.WP_OK
+            self.wp._lib.wp_solution_free(hs)
+            out.append((sl, res))
+        return out
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            self.wp._lib.faddeev_batch_free(self.h)
+            self.h = None
+
+
+class LatticeWorker:
+    """Admission + stepping loop of one lattice; runs in its own thread."""
+
+    def __init__(self, backend, clock):
+        self.b = backend
+        self.clock = clock
+        self.queue = deque()
+        self.inflight = {}
+        self.finished = []
+        self.lock = threading.Lock()
+        self.steps = 0
+
+    def submit(self, req):
+        with self.lock:
+            self.queue.append(req)
+
+    def pump(self):
+        """Admit what fits, then one step. Returns True if any work was done."""
+        with self.lock:
+            while self.queue:
+                sl = self.b.admit(self.queue[0].E_lab)
+                if sl is None:
+                    break
+                req = self.queue.popleft()
+                req.t_admit = self.clock()
+                self.inflight[sl] = req
+        if not self.inflight:
+            return False
+        for sl, res in self.b.step():
+            req = self.inflight.pop(sl)
+            req.t_done = self.clock()
+            req.result = res
+            self.finished.append(req)
+        self.steps += 1
+        return True
+
+
+def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, threaded=True):
+    """Serve (t_arrival, lattice, E_lab) requests in arrival order; returns finished Requests and stats.
+
+    With threaded=True each lattice is stepped by its own thread; with False a single loop
+    round-robins the lattices (deterministic, used with a virtual clock).
+    """
+    reqs = [Request(k, t, lat, E) for k, (t, lat, E) in enumerate(sorted(requests))]
+    t0 = clock()
+    now = lambda: clock() - t0
+    workers = [LatticeWorker(b, now) for b in backends]
+    pending = deque(reqs)
+    stop = threading.Event()
+
+    def feed():
+        while pending and pending[0].t_arrival <= now():
+            r = pending.popleft()
+            workers[r.lattice].submit(r)
+
+    def worker_loop(w):
+        while not stop.is_set():
+            if not w.pump():
+                sleep(0.0002)
+
+    if threaded:
+        threads = [threading.Thread(target=worker_loop, args=(w,), daemon=True) for w in workers]
+        for t in threads:
+            t.start()
+        while pending or any(w.queue or w.inflight for w in workers):
+            feed()
+            if pending and pending[0].t_arrival > now():
+                sleep(min(0.001, pending[0].t_arrival - now()))
+            else:
+                sleep(0.0005)
+        stop.set()
+        for t in threads:
+            t.join()
+    else:
+        while pending or any(w.queue or w.inflight for w in workers):
+            feed()
+            busy = False
+            for w in workers:
+                busy |= w.pump()
+            if not busy and pending:
+                sleep(max(0.0, pending[0].t_arrival - now()))
+    t_end = now()
+    done = [r for w in workers for r in w.finished]
+    done.sort(key=lambda r: r.rid)
+    lat = sorted(r.t_done - r.t_arrival for r in done)
+
+    def pct(p):
+        if not lat:
+            return float("nan")
+        k = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
+        return lat[k]
+    span = (max(r.t_done for r in done) - min(r.t_arrival for r in done)) if done else 0.0
+    stats = dict(n=len(done), p50_ms=pct(50) * 1e3, p99_ms=pct(99) * 1e3, mean_ms=(sum(lat) / len(lat) * 1e3) if lat else 0,
+                 solves_per_s=len(done) / span if span > 0 else 0.0, wall_s=t_end,
+                 steps=[w.steps for w in workers])
+    return done, stats

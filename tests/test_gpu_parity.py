@@ -51,6 +51,8 @@ def _oracle_blocks(s):
 
 
 SPECS = {
+    "pw10_mt_8": pipeline.Spec(M=8, N=8, two_J=1, j_max=1, swave_only=False, pot="mt"),
+    "pw18_mt_6": pipeline.Spec(M=6, N=7, two_J=1, j_max=2, swave_only=False, pot="mt"),
     "quartet_yam_24": pipeline.Spec(M=24, N=24, two_J=3, pot="yamaguchi"),
     "doublet_mt_20": pipeline.Spec(M=20, N=20, two_J=1, pot="mt"),
     "quartet_yam_ragged_17x13": pipeline.Spec(M=17, N=13, two_J=3, pot="yamaguchi", n_x=6, n_phi=10),
@@ -125,7 +127,8 @@ def test_p0_rebuild_is_bit_identical():
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("name,E", [("quartet_yam_24", 1.0), ("quartet_yam_24", 3.0), ("quartet_yam_24", 10.0),
+@pytest.mark.parametrize("name,E", [("pw10_mt_8", 3.0), ("pw10_mt_8", 22.7), ("pw18_mt_6", 3.0),
+                                    ("quartet_yam_24", 1.0), ("quartet_yam_24", 3.0), ("quartet_yam_24", 10.0),
                                     ("doublet_mt_20", 3.0), ("doublet_mt_20", 14.1),
                                     ("quartet_yam_ragged_17x13", 10.0)])
 def test_solve_fp64_matches_oracle(systems, name, E):
@@ -134,18 +137,21 @@ def test_solve_fp64_matches_oracle(systems, name, E):
     sol = L.solve([E], "fp64")
     got = sol.amplitude(0)
     ref = pipeline.solve_energy(s, E)
-    a, b = got["A"][0, 0], ref["A"][0, 0]
-    bound = 1e-10 * abs(b) + 30 * max(got["err"][0], ref["rel_err"]) * abs(b)
+    A, Ar = got["A"], ref["A"]
+    scale = np.max(np.abs(Ar))
+    bound = 1e-10 * scale + 30 * max(np.max(got["err"]), ref["rel_err"]) * scale
     if name.startswith("quartet"):
-        bound = 1e-10 * abs(b)
-    assert abs(a - b) <= bound, (abs(a - b) / abs(b), got["err"], ref["rel_err"])
+        bound = 1e-10 * scale
+    assert np.max(np.abs(A - Ar)) <= bound, (np.max(np.abs(A - Ar)) / scale, got["err"], ref["rel_err"])
     if SPECS[name].M * SPECS[name].N * len(s.chans) <= 1000:
         # against the exact discrete solution (dense LU): Pade on the divergent doublet series
         # reaches about 1e-9 relative (measured), the convergent quartet series 1e-12
         d = pipeline.solve_energy(s, E, direct=True)
         lim = 1e-10 if name.startswith("quartet") else 1e-8
-        assert abs(a - d["A"][0, 0]) <= lim * abs(d["A"][0, 0])
-    if E < 1.5 * 2.2246:   # below breakup: |S| = 1 for the discrete system
+        assert np.max(np.abs(A - d["A"])) <= lim * np.max(np.abs(d["A"]))
+    if E < 1.5 * 2.2246 and len(got["S"]) == 1:
+        # below breakup with one open channel, G1 has a single imaginary entry and the discrete
+        # S is exactly unitary (with two open channels only up to discretisation errors)
         assert abs(abs(got["S"][0, 0]) - 1.0) < 1e-9
 
 
