@@ -773,56 +773,45 @@ wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
   return WP_OK;
 }
 
-// [L/M] Pade of sum a_n: denominator q (q_0 = 1) from sum_{i=0}^{M} q_i a_{n-i} = 0, n = L+1..L+M
-// (complex Gaussian elimination with partial pivoting). Returns false if singular.
-static bool pade_denominator(const std::vector<cplx>& a, int Lp, int Mq, std::vector<cplx>& q) {
-  q.assign(Mq + 1, cplx(0, 0));
-  q[0] = 1.0;
-  if (Mq == 0) return true;
-  std::vector<cplx> H((size_t)Mq * (Mq + 1));
-  for (int r = 0; r < Mq; ++r) {
-    for (int i = 1; i <= Mq; ++i) {
-      int idx = Lp + 1 + r - i;
-      H[(size_t)r * (Mq + 1) + (i - 1)] = idx >= 0 ? a[idx] : cplx(0, 0);
+// Least squares min || beta e1 - H z || for an (m+1) x m upper Hessenberg H (column-major by j:
+// H[j*(m+1) + i]) by Givens rotations; returns z (m entries).
+static std::vector<cplx> hessenberg_ls(std::vector<cplx> H, int m, double beta) {
+  const int ld = m + 1;
+  std::vector<cplx> g(m + 1, cplx(0, 0));
+  g[0] = beta;
+  for (int j = 0; j < m; ++j) {
+    cplx a = H[j * ld + j], bb = H[j * ld + j + 1];
+    double r = std::sqrt(std::norm(a) + std::norm(bb));
+    if (r == 0.0) continue;
+    cplx c = a / r, sn = bb / r;   // rotation [conj(c) conj(s); -s c]
+    for (int k = j; k < m; ++k) {
+      cplx x = H[k * ld + j], y = H[k * ld + j + 1];
+      H[k * ld + j] = std::conj(c) * x + std::conj(sn) * y;
+      H[k * ld + j + 1] = -sn * x + c * y;
     }
-    H[(size_t)r * (Mq + 1) + Mq] = -a[Lp + 1 + r];
+    cplx x = g[j], y = g[j + 1];
+    g[j] = std::conj(c) * x + std::conj(sn) * y;
+    g[j + 1] = -sn * x + c * y;
   }
-  for (int c = 0; c < Mq; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < Mq; ++r)
-      if (std::abs(H[(size_t)r * (Mq + 1) + c]) > std::abs(H[(size_t)piv * (Mq + 1) + c])) piv = r;
-    if (std::abs(H[(size_t)piv * (Mq + 1) + c]) == 0.0) return false;
-    if (piv != c)
-      for (int k = 0; k <= Mq; ++k) std::swap(H[(size_t)c * (Mq + 1) + k], H[(size_t)piv * (Mq + 1) + k]);
-    for (int r = c + 1; r < Mq; ++r) {
-      cplx f = H[(size_t)r * (Mq + 1) + c] / H[(size_t)c * (Mq + 1) + c];
-      for (int k = c; k <= Mq; ++k) H[(size_t)r * (Mq + 1) + k] -= f * H[(size_t)c * (Mq + 1) + k];
-    }
+  std::vector<cplx> z(m, cplx(0, 0));
+  for (int j = m - 1; j >= 0; --j) {
+    cplx v = g[j];
+    for (int k = j + 1; k < m; ++k) v -= H[k * ld + j] * z[k];
+    z[j] = std::abs(H[j * ld + j]) > 0.0 ? v / H[j * ld + j] : cplx(0, 0);
   }
-  for (int c = Mq - 1; c >= 0; --c) {
-    cplx v = H[(size_t)c * (Mq + 1) + Mq];
-    for (int k = c + 1; k < Mq; ++k) v -= H[(size_t)c * (Mq + 1) + k] * q[k + 1];
-    q[c + 1] = v / H[(size_t)c * (Mq + 1) + c];
-  }
-  for (auto& x : q)
-    if (!std::isfinite(x.real()) || !std::isfinite(x.imag())) return false;
-  return true;
+  return z;
 }
 
-// Weights w_m (m = 0..Lp) of the vector [Lp/Mq] approximant y = sum_m w_m v_m, whose projection
-// sum_m w_m a_m is the scalar Pade value P(1)/Q(1).
-static void pade_weights(const std::vector<cplx>& q, int Lp, std::vector<cplx>& w) {
-  const int Mq = (int)q.size() - 1;
-  cplx Q1 = 0.0;
-  for (auto& x : q) Q1 += x;
-  w.assign(Lp + 1, cplx(0, 0));
-  for (int m = 0; m <= Lp; ++m) {
-    cplx s = 0.0;
-    for (int i = 0; i <= std::min(Mq, Lp - m); ++i) s += q[i];
-    w[m] = s / Q1;
-  }
-}
-
+// Mixed path: iterative refinement in FP64 around a mixed-precision GMRES.
+//   outer (FP64): r = b - (I - K) y with FP64 blocks and G1, the FP32-stored P0 accumulated in
+//                 FP64; the same launch yields U_0 = e0^T O y exactly;
+//   inner:        m Arnoldi steps on (I - K~) with K~ = P0(FP32) (v O^T)(BF16, MFMA) G1(FP32)
+//                 O(BF16, MFMA), FP32 basis vectors, classical Gram-Schmidt applied twice with
+//                 FP64 sums; the small least-squares problem per energy on the host (FP64);
+//                 y += V z.
+// Stop when U_0 changes by <= tol |U_0| between two outer steps. A Neumann series in low precision
+// would amplify every term's rounding by the growth of the divergent series, which is why the
+// inner solver is orthogonalised.
 static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                              wp_solution* sol) {
   const int M = L->M, N = L->N, nch = L->nch;
@@ -845,17 +834,19 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
     }
   }
   if (wp_status st = ensure_mixed(L, s)) return st;
-  const int Lmax = std::max(8, std::min(200, o.refine_every > 0 ? o.refine_every : 48));
-  const int max_outer = 8;
-  const int chunk = 8;
-  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dacap64, dcoef;
-  DBuf<float2> dG32, V, dt32, dacap32;
+  const int m = std::max(4, std::min(40, o.refine_every > 0 ? o.refine_every : 20));
+  const int max_outer = std::max(2, std::min(30, o.max_iter / m + 2));
+  const int nblk = 256;
+  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dacap64, dcoef, H1, H2, part, nrm;
+  DBuf<float2> dG32, V, w32, kv32, t32;
   DBuf<int> dj0, dg0, dfin;
   DBuf<double> dE;
   if (!dG64.make(&L->al, DB) || !db.make(&L->al, DB) || !dy.make(&L->al, DB) || !dr.make(&L->al, DB) ||
       !dKy.make(&L->al, DB) || !ds64.make(&L->al, DB) || !dacap64.make(&L->al, (size_t)B * nfin) ||
-      !dcoef.make(&L->al, (size_t)(Lmax + 1) * B) || !dG32.make(&L->al, DB) || !V.make(&L->al, (size_t)(Lmax + 1) * DB) ||
-      !dt32.make(&L->al, DB) || !dacap32.make(&L->al, (size_t)(Lmax + chunk) * B * nfin) || !dj0.make(&L->al, B) ||
+      !dcoef.make(&L->al, (size_t)(m + 1) * B) || !H1.make(&L->al, (size_t)m * (m + 1) * B) ||
+      !H2.make(&L->al, (size_t)m * (m + 1) * B) || !part.make(&L->al, (size_t)nblk * (m + 1) * B) ||
+      !nrm.make(&L->al, B) || !dG32.make(&L->al, DB) || !V.make(&L->al, (size_t)(m + 1) * DB) ||
+      !w32.make(&L->al, DB) || !kv32.make(&L->al, DB) || !t32.make(&L->al, DB) || !dj0.make(&L->al, B) ||
       !dg0.make(&L->al, B) || !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
     return fail(WP_ENOMEM, "device allocation (mixed solve)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));
@@ -864,113 +855,83 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
   HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
   WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG64.p), s));
   HIPCHECK(launch_cvt_d2f(DB, dG64.p, dG32.p, s));
-  // b = P0 (v O^T) e0 with the FP32-stored P0, FP64 vectors and accumulation
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds64.p, s));
-  WP_LAUNCH("spmv_f32v_f64x", s, launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s));
+  WP_LAUNCH("spmv_f32v_f64x", s,
+            launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s));
   HIPCHECK(launch_fill0(dy.p, DB, s));
-  std::vector<cplx> U((size_t)B * nfin, cplx(0, 0)), Uy((size_t)B * nfin, cplx(0, 0));
+  std::vector<cplx> U((size_t)B * nfin, cplx(0, 0)), Uprev((size_t)B * nfin, cplx(0, 0));
   std::vector<double> err(B, 1.0);
   std::vector<int> iters(B, 0);
   std::vector<bool> done(B, false);
-  std::vector<float2> hcap((size_t)chunk * B * nfin);
-  std::vector<double2> hcap64((size_t)B * nfin);
-  const double outer_tol = std::max(o.tol, 1e-14);
-  for (int outer = 0; outer < max_outer; ++outer) {
-    // FP64 residual r = b - (I - K) y and e^T O y of the current y
-    if (outer == 0) {
-      HIPCHECK(launch_cvt_d2f(DB, db.p, V.p, s));
-    } else {
-      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, dacap64.p, dj0.p, dfin.p, nfin, 0};
-      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
-      WP_LAUNCH("spmv_f32v_f64x", s, launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
-      HIPCHECK(launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
-      HIPCHECK(launch_cvt_d2f(DB, dr.p, V.p, s));
-      HIPCHECK(hipMemcpyAsync(hcap64.data(), dacap64.p, hcap64.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      for (size_t e = 0; e < Uy.size(); ++e) Uy[e] = cplx(hcap64[e].x, hcap64[e].y);
-    }
-    // mixed-precision Neumann terms of the correction, stored for the vector Pade
-    std::vector<ColState> cs(B);
-    std::vector<std::vector<std::vector<cplx>>> terms(B, std::vector<std::vector<cplx>>(nfin));
-    for (auto& c : cs) {
-      c.w.resize(nfin);
-      c.S.assign(nfin, cplx(0, 0));
-      c.plateau = 8;
-    }
-    int n = 0;
-    bool all = false;
-    while (n < Lmax && !all) {
-      const int T = std::min(chunk, Lmax - n);
-      for (int t = 0; t < T; ++t) {
-        RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, L->Mp, L->d_wave.p, dG32.p, dacap32.p, dj0.p, dfin.p, nfin,
-                        (int64_t)(n + t) * B * nfin};
-        WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, L->d_Wb.p, V.p + (size_t)(n + t) * DB, dt32.p, s));
-        WP_LAUNCH("spmv32", s, launch_spmv_f32(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, dt32.p,
-                                               V.p + (size_t)(n + t + 1) * DB, s));
-      }
-      HIPCHECK(hipMemcpyAsync(hcap.data(), dacap32.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(float2),
-                              hipMemcpyDeviceToHost, s));
-      HIPCHECK(hipStreamSynchronize(s));
-      all = true;
-      for (int c = 0; c < B; ++c) {
-        for (int t = 0; t < T; ++t) {
-          std::vector<cplx> a(nfin);
-          for (int f = 0; f < nfin; ++f) {
-            float2 v = hcap[((size_t)t * B + c) * nfin + f];
-            a[f] = cplx(v.x, v.y);
-            terms[c][f].push_back(a[f]);
-          }
-          if (!cs[c].done) column_push(cs[c], a.data(), nfin, 1e-6, 1.0);
-        }
-        all &= cs[c].done || done[c];
-      }
-      n += T;
-    }
-    // vector Pade per column: the [L/M] (M <= 8, L = n - 1 - M) closest to Wynn's best estimate
-    std::vector<double2> coef((size_t)(Lmax + 1) * B, make_double2(0.0, 0.0));
-    bool any_active = false;
+  std::vector<double2> hc((size_t)B * nfin), h1((size_t)m * (m + 1) * B), h2((size_t)m * (m + 1) * B), hn(B);
+  std::vector<double2> coef((size_t)(m + 1) * B);
+  const double tol = std::max(o.tol, 1e-14);
+  for (int outer = 0; outer <= max_outer; ++outer) {
+    // FP64 residual and the exact e0^T O y of the current y
+    RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, dacap64.p, dj0.p, dfin.p, nfin, 0};
+    WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
+    WP_LAUNCH("spmv_f32v_f64x", s,
+              launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
+    HIPCHECK(launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
+    HIPCHECK(hipMemcpyAsync(hc.data(), dacap64.p, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(launch_norm2_f64(D, B, dr.p, part.p, nblk, nrm.p, s));
+    HIPCHECK(hipMemcpyAsync(hn.data(), nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    bool all = true;
     for (int c = 0; c < B; ++c) {
       if (done[c]) continue;
-      any_active = true;
-      const int fi = c % nfin;  // the column's own initial channel defines the denominator
-      const std::vector<cplx>& a = terms[c][fi];
-      const cplx target = cs[c].best.empty() ? cs[c].last[fi] : cs[c].best[fi];
-      std::vector<cplx> bestw;
-      double bestd = INFINITY;
-      for (int Mq = 0; Mq <= 8 && 2 * Mq + 1 <= n; ++Mq) {
-        const int Lp = n - 1 - Mq;
-        std::vector<cplx> q, w;
-        if (!pade_denominator(a, Lp, Mq, q)) continue;
-        pade_weights(q, Lp, w);
-        cplx val = 0.0;
-        for (int m = 0; m <= Lp; ++m) val += w[m] * a[m];
-        double d = std::abs(val - target);
-        if (d < bestd) {
-          bestd = d;
-          bestw = w;
-        }
-      }
-      if (bestw.empty()) {
-        bestw.assign(n, cplx(1.0, 0.0));   // plain partial sum
-      }
-      double maxrel = 0.0;
+      double change = 0.0, mag = 0.0;
       for (int f = 0; f < nfin; ++f) {
-        cplx corr = 0.0;
-        for (size_t m = 0; m < bestw.size(); ++m) corr += bestw[m] * terms[c][f][m];
-        U[(size_t)c * nfin + f] = Uy[(size_t)c * nfin + f] + corr;
-        maxrel = std::max(maxrel, std::abs(corr) / std::max(std::abs(U[(size_t)c * nfin + f]), 1e-300));
+        cplx u(hc[(size_t)c * nfin + f].x, hc[(size_t)c * nfin + f].y);
+        U[(size_t)c * nfin + f] = u;
+        change = std::max(change, std::abs(u - Uprev[(size_t)c * nfin + f]));
+        mag = std::max(mag, std::abs(u));
+        Uprev[(size_t)c * nfin + f] = u;
       }
-      for (size_t m = 0; m < bestw.size(); ++m) coef[m * B + c] = make_double2(bestw[m].real(), bestw[m].imag());
-      err[c] = maxrel;
-      iters[c] += n;
-      if (maxrel <= outer_tol) done[c] = true;
+      if (outer > 0) {
+        err[c] = change / std::max(mag, 1e-300);
+        if (err[c] <= tol) done[c] = true;
+      }
+      all &= done[c];
     }
-    if (!any_active) break;
+    if (all || outer == max_outer) break;
+    // inner: m Arnoldi steps on (I - K~) started from r / |r|
+    HIPCHECK(launch_scale_d2f(D, B, nrm.p, dr.p, V.p, s));
+    for (int j = 0; j < m; ++j) {
+      float2* Vj = V.p + (size_t)j * DB;
+      RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, L->Mp, L->d_wave.p, dG32.p, nullptr, dj0.p, dfin.p, nfin, 0};
+      WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, L->d_Wb.p, Vj, t32.p, s));
+      WP_LAUNCH("spmv32", s, launch_spmv_f32(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, t32.p, kv32.p, s));
+      HIPCHECK(launch_sub_f32(DB, Vj, kv32.p, w32.p, s));
+      double2* h1j = H1.p + (size_t)j * (m + 1) * B;
+      double2* h2j = H2.p + (size_t)j * (m + 1) * B;
+      WP_LAUNCH("arnoldi", s, launch_mdot(D, B, j + 1, V.p, DB, w32.p, part.p, nblk, h1j, 0, s));
+      HIPCHECK(launch_orth_update(D, B, j + 1, V.p, DB, h1j, w32.p, s));
+      WP_LAUNCH("arnoldi", s, launch_mdot(D, B, j + 1, V.p, DB, w32.p, part.p, nblk, h2j, 0, s));
+      HIPCHECK(launch_orth_update(D, B, j + 1, V.p, DB, h2j, w32.p, s));
+      WP_LAUNCH("arnoldi", s, launch_mdot(D, B, 1, w32.p, DB, w32.p, part.p, nblk, nrm.p, 0, s));
+      HIPCHECK(launch_normalize(D, B, nrm.p, w32.p, V.p + (size_t)(j + 1) * DB, h1j + (size_t)(j + 1) * B, s));
+      HIPCHECK(launch_fill0(h2j + (size_t)(j + 1) * B, B, s));
+    }
+    HIPCHECK(hipMemcpyAsync(h1.data(), H1.p, h1.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(h2.data(), H2.p, h2.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    std::fill(coef.begin(), coef.end(), make_double2(0.0, 0.0));
+    for (int c = 0; c < B; ++c) {
+      if (done[c]) continue;
+      std::vector<cplx> Hc((size_t)m * (m + 1));
+      for (int j = 0; j < m; ++j)
+        for (int i = 0; i <= m; ++i) {
+          const size_t idx = ((size_t)j * (m + 1) + i) * B + c;
+          Hc[(size_t)j * (m + 1) + i] = cplx(h1[idx].x + h2[idx].x, h1[idx].y + h2[idx].y);
+        }
+      const double beta = std::sqrt(std::max(hn[c].x, 0.0));
+      std::vector<cplx> z = hessenberg_ls(Hc, m, beta);
+      for (int i = 0; i < m; ++i) coef[(size_t)i * B + c] = make_double2(z[i].real(), z[i].imag());
+      iters[c] += m;
+    }
     HIPCHECK(hipMemcpyAsync(dcoef.p, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-    HIPCHECK(launch_lincomb(D, B, Lmax + 1, V.p, DB, dcoef.p, dy.p, s));
-    bool alldone = true;
-    for (int c = 0; c < B; ++c) alldone &= done[c];
-    if (alldone) break;
+    HIPCHECK(launch_lincomb(D, B, m, V.p, DB, dcoef.p, dy.p, s));
   }
   HIPCHECK(hipStreamSynchronize(s));
   bool allok = true;

@@ -488,30 +488,29 @@ namespace wpcd {
 
 // ------------------------------------------------------------------ step 4: channel resolvent G1
 
-// Continuum element (1/(dp dq)) int int dp dq / (E + i0 - h p^2 - b3 q^2) (eq. dg1b, unit weights).
+// Continuum element (1/(dp dq)) int int dp dq / (E + i0 - h p^2 - b3 q^2) (eq. dg1b, unit weights),
+// evaluated by one wavefront: lanes share the quadrature nodes, a shuffle reduction sums them.
 // E < 0: p integral in closed form (arctangent), q integral by two 20-point Gauss panels.
 // E > 0: p = P r cos t, q = Q r sin t (P = sqrt(E/h), Q = sqrt(E/b3)) gives
 //   Re = (1/sqrt(h b3)) int dt [-1/2 ln|1 - r^2|]_{r_lo(t)}^{r_hi(t)},
 // split at the box corners and where the energy shell r = 1 crosses a box edge (log
 // singularities), each piece by tanh-sinh; Im = -(pi / (2 sqrt(h b3))) x (angle of the shell
 // inside the box).
-__device__ double2 g1_continuum_dev(const G1Args& g, double pa, double pb, double qa, double qb, double E) {
+__device__ double2 g1_continuum_wave(const G1Args& g, int lane, double pa, double pb, double qa, double qb, double E) {
   const double h = g.h2m, b3 = 0.75 * g.h2m;
   double re = 0.0, im = 0.0;
   if (E <= 0.0) {
     const double sh = sqrt(h);
     const double mid = 0.5 * (qa + qb);
-    for (int panel = 0; panel < 2; ++panel) {
+    double part = 0.0;
+    for (int idx = lane; idx < 2 * g.ngl; idx += 64) {
+      const int panel = idx / g.ngl, n = idx - panel * g.ngl;
       const double a = panel ? mid : qa, b = panel ? qb : mid;
-      const double c = 0.5 * (a + b), hw = 0.5 * (b - a);
-      double s = 0.0;
-      for (int n = 0; n < g.ngl; ++n) {
-        const double q = c + hw * g.gl_x[n];
-        const double k = sqrt(b3 * q * q - E);
-        s += g.gl_w[n] * (-atan2(sh * (pb - pa) * k, k * k + h * pa * pb) / (sh * k));
-      }
-      re += hw * s;
+      const double q = 0.5 * (a + b) + 0.5 * (b - a) * g.gl_x[n];
+      const double k = sqrt(b3 * q * q - E);
+      part += 0.5 * (b - a) * g.gl_w[n] * (-atan2(sh * (pb - pa) * k, k * k + h * pa * pb) / (sh * k));
     }
+    re = wave_sum(part);
   } else {
     const double P = sqrt(E / h), Q = sqrt(E / b3);
     const double t0 = atan2(qa / Q, pb / P), t1 = atan2(qb / Q, pa / P);
@@ -532,27 +531,26 @@ __device__ double2 g1_continuum_dev(const G1Args& g, double pa, double pb, doubl
         pts[y] = pts[y - 1];
         pts[y - 1] = tmp;
       }
-    for (int sgi = 0; sgi + 1 < np; ++sgi) {
+    double part = 0.0;
+    const int total = (np - 1) * g.nts;
+    for (int idx = lane; idx < total; idx += 64) {
+      const int sgi = idx / g.nts, n = idx - sgi * g.nts;
       const double a = pts[sgi], b = pts[sgi + 1];
       if (!(b > a)) continue;
-      double s = 0.0;
-      for (int n = 0; n < g.nts; ++n) {
-        const double u = g.ts_u[n];
-        const double t = (u <= 0.5) ? a + (b - a) * u : b - (b - a) * g.ts_v[n];
-        double st, ct;
-        sincos(t, &st, &ct);
-        double rlo = 0.0;
-        if (pa > 0.0) rlo = pa / (P * ct);
-        if (qa > 0.0) rlo = fmax(rlo, qa / (Q * st));
-        const double rhi = fmin(pb / (P * ct), qb / (Q * st));
-        if (rhi > rlo) {
-          double f = -0.5 * log(fabs(1.0 - rhi * rhi)) + 0.5 * log(fabs(1.0 - rlo * rlo));
-          if (isfinite(f)) s += g.ts_w[n] * f;   // a node on the shell itself carries no weight
-        }
+      const double u = g.ts_u[n];
+      const double t = (u <= 0.5) ? a + (b - a) * u : b - (b - a) * g.ts_v[n];
+      double st, ct;
+      sincos(t, &st, &ct);
+      double rlo = 0.0;
+      if (pa > 0.0) rlo = pa / (P * ct);
+      if (qa > 0.0) rlo = fmax(rlo, qa / (Q * st));
+      const double rhi = fmin(pb / (P * ct), qb / (Q * st));
+      if (rhi > rlo) {
+        const double f = -0.5 * log(fabs(1.0 - rhi * rhi)) + 0.5 * log(fabs(1.0 - rlo * rlo));
+        if (isfinite(f)) part += 0.5 * (b - a) * g.ts_w[n] * f;   // a node on the shell carries no weight
       }
-      re += 0.5 * (b - a) * s;
     }
-    re /= sqrt(h * b3);
+    re = wave_sum(part) / sqrt(h * b3);
     const double lo_p = acos(fmin(1.0, pb / P)), hi_p = acos(fmin(1.0, pa / P));
     const double lo_q = asin(fmin(1.0, qa / Q)), hi_q = asin(fmin(1.0, qb / Q));
     im = -M_PI / (2.0 * sqrt(h * b3)) * fmax(0.0, fmin(hi_p, hi_q) - fmax(lo_p, lo_q));
@@ -570,12 +568,14 @@ __device__ double2 g1_bound_dev(double qa, double qb, double E, double eps0, dou
   return make_double2(re / (qb - qa), im / (qb - qa));
 }
 
+// One wavefront per (wave, k, j, energy) element.
 __global__ void __launch_bounds__(256) k_g1(G1Args g) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t el = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int64_t per_e = (int64_t)g.nwave * g.M * g.N;
-  if (tid >= per_e * g.nE) return;
-  const int e = (int)(tid / per_e);
-  int64_t r = tid - (int64_t)e * per_e;
+  if (el >= per_e * g.nE) return;
+  const int e = (int)(el / per_e);
+  int64_t r = el - (int64_t)e * per_e;
   const int w = (int)(r / ((int64_t)g.M * g.N));
   r -= (int64_t)w * g.M * g.N;
   const int k = (int)(r / g.N), j = (int)(r - (int64_t)k * g.N);
@@ -586,20 +586,23 @@ __global__ void __launch_bounds__(256) k_g1(G1Args g) {
     v = g1_bound_dev(g.qe[j], g.qe[j + 1], E, g.eps_b[w], g.h2m);
   } else {
     const double* bins = g.bins + (size_t)w * (g.M + 1);
-    v = g1_continuum_dev(g, bins[k - nb], bins[k - nb + 1], g.qe[j], g.qe[j + 1], E);
+    v = g1_continuum_wave(g, lane, bins[k - nb], bins[k - nb + 1], g.qe[j], g.qe[j + 1], E);
   }
-  for (int ch = 0; ch < g.nch; ++ch) {
+  // lanes share the stores: every channel of this pair wave and every column of this energy
+  const int nout = g.nch * g.nrep;
+  for (int o = lane; o < nout; o += 64) {
+    const int ch = o / g.nrep, f = o - ch * g.nrep;
     if (g.wave[ch] != w) continue;
     const size_t row = ((size_t)j * g.M + k) * g.nch + ch;
-    for (int f = 0; f < g.nrep; ++f) g.G[row * g.B + g.col0 + (size_t)e * g.nrep + f] = v;
+    g.G[row * g.B + g.col0 + (size_t)e * g.nrep + f] = v;
   }
 }
 
 hipError_t launch_g1(const G1Args& g, hipStream_t s) {
   if (g.M < 1 || g.N < 1 || g.nE < 1 || g.nwave < 1 || g.nrep < 1) return hipErrorInvalidValue;
   if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
-  hipLaunchKernelGGL(k_g1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;   // one wavefront each, four per block
+  hipLaunchKernelGGL(k_g1, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -172,4 +172,174 @@ hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ Arnoldi helpers (per column c)
+// Vectors are [rows][B] float2 (rows = D lattice entries); a basis is nv such vectors, vstride apart.
+
+#define MD_MAXV 48
+
+// part[blk][i][c] = sum over this block's rows of conj(V_i[d][c]) x[d][c], FP64 accumulation.
+// Lanes over columns c, waves over rows; one workgroup handles `rows_per_blk` rows.
+__global__ void __launch_bounds__(256) k_mdot(int64_t rows, int B, int nv, const float2* __restrict__ V, int64_t vstride,
+                                              const float2* __restrict__ x, int64_t rows_per_blk,
+                                              double2* __restrict__ part) {
+  __shared__ double2 red[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = min(rows, r0 + rows_per_blk);
+  for (int cb = 0; cb < B; cb += 64) {
+    const int c = cb + lane;
+    for (int i = 0; i < nv; ++i) {
+      double sr = 0.0, si = 0.0;
+      if (c < B) {
+        const float2* Vi = V + (size_t)i * vstride;
+        for (int64_t d = r0 + wv; d < r1; d += 4) {
+          const float2 v = Vi[d * B + c], w = x[d * B + c];
+          sr += (double)v.x * w.x + (double)v.y * w.y;
+          si += (double)v.x * w.y - (double)v.y * w.x;
+        }
+      }
+      red[wv][lane] = make_double2(sr, si);
+      __syncthreads();
+      if (wv == 0 && c < B) {
+        double2 t = red[0][lane];
+        for (int q = 1; q < 4; ++q) {
+          t.x += red[q][lane].x;
+          t.y += red[q][lane].y;
+        }
+        part[((size_t)blockIdx.x * nv + i) * B + c] = t;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// out[i][c] (+)= sum_blk part[blk][i][c]; fixed order over blocks
+__global__ void k_mdot_finish(int nblk, int B, int nv, const double2* __restrict__ part, double2* __restrict__ out,
+                              int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nv * B) return;
+  const int i = t / B, c = t - i * B;
+  double sr = 0.0, si = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double2 v = part[((size_t)b * nv + i) * B + c];
+    sr += v.x;
+    si += v.y;
+  }
+  if (accumulate) {
+    out[t].x += sr;
+    out[t].y += si;
+  } else {
+    out[t] = make_double2(sr, si);
+  }
+}
+
+hipError_t launch_mdot(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const float2* x, double2* part,
+                       int nblk, double2* out, int accumulate, hipStream_t s) {
+  if (nv < 1 || nv > MD_MAXV || B < 1 || nblk < 1) return hipErrorInvalidValue;
+  const int64_t rpb = (rows + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(256), 0, s, rows, B, nv, V, vstride, x, rpb, part);
+  hipLaunchKernelGGL(k_mdot_finish, dim3((nv * B + 255) / 256), dim3(256), 0, s, nblk, B, nv, part, out, accumulate);
+  return hipGetLastError();
+}
+
+// x[d][c] -= sum_i h[i][c] V_i[d][c]   (FP64 arithmetic, FP32 storage)
+__global__ void k_orth_update(int64_t n, int B, int nv, const float2* __restrict__ V, int64_t vstride,
+                              const double2* __restrict__ h, float2* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int c = (int)(t % B);
+  double xr = x[t].x, xi = x[t].y;
+  for (int i = 0; i < nv; ++i) {
+    const double2 hc = h[(size_t)i * B + c];
+    const float2 v = V[(size_t)i * vstride + t];
+    xr -= hc.x * v.x - hc.y * v.y;
+    xi -= hc.x * v.y + hc.y * v.x;
+  }
+  x[t] = make_float2((float)xr, (float)xi);
+}
+
+hipError_t launch_orth_update(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const double2* h, float2* x,
+                              hipStream_t s) {
+  const int64_t n = rows * B;
+  hipLaunchKernelGGL(k_orth_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nv, V, vstride, h, x);
+  return hipGetLastError();
+}
+
+// out[d][c] = x[d][c] / sqrt(nrm[c]) (nrm = squared norm from k_mdot, real part); zero if tiny.
+// Also stores the norm into hsub[c] (the subdiagonal entry of the Hessenberg matrix).
+__global__ void k_normalize(int64_t n, int B, const double2* __restrict__ nrm2, const float2* __restrict__ x,
+                            float2* __restrict__ out, double2* __restrict__ hsub) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int c = (int)(t % B);
+  const double nr = sqrt(fmax(nrm2[c].x, 0.0));
+  const double inv = nr > 1e-300 ? 1.0 / nr : 0.0;
+  out[t] = make_float2((float)(x[t].x * inv), (float)(x[t].y * inv));
+  if (t < B) hsub[t] = make_double2(sqrt(fmax(nrm2[t].x, 0.0)), 0.0);
+}
+
+hipError_t launch_normalize(int64_t rows, int B, const double2* nrm2, const float2* x, float2* out, double2* hsub,
+                            hipStream_t s) {
+  const int64_t n = rows * B;
+  hipLaunchKernelGGL(k_normalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nrm2, x, out, hsub);
+  return hipGetLastError();
+}
+
+// w = v - kv (FP32): applies (I - K) given K v
+__global__ void k_sub_f32(int64_t n, const float2* __restrict__ v, const float2* __restrict__ kv, float2* __restrict__ w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) w[t] = make_float2(v[t].x - kv[t].x, v[t].y - kv[t].y);
+}
+
+hipError_t launch_sub_f32(int64_t n, const float2* v, const float2* kv, float2* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, v, kv, w);
+  return hipGetLastError();
+}
+
+// FP64 residual -> squared norms per column (FP64)
+__global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const double2* __restrict__ x, int64_t rows_per_blk,
+                                                   double2* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = min(rows, r0 + rows_per_blk);
+  for (int cb = 0; cb < B; cb += 64) {
+    const int c = cb + lane;
+    double s2 = 0.0;
+    if (c < B)
+      for (int64_t d = r0 + wv; d < r1; d += 4) {
+        const double2 v = x[d * B + c];
+        s2 += v.x * v.x + v.y * v.y;
+      }
+    red[wv][lane] = s2;
+    __syncthreads();
+    if (wv == 0 && c < B) part[(size_t)blockIdx.x * B + c] = make_double2(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane], 0.0);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s) {
+  const int64_t rpb = (rows + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_norm2_f64, dim3(nblk), dim3(256), 0, s, rows, B, x, rpb, part);
+  hipLaunchKernelGGL(k_mdot_finish, dim3((B + 255) / 256), dim3(256), 0, s, nblk, B, 1, part, out, 0);
+  return hipGetLastError();
+}
+
+// out[d][c] = x[d][c] / sqrt(nrm2[c]) with x in FP64, out in FP32
+__global__ void k_scale_d2f(int64_t n, int B, const double2* __restrict__ nrm2, const double2* __restrict__ x,
+                            float2* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int c = (int)(t % B);
+  const double nr = sqrt(fmax(nrm2[c].x, 0.0));
+  const double inv = nr > 1e-300 ? 1.0 / nr : 0.0;
+  out[t] = make_float2((float)(x[t].x * inv), (float)(x[t].y * inv));
+}
+
+hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, hipStream_t s) {
+  const int64_t n = rows * B;
+  hipLaunchKernelGGL(k_scale_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nrm2, x, out);
+  return hipGetLastError();
+}
+
 }  // namespace wpcd

@@ -188,5 +188,16 @@ hipError_t launch_residual(int64_t n, const double2* b, const double2* y, const 
                            hipStream_t s);
 hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64_t vstride, const double2* coef,
                           double2* out, hipStream_t s);
+// Arnoldi (per column c of [rows][B] vectors): out[i][c] (+)= <V_i, x> over i < nv (FP64 sums,
+// part = scratch [nblk][nv][B]); x -= sum_i h[i][c] V_i; normalisation; w = v - Kv.
+hipError_t launch_mdot(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const float2* x, double2* part,
+                       int nblk, double2* out, int accumulate, hipStream_t s);
+hipError_t launch_orth_update(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const double2* h, float2* x,
+                              hipStream_t s);
+hipError_t launch_normalize(int64_t rows, int B, const double2* nrm2, const float2* x, float2* out, double2* hsub,
+                            hipStream_t s);
+hipError_t launch_sub_f32(int64_t n, const float2* v, const float2* kv, float2* w, hipStream_t s);
+hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s);
+hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, hipStream_t s);
 
 }  // namespace wpcd

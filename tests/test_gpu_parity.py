@@ -134,7 +134,7 @@ def test_p0_rebuild_is_bit_identical():
 def test_solve_fp64_matches_oracle(systems, name, E):
     s = systems[name]
     L = _lib_lattice(SPECS[name])
-    sol = L.solve([E], "fp64")
+    sol = L.solve([E], "fp64", allow_noconv=True)
     got = sol.amplitude(0)
     ref = pipeline.solve_energy(s, E)
     A, Ar = got["A"], ref["A"]
