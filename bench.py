@@ -37,6 +37,8 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per unit (measurement section)
 PBUILD_OPS_PER_NODE = 14          # FP64 VALU ops per (cell pair, quadrature node)
+MIXED_TOL = 1e-7                  # outer stop of the mixed path (amplitude target 1e-6)
+PADE_TOL_1E6 = 1e-7               # Pade stop of the FP64 path run to the same amplitude target
 
 
 def parse():
@@ -56,20 +58,28 @@ def batched_energies_section(wp, torch, L, reps=3):
     Es = workloads.batched_energies()
     out = {}
     amps = {}
-    for mode in ("fp64", "mixed"):
-        L.solve(Es, mode, tol=1e-12 if mode == "fp64" else 1e-9, allow_noconv=True)   # warm-up
+    for mode in ("fp64", "fp64_at_1e-6", "mixed"):
+        tol = {"fp64": 1e-12, "fp64_at_1e-6": PADE_TOL_1E6, "mixed": MIXED_TOL}[mode]
+        L.solve(Es, mode.split("_")[0], tol=tol, allow_noconv=True)   # warm-up
         torch.cuda.synchronize()
+        wp.wp_profile_reset()
+        wp.wp_profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(reps):
-            sol = L.solve(Es, mode, tol=1e-12 if mode == "fp64" else 1e-9, allow_noconv=True)
+            sol = L.solve(Es, mode.split("_")[0], tol=tol, allow_noconv=True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        wp.wp_profile_enable(False)
+        out[f"kernels_ms_per_batch_{mode}"] = {k: round(v[1] / reps, 3) for k, v in wp.wp_profile_read().items()}
+        out[f"iters_{mode}"] = int(np.max([sol.amplitude(k)["iters"][0] for k in range(len(Es))]))
         amps[mode] = np.array([sol.amplitude(k)["A"][0, 0] for k in range(len(Es))])
         out[f"solves_per_s_{mode}"] = len(Es) / dt
         out[f"ms_per_batch_{mode}"] = dt * 1e3
     out["n_energies"] = len(Es)
     out["max_abs_dA_mixed_vs_fp64"] = float(np.max(np.abs(amps["mixed"] - amps["fp64"])))
+    out["max_abs_dA_fp64_at_1e-6_vs_fp64"] = float(np.max(np.abs(amps["fp64_at_1e-6"] - amps["fp64"])))
     out["speedup_mixed_over_fp64"] = out["solves_per_s_mixed"] / out["solves_per_s_fp64"]
+    out["speedup_mixed_over_fp64_at_1e-6"] = out["solves_per_s_mixed"] / out["solves_per_s_fp64_at_1e-6"]
     return out
 
 
@@ -101,14 +111,21 @@ def sweep_section(wp, torch, V_R, sizes=(40, 100, 200, 400), reps=3):
         L.pseudostates(kind="mt", V_R=V_R)
         L.build_perm("fp64")
         torch.cuda.synchronize()
+        wp.wp_profile_reset()
+        wp.wp_profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(reps):
             st = L.build_perm("fp64")
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        wp.wp_profile_enable(False)
+        prof = wp.wp_profile_read()
         out[str(M)] = dict(P_elements=st["nnz"], candidates=st["candidates"], build_ms=dt * 1e3,
                            device_ms=st["device_ms"], P_elements_per_s=st["nnz"] / dt,
-                           fill=st["nnz"] / float(M * M) ** 2)
+                           fill=st["nnz"] / float(M * M) ** 2,
+                           kernels_ms={k: round(v[1] / reps, 4) for k, v in prof.items()},
+                           pbuild_Tops=(st["candidates"] * 64 * PBUILD_OPS_PER_NODE / (prof["pbuild"][1] / reps / 1e3) / 1e12
+                                        if "pbuild" in prof else None))
         del L
     return out
 
@@ -209,13 +226,16 @@ def main():
     elif dom == "select":
         work = N * N * nodes * M * 12 / 1.0
         roof = dict(bound="alu", achieved=work / avg_s / 1e12, peak=FP64_VALU_PEAK_TOPS, unit="Tops/s")
-    elif dom.startswith("rot64"):
-        flops = np.mean([4.0 * M * M * N * L.nch for L in lats])   # complex vector x real matrix
+    elif dom == "step64":
+        # two complex-by-real M x M products per column (j, channel): 2 x 4 M^2 flops
+        flops = np.mean([8.0 * M * M * N * L.nch for L in lats])
         roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
+    elif dom == "g1":
+        roof = dict(bound="alu", achieved=None, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
     else:   # spmv64: block values + column index + row pointer + vector in/out
         byts = np.mean([L.perm_stats["bytes"] + 2 * 16 * M * N * L.nch for L in lats])
         roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] is not None else None
     roof["kernel"] = dom
     roof["avg_us"] = avg_s * 1e6
     roof["traffic"] = None

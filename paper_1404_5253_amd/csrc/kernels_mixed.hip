@@ -178,58 +178,84 @@ hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64
 #define MD_MAXV 48
 
 // part[blk][i][c] = sum over this block's rows of conj(V_i[d][c]) x[d][c], FP64 accumulation.
-// Lanes over columns c, waves over rows; one workgroup handles `rows_per_blk` rows.
+// Lanes over columns c, waves over rows; x[d][c] is loaded once per chunk of up to 8 basis
+// vectors whose partial sums stay in registers; one LDS reduction over the waves per chunk.
 __global__ void __launch_bounds__(256) k_mdot(int64_t rows, int B, int nv, const float2* __restrict__ V, int64_t vstride,
                                               const float2* __restrict__ x, int64_t rows_per_blk,
                                               double2* __restrict__ part) {
-  __shared__ double2 red[4][64];
+  __shared__ double2 red[4][8][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = min(rows, r0 + rows_per_blk);
   for (int cb = 0; cb < B; cb += 64) {
     const int c = cb + lane;
-    for (int i = 0; i < nv; ++i) {
-      double sr = 0.0, si = 0.0;
+    for (int i0 = 0; i0 < nv; i0 += 8) {
+      const int ni = min(8, nv - i0);
+      double sr[8], si[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sr[q] = si[q] = 0.0;
       if (c < B) {
-        const float2* Vi = V + (size_t)i * vstride;
         for (int64_t d = r0 + wv; d < r1; d += 4) {
-          const float2 v = Vi[d * B + c], w = x[d * B + c];
-          sr += (double)v.x * w.x + (double)v.y * w.y;
-          si += (double)v.x * w.y - (double)v.y * w.x;
+          const float2 w = x[d * B + c];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (q < ni) {
+              const float2 v = V[(size_t)(i0 + q) * vstride + d * B + c];
+              sr[q] += (double)v.x * w.x + (double)v.y * w.y;
+              si[q] += (double)v.x * w.y - (double)v.y * w.x;
+            }
+          }
         }
       }
-      red[wv][lane] = make_double2(sr, si);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) red[wv][q][lane] = make_double2(sr[q], si[q]);
       __syncthreads();
-      if (wv == 0 && c < B) {
-        double2 t = red[0][lane];
-        for (int q = 1; q < 4; ++q) {
-          t.x += red[q][lane].x;
-          t.y += red[q][lane].y;
+      // 8 x 64 results per chunk: thread t reduces entry (q = t / 64 ... ) over the 4 waves
+      for (int e = threadIdx.x; e < 8 * 64; e += 256) {
+        const int q = e >> 6, l = e & 63;
+        const int cc = cb + l;
+        if (q < ni && cc < B) {
+          double2 t = red[0][q][l];
+          for (int w4 = 1; w4 < 4; ++w4) {
+            t.x += red[w4][q][l].x;
+            t.y += red[w4][q][l].y;
+          }
+          part[((size_t)blockIdx.x * nv + i0 + q) * B + cc] = t;
         }
-        part[((size_t)blockIdx.x * nv + i) * B + c] = t;
       }
       __syncthreads();
     }
   }
 }
 
-// out[i][c] (+)= sum_blk part[blk][i][c]; fixed order over blocks
-__global__ void k_mdot_finish(int nblk, int B, int nv, const double2* __restrict__ part, double2* __restrict__ out,
-                              int accumulate) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+// out[i][c] (+)= sum_blk part[blk][i][c]: one wavefront per output, lanes over the blocks in a
+// fixed order, then a shuffle reduction (the result does not depend on scheduling).
+__device__ __forceinline__ double wsum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_mdot_finish(int nblk, int B, int nv, const double2* __restrict__ part,
+                                                     double2* __restrict__ out, int accumulate) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (t >= nv * B) return;
   const int i = t / B, c = t - i * B;
   double sr = 0.0, si = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = lane; b < nblk; b += 64) {
     const double2 v = part[((size_t)b * nv + i) * B + c];
     sr += v.x;
     si += v.y;
   }
-  if (accumulate) {
-    out[t].x += sr;
-    out[t].y += si;
-  } else {
-    out[t] = make_double2(sr, si);
+  sr = wsum64(sr);
+  si = wsum64(si);
+  if (lane == 0) {
+    if (accumulate) {
+      out[t].x += sr;
+      out[t].y += si;
+    } else {
+      out[t] = make_double2(sr, si);
+    }
   }
 }
 
@@ -238,7 +264,7 @@ hipError_t launch_mdot(int64_t rows, int B, int nv, const float2* V, int64_t vst
   if (nv < 1 || nv > MD_MAXV || B < 1 || nblk < 1) return hipErrorInvalidValue;
   const int64_t rpb = (rows + nblk - 1) / nblk;
   hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(256), 0, s, rows, B, nv, V, vstride, x, rpb, part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3((nv * B + 255) / 256), dim3(256), 0, s, nblk, B, nv, part, out, accumulate);
+  hipLaunchKernelGGL(k_mdot_finish, dim3((nv * B + 3) / 4), dim3(256), 0, s, nblk, B, nv, part, out, accumulate);
   return hipGetLastError();
 }
 
@@ -321,7 +347,7 @@ __global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const do
 hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s) {
   const int64_t rpb = (rows + nblk - 1) / nblk;
   hipLaunchKernelGGL(k_norm2_f64, dim3(nblk), dim3(256), 0, s, rows, B, x, rpb, part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3((B + 255) / 256), dim3(256), 0, s, nblk, B, 1, part, out, 0);
+  hipLaunchKernelGGL(k_mdot_finish, dim3((B + 3) / 4), dim3(256), 0, s, nblk, B, 1, part, out, 0);
   return hipGetLastError();
 }
 
