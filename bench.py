@@ -37,8 +37,7 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic work per unit (measurement section)
 PBUILD_OPS_PER_NODE = 14          # FP64 VALU ops per (cell pair, quadrature node)
-MIXED_TOL = 1e-7                  # outer stop of the mixed path (amplitude target 1e-6)
-PADE_TOL_1E6 = 1e-7               # Pade stop of the FP64 path run to the same amplitude target
+AMP_TARGET = 1e-6                 # amplitude error at which the solve paths are compared
 
 
 def parse():
@@ -54,32 +53,46 @@ def parse():
 
 
 def batched_energies_section(wp, torch, L, reps=3):
-    """64 energies U[1, 50] MeV (seed 1234) on the resident doublet lattice: FP64 vs mixed."""
+    """64 energies U[1, 50] MeV (seed 1234) on the resident doublet lattice.
+
+    FP64 path to its rounding floor, then every path at 1e-6 amplitude error: each path's
+    tolerance (and Arnoldi cycle length) is chosen by the autotuner on a separate calibration
+    draw of 64 energies (seed 4321) against the converged FP64 amplitudes, then timed on the
+    bench energies, where the error against the converged FP64 amplitudes is reported."""
+    from paper_1404_5253_amd.tune import tune
     Es = workloads.batched_energies()
-    out = {}
+    Ecal = workloads.batched_energies(seed=4321)
+    best, _ = tune(L, Ecal, target=AMP_TARGET, sync=torch.cuda.synchronize)
+    out = {"autotuned": {k: {kk: (float(vv) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                         for k, v in best.items()}}
     amps = {}
-    for mode in ("fp64", "fp64_at_1e-6", "mixed"):
-        tol = {"fp64": 1e-12, "fp64_at_1e-6": PADE_TOL_1E6, "mixed": MIXED_TOL}[mode]
-        L.solve(Es, mode.split("_")[0], tol=tol, allow_noconv=True)   # warm-up
+    runs = [("fp64", "fp64", 1e-12, 0)] + [(f"{m}_at_1e-6", m, v["tol"], v["refine_every"]) for m, v in best.items()]
+    for label, mode, tol, cyc in runs:
+        L.solve(Es, mode, tol=tol, refine_every=cyc, allow_noconv=True)   # warm-up
         torch.cuda.synchronize()
         wp.wp_profile_reset()
         wp.wp_profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(reps):
-            sol = L.solve(Es, mode.split("_")[0], tol=tol, allow_noconv=True)
+            sol = L.solve(Es, mode, tol=tol, refine_every=cyc, allow_noconv=True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         wp.wp_profile_enable(False)
-        out[f"kernels_ms_per_batch_{mode}"] = {k: round(v[1] / reps, 3) for k, v in wp.wp_profile_read().items()}
-        out[f"iters_{mode}"] = int(np.max([sol.amplitude(k)["iters"][0] for k in range(len(Es))]))
-        amps[mode] = np.array([sol.amplitude(k)["A"][0, 0] for k in range(len(Es))])
-        out[f"solves_per_s_{mode}"] = len(Es) / dt
-        out[f"ms_per_batch_{mode}"] = dt * 1e3
+        out[f"kernels_ms_per_batch_{label}"] = {k: round(v[1] / reps, 3) for k, v in wp.wp_profile_read().items()}
+        out[f"iters_{label}"] = int(np.max([sol.amplitude(k)["iters"][0] for k in range(len(Es))]))
+        amps[label] = np.array([sol.amplitude(k)["A"][0, 0] for k in range(len(Es))])
+        out[f"solves_per_s_{label}"] = len(Es) / dt
+        out[f"ms_per_batch_{label}"] = dt * 1e3
     out["n_energies"] = len(Es)
-    out["max_abs_dA_mixed_vs_fp64"] = float(np.max(np.abs(amps["mixed"] - amps["fp64"])))
-    out["max_abs_dA_fp64_at_1e-6_vs_fp64"] = float(np.max(np.abs(amps["fp64_at_1e-6"] - amps["fp64"])))
-    out["speedup_mixed_over_fp64"] = out["solves_per_s_mixed"] / out["solves_per_s_fp64"]
-    out["speedup_mixed_over_fp64_at_1e-6"] = out["solves_per_s_mixed"] / out["solves_per_s_fp64_at_1e-6"]
+    for label in amps:
+        if label != "fp64":
+            out[f"max_abs_dA_{label}_vs_fp64"] = float(np.max(np.abs(amps[label] - amps["fp64"])))
+    fp = out.get("solves_per_s_fp64_at_1e-6")
+    mixed = [l for l in amps if l.startswith("mixed")]
+    if fp and mixed:
+        top = max(mixed, key=lambda l: out[f"solves_per_s_{l}"])
+        out["best_mixed"] = top
+        out["speedup_best_mixed_over_fp64_at_1e-6"] = out[f"solves_per_s_{top}"] / fp
     return out
 
 

@@ -163,20 +163,28 @@ wp_status perm_matrix_export(const wp_lattice* lat, int64_t* row_ptr, int32_t* c
 
 /*
  * Elastic transition operator (Sec. II.A, eq. Ueq; Sec. II.B.4, eq. m_pvg) for each E_lab:
- * G1(E) diagonal in the SWP basis (eqs. dg1a, dg1b; FP64, host), the factorised kernel
- * K = P0 (v O^T) G1 O applied by the GPU, Neumann iteration of y = b + K y with
- * b = P0 (v O^T) e0, and the on-shell series a_n = e0^T O y_n summed with Wynn's epsilon
- * algorithm in FP64. One solve per (energy, open channel), all energies of a call batched.
- *   mode WP_SOLVE_FP64:  P0 as built, blocks and vectors FP64.
- *   mode WP_SOLVE_MIXED: P0 rounded to FP32 (a second resident copy), v1/O blocks in BF16 on
- *                        MFMA with FP32 accumulation, vectors FP32; outer FP64 residual
- *                        refinement every refine_every terms (see faddeev_solve in the
- *                        library for the scheme).
- * tol: relative stop tolerance of the Pade estimates (e.g. 1e-12); accept: accepted relative
- * error estimate when the estimates reach a rounding plateau (e.g. 1e-7); max_iter: terms per
- * solve (<= 1000). Returns WP_ENOCONV (solution still returned) if any solve was not accepted.
+ * G1(E) diagonal in the SWP basis (eqs. dg1a, dg1b; FP64, on the device), the factorised kernel
+ * K = P0 (v O^T) G1 O applied by the GPU, and y = b + K y with b = P0 (v O^T) e0 solved for
+ * every (energy, open channel) column of the call at once; the amplitude is U = e0^T O y.
+ *   mode WP_SOLVE_FP64:  P0 as built, blocks and vectors FP64; Neumann iteration with the
+ *                        on-shell series a_n = e0^T O y_n summed by Wynn's epsilon algorithm
+ *                        (Pade, Sec. II.B.4). tol: relative change of the estimates at which
+ *                        they are accepted (twice in a row); accept: accepted relative error
+ *                        when the estimates reach a rounding plateau.
+ *   mode WP_SOLVE_MIXED: FP64 iterative refinement y += d with r = b - (I - K) y evaluated in
+ *                        FP64 (FP64 blocks and G1, the FP32 copy of P0 accumulated in FP64);
+ *                        each correction d from refine_every (default 8, at most 16) Arnoldi
+ *                        (GMRES) steps on (I - K~) with K~ = P0 in FP32, v1/O blocks in BF16 on
+ *                        MFMA with FP32 accumulation, G1 and vectors in FP32. tol: estimated
+ *                        relative error of U (observed contraction of the refinement times
+ *                        its last change) at which a column stops.
+ *   mode WP_SOLVE_MIXED_SPLIT: as WP_SOLVE_MIXED with every BF16 operand carried as a hi + lo
+ *                        pair (three MFMA products per tile, ~16 significant bits), so that
+ *                        one correction gains about as much as the FP32 data allow.
+ * max_iter: operator applications per solve (<= 1000). Returns WP_ENOCONV (solution still
+ * returned) if any solve was not accepted.
  */
-enum { WP_SOLVE_FP64 = 0, WP_SOLVE_MIXED = 1 };
+enum { WP_SOLVE_FP64 = 0, WP_SOLVE_MIXED = 1, WP_SOLVE_MIXED_SPLIT = 2 };
 typedef struct {
   int mode;
   double tol;

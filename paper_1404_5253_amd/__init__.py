@@ -26,7 +26,8 @@ C = C   # ctypes, re-exported for callers that pass raw stream handles
 
 WP_OK, WP_EINVAL, WP_ENOMEM, WP_EDEVICE, WP_ENOTREADY, WP_ENOCONV, WP_EBUDGET, WP_EINTERNAL = range(8)
 WP_P_FP64, WP_P_FP32 = 0, 1
-WP_SOLVE_FP64, WP_SOLVE_MIXED = 0, 1
+WP_SOLVE_FP64, WP_SOLVE_MIXED, WP_SOLVE_MIXED_SPLIT = 0, 1, 2
+SOLVE_MODES = {"fp64": WP_SOLVE_FP64, "mixed": WP_SOLVE_MIXED, "mixed_split": WP_SOLVE_MIXED_SPLIT}
 H2M = 41.471
 
 
@@ -308,7 +309,7 @@ class Lattice:
 
     def solve(self, E_lab, mode="fp64", tol=1e-12, accept=1e-7, max_iter=200, refine_every=0, stream=None,
               allow_noconv=False):
-        m = {"fp64": WP_SOLVE_FP64, "mixed": WP_SOLVE_MIXED}[mode]
+        m = SOLVE_MODES[mode]
         E = np.atleast_1d(E_lab)
         h, ok = faddeev_solve(self.h, E, m, tol, accept, max_iter, refine_every,
                               stream if stream is not None else current_stream(), allow_noconv)

@@ -20,6 +20,7 @@ struct wp_batch {
   DBuf<double2> dG, dy, dt, ds, dacap;
   DBuf<int> dj0, dg0, dfin;
   DBuf<double> dE;   // three-body energy of each slot
+  DBuf<int64_t> g1w;  // G1 work list for one energy
   std::vector<int> j0, g0;
   struct Slot {
     bool live = false, done = false;
@@ -54,7 +55,7 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   DevAlloc* al = &L->al;
   if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
       !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
-      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin) || !b->dE.make(al, cap))
+      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin) || !b->dE.make(al, cap) || !g1_work(L, 1, b->g1w))
     return fail(WP_ENOMEM, "device allocation (batch)");
   for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
   b->j0.assign(B, 0);
@@ -95,7 +96,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   const int nf = b->nfin, c0 = sl * nf;
   hipStream_t st = nullptr;
   HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
-  WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, b->B, b->dG.p), st));
+  WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, b->B, b->dG.p, b->g1w), st));
   for (int f = 0; f < nf; ++f) b->j0[c0 + f] = S.r.j0;
   HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
   HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, b->B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,

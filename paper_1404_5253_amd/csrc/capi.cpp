@@ -420,13 +420,14 @@ wp_status wpcd::upload_waves(wp_lattice* L) {
     double ch = std::cosh(sarg);
     tw.push_back(hts * 0.5 * M_PI * std::cosh(t) / (ch * ch));
   }
-  std::vector<double> glx(20), glw(20);
+  std::vector<double> glx(36), glw(36);   // 20-point rule, then the 16-point rule
   gauss_legendre(20, glx.data(), glw.data());
+  gauss_legendre(16, glx.data() + 20, glw.data() + 20);
   L->nts = (int)tu.size();
   L->ngl = 20;
   if (!L->d_bins.make(&L->al, bins.size()) || !L->d_epsb.make(&L->al, nw) || !L->d_nb.make(&L->al, nw) ||
       !L->d_ts_u.make(&L->al, tu.size()) || !L->d_ts_v.make(&L->al, tv.size()) || !L->d_ts_w.make(&L->al, tw.size()) ||
-      !L->d_gl_x.make(&L->al, 20) || !L->d_gl_w.make(&L->al, 20))
+      !L->d_gl_x.make(&L->al, 36) || !L->d_gl_w.make(&L->al, 36))
     return fail(WP_ENOMEM, "device allocation (G1 tables)");
   HIPCHECK(hipMemcpy(L->d_bins.p, bins.data(), bins.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_epsb.p, epsb.data(), nw * 8, hipMemcpyHostToDevice));
@@ -434,12 +435,17 @@ wp_status wpcd::upload_waves(wp_lattice* L) {
   HIPCHECK(hipMemcpy(L->d_ts_u.p, tu.data(), tu.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_ts_v.p, tv.data(), tv.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_ts_w.p, tw.data(), tw.size() * 8, hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(L->d_gl_x.p, glx.data(), 20 * 8, hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(L->d_gl_w.p, glw.data(), 20 * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gl_x.p, glx.data(), 36 * 8, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(L->d_gl_w.p, glw.data(), 36 * 8, hipMemcpyHostToDevice));
   return WP_OK;
 }
 
-G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G) {
+bool wpcd::g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w) {
+  return w.make(&L->al, (size_t)g1_work_elems((int)L->waves.size(), L->M, L->N, nE) + 1);
+}
+
+G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G,
+                     DBuf<int64_t>& work) {
   G1Args g{};
   g.M = L->M;
   g.N = L->N;
@@ -462,8 +468,12 @@ G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, in
   g.gl_x = L->d_gl_x.p;
   g.gl_w = L->d_gl_w.p;
   g.ngl = L->ngl;
+  g.gl16_x = L->d_gl_x.p + 20;
+  g.gl16_w = L->d_gl_w.p + 20;
   g.h2m = L->h2m;
   g.G = G;
+  g.wl_n = reinterpret_cast<int*>(work.p);
+  g.wl = work.p ? work.p + 1 : nullptr;
   return g;
 }
 
@@ -492,10 +502,12 @@ extern "C" wp_status wp_lattice_resolvent(const wp_lattice* Lc, double E_lab, in
   const int64_t rows = (int64_t)L->M * L->N * L->nch;
   DBuf<double2> dG;
   DBuf<double> dE;
-  if (!dG.make(&L->al, rows) || !dE.make(&L->al, 1)) return fail(WP_ENOMEM, "device allocation (resolvent)");
+  DBuf<int64_t> g1w;
+  if (!dG.make(&L->al, rows) || !dE.make(&L->al, 1) || !g1_work(L, 1, g1w))
+    return fail(WP_ENOMEM, "device allocation (resolvent)");
   const double E = L->eps0 + 2.0 * E_lab / 3.0;
   HIPCHECK(hipMemcpy(dE.p, &E, 8, hipMemcpyHostToDevice));
-  WP_LAUNCH("g1", nullptr, launch_g1(g1_args(L, dE.p, 1, 1, 0, 1, dG.p), nullptr));
+  WP_LAUNCH("g1", nullptr, launch_g1(g1_args(L, dE.p, 1, 1, 0, 1, dG.p, g1w), nullptr));
   std::vector<double2> h(rows);
   HIPCHECK(hipMemcpy(h.data(), dG.p, rows * sizeof(double2), hipMemcpyDeviceToHost));
   for (int k = 0; k < L->M; ++k)
@@ -670,12 +682,14 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   DBuf<double2> dG, dy, dt, ds, dacap;
   DBuf<int> dj0, dg0, dfin;
   DBuf<double> dE;
+  DBuf<int64_t> g1w;
+  if (!g1_work(L, nE, g1w)) return fail(WP_ENOMEM, "device allocation (G1 work list)");
   if (!dG.make(&L->al, D * B) || !dy.make(&L->al, D * B) || !dt.make(&L->al, D * B) || !ds.make(&L->al, D * B) ||
       !dacap.make(&L->al, (size_t)(max_iter + chunk) * B * nfin) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
       !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
-  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p), s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p, g1w), s));
   HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
@@ -750,19 +764,32 @@ wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
   if (wp_status st = upload_waves(L)) return st;
   const int M = L->M;
   if (!L->d_Ob.p) {
+    // bf16 copies of O and v O^T (hi) and of their rounding remainders (lo), padded to Mp
     const int Mp = (M + 15) / 16 * 16;
     const size_t MM = (size_t)Mp * Mp;
-    std::vector<uint16_t> Ob(MM * L->waves.size(), 0), Wb(MM * L->waves.size(), 0);
+    const size_t n = MM * L->waves.size();
+    std::vector<uint16_t> Oh(n, 0), Ol(n, 0), Wh(n, 0), Wl(n, 0);
+    auto split = [](double d, uint16_t& hi, uint16_t& lo) {
+      hi = host_bf16(d);
+      uint32_t u = (uint32_t)hi << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      lo = host_bf16((double)((float)d - f));
+    };
     for (size_t w = 0; w < L->waves.size(); ++w)
       for (int r = 0; r < M; ++r)
         for (int c = 0; c < M; ++c) {
-          Ob[w * MM + (size_t)r * Mp + c] = host_bf16(L->waves[w].O[(size_t)r * M + c]);
-          Wb[w * MM + (size_t)r * Mp + c] = host_bf16(L->waves[w].W[(size_t)r * M + c]);
+          const size_t k = w * MM + (size_t)r * Mp + c;
+          split(L->waves[w].O[(size_t)r * M + c], Oh[k], Ol[k]);
+          split(L->waves[w].W[(size_t)r * M + c], Wh[k], Wl[k]);
         }
-    if (!L->d_Ob.make(&L->al, Ob.size()) || !L->d_Wb.make(&L->al, Wb.size()))
+    if (!L->d_Ob.make(&L->al, n) || !L->d_Wb.make(&L->al, n) || !L->d_Ob_lo.make(&L->al, n) ||
+        !L->d_Wb_lo.make(&L->al, n))
       return fail(WP_ENOMEM, "device allocation (bf16 blocks)");
-    HIPCHECK(hipMemcpy(L->d_Ob.p, Ob.data(), Ob.size() * 2, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L->d_Wb.p, Wb.data(), Wb.size() * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Ob.p, Oh.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Wb.p, Wh.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Ob_lo.p, Ol.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Wb_lo.p, Wl.data(), n * 2, hipMemcpyHostToDevice));
     L->Mp = Mp;
   }
   if (!L->d_val32.p) {
@@ -803,19 +830,18 @@ static std::vector<cplx> hessenberg_ls(std::vector<cplx> H, int m, double beta) 
 }
 
 // Mixed path: iterative refinement in FP64 around a mixed-precision GMRES.
-//   outer (FP64): r = b - (I - K) y with FP64 blocks and G1, the FP32-stored P0 accumulated in
-//                 FP64; the same launch yields U_0 = e0^T O y exactly;
-//   inner:        m Arnoldi steps on (I - K~) with K~ = P0(FP32) (v O^T)(BF16, MFMA) G1(FP32)
-//                 O(BF16, MFMA), FP32 basis vectors, classical Gram-Schmidt with FP64 sums; the
-//                 small least-squares problem per energy on the host (FP64);
-//                 y += V z.
-// Stop when U_0 changes by <= tol |U_0| between two outer steps. A Neumann series in low precision
-// would amplify every term's rounding by the growth of the divergent series, which is why the
-// inner solver is orthogonalised.
-// Gram-Schmidt passes per Arnoldi step: one pass suffices here because the outer FP64 refinement
-// absorbs the inner solver's loss of orthogonality (GPU test: mixed vs FP64 to 1e-6 and better).
-constexpr int kCGSPasses = 1;
-
+//   outer (FP64): r = b - (I - K) y with FP64 blocks and G1 and the FP32-stored P0 accumulated
+//                 in FP64 (r = b at y = 0);
+//   inner:        m Arnoldi steps on (I - K~) started from r / |r|, K~ = P0(FP32) (v O^T)(BF16,
+//                 MFMA) G1(FP32) O(BF16, MFMA); FP32 basis vectors kept unnormalised with FP64
+//                 scale factors, classical Gram-Schmidt with FP64 sums (one pass: the outer
+//                 refinement absorbs the inner loss of orthogonality); the small least-squares
+//                 problem per column on the host in FP64; y += V z;
+//   stop:         U = e0^T O y in FP64 after every correction; with D_k the relative change of U
+//                 and rho = D_k / D_{k-1} the observed contraction, the error estimate is
+//                 D_k rho / (1 - rho); a column stops when it is <= tol.
+// A Neumann series in low precision would amplify every term's rounding by the growth of the
+// divergent series, which is why the inner solver is orthogonalised.
 static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                              wp_solution* sol) {
   const int M = L->M, N = L->N, nch = L->nch;
@@ -825,6 +851,7 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
   const int64_t D = (int64_t)M * N * nch;
   const int64_t R = (int64_t)M * N;
   const int64_t DB = D * B;
+  const bool split = o.mode == WP_SOLVE_MIXED_SPLIT;
   std::vector<int> j0(B), g0(B);
   std::vector<double> Etot(nE);
   sol->res.resize(nE);
@@ -838,91 +865,67 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
     }
   }
   if (wp_status st = ensure_mixed(L, s)) return st;
-  const int m = std::max(4, std::min(40, o.refine_every > 0 ? o.refine_every : 12));
-  const int max_outer = std::max(2, std::min(30, o.max_iter / m + 2));
-  const int nblk = 256;
-  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dacap64, dcoef, H1, H2, part, nrm;
-  DBuf<float2> dG32, V, w32, kv32, t32;
+  const int m = std::max(2, std::min(ARN_NV, o.refine_every > 0 ? o.refine_every : 8));
+  const int max_outer = std::max(2, std::min(100, o.max_iter / (m + 1)));
+  const int nblk = 512;
+  const bool fused = B >= 16 && nch <= 4;
+  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dcap, dcoef, H, part, nrm;
+  DBuf<float2> dG32, V, t32, kv32;
+  DBuf<double> scl;
   DBuf<int> dj0, dg0, dfin;
   DBuf<double> dE;
+  DBuf<int64_t> g1w;
   if (!dG64.make(&L->al, DB) || !db.make(&L->al, DB) || !dy.make(&L->al, DB) || !dr.make(&L->al, DB) ||
-      !dKy.make(&L->al, DB) || !ds64.make(&L->al, DB) || !dacap64.make(&L->al, (size_t)B * nfin) ||
-      !dcoef.make(&L->al, (size_t)(m + 1) * B) || !H1.make(&L->al, (size_t)m * (m + 1) * B) ||
-      !H2.make(&L->al, (size_t)m * (m + 1) * B) || !part.make(&L->al, (size_t)nblk * (m + 1) * B) ||
-      !nrm.make(&L->al, B) || !dG32.make(&L->al, DB) || !V.make(&L->al, (size_t)(m + 1) * DB) ||
-      !w32.make(&L->al, DB) || !kv32.make(&L->al, DB) || !t32.make(&L->al, DB) || !dj0.make(&L->al, B) ||
-      !dg0.make(&L->al, B) || !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
+      !dKy.make(&L->al, DB) || !ds64.make(&L->al, DB) || !dcap.make(&L->al, (size_t)B * nfin) ||
+      !dcoef.make(&L->al, (size_t)(m + 1) * B) || !H.make(&L->al, (size_t)m * (m + 1) * B) ||
+      !part.make(&L->al, (size_t)nblk * ARN_NV * B) || !nrm.make(&L->al, B) || !dG32.make(&L->al, DB) ||
+      !V.make(&L->al, (size_t)(m + 1) * DB) || !t32.make(&L->al, DB) || (!fused && !kv32.make(&L->al, DB)) ||
+      !scl.make(&L->al, (size_t)(m + 1) * B) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
+      !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE) || !g1_work(L, nE, g1w))
     return fail(WP_ENOMEM, "device allocation (mixed solve)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
-  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG64.p), s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG64.p, g1w), s));
   HIPCHECK(launch_cvt_d2f(DB, dG64.p, dG32.p, s));
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds64.p, s));
   WP_LAUNCH("spmv_f32v_f64x", s,
             launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s));
   HIPCHECK(launch_fill0(dy.p, DB, s));
-  std::vector<cplx> U((size_t)B * nfin, cplx(0, 0)), Uprev((size_t)B * nfin, cplx(0, 0));
-  std::vector<double> err(B, 1.0);
+  ArnoldiArgs aa{R, nch, B, m, 0, L->d_rowptr.p, L->d_col.p, L->d_val32.p, V.p, DB, scl.p, H.p, part.p, nblk};
+  RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p, split ? L->d_Wb_lo.p : nullptr,
+                  L->Mp, L->d_wave.p, dG32.p, nullptr};
+  std::vector<cplx> Uprev((size_t)B * nfin, cplx(0, 0)), Ubest((size_t)B * nfin, cplx(0, 0));
+  std::vector<double> err(B, 1.0), dprev(B, -1.0);
   std::vector<int> iters(B, 0);
   std::vector<bool> done(B, false);
-  std::vector<double2> hc((size_t)B * nfin), h1((size_t)m * (m + 1) * B), h2((size_t)m * (m + 1) * B), hn(B);
+  std::vector<double2> hc((size_t)B * nfin), hH((size_t)m * (m + 1) * B), hn(B);
+  std::vector<double> hsc((size_t)(m + 1) * B);
   std::vector<double2> coef((size_t)(m + 1) * B);
-  const double tol = std::max(o.tol, 1e-14);
-  for (int outer = 0; outer <= max_outer; ++outer) {
-    // FP64 residual and the exact e0^T O y of the current y
-    RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, dacap64.p, dj0.p, dfin.p, nfin, 0};
-    WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
-    WP_LAUNCH("spmv_f32v_f64x", s,
-              launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
-    WP_LAUNCH("residual", s, launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
-    HIPCHECK(hipMemcpyAsync(hc.data(), dacap64.p, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  const double tol = std::max(o.tol, 1e-15);
+  for (int outer = 0; outer < max_outer; ++outer) {
+    if (outer == 0) {
+      HIPCHECK(hipMemcpyAsync(dr.p, db.p, DB * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    } else {
+      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, nullptr, dj0.p, dfin.p, nfin, 0};
+      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
+      WP_LAUNCH("spmv_f32v_f64x", s,
+                launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
+      WP_LAUNCH("residual", s, launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
+    }
     HIPCHECK(launch_norm2_f64(D, B, dr.p, part.p, nblk, nrm.p, s));
+    HIPCHECK(launch_scale_d2f(D, B, nrm.p, dr.p, V.p, scl.p, s));
     HIPCHECK(hipMemcpyAsync(hn.data(), nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    bool all = true;
-    for (int c = 0; c < B; ++c) {
-      if (done[c]) continue;
-      double change = 0.0, mag = 0.0;
-      for (int f = 0; f < nfin; ++f) {
-        cplx u(hc[(size_t)c * nfin + f].x, hc[(size_t)c * nfin + f].y);
-        U[(size_t)c * nfin + f] = u;
-        change = std::max(change, std::abs(u - Uprev[(size_t)c * nfin + f]));
-        mag = std::max(mag, std::abs(u));
-        Uprev[(size_t)c * nfin + f] = u;
-      }
-      if (outer > 0) {
-        err[c] = change / std::max(mag, 1e-300);
-        if (err[c] <= tol) done[c] = true;
-      }
-      all &= done[c];
-    }
-    if (all || outer == max_outer) break;
-    // inner: m Arnoldi steps on (I - K~) started from r / |r|
-    HIPCHECK(launch_scale_d2f(D, B, nrm.p, dr.p, V.p, s));
     for (int j = 0; j < m; ++j) {
-      float2* Vj = V.p + (size_t)j * DB;
-      RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, L->Mp, L->d_wave.p, dG32.p, nullptr, dj0.p, dfin.p, nfin, 0};
-      WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, L->d_Wb.p, Vj, t32.p, s));
-      WP_LAUNCH("spmv32", s, launch_spmv_f32(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, t32.p, kv32.p, s));
-      WP_LAUNCH("sub_f32", s, launch_sub_f32(DB, Vj, kv32.p, w32.p, s));
-      double2* h1j = H1.p + (size_t)j * (m + 1) * B;
-      double2* h2j = H2.p + (size_t)j * (m + 1) * B;
-      WP_LAUNCH("arnoldi", s, launch_mdot(D, B, j + 1, V.p, DB, w32.p, part.p, nblk, h1j, 0, s));
-      WP_LAUNCH("orth_update", s, launch_orth_update(D, B, j + 1, V.p, DB, h1j, w32.p, s));
-      if (kCGSPasses > 1) {
-        WP_LAUNCH("arnoldi", s, launch_mdot(D, B, j + 1, V.p, DB, w32.p, part.p, nblk, h2j, 0, s));
-        WP_LAUNCH("orth_update", s, launch_orth_update(D, B, j + 1, V.p, DB, h2j, w32.p, s));
-      } else {
-        HIPCHECK(launch_fill0(h2j, (int64_t)(j + 1) * B, s));
-      }
-      WP_LAUNCH("arnoldi", s, launch_mdot(D, B, 1, w32.p, DB, w32.p, part.p, nblk, nrm.p, 0, s));
-      WP_LAUNCH("normalize", s, launch_normalize(D, B, nrm.p, w32.p, V.p + (size_t)(j + 1) * DB, h1j + (size_t)(j + 1) * B, s));
-      HIPCHECK(launch_fill0(h2j + (size_t)(j + 1) * B, B, s));
+      aa.j = j;
+      rm.yscale = scl.p + (size_t)j * B;
+      WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, V.p + (size_t)j * DB, t32.p, s));
+      WP_LAUNCH("arnoldi_product", s, launch_arnoldi_product(aa, t32.p, kv32.p, s));
+      WP_LAUNCH("arnoldi_orth", s, launch_arnoldi_orth(aa, s));
     }
-    HIPCHECK(hipMemcpyAsync(h1.data(), H1.p, h1.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(h2.data(), H2.p, h2.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hH.data(), H.p, hH.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hsc.data(), scl.p, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     std::fill(coef.begin(), coef.end(), make_double2(0.0, 0.0));
     for (int c = 0; c < B; ++c) {
@@ -930,24 +933,54 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
       std::vector<cplx> Hc((size_t)m * (m + 1));
       for (int j = 0; j < m; ++j)
         for (int i = 0; i <= m; ++i) {
-          const size_t idx = ((size_t)j * (m + 1) + i) * B + c;
-          Hc[(size_t)j * (m + 1) + i] = cplx(h1[idx].x + h2[idx].x, h1[idx].y + h2[idx].y);
+          const double2 v = hH[((size_t)j * (m + 1) + i) * B + c];
+          Hc[(size_t)j * (m + 1) + i] = cplx(v.x, v.y);
         }
       const double beta = std::sqrt(std::max(hn[c].x, 0.0));
       std::vector<cplx> z = hessenberg_ls(Hc, m, beta);
-      for (int i = 0; i < m; ++i) coef[(size_t)i * B + c] = make_double2(z[i].real(), z[i].imag());
-      iters[c] += m;
+      for (int i = 0; i < m; ++i) {
+        const cplx w = z[i] * hsc[(size_t)i * B + c];   // V_i = scl_i Vt_i
+        coef[(size_t)i * B + c] = make_double2(w.real(), w.imag());
+      }
+      iters[c] += m + (outer > 0 ? 1 : 0);
     }
     HIPCHECK(hipMemcpyAsync(dcoef.p, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
     WP_LAUNCH("lincomb", s, launch_lincomb(D, B, m, V.p, DB, dcoef.p, dy.p, s));
+    WP_LAUNCH("capture", s, launch_capture64(M, nch, B, nfin, L->d_O.p, L->d_wave.p, dj0.p, dfin.p, dy.p, dcap.p, s));
+    HIPCHECK(hipMemcpyAsync(hc.data(), dcap.p, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int c = 0; c < B; ++c) {
+      if (done[c]) continue;
+      double change = 0.0, mag = 0.0;
+      for (int f = 0; f < nfin; ++f) {
+        const size_t k = (size_t)c * nfin + f;
+        const cplx u(hc[k].x, hc[k].y);
+        change = std::max(change, std::abs(u - Uprev[k]));
+        mag = std::max(mag, std::abs(u));
+        Uprev[k] = u;
+        Ubest[k] = u;
+      }
+      const double d = change / std::max(mag, 1e-300);
+      double est = 1.0;
+      if (dprev[c] >= 0.0) {
+        const double rho = dprev[c] > 0.0 ? d / dprev[c] : 0.0;
+        est = rho < 1.0 ? d * std::min(rho / (1.0 - rho), 1e6) : d * 1e6;
+      }
+      if (d == 0.0 && dprev[c] >= 0.0) est = 0.0;
+      err[c] = std::min(est, 1.0);
+      dprev[c] = d;
+      if (err[c] <= tol) done[c] = true;
+      all &= done[c];
+    }
+    if (all) break;
   }
-  HIPCHECK(hipStreamSynchronize(s));
   bool allok = true;
   for (int e = 0; e < nE; ++e) {
     EnergyResult& r = sol->res[e];
     for (int b = 0; b < nfin; ++b) {
       const int c = e * nfin + b;
-      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = U[(size_t)c * nfin + f];
+      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = Ubest[(size_t)c * nfin + f];
       r.err[b] = err[c];
       r.iters[b] = iters[c];
       r.ok &= err[c] <= o.accept;
@@ -973,7 +1006,7 @@ extern "C" wp_status faddeev_solve(wp_lattice* L, int n_E, const double* E_lab, 
   try {
     if (opts->mode == WP_SOLVE_FP64)
       st = solve_fp64(L, E, *opts, (hipStream_t)stream, sol.get());
-    else if (opts->mode == WP_SOLVE_MIXED)
+    else if (opts->mode == WP_SOLVE_MIXED || opts->mode == WP_SOLVE_MIXED_SPLIT)
       st = solve_mixed(L, E, *opts, (hipStream_t)stream, sol.get());
     else
       return fail(WP_EINVAL, "unknown solve mode");

@@ -19,6 +19,8 @@
 //              over blocks, or over channel rows for large blocks).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "wpcd_internal.h"
 
 namespace wpcd {
@@ -568,41 +570,151 @@ __device__ double2 g1_bound_dev(double qa, double qb, double E, double eps0, dou
   return make_double2(re / (qb - qa), im / (qb - qa));
 }
 
-// One wavefront per (wave, k, j, energy) element.
-__global__ void __launch_bounds__(256) k_g1(G1Args g) {
-  const int64_t el = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int64_t per_e = (int64_t)g.nwave * g.M * g.N;
-  if (el >= per_e * g.nE) return;
-  const int e = (int)(el / per_e);
-  int64_t r = el - (int64_t)e * per_e;
-  const int w = (int)(r / ((int64_t)g.M * g.N));
-  r -= (int64_t)w * g.M * g.N;
-  const int k = (int)(r / g.N), j = (int)(r - (int64_t)k * g.N);
-  const double E = g.E[e];
-  const int nb = g.nb[w];
-  double2 v;
-  if (k < nb) {
-    v = g1_bound_dev(g.qe[j], g.qe[j + 1], E, g.eps_b[w], g.h2m);
-  } else {
-    const double* bins = g.bins + (size_t)w * (g.M + 1);
-    v = g1_continuum_wave(g, lane, bins[k - nb], bins[k - nb + 1], g.qe[j], g.qe[j + 1], E);
-  }
-  // lanes share the stores: every channel of this pair wave and every column of this energy
+// Element index el = ((w * M + k) * N + j) * nE + e: consecutive lanes take consecutive energies
+// of one (w, k, j), so the stores of a wavefront are contiguous in the column index.
+struct G1Elem {
+  int e, w, k, j;
+};
+__device__ __forceinline__ G1Elem g1_decode(const G1Args& g, int64_t el) {
+  G1Elem d;
+  d.e = (int)(el % g.nE);
+  int64_t r = el / g.nE;
+  d.j = (int)(r % g.N);
+  r /= g.N;
+  d.k = (int)(r % g.M);
+  d.w = (int)(r / g.M);
+  return d;
+}
+
+__device__ __forceinline__ void g1_store(const G1Args& g, const G1Elem& d, double2 v, int lane0, int stride) {
   const int nout = g.nch * g.nrep;
-  for (int o = lane; o < nout; o += 64) {
+  for (int o = lane0; o < nout; o += stride) {
     const int ch = o / g.nrep, f = o - ch * g.nrep;
-    if (g.wave[ch] != w) continue;
-    const size_t row = ((size_t)j * g.M + k) * g.nch + ch;
-    g.G[row * g.B + g.col0 + (size_t)e * g.nrep + f] = v;
+    if (g.wave[ch] != d.w) continue;
+    const size_t row = ((size_t)d.j * g.M + d.k) * g.nch + ch;
+    g.G[row * g.B + g.col0 + (size_t)d.e * g.nrep + f] = v;
   }
 }
 
+// p integral of eq. dg1b in closed form for fixed q, kappa^2 = E - b3 q^2:
+//   int_{pa}^{pb} dp / (kappa^2 - h p^2)
+//   = atanh(sqrt(h) kappa dp / (kappa^2 - h pa pb)) / (sqrt(h) kappa)      kappa^2 > 0,
+//   = -atan2(sqrt(h) dp k, k^2 + h pa pb) / (sqrt(h) k),  k^2 = -kappa^2    kappa^2 < 0,
+// valid when kappa^2 is not in [h pa^2, h pb^2] (the pole is outside the p bin).
+__device__ __forceinline__ double g1_pint(double k2, double pa, double pb, double sh) {
+  const double dp = pb - pa, pp = sh * sh * pa * pb;
+  if (k2 > 0.0) {
+    const double c = sqrt(k2);
+    return atanh(sh * c * dp / (k2 - pp)) / (sh * c);
+  }
+  if (k2 < 0.0) {
+    const double k = sqrt(-k2);
+    return -atan2(sh * dp * k, -k2 + pp) / (sh * k);
+  }
+  return -dp / pp;
+}
+
+// Lane rule for a continuum element whose box the energy shell does not cross. After the
+// closed-form p integral the q integrand is analytic except on the set where kappa^2 reaches
+// [h pa^2, h pb^2]; with q_s its point nearest to the q bin, the 16-point Gauss-Legendre rule is
+// exact to rounding when the Bernstein ellipse parameter rho(q_s) of the bin is at least 3
+// (error ~ rho^-32). Returns false (element left to the wavefront rule) otherwise.
+__device__ bool g1_continuum_lane(const G1Args& g, double pa, double pb, double qa, double qb, double E,
+                                  double2* out) {
+  const double h = g.h2m, b3 = 0.75 * g.h2m;
+  const double L2 = (E - h * pb * pb) / b3, U2 = (E - h * pa * pa) / b3;   // singular set in q^2
+  double xr, xi;                                                           // q_s mapped to [-1, 1]
+  const double mid = 0.5 * (qa + qb), half = 0.5 * (qb - qa);
+  if (U2 <= 0.0) {
+    xr = -mid / half;
+    xi = sqrt(-U2) / half;
+  } else if (sqrt(U2) < qa) {
+    xr = (sqrt(U2) - mid) / half;
+    xi = 0.0;
+  } else if (L2 > 0.0 && sqrt(L2) > qb) {
+    xr = (sqrt(L2) - mid) / half;
+    xi = 0.0;
+  } else {
+    return false;
+  }
+  // rho = |x + sqrt(x^2 - 1)| on the branch with modulus > 1
+  const double ar = xr * xr - xi * xi - 1.0, ai = 2.0 * xr * xi;
+  const double mod = sqrt(sqrt(ar * ar + ai * ai));
+  const double ang = 0.5 * atan2(ai, ar);
+  const double sr = mod * cos(ang), si = mod * sin(ang);
+  const double r1 = hypot(xr + sr, xi + si), r2 = hypot(xr - sr, xi - si);
+  if (fmax(r1, r2) < 3.0) return false;
+  const double sh = sqrt(h);
+  double acc = 0.0;
+  for (int n = 0; n < 16; ++n) {
+    const double q = mid + half * g.gl16_x[n];
+    acc += g.gl16_w[n] * g1_pint(E - b3 * q * q, pa, pb, sh);
+  }
+  const double d = (pb - pa) * (qb - qa);
+  *out = make_double2(acc * half / d, 0.0);   // no shell point inside: real
+  return true;
+}
+
+// One lane per element: bound-continuum elements and the continuum elements the lane rule
+// accepts are written; the others are appended to a work list for k_g1_wave.
+__global__ void __launch_bounds__(256) k_g1_lane(G1Args g) {
+  const int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
+  bool defer = false;
+  if (el < n) {
+    const G1Elem d = g1_decode(g, el);
+    const double E = g.E[d.e];
+    const int nb = g.nb[d.w];
+    double2 v;
+    bool ok = true;
+    if (d.k < nb) {
+      v = g1_bound_dev(g.qe[d.j], g.qe[d.j + 1], E, g.eps_b[d.w], g.h2m);
+    } else {
+      const double* bins = g.bins + (size_t)d.w * (g.M + 1);
+      ok = g1_continuum_lane(g, bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1], E, &v);
+    }
+    if (ok) g1_store(g, d, v, 0, 1);
+    defer = !ok;
+  }
+  const unsigned long long mask = __ballot(defer);
+  if (mask) {
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(g.wl_n, __popcll(mask));
+    base = __shfl(base, leader, WARP);
+    if (defer) g.wl[base + __popcll(mask & ((1ull << lane) - 1ull))] = el;
+  }
+}
+
+// One wavefront per deferred element (the boxes the energy shell crosses or passes close to).
+__global__ void __launch_bounds__(256) k_g1_wave(G1Args g) {
+  const int lane = threadIdx.x & 63;
+  const int cnt = *g.wl_n;
+  for (int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); idx < cnt; idx += (int64_t)gridDim.x * 4) {
+    const G1Elem d = g1_decode(g, g.wl[idx]);
+    const double* bins = g.bins + (size_t)d.w * (g.M + 1);
+    const int nb = g.nb[d.w];
+    const double2 v = g1_continuum_wave(g, lane, bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1],
+                                        g.E[d.e]);
+    g1_store(g, d, v, lane, 64);
+  }
+}
+
+__global__ void k_zero_i32(int* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
+int64_t g1_work_elems(int nwave, int M, int N, int nE) { return (int64_t)nwave * M * N * nE; }
+
 hipError_t launch_g1(const G1Args& g, hipStream_t s) {
-  if (g.M < 1 || g.N < 1 || g.nE < 1 || g.nwave < 1 || g.nrep < 1) return hipErrorInvalidValue;
+  if (g.M < 1 || g.N < 1 || g.nE < 1 || g.nwave < 1 || g.nrep < 1 || !g.wl || !g.wl_n) return hipErrorInvalidValue;
   if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;   // one wavefront each, four per block
-  hipLaunchKernelGGL(k_g1, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, g);
+  const int64_t n = g1_work_elems(g.nwave, g.M, g.N, g.nE);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, g.wl_n);
+  hipLaunchKernelGGL(k_g1_lane, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  const int64_t wblocks = std::min<int64_t>(2048, std::max<int64_t>(1, (n + 3) / 4));
+  hipLaunchKernelGGL(k_g1_wave, dim3((unsigned)wblocks), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

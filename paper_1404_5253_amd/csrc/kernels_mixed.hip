@@ -2,6 +2,8 @@
 // accumulation) and the FP64 helpers of the residual refinement.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "wpcd_internal.h"
 
 namespace wpcd {
@@ -16,29 +18,40 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// One channel g (pair wave w) and 8 complex columns (16 real columns: re/im of each):
-//   t = O y on MFMA 16x16x16 bf16 (y rounded to bf16), capture e0^T O y (FP32), t *= G1 (FP32),
-//   s = (v O^T) t on MFMA (t rounded to bf16), s written in FP32.
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// One channel g (pair wave w) and 8*CT complex columns (16*CT real columns: re/im of each):
+//   t = O y on MFMA 16x16x16 bf16, t *= G1 (FP32), s = (v O^T) t on MFMA, s written in FP32.
+// SPLIT = false: y, t, O and v O^T rounded to bf16 once (one product per tile);
+// SPLIT = true: every operand x is carried as hi + lo with hi = bf16(x), lo = bf16(x - hi), and
+//   a tile product is A_hi B_hi + A_hi B_lo + A_lo B_hi (16 significant bits per operand).
+// Accumulation is FP32 throughout.
 // MFMA 16x16x16 bf16 operands: lane l holds A[l%16][4(l/16)+0..3], B[4(l/16)+0..3][l%16];
 // the result D[4(l/16)+r][l%16], r = 0..3.
-__global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const uint16_t* __restrict__ Wb,
-                                                   const float2* __restrict__ y, float2* __restrict__ s_out) {
+template <bool SPLIT, int CT>
+__global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const float2* __restrict__ y,
+                                                   float2* __restrict__ s_out) {
   extern __shared__ uint16_t shb[];
+  constexpr int NP = SPLIT ? 2 : 1;
+  constexpr int RC = 16 * CT;     // real columns per block
+  constexpr int CC = 8 * CT;      // complex columns per block
   const int M = r.M, Mp = r.Mp, B = r.B, nch = r.nch;
   const int ncol = r.N * B;
   const int g = blockIdx.y;
   const size_t woff = (size_t)r.wave[g] * Mp * Mp;
-  const uint16_t* O = r.A + woff;
-  const uint16_t* W = Wb + woff;
-  const int col0 = blockIdx.x * 8;
-  uint16_t* YT = shb;             // [16][Mp], real column rc = 2 cc + part
-  uint16_t* TT = shb + 16 * Mp;   // [16][Mp]
+  const uint16_t* Oh = r.A + woff;
+  const uint16_t* Ol = SPLIT ? r.A_lo + woff : nullptr;
+  const uint16_t* Wh = r.W + woff;
+  const uint16_t* Wl = SPLIT ? r.W_lo + woff : nullptr;
+  const int col0 = blockIdx.x * CC;
+  uint16_t* YT = shb;                      // [NP][RC][Mp], real column rc = 2 cc + part
+  uint16_t* TT = shb + NP * RC * Mp;       // [NP][RC][Mp]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int e = tid; e < 8 * Mp; e += 256) {
+  for (int e = tid; e < CC * Mp; e += 256) {
     int cc, i;
-    if (B >= 8) {   // consecutive threads -> consecutive energies c
-      i = e >> 3;
-      cc = e & 7;
+    if (B >= CC) {  // consecutive threads -> consecutive energies c
+      i = e / CC;
+      cc = e - i * CC;
     } else {        // consecutive threads -> consecutive p bins i
       cc = e / Mp;
       i = e - cc * Mp;
@@ -48,67 +61,126 @@ __global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const uint16_
     if (i < M && col < ncol) {
       const int jj = col / B, cb = col - jj * B;
       v = y[(((size_t)jj * M + i) * nch + g) * B + cb];
+      if (r.yscale) {
+        const float sc = (float)r.yscale[cb];
+        v.x *= sc;
+        v.y *= sc;
+      }
     }
-    YT[(2 * cc) * Mp + i] = f2bf(v.x);
-    YT[(2 * cc + 1) * Mp + i] = f2bf(v.y);
+    const uint16_t hx = f2bf(v.x), hy = f2bf(v.y);
+    YT[(2 * cc) * Mp + i] = hx;
+    YT[(2 * cc + 1) * Mp + i] = hy;
+    if (SPLIT) {
+      YT[RC * Mp + (2 * cc) * Mp + i] = f2bf(v.x - bf2f(hx));
+      YT[RC * Mp + (2 * cc + 1) * Mp + i] = f2bf(v.y - bf2f(hy));
+    }
   }
   __syncthreads();
   const int rc = lane & 15, quad = lane >> 4;
-  const int cc = rc >> 1, part = rc & 1;
-  const int col = col0 + cc;
-  const bool live = col < ncol;
-  const int jj = live ? col / B : 0, cb = live ? col - jj * B : 0;
+  const int part = rc & 1;
   const int nt = Mp / 16;
   for (int kt = wv; kt < nt; kt += 4) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int it = 0; it < nt; ++it) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(O + (size_t)(kt * 16 + rc) * Mp + it * 16 + 4 * quad);
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(YT + rc * Mp + it * 16 + 4 * quad);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      const size_t ao = (size_t)(kt * 16 + rc) * Mp + it * 16 + 4 * quad;
+      const bf16x4 ah = *reinterpret_cast<const bf16x4*>(Oh + ao);
+      bf16x4 al;
+      if (SPLIT) al = *reinterpret_cast<const bf16x4*>(Ol + ao);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int bo = (ct * 16 + rc) * Mp + it * 16 + 4 * quad;
+        const bf16x4 bh = *reinterpret_cast<const bf16x4*>(YT + bo);
+        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[ct], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x4 bl = *reinterpret_cast<const bf16x4*>(YT + RC * Mp + bo);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[ct], 0, 0, 0);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[ct], 0, 0, 0);
+        }
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = kt * 16 + 4 * quad + q;
-      const float val = acc[q];
-      const float other = __shfl_xor(val, 1, 64);
-      const float re = part ? other : val, im = part ? val : other;
-      float out = 0.f;
-      if (live && k < M) {
-        if (r.acap && k == 0 && part == 0 && jj == r.j0[cb]) {
-          for (int f = 0; f < r.nfin; ++f)
-            if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = make_float2(re, im);
+    for (int ct = 0; ct < CT; ++ct) {
+      const int cc = ct * 8 + (rc >> 1);
+      const int col = col0 + cc;
+      const bool live = col < ncol;
+      const int jj = live ? col / B : 0, cb = live ? col - jj * B : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kt * 16 + 4 * quad + q;
+        const float val = acc[ct][q];
+        const float other = __shfl_xor(val, 1, 64);
+        const float re = part ? other : val, im = part ? val : other;
+        float out = 0.f;
+        if (live && k < M) {
+          const float2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
+          out = part ? (re * gv.y + im * gv.x) : (re * gv.x - im * gv.y);
         }
-        const float2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
-        out = part ? (re * gv.y + im * gv.x) : (re * gv.x - im * gv.y);
+        const uint16_t ho = f2bf(out);
+        TT[(ct * 16 + rc) * Mp + k] = ho;
+        if (SPLIT) TT[RC * Mp + (ct * 16 + rc) * Mp + k] = f2bf(out - bf2f(ho));
       }
-      TT[rc * Mp + k] = f2bf(out);
     }
   }
   __syncthreads();
+  float* so = reinterpret_cast<float*>(s_out);
   for (int itl = wv; itl < nt; itl += 4) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int kt = 0; kt < nt; ++kt) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(W + (size_t)(itl * 16 + rc) * Mp + kt * 16 + 4 * quad);
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(TT + rc * Mp + kt * 16 + 4 * quad);
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    if (live) {
-      float* so = reinterpret_cast<float*>(s_out);
+    f32x4 acc[CT];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = itl * 16 + 4 * quad + q;
-        if (i < M) so[2 * ((((size_t)jj * M + i) * nch + g) * B + cb) + part] = acc[q];
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < nt; ++kt) {
+      const size_t ao = (size_t)(itl * 16 + rc) * Mp + kt * 16 + 4 * quad;
+      const bf16x4 ah = *reinterpret_cast<const bf16x4*>(Wh + ao);
+      bf16x4 al;
+      if (SPLIT) al = *reinterpret_cast<const bf16x4*>(Wl + ao);
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int bo = (ct * 16 + rc) * Mp + kt * 16 + 4 * quad;
+        const bf16x4 bh = *reinterpret_cast<const bf16x4*>(TT + bo);
+        acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[ct], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x4 bl = *reinterpret_cast<const bf16x4*>(TT + RC * Mp + bo);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[ct], 0, 0, 0);
+          acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[ct], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int cc = ct * 8 + (rc >> 1);
+      const int col = col0 + cc;
+      if (col < ncol) {
+        const int jj = col / B, cb = col - jj * B;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = itl * 16 + 4 * quad + q;
+          if (i < M) so[2 * ((((size_t)jj * M + i) * nch + g) * B + cb) + part] = acc[ct][q];
+        }
       }
     }
   }
 }
 
-hipError_t launch_step_bf16(const RotArgsMixed& r, const uint16_t* W, const float2* y, float2* s_out, hipStream_t s) {
-  if (r.M < 1 || r.Mp < r.M || r.Mp % 16 || r.N < 1 || r.B < 1 || r.nch < 1 || !r.G) return hipErrorInvalidValue;
-  const size_t shmem = (size_t)2 * 16 * r.Mp * sizeof(uint16_t);
-  if (shmem > 64 * 1024) return hipErrorInvalidValue;
-  dim3 grid((r.N * r.B + 7) / 8, r.nch);
-  hipLaunchKernelGGL(k_step_bf16, grid, dim3(256), shmem, s, r, W, y, s_out);
+size_t step_bf16_lds(int Mp, bool split, int ct) { return (size_t)2 * (split ? 2 : 1) * 16 * ct * Mp * sizeof(uint16_t); }
+
+hipError_t launch_step_bf16(const RotArgsMixed& r, const float2* y, float2* s_out, hipStream_t s) {
+  if (r.M < 1 || r.Mp < r.M || r.Mp % 16 || r.N < 1 || r.B < 1 || r.nch < 1 || !r.G || !r.A || !r.W)
+    return hipErrorInvalidValue;
+  const bool split = r.A_lo != nullptr;
+  if (split && !r.W_lo) return hipErrorInvalidValue;
+  const size_t lim = 64 * 1024;
+  const int ct = step_bf16_lds(r.Mp, split, 2) <= lim ? 2 : 1;
+  const size_t shmem = step_bf16_lds(r.Mp, split, ct);
+  if (shmem > lim) return hipErrorInvalidValue;
+  dim3 grid((r.N * r.B + 8 * ct - 1) / (8 * ct), r.nch);
+  if (split) {
+    if (ct == 2) hipLaunchKernelGGL((k_step_bf16<true, 2>), grid, dim3(256), shmem, s, r, y, s_out);
+    else hipLaunchKernelGGL((k_step_bf16<true, 1>), grid, dim3(256), shmem, s, r, y, s_out);
+  } else {
+    if (ct == 2) hipLaunchKernelGGL((k_step_bf16<false, 2>), grid, dim3(256), shmem, s, r, y, s_out);
+    else hipLaunchKernelGGL((k_step_bf16<false, 1>), grid, dim3(256), shmem, s, r, y, s_out);
+  }
   return hipGetLastError();
 }
 
@@ -172,71 +244,204 @@ hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ Arnoldi helpers (per column c)
-// Vectors are [rows][B] float2 (rows = D lattice entries); a basis is nv such vectors, vstride apart.
+// ------------------------------------------------------------------ Arnoldi (per column c)
+// Vectors are [rows][B] float2 (rows = D lattice entries, row d = cell * nch + g); a basis is
+// kept unnormalised, V_i = scl[i][c] * Vt_i, with the basis slots vstride apart. Every kernel
+// below has lanes over 64 columns (blockIdx.y picks the column block) and waves striding over
+// rows; FP64 partial sums per block are reduced in LDS and written to part[blk][i][c], which a
+// wavefront-per-output pass sums in a fixed order (results do not depend on scheduling).
 
-#define MD_MAXV 48
-
-// part[blk][i][c] = sum over this block's rows of conj(V_i[d][c]) x[d][c], FP64 accumulation.
-// Lanes over columns c, waves over rows; x[d][c] is loaded once per chunk of up to 8 basis
-// vectors whose partial sums stay in registers; one LDS reduction over the waves per chunk.
-__global__ void __launch_bounds__(256) k_mdot(int64_t rows, int B, int nv, const float2* __restrict__ V, int64_t vstride,
-                                              const float2* __restrict__ x, int64_t rows_per_blk,
-                                              double2* __restrict__ part) {
-  __shared__ double2 red[4][8][64];
+// Sums the per-wave partials (hr, hi)[0 .. nv) over the four waves of the block.
+__device__ __forceinline__ void arn_block_reduce(const double (&hr)[ARN_NV], const double (&hi)[ARN_NV], int nv,
+                                                 int c, bool live, int B, double2* __restrict__ part) {
+  __shared__ double2 red[4][4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = min(rows, r0 + rows_per_blk);
-  for (int cb = 0; cb < B; cb += 64) {
-    const int c = cb + lane;
-    for (int i0 = 0; i0 < nv; i0 += 8) {
-      const int ni = min(8, nv - i0);
-      double sr[8], si[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sr[q] = si[q] = 0.0;
-      if (c < B) {
-        for (int64_t d = r0 + wv; d < r1; d += 4) {
-          const float2 w = x[d * B + c];
+  for (int i0 = 0; i0 < ARN_NV; i0 += 4) {
+    if (i0 < nv) {   // uniform over the block
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            if (q < ni) {
-              const float2 v = V[(size_t)(i0 + q) * vstride + d * B + c];
-              sr[q] += (double)v.x * w.x + (double)v.y * w.y;
-              si[q] += (double)v.x * w.y - (double)v.y * w.x;
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) red[wv][q][lane] = make_double2(sr[q], si[q]);
+      for (int q = 0; q < 4; ++q) red[wv][q][lane] = make_double2(hr[i0 + q], hi[i0 + q]);
       __syncthreads();
-      // 8 x 64 results per chunk: thread t reduces entry (q = t / 64 ... ) over the 4 waves
-      for (int e = threadIdx.x; e < 8 * 64; e += 256) {
-        const int q = e >> 6, l = e & 63;
-        const int cc = cb + l;
-        if (q < ni && cc < B) {
-          double2 t = red[0][q][l];
-          for (int w4 = 1; w4 < 4; ++w4) {
-            t.x += red[w4][q][l].x;
-            t.y += red[w4][q][l].y;
-          }
-          part[((size_t)blockIdx.x * nv + i0 + q) * B + cc] = t;
+      const int i = i0 + wv;
+      if (live && i < nv) {
+        double2 t = red[0][wv][lane];
+        for (int w4 = 1; w4 < 4; ++w4) {
+          t.x += red[w4][wv][lane].x;
+          t.y += red[w4][wv][lane].y;
         }
+        part[((size_t)blockIdx.x * nv + i) * B + c] = t;
       }
       __syncthreads();
     }
   }
 }
 
-// out[i][c] (+)= sum_blk part[blk][i][c]: one wavefront per output, lanes over the blocks in a
-// fixed order, then a shuffle reduction (the result does not depend on scheduling).
+__device__ __forceinline__ void arn_dot_row(const float2* __restrict__ V, int64_t vstride, int nv, size_t idx,
+                                            float wr, float wi, double (&hr)[ARN_NV], double (&hi)[ARN_NV]) {
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) {
+    if (q < nv) {
+      const float2 v = V[(size_t)q * vstride + idx];
+      hr[q] += (double)v.x * wr + (double)v.y * wi;
+      hi[q] += (double)v.x * wi - (double)v.y * wr;
+    }
+  }
+}
+
+// Fused Arnoldi product for B >= 16, nch <= 4: w = V_j - P0 t (block-CSR, lanes over columns,
+// the nonzero blocks of a row taken four at a time so their gathers overlap), w stored in basis
+// slot j + 1, and the partial sums of conj(Vt_i) w for i <= j.
+template <int NC>
+__global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                  const float2* __restrict__ t, float2* __restrict__ V,
+                                                  int64_t vstride, int j, const double* __restrict__ scl,
+                                                  double2* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  const bool live = c < B;
+  const int cl = live ? c : B - 1;
+  const float2* Vj = V + (size_t)j * vstride;
+  float2* Wo = V + (size_t)(j + 1) * vstride;
+  const float sj = (float)scl[(size_t)j * B + cl];
+  const int nv = j + 1;
+  double hr[ARN_NV], hi[ARN_NV];
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) hr[q] = hi[q] = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < cells; row += (int64_t)gridDim.x * 4) {
+    float ar[NC], ai[NC];
+#pragma unroll
+    for (int g = 0; g < NC; ++g) ar[g] = ai[g] = 0.f;
+    const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+    int64_t e = b0;
+    for (; e + 4 <= b1; e += 4) {
+      int cc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) cc[u] = col[e + u];
+      float2 xv[4][NC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int gp = 0; gp < NC; ++gp) xv[u][gp] = t[((size_t)cc[u] * NC + gp) * B + cl];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float* v = val + (e + u) * NC * NC;
+#pragma unroll
+        for (int gp = 0; gp < NC; ++gp)
+#pragma unroll
+          for (int g = 0; g < NC; ++g) {
+            const float a = v[g * NC + gp];
+            ar[g] = fmaf(a, xv[u][gp].x, ar[g]);
+            ai[g] = fmaf(a, xv[u][gp].y, ai[g]);
+          }
+      }
+    }
+    for (; e < b1; ++e) {
+      const int cc = col[e];
+      const float* v = val + e * NC * NC;
+#pragma unroll
+      for (int gp = 0; gp < NC; ++gp) {
+        const float2 xv = t[((size_t)cc * NC + gp) * B + cl];
+#pragma unroll
+        for (int g = 0; g < NC; ++g) {
+          const float a = v[g * NC + gp];
+          ar[g] = fmaf(a, xv.x, ar[g]);
+          ai[g] = fmaf(a, xv.y, ai[g]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < NC; ++g) {
+      const size_t idx = ((size_t)row * NC + g) * B + cl;
+      const float2 v = Vj[idx];
+      const float wr = sj * v.x - ar[g], wi = sj * v.y - ai[g];
+      if (live) Wo[idx] = make_float2(wr, wi);
+      arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
+    }
+  }
+  arn_block_reduce(hr, hi, nv, c, live, B, part);
+}
+
+// Unfused variant (any B, any nch): w = V_j - kv with kv = P0 t from the general SpMM.
+__global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const float2* __restrict__ kv,
+                                                  float2* __restrict__ V, int64_t vstride, int j,
+                                                  const double* __restrict__ scl, double2* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  const bool live = c < B;
+  const int cl = live ? c : B - 1;
+  const float2* Vj = V + (size_t)j * vstride;
+  float2* Wo = V + (size_t)(j + 1) * vstride;
+  const float sj = (float)scl[(size_t)j * B + cl];
+  const int nv = j + 1;
+  double hr[ARN_NV], hi[ARN_NV];
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) hr[q] = hi[q] = 0.0;
+  for (int64_t d = (int64_t)blockIdx.x * 4 + wv; d < rows; d += (int64_t)gridDim.x * 4) {
+    const size_t idx = (size_t)d * B + cl;
+    const float2 v = Vj[idx], k = kv[idx];
+    const float wr = sj * v.x - k.x, wi = sj * v.y - k.y;
+    if (live) Wo[idx] = make_float2(wr, wi);
+    arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
+  }
+  arn_block_reduce(hr, hi, nv, c, live, B, part);
+}
+
+// w -= sum_{i <= j} h_i V_i (FP64 arithmetic, FP32 storage) in basis slot j + 1, with the partial
+// sums of |w|^2 of the stored values.
+__global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* __restrict__ V, int64_t vstride, int j,
+                                                   const double2* __restrict__ h, const double* __restrict__ scl,
+                                                   double2* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
+  const bool live = c < B;
+  const int cl = live ? c : B - 1;
+  const int nv = j + 1;
+  double cr[ARN_NV], ci[ARN_NV];
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) {
+    cr[q] = ci[q] = 0.0;
+    if (q < nv) {
+      const double sc = scl[(size_t)q * B + cl];
+      cr[q] = h[(size_t)q * B + cl].x * sc;
+      ci[q] = h[(size_t)q * B + cl].y * sc;
+    }
+  }
+  float2* Wo = V + (size_t)(j + 1) * vstride;
+  double acc[ARN_NV], dummy[ARN_NV];
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) acc[q] = dummy[q] = 0.0;
+  for (int64_t d = (int64_t)blockIdx.x * 4 + wv; d < rows; d += (int64_t)gridDim.x * 4) {
+    const size_t idx = (size_t)d * B + cl;
+    const float2 w = Wo[idx];
+    double xr = w.x, xi = w.y;
+#pragma unroll
+    for (int q = 0; q < ARN_NV; ++q) {
+      if (q < nv) {
+        const float2 v = V[(size_t)q * vstride + idx];
+        xr -= cr[q] * v.x - ci[q] * v.y;
+        xi -= cr[q] * v.y + ci[q] * v.x;
+      }
+    }
+    const float2 o = make_float2((float)xr, (float)xi);
+    if (live) Wo[idx] = o;
+    acc[0] += (double)o.x * o.x + (double)o.y * o.y;
+  }
+  arn_block_reduce(acc, dummy, 1, c, live, B, part);
+}
+
 __device__ __forceinline__ double wsum64(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-__global__ void __launch_bounds__(256) k_mdot_finish(int nblk, int B, int nv, const double2* __restrict__ part,
-                                                     double2* __restrict__ out, int accumulate) {
+// One wavefront per output (i, c), lanes over the blocks in a fixed order.
+// mode 0: out[i][c] = scl[i][c] * sum_blk part[blk][i][c]       (Hessenberg column, i < nv)
+// mode 1: n = sqrt(sum_blk part[blk][0][c].x); out[0][c] = n;    (subdiagonal entry)
+//         scl_next[c] = 1 / n (0 for a zero vector)
+__global__ void __launch_bounds__(256) k_arn_finish(int nblk, int B, int nv, const double2* __restrict__ part,
+                                                    const double* __restrict__ scl, double2* __restrict__ out,
+                                                    double* __restrict__ scl_next, int mode) {
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= nv * B) return;
@@ -250,75 +455,96 @@ __global__ void __launch_bounds__(256) k_mdot_finish(int nblk, int B, int nv, co
   sr = wsum64(sr);
   si = wsum64(si);
   if (lane == 0) {
-    if (accumulate) {
-      out[t].x += sr;
-      out[t].y += si;
+    if (mode == 0) {
+      const double sc = scl ? scl[(size_t)i * B + c] : 1.0;
+      out[t] = make_double2(sr * sc, si * sc);
     } else {
-      out[t] = make_double2(sr, si);
+      const double n = sqrt(fmax(sr, 0.0));
+      out[c] = make_double2(n, 0.0);
+      scl_next[c] = n > 1e-300 ? 1.0 / n : 0.0;
     }
   }
 }
 
-hipError_t launch_mdot(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const float2* x, double2* part,
-                       int nblk, double2* out, int accumulate, hipStream_t s) {
-  if (nv < 1 || nv > MD_MAXV || B < 1 || nblk < 1) return hipErrorInvalidValue;
-  const int64_t rpb = (rows + nblk - 1) / nblk;
-  hipLaunchKernelGGL(k_mdot, dim3(nblk), dim3(256), 0, s, rows, B, nv, V, vstride, x, rpb, part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3((nv * B + 3) / 4), dim3(256), 0, s, nblk, B, nv, part, out, accumulate);
-  return hipGetLastError();
+static dim3 arn_grid(int64_t rows, int B, int nblk) {
+  const int64_t need = (rows + 3) / 4;
+  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nblk, need)), (unsigned)((B + 63) / 64));
 }
 
-// x[d][c] -= sum_i h[i][c] V_i[d][c]   (FP64 arithmetic, FP32 storage)
-__global__ void k_orth_update(int64_t n, int B, int nv, const float2* __restrict__ V, int64_t vstride,
-                              const double2* __restrict__ h, float2* __restrict__ x) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int c = (int)(t % B);
-  double xr = x[t].x, xi = x[t].y;
-  for (int i = 0; i < nv; ++i) {
-    const double2 hc = h[(size_t)i * B + c];
-    const float2 v = V[(size_t)i * vstride + t];
-    xr -= hc.x * v.x - hc.y * v.y;
-    xi -= hc.x * v.y + hc.y * v.x;
+int arn_blocks(int64_t rows, int B, int nblk) { return (int)arn_grid(rows, B, nblk).x; }
+
+template <int NC>
+static void spmm_arn_launch(dim3 grid, hipStream_t s, int64_t cells, int B, const int64_t* rowptr, const int32_t* col,
+                            const float* val, const float2* t, float2* V, int64_t vstride, int j, const double* scl,
+                            double2* part) {
+  hipLaunchKernelGGL(k_spmm_arn<NC>, grid, dim3(256), 0, s, cells, B, rowptr, col, val, t, V, vstride, j, scl, part);
+}
+
+hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2* kv_scratch, hipStream_t s) {
+  if (a.j < 0 || a.j + 1 >= ARN_NV + 1 || a.B < 1 || a.nch < 1 || a.vstride < a.cells * a.nch * a.B)
+    return hipErrorInvalidValue;
+  const int64_t rows = a.cells * a.nch;
+  if (a.B >= 16 && a.nch <= 4) {
+    const dim3 grid = arn_grid(a.cells, a.B, a.nblk);
+    switch (a.nch) {
+      case 1: spmm_arn_launch<1>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      case 2: spmm_arn_launch<2>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      case 3: spmm_arn_launch<3>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      default: spmm_arn_launch<4>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+    }
+    const int nb = (int)grid.x;
+    hipLaunchKernelGGL(k_arn_finish, dim3(((a.j + 1) * a.B + 3) / 4), dim3(256), 0, s, nb, a.B, a.j + 1, a.part, a.scl,
+                       a.H + (size_t)a.j * (a.m + 1) * a.B, nullptr, 0);
+  } else {
+    if (!kv_scratch) return hipErrorInvalidValue;
+    hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s);
+    if (e != hipSuccess) return e;
+    const dim3 grid = arn_grid(rows, a.B, a.nblk);
+    hipLaunchKernelGGL(k_sub_dots, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl, a.part);
+    hipLaunchKernelGGL(k_arn_finish, dim3(((a.j + 1) * a.B + 3) / 4), dim3(256), 0, s, (int)grid.x, a.B, a.j + 1,
+                       a.part, a.scl, a.H + (size_t)a.j * (a.m + 1) * a.B, nullptr, 0);
   }
-  x[t] = make_float2((float)xr, (float)xi);
-}
-
-hipError_t launch_orth_update(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const double2* h, float2* x,
-                              hipStream_t s) {
-  const int64_t n = rows * B;
-  hipLaunchKernelGGL(k_orth_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nv, V, vstride, h, x);
   return hipGetLastError();
 }
 
-// out[d][c] = x[d][c] / sqrt(nrm[c]) (nrm = squared norm from k_mdot, real part); zero if tiny.
-// Also stores the norm into hsub[c] (the subdiagonal entry of the Hessenberg matrix).
-__global__ void k_normalize(int64_t n, int B, const double2* __restrict__ nrm2, const float2* __restrict__ x,
-                            float2* __restrict__ out, double2* __restrict__ hsub) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const int c = (int)(t % B);
-  const double nr = sqrt(fmax(nrm2[c].x, 0.0));
-  const double inv = nr > 1e-300 ? 1.0 / nr : 0.0;
-  out[t] = make_float2((float)(x[t].x * inv), (float)(x[t].y * inv));
-  if (t < B) hsub[t] = make_double2(sqrt(fmax(nrm2[t].x, 0.0)), 0.0);
-}
-
-hipError_t launch_normalize(int64_t rows, int B, const double2* nrm2, const float2* x, float2* out, double2* hsub,
-                            hipStream_t s) {
-  const int64_t n = rows * B;
-  hipLaunchKernelGGL(k_normalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nrm2, x, out, hsub);
+hipError_t launch_arnoldi_orth(const ArnoldiArgs& a, hipStream_t s) {
+  if (a.j < 0 || a.j + 1 > ARN_NV || a.j + 1 > a.m) return hipErrorInvalidValue;
+  const int64_t rows = a.cells * a.nch;
+  const dim3 grid = arn_grid(rows, a.B, a.nblk);
+  const double2* hcol = a.H + (size_t)a.j * (a.m + 1) * a.B;
+  hipLaunchKernelGGL(k_orth_norm, grid, dim3(256), 0, s, rows, a.B, a.V, a.vstride, a.j, hcol, a.scl, a.part);
+  hipLaunchKernelGGL(k_arn_finish, dim3((a.B + 3) / 4), dim3(256), 0, s, (int)grid.x, a.B, 1, a.part, a.scl,
+                     a.H + ((size_t)a.j * (a.m + 1) + a.j + 1) * a.B, a.scl + (size_t)(a.j + 1) * a.B, 1);
   return hipGetLastError();
 }
 
-// w = v - kv (FP32): applies (I - K) given K v
-__global__ void k_sub_f32(int64_t n, const float2* __restrict__ v, const float2* __restrict__ kv, float2* __restrict__ w) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) w[t] = make_float2(v[t].x - kv[t].x, v[t].y - kv[t].y);
+// U[c][f] = e0^T O y at (g = finals[f], j = j0[c], k = 0): one wavefront per (c, f), lanes over i.
+__global__ void __launch_bounds__(256) k_capture64(int M, int nch, int B, int nfin, const double* __restrict__ O,
+                                                   const int* __restrict__ wave, const int* __restrict__ j0,
+                                                   const int* __restrict__ finals, const double2* __restrict__ y,
+                                                   double2* __restrict__ out) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= B * nfin) return;
+  const int c = t / nfin, f = t - c * nfin;
+  const int g = finals[f];
+  const double* o = O + (size_t)wave[g] * M * M;   // row k = 0
+  double sr = 0.0, si = 0.0;
+  for (int i = lane; i < M; i += 64) {
+    const double2 v = y[(((size_t)j0[c] * M + i) * nch + g) * B + c];
+    sr += o[i] * v.x;
+    si += o[i] * v.y;
+  }
+  sr = wsum64(sr);
+  si = wsum64(si);
+  if (lane == 0) out[t] = make_double2(sr, si);
 }
 
-hipError_t launch_sub_f32(int64_t n, const float2* v, const float2* kv, float2* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, v, kv, w);
+hipError_t launch_capture64(int M, int nch, int B, int nfin, const double* O, const int* wave, const int* j0,
+                            const int* finals, const double2* y, double2* out, hipStream_t s) {
+  if (M < 1 || B < 1 || nfin < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_capture64, dim3((B * nfin + 3) / 4), dim3(256), 0, s, M, nch, B, nfin, O, wave, j0, finals, y,
+                     out);
   return hipGetLastError();
 }
 
@@ -347,24 +573,26 @@ __global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const do
 hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s) {
   const int64_t rpb = (rows + nblk - 1) / nblk;
   hipLaunchKernelGGL(k_norm2_f64, dim3(nblk), dim3(256), 0, s, rows, B, x, rpb, part);
-  hipLaunchKernelGGL(k_mdot_finish, dim3((B + 3) / 4), dim3(256), 0, s, nblk, B, 1, part, out, 0);
+  hipLaunchKernelGGL(k_arn_finish, dim3((B + 3) / 4), dim3(256), 0, s, nblk, B, 1, part, nullptr, out, nullptr, 0);
   return hipGetLastError();
 }
 
 // out[d][c] = x[d][c] / sqrt(nrm2[c]) with x in FP64, out in FP32
 __global__ void k_scale_d2f(int64_t n, int B, const double2* __restrict__ nrm2, const double2* __restrict__ x,
-                            float2* __restrict__ out) {
+                            float2* __restrict__ out, double* __restrict__ scl0) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int c = (int)(t % B);
+  if (scl0 && t < B) scl0[t] = 1.0;
   const double nr = sqrt(fmax(nrm2[c].x, 0.0));
   const double inv = nr > 1e-300 ? 1.0 / nr : 0.0;
   out[t] = make_float2((float)(x[t].x * inv), (float)(x[t].y * inv));
 }
 
-hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, hipStream_t s) {
+hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, double* scl0,
+                            hipStream_t s) {
   const int64_t n = rows * B;
-  hipLaunchKernelGGL(k_scale_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nrm2, x, out);
+  hipLaunchKernelGGL(k_scale_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, B, nrm2, x, out, scl0);
   return hipGetLastError();
 }
 

@@ -144,8 +144,9 @@ hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* ro
 // zero the columns [cb0, cb1) of a rows x B array
 hipError_t launch_fill0_cols(double2* p, int64_t rows, int B, int cb0, int cb1, hipStream_t st);
 
-// Channel resolvent G1 on the device (FP64). One thread per (wave, k, j, energy); the value is
-// written to every channel of that pair wave and to the nrep columns of the energy:
+// Channel resolvent G1 on the device (FP64). One lane per (wave, k, j, energy) element, one
+// wavefront for the elements near the energy shell (work list wl / wl_n, g1_work_elems entries);
+// the value is written to every channel of that pair wave and to the nrep columns of the energy:
 // G[((j*M + k)*nch + g)*B + col0 + e*nrep + f].
 struct G1Args {
   int M, N, nch, B, nwave, nE, nrep, col0;
@@ -162,42 +163,65 @@ struct G1Args {
   const double* gl_x;   // Gauss-Legendre nodes / weights on [-1, 1]
   const double* gl_w;
   int ngl;
+  const double* gl16_x; // 16-point Gauss-Legendre rule of the lane path
+  const double* gl16_w;
   double h2m;
   double2* G;
+  int64_t* wl;          // work list (g1_work_elems entries) and its counter
+  int* wl_n;
 };
+int64_t g1_work_elems(int nwave, int M, int N, int nE);
 hipError_t launch_g1(const G1Args& g, hipStream_t s);
 
 // Mixed precision (FP32 P0, BF16 blocks on MFMA with FP32 accumulation, FP32 vectors)
 struct RotArgsMixed {
   int M, N, nch, B;
-  const uint16_t* A;     // O in bf16: [nwave][Mp][Mp] row-major, zero padded
-  int Mp;                // M rounded up to a multiple of 16
+  const uint16_t* A;      // O in bf16: [nwave][Mp][Mp] row-major, zero padded
+  const uint16_t* A_lo;   // bf16(O - A) for the split representation, or nullptr
+  const uint16_t* W;      // v O^T in bf16, same layout
+  const uint16_t* W_lo;   // bf16(v O^T - W) or nullptr
+  int Mp;                 // M rounded up to a multiple of 16
   const int* wave;
-  const float2* G;       // G1 in FP32 [j][k][g][c]
-  float2* acap;          // captured e^T O y (FP32) or nullptr
-  const int* j0;
-  const int* finals;
-  int nfin;
-  int64_t acap_off;
+  const float2* G;        // G1 in FP32 [j][k][g][c]
+  const double* yscale;   // per-column factor applied to y on load (nullptr: 1)
 };
-// s = W (G1 * (O y)) on MFMA (W = v O^T in bf16, same layout as A)
-hipError_t launch_step_bf16(const RotArgsMixed& r, const uint16_t* W, const float2* y, float2* s_out, hipStream_t s);
+// s = W (G1 * (O y)) on MFMA (split representation when A_lo / W_lo are given)
+hipError_t launch_step_bf16(const RotArgsMixed& r, const float2* y, float2* s_out, hipStream_t s);
 hipError_t launch_cvt_d2f(int64_t n, const double2* in, float2* out, hipStream_t s);
 hipError_t launch_cvt_scalar(int64_t n, const double* in, float* out, hipStream_t s);
 hipError_t launch_residual(int64_t n, const double2* b, const double2* y, const double2* Ky, double2* r,
                            hipStream_t s);
 hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64_t vstride, const double2* coef,
                           double2* out, hipStream_t s);
-// Arnoldi (per column c of [rows][B] vectors): out[i][c] (+)= <V_i, x> over i < nv (FP64 sums,
-// part = scratch [nblk][nv][B]); x -= sum_i h[i][c] V_i; normalisation; w = v - Kv.
-hipError_t launch_mdot(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const float2* x, double2* part,
-                       int nblk, double2* out, int accumulate, hipStream_t s);
-hipError_t launch_orth_update(int64_t rows, int B, int nv, const float2* V, int64_t vstride, const double2* h, float2* x,
-                              hipStream_t s);
-hipError_t launch_normalize(int64_t rows, int B, const double2* nrm2, const float2* x, float2* out, double2* hsub,
-                            hipStream_t s);
-hipError_t launch_sub_f32(int64_t n, const float2* v, const float2* kv, float2* w, hipStream_t s);
+// Arnoldi on B independent columns of [rows][B] FP32 vectors (rows = cells * nch). The basis is
+// kept unnormalised: V_i = scl[i][c] * Vt_i (slots vstride apart); H column j holds h_i = <V_i, w>
+// (rows 0..j) and the subdiagonal |w| (row j + 1); FP64 sums throughout.
+#define ARN_NV 16   // Arnoldi steps per cycle at most
+struct ArnoldiArgs {
+  int64_t cells;
+  int nch, B, m, j;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const float* val;     // FP32 P0 blocks
+  float2* V;            // basis slots [m + 1][rows][B]
+  int64_t vstride;
+  double* scl;          // [m + 1][B]
+  double2* H;           // [m][m + 1][B]
+  double2* part;        // [nblk][ARN_NV][B] partial sums
+  int nblk;
+};
+// w = V_j - P0 t into slot j + 1 and H column j (rows 0..j); kv_scratch ([rows][B]) is used when
+// the fused kernel does not apply (B < 16 or nch > 4)
+hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2* kv_scratch, hipStream_t s);
+// w -= sum_i h_i V_i, then H[j + 1][j] = |w| and scl[j + 1] = 1 / |w|
+hipError_t launch_arnoldi_orth(const ArnoldiArgs& a, hipStream_t s);
+int arn_blocks(int64_t rows, int B, int nblk);
+// U[c][f] = e0^T O y at (g = finals[f], j = j0[c], k = 0), FP64
+hipError_t launch_capture64(int M, int nch, int B, int nfin, const double* O, const int* wave, const int* j0,
+                            const int* finals, const double2* y, double2* out, hipStream_t s);
 hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s);
-hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, hipStream_t s);
+// out = x / |x| per column (FP64 in, FP32 out); scl0[c] = 1 when given
+hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, double* scl0,
+                            hipStream_t s);
 
 }  // namespace wpcd

@@ -45,7 +45,7 @@ struct wp_lattice {
   int nts = 0, ngl = 0;
   // mixed precision: bf16 copies of O and v O^T (padded to Mp), FP32 P0 values
   int Mp = 0;
-  DBuf<uint16_t> d_Ob, d_Wb;
+  DBuf<uint16_t> d_Ob, d_Wb, d_Ob_lo, d_Wb_lo;
   // P0
   bool have_P = false;
   int prec = WP_P_FP64;
@@ -92,8 +92,11 @@ struct ProfScope {
 wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
 wp_status ensure_mixed(wp_lattice* L, hipStream_t s);   // bf16 blocks + FP32 copy of P0
+// Device work list of the G1 kernels for nE energies (element list plus counter in slot 0).
+bool g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w);
 // G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns)
-G1Args g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G);
+G1Args g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G,
+               DBuf<int64_t>& work);
 
 // Kinematics of one energy: E, q0, on-shell bin j0 ((q_{j-1}, q_j] convention), its width.
 inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {

@@ -264,15 +264,28 @@ def test_wide_batch_matches_single():
         assert abs(a["A"][0, 0] - b["A"][0, 0]) <= 1e-10 * ref + 30 * max(a["err"][0], b["err"][0]) * ref
 
 
-@pytest.mark.parametrize("name", ["quartet_yam_24", "doublet_mt_20"])
-def test_mixed_matches_fp64(name):
-    """Mixed path (FP32 P0, BF16 blocks on MFMA, FP64 residual refinement): |dA| <= 1e-6
-    against the FP64 path for every energy of a batch (the amplitude itself is at most 1/pi)."""
+@pytest.mark.parametrize("mode", ["mixed", "mixed_split"])
+@pytest.mark.parametrize("name,n_E", [("quartet_yam_24", 5), ("doublet_mt_20", 5), ("doublet_mt_20", 20),
+                                      ("pw10_mt_8", 3)])
+def test_mixed_matches_fp64(name, n_E, mode):
+    """Mixed paths (FP32 P0, BF16 blocks on MFMA, FP64 residual refinement): |dA| <= 1e-6
+    against the FP64 path for every energy of a batch (the amplitude itself is at most 1/pi).
+    20 energies take the fused SpMM + Gram-Schmidt kernel, 5 energies and 10 channels the
+    general SpMM followed by the separate difference/dot kernel."""
     spec = SPECS[name]
     L = _lib_lattice(spec)
-    Es = [1.5, 3.0, 9.0, 14.1, 33.0]
-    ref = L.solve(Es, "fp64")
-    mix = L.solve(Es, "mixed", tol=1e-9)
+    Es = {5: [1.5, 3.0, 9.0, 14.1, 33.0], 3: [9.0, 14.1, 33.0]}.get(n_E)
+    if Es is None:
+        Es = list(np.random.default_rng(17).uniform(1.0, 50.0, n_E))
+    ref = L.solve(Es, "fp64", allow_noconv=True)
+    mix = L.solve(Es, mode, tol=1e-8)
+    compared = 0
     for k in range(len(Es)):
         a, b = mix.amplitude(k), ref.amplitude(k)
-        assert abs(a["A"][0, 0] - b["A"][0, 0]) <= 1e-6, (Es[k], abs(a["A"][0, 0] - b["A"][0, 0]), a["err"], a["iters"])
+        if max(b["err"]) > 1e-9:      # FP64 Pade estimate not converged: no reference
+            continue
+        d = np.max(np.abs(a["A"] - b["A"]))
+        assert d <= 1e-6, (Es[k], d, a["err"], a["iters"])
+        assert max(a["iters"]) <= 120
+        compared += 1
+    assert compared >= 2
