@@ -158,7 +158,8 @@ typedef struct {
 wp_status perm_matrix_build(wp_lattice* lat, int precision, void* stream, wp_perm_stats* stats);
 
 /* Host copy of the resident P0: row_ptr[N*M + 1] (block offsets), col[blocks], val[blocks *
- * n_ch * n_ch] (FP32 storage is widened). Any pointer may be NULL to skip it. */
+ * n_ch * n_ch] with block b's entry (g, g') at val[(b * n_ch + g) * n_ch + g'] (the device keeps
+ * blocks column-major; FP32 storage is widened). Any pointer may be NULL to skip it. */
 wp_status perm_matrix_export(const wp_lattice* lat, int64_t* row_ptr, int32_t* col, double* val);
 
 /*

@@ -102,7 +102,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, b->B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
                              c0 + nf));
   HIPCHECK(launch_spmv_f64((int64_t)L->M * L->N, L->nch, b->B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
-                         b->dy.p, st, c0, c0 + nf));
+                         b->dy.p, st, c0, c0 + nf, L->d_order.p));
   HIPCHECK(hipStreamSynchronize(st));
   S.cs.resize(nf);
   for (auto& c : S.cs) {
@@ -127,7 +127,8 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
   for (int t = 0; t < terms; ++t) {
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
     WP_LAUNCH("step64", st, launch_step64(ro, L->d_W.p, b->dy.p, b->ds.p, st));
-    WP_LAUNCH("spmv64", st, launch_spmv_f64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st));
+    WP_LAUNCH("spmv64", st, launch_spmv_f64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
+                                            b->dy.p, st, 0, -1, L->d_order.p));
   }
   HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
                           st));

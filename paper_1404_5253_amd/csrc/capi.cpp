@@ -621,6 +621,18 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   std::swap(L->d_rowptr.p, rowptr.p);
   std::swap(L->d_rowptr.n, rowptr.n);
   L->d_rowptr.al = &L->al;
+  {
+    // SpMV work order: block rows by decreasing length, ties by index, so that the longest rows
+    // start first and do not trail at the end of a launch
+    std::vector<int64_t> rp(R + 1);
+    HIPCHECK(hipMemcpy(rp.data(), L->d_rowptr.p, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> ord(R);
+    for (int64_t r = 0; r < R; ++r) ord[r] = (int32_t)r;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+    if (!L->d_order.make(&L->al, R)) return fail(WP_ENOMEM, "device allocation (row order)");
+    HIPCHECK(hipMemcpy(L->d_order.p, ord.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   L->blocks = nblk;
   L->prec = precision;
   L->have_P = true;
@@ -641,13 +653,19 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
   if (rowptr) HIPCHECK(hipMemcpy(rowptr, L->d_rowptr.p, (R + 1) * 8, hipMemcpyDeviceToHost));
   if (col) HIPCHECK(hipMemcpy(col, L->d_col.p, L->blocks * 4, hipMemcpyDeviceToHost));
   if (val) {
+    // device blocks are column-major; the export is row-major: val[(blk * nch + g) * nch + g']
+    std::vector<double> d(L->blocks * nc2);
     if (L->prec == WP_P_FP64) {
-      HIPCHECK(hipMemcpy(val, L->d_val64.p, L->blocks * nc2 * 8, hipMemcpyDeviceToHost));
+      HIPCHECK(hipMemcpy(d.data(), L->d_val64.p, d.size() * 8, hipMemcpyDeviceToHost));
     } else {
-      std::vector<float> f(L->blocks * nc2);
+      std::vector<float> f(d.size());
       HIPCHECK(hipMemcpy(f.data(), L->d_val32.p, f.size() * 4, hipMemcpyDeviceToHost));
-      for (size_t e = 0; e < f.size(); ++e) val[e] = f[e];
+      for (size_t e = 0; e < f.size(); ++e) d[e] = f[e];
     }
+    const int nch = L->nch;
+    for (int64_t b = 0; b < L->blocks; ++b)
+      for (int g = 0; g < nch; ++g)
+        for (int gp = 0; gp < nch; ++gp) val[b * nc2 + g * nch + gp] = d[b * nc2 + gp * nch + g];
   }
   return WP_OK;
 }
@@ -696,7 +714,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const double* val = L->d_val64.p;
   if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
-  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, L->d_order.p));
   std::vector<ColState> cs(B);
   for (auto& c : cs) {
     c.w.resize(nfin);
@@ -710,7 +728,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
     for (int t = 0; t < T; ++t) {
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin, (int64_t)(n + t) * B * nfin};
       WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
-      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s));
+      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, L->d_order.p));
     }
     HIPCHECK(hipMemcpyAsync(hcap.data(), dacap.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(double2),
                             hipMemcpyDeviceToHost, s));
@@ -891,9 +909,10 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
   HIPCHECK(launch_cvt_d2f(DB, dG64.p, dG32.p, s));
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds64.p, s));
   WP_LAUNCH("spmv_f32v_f64x", s,
-            launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s));
+            launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s, 0, -1,
+                                  L->d_order.p));
   HIPCHECK(launch_fill0(dy.p, DB, s));
-  ArnoldiArgs aa{R, nch, B, m, 0, L->d_rowptr.p, L->d_col.p, L->d_val32.p, V.p, DB, scl.p, H.p, part.p, nblk};
+  ArnoldiArgs aa{R, nch, B, m, 0, L->d_rowptr.p, L->d_col.p, L->d_val32.p, L->d_order.p, V.p, DB, scl.p, H.p, part.p, nblk};
   RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p, split ? L->d_Wb_lo.p : nullptr,
                   L->Mp, L->d_wave.p, dG32.p, nullptr};
   std::vector<cplx> Uprev((size_t)B * nfin, cplx(0, 0)), Ubest((size_t)B * nfin, cplx(0, 0));
@@ -911,7 +930,8 @@ static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, con
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, nullptr, dj0.p, dfin.p, nfin, 0};
       WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
       WP_LAUNCH("spmv_f32v_f64x", s,
-                launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s));
+                launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s, 0, -1,
+                                      L->d_order.p));
       WP_LAUNCH("residual", s, launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
     }
     HIPCHECK(launch_norm2_f64(D, B, dr.p, part.p, nblk, nrm.p, s));

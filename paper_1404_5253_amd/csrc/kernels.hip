@@ -399,6 +399,8 @@ hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t*
   return hipGetLastError();
 }
 
+// The final blocks are stored column-major: P[g][g'] of block d at val[d * nc2 + g' * nch + g], so
+// that lanes over the output channel g read contiguous memory for every g'.
 __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const int64_t* __restrict__ rowptr_c,
                                                  const int32_t* __restrict__ col_c, const double* __restrict__ val_c,
                                                  const uint8_t* __restrict__ flag, const int64_t* __restrict__ rowptr,
@@ -415,13 +417,31 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
     bool f = (e < b1) && flag[e];
     unsigned long long mask = __ballot(f);
     int before = __popcll(mask & ((1ull << lane) - 1ull));
-    if (f) {
-      int64_t d = out + before;
-      col[d] = col_c[e];
-      for (int g = 0; g < nc2; ++g) {
-        double v = val_c[e * nc2 + g];
-        if (val64) val64[d * nc2 + g] = v;
-        if (val32) val32[d * nc2 + g] = (float)v;
+    if (f) col[out + before] = col_c[e];
+    if (nc2 <= 16) {   // a lane copies its own block
+      if (f) {
+        const int64_t d = out + before;
+        for (int g = 0; g < nch; ++g)
+          for (int gp = 0; gp < nch; ++gp) {
+            const double v = val_c[e * nc2 + g * nch + gp];
+            if (val64) val64[d * nc2 + gp * nch + g] = v;
+            if (val32) val32[d * nc2 + gp * nch + g] = (float)v;
+          }
+      }
+    } else {           // the wave copies each kept block, lanes over its entries
+      unsigned long long m = mask;
+      int k = 0;
+      while (m) {
+        const int src = __ffsll((long long)m) - 1;
+        m &= m - 1ull;
+        const int64_t es = base + src, d = out + k;
+        ++k;
+        for (int t = lane; t < nc2; t += 64) {
+          const int gp = t / nch, g = t - gp * nch;
+          const double v = val_c[es * nc2 + g * nch + gp];
+          if (val64) val64[d * nc2 + t] = v;
+          if (val32) val32[d * nc2 + t] = (float)v;
+        }
       }
     }
     out += __popcll(mask);
@@ -843,10 +863,11 @@ __device__ __forceinline__ XT make_x(AT re, AT im) {
 template <typename VT, typename XT, typename AT, int NC>
 __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                              const XT* __restrict__ x, XT* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+                                              const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int c = cb0 + blockIdx.y * 64 + (threadIdx.x & 63);
-  if (row >= rows || c >= cb1) return;
+  if (w >= rows || c >= cb1) return;
+  const int64_t row = order ? order[w] : w;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   AT ar[NC], ai[NC];
 #pragma unroll
@@ -859,7 +880,7 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int 
       const XT xv = x[((size_t)cc * NC + gp) * B + c];
 #pragma unroll
       for (int g = 0; g < NC; ++g) {
-        const AT a = (AT)v[g * NC + gp];
+        const AT a = (AT)v[gp * NC + g];
         ar[g] = fma(a, (AT)xv.x, ar[g]);
         ai[g] = fma(a, (AT)xv.y, ai[g]);
       }
@@ -873,10 +894,11 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int 
 template <typename VT, typename XT, typename AT, int NC>
 __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const VT* __restrict__ val,
-                                              const XT* __restrict__ x, XT* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+                                              const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= rows) return;
+  if (w >= rows) return;
+  const int64_t row = order ? order[w] : w;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   for (int c = cb0; c < cb1; ++c) {
     AT ar[NC], ai[NC];
@@ -890,7 +912,7 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int 
         const XT xv = x[((size_t)cc * NC + gp) * B + c];
 #pragma unroll
         for (int g = 0; g < NC; ++g) {
-          const AT a = (AT)v[g * NC + gp];
+          const AT a = (AT)v[gp * NC + g];
           ar[g] = fma(a, (AT)xv.x, ar[g]);
           ai[g] = fma(a, (AT)xv.y, ai[g]);
         }
@@ -906,48 +928,49 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int 
 
 template <typename VT, typename XT, typename AT, int NC>
 static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* rowptr, const int32_t* col,
-                          const VT* val, const XT* x, XT* y, hipStream_t s) {
+                          const VT* val, const XT* x, XT* y, hipStream_t s, const int32_t* order) {
   // the choice depends on B only, so every launch on a given batch width sums in one order
   if (B >= 16) {
     dim3 grid((unsigned)((rows + 3) / 4), (cb1 - cb0 + 63) / 64);
-    hipLaunchKernelGGL((k_spmm<VT, XT, AT, NC>), grid, dim3(256), 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y);
+    hipLaunchKernelGGL((k_spmm<VT, XT, AT, NC>), grid, dim3(256), 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y, order);
   } else {
     hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, B, cb0, cb1,
-                       rowptr, col, val, x, y);
+                       rowptr, col, val, x, y, order);
   }
 }
 
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1);
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order);
 
 template <typename VT, typename XT, typename AT>
 static hipError_t spmv_any(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1) {
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
   if (cb1 < 0) cb1 = B;
   if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1) return hipErrorInvalidValue;
-  if (nch > 4) return launch_spmv_gen<VT, XT, AT>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+  if (nch > 4) return launch_spmv_gen<VT, XT, AT>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
   switch (nch) {
-    case 1: spmv_dispatch<VT, XT, AT, 1>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
-    case 2: spmv_dispatch<VT, XT, AT, 2>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
-    case 3: spmv_dispatch<VT, XT, AT, 3>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
-    case 4: spmv_dispatch<VT, XT, AT, 4>(rows, B, cb0, cb1, rowptr, col, val, x, y, s); break;
+    case 1: spmv_dispatch<VT, XT, AT, 1>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
+    case 2: spmv_dispatch<VT, XT, AT, 2>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
+    case 3: spmv_dispatch<VT, XT, AT, 3>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
+    case 4: spmv_dispatch<VT, XT, AT, 4>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
-                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
-  return spmv_any<double, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
+  return spmv_any<double, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
 }
 hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
-                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1) {
-  return spmv_any<float, float2, float>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
+  return spmv_any<float, float2, float>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
 }
 hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
-                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1) {
-  return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1);
+                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1,
+                                 const int32_t* order) {
+  return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
 }
 
 }  // namespace wpcd
@@ -1097,39 +1120,226 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
 }
 
 // ------------------------------------------------------------------ block-CSR product, many channels
-// One wavefront per block row; lanes over (g, c) outputs (NC x cols), looping over g' per block.
-template <typename VT, typename XT, typename AT>
+// Few columns (B < 16): one wavefront per block row, lanes over (slot, g) with 64 / NC slots, so
+// that a wavefront takes that many blocks at once; for each g' the lanes of a slot read the
+// contiguous column g' of their (column-major) block and the slot's x entries are broadcast.
+// The slots of a row are summed by shuffles in a fixed order.
+template <typename VT, typename XT, typename AT, int CT>
 __global__ void __launch_bounds__(256) k_spmv_gen(int64_t rows, int NC, int B, int cb0, int cb1,
                                                   const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= rows) return;
-  const int ncols = cb1 - cb0;
-  const int nout = NC * ncols;
+  if (w >= rows) return;
+  const int64_t row = order ? order[w] : w;
+  const int SL = 64 / NC;
+  const int s = lane / NC, g = lane - s * NC;
+  const bool act = s < SL;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   const int nc2 = NC * NC;
-  for (int o0 = 0; o0 < nout; o0 += 64) {
-    const int o = o0 + lane;
-    const bool act = o < nout;
-    const int g = act ? o / ncols : 0;
-    const int c = cb0 + (act ? o - g * ncols : 0);
-    AT ar = 0, ai = 0;
-    if (act) {
-      for (int64_t e = b0; e < b1; ++e) {
-        const int cc = col[e];
-        const VT* v = val + e * nc2 + g * NC;
-        const XT* xr = x + (size_t)cc * NC * B + c;
-        for (int gp = 0; gp < NC; ++gp) {
-          const AT a = (AT)v[gp];
-          const XT xv = xr[(size_t)gp * B];
-          ar = fma(a, (AT)xv.x, ar);
-          ai = fma(a, (AT)xv.y, ai);
+  for (int c0 = cb0; c0 < cb1; c0 += CT) {
+    AT ar[CT], ai[CT];
+#pragma unroll
+    for (int q = 0; q < CT; ++q) ar[q] = ai[q] = AT(0);
+    for (int64_t e0 = b0; e0 < b1; e0 += SL) {
+      const int64_t e = e0 + s;
+      const bool ok = act && e < b1;
+      const int cc = ok ? col[e] : 0;
+      const VT* v = val + (ok ? e : b0) * nc2 + g;
+      const XT* xr = x + (size_t)cc * NC * B;
+      int gp = 0;
+      for (; gp + 4 <= NC; gp += 4) {
+        AT a[4];
+        XT xv[4][CT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = ok ? (AT)v[(gp + u) * NC] : AT(0);
+#pragma unroll
+          for (int q = 0; q < CT; ++q) xv[u][q] = xr[(size_t)(gp + u) * B + min(c0 + q, cb1 - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < CT; ++q) {
+            ar[q] = fma(a[u], (AT)xv[u][q].x, ar[q]);
+            ai[q] = fma(a[u], (AT)xv[u][q].y, ai[q]);
+          }
+      }
+      for (; gp < NC; ++gp) {
+        const AT a = ok ? (AT)v[gp * NC] : AT(0);
+#pragma unroll
+        for (int q = 0; q < CT; ++q) {
+          const XT xv = xr[(size_t)gp * B + min(c0 + q, cb1 - 1)];
+          ar[q] = fma(a, (AT)xv.x, ar[q]);
+          ai[q] = fma(a, (AT)xv.y, ai[q]);
         }
       }
+    }
+    // sum over the slots: lane (0, g) collects (s, g), s = 1 .. SL - 1, in order
+#pragma unroll
+    for (int q = 0; q < CT; ++q) {
+      AT sr = ar[q], si = ai[q];
+      for (int t = 1; t < SL; ++t) {
+        const AT r2 = __shfl(ar[q], min(lane + t * NC, 63), WARP);
+        const AT i2 = __shfl(ai[q], min(lane + t * NC, 63), WARP);
+        if (s == 0) {
+          sr += r2;
+          si += i2;
+        }
+      }
+      if (s == 0 && c0 + q < cb1) {
+        XT out;
+        out.x = sr;
+        out.y = si;
+        y[((size_t)row * NC + g) * B + c0 + q] = out;
+      }
+    }
+  }
+}
+
+// Even NC, few columns: lanes over (slot, h) own the channel pair g = 2h, 2h + 1 and read it as
+// one vector per g' (16 bytes in FP64) from the column-major block, so a wavefront streams
+// SL = 128 / NC blocks per pass with fully used cache lines. The x entries the pass needs
+// (SL slots x NC x CT) are loaded once, coalesced, into the wavefront's LDS and read from there
+// by broadcast; the column indices of up to 63 blocks are loaded once and passed by shuffles;
+// UN values of g' are loaded ahead of their use. Blocks past the row end load nothing.
+template <typename V2, typename XT, typename AT, int CT, int UN>
+__global__ void __launch_bounds__(256) k_spmv_lds(int64_t rows, int NC, int B, int cb0, int cb1,
+                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                  const V2* __restrict__ val2, const XT* __restrict__ x,
+                                                  XT* __restrict__ y, const int32_t* __restrict__ order) {
+  __shared__ XT xs_all[4][128 * CT];
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  XT* xs = xs_all[threadIdx.x >> 6];
+  if (w >= rows) return;
+  const int64_t row = order ? order[w] : w;
+  const int NH = NC >> 1;            // lanes per block column
+  const int SL = 64 / NH;            // blocks per pass
+  const int CH = SL * (64 / SL);     // blocks per column-index chunk (<= 64)
+  const int s = lane / NH, h = lane - s * NH;
+  const bool act = s < SL;
+  const int per = NC * CT;           // staged x entries per slot
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  const int64_t nh2 = (int64_t)NC * NH;   // V2 entries per block
+  for (int c0 = cb0; c0 < cb1; c0 += CT) {
+    AT ar[2][CT], ai[2][CT];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < CT; ++q) ar[k][q] = ai[k][q] = AT(0);
+    for (int64_t cb = b0; cb < b1; cb += CH) {
+      const int colreg = (lane < CH && cb + lane < b1) ? col[cb + lane] : 0;
+      for (int k0 = 0; k0 < CH && cb + k0 < b1; k0 += SL) {
+        const int nsl = (int)min((int64_t)SL, b1 - (cb + k0));
+        for (int t0 = 0; t0 < SL * per; t0 += 64) {   // uniform trip count: all lanes shuffle
+          const int t = t0 + lane;
+          const int sl = min(t / per, SL - 1), off = t - sl * per;
+          const int gp = off / CT, q = off - gp * CT;
+          const int c2 = __shfl(colreg, min(k0 + sl, 63), WARP);
+          if (t < SL * per && sl < nsl) xs[t] = x[((size_t)c2 * NC + gp) * B + min(c0 + q, cb1 - 1)];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int64_t e = cb + k0 + s;
+        if (act && e < b1) {
+          const V2* v = val2 + e * nh2 + h;
+          const XT* xr = xs + s * per;
+          int gp = 0;
+          for (; gp + UN <= NC; gp += UN) {
+            V2 a[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) a[u] = v[(size_t)(gp + u) * NH];
+#pragma unroll
+            for (int u = 0; u < UN; ++u)
+#pragma unroll
+              for (int q = 0; q < CT; ++q) {
+                const XT xv = xr[(gp + u) * CT + q];
+                ar[0][q] = fma((AT)a[u].x, (AT)xv.x, ar[0][q]);
+                ai[0][q] = fma((AT)a[u].x, (AT)xv.y, ai[0][q]);
+                ar[1][q] = fma((AT)a[u].y, (AT)xv.x, ar[1][q]);
+                ai[1][q] = fma((AT)a[u].y, (AT)xv.y, ai[1][q]);
+              }
+          }
+          for (; gp < NC; ++gp) {
+            const V2 a = v[(size_t)gp * NH];
+#pragma unroll
+            for (int q = 0; q < CT; ++q) {
+              const XT xv = xr[gp * CT + q];
+              ar[0][q] = fma((AT)a.x, (AT)xv.x, ar[0][q]);
+              ai[0][q] = fma((AT)a.x, (AT)xv.y, ai[0][q]);
+              ar[1][q] = fma((AT)a.y, (AT)xv.x, ar[1][q]);
+              ai[1][q] = fma((AT)a.y, (AT)xv.y, ai[1][q]);
+            }
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    // sum over the slots: lane (0, h) collects (s, h), s = 1 .. SL - 1, in order
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < CT; ++q) {
+        AT sr = ar[k][q], si = ai[k][q];
+        for (int t = 1; t < SL; ++t) {
+          const AT r2 = __shfl(ar[k][q], min(lane + t * NH, 63), WARP);
+          const AT i2 = __shfl(ai[k][q], min(lane + t * NH, 63), WARP);
+          if (s == 0) {
+            sr += r2;
+            si += i2;
+          }
+        }
+        if (s == 0 && c0 + q < cb1) {
+          XT out;
+          out.x = sr;
+          out.y = si;
+          y[((size_t)row * NC + 2 * h + k) * B + c0 + q] = out;
+        }
+      }
+  }
+}
+
+template <typename VT> struct Vec2;
+template <> struct Vec2<double> { using T = double2; };
+template <> struct Vec2<float> { using T = float2; };
+
+// Many columns (B >= 16): lanes over columns, the block entries wave-uniform, up to NCMAX
+// channel accumulators per lane.
+#define NCMAX 24
+template <typename VT, typename XT, typename AT>
+__global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, int cb0, int cb1,
+                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = cb0 + blockIdx.y * 64 + (threadIdx.x & 63);
+  if (w >= rows || c >= cb1) return;
+  const int64_t row = order ? order[w] : w;
+  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
+  const int nc2 = NC * NC;
+  AT ar[NCMAX], ai[NCMAX];
+#pragma unroll
+  for (int g = 0; g < NCMAX; ++g) ar[g] = ai[g] = AT(0);
+  for (int64_t e = b0; e < b1; ++e) {
+    const int cc = col[e];
+    const VT* v = val + e * nc2;
+    for (int gp = 0; gp < NC; ++gp) {
+      const XT xv = x[((size_t)cc * NC + gp) * B + c];
+#pragma unroll
+      for (int g = 0; g < NCMAX; ++g) {
+        if (g < NC) {
+          const AT a = (AT)v[gp * NC + g];
+          ar[g] = fma(a, (AT)xv.x, ar[g]);
+          ai[g] = fma(a, (AT)xv.y, ai[g]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NCMAX; ++g) {
+    if (g < NC) {
       XT out;
-      out.x = ar;
-      out.y = ai;
+      out.x = ar[g];
+      out.y = ai[g];
       y[((size_t)row * NC + g) * B + c] = out;
     }
   }
@@ -1137,19 +1347,54 @@ __global__ void __launch_bounds__(256) k_spmv_gen(int64_t rows, int NC, int B, i
 
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1) {
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
   if (cb1 < 0) cb1 = B;
-  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B, cb0, cb1,
-                     rowptr, col, val, x, y);
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 1 || nch > 64) return hipErrorInvalidValue;
+  // the choice depends on B and nch only, so every launch on a given batch width sums in one order
+  if (B >= 16 && nch <= NCMAX) {
+    dim3 grid((unsigned)((rows + 3) / 4), (cb1 - cb0 + 63) / 64);
+    hipLaunchKernelGGL((k_spmm_gen<VT, XT, AT>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, val, x, y, order);
+  } else if (nch % 2 == 0 && nch >= 4) {
+    using V2 = typename Vec2<VT>::T;
+    const V2* v2 = reinterpret_cast<const V2*>(val);
+    const dim3 grid((unsigned)((rows + 3) / 4));
+    const int ncols = cb1 - cb0;
+    if (nch % 9 == 0) {
+      if (ncols >= 4)
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 4, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+      else if (ncols >= 2)
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 2, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+      else
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 1, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+    } else {
+      if (ncols >= 4)
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 4, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+      else if (ncols >= 2)
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 2, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+      else
+        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 1, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
+    }
+  } else if (B >= 4) {
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 4>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+                       cb0, cb1, rowptr, col, val, x, y, order);
+  } else if (B >= 2) {
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 2>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+                       cb0, cb1, rowptr, col, val, x, y, order);
+  } else {
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 1>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+                       cb0, cb1, rowptr, col, val, x, y, order);
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_spmv_gen<double, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
-                                                             const double*, const double2*, double2*, hipStream_t, int, int);
+                                                             const double*, const double2*, double2*, hipStream_t, int, int,
+                                                             const int32_t*);
 template hipError_t launch_spmv_gen<float, float2, float>(int64_t, int, int, const int64_t*, const int32_t*,
-                                                          const float*, const float2*, float2*, hipStream_t, int, int);
+                                                          const float*, const float2*, float2*, hipStream_t, int, int,
+                                                          const int32_t*);
 template hipError_t launch_spmv_gen<float, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
-                                                            const float*, const double2*, double2*, hipStream_t, int, int);
+                                                            const float*, const double2*, double2*, hipStream_t, int, int,
+                                                            const int32_t*);
 
 }  // namespace wpcd

@@ -251,9 +251,34 @@ hipError_t launch_lincomb(int64_t rows, int B, int nv, const float2* vecs, int64
 // rows; FP64 partial sums per block are reduced in LDS and written to part[blk][i][c], which a
 // wavefront-per-output pass sums in a fixed order (results do not depend on scheduling).
 
-// Sums the per-wave partials (hr, hi)[0 .. nv) over the four waves of the block.
+// Lane layout of the column kernels: with Bp = min(64, B rounded up to a power of two), lane l
+// takes column blockIdx.y * 64 + l % Bp and row offset l / Bp, so a wavefront covers 64 / Bp rows
+// per pass and no lane idles for small B.
+struct ArnLanes {
+  int Bp, R, cw, rsub, c;
+  bool live;
+};
+__device__ __forceinline__ ArnLanes arn_lanes(int B) {
+  ArnLanes a;
+  const int lane = threadIdx.x & 63;
+  const int bb = B - (int)blockIdx.y * 64;
+  a.Bp = 64;
+  if (bb < 64) {
+    a.Bp = 1;
+    while (a.Bp < bb) a.Bp <<= 1;
+  }
+  a.R = 64 / a.Bp;
+  a.cw = lane % a.Bp;
+  a.rsub = lane / a.Bp;
+  a.c = (int)blockIdx.y * 64 + a.cw;
+  a.live = a.c < B;
+  return a;
+}
+
+// Sums the per-lane partials (hr, hi)[0 .. nv) of equal column over the lanes and waves of the
+// block (fixed order: wave, then row offset) into part[blk][i][c].
 __device__ __forceinline__ void arn_block_reduce(const double (&hr)[ARN_NV], const double (&hi)[ARN_NV], int nv,
-                                                 int c, bool live, int B, double2* __restrict__ part) {
+                                                 const ArnLanes& ln, int B, double2* __restrict__ part) {
   __shared__ double2 red[4][4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -262,13 +287,15 @@ __device__ __forceinline__ void arn_block_reduce(const double (&hr)[ARN_NV], con
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wv][q][lane] = make_double2(hr[i0 + q], hi[i0 + q]);
       __syncthreads();
-      const int i = i0 + wv;
-      if (live && i < nv) {
-        double2 t = red[0][wv][lane];
-        for (int w4 = 1; w4 < 4; ++w4) {
-          t.x += red[w4][wv][lane].x;
-          t.y += red[w4][wv][lane].y;
-        }
+      const int q = wv, i = i0 + wv, l = lane;
+      const int c = (int)blockIdx.y * 64 + l;
+      if (l < ln.Bp && i < nv && c < B) {
+        double2 t = make_double2(0.0, 0.0);
+        for (int w4 = 0; w4 < 4; ++w4)
+          for (int r = 0; r < ln.R; ++r) {
+            t.x += red[w4][q][r * ln.Bp + l].x;
+            t.y += red[w4][q][r * ln.Bp + l].y;
+          }
         part[((size_t)blockIdx.x * nv + i) * B + c] = t;
       }
       __syncthreads();
@@ -294,12 +321,20 @@ __device__ __forceinline__ void arn_dot_row(const float2* __restrict__ V, int64_
 template <int NC>
 __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const int64_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ col, const float* __restrict__ val,
+                                                  const int32_t* __restrict__ order,
                                                   const float2* __restrict__ t, float2* __restrict__ V,
                                                   int64_t vstride, int j, const double* __restrict__ scl,
                                                   double2* __restrict__ part) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
-  const bool live = c < B;
+  ArnLanes ln;
+  ln.Bp = 64;
+  ln.R = 1;
+  ln.cw = lane;
+  ln.rsub = 0;
+  ln.c = blockIdx.y * 64 + lane;
+  ln.live = ln.c < B;
+  const int c = ln.c;
+  const bool live = ln.live;
   const int cl = live ? c : B - 1;
   const float2* Vj = V + (size_t)j * vstride;
   float2* Wo = V + (size_t)(j + 1) * vstride;
@@ -308,7 +343,8 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
   double hr[ARN_NV], hi[ARN_NV];
 #pragma unroll
   for (int q = 0; q < ARN_NV; ++q) hr[q] = hi[q] = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + wv; row < cells; row += (int64_t)gridDim.x * 4) {
+  for (int64_t rw = (int64_t)blockIdx.x * 4 + wv; rw < cells; rw += (int64_t)gridDim.x * 4) {
+    const int64_t row = order ? order[rw] : rw;
     float ar[NC], ai[NC];
 #pragma unroll
     for (int g = 0; g < NC; ++g) ar[g] = ai[g] = 0.f;
@@ -330,7 +366,7 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
         for (int gp = 0; gp < NC; ++gp)
 #pragma unroll
           for (int g = 0; g < NC; ++g) {
-            const float a = v[g * NC + gp];
+            const float a = v[gp * NC + g];
             ar[g] = fmaf(a, xv[u][gp].x, ar[g]);
             ai[g] = fmaf(a, xv[u][gp].y, ai[g]);
           }
@@ -344,7 +380,7 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
         const float2 xv = t[((size_t)cc * NC + gp) * B + cl];
 #pragma unroll
         for (int g = 0; g < NC; ++g) {
-          const float a = v[g * NC + gp];
+          const float a = v[gp * NC + g];
           ar[g] = fmaf(a, xv.x, ar[g]);
           ai[g] = fmaf(a, xv.y, ai[g]);
         }
@@ -359,17 +395,16 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
       arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
     }
   }
-  arn_block_reduce(hr, hi, nv, c, live, B, part);
+  arn_block_reduce(hr, hi, nv, ln, B, part);
 }
 
 // Unfused variant (any B, any nch): w = V_j - kv with kv = P0 t from the general SpMM.
 __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const float2* __restrict__ kv,
                                                   float2* __restrict__ V, int64_t vstride, int j,
                                                   const double* __restrict__ scl, double2* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
-  const bool live = c < B;
-  const int cl = live ? c : B - 1;
+  const int wv = threadIdx.x >> 6;
+  const ArnLanes ln = arn_lanes(B);
+  const int cl = ln.live ? ln.c : B - 1;
   const float2* Vj = V + (size_t)j * vstride;
   float2* Wo = V + (size_t)(j + 1) * vstride;
   const float sj = (float)scl[(size_t)j * B + cl];
@@ -377,14 +412,15 @@ __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const flo
   double hr[ARN_NV], hi[ARN_NV];
 #pragma unroll
   for (int q = 0; q < ARN_NV; ++q) hr[q] = hi[q] = 0.0;
-  for (int64_t d = (int64_t)blockIdx.x * 4 + wv; d < rows; d += (int64_t)gridDim.x * 4) {
+  const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
+  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
     const size_t idx = (size_t)d * B + cl;
     const float2 v = Vj[idx], k = kv[idx];
     const float wr = sj * v.x - k.x, wi = sj * v.y - k.y;
-    if (live) Wo[idx] = make_float2(wr, wi);
-    arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
+    if (ln.live) Wo[idx] = make_float2(wr, wi);
+    if (ln.live) arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
   }
-  arn_block_reduce(hr, hi, nv, c, live, B, part);
+  arn_block_reduce(hr, hi, nv, ln, B, part);
 }
 
 // w -= sum_{i <= j} h_i V_i (FP64 arithmetic, FP32 storage) in basis slot j + 1, with the partial
@@ -392,10 +428,9 @@ __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const flo
 __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* __restrict__ V, int64_t vstride, int j,
                                                    const double2* __restrict__ h, const double* __restrict__ scl,
                                                    double2* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.y * 64 + lane;
-  const bool live = c < B;
-  const int cl = live ? c : B - 1;
+  const int wv = threadIdx.x >> 6;
+  const ArnLanes ln = arn_lanes(B);
+  const int cl = ln.live ? ln.c : B - 1;
   const int nv = j + 1;
   double cr[ARN_NV], ci[ARN_NV];
 #pragma unroll
@@ -411,7 +446,9 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
   double acc[ARN_NV], dummy[ARN_NV];
 #pragma unroll
   for (int q = 0; q < ARN_NV; ++q) acc[q] = dummy[q] = 0.0;
-  for (int64_t d = (int64_t)blockIdx.x * 4 + wv; d < rows; d += (int64_t)gridDim.x * 4) {
+  const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
+  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
+    if (!ln.live) continue;
     const size_t idx = (size_t)d * B + cl;
     const float2 w = Wo[idx];
     double xr = w.x, xi = w.y;
@@ -424,10 +461,10 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
       }
     }
     const float2 o = make_float2((float)xr, (float)xi);
-    if (live) Wo[idx] = o;
+    Wo[idx] = o;
     acc[0] += (double)o.x * o.x + (double)o.y * o.y;
   }
-  arn_block_reduce(acc, dummy, 1, c, live, B, part);
+  arn_block_reduce(acc, dummy, 1, ln, B, part);
 }
 
 __device__ __forceinline__ double wsum64(double v) {
@@ -475,9 +512,10 @@ int arn_blocks(int64_t rows, int B, int nblk) { return (int)arn_grid(rows, B, nb
 
 template <int NC>
 static void spmm_arn_launch(dim3 grid, hipStream_t s, int64_t cells, int B, const int64_t* rowptr, const int32_t* col,
-                            const float* val, const float2* t, float2* V, int64_t vstride, int j, const double* scl,
-                            double2* part) {
-  hipLaunchKernelGGL(k_spmm_arn<NC>, grid, dim3(256), 0, s, cells, B, rowptr, col, val, t, V, vstride, j, scl, part);
+                            const float* val, const int32_t* order, const float2* t, float2* V, int64_t vstride, int j,
+                            const double* scl, double2* part) {
+  hipLaunchKernelGGL(k_spmm_arn<NC>, grid, dim3(256), 0, s, cells, B, rowptr, col, val, order, t, V, vstride, j, scl,
+                     part);
 }
 
 hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2* kv_scratch, hipStream_t s) {
@@ -487,17 +525,17 @@ hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2*
   if (a.B >= 16 && a.nch <= 4) {
     const dim3 grid = arn_grid(a.cells, a.B, a.nblk);
     switch (a.nch) {
-      case 1: spmm_arn_launch<1>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
-      case 2: spmm_arn_launch<2>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
-      case 3: spmm_arn_launch<3>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
-      default: spmm_arn_launch<4>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      case 1: spmm_arn_launch<1>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, a.order, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      case 2: spmm_arn_launch<2>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, a.order, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      case 3: spmm_arn_launch<3>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, a.order, t, a.V, a.vstride, a.j, a.scl, a.part); break;
+      default: spmm_arn_launch<4>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, a.order, t, a.V, a.vstride, a.j, a.scl, a.part); break;
     }
     const int nb = (int)grid.x;
     hipLaunchKernelGGL(k_arn_finish, dim3(((a.j + 1) * a.B + 3) / 4), dim3(256), 0, s, nb, a.B, a.j + 1, a.part, a.scl,
                        a.H + (size_t)a.j * (a.m + 1) * a.B, nullptr, 0);
   } else {
     if (!kv_scratch) return hipErrorInvalidValue;
-    hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s);
+    hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s, 0, -1, a.order);
     if (e != hipSuccess) return e;
     const dim3 grid = arn_grid(rows, a.B, a.nblk);
     hipLaunchKernelGGL(k_sub_dots, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl, a.part);
@@ -549,31 +587,26 @@ hipError_t launch_capture64(int M, int nch, int B, int nfin, const double* O, co
 }
 
 // FP64 residual -> squared norms per column (FP64)
-__global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const double2* __restrict__ x, int64_t rows_per_blk,
+__global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const double2* __restrict__ x,
                                                    double2* __restrict__ part) {
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = min(rows, r0 + rows_per_blk);
-  for (int cb = 0; cb < B; cb += 64) {
-    const int c = cb + lane;
-    double s2 = 0.0;
-    if (c < B)
-      for (int64_t d = r0 + wv; d < r1; d += 4) {
-        const double2 v = x[d * B + c];
-        s2 += v.x * v.x + v.y * v.y;
-      }
-    red[wv][lane] = s2;
-    __syncthreads();
-    if (wv == 0 && c < B) part[(size_t)blockIdx.x * B + c] = make_double2(red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane], 0.0);
-    __syncthreads();
-  }
+  const int wv = threadIdx.x >> 6;
+  const ArnLanes ln = arn_lanes(B);
+  double acc[ARN_NV], dummy[ARN_NV];
+#pragma unroll
+  for (int q = 0; q < ARN_NV; ++q) acc[q] = dummy[q] = 0.0;
+  const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
+  if (ln.live)
+    for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
+      const double2 v = x[(size_t)d * B + ln.c];
+      acc[0] += v.x * v.x + v.y * v.y;
+    }
+  arn_block_reduce(acc, dummy, 1, ln, B, part);
 }
 
 hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s) {
-  const int64_t rpb = (rows + nblk - 1) / nblk;
-  hipLaunchKernelGGL(k_norm2_f64, dim3(nblk), dim3(256), 0, s, rows, B, x, rpb, part);
-  hipLaunchKernelGGL(k_arn_finish, dim3((B + 3) / 4), dim3(256), 0, s, nblk, B, 1, part, nullptr, out, nullptr, 0);
+  const dim3 grid = arn_grid(rows, B, nblk);
+  hipLaunchKernelGGL(k_norm2_f64, grid, dim3(256), 0, s, rows, B, x, part);
+  hipLaunchKernelGGL(k_arn_finish, dim3((B + 3) / 4), dim3(256), 0, s, (int)grid.x, B, 1, part, nullptr, out, nullptr, 0);
   return hipGetLastError();
 }
 

@@ -134,13 +134,16 @@ hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, cons
 hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st);
 // Block-CSR products for any storage/vector precision: lanes over columns when all B >= 16
 // columns are requested, else lanes over blocks with a wave reduction.
+// order: the block rows in the sequence the wavefronts take them (longest first), or nullptr
 hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
-                           const double2* x, double2* y, hipStream_t s, int cb0 = 0, int cb1 = -1);
+                           const double2* x, double2* y, hipStream_t s, int cb0 = 0, int cb1 = -1,
+                           const int32_t* order = nullptr);
 hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
-                           const float2* x, float2* y, hipStream_t s, int cb0 = 0, int cb1 = -1);
+                           const float2* x, float2* y, hipStream_t s, int cb0 = 0, int cb1 = -1,
+                           const int32_t* order = nullptr);
 hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
                                  const float* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
-                                 int cb1 = -1);
+                                 int cb1 = -1, const int32_t* order = nullptr);
 // zero the columns [cb0, cb1) of a rows x B array
 hipError_t launch_fill0_cols(double2* p, int64_t rows, int B, int cb0, int cb1, hipStream_t st);
 
@@ -203,6 +206,7 @@ struct ArnoldiArgs {
   const int64_t* rowptr;
   const int32_t* col;
   const float* val;     // FP32 P0 blocks
+  const int32_t* order; // row sequence (longest first) or nullptr
   float2* V;            // basis slots [m + 1][rows][B]
   int64_t vstride;
   double* scl;          // [m + 1][B]

@@ -52,6 +52,7 @@ struct wp_lattice {
   int64_t blocks = 0;
   DBuf<int64_t> d_rowptr;
   DBuf<int32_t> d_col;
+  DBuf<int32_t> d_order;   // block rows by decreasing length (ties by index): SpMV work order
   DBuf<double> d_val64;
   DBuf<float> d_val32;
   wp_perm_stats stats{};
