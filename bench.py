@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched-energy and serving measurements")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--sweep", action="store_true", help="also time the s-wave P0 build for M = N in 40..400")
+    ap.add_argument("--only", choices=["batched", "serving", "pw150"], default=None,
+                    help="run only this extra section (no headline step); for profiling runs")
     return ap.parse_args()
 
 
@@ -96,23 +98,106 @@ def batched_energies_section(wp, torch, L, reps=3):
     return out
 
 
-def serving_section(wp, torch, lats, seconds):
-    """Poisson stream (200 req/s, seed 2026) over the resident lattices, continuous batching."""
+SERVING_LATTICES = (   # M = N, two_J, j_max, s-wave only  (channel counts 2, 2, 18, 10)
+    (60, 1, 1, True), (100, 1, 1, True), (150, 1, 2, False), (200, 1, 1, False))
+SERVING_MODES = (("fp64", dict(tol=3e-7, accept=1e-7, refine_every=0)),
+                 ("mixed_split", dict(tol=1e-5, accept=1e-5, refine_every=8)))
+
+
+def serving_section(wp, torch, V_R, seconds, lats_by_key=None):
+    """Poisson stream (200 req/s, seed 2026) over four resident lattices, continuous batching, once
+    with FP64 batches and once with split-BF16 mixed batches, each at a stop tolerance that keeps
+    the amplitude error below 1e-6; afterwards every served amplitude is compared with a converged
+    FP64 solve of the same energy (outside the timing)."""
     from paper_1404_5253_amd.serve import BatchBackend, run_stream
-    backs = []
-    for L in lats:
-        st = torch.cuda.Stream()
-        backs.append(BatchBackend(L, slots=32, hbm_budget=8 << 30, terms=4,
-                                  stream=wp.C.c_void_p(st.cuda_stream)))
-        backs[-1]._torch_stream = st
+    lats = []
+    for (M, two_J, j_max, sw) in SERVING_LATTICES:
+        L = (lats_by_key or {}).get((M, two_J, j_max, sw))
+        if L is None:
+            L = wp.Lattice(M, M, two_J=two_J, j_max=j_max, swave_only=sw)
+            L.pseudostates(kind="mt", V_R=V_R)
+            L.build_perm("fp64")
+        lats.append(L)
     reqs = workloads.serving_requests(len(lats), rate=200.0, duration=seconds)
-    done, stats = run_stream(backs, reqs)
-    for b in backs:
-        b.close()
-    stats["requests"] = len(reqs)
-    stats["accepted"] = sum(1 for r in done if r.result.get("accepted", True))
-    stats["lattices"] = [f"M=N={L.M}, {L.nch} ch" for L in lats]
-    return stats
+    out = {"lattices": [f"M=N={M}, {L.nch} ch" for (M, *_), L in zip(SERVING_LATTICES, lats)], "requests": len(reqs)}
+    served = {}
+    for mode, kw in SERVING_MODES:
+        backs = []
+        for L in lats:
+            st = torch.cuda.Stream()
+            b = BatchBackend(L, slots=32, hbm_budget=16 << 30, terms=8, stream=wp.C.c_void_p(st.cuda_stream),
+                             mode=mode, max_iter=400, **kw)
+            b._torch_stream = st
+            backs.append(b)
+        done, stats = run_stream(backs, reqs)
+        for b in backs:
+            b.close()
+        stats["accepted"] = sum(1 for r in done if r.result.get("accepted", True))
+        out[mode] = stats
+        served[mode] = {r.rid: (r.lattice, r.E_lab, r.result["A"]) for r in done}
+    # accuracy of every served amplitude against a converged FP64 solve (batched per lattice)
+    for mode in served:
+        worst = 0.0
+        for li, L in enumerate(lats):
+            items = [(rid, E, A) for rid, (l, E, A) in served[mode].items() if l == li]
+            for k0 in range(0, len(items), 64):
+                chunk = items[k0:k0 + 64]
+                ref = L.solve([E for _, E, _ in chunk], "fp64", tol=1e-12, max_iter=400, allow_noconv=True)
+                for k, (_, _, A) in enumerate(chunk):
+                    worst = max(worst, float(np.max(np.abs(A - ref.amplitude(k)["A"]))))
+        out[mode]["max_abs_dA_vs_converged_fp64"] = worst
+    out["speedup_mixed_split_over_fp64_solves_per_s"] = out["mixed_split"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    return out
+
+
+def pw150_section(wp, torch, V_R, reps=3):
+    """18-channel J = 1/2+ lattice (j <= 2), M = N = 150: P0 build rate, the FP64 SpMV against the
+    HBM roofline, and the FP64 and mixed solves of E_lab = 3 and 22.7 MeV (one call each)."""
+    wl = workloads.WORKLOADS["pw_mt_150"]
+    sysd = wl["systems"][0]
+    M = wl["M"]
+    L = wp.Lattice(M, M, two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"], n_x=wl["n_x"],
+                   n_phi=wl["n_phi"])
+    L.pseudostates(kind="mt", V_R=V_R)
+    L.build_perm("fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = L.build_perm("fp64")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = dict(channels=L.nch, P_elements=st["nnz"], P_blocks=st["blocks"], P_bytes=st["bytes"],
+               build_ms=dt * 1e3, build_device_ms=st["device_ms"], P_elements_per_s=st["nnz"] / dt)
+    Es = wl["E_lab"]
+    amps = {}
+    for mode, tol in (("fp64", 1e-10), ("mixed", 1e-8), ("mixed_split", 1e-8)):
+        L.solve(Es, mode, tol=tol, max_iter=400, allow_noconv=True)
+        torch.cuda.synchronize()
+        wp.wp_profile_reset()
+        wp.wp_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sol = L.solve(Es, mode, tol=tol, max_iter=400, allow_noconv=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        wp.wp_profile_enable(False)
+        prof = wp.wp_profile_read()
+        amps[mode] = np.array([sol.amplitude(k)["A"] for k in range(len(Es))])
+        out[f"ms_per_call_{mode}"] = dt * 1e3
+        out[f"solves_per_s_{mode}"] = len(Es) / dt
+        out[f"kernels_ms_per_call_{mode}"] = {k: round(v[1] / reps, 3) for k, v in prof.items()}
+        if mode == "fp64":
+            n, ms = prof["spmv64"]
+            us = ms / n * 1e3
+            byts = st["bytes"] + 2 * 16 * M * M * L.nch * len(Es) * 2
+            out["spmv64_roofline"] = dict(bound="hbm", achieved=byts / us / 1e3, peak=HBM_PEAK_GBS, unit="GB/s",
+                                          frac=byts / us / 1e3 / HBM_PEAK_GBS, avg_us=us, bytes_per_launch=byts)
+    for mode in ("mixed", "mixed_split"):
+        out[f"max_abs_dA_{mode}_vs_fp64"] = float(np.max(np.abs(amps[mode] - amps["fp64"])))
+        out[f"speedup_{mode}_over_fp64"] = out[f"solves_per_s_{mode}"] / out["solves_per_s_fp64"]
+    S = L.solve([Es[0]], "fp64", tol=1e-10, max_iter=400).amplitude(0)["S"]
+    out["unitarity_defect_3MeV"] = float(np.max(np.abs(S @ S.conj().T - np.eye(len(S)))))
+    return out
 
 
 def sweep_section(wp, torch, V_R, sizes=(40, 100, 200, 400), reps=3):
@@ -193,6 +278,16 @@ def main():
                        n_x=wl["n_x"], n_phi=wl["n_phi"])
         L.pseudostates(kind="mt", V_R=V_R)
         lats.append(L)
+    if args.only:
+        if args.only == "pw150":
+            res = pw150_section(wp, torch, V_R)
+        else:
+            for L in lats:
+                L.build_perm("fp64")
+            res = (batched_energies_section(wp, torch, lats[0]) if args.only == "batched"
+                   else serving_section(wp, torch, V_R, args.serve_seconds, {(M, 1, 1, True): lats[0]}))
+        print(json.dumps({"section": args.only, "result": res}))
+        return
 
     def step(times):
         for L in lats:
@@ -210,8 +305,6 @@ def main():
 
     for _ in range(args.warmup):
         step(dict(build=0.0, solve=0.0, amps=[]))
-    wp.wp_profile_reset()
-    wp.wp_profile_enable(True)
     times = dict(build=0.0, solve=0.0, amps=[])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -219,6 +312,13 @@ def main():
         step(times)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the same K steps again with HIP events recorded around every launch (on its stream): the
+    # per-kernel durations for the roofline (the events' host cost is kept out of the timing above)
+    wp.wp_profile_reset()
+    wp.wp_profile_enable(True)
+    for _ in range(args.steps):
+        step(dict(build=0.0, solve=0.0, amps=[]))
+    torch.cuda.synchronize()
     wp.wp_profile_enable(False)
     prof = wp.wp_profile_read()
     K = args.steps
@@ -277,7 +377,8 @@ def main():
     }
     if not args.no_extras:
         out["batched_64_energies"] = batched_energies_section(wp, torch, lats[0])
-        out["serving"] = serving_section(wp, torch, lats, args.serve_seconds)
+        out["serving"] = serving_section(wp, torch, V_R, args.serve_seconds, {(M, 1, 1, True): lats[0]})
+        out["pw_mt_150"] = pw150_section(wp, torch, V_R)
     if args.sweep:
         out["swave_sweep"] = sweep_section(wp, torch, V_R)
     if not args.no_cpu_baseline:

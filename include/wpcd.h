@@ -215,10 +215,13 @@ void wp_solution_free(wp_solution* sol);
  * Continuous batching (serving): up to max_slots energies of one lattice share every kernel
  * launch of a step. faddeev_batch_admit takes a free slot (or WP_EBUDGET when none is free or
  * the slot's vectors would exceed hbm_budget bytes); faddeev_batch_step advances every live
- * slot by `terms` Neumann terms (one batched launch sequence) and reports the slots whose
- * Pade estimate was accepted; faddeev_batch_take moves a finished slot's result out and frees
- * the slot. Each slot's arithmetic is independent of the other slots (column-wise kernels,
- * fixed reduction order), so a result does not depend on its batch-mates.
+ * slot and reports the slots that finished; faddeev_batch_take moves a finished slot's result
+ * out and frees the slot. opts->mode selects the path: WP_SOLVE_FP64 advances every slot by
+ * `terms` Neumann terms (a slot finishes when its Pade estimate is accepted); the mixed modes
+ * run one refinement cycle (FP64 residual, refine_every mixed-precision Arnoldi steps,
+ * correction) per step whatever `terms` is, a slot finishing when its error estimate is <= tol.
+ * Each slot's arithmetic is independent of the other slots (column-wise kernels, fixed
+ * reduction order), so a result does not depend on its batch-mates.
  */
 wp_status faddeev_batch_create(wp_lattice* lat, int max_slots, size_t hbm_budget,
                                const wp_solve_opts* opts, wp_batch** out);

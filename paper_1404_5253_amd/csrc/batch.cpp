@@ -3,10 +3,15 @@
 // A batch owns max_slots energy slots; slot s uses the columns s*n_open .. s*n_open + n_open - 1
 // of the solve vectors (one column per open initial channel). Admission computes the slot's G1
 // on the device (FP64) straight into the slot's columns and builds the slot's right-hand side
-// b = P0 (v O^T) e0 with column-range kernels, so live slots are not disturbed. A step advances
-// every column by `terms` Neumann terms with the same launches as faddeev_solve. The kernels
-// are column-wise with a fixed reduction order, so a slot's numbers do not depend on which
-// other slots are live. Finished or free slots get G1 = 0, which keeps their vectors at zero.
+// b = P0 (v O^T) e0 with column-range kernels, so live slots are not disturbed.
+//   FP64 batches: a step advances every column by `terms` Neumann terms with the same launches as
+//     faddeev_solve; finished or free slots get G1 = 0, which keeps their vectors at zero.
+//   Mixed batches: a step is one refinement cycle (FP64 residual, refine_every Arnoldi steps in
+//     mixed precision, correction, captured U) over every column; a new slot starts from y = 0,
+//     so its first residual is b exactly, and finished slots take no correction.
+// The kernels are column-wise with a fixed reduction order, so a slot's FP64 numbers do not
+// depend on which other slots are live; in a mixed batch the block-level partial sums of the
+// Gram-Schmidt products are also per column, so the same holds there.
 #include <algorithm>
 #include <memory>
 
@@ -15,17 +20,24 @@
 struct wp_batch {
   wp_lattice* L = nullptr;
   wp_solve_opts o{};
-  int slots = 0, nfin = 0, B = 0, max_terms = 0;
+  bool mixed = false;
+  int slots = 0, nfin = 0, B = 0, max_terms = 0, m = 0;
   int64_t D = 0;
+  // FP64 path
   DBuf<double2> dG, dy, dt, ds, dacap;
-  DBuf<int> dj0, dg0, dfin;
-  DBuf<double> dE;   // three-body energy of each slot
+  DBuf<int> dj0, dfin;
+  // mixed path
+  MixedWork mw;
+  // both
+  DBuf<int> dg0;
+  DBuf<double> dE;    // three-body energy of each slot
   DBuf<int64_t> g1w;  // G1 work list for one energy
   std::vector<int> j0, g0;
   struct Slot {
-    bool live = false, done = false;
+    bool live = false, done = false, fresh = true;
     EnergyResult r;
     std::vector<ColState> cs;
+    std::vector<MixedCol> mc;
   };
   std::vector<Slot> s;
   std::vector<double2> hcap;
@@ -36,37 +48,55 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   if (!L || !o || !out || max_slots < 1) return fail(WP_EINVAL, "faddeev_batch_create: bad argument");
   *out = nullptr;
   if (!L->pseudo || !L->have_P) return fail(WP_ENOTREADY, "lattice needs pseudostates and P0");
-  if (o->mode != WP_SOLVE_FP64) return fail(WP_EINVAL, "batches run the FP64 path");
+  if (o->mode != WP_SOLVE_FP64 && o->mode != WP_SOLVE_MIXED && o->mode != WP_SOLVE_MIXED_SPLIT)
+    return fail(WP_EINVAL, "unknown solve mode");
   if (!L->d_val64.p) return fail(WP_ENOTREADY, "batch needs P0 built with WP_P_FP64");
   if (o->tol <= 0 || o->accept <= 0 || o->max_iter < 4) return fail(WP_EINVAL, "bad solve options");
   if (wp_status st = upload_waves(L)) return st;
+  if (wp_status st = ensure_order(L)) return st;
   std::unique_ptr<wp_batch> b(new wp_batch());
   b->L = L;
   b->o = *o;
+  b->mixed = o->mode != WP_SOLVE_FP64;
   b->nfin = (int)L->opens.size();
   b->D = (int64_t)L->M * L->N * L->nch;
   b->max_terms = 64;
-  const size_t per_slot = (size_t)b->nfin * (4 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
+  b->m = std::max(2, std::min(ARN_NV, o->refine_every > 0 ? o->refine_every : 8));
+  const size_t per_slot =
+      b->mixed ? (size_t)b->nfin * mixed_bytes_per_column(L, b->m)
+               : (size_t)b->nfin * (4 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
   int cap = (int)std::min<size_t>((size_t)max_slots, hbm_budget / std::max<size_t>(per_slot, 1));
   if (cap < 1) return fail(WP_EBUDGET, "hbm_budget smaller than one slot");
   b->slots = cap;
   b->B = cap * b->nfin;
   const int B = b->B;
   DevAlloc* al = &L->al;
-  if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
-      !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
-      !b->dg0.make(al, B) || !b->dfin.make(al, b->nfin) || !b->dE.make(al, cap) || !g1_work(L, 1, b->g1w))
+  if (!b->dg0.make(al, B) || !b->dE.make(al, cap) || !g1_work(L, 1, b->g1w))
     return fail(WP_ENOMEM, "device allocation (batch)");
-  for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
   b->j0.assign(B, 0);
   b->g0.assign(B, 0);
   for (int c = 0; c < B; ++c) b->g0[c] = L->opens[c % b->nfin];
-  HIPCHECK(hipMemcpy(b->dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(b->dg0.p, b->g0.data(), B * sizeof(int), hipMemcpyHostToDevice));
-  HIPCHECK(hipMemcpy(b->dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
+  if (b->mixed) {
+    if (wp_status st = ensure_mixed(L, nullptr)) return st;
+    if (wp_status st = b->mw.make(L, B, b->m, o->mode == WP_SOLVE_MIXED_SPLIT)) return st;
+    MixedWork& w = b->mw;
+    for (auto* p : {&w.dG64, &w.db, &w.dy}) HIPCHECK(hipMemset(p->p, 0, w.DB * sizeof(double2)));
+    HIPCHECK(hipMemset(w.dG32.p, 0, w.DB * sizeof(float2)));
+    HIPCHECK(hipMemcpy(w.dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(w.dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
+  } else {
+    if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
+        !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
+        !b->dfin.make(al, b->nfin))
+      return fail(WP_ENOMEM, "device allocation (batch)");
+    for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
+    HIPCHECK(hipMemcpy(b->dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
+    b->hcap.resize((size_t)b->max_terms * B * b->nfin);
+  }
   HIPCHECK(hipDeviceSynchronize());
   b->s.resize(cap);
-  b->hcap.resize((size_t)b->max_terms * B * b->nfin);
   *out = b.release();
   return WP_OK;
 }
@@ -93,24 +123,94 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   auto& S = b->s[sl];
   S = wp_batch::Slot();
   if (!kinematics(L, E_lab, S.r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
-  const int nf = b->nfin, c0 = sl * nf;
+  const int nf = b->nfin, c0 = sl * nf, B = b->B;
+  const int64_t R = (int64_t)L->M * L->N;
   hipStream_t st = nullptr;
-  HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
-  WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, b->B, b->dG.p, b->g1w), st));
   for (int f = 0; f < nf; ++f) b->j0[c0 + f] = S.r.j0;
-  HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, b->B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
-                             c0 + nf));
-  HIPCHECK(launch_spmv_f64((int64_t)L->M * L->N, L->nch, b->B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
-                         b->dy.p, st, c0, c0 + nf, L->d_order.p));
-  HIPCHECK(hipStreamSynchronize(st));
-  S.cs.resize(nf);
-  for (auto& c : S.cs) {
-    c.w.resize(nf);
-    c.S.assign(nf, cplx(0, 0));
+  HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
+  if (b->mixed) {
+    MixedWork& w = b->mw;
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, w.dG64.p, b->g1w), st));
+    HIPCHECK(launch_cvt_d2f_cols(b->D, B, c0, c0 + nf, w.dG64.p, w.dG32.p, st));
+    HIPCHECK(hipMemcpyAsync(w.dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0,
+                               c0 + nf));
+    HIPCHECK(launch_spmv_f32v_f64x(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, st, c0,
+                                   c0 + nf, L->d_order.p));
+    HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c0 + nf, st));
+    S.mc.assign(nf, MixedCol());
+  } else {
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, b->dG.p, b->g1w), st));
+    HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
+                               c0 + nf));
+    HIPCHECK(launch_spmv_f64(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st, c0, c0 + nf,
+                             L->d_order.p));
+    S.cs.resize(nf);
+    for (auto& c : S.cs) {
+      c.w.resize(nf);
+      c.S.assign(nf, cplx(0, 0));
+    }
   }
+  HIPCHECK(hipStreamSynchronize(st));
   S.live = true;
   *slot = sl;
+  return WP_OK;
+}
+
+static void finish_slot(wp_batch* b, wp_batch::Slot& S) {
+  const int nf = b->nfin;
+  S.done = true;
+  for (int f0 = 0; f0 < nf; ++f0) {
+    if (b->mixed) {
+      const MixedCol& c = S.mc[f0];
+      for (int f = 0; f < nf; ++f) S.r.U[f * nf + f0] = c.U.empty() ? cplx(0, 0) : c.U[f];
+      S.r.err[f0] = c.err;
+      S.r.iters[f0] = c.iters;
+      S.r.ok &= c.err <= b->o.accept;
+    } else {
+      ColState& cs = S.cs[f0];
+      const std::vector<cplx>& est = cs.best.empty() ? cs.last : cs.best;
+      for (int f = 0; f < nf; ++f) S.r.U[f * nf + f0] = est[f];
+      S.r.err[f0] = cs.err;
+      S.r.iters[f0] = cs.n;
+      S.r.ok &= cs.ok;
+    }
+  }
+}
+
+static wp_status step_mixed(wp_batch* b, hipStream_t st, int* n_done, int* done_slots) {
+  const int nf = b->nfin, B = b->B, m = b->m;
+  const double tol = std::max(b->o.tol, 1e-15);
+  std::vector<char> active(B, 0);
+  bool y_zero = true;
+  for (int sl = 0; sl < b->slots; ++sl) {
+    const auto& S = b->s[sl];
+    if (!S.live || S.done) continue;
+    for (int f = 0; f < nf; ++f) active[sl * nf + f] = S.mc[f].err > tol ? 1 : 0;
+    y_zero &= S.fresh;
+  }
+  if (wp_status s = mixed_cycle(b->mw, st, y_zero, active)) return s;
+  for (int sl = 0; sl < b->slots; ++sl) {
+    auto& S = b->s[sl];
+    if (!S.live || S.done) continue;
+    bool all = true;
+    for (int f0 = 0; f0 < nf; ++f0) {
+      MixedCol& c = S.mc[f0];
+      const int col = sl * nf + f0;
+      if (active[col]) {
+        c.iters += m + (y_zero ? 0 : 1);
+        c.update(&b->mw.hc[(size_t)col * nf], nf, tol);
+      }
+      all &= c.err <= tol || c.iters >= b->o.max_iter;
+    }
+    S.fresh = false;
+    if (all) {
+      finish_slot(b, S);
+      if (done_slots) done_slots[*n_done] = sl;
+      ++*n_done;
+    }
+  }
   return WP_OK;
 }
 
@@ -124,6 +224,7 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
   bool any = false;
   for (auto& s : b->s) any |= (s.live && !s.done);
   if (!any) return WP_OK;
+  if (b->mixed) return step_mixed(b, st, n_done, done_slots);
   for (int t = 0; t < terms; ++t) {
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
     WP_LAUNCH("step64", st, launch_step64(ro, L->d_W.p, b->dy.p, b->ds.p, st));
@@ -157,15 +258,7 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
       all &= cs.done;
     }
     if (all) {
-      S.done = true;
-      for (int f0 = 0; f0 < nf; ++f0) {
-        ColState& cs = S.cs[f0];
-        const std::vector<cplx>& est = cs.best.empty() ? cs.last : cs.best;
-        for (int f = 0; f < nf; ++f) S.r.U[f * nf + f0] = est[f];
-        S.r.err[f0] = cs.err;
-        S.r.iters[f0] = cs.n;
-        S.r.ok &= cs.ok;
-      }
+      finish_slot(b, S);
       // finished: G1 = 0 on the slot's columns keeps its vectors at zero until it is reused
       HIPCHECK(launch_fill0_cols(b->dG.p, b->D, b->B, sl * nf, sl * nf + nf, st));
       if (done_slots) done_slots[*n_done] = sl;
@@ -187,7 +280,7 @@ extern "C" wp_status faddeev_batch_take(wp_batch* b, int slot, wp_solution** out
   const bool ok = S.r.ok;
   S = wp_batch::Slot();
   *out = sol.release();
-  return ok ? WP_OK : fail(WP_ENOCONV, "slot's Pade summation was not accepted (result still returned)");
+  return ok ? WP_OK : fail(WP_ENOCONV, "slot's solve was not accepted (result still returned)");
 }
 
 extern "C" void faddeev_batch_free(wp_batch* b) { delete b; }

@@ -621,18 +621,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   std::swap(L->d_rowptr.p, rowptr.p);
   std::swap(L->d_rowptr.n, rowptr.n);
   L->d_rowptr.al = &L->al;
-  {
-    // SpMV work order: block rows by decreasing length, ties by index, so that the longest rows
-    // start first and do not trail at the end of a launch
-    std::vector<int64_t> rp(R + 1);
-    HIPCHECK(hipMemcpy(rp.data(), L->d_rowptr.p, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> ord(R);
-    for (int64_t r = 0; r < R; ++r) ord[r] = (int32_t)r;
-    std::stable_sort(ord.begin(), ord.end(),
-                     [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
-    if (!L->d_order.make(&L->al, R)) return fail(WP_ENOMEM, "device allocation (row order)");
-    HIPCHECK(hipMemcpy(L->d_order.p, ord.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
-  }
+  L->d_order.reset();   // the SpMV row order is derived from this P0 at its first use
   L->blocks = nblk;
   L->prec = precision;
   L->have_P = true;
@@ -672,6 +661,25 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
 
 // ------------------------------------------------------------------ solve (FP64 path)
 
+// SpMV work order of the resident P0 (made once per build, at the first solve): block rows by
+// decreasing length, ties by index, so that the longest rows start first and do not trail at the
+// end of a launch (rows hold 0 to ~10x the median number of blocks); the measured alternative,
+// lattice order in one contiguous chunk per XCD, was slower.
+wp_status wpcd::ensure_order(wp_lattice* L) {
+  if (L->d_order.p || !L->have_P) return WP_OK;
+  const int64_t R = (int64_t)L->M * L->N;
+  std::vector<int64_t> rp(R + 1);
+  HIPCHECK(hipMemcpy(rp.data(), L->d_rowptr.p, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+  std::vector<int32_t> ord(R);
+  for (int64_t r = 0; r < R; ++r) ord[r] = (int32_t)r;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+  if (!L->d_order.make(&L->al, R)) return fail(WP_ENOMEM, "device allocation (row order)");
+  HIPCHECK(hipMemcpy(L->d_order.p, ord.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
+  return WP_OK;
+}
+
+
 
 static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                             wp_solution* sol) {
@@ -697,6 +705,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const int max_iter = std::max(4, std::min(1000, o.max_iter));
   const int chunk = 8;
   if (wp_status us = upload_waves(L)) return us;
+  if (wp_status so = ensure_order(L)) return so;
   DBuf<double2> dG, dy, dt, ds, dacap;
   DBuf<int> dj0, dg0, dfin;
   DBuf<double> dE;
@@ -720,22 +729,88 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
     c.w.resize(nfin);
     c.S.assign(nfin, cplx(0, 0));
   }
-  std::vector<double2> hcap((size_t)chunk * B * nfin);
-  int n = 0;
-  bool all_done = false;
-  while (n < max_iter && !all_done) {
-    int T = std::min(chunk, max_iter - n);
-    for (int t = 0; t < T; ++t) {
-      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin, (int64_t)(n + t) * B * nfin};
-      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
-      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, L->d_order.p));
+  // Chunks of `chunk` iterations; the captured terms of a chunk go to pinned host memory. For
+  // small batches (iterations of a few microseconds) chunk k + 1 is enqueued before chunk k is
+  // read, so the device does not wait for the Pade check, at the price of at most one chunk
+  // past convergence; large batches read each chunk before the next is enqueued.
+  const size_t per_chunk = (size_t)chunk * B * nfin;
+  const bool overlap = D * B <= ((int64_t)1 << 20);
+  std::unique_lock<std::mutex> pin_lock(L->pin_mu, std::try_to_lock);
+  double2* own = nullptr;
+  double2* pin = nullptr;
+  if (pin_lock.owns_lock()) {
+    if (L->pin_cap < 2 * per_chunk) {
+      if (L->pin) (void)hipHostFree(L->pin);
+      L->pin = nullptr;
+      L->pin_cap = 0;
+      HIPCHECK(hipHostMalloc((void**)&L->pin, 2 * per_chunk * sizeof(double2), hipHostMallocDefault));
+      L->pin_cap = 2 * per_chunk;
     }
-    HIPCHECK(hipMemcpyAsync(hcap.data(), dacap.p + (size_t)n * B * nfin, (size_t)T * B * nfin * sizeof(double2),
-                            hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    all_done = true;
+    pin = L->pin;
+  } else {   // another call on this lattice holds the shared buffer
+    HIPCHECK(hipHostMalloc((void**)&own, 2 * per_chunk * sizeof(double2), hipHostMallocDefault));
+    pin = own;
+  }
+  struct PinGuard {   // the stream drains before the staging buffer is released (also on errors)
+    double2* own;
+    hipStream_t s;
+    ~PinGuard() {
+      (void)hipStreamSynchronize(s);
+      if (own) (void)hipHostFree(own);
+    }
+  } pin_guard{own, s};
+  hipEvent_t ev[2];
+  HIPCHECK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  HIPCHECK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+  } ev_guard{ev};
+  int launched = 0;   // iterations enqueued
+  int T_of[2] = {0, 0};
+  auto enqueue = [&](int slot) -> wp_status {
+    const int T = std::min(chunk, max_iter - launched);
+    for (int t = 0; t < T; ++t) {
+      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin,
+                 (int64_t)(launched + t) * B * nfin};
+      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
+      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1,
+                                             L->d_order.p));
+    }
+    HIPCHECK(hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)launched * B * nfin,
+                            (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipEventRecord(ev[slot], s));
+    T_of[slot] = T;
+    launched += T;
+    return WP_OK;
+  };
+  int pending = -1;   // slot of a chunk enqueued and not yet read
+  if (overlap) {
+    if (wp_status st0 = enqueue(0)) return st0;
+    pending = 0;
+  }
+  for (int k = 0;; ++k) {
+    int cur;
+    if (overlap) {
+      cur = pending;
+      pending = -1;
+      if (launched < max_iter) {
+        if (wp_status st1 = enqueue(cur ^ 1)) return st1;   // runs while chunk `cur` is read
+        pending = cur ^ 1;
+      }
+    } else {
+      if (launched >= max_iter) break;
+      cur = k & 1;
+      if (wp_status st1 = enqueue(cur)) return st1;
+    }
+    HIPCHECK(hipEventSynchronize(ev[cur]));
+    const double2* hcap = pin + cur * per_chunk;
+    bool all_done = true;
     for (int c = 0; c < B; ++c) {
-      for (int t = 0; t < T && !cs[c].done; ++t) {
+      for (int t = 0; t < T_of[cur] && !cs[c].done; ++t) {
         std::vector<cplx> a(nfin);
         for (int f = 0; f < nfin; ++f) {
           double2 v = hcap[((size_t)t * B + c) * nfin + f];
@@ -745,8 +820,9 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
       }
       all_done &= cs[c].done;
     }
-    n += T;
+    if (all_done || (overlap && pending < 0)) break;
   }
+  HIPCHECK(hipStreamSynchronize(s));
   bool allok = true;
   for (int e = 0; e < nE; ++e) {
     EnergyResult& r = sol->res[e];
@@ -767,248 +843,6 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   return allok ? WP_OK : fail(WP_ENOCONV, "Pade summation did not reach the accepted accuracy for some energy");
 }
 
-
-// ------------------------------------------------------------------ solve (mixed path)
-
-static uint16_t host_bf16(double d) {
-  float f = (float)d;
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
-  if (wp_status st = upload_waves(L)) return st;
-  const int M = L->M;
-  if (!L->d_Ob.p) {
-    // bf16 copies of O and v O^T (hi) and of their rounding remainders (lo), padded to Mp
-    const int Mp = (M + 15) / 16 * 16;
-    const size_t MM = (size_t)Mp * Mp;
-    const size_t n = MM * L->waves.size();
-    std::vector<uint16_t> Oh(n, 0), Ol(n, 0), Wh(n, 0), Wl(n, 0);
-    auto split = [](double d, uint16_t& hi, uint16_t& lo) {
-      hi = host_bf16(d);
-      uint32_t u = (uint32_t)hi << 16;
-      float f;
-      std::memcpy(&f, &u, 4);
-      lo = host_bf16((double)((float)d - f));
-    };
-    for (size_t w = 0; w < L->waves.size(); ++w)
-      for (int r = 0; r < M; ++r)
-        for (int c = 0; c < M; ++c) {
-          const size_t k = w * MM + (size_t)r * Mp + c;
-          split(L->waves[w].O[(size_t)r * M + c], Oh[k], Ol[k]);
-          split(L->waves[w].W[(size_t)r * M + c], Wh[k], Wl[k]);
-        }
-    if (!L->d_Ob.make(&L->al, n) || !L->d_Wb.make(&L->al, n) || !L->d_Ob_lo.make(&L->al, n) ||
-        !L->d_Wb_lo.make(&L->al, n))
-      return fail(WP_ENOMEM, "device allocation (bf16 blocks)");
-    HIPCHECK(hipMemcpy(L->d_Ob.p, Oh.data(), n * 2, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L->d_Wb.p, Wh.data(), n * 2, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L->d_Ob_lo.p, Ol.data(), n * 2, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(L->d_Wb_lo.p, Wl.data(), n * 2, hipMemcpyHostToDevice));
-    L->Mp = Mp;
-  }
-  if (!L->d_val32.p) {
-    const int64_t n = L->blocks * L->nch * L->nch;
-    if (!L->d_val32.make(&L->al, std::max<int64_t>(n, 1))) return fail(WP_ENOMEM, "device allocation (FP32 P0)");
-    if (n > 0) HIPCHECK(launch_cvt_scalar(n, L->d_val64.p, L->d_val32.p, s));
-  }
-  return WP_OK;
-}
-
-// Least squares min || beta e1 - H z || for an (m+1) x m upper Hessenberg H (column-major by j:
-// H[j*(m+1) + i]) by Givens rotations; returns z (m entries).
-static std::vector<cplx> hessenberg_ls(std::vector<cplx> H, int m, double beta) {
-  const int ld = m + 1;
-  std::vector<cplx> g(m + 1, cplx(0, 0));
-  g[0] = beta;
-  for (int j = 0; j < m; ++j) {
-    cplx a = H[j * ld + j], bb = H[j * ld + j + 1];
-    double r = std::sqrt(std::norm(a) + std::norm(bb));
-    if (r == 0.0) continue;
-    cplx c = a / r, sn = bb / r;   // rotation [conj(c) conj(s); -s c]
-    for (int k = j; k < m; ++k) {
-      cplx x = H[k * ld + j], y = H[k * ld + j + 1];
-      H[k * ld + j] = std::conj(c) * x + std::conj(sn) * y;
-      H[k * ld + j + 1] = -sn * x + c * y;
-    }
-    cplx x = g[j], y = g[j + 1];
-    g[j] = std::conj(c) * x + std::conj(sn) * y;
-    g[j + 1] = -sn * x + c * y;
-  }
-  std::vector<cplx> z(m, cplx(0, 0));
-  for (int j = m - 1; j >= 0; --j) {
-    cplx v = g[j];
-    for (int k = j + 1; k < m; ++k) v -= H[k * ld + j] * z[k];
-    z[j] = std::abs(H[j * ld + j]) > 0.0 ? v / H[j * ld + j] : cplx(0, 0);
-  }
-  return z;
-}
-
-// Mixed path: iterative refinement in FP64 around a mixed-precision GMRES.
-//   outer (FP64): r = b - (I - K) y with FP64 blocks and G1 and the FP32-stored P0 accumulated
-//                 in FP64 (r = b at y = 0);
-//   inner:        m Arnoldi steps on (I - K~) started from r / |r|, K~ = P0(FP32) (v O^T)(BF16,
-//                 MFMA) G1(FP32) O(BF16, MFMA); FP32 basis vectors kept unnormalised with FP64
-//                 scale factors, classical Gram-Schmidt with FP64 sums (one pass: the outer
-//                 refinement absorbs the inner loss of orthogonality); the small least-squares
-//                 problem per column on the host in FP64; y += V z;
-//   stop:         U = e0^T O y in FP64 after every correction; with D_k the relative change of U
-//                 and rho = D_k / D_{k-1} the observed contraction, the error estimate is
-//                 D_k rho / (1 - rho); a column stops when it is <= tol.
-// A Neumann series in low precision would amplify every term's rounding by the growth of the
-// divergent series, which is why the inner solver is orthogonalised.
-static wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
-                             wp_solution* sol) {
-  const int M = L->M, N = L->N, nch = L->nch;
-  const int nfin = (int)L->opens.size();
-  const int nE = (int)Elab.size();
-  const int B = nE * nfin;
-  const int64_t D = (int64_t)M * N * nch;
-  const int64_t R = (int64_t)M * N;
-  const int64_t DB = D * B;
-  const bool split = o.mode == WP_SOLVE_MIXED_SPLIT;
-  std::vector<int> j0(B), g0(B);
-  std::vector<double> Etot(nE);
-  sol->res.resize(nE);
-  for (int e = 0; e < nE; ++e) {
-    EnergyResult& r = sol->res[e];
-    if (!kinematics(L, Elab[e], r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
-    Etot[e] = r.E;
-    for (int b = 0; b < nfin; ++b) {
-      j0[e * nfin + b] = r.j0;
-      g0[e * nfin + b] = L->opens[b];
-    }
-  }
-  if (wp_status st = ensure_mixed(L, s)) return st;
-  const int m = std::max(2, std::min(ARN_NV, o.refine_every > 0 ? o.refine_every : 8));
-  const int max_outer = std::max(2, std::min(100, o.max_iter / (m + 1)));
-  const int nblk = 512;
-  const bool fused = B >= 16 && nch <= 4;
-  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dcap, dcoef, H, part, nrm;
-  DBuf<float2> dG32, V, t32, kv32;
-  DBuf<double> scl;
-  DBuf<int> dj0, dg0, dfin;
-  DBuf<double> dE;
-  DBuf<int64_t> g1w;
-  if (!dG64.make(&L->al, DB) || !db.make(&L->al, DB) || !dy.make(&L->al, DB) || !dr.make(&L->al, DB) ||
-      !dKy.make(&L->al, DB) || !ds64.make(&L->al, DB) || !dcap.make(&L->al, (size_t)B * nfin) ||
-      !dcoef.make(&L->al, (size_t)(m + 1) * B) || !H.make(&L->al, (size_t)m * (m + 1) * B) ||
-      !part.make(&L->al, (size_t)nblk * ARN_NV * B) || !nrm.make(&L->al, B) || !dG32.make(&L->al, DB) ||
-      !V.make(&L->al, (size_t)(m + 1) * DB) || !t32.make(&L->al, DB) || (!fused && !kv32.make(&L->al, DB)) ||
-      !scl.make(&L->al, (size_t)(m + 1) * B) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
-      !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE) || !g1_work(L, nE, g1w))
-    return fail(WP_ENOMEM, "device allocation (mixed solve)");
-  HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
-  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG64.p, g1w), s));
-  HIPCHECK(launch_cvt_d2f(DB, dG64.p, dG32.p, s));
-  HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds64.p, s));
-  WP_LAUNCH("spmv_f32v_f64x", s,
-            launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, db.p, s, 0, -1,
-                                  L->d_order.p));
-  HIPCHECK(launch_fill0(dy.p, DB, s));
-  ArnoldiArgs aa{R, nch, B, m, 0, L->d_rowptr.p, L->d_col.p, L->d_val32.p, L->d_order.p, V.p, DB, scl.p, H.p, part.p, nblk};
-  RotArgsMixed rm{M, N, nch, B, L->d_Ob.p, split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p, split ? L->d_Wb_lo.p : nullptr,
-                  L->Mp, L->d_wave.p, dG32.p, nullptr};
-  std::vector<cplx> Uprev((size_t)B * nfin, cplx(0, 0)), Ubest((size_t)B * nfin, cplx(0, 0));
-  std::vector<double> err(B, 1.0), dprev(B, -1.0);
-  std::vector<int> iters(B, 0);
-  std::vector<bool> done(B, false);
-  std::vector<double2> hc((size_t)B * nfin), hH((size_t)m * (m + 1) * B), hn(B);
-  std::vector<double> hsc((size_t)(m + 1) * B);
-  std::vector<double2> coef((size_t)(m + 1) * B);
-  const double tol = std::max(o.tol, 1e-15);
-  for (int outer = 0; outer < max_outer; ++outer) {
-    if (outer == 0) {
-      HIPCHECK(hipMemcpyAsync(dr.p, db.p, DB * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    } else {
-      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG64.p, nullptr, dj0.p, dfin.p, nfin, 0};
-      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds64.p, s));
-      WP_LAUNCH("spmv_f32v_f64x", s,
-                launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, ds64.p, dKy.p, s, 0, -1,
-                                      L->d_order.p));
-      WP_LAUNCH("residual", s, launch_residual(DB, db.p, dy.p, dKy.p, dr.p, s));
-    }
-    HIPCHECK(launch_norm2_f64(D, B, dr.p, part.p, nblk, nrm.p, s));
-    HIPCHECK(launch_scale_d2f(D, B, nrm.p, dr.p, V.p, scl.p, s));
-    HIPCHECK(hipMemcpyAsync(hn.data(), nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
-    for (int j = 0; j < m; ++j) {
-      aa.j = j;
-      rm.yscale = scl.p + (size_t)j * B;
-      WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, V.p + (size_t)j * DB, t32.p, s));
-      WP_LAUNCH("arnoldi_product", s, launch_arnoldi_product(aa, t32.p, kv32.p, s));
-      WP_LAUNCH("arnoldi_orth", s, launch_arnoldi_orth(aa, s));
-    }
-    HIPCHECK(hipMemcpyAsync(hH.data(), H.p, hH.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipMemcpyAsync(hsc.data(), scl.p, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    std::fill(coef.begin(), coef.end(), make_double2(0.0, 0.0));
-    for (int c = 0; c < B; ++c) {
-      if (done[c]) continue;
-      std::vector<cplx> Hc((size_t)m * (m + 1));
-      for (int j = 0; j < m; ++j)
-        for (int i = 0; i <= m; ++i) {
-          const double2 v = hH[((size_t)j * (m + 1) + i) * B + c];
-          Hc[(size_t)j * (m + 1) + i] = cplx(v.x, v.y);
-        }
-      const double beta = std::sqrt(std::max(hn[c].x, 0.0));
-      std::vector<cplx> z = hessenberg_ls(Hc, m, beta);
-      for (int i = 0; i < m; ++i) {
-        const cplx w = z[i] * hsc[(size_t)i * B + c];   // V_i = scl_i Vt_i
-        coef[(size_t)i * B + c] = make_double2(w.real(), w.imag());
-      }
-      iters[c] += m + (outer > 0 ? 1 : 0);
-    }
-    HIPCHECK(hipMemcpyAsync(dcoef.p, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-    WP_LAUNCH("lincomb", s, launch_lincomb(D, B, m, V.p, DB, dcoef.p, dy.p, s));
-    WP_LAUNCH("capture", s, launch_capture64(M, nch, B, nfin, L->d_O.p, L->d_wave.p, dj0.p, dfin.p, dy.p, dcap.p, s));
-    HIPCHECK(hipMemcpyAsync(hc.data(), dcap.p, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    bool all = true;
-    for (int c = 0; c < B; ++c) {
-      if (done[c]) continue;
-      double change = 0.0, mag = 0.0;
-      for (int f = 0; f < nfin; ++f) {
-        const size_t k = (size_t)c * nfin + f;
-        const cplx u(hc[k].x, hc[k].y);
-        change = std::max(change, std::abs(u - Uprev[k]));
-        mag = std::max(mag, std::abs(u));
-        Uprev[k] = u;
-        Ubest[k] = u;
-      }
-      const double d = change / std::max(mag, 1e-300);
-      double est = 1.0;
-      if (dprev[c] >= 0.0) {
-        const double rho = dprev[c] > 0.0 ? d / dprev[c] : 0.0;
-        est = rho < 1.0 ? d * std::min(rho / (1.0 - rho), 1e6) : d * 1e6;
-      }
-      if (d == 0.0 && dprev[c] >= 0.0) est = 0.0;
-      err[c] = std::min(est, 1.0);
-      dprev[c] = d;
-      if (err[c] <= tol) done[c] = true;
-      all &= done[c];
-    }
-    if (all) break;
-  }
-  bool allok = true;
-  for (int e = 0; e < nE; ++e) {
-    EnergyResult& r = sol->res[e];
-    for (int b = 0; b < nfin; ++b) {
-      const int c = e * nfin + b;
-      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = Ubest[(size_t)c * nfin + f];
-      r.err[b] = err[c];
-      r.iters[b] = iters[c];
-      r.ok &= err[c] <= o.accept;
-    }
-    allok &= r.ok;
-  }
-  return allok ? WP_OK : fail(WP_ENOCONV, "mixed refinement did not reach the accepted accuracy for some energy");
-}
 
 extern "C" wp_status faddeev_solve(wp_lattice* L, int n_E, const double* E_lab, const wp_solve_opts* opts, void* stream,
                                    wp_solution** out) {

@@ -40,6 +40,14 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
+// Row-per-wavefront launches: wavefront w takes row order[w] (the rows longest first), or row w
+// without an order; -1 past the end.
+__device__ __forceinline__ int64_t spmv_row(int64_t rows, const int32_t* __restrict__ order) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= rows) return -1;
+  return order ? order[w] : w;
+}
+
 struct Node {
   double r1, r2, z1, Q1, Q2, w, x, c, s;
 };
@@ -784,36 +792,61 @@ __global__ void __launch_bounds__(256) k_step64(RotArgs r, const double* __restr
   const bool live = col < ncol;
   const int jj = live ? col / B : 0, cb = live ? col - jj * B : 0;
   for (int k = rg; k < M; k += nrg) {
-    double ar = 0.0, ai = 0.0;
+    // four partial sums over i = 0, 1, 2, 3 (mod 4), added in a fixed order: four loads of O in
+    // flight per thread instead of one dependent chain
+    double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
     const double* Ok = O + (size_t)k * M;
-    for (int i = 0; i < M; ++i) {
+    int i = 0;
+    for (; i + 4 <= M; i += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double a = Ok[i + u];
+        const double2 x = Xs[(i + u) * TC + cc];
+        ar[u] = fma(a, x.x, ar[u]);
+        ai[u] = fma(a, x.y, ai[u]);
+      }
+    }
+    for (int u = 0; i < M; ++i, ++u) {
       const double a = Ok[i];
       const double2 x = Xs[i * TC + cc];
-      ar = fma(a, x.x, ar);
-      ai = fma(a, x.y, ai);
+      ar[u] = fma(a, x.x, ar[u]);
+      ai[u] = fma(a, x.y, ai[u]);
     }
-    double2 v = make_double2(ar, ai);
+    double2 v = make_double2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
+    const double vr = v.x, vi = v.y;
     if (live) {
       if (r.acap && k == 0 && jj == r.j0[cb]) {
         for (int f = 0; f < r.nfin; ++f)
           if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = v;
       }
       const double2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
-      v = make_double2(ar * gv.x - ai * gv.y, ar * gv.y + ai * gv.x);
+      v = make_double2(vr * gv.x - vi * gv.y, vr * gv.y + vi * gv.x);
     }
     Ts[k * TC + cc] = v;
   }
   __syncthreads();
   for (int i = rg; i < M; i += nrg) {
-    double sr = 0.0, si = 0.0;
+    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
     const double* Wi = W + (size_t)i * M;
-    for (int k = 0; k < M; ++k) {
+    int k = 0;
+    for (; k + 4 <= M; k += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double a = Wi[k + u];
+        const double2 t = Ts[(k + u) * TC + cc];
+        sr[u] = fma(a, t.x, sr[u]);
+        si[u] = fma(a, t.y, si[u]);
+      }
+    }
+    for (int u = 0; k < M; ++k, ++u) {
       const double a = Wi[k];
       const double2 t = Ts[k * TC + cc];
-      sr = fma(a, t.x, sr);
-      si = fma(a, t.y, si);
+      sr[u] = fma(a, t.x, sr[u]);
+      si[u] = fma(a, t.y, si[u]);
     }
-    if (live) s_out[(((size_t)jj * M + i) * nch + g) * B + cb] = make_double2(sr, si);
+    if (live)
+      s_out[(((size_t)jj * M + i) * nch + g) * B + cb] =
+          make_double2((sr[0] + sr[1]) + (sr[2] + sr[3]), (si[0] + si[1]) + (si[2] + si[3]));
   }
 }
 
@@ -864,10 +897,9 @@ template <typename VT, typename XT, typename AT, int NC>
 __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const VT* __restrict__ val,
                                               const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row = spmv_row(rows, order);
   const int c = cb0 + blockIdx.y * 64 + (threadIdx.x & 63);
-  if (w >= rows || c >= cb1) return;
-  const int64_t row = order ? order[w] : w;
+  if (row < 0 || c >= cb1) return;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   AT ar[NC], ai[NC];
 #pragma unroll
@@ -895,10 +927,9 @@ template <typename VT, typename XT, typename AT, int NC>
 __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const VT* __restrict__ val,
                                               const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row = spmv_row(rows, order);
   const int lane = threadIdx.x & 63;
-  if (w >= rows) return;
-  const int64_t row = order ? order[w] : w;
+  if (row < 0) return;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   for (int c = cb0; c < cb1; ++c) {
     AT ar[NC], ai[NC];
@@ -926,15 +957,17 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int 
   }
 }
 
+static int64_t spmv_blocks(int64_t rows, const int32_t*) { return (rows + 3) / 4; }
+
 template <typename VT, typename XT, typename AT, int NC>
 static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* rowptr, const int32_t* col,
                           const VT* val, const XT* x, XT* y, hipStream_t s, const int32_t* order) {
   // the choice depends on B only, so every launch on a given batch width sums in one order
   if (B >= 16) {
-    dim3 grid((unsigned)((rows + 3) / 4), (cb1 - cb0 + 63) / 64);
+    dim3 grid((unsigned)spmv_blocks(rows, order), (cb1 - cb0 + 63) / 64);
     hipLaunchKernelGGL((k_spmm<VT, XT, AT, NC>), grid, dim3(256), 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y, order);
   } else {
-    hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, B, cb0, cb1,
+    hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, B, cb0, cb1,
                        rowptr, col, val, x, y, order);
   }
 }
@@ -1128,10 +1161,9 @@ template <typename VT, typename XT, typename AT, int CT>
 __global__ void __launch_bounds__(256) k_spmv_gen(int64_t rows, int NC, int B, int cb0, int cb1,
                                                   const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                   const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row = spmv_row(rows, order);
   const int lane = threadIdx.x & 63;
-  if (w >= rows) return;
-  const int64_t row = order ? order[w] : w;
+  if (row < 0) return;
   const int SL = 64 / NC;
   const int s = lane / NC, g = lane - s * NC;
   const bool act = s < SL;
@@ -1209,11 +1241,10 @@ __global__ void __launch_bounds__(256) k_spmv_lds(int64_t rows, int NC, int B, i
                                                   const V2* __restrict__ val2, const XT* __restrict__ x,
                                                   XT* __restrict__ y, const int32_t* __restrict__ order) {
   __shared__ XT xs_all[4][128 * CT];
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row = spmv_row(rows, order);
   const int lane = threadIdx.x & 63;
   XT* xs = xs_all[threadIdx.x >> 6];
-  if (w >= rows) return;
-  const int64_t row = order ? order[w] : w;
+  if (row < 0) return;
   const int NH = NC >> 1;            // lanes per block column
   const int SL = 64 / NH;            // blocks per pass
   const int CH = SL * (64 / SL);     // blocks per column-index chunk (<= 64)
@@ -1303,17 +1334,24 @@ template <typename VT> struct Vec2;
 template <> struct Vec2<double> { using T = double2; };
 template <> struct Vec2<float> { using T = float2; };
 
-// Many columns (B >= 16): lanes over columns, the block entries wave-uniform, up to NCMAX
-// channel accumulators per lane.
+// Many columns (B >= 16): lanes over columns, up to NCMAX channel accumulators per lane. The
+// wavefront stages each block's NC x NC entries in its own LDS slice with coalesced loads (one
+// global read per entry instead of one scalar load per entry and column block) and reads them
+// back by broadcast, two channels g per read.
 #define NCMAX 24
 template <typename VT, typename XT, typename AT>
 __global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, int cb0, int cb1,
                                                   const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int c = cb0 + blockIdx.y * 64 + (threadIdx.x & 63);
-  if (w >= rows || c >= cb1) return;
-  const int64_t row = order ? order[w] : w;
+                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
+                                                  const int32_t* __restrict__ order) {
+  __shared__ VT vs_all[4][NCMAX * NCMAX + 2];
+  VT* vs = vs_all[threadIdx.x >> 6];
+  const int64_t row = spmv_row(rows, order);
+  const int lane = threadIdx.x & 63;
+  const int c = cb0 + blockIdx.y * 64 + lane;
+  if (row < 0) return;
+  const bool live = c < cb1;
+  const int cl = live ? c : cb1 - 1;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   const int nc2 = NC * NC;
   AT ar[NCMAX], ai[NCMAX];
@@ -1322,18 +1360,36 @@ __global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, i
   for (int64_t e = b0; e < b1; ++e) {
     const int cc = col[e];
     const VT* v = val + e * nc2;
-    for (int gp = 0; gp < NC; ++gp) {
-      const XT xv = x[((size_t)cc * NC + gp) * B + c];
+    __builtin_amdgcn_wave_barrier();
+    for (int t = lane; t < nc2; t += 64) vs[t] = v[t];
+    if (lane == 0 && (nc2 & 1)) vs[nc2] = VT(0);   // pad for the paired reads of an odd NC
+    __builtin_amdgcn_wave_barrier();
+    for (int gp0 = 0; gp0 < NC; gp0 += 6) {   // six x loads in flight, then their products
+      XT xg[6];
 #pragma unroll
-      for (int g = 0; g < NCMAX; ++g) {
-        if (g < NC) {
-          const AT a = (AT)v[gp * NC + g];
-          ar[g] = fma(a, (AT)xv.x, ar[g]);
-          ai[g] = fma(a, (AT)xv.y, ai[g]);
+      for (int u = 0; u < 6; ++u)
+        if (gp0 + u < NC) xg[u] = x[((size_t)cc * NC + gp0 + u) * B + cl];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        if (gp0 + u >= NC) break;
+        const XT xv = xg[u];
+        const VT* vg = vs + (gp0 + u) * NC;   // column g' of the block: entries g = 0 .. NC - 1
+#pragma unroll
+        for (int g = 0; g < NCMAX; g += 2) {
+          if (g < NC) {
+            const AT a0 = (AT)vg[g], a1 = (g + 1 < NC) ? (AT)vg[g + 1] : AT(0);
+            ar[g] = fma(a0, (AT)xv.x, ar[g]);
+            ai[g] = fma(a0, (AT)xv.y, ai[g]);
+            if (g + 1 < NCMAX) {
+              ar[g + 1] = fma(a1, (AT)xv.x, ar[g + 1]);
+              ai[g + 1] = fma(a1, (AT)xv.y, ai[g + 1]);
+            }
+          }
         }
       }
     }
   }
+  if (!live) return;
 #pragma unroll
   for (int g = 0; g < NCMAX; ++g) {
     if (g < NC) {
@@ -1345,6 +1401,7 @@ __global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, i
   }
 }
 
+
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
                            const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
@@ -1352,12 +1409,12 @@ hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, 
   if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 1 || nch > 64) return hipErrorInvalidValue;
   // the choice depends on B and nch only, so every launch on a given batch width sums in one order
   if (B >= 16 && nch <= NCMAX) {
-    dim3 grid((unsigned)((rows + 3) / 4), (cb1 - cb0 + 63) / 64);
+    dim3 grid((unsigned)spmv_blocks(rows, order), (cb1 - cb0 + 63) / 64);
     hipLaunchKernelGGL((k_spmm_gen<VT, XT, AT>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, val, x, y, order);
   } else if (nch % 2 == 0 && nch >= 4) {
     using V2 = typename Vec2<VT>::T;
     const V2* v2 = reinterpret_cast<const V2*>(val);
-    const dim3 grid((unsigned)((rows + 3) / 4));
+    const dim3 grid((unsigned)spmv_blocks(rows, order));
     const int ncols = cb1 - cb0;
     if (nch % 9 == 0) {
       if (ncols >= 4)
@@ -1375,13 +1432,13 @@ hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, 
         hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 1, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
     }
   } else if (B >= 4) {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 4>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 4>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
                        cb0, cb1, rowptr, col, val, x, y, order);
   } else if (B >= 2) {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 2>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 2>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
                        cb0, cb1, rowptr, col, val, x, y, order);
   } else {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 1>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, B,
+    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 1>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
                        cb0, cb1, rowptr, col, val, x, y, order);
   }
   return hipGetLastError();

@@ -201,6 +201,24 @@ hipError_t launch_cvt_scalar(int64_t n, const double* in, float* out, hipStream_
   return hipGetLastError();
 }
 
+// the columns [c0, c1) of a [rows][B] array
+__global__ void k_cvt_d2f_cols(int64_t rows, int B, int c0, int c1, const double2* __restrict__ in,
+                               float2* __restrict__ out) {
+  const int w = c1 - c0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * w) return;
+  const int64_t d = t / w;
+  const size_t i = (size_t)d * B + c0 + (int)(t - d * w);
+  out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+hipError_t launch_cvt_d2f_cols(int64_t rows, int B, int c0, int c1, const double2* in, float2* out, hipStream_t s) {
+  if (c0 < 0 || c1 > B || c0 >= c1) return hipErrorInvalidValue;
+  const int64_t n = rows * (c1 - c0);
+  hipLaunchKernelGGL(k_cvt_d2f_cols, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, rows, B, c0, c1, in, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_cvt_d2f(int64_t n, const double2* in, float2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_cvt_d2f, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);
   return hipGetLastError();

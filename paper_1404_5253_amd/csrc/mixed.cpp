@@ -1,0 +1,285 @@
+// Mixed-precision solve of y = b + K y (Sec. II.B.4, eq. m_pvg): FP64 iterative refinement around
+// a mixed-precision GMRES, shared by faddeev_solve (all energies of a call) and the continuous
+// batch (faddeev_batch_*, one refinement cycle per step).
+//
+//   outer (FP64): r = b - (I - K) y with FP64 blocks and G1 and the FP32-stored P0 accumulated in
+//                 FP64 (r = b at y = 0);
+//   inner:        m Arnoldi steps on (I - K~) started from r / |r|, K~ = P0(FP32) (v O^T)(BF16,
+//                 MFMA) G1(FP32) O(BF16, MFMA); FP32 basis vectors kept unnormalised with FP64
+//                 scale factors, classical Gram-Schmidt with FP64 sums (one pass: the outer
+//                 refinement absorbs the inner loss of orthogonality); the small least-squares
+//                 problem per column on the host in FP64; y += V z;
+//   stop:         U = e0^T O y in FP64 after every correction; with D_k the relative change of U
+//                 and rho = D_k / D_{k-1} the observed contraction, the error estimate is
+//                 D_k rho / (1 - rho); a column stops when it is <= tol.
+// A Neumann series in low precision would amplify every term's rounding by the growth of the
+// divergent series, which is why the inner solver is orthogonalised.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "wpcd_objects.h"
+
+using namespace wpcd;
+
+static uint16_t host_bf16(double d) {
+  float f = (float)d;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
+  if (wp_status st = upload_waves(L)) return st;
+  const int M = L->M;
+  if (!L->d_Ob.p) {
+    // bf16 copies of O and v O^T (hi) and of their rounding remainders (lo), padded to Mp
+    const int Mp = (M + 15) / 16 * 16;
+    const size_t MM = (size_t)Mp * Mp;
+    const size_t n = MM * L->waves.size();
+    std::vector<uint16_t> Oh(n, 0), Ol(n, 0), Wh(n, 0), Wl(n, 0);
+    auto split = [](double d, uint16_t& hi, uint16_t& lo) {
+      hi = host_bf16(d);
+      uint32_t u = (uint32_t)hi << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      lo = host_bf16((double)((float)d - f));
+    };
+    for (size_t w = 0; w < L->waves.size(); ++w)
+      for (int r = 0; r < M; ++r)
+        for (int c = 0; c < M; ++c) {
+          const size_t k = w * MM + (size_t)r * Mp + c;
+          split(L->waves[w].O[(size_t)r * M + c], Oh[k], Ol[k]);
+          split(L->waves[w].W[(size_t)r * M + c], Wh[k], Wl[k]);
+        }
+    if (!L->d_Ob.make(&L->al, n) || !L->d_Wb.make(&L->al, n) || !L->d_Ob_lo.make(&L->al, n) ||
+        !L->d_Wb_lo.make(&L->al, n))
+      return fail(WP_ENOMEM, "device allocation (bf16 blocks)");
+    HIPCHECK(hipMemcpy(L->d_Ob.p, Oh.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Wb.p, Wh.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Ob_lo.p, Ol.data(), n * 2, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_Wb_lo.p, Wl.data(), n * 2, hipMemcpyHostToDevice));
+    L->Mp = Mp;
+  }
+  if (!L->d_val32.p) {
+    const int64_t n = L->blocks * L->nch * L->nch;
+    if (!L->d_val32.make(&L->al, std::max<int64_t>(n, 1))) return fail(WP_ENOMEM, "device allocation (FP32 P0)");
+    if (n > 0) HIPCHECK(launch_cvt_scalar(n, L->d_val64.p, L->d_val32.p, s));
+  }
+  return WP_OK;
+}
+
+// Least squares min || beta e1 - H z || for an (m+1) x m upper Hessenberg H (column-major by j:
+// H[j*(m+1) + i]) by Givens rotations; returns z (m entries).
+static std::vector<cplx> hessenberg_ls(std::vector<cplx> H, int m, double beta) {
+  const int ld = m + 1;
+  std::vector<cplx> g(m + 1, cplx(0, 0));
+  g[0] = beta;
+  for (int j = 0; j < m; ++j) {
+    cplx a = H[j * ld + j], bb = H[j * ld + j + 1];
+    double r = std::sqrt(std::norm(a) + std::norm(bb));
+    if (r == 0.0) continue;
+    cplx c = a / r, sn = bb / r;   // rotation [conj(c) conj(s); -s c]
+    for (int k = j; k < m; ++k) {
+      cplx x = H[k * ld + j], y = H[k * ld + j + 1];
+      H[k * ld + j] = std::conj(c) * x + std::conj(sn) * y;
+      H[k * ld + j + 1] = -sn * x + c * y;
+    }
+    cplx x = g[j], y = g[j + 1];
+    g[j] = std::conj(c) * x + std::conj(sn) * y;
+    g[j + 1] = -sn * x + c * y;
+  }
+  std::vector<cplx> z(m, cplx(0, 0));
+  for (int j = m - 1; j >= 0; --j) {
+    cplx v = g[j];
+    for (int k = j + 1; k < m; ++k) v -= H[k * ld + j] * z[k];
+    z[j] = std::abs(H[j * ld + j]) > 0.0 ? v / H[j * ld + j] : cplx(0, 0);
+  }
+  return z;
+}
+
+size_t wpcd::mixed_bytes_per_column(const wp_lattice* L, int m) {
+  const size_t D = (size_t)L->M * L->N * L->nch;
+  // FP64: G1, b, y, r, Ky, s; FP32: G1, basis (m + 1), t, Kv
+  return D * (6 * sizeof(double2) + (m + 4) * sizeof(float2)) + (size_t)(m + 1) * (m + 2) * 24;
+}
+
+wp_status wpcd::MixedWork::make(wp_lattice* Lp, int B_, int m_, bool split_) {
+  L = Lp;
+  B = B_;
+  m = m_;
+  split = split_;
+  nfin = (int)L->opens.size();
+  R = (int64_t)L->M * L->N;
+  D = R * L->nch;
+  DB = D * B;
+  fused = B >= 16 && L->nch <= 4;
+  DevAlloc* al = &L->al;
+  if (!dG64.make(al, DB) || !db.make(al, DB) || !dy.make(al, DB) || !dr.make(al, DB) || !dKy.make(al, DB) ||
+      !ds64.make(al, DB) || !dcap.make(al, (size_t)B * nfin) || !dcoef.make(al, (size_t)(m + 1) * B) ||
+      !H.make(al, (size_t)m * (m + 1) * B) || !part.make(al, (size_t)kNblk * ARN_NV * B) || !nrm.make(al, B) ||
+      !dG32.make(al, DB) || !V.make(al, (size_t)(m + 1) * DB) || !t32.make(al, DB) ||
+      (!fused && !kv32.make(al, DB)) || !scl.make(al, (size_t)(m + 1) * B) || !dj0.make(al, B) ||
+      !dfin.make(al, nfin))
+    return fail(WP_ENOMEM, "device allocation (mixed solve)");
+  hc.resize((size_t)B * nfin);
+  hH.resize((size_t)m * (m + 1) * B);
+  hn.resize(B);
+  hsc.resize((size_t)(m + 1) * B);
+  coef.resize((size_t)(m + 1) * B);
+  return WP_OK;
+}
+
+// One refinement cycle on every column: FP64 residual (skipped when all y = 0), m Arnoldi steps,
+// the least-squares corrections of the columns with active[c] (zero for the others), y += V z and
+// the captured U of every column (hc, [c][final]).
+wp_status wpcd::mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const std::vector<char>& active) {
+  wp_lattice* L = w.L;
+  const int M = L->M, N = L->N, nch = L->nch, B = w.B, m = w.m, nfin = w.nfin;
+  const int64_t D = w.D, DB = w.DB, R = w.R;
+  if (y_is_zero) {
+    HIPCHECK(hipMemcpyAsync(w.dr.p, w.db.p, DB * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  } else {
+    RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, w.dG64.p, nullptr, w.dj0.p, w.dfin.p, nfin, 0};
+    WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, w.dy.p, w.ds64.p, s));
+    WP_LAUNCH("spmv_f32v_f64x", s,
+              launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.dKy.p, s, 0, -1,
+                                    L->d_order.p));
+    WP_LAUNCH("residual", s, launch_residual(DB, w.db.p, w.dy.p, w.dKy.p, w.dr.p, s));
+  }
+  HIPCHECK(launch_norm2_f64(D, B, w.dr.p, w.part.p, kNblk, w.nrm.p, s));
+  HIPCHECK(launch_scale_d2f(D, B, w.nrm.p, w.dr.p, w.V.p, w.scl.p, s));
+  HIPCHECK(hipMemcpyAsync(w.hn.data(), w.nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
+  ArnoldiArgs aa{R,         nch,     B,      m,    0,          L->d_rowptr.p, L->d_col.p, L->d_val32.p,
+                 L->d_order.p, w.V.p, DB,    w.scl.p, w.H.p, w.part.p, kNblk};
+  RotArgsMixed rm{M,          N, nch, B, L->d_Ob.p, w.split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p,
+                  w.split ? L->d_Wb_lo.p : nullptr, L->Mp, L->d_wave.p, w.dG32.p, nullptr};
+  for (int j = 0; j < m; ++j) {
+    aa.j = j;
+    rm.yscale = w.scl.p + (size_t)j * B;
+    WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, w.V.p + (size_t)j * DB, w.t32.p, s));
+    WP_LAUNCH("arnoldi_product", s, launch_arnoldi_product(aa, w.t32.p, w.kv32.p, s));
+    WP_LAUNCH("arnoldi_orth", s, launch_arnoldi_orth(aa, s));
+  }
+  HIPCHECK(hipMemcpyAsync(w.hH.data(), w.H.p, w.hH.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(w.hsc.data(), w.scl.p, w.hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  std::fill(w.coef.begin(), w.coef.end(), make_double2(0.0, 0.0));
+  std::vector<cplx> Hc((size_t)m * (m + 1));
+  for (int c = 0; c < B; ++c) {
+    if (!active[c]) continue;
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i <= m; ++i) {
+        const double2 v = w.hH[((size_t)j * (m + 1) + i) * B + c];
+        Hc[(size_t)j * (m + 1) + i] = cplx(v.x, v.y);
+      }
+    const double beta = std::sqrt(std::max(w.hn[c].x, 0.0));
+    std::vector<cplx> z = hessenberg_ls(Hc, m, beta);
+    for (int i = 0; i < m; ++i) {
+      const cplx v = z[i] * w.hsc[(size_t)i * B + c];   // V_i = scl_i Vt_i
+      w.coef[(size_t)i * B + c] = make_double2(v.real(), v.imag());
+    }
+  }
+  HIPCHECK(hipMemcpyAsync(w.dcoef.p, w.coef.data(), w.coef.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+  WP_LAUNCH("lincomb", s, launch_lincomb(D, B, m, w.V.p, DB, w.dcoef.p, w.dy.p, s));
+  WP_LAUNCH("capture", s,
+            launch_capture64(M, nch, B, nfin, L->d_O.p, L->d_wave.p, w.dj0.p, w.dfin.p, w.dy.p, w.dcap.p, s));
+  HIPCHECK(hipMemcpyAsync(w.hc.data(), w.dcap.p, w.hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return WP_OK;
+}
+
+// Error estimate of one column after a correction (see the stop rule above); true when done.
+bool wpcd::MixedCol::update(const double2* u_new, int nfin, double tol) {
+  double change = 0.0, mag = 0.0;
+  if (U.size() != (size_t)nfin) U.assign(nfin, cplx(0, 0));
+  for (int f = 0; f < nfin; ++f) {
+    const cplx u(u_new[f].x, u_new[f].y);
+    change = std::max(change, std::abs(u - U[f]));
+    mag = std::max(mag, std::abs(u));
+    U[f] = u;
+  }
+  const double d = change / std::max(mag, 1e-300);
+  double est = 1.0;
+  if (dprev >= 0.0) {
+    const double rho = dprev > 0.0 ? d / dprev : 0.0;
+    est = rho < 1.0 ? d * std::min(rho / (1.0 - rho), 1e6) : d * 1e6;
+    if (d == 0.0) est = 0.0;
+  }
+  err = std::min(est, 1.0);
+  dprev = d;
+  return err <= tol;
+}
+
+wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
+                            wp_solution* sol) {
+  const int M = L->M, N = L->N, nch = L->nch;
+  const int nfin = (int)L->opens.size();
+  const int nE = (int)Elab.size();
+  const int B = nE * nfin;
+  std::vector<int> j0(B), g0(B);
+  std::vector<double> Etot(nE);
+  sol->res.resize(nE);
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    if (!kinematics(L, Elab[e], r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
+    Etot[e] = r.E;
+    for (int b = 0; b < nfin; ++b) {
+      j0[e * nfin + b] = r.j0;
+      g0[e * nfin + b] = L->opens[b];
+    }
+  }
+  if (wp_status st = ensure_mixed(L, s)) return st;
+  if (wp_status so = ensure_order(L)) return so;
+  const int m = std::max(2, std::min(ARN_NV, o.refine_every > 0 ? o.refine_every : 8));
+  const int max_outer = std::max(2, std::min(100, o.max_iter / (m + 1)));
+  MixedWork w;
+  if (wp_status st = w.make(L, B, m, o.mode == WP_SOLVE_MIXED_SPLIT)) return st;
+  DBuf<int> dg0;
+  DBuf<double> dE;
+  DBuf<int64_t> g1w;
+  if (!dg0.make(&L->al, B) || !dE.make(&L->al, nE) || !g1_work(L, nE, g1w))
+    return fail(WP_ENOMEM, "device allocation (mixed solve)");
+  const int64_t DB = w.DB, R = w.R;
+  HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(w.dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(w.dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, w.dG64.p, g1w), s));
+  HIPCHECK(launch_cvt_d2f(DB, w.dG64.p, w.dG32.p, s));
+  HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, dg0.p, w.ds64.p, s));
+  WP_LAUNCH("spmv_f32v_f64x", s,
+            launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, s, 0, -1,
+                                  L->d_order.p));
+  HIPCHECK(launch_fill0(w.dy.p, DB, s));
+  std::vector<MixedCol> col(B);
+  std::vector<char> active(B, 1);
+  for (int outer = 0; outer < max_outer; ++outer) {
+    if (wp_status st = mixed_cycle(w, s, outer == 0, active)) return st;
+    bool all = true;
+    for (int c = 0; c < B; ++c) {
+      if (!active[c]) continue;
+      col[c].iters += m + (outer > 0 ? 1 : 0);
+      if (col[c].update(&w.hc[(size_t)c * nfin], nfin, std::max(o.tol, 1e-15))) active[c] = 0;
+      all &= !active[c];
+    }
+    if (all) break;
+  }
+  bool allok = true;
+  for (int e = 0; e < nE; ++e) {
+    EnergyResult& r = sol->res[e];
+    for (int b = 0; b < nfin; ++b) {
+      const MixedCol& c = col[e * nfin + b];
+      for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = c.U.empty() ? cplx(0, 0) : c.U[f];
+      r.err[b] = c.err;
+      r.iters[b] = c.iters;
+      r.ok &= c.err <= o.accept;
+    }
+    allok &= r.ok;
+  }
+  return allok ? WP_OK : fail(WP_ENOCONV, "mixed refinement did not reach the accepted accuracy for some energy");
+}

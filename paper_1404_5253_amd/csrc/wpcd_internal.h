@@ -191,6 +191,7 @@ struct RotArgsMixed {
 // s = W (G1 * (O y)) on MFMA (split representation when A_lo / W_lo are given)
 hipError_t launch_step_bf16(const RotArgsMixed& r, const float2* y, float2* s_out, hipStream_t s);
 hipError_t launch_cvt_d2f(int64_t n, const double2* in, float2* out, hipStream_t s);
+hipError_t launch_cvt_d2f_cols(int64_t rows, int B, int c0, int c1, const double2* in, float2* out, hipStream_t s);
 hipError_t launch_cvt_scalar(int64_t n, const double* in, float* out, hipStream_t s);
 hipError_t launch_residual(int64_t n, const double2* b, const double2* y, const double2* Ky, double2* r,
                            hipStream_t s);

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "wpcd_internal.h"
@@ -53,6 +54,13 @@ struct wp_lattice {
   DBuf<int64_t> d_rowptr;
   DBuf<int32_t> d_col;
   DBuf<int32_t> d_order;   // block rows by decreasing length (ties by index): SpMV work order
+  // pinned host staging of the captured series terms (FP64 solve), reused across calls
+  std::mutex pin_mu;
+  double2* pin = nullptr;
+  size_t pin_cap = 0;
+  ~wp_lattice() {
+    if (pin) (void)hipHostFree(pin);
+  }
   DBuf<double> d_val64;
   DBuf<float> d_val32;
   wp_perm_stats stats{};
@@ -93,6 +101,35 @@ struct ProfScope {
 wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
 wp_status ensure_mixed(wp_lattice* L, hipStream_t s);   // bf16 blocks + FP32 copy of P0
+wp_status ensure_order(wp_lattice* L);                  // SpMV row order of the resident P0
+
+// ------------------------------------------------------------------ mixed path (mixed.cpp)
+constexpr int kNblk = 512;   // workgroups of the column reductions
+// device and host work space of the mixed refinement for B columns
+struct MixedWork {
+  wp_lattice* L = nullptr;
+  int B = 0, m = 0, nfin = 0;
+  int64_t R = 0, D = 0, DB = 0;
+  bool fused = false, split = false;
+  DBuf<double2> dG64, db, dy, dr, dKy, ds64, dcap, dcoef, H, part, nrm;
+  DBuf<float2> dG32, V, t32, kv32;
+  DBuf<double> scl;
+  DBuf<int> dj0, dfin;
+  std::vector<double2> hc, hH, hn, coef;
+  std::vector<double> hsc;
+  wp_status make(wp_lattice* L, int B, int m, bool split);
+};
+// per-column state of the refinement's stop rule
+struct MixedCol {
+  std::vector<cplx> U;
+  double dprev = -1.0, err = 1.0;
+  int iters = 0;
+  bool update(const double2* u_new, int nfin, double tol);
+};
+size_t mixed_bytes_per_column(const wp_lattice* L, int m);
+wp_status mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const std::vector<char>& active);
+wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
+                      wp_solution* sol);
 // Device work list of the G1 kernels for nE energies (element list plus counter in slot 0).
 bool g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w);
 // G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns)

@@ -1,4 +1,5 @@
-"""Continuous-batching serving loop over resident lattices (faddeev_batch_* of libwpcd).
+"""Continuous-batching serving loop over resident lattices (faddeev_batch_* of libwpcd, FP64 or
+mixed precision).
 
 Each resident lattice owns one batch (a fixed number of energy slots sized by a device-memory
 budget) and one worker thread with its own HIP stream, so the steps of different lattices
@@ -31,14 +32,18 @@ class Request:
 
 
 class BatchBackend:
-    """One lattice's continuous batch on the GPU (FP64 path)."""
+    """One lattice's continuous batch on the GPU: mode "fp64" (Pade-summed Neumann terms, `terms`
+    per step) or "mixed" / "mixed_split" (one FP64-refined mixed-precision cycle of refine_every
+    Arnoldi steps per step)."""
 
-    def __init__(self, lattice, slots, hbm_budget, terms=4, tol=1e-12, accept=1e-7, max_iter=200, stream=None):
+    def __init__(self, lattice, slots, hbm_budget, terms=4, tol=1e-12, accept=1e-7, max_iter=200, stream=None,
+                 mode="fp64", refine_every=0):
         import paper_1404_5253_amd as wp
         self.wp = wp
         self.L = lattice
         self.terms = terms
-        o = wp._SolveOpts(wp.WP_SOLVE_FP64, tol, accept, max_iter, 0)
+        self.mode = mode
+        o = wp._SolveOpts(wp.SOLVE_MODES[mode], tol, accept, max_iter, refine_every)
         self.h = C.c_void_p()
         wp._check(wp._lib.faddeev_batch_create(lattice.h, slots, hbm_budget, C.byref(o), C.byref(self.h)))
         self.slots = slots

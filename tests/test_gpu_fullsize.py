@@ -1,0 +1,131 @@
+"""Full-size GPU checks on the bench workloads, in the launch configuration bench.py times.
+
+* s-wave Malfliet-Tjon, M = N = 100 (doublet and quartet, V_R seed 0): the number of stored cell
+  pairs against the oracle's count (exact), 64 seeded P0 elements recomputed one by one with the
+  oracle's rule, and the on-shell amplitudes at 14.1 MeV against the oracle's FP64 solve
+  (tests/golden/swave_mt_100.json, written by tests/golden/make_golden.py from the oracle only).
+* 18-channel Malfliet-Tjon, M = N = 150 (J = 1/2+, j <= 2): sampled P0 blocks against the
+  oracle's rule for every moment contracted with the oracle's recoupling coefficients; the 2 x 2
+  S matrix at 3 MeV (below breakup) unitary; both mixed paths against the FP64 path.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import paper_1404_5253_amd as wp
+
+import workloads
+from oracle import pipeline, recoupling
+from oracle.perm import channel_terms, element_rule
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _lattice(M, two_J, j_max, swave, V_R):
+    L = wp.Lattice(M, M, two_J=two_J, j_max=j_max, swave_only=swave, n_x=8, n_phi=8)
+    L.pseudostates(kind="mt", V_R=V_R)
+    st = L.build_perm("fp64")
+    return L, st
+
+
+def _oracle_C(spec):
+    chans = pipeline.channel_list(spec)
+    gt = {(a, b): recoupling.g_table(chans[a], chans[b], spec.two_J)
+          for a in range(len(chans)) for b in range(len(chans))}
+    keys, C = channel_terms(chans, gt)
+    return chans, keys, C
+
+
+def _block(rp, col, val, r, c):
+    lo, hi = rp[r], rp[r + 1]
+    k = np.nonzero(col[lo:hi] == c)[0]
+    return val[lo + k[0]] if len(k) == 1 else None
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(os.path.join(HERE, "golden", "swave_mt_100.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("two_J", [1, 3])
+def test_swave_mt_100_against_oracle(golden, two_J):
+    g = golden["systems"][str(two_J)]
+    M = golden["M"]
+    L, st = _lattice(M, two_J, 1, True, golden["V_R"])
+    assert [list(c) for c in L.channels] == g["channels"]
+    assert st["blocks"] == g["geo_nnz"]           # stored cell pairs: exact count
+    rp, col, val = L.export_perm()
+    spec = pipeline.Spec(M=M, N=M, two_J=two_J, pot="mt", V_R=golden["V_R"])
+    _, keys, C = _oracle_C(spec)
+    assert keys == [(0, 0, 0, 0, 0)]
+    scale = np.abs(val).max()
+    for i, j, ip, jp, v in g["p0_samples"]:
+        blk = _block(rp, col, val, j * M + i, jp * M + ip)
+        assert blk is not None, (i, j, ip, jp)
+        assert np.max(np.abs(blk - C[:, :, 0] * v)) <= 1e-12 * scale, (i, j, ip, jp)
+    ref = g["results"]["14.1"]
+    Ar = ref["A_re"] + 1j * ref["A_im"]
+    a = L.solve([14.1], "fp64").amplitude(0)
+    bound = 1e-10 * abs(Ar) + 30 * max(a["err"][0], ref["rel_err"]) * abs(Ar)
+    assert abs(a["A"][0, 0] - Ar) <= bound, (abs(a["A"][0, 0] - Ar) / abs(Ar), a["err"])
+    for mode in ("mixed", "mixed_split"):
+        m = L.solve([14.1], mode, tol=1e-8).amplitude(0)
+        assert abs(m["A"][0, 0] - Ar) <= 1e-6, (mode, abs(m["A"][0, 0] - Ar))
+
+
+@pytest.fixture(scope="module")
+def pw150():
+    wl = workloads.WORKLOADS["pw_mt_150"]
+    V_R = workloads.mt_repulsion(wl["V_R_seed"])
+    sysd = wl["systems"][0]
+    L, st = _lattice(wl["M"], sysd["two_J"], sysd["j_max"], sysd["swave"], V_R)
+    spec = pipeline.Spec(M=wl["M"], N=wl["N"], two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=False,
+                         pot="mt", V_R=V_R)
+    return L, st, spec, wl
+
+
+def test_pw_mt_150_sampled_blocks(pw150):
+    L, st, spec, wl = pw150
+    M = wl["M"]
+    chans, keys, C = _oracle_C(spec)
+    assert [tuple(c) for c in L.channels] == [tuple(c) for c in chans]
+    rp, col, val = L.export_perm()
+    assert len(col) == st["blocks"]
+    scale = np.abs(val).max()
+    rng = np.random.default_rng(11)
+    lens = np.diff(rp)
+    picks = list(rng.choice(st["blocks"], 20, replace=False))
+    longest = int(np.argmax(lens))
+    picks += [0, st["blocks"] - 1, rp[longest], rp[longest + 1] - 1]
+    pe, qe = L.edges()
+    for b in picks:
+        r = int(np.searchsorted(rp, b, side="right") - 1)
+        c = int(col[b])
+        j, i = divmod(r, M)
+        jp, ip = divmod(c, M)
+        mom = np.array([element_rule(pe, qe, i, j, ip, jp, k, 8, 8) for k in keys])
+        ref = np.einsum("abm,m->ab", C, mom)
+        assert np.max(np.abs(val[b] - ref)) <= 1e-12 * scale, (i, j, ip, jp, np.max(np.abs(val[b] - ref)) / scale)
+
+
+def test_pw_mt_150_unitarity_and_mixed(pw150):
+    L, st, spec, wl = pw150
+    E_lo, E_hi = wl["E_lab"]
+    ref = L.solve([E_lo, E_hi], "fp64", tol=1e-10, max_iter=400)
+    lo = ref.amplitude(0)
+    S = lo["S"]
+    assert S.shape == (2, 2)
+    assert np.max(np.abs(S @ S.conj().T - np.eye(2))) <= 1e-6      # two open channels below breakup
+    for mode in ("mixed", "mixed_split"):
+        mix = L.solve([E_lo, E_hi], mode, tol=1e-8)
+        for k in range(2):
+            d = np.max(np.abs(mix.amplitude(k)["A"] - ref.amplitude(k)["A"]))
+            assert d <= 1e-6, (mode, k, d)

@@ -203,10 +203,10 @@ def test_batch_api_matches_solve():
         assert np.array_equal(r["A"], solo["A"]), E
 
 
-def _run_batch(L, energies, slots, terms=4):
+def _run_batch(L, energies, slots, terms=4, mode="fp64", tol=1e-12):
     """Drive the continuous-batching API until every energy is done; returns {E: amplitude}."""
     import ctypes as C
-    o = wp._SolveOpts(wp.WP_SOLVE_FP64, 1e-12, 1e-7, 200, 0)
+    o = wp._SolveOpts(wp.SOLVE_MODES[mode], tol, 1e-7, 200, 0)
     b = C.c_void_p()
     wp._check(wp._lib.faddeev_batch_create(L.h, slots, 1 << 33, C.byref(o), C.byref(b)))
     queue = list(energies)
@@ -249,6 +249,40 @@ def test_serving_result_alone_equals_in_mix():
         solo = L.solve([E], "fp64").amplitude(0)
         ref = abs(solo["A"][0, 0])
         assert abs(alone["A"][0, 0] - solo["A"][0, 0]) <= 1e-10 * ref + 30 * max(alone["err"][0], solo["err"][0]) * ref
+
+
+@pytest.mark.parametrize("mode", ["mixed", "mixed_split"])
+def test_mixed_serving_result_alone_equals_in_mix(mode):
+    """Mixed-precision continuous batching (one refinement cycle per step, slots admitted between
+    cycles): a request gives bit-identical numbers alone or among 23 others in a 24-slot batch,
+    and agrees with the FP64 path to 1e-6."""
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    rng = np.random.default_rng(5)
+    mix = list(rng.uniform(1.0, 50.0, 40))
+    probe = [mix[2], mix[19], mix[37]]
+    together = _run_batch(L, mix, slots=24, mode=mode, tol=1e-8)
+    assert len(together) == 40
+    for E in probe:
+        alone = _run_batch(L, [E], slots=24, mode=mode, tol=1e-8)[E]
+        assert np.array_equal(alone["A"], together[E]["A"]), E
+    ref = L.solve(mix, "fp64")
+    for k, E in enumerate(mix):
+        assert np.max(np.abs(together[E]["A"] - ref.amplitude(k)["A"])) <= 1e-6, E
+
+
+def test_many_channel_wide_batch_matches_single():
+    """10 channels: 10 energies x 2 open channels (20 columns, the LDS-staged lanes-over-columns
+    SpMM) against one energy at a time (2 columns, the lanes-over-channel-pairs SpMV)."""
+    spec = SPECS["pw10_mt_8"]
+    L = _lib_lattice(spec)
+    Es = [9.0, 11.0, 14.1, 17.0, 21.0, 26.0, 30.0, 35.0, 40.0, 45.0]
+    many = L.solve(Es, "fp64", allow_noconv=True)
+    for k, E in enumerate(Es):
+        a = many.amplitude(k)
+        b = L.solve([E], "fp64", allow_noconv=True).amplitude(0)
+        ref = np.max(np.abs(b["A"]))
+        assert np.max(np.abs(a["A"] - b["A"])) <= 1e-10 * ref + 30 * max(np.max(a["err"]), np.max(b["err"])) * ref, E
 
 
 def test_wide_batch_matches_single():
