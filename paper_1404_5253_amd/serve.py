@@ -151,10 +151,8 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
             t.start()
         while pending or any(w.queue or w.inflight for w in workers):
             feed()
-            if pending and pending[0].t_arrival > now():
-                sleep(min(0.001, pending[0].t_arrival - now()))
-            else:
-                sleep(0.0005)
+            wait = pending[0].t_arrival - now() if pending else 0.0
+            sleep(min(0.001, wait) if wait > 0 else 0.0005)
         stop.set()
         for t in threads:
             t.join()
@@ -165,7 +163,7 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
             for w in workers:
                 busy |= w.pump()
             if not busy and pending:
-                sleep(max(0.0, pending[0].t_arrival - now()))
+                sleep(max(0.0, pending[0].t_arrival - now()))   # clamped: the clock moves on
     t_end = now()
     done = [r for w in workers for r in w.finished]
     done.sort(key=lambda r: r.rid)
