@@ -850,11 +850,169 @@ __global__ void __launch_bounds__(256) k_step64(RotArgs r, const double* __restr
   }
 }
 
+// FP64 MFMA version (v_mfma_f64_16x16x4f64) for one channel g and 8*CT complex columns
+// (16*CT real columns, re/im adjacent): Y and T tiles [Mp][16 CT + 1] in LDS (padded rows),
+// O and v O^T read as the A operand. Operand layout of the 16x16x4 FP64 instruction: lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; the result D[l/16 + 4v][l%16], v = 0..3.
+typedef double d4v __attribute__((ext_vector_type(4)));
+template <int CT>
+__global__ void __launch_bounds__(256) k_step64m(RotArgs r, const double* __restrict__ Wm,
+                                                 const double2* __restrict__ y, double2* __restrict__ s_out, int Mp) {
+  extern __shared__ double shd[];
+  constexpr int RC = 16 * CT, CC = 8 * CT, RCP = RC + 1;
+  const int M = r.M, B = r.B, nch = r.nch;
+  const int ncol = r.N * B;
+  const int g = blockIdx.y;
+  const size_t woff = (size_t)r.wave[g] * M * M;
+  const double* O = r.A + woff;
+  const double* W = Wm + woff;
+  const int col0 = blockIdx.x * CC;
+  double* YT = shd;              // [Mp][RCP]
+  double* TT = shd + Mp * RCP;   // [Mp][RCP]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < CC * Mp; e += 256) {
+    int i, cc;
+    if (B >= CC) {   // consecutive threads -> consecutive energies
+      i = e / CC;
+      cc = e - i * CC;
+    } else {
+      cc = e / Mp;
+      i = e - cc * Mp;
+    }
+    const int col = col0 + cc;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < M && col < ncol) {
+      const int jj = col / B, cb = col - jj * B;
+      v = y[(((size_t)jj * M + i) * nch + g) * B + cb];
+    }
+    YT[i * RCP + 2 * cc] = v.x;
+    YT[i * RCP + 2 * cc + 1] = v.y;
+  }
+  __syncthreads();
+  const int r16 = lane & 15, q4 = lane >> 4, part = r16 & 1;
+  const int nt = Mp / 16;
+  // each wavefront takes two row tiles at a time: 2 x CT independent accumulator chains
+  for (int kp = wv; 2 * kp < nt; kp += 4) {
+    d4v acc2[2][CT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc2[h][ct] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int krow0 = 2 * kp * 16 + r16, krow1 = krow0 + 16;
+    const double* Ok0 = O + (size_t)min(krow0, M - 1) * M;
+    const double* Ok1 = O + (size_t)min(krow1, M - 1) * M;
+#pragma unroll 4
+    for (int i0 = 0; i0 < Mp; i0 += 4) {
+      const int ic = i0 + q4;
+      const double a0 = (krow0 < M && ic < M) ? Ok0[ic] : 0.0;
+      const double a1 = (krow1 < M && ic < M) ? Ok1[ic] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const double b = YT[ic * RCP + ct * 16 + r16];
+        acc2[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc2[0][ct], 0, 0, 0);
+        acc2[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc2[1][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+    const int kt = 2 * kp + h;
+    if (kt >= nt) break;
+    d4v* acc = acc2[h];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int cc = ct * 8 + (r16 >> 1);
+      const int col = col0 + cc;
+      const bool live = col < ncol;
+      const int jj = live ? col / B : 0, cb = live ? col - jj * B : 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kt * 16 + q4 + 4 * v;
+        const double val = acc[ct][v];
+        const double other = __shfl_xor(val, 1, WARP);
+        const double re = part ? other : val, im = part ? val : other;
+        double out = 0.0;
+        if (live && k < M) {
+          if (r.acap && k == 0 && part == 0 && jj == r.j0[cb]) {
+            for (int f = 0; f < r.nfin; ++f)
+              if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb * r.nfin + f] = make_double2(re, im);
+          }
+          const double2 gv = r.G[(((size_t)jj * M + k) * nch + g) * B + cb];
+          out = part ? (re * gv.y + im * gv.x) : (re * gv.x - im * gv.y);
+        }
+        TT[k * RCP + ct * 16 + r16] = out;
+      }
+    }
+    }
+  }
+  __syncthreads();
+  double* so = reinterpret_cast<double*>(s_out);
+  for (int ip = wv; 2 * ip < nt; ip += 4) {
+    d4v acc2[2][CT];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc2[h][ct] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int irow0 = 2 * ip * 16 + r16, irow1 = irow0 + 16;
+    const double* Wi0 = W + (size_t)min(irow0, M - 1) * M;
+    const double* Wi1 = W + (size_t)min(irow1, M - 1) * M;
+#pragma unroll 4
+    for (int k0 = 0; k0 < Mp; k0 += 4) {
+      const int kc = k0 + q4;
+      const double a0 = (irow0 < M && kc < M) ? Wi0[kc] : 0.0;
+      const double a1 = (irow1 < M && kc < M) ? Wi1[kc] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const double b = TT[kc * RCP + ct * 16 + r16];
+        acc2[0][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc2[0][ct], 0, 0, 0);
+        acc2[1][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc2[1][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+    const int it = 2 * ip + h;
+    if (it >= nt) break;
+    d4v* acc = acc2[h];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      const int cc = ct * 8 + (r16 >> 1);
+      const int col = col0 + cc;
+      if (col >= ncol) continue;
+      const int jj = col / B, cb = col - jj * B;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = it * 16 + q4 + 4 * v;
+        if (i < M) so[2 * ((((size_t)jj * M + i) * nch + g) * B + cb) + part] = acc[ct][v];
+      }
+    }
+    }
+  }
+}
+
+static size_t step64m_lds(int Mp, int ct) { return (size_t)2 * Mp * (16 * ct + 1) * sizeof(double); }
+
 hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s) {
   if (r.M < 1 || r.N < 1 || r.B < 1 || r.nch < 1 || !r.G) return hipErrorInvalidValue;
   const int ncol = r.N * r.B;
+  {
+    // FP64 MFMA tiles: 16 complex columns per workgroup when the two tiles fit 64 KB of LDS and
+    // that still gives every CU a workgroup, else 8
+    const int Mp = (r.M + 15) / 16 * 16;
+    const size_t lim = 64 * 1024;
+    int ct = (step64m_lds(Mp, 2) <= lim && (int64_t)((ncol + 15) / 16) * r.nch >= 256) ? 2 : 1;
+    // a small grid (one energy on few channels) stays with the VALU version, whose wavefronts
+    // run their rows in parallel instead of one MFMA chain per tile
+    if (step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch >= 256) {
+      dim3 grid((ncol + 8 * ct - 1) / (8 * ct), r.nch);
+      if (ct == 2) hipLaunchKernelGGL(k_step64m<2>, grid, dim3(256), step64m_lds(Mp, 2), s, r, W, y, s_out, Mp);
+      else hipLaunchKernelGGL(k_step64m<1>, grid, dim3(256), step64m_lds(Mp, 1), s, r, W, y, s_out, Mp);
+      return hipGetLastError();
+    }
+  }
+  // large M: the VALU version
+  // widest column tile that fits 64 KB of LDS and still gives every CU a workgroup (the threads of a
+  // wavefront then share fewer rows of O, so its loads hit fewer cache lines)
   int tc = 16;
-  while (tc > 2 && ((size_t)2 * r.M * tc * sizeof(double2) > 64 * 1024 || ncol / tc < 64)) tc >>= 1;
+  while (tc > 2 && ((size_t)2 * r.M * tc * sizeof(double2) > 64 * 1024 || (int64_t)(ncol / tc) * r.nch < 256)) tc >>= 1;
   const size_t shmem = (size_t)2 * r.M * tc * sizeof(double2);
   if (shmem > 64 * 1024) return hipErrorInvalidValue;
   dim3 grid((ncol + tc - 1) / tc, r.nch);
@@ -904,7 +1062,30 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int 
   AT ar[NC], ai[NC];
 #pragma unroll
   for (int g = 0; g < NC; ++g) ar[g] = ai[g] = AT(0);
-  for (int64_t e = b0; e < b1; ++e) {
+  int64_t e = b0;
+  for (; e + 4 <= b1; e += 4) {   // four blocks' gathers in flight; sums in block order
+    int cc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cc[u] = col[e + u];
+    XT xv[4][NC];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int gp = 0; gp < NC; ++gp) xv[u][gp] = x[((size_t)cc[u] * NC + gp) * B + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const VT* v = val + (e + u) * NC * NC;
+#pragma unroll
+      for (int gp = 0; gp < NC; ++gp)
+#pragma unroll
+        for (int g = 0; g < NC; ++g) {
+          const AT a = (AT)v[gp * NC + g];
+          ar[g] = fma(a, (AT)xv[u][gp].x, ar[g]);
+          ai[g] = fma(a, (AT)xv[u][gp].y, ai[g]);
+        }
+    }
+  }
+  for (; e < b1; ++e) {
     const int cc = col[e];
     const VT* v = val + e * NC * NC;
 #pragma unroll
