@@ -543,6 +543,19 @@ static wp_status upload_tables(wp_lattice* L) {
   return WP_OK;
 }
 
+// Sub-allocations of one device buffer (256-byte aligned); with base = nullptr it only sizes.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
 extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* stream, wp_perm_stats* stats) {
   if (!L) return fail(WP_EINVAL, "NULL lattice");
   if (precision != WP_P_FP64 && precision != WP_P_FP32) return fail(WP_EINVAL, "precision must be FP64 or FP32");
@@ -553,74 +566,118 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   const int64_t R = (int64_t)M * N;
   PBuildArgs a{M, N, nch, (int)L->keys.size(), L->n_x, L->n_phi, L->d_pe.p, L->d_qe.p, L->d_gx.p,
                L->d_gwx.p, L->d_gp.p, L->d_gwp.p, L->d_keys.p, L->d_C.p};
-  DBuf<int> cnt, lo, segoff;
-  DBuf<int64_t> rowcnt, rowptr_c, tmp, rowptr;
-  size_t nbox = (size_t)N * N * M;
-  if (!cnt.make(&L->al, nbox) || !lo.make(&L->al, nbox) || !segoff.make(&L->al, nbox) || !rowcnt.make(&L->al, R) ||
-      !rowptr_c.make(&L->al, R + 1) || !tmp.make(&L->al, scan_tmp_size(R)) || !rowptr.make(&L->al, R + 1))
-    return fail(WP_ENOMEM, "device allocation (selection)");
+  // Scratch is carved from two grow-only buffers of the lattice (the selection arrays, sized by
+  // the lattice, and the candidate arrays, sized by the candidate count), so that a rebuild
+  // allocates nothing; a buffer above kKeepScratch is released when the build ends.
+  const size_t kKeepScratch = (size_t)512 << 20;
+  const size_t nbox = (size_t)N * N * M;
+  int *cnt, *lo, *segoff;
+  int64_t *rowcnt, *rowptr_c, *tmp, *rowptr;
+  auto sel_layout = [&](char* base) {
+    Carve c{base};
+    cnt = c.take<int>(nbox);
+    lo = c.take<int>(nbox);
+    segoff = c.take<int>(nbox);
+    rowcnt = c.take<int64_t>(R);
+    rowptr_c = c.take<int64_t>(R + 1);
+    tmp = c.take<int64_t>(scan_tmp_size(R));
+    rowptr = c.take<int64_t>(R + 1);
+    return c.off;
+  };
+  const size_t sel_bytes = sel_layout(nullptr);
+  if (L->scratch_sel.n < sel_bytes) {
+    L->scratch_sel.reset();
+    if (!L->scratch_sel.make(&L->al, sel_bytes)) return fail(WP_ENOMEM, "device allocation (selection)");
+  }
+  sel_layout(L->scratch_sel.p);
+  if (L->d_rowptr.n < (size_t)(R + 1)) {
+    L->d_rowptr.reset();
+    if (!L->d_rowptr.make(&L->al, R + 1)) return fail(WP_ENOMEM, "device allocation (row pointer)");
+  }
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0));
   HIPCHECK(hipEventCreate(&e1));
   HIPCHECK(hipEventRecord(e0, s));
-  WP_LAUNCH("select", s, launch_select(a, cnt.p, lo.p, s));
-  WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt.p, segoff.p, rowcnt.p, s));
-  WP_LAUNCH("scan", s, launch_scan(rowcnt.p, rowptr_c.p, R, tmp.p, s));
+  WP_LAUNCH("select", s, launch_select(a, cnt, lo, s));
+  WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt, segoff, rowcnt, s));
+  WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr_c, R, tmp, s));
   int64_t ncand = 0;
-  HIPCHECK(hipMemcpyAsync(&ncand, rowptr_c.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(&ncand, rowptr_c + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  DBuf<int32_t> col_c;
-  DBuf<double> val_c;
-  DBuf<uint8_t> flag;
-  if (!col_c.make(&L->al, std::max<int64_t>(ncand, 1)) || !val_c.make(&L->al, std::max<int64_t>(ncand, 1) * nc2) ||
-      !flag.make(&L->al, std::max<int64_t>(ncand, 1)))
-    return fail(WP_ENOMEM, "device allocation (candidates)");
   const bool general = L->keys.size() > 8;
-  DBuf<double> mom, nrm, Ct;
+  const int nm = (int)L->keys.size();
+  const size_t nc = (size_t)std::max<int64_t>(ncand, 1);
+  int32_t* col_c;
+  double *val_c, *mom, *nrm, *Ct;
+  uint8_t* flag;
+  auto cand_layout = [&](char* base) {
+    Carve c{base};
+    col_c = c.take<int32_t>(nc);
+    val_c = c.take<double>(nc * nc2);
+    flag = c.take<uint8_t>(nc);
+    mom = general ? c.take<double>(nc * nm) : nullptr;
+    nrm = general ? c.take<double>(nc) : nullptr;
+    Ct = general ? c.take<double>((size_t)nm * nc2) : nullptr;
+    return c.off;
+  };
+  const size_t cand_bytes = cand_layout(nullptr);
+  if (L->scratch_cand.n < cand_bytes) {
+    L->scratch_cand.reset();
+    if (!L->scratch_cand.make(&L->al, cand_bytes)) return fail(WP_ENOMEM, "device allocation (candidates)");
+  }
+  cand_layout(L->scratch_cand.p);
   if (ncand > 0 && general) {
     // transposed coefficient table [nmom][nch*nch] for the combine contraction
-    const int nm = (int)L->keys.size();
     std::vector<double> ct((size_t)nm * nc2);
     for (int gg = 0; gg < nc2; ++gg)
       for (int m = 0; m < nm; ++m) ct[(size_t)m * nc2 + gg] = L->C[(size_t)gg * nm + m];
-    if (!mom.make(&L->al, (size_t)ncand * nm) || !nrm.make(&L->al, ncand) || !Ct.make(&L->al, ct.size()))
-      return fail(WP_ENOMEM, "device allocation (moments)");
-    HIPCHECK(hipMemcpyAsync(Ct.p, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
-    WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct.p, cnt.p, lo.p, segoff.p, rowptr_c.p, ncand, col_c.p,
-                                                         mom.p, nrm.p, val_c.p, flag.p, s));
+    HIPCHECK(hipMemcpyAsync(Ct, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
+    WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c,
+                                                         mom, nrm, val_c, flag, s));
   } else if (ncand > 0) {
-    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt.p, lo.p, segoff.p, rowptr_c.p, col_c.p, val_c.p, flag.p, s));
+    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, s));
   }
   if (ncand > 0) {
-    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c.p, flag.p, rowcnt.p, s));
+    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, s));
   } else {
-    HIPCHECK(hipMemsetAsync(rowcnt.p, 0, R * sizeof(int64_t), s));
+    HIPCHECK(hipMemsetAsync(rowcnt, 0, R * sizeof(int64_t), s));
   }
-  WP_LAUNCH("scan", s, launch_scan(rowcnt.p, rowptr.p, R, tmp.p, s));
+  WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr, R, tmp, s));
   int64_t nblk = 0;
-  HIPCHECK(hipMemcpyAsync(&nblk, rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(&nblk, rowptr + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
-  L->d_col.reset();
-  L->d_val64.reset();
-  L->d_val32.reset();
-  if (!L->d_col.make(&L->al, std::max<int64_t>(nblk, 1))) return fail(WP_ENOMEM, "device allocation (P0 columns)");
+  // the resident P0 arrays are reused by a rebuild that fits them (grow-only); the other
+  // precision's copy, derived from the previous P0, is dropped
+  const size_t nb1 = (size_t)std::max<int64_t>(nblk, 1);
+  if (L->d_col.n < nb1) {
+    L->d_col.reset();
+    if (!L->d_col.make(&L->al, nb1)) return fail(WP_ENOMEM, "device allocation (P0 columns)");
+  }
   if (precision == WP_P_FP64) {
-    if (!L->d_val64.make(&L->al, std::max<int64_t>(nblk, 1) * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+    L->d_val32.reset();
+    if (L->d_val64.n < nb1 * nc2) {
+      L->d_val64.reset();
+      if (!L->d_val64.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+    }
   } else {
-    if (!L->d_val32.make(&L->al, std::max<int64_t>(nblk, 1) * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+    L->d_val64.reset();
+    if (L->d_val32.n < nb1 * nc2) {
+      L->d_val32.reset();
+      if (!L->d_val32.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+    }
   }
   if (ncand > 0)
-    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c.p, col_c.p, val_c.p, flag.p, rowptr.p, L->d_col.p,
+    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, rowptr, L->d_col.p,
                                            L->d_val64.p, L->d_val32.p, s));
+  HIPCHECK(hipMemcpyAsync(L->d_rowptr.p, rowptr, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  std::swap(L->d_rowptr.p, rowptr.p);
-  std::swap(L->d_rowptr.n, rowptr.n);
-  L->d_rowptr.al = &L->al;
+  if (L->scratch_sel.n > kKeepScratch) L->scratch_sel.reset();
+  if (L->scratch_cand.n > kKeepScratch) L->scratch_cand.reset();
   L->d_order.reset();   // the SpMV row order is derived from this P0 at its first use
   L->blocks = nblk;
   L->prec = precision;

@@ -153,23 +153,40 @@ hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) 
 
 // ------------------------------------------------------------------ row segments
 
+// Four threads per row r = j*M + i: thread h sums the candidate counts of the boxes jp in its
+// quarter, the four sums are scanned by shuffles, then each thread writes its boxes' offsets.
 __global__ void k_rowseg(int M, int N, const int* __restrict__ cnt, int* __restrict__ segoff,
                          int64_t* __restrict__ rowcnt) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;   // r = j*M + i
-  if (r >= M * N) return;
-  int j = r / M, i = r - j * M;
-  int64_t run = 0;
-  for (int jp = 0; jp < N; ++jp) {
-    size_t idx = ((size_t)j * N + jp) * M + i;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = t >> 2;
+  const int h = (int)(t & 3);
+  const bool live = r < (int64_t)M * N;
+  const int j = live ? (int)(r / M) : 0, i = live ? (int)(r - (int64_t)j * M) : 0;
+  const int q = (N + 3) / 4, jp0 = min(N, h * q), jp1 = min(N, jp0 + q);
+  int64_t part = 0;
+  if (live)
+    for (int jp = jp0; jp < jp1; ++jp) part += cnt[((size_t)j * N + jp) * M + i];
+  // exclusive prefix over the four quarters of the row (lanes 4k .. 4k+3 of the wavefront)
+  const int lane = threadIdx.x & 63, base = lane & ~3;
+  int64_t before = 0, total = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int64_t v = __shfl(part, base + k, WARP);
+    if (k < h) before += v;
+    total += v;
+  }
+  if (!live) return;
+  int64_t run = before;
+  for (int jp = jp0; jp < jp1; ++jp) {
+    const size_t idx = ((size_t)j * N + jp) * M + i;
     segoff[idx] = (int)run;
     run += cnt[idx];
   }
-  rowcnt[r] = run;
+  if (h == 0) rowcnt[r] = total;
 }
 
 hipError_t launch_rowseg(int M, int N, const int* cnt, int* segoff, int64_t* rowcnt, hipStream_t s) {
-  int R = M * N;
-  hipLaunchKernelGGL(k_rowseg, dim3((R + 255) / 256), dim3(256), 0, s, M, N, cnt, segoff, rowcnt);
+  const int64_t T = (int64_t)M * N * 4;   // four threads per row
+  hipLaunchKernelGGL(k_rowseg, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, s, M, N, cnt, segoff, rowcnt);
   return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct wp_lattice {
   DBuf<int64_t> d_rowptr;
   DBuf<int32_t> d_col;
   DBuf<int32_t> d_order;   // block rows by decreasing length (ties by index): SpMV work order
+  DBuf<char> scratch_sel, scratch_cand;   // P0 build scratch kept between builds (grow-only)
   // pinned host staging of the captured series terms (FP64 solve), reused across calls
   std::mutex pin_mu;
   double2* pin = nullptr;
