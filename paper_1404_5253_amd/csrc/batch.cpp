@@ -53,7 +53,8 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   if (!L->d_val64.p) return fail(WP_ENOTREADY, "batch needs P0 built with WP_P_FP64");
   if (o->tol <= 0 || o->accept <= 0 || o->max_iter < 4) return fail(WP_EINVAL, "bad solve options");
   if (wp_status st = upload_waves(L)) return st;
-  if (wp_status st = ensure_order(L)) return st;
+  if (wp_status st = ensure_order(L, nullptr)) return st;
+  HIPCHECK(hipStreamSynchronize(nullptr));   // the order is ready before any step, on any stream
   std::unique_ptr<wp_batch> b(new wp_batch());
   b->L = L;
   b->o = *o;

@@ -441,7 +441,7 @@ wp_status wpcd::upload_waves(wp_lattice* L) {
 }
 
 bool wpcd::g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w) {
-  return w.make(&L->al, (size_t)g1_work_elems((int)L->waves.size(), L->M, L->N, nE) + 1);
+  return grow(w, &L->al, (size_t)g1_work_elems((int)L->waves.size(), L->M, L->N, nE) + 1);
 }
 
 G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G,
@@ -543,6 +543,14 @@ static wp_status upload_tables(wp_lattice* L) {
   return WP_OK;
 }
 
+// Destroys an event when the scope ends.
+struct EventGuard {
+  hipEvent_t e;
+  ~EventGuard() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // Sub-allocations of one device buffer (256-byte aligned); with base = nullptr it only sizes.
 struct Carve {
   char* base;
@@ -569,10 +577,14 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   // Scratch is carved from two grow-only buffers of the lattice (the selection arrays, sized by
   // the lattice, and the candidate arrays, sized by the candidate count), so that a rebuild
   // allocates nothing; a buffer above kKeepScratch is released when the build ends.
+  // A rebuild whose candidate scratch and resident P0 arrays already exist runs every stage with
+  // their capacities as bounds and reads the two totals (candidates, kept blocks) once at the end;
+  // a first build, or one that outgrew those capacities, sizes each stage from the previous
+  // stage's total instead (two host round trips).
   const size_t kKeepScratch = (size_t)512 << 20;
   const size_t nbox = (size_t)N * N * M;
   int *cnt, *lo, *segoff;
-  int64_t *rowcnt, *rowptr_c, *tmp, *rowptr;
+  int64_t *rowcnt, *rowptr_c, *tmp;
   auto sel_layout = [&](char* base) {
     Carve c{base};
     cnt = c.take<int>(nbox);
@@ -581,7 +593,6 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     rowcnt = c.take<int64_t>(R);
     rowptr_c = c.take<int64_t>(R + 1);
     tmp = c.take<int64_t>(scan_tmp_size(R));
-    rowptr = c.take<int64_t>(R + 1);
     return c.off;
   };
   const size_t sel_bytes = sel_layout(nullptr);
@@ -594,23 +605,16 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     L->d_rowptr.reset();
     if (!L->d_rowptr.make(&L->al, R + 1)) return fail(WP_ENOMEM, "device allocation (row pointer)");
   }
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0));
-  HIPCHECK(hipEventCreate(&e1));
-  HIPCHECK(hipEventRecord(e0, s));
-  WP_LAUNCH("select", s, launch_select(a, cnt, lo, s));
-  WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt, segoff, rowcnt, s));
-  WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr_c, R, tmp, s));
-  int64_t ncand = 0;
-  HIPCHECK(hipMemcpyAsync(&ncand, rowptr_c + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
+  if (!L->h_tot) HIPCHECK(hipHostMalloc((void**)&L->h_tot, 2 * sizeof(int64_t)));
+  // the other precision's copy, derived from the previous P0, is dropped
+  if (precision == WP_P_FP64) L->d_val32.reset();
+  else L->d_val64.reset();
   const bool general = L->keys.size() > 8;
   const int nm = (int)L->keys.size();
-  const size_t nc = (size_t)std::max<int64_t>(ncand, 1);
   int32_t* col_c;
   double *val_c, *mom, *nrm, *Ct;
   uint8_t* flag;
-  auto cand_layout = [&](char* base) {
+  auto cand_layout = [&](char* base, size_t nc) {
     Carve c{base};
     col_c = c.take<int32_t>(nc);
     val_c = c.take<double>(nc * nc2);
@@ -620,65 +624,107 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     Ct = general ? c.take<double>((size_t)nm * nc2) : nullptr;
     return c.off;
   };
-  const size_t cand_bytes = cand_layout(nullptr);
-  if (L->scratch_cand.n < cand_bytes) {
-    L->scratch_cand.reset();
-    if (!L->scratch_cand.make(&L->al, cand_bytes)) return fail(WP_ENOMEM, "device allocation (candidates)");
+  auto blk_cap = [&]() -> int64_t {
+    const size_t nv = precision == WP_P_FP64 ? L->d_val64.n : L->d_val32.n;
+    return (int64_t)std::min(L->d_col.n, nv / (size_t)nc2);
+  };
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(hipEventCreate(&e0));
+  EventGuard eg0{e0};
+  HIPCHECK(hipEventCreate(&e1));
+  EventGuard eg1{e1};
+  HIPCHECK(hipEventRecord(e0, s));
+  WP_LAUNCH("select", s, launch_select(a, cnt, lo, s));
+  WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt, segoff, rowcnt, s));
+  WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr_c, R, tmp, s));
+  int64_t ncand = -1, nblk = -1;
+  bool done = false;
+  const int64_t bcap0 = blk_cap();
+  if (!general && L->cand_cap > 0 && bcap0 > 0) {
+    cand_layout(L->scratch_cand.p, (size_t)L->cand_cap);
+    val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
+    val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
+    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s));
+    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
+    WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
+    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p, val64,
+                                           val32, L->cand_cap, bcap0, s));
+    WP_LAUNCH("totals", s, launch_totals(rowptr_c + R, L->d_rowptr.p + R, L->h_tot, s));
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
+    ncand = L->h_tot[0];
+    nblk = L->h_tot[1];
+    done = ncand <= L->cand_cap && nblk <= bcap0;
   }
-  cand_layout(L->scratch_cand.p);
-  if (ncand > 0 && general) {
-    // transposed coefficient table [nmom][nch*nch] for the combine contraction
-    std::vector<double> ct((size_t)nm * nc2);
-    for (int gg = 0; gg < nc2; ++gg)
-      for (int m = 0; m < nm; ++m) ct[(size_t)m * nc2 + gg] = L->C[(size_t)gg * nm + m];
-    HIPCHECK(hipMemcpyAsync(Ct, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
-    WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c,
-                                                         mom, nrm, val_c, flag, s));
-  } else if (ncand > 0) {
-    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, s));
-  }
-  if (ncand > 0) {
-    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, s));
-  } else {
-    HIPCHECK(hipMemsetAsync(rowcnt, 0, R * sizeof(int64_t), s));
-  }
-  WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr, R, tmp, s));
-  int64_t nblk = 0;
-  HIPCHECK(hipMemcpyAsync(&nblk, rowptr + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
-  // the resident P0 arrays are reused by a rebuild that fits them (grow-only); the other
-  // precision's copy, derived from the previous P0, is dropped
-  const size_t nb1 = (size_t)std::max<int64_t>(nblk, 1);
-  if (L->d_col.n < nb1) {
-    L->d_col.reset();
-    if (!L->d_col.make(&L->al, nb1)) return fail(WP_ENOMEM, "device allocation (P0 columns)");
-  }
-  if (precision == WP_P_FP64) {
-    L->d_val32.reset();
-    if (L->d_val64.n < nb1 * nc2) {
-      L->d_val64.reset();
-      if (!L->d_val64.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+  if (!done) {
+    if (ncand < 0) {
+      HIPCHECK(hipMemcpyAsync(L->h_tot, rowptr_c + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      ncand = L->h_tot[0];
     }
-  } else {
-    L->d_val64.reset();
-    if (L->d_val32.n < nb1 * nc2) {
-      L->d_val32.reset();
-      if (!L->d_val32.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+    const size_t nc = (size_t)std::max<int64_t>(ncand, 1);
+    if ((size_t)L->cand_cap < nc) {
+      L->scratch_cand.reset();
+      L->cand_cap = 0;
+      if (!L->scratch_cand.make(&L->al, cand_layout(nullptr, nc))) return fail(WP_ENOMEM, "device allocation (candidates)");
+      L->cand_cap = (int64_t)nc;
     }
+    cand_layout(L->scratch_cand.p, (size_t)L->cand_cap);
+    if (ncand > 0 && general) {
+      // transposed coefficient table [nmom][nch*nch] for the combine contraction
+      std::vector<double> ct((size_t)nm * nc2);
+      for (int gg = 0; gg < nc2; ++gg)
+        for (int m = 0; m < nm; ++m) ct[(size_t)m * nc2 + gg] = L->C[(size_t)gg * nm + m];
+      HIPCHECK(hipMemcpyAsync(Ct, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
+      WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c,
+                                                           mom, nrm, val_c, flag, s));
+    } else if (ncand > 0) {
+      WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s));
+    }
+    if (ncand > 0) {
+      WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
+    } else {
+      HIPCHECK(hipMemsetAsync(rowcnt, 0, R * sizeof(int64_t), s));
+    }
+    WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
+    HIPCHECK(hipMemcpyAsync(L->h_tot + 1, L->d_rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    nblk = L->h_tot[1];
+    // the resident P0 arrays are reused by a rebuild that fits them (grow-only)
+    const size_t nb1 = (size_t)std::max<int64_t>(nblk, 1);
+    if (L->d_col.n < nb1) {
+      L->d_col.reset();
+      if (!L->d_col.make(&L->al, nb1)) return fail(WP_ENOMEM, "device allocation (P0 columns)");
+    }
+    if (precision == WP_P_FP64) {
+      if (L->d_val64.n < nb1 * nc2) {
+        L->d_val64.reset();
+        if (!L->d_val64.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+      }
+    } else {
+      if (L->d_val32.n < nb1 * nc2) {
+        L->d_val32.reset();
+        if (!L->d_val32.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+      }
+    }
+    val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
+    val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
+    if (ncand > 0)
+      WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p,
+                                             val64, val32, L->cand_cap, blk_cap(), s));
+    HIPCHECK(hipEventRecord(e1, s));
+    HIPCHECK(hipEventSynchronize(e1));
   }
-  if (ncand > 0)
-    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, rowptr, L->d_col.p,
-                                           L->d_val64.p, L->d_val32.p, s));
-  HIPCHECK(hipMemcpyAsync(L->d_rowptr.p, rowptr, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-  HIPCHECK(hipEventRecord(e1, s));
-  HIPCHECK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (L->scratch_sel.n > kKeepScratch) L->scratch_sel.reset();
-  if (L->scratch_cand.n > kKeepScratch) L->scratch_cand.reset();
-  L->d_order.reset();   // the SpMV row order is derived from this P0 at its first use
+  if (L->scratch_cand.n > kKeepScratch) {
+    L->scratch_cand.reset();
+    L->cand_cap = 0;
+  }
+  L->order_ok = false;   // the SpMV row order is derived from this P0 at its first use
   L->blocks = nblk;
   L->prec = precision;
   L->have_P = true;
@@ -722,21 +768,22 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
 // decreasing length, ties by index, so that the longest rows start first and do not trail at the
 // end of a launch (rows hold 0 to ~10x the median number of blocks); the measured alternative,
 // lattice order in one contiguous chunk per XCD, was slower.
-wp_status wpcd::ensure_order(wp_lattice* L) {
-  if (L->d_order.p || !L->have_P) return WP_OK;
+// Computed on the device on stream s after each build; a call on another stream waits for it.
+wp_status wpcd::ensure_order(wp_lattice* L, hipStream_t s) {
+  if (!L->have_P) return WP_OK;
+  std::lock_guard<std::mutex> lk(L->order_mu);
+  if (!L->order_ev) HIPCHECK(hipEventCreateWithFlags(&L->order_ev, hipEventDisableTiming));
+  if (L->order_ok) {
+    HIPCHECK(hipStreamWaitEvent(s, L->order_ev, 0));
+    return WP_OK;
+  }
   const int64_t R = (int64_t)L->M * L->N;
-  std::vector<int64_t> rp(R + 1);
-  HIPCHECK(hipMemcpy(rp.data(), L->d_rowptr.p, (R + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
-  std::vector<int32_t> ord(R);
-  for (int64_t r = 0; r < R; ++r) ord[r] = (int32_t)r;
-  std::stable_sort(ord.begin(), ord.end(),
-                   [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
-  if (!L->d_order.make(&L->al, R)) return fail(WP_ENOMEM, "device allocation (row order)");
-  HIPCHECK(hipMemcpy(L->d_order.p, ord.data(), R * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!grow(L->d_order, &L->al, (size_t)R)) return fail(WP_ENOMEM, "device allocation (row order)");
+  WP_LAUNCH("row_order", s, launch_row_order(R, L->d_rowptr.p, L->d_order.p, s));
+  HIPCHECK(hipEventRecord(L->order_ev, s));
+  L->order_ok = true;
   return WP_OK;
 }
-
-
 
 static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                             wp_solution* sol) {
@@ -762,15 +809,21 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const int max_iter = std::max(4, std::min(1000, o.max_iter));
   const int chunk = 8;
   if (wp_status us = upload_waves(L)) return us;
-  if (wp_status so = ensure_order(L)) return so;
-  DBuf<double2> dG, dy, dt, ds, dacap;
-  DBuf<int> dj0, dg0, dfin;
-  DBuf<double> dE;
-  DBuf<int64_t> g1w;
+  if (wp_status so = ensure_order(L, s)) return so;
+  // the lattice's workspace when no other call holds it, else one of this call's own
+  std::unique_lock<std::mutex> ws_lock(L->ws_mu, std::try_to_lock);
+  wp_lattice::Solve64WS own_ws;
+  wp_lattice::Solve64WS& ws = ws_lock.owns_lock() ? L->ws64 : own_ws;
+  StreamDrain drain{s};   // idle stream before the workspace is released or handed on
+  DBuf<double2>&dG = ws.dG, &dy = ws.dy, &dt = ws.dt, &ds = ws.ds, &dacap = ws.dacap;
+  DBuf<int>&dj0 = ws.dj0, &dg0 = ws.dg0, &dfin = ws.dfin;
+  DBuf<double>& dE = ws.dE;
+  DBuf<int64_t>& g1w = ws.g1w;
+  DevAlloc* al = &L->al;
   if (!g1_work(L, nE, g1w)) return fail(WP_ENOMEM, "device allocation (G1 work list)");
-  if (!dG.make(&L->al, D * B) || !dy.make(&L->al, D * B) || !dt.make(&L->al, D * B) || !ds.make(&L->al, D * B) ||
-      !dacap.make(&L->al, (size_t)(max_iter + chunk) * B * nfin) || !dj0.make(&L->al, B) || !dg0.make(&L->al, B) ||
-      !dfin.make(&L->al, nfin) || !dE.make(&L->al, nE))
+  if (!grow(dG, al, D * B) || !grow(dy, al, D * B) || !grow(dt, al, D * B) || !grow(ds, al, D * B) ||
+      !grow(dacap, al, (size_t)(max_iter + chunk) * B * nfin) || !grow(dj0, al, B) || !grow(dg0, al, B) ||
+      !grow(dfin, al, nfin) || !grow(dE, al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
   WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p, g1w), s));

@@ -52,26 +52,47 @@ struct Node {
   double r1, r2, z1, Q1, Q2, w, x, c, s;
 };
 
-// Quadrature node nd of q-box (j, jp): x_a on [-1, 1], phi_b on [phi1, phi2] with
+// Quadrature nodes of q-box (j, jp): x_a on [-1, 1], phi_b on [phi1, phi2] with
 // phi1 = atan(q'_{j'-1}/q_j), phi2 = atan(q'_{j'}/q_{j-1}); zeta1, zeta2 and the Q range of the box.
-__device__ Node box_node(const PBuildArgs& a, int j, int jp, int nd) {
+// What depends on phi alone (cos, sin, the Q range) is tabulated once per phi node by
+// box_phi_table, and box_node_at completes node nd = a * n_phi + b from that table; the values are
+// the same, operation by operation, as evaluating every node from scratch.
+#define PHI_STRIDE 5   // c, s, Q1, Q2, phi-weight factor per phi node
+// phi node ib of the box into tab[ib * PHI_STRIDE ...]
+__device__ void box_phi_row(const PBuildArgs& a, int j, int jp, int ib, double* tab) {
+  const double qa = a.qe[j], qb = a.qe[j + 1], qpa = a.qe[jp], qpb = a.qe[jp + 1];
+  const double phi1 = atan2(qpa, qb), phi2 = atan2(qpb, qa);
+  const double hphi = 0.5 * (phi2 - phi1);
+  const double phi = 0.5 * (phi1 + phi2) + hphi * a.gp[ib];
+  double c, sn;
+  sincos(phi, &sn, &c);
+  double* t = tab + ib * PHI_STRIDE;
+  t[0] = c;
+  t[1] = sn;
+  t[2] = fmax(qa / c, qpa / sn);
+  t[3] = fmin(qb / c, qpb / sn);
+  t[4] = hphi;
+}
+__device__ Node box_node_at(const PBuildArgs& a, const double* tab, int nd) {
   Node n;
-  int ia = nd / a.n_phi, ib = nd - ia * a.n_phi;
-  double qa = a.qe[j], qb = a.qe[j + 1], qpa = a.qe[jp], qpb = a.qe[jp + 1];
-  double phi1 = atan2(qpa, qb), phi2 = atan2(qpb, qa);
-  double hphi = 0.5 * (phi2 - phi1);
-  double phi = 0.5 * (phi1 + phi2) + hphi * a.gp[ib];
-  n.w = a.gwx[ia] * hphi * a.gwp[ib];
+  const int ia = nd / a.n_phi, ib = nd - ia * a.n_phi;
+  const double* t = tab + ib * PHI_STRIDE;
+  n.c = t[0];
+  n.s = t[1];
+  n.Q1 = t[2];
+  n.Q2 = t[3];
+  n.w = a.gwx[ia] * t[4] * a.gwp[ib];
   n.x = a.gx[ia];
-  sincos(phi, &n.s, &n.c);
-  double cs = n.c * n.s;
+  const double cs = n.c * n.s;
   n.z1 = sqrt(n.c * n.c + 0.25 * n.s * n.s + n.x * cs);
-  double z2 = sqrt(0.25 * n.c * n.c + n.s * n.s + n.x * cs);
+  const double z2 = sqrt(0.25 * n.c * n.c + n.s * n.s + n.x * cs);
   n.r1 = 1.0 / n.z1;
   n.r2 = 1.0 / z2;
-  n.Q1 = fmax(qa / n.c, qpa / n.s);
-  n.Q2 = fmin(qb / n.c, qpb / n.s);
   return n;
+}
+// the phi table of box (j, jp) in LDS, filled by the first n_phi threads of the workgroup
+__device__ __forceinline__ void fill_phi_table(const PBuildArgs& a, int j, int jp, double* tab) {
+  for (int ib = threadIdx.x; ib < a.n_phi; ib += blockDim.x) box_phi_row(a, j, jp, ib, tab);
 }
 
 // ------------------------------------------------------------------ step 2: selection
@@ -89,12 +110,15 @@ __global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ 
   double* s_z1 = s_r2 + nn;
   double* s_Q1 = s_z1 + nn;
   double* s_Q2 = s_Q1 + nn;
+  double* s_phi = s_Q2 + nn;     // n_phi * PHI_STRIDE
   const int box = blockIdx.x;
   const int j = box / a.N, jp = box - j * a.N;
   const int t = threadIdx.x;
   for (int i = t; i <= M; i += blockDim.x) spe[i] = a.pe[i];
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
   for (int nd = t; nd < nn; nd += blockDim.x) {
-    Node n = box_node(a, j, jp, nd);
+    Node n = box_node_at(a, s_phi, nd);
     s_r2[nd] = n.r2;
     s_z1[nd] = n.z1;
     s_Q1[nd] = n.Q1;
@@ -143,10 +167,154 @@ __global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ 
   }
 }
 
+// The same selection with the node data held in registers: one wavefront per q-box, lane l takes
+// the nodes nd = (l mod 8) + 8u and the rows i = (l / 8) + 8k; the per-row hull bounds are reduced
+// over the eight lanes that share a row, then the binary searches run with lanes over rows. min and
+// max are exact, so the hull is the same as node-by-node in one lane.
+// Rows are first restricted exactly: node n can be active in row i only if p_{i-1} r2 < Q2 and
+// p_i r2 > Q1 (A >= p_{i-1} r2, B <= p_i r2), and with a positive factor r2 the rounded products are
+// nondecreasing in i, so these rows form an interval [i0(n), i1(n)) found by binary search with the
+// same products; rows outside the union's hull have no active node and get an empty p' range.
+template <int NPL>
+__global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict__ cnt, int* __restrict__ lo_out) {
+  extern __shared__ double sh[];
+  const int M = a.M;
+  const int nn = a.n_x * a.n_phi;
+  double* spe = sh;              // M + 1
+  double* s_r2 = spe + M + 1;    // nn
+  double* s_z1 = s_r2 + nn;
+  double* s_Q1 = s_z1 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_phi = s_Q2 + nn;     // n_phi * PHI_STRIDE
+  double* s_xlo = s_phi + PHI_STRIDE * a.n_phi;   // M
+  double* s_xhi = s_xlo + M;                      // M
+  const int box = blockIdx.x;
+  const int j = box / a.N, jp = box - j * a.N;
+  const int t = threadIdx.x;
+  for (int i = t; i <= M; i += 64) spe[i] = a.pe[i];
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
+  for (int nd = t; nd < nn; nd += 64) {
+    Node n = box_node_at(a, s_phi, nd);
+    s_r2[nd] = n.r2;
+    s_z1[nd] = n.z1;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
+  }
+  __syncthreads();
+  // hull [ilo, ihi) of the rows where any node can be active
+  int ilo = M, ihi = 0;
+  for (int nd = t; nd < nn; nd += 64) {
+    const double r2n = s_r2[nd], Q1n = s_Q1[nd], Q2n = s_Q2[nd];
+    if (!(Q1n < Q2n)) continue;
+    int lo = 0, hi = M;   // i1: smallest i in [0, M] with p_{i-1} r2 >= Q2 (pe[M] r2 treated as >= Q2)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (spe[mid] * r2n >= Q2n) hi = mid;
+      else lo = mid + 1;
+    }
+    const int i1 = lo;
+    lo = 0;
+    hi = M;               // i0: smallest i in [0, M] with p_i r2 > Q1 (i = M: none)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (spe[mid + 1] * r2n > Q1n) hi = mid;
+      else lo = mid + 1;
+    }
+    const int i0 = lo;
+    if (i0 < i1) {
+      ilo = min(ilo, i0);
+      ihi = max(ihi, i1);
+    }
+  }
+  ilo = wave_min(ilo);
+  ihi = wave_max(ihi);
+  for (int i = t; i < M; i += 64)
+    if (i < ilo || i >= ihi) {
+      s_xlo[i] = INFINITY;
+      s_xhi[i] = -INFINITY;
+    }
+  const int ng = t & 7, rg = t >> 3;
+  double r2[NPL], z1[NPL], Q1[NPL], Q2[NPL];
+#pragma unroll
+  for (int u = 0; u < NPL; ++u) {
+    const int nd = ng + 8 * u;
+    const bool ok = nd < nn;
+    r2[u] = ok ? s_r2[nd] : 0.0;
+    z1[u] = ok ? s_z1[nd] : 0.0;
+    Q1[u] = ok ? s_Q1[nd] : 1.0;   // padding nodes: A >= 1 > 0 >= B, never active
+    Q2[u] = ok ? s_Q2[nd] : 0.0;
+  }
+  for (int i0 = ilo; i0 < ihi; i0 += 8) {
+    const int i = i0 + rg;
+    const int ic = i < M ? i : M - 1;
+    const double pa = spe[ic], pb = spe[ic + 1];
+    double xlo = INFINITY, xhi = -INFINITY;
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+      const double A = fmax(Q1[u], pa * r2[u]);
+      const double B = fmin(Q2[u], pb * r2[u]);
+      if (A < B) {
+        xlo = fmin(xlo, A * z1[u]);
+        xhi = fmax(xhi, B * z1[u]);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      xlo = fmin(xlo, __shfl_xor(xlo, o, WARP));
+      xhi = fmax(xhi, __shfl_xor(xhi, o, WARP));
+    }
+    if (ng == 0 && i < ihi) {
+      s_xlo[i] = xlo;
+      s_xhi[i] = xhi;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < M; i += 64) {
+    const double xlo = s_xlo[i], xhi = s_xhi[i];
+    int c = 0, l2 = 0;
+    if (xlo < xhi) {
+      int lo = 0, hi = M;   // smallest e in [1, M] with spe[e] > xlo
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (spe[mid] > xlo) hi = mid;
+        else lo = mid + 1;
+      }
+      int blo = max(lo - 1, 0);
+      lo = 0;
+      hi = M;
+      while (lo < hi) {  // smallest e in [0, M] with spe[e] >= xhi
+        int mid = (lo + hi) >> 1;
+        if (spe[mid] >= xhi) hi = mid;
+        else lo = mid + 1;
+      }
+      int bhi = min(lo - 1, M - 1);
+      if (bhi >= blo) {
+        l2 = max(0, blo - 1);
+        int h2 = min(M - 1, bhi + 1);
+        c = h2 - l2 + 1;
+      }
+    }
+    cnt[(size_t)box * M + i] = c;
+    lo_out[(size_t)box * M + i] = l2;
+  }
+}
+
 hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) {
   int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > 256 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
-  size_t shmem = (a.M + 1) * sizeof(double) + 4 * nn * sizeof(double);
+  if (nn <= 128) {
+    // node data in registers: 8 lanes per row, nn / 8 nodes per lane
+    const size_t sh = (a.M + 1) * sizeof(double) + (4 * nn + PHI_STRIDE * a.n_phi + 2 * a.M) * sizeof(double);
+    if (sh <= 64 * 1024) {
+      const int npl = (nn + 7) / 8;
+      if (npl <= 4) hipLaunchKernelGGL(k_select_reg<4>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
+      else if (npl <= 8) hipLaunchKernelGGL(k_select_reg<8>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
+      else hipLaunchKernelGGL(k_select_reg<16>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
+      return hipGetLastError();
+    }
+  }
+  size_t shmem = (a.M + 1) * sizeof(double) + (4 * nn + PHI_STRIDE * a.n_phi) * sizeof(double);
   hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(128), shmem, s, a, cnt, lo);
   return hipGetLastError();
 }
@@ -262,8 +430,104 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
 
 size_t scan_tmp_size(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1); }
 
+// Up to SCAN1_MAX entries: one workgroup of 1024 threads, thread t scanning its own run of
+// consecutive entries, the run totals scanned across the workgroup (one launch instead of three).
+#define SCAN1_T 1024
+#define SCAN1_MAX (SCAN1_T * 32)
+__global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restrict__ in, int64_t* __restrict__ out,
+                                                        int64_t n) {
+  __shared__ int64_t wsum[SCAN1_T / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
+  const int64_t b0 = min(n, (int64_t)t * per), b1 = min(n, b0 + per);
+  int64_t loc = 0;
+  for (int64_t k = b0; k < b1; ++k) loc += in[k];
+  int64_t x = loc;   // inclusive scan over the wavefront
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, WARP);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int w = 0; w < SCAN1_T / 64; ++w) {
+    const int64_t v = wsum[w];
+    if (w < wv) before += v;
+    total += v;
+  }
+  int64_t run = before + x - loc;
+  for (int64_t k = b0; k < b1; ++k) {
+    const int64_t v = in[k];
+    out[k] = run;
+    run += v;
+  }
+  if (t == 0) out[n] = total;
+}
+
+// the two totals of a build (candidates, kept blocks), stored straight into pinned host memory
+__global__ void k_totals(const int64_t* __restrict__ a, const int64_t* __restrict__ b, int64_t* __restrict__ host) {
+  if (threadIdx.x == 0) {
+    host[0] = *a;
+    host[1] = *b;
+  }
+}
+
+hipError_t launch_totals(const int64_t* a, const int64_t* b, int64_t* host, hipStream_t s) {
+  hipLaunchKernelGGL(k_totals, dim3(1), dim3(64), 0, s, a, b, host);
+  return hipGetLastError();
+}
+
+// SpMV work order: the block rows by decreasing length (counting sort over 256 length buckets,
+// rows of 255 blocks or more sharing the first), in one workgroup. Rows of one bucket land in
+// arbitrary order; every row's product is computed on its own, so the order changes no result.
+__global__ void __launch_bounds__(1024) k_row_order(int64_t R, const int64_t* __restrict__ rowptr,
+                                                    int32_t* __restrict__ order) {
+  __shared__ int hist[256];
+  const int t = threadIdx.x;
+  if (t < 256) hist[t] = 0;
+  __syncthreads();
+  for (int64_t r = t; r < R; r += 1024) {
+    const int64_t len = rowptr[r + 1] - rowptr[r];
+    atomicAdd(&hist[255 - (int)min(len, (int64_t)255)], 1);
+  }
+  __syncthreads();
+  if (t < 64) {   // exclusive scan of the 256 bucket counts, four per lane
+    int v[4], loc = 0;
+    for (int k = 0; k < 4; ++k) {
+      v[k] = hist[4 * t + k];
+      loc += v[k];
+    }
+    int x = loc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, WARP);
+      if (t >= o) x += y;
+    }
+    int run = x - loc;
+    for (int k = 0; k < 4; ++k) {
+      hist[4 * t + k] = run;
+      run += v[k];
+    }
+  }
+  __syncthreads();
+  for (int64_t r = t; r < R; r += 1024) {
+    const int64_t len = rowptr[r + 1] - rowptr[r];
+    const int pos = atomicAdd(&hist[255 - (int)min(len, (int64_t)255)], 1);
+    order[pos] = (int32_t)r;
+  }
+}
+
+hipError_t launch_row_order(int64_t R, const int64_t* rowptr, int32_t* order, hipStream_t s) {
+  if (R < 1 || R > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_row_order, dim3(1), dim3(1024), 0, s, R, rowptr, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
   if (n <= 0) return hipErrorInvalidValue;
+  if (n <= SCAN1_MAX) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_T), 0, s, in, out, n);
+    return hipGetLastError();
+  }
   int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
   hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(SCAN_T), 0, s, in, out, n, tmp);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_T), 0, s, tmp, nb, out + n);
@@ -298,20 +562,22 @@ template <int NMOM>
 __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
                                                const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
                                                int32_t* __restrict__ col_c, double* __restrict__ val_c,
-                                               uint8_t* __restrict__ flag) {
+                                               uint8_t* __restrict__ flag, int64_t cap) {
   extern __shared__ double sh[];
   const int M = a.M, N = a.N;
   const int nn = a.n_x * a.n_phi;
   const int box = blockIdx.x;
   const int j = box / N, jp = box - j * N;
   const int t = threadIdx.x;
-  // LDS: r1, r2, Q1, Q2 [nn], weights [NMOM][nn], pe [M+1], pref [M+1] (int), lo [M] (int)
+  // LDS: r1, r2, Q1, Q2 [nn], weights [NMOM][nn], phi table [n_phi][PHI_STRIDE], pe [M+1],
+  // pref [M+1] (int), lo [M] (int)
   double* s_r1 = sh;
   double* s_r2 = s_r1 + nn;
   double* s_Q1 = s_r2 + nn;
   double* s_Q2 = s_Q1 + nn;
   double* s_w = s_Q2 + nn;
-  double* s_pe = s_w + NMOM * nn;
+  double* s_phi = s_w + NMOM * nn;
+  double* s_pe = s_phi + PHI_STRIDE * a.n_phi;
   int* s_pref = reinterpret_cast<int*>(s_pe + M + 1);
   int* s_lo = s_pref + M + 1;
 
@@ -335,8 +601,10 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
   if (total == 0) return;
   if (t == 0) s_pref[M] = total;
   for (int i = t; i <= M; i += 64) s_pe[i] = a.pe[i];
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
   for (int nd = t; nd < nn; nd += 64) {
-    Node n = box_node(a, j, jp, nd);
+    Node n = box_node_at(a, s_phi, nd);
     s_r1[nd] = n.r1;
     s_r2[nd] = n.r2;
     s_Q1[nd] = n.Q1;
@@ -372,6 +640,7 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
     }
     const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
     const int64_t blk = rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] + (ip - s_lo[i]);
+    if (blk >= cap) continue;   // the candidate arrays are too small: the caller sees the total and builds again
     col_c[blk] = jp * M + ip;
     bool nz = false;
     for (int gg = 0; gg < nc2; ++gg) {
@@ -387,40 +656,198 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
   }
 }
 
+// The same quadrature with the node data in registers: lane l holds nodes nd = (l mod 8) + 8u and
+// works on candidate (l / 8) + 8k; the moments are summed over the eight lanes of a candidate, which
+// then write its channel values (lane l mod 8 takes the channel pairs gg = l mod 8, + 8, ...).
+// Everything a candidate needs besides its own nodes is staged in LDS first (the output position of
+// the row's first candidate, the channel coefficients), so that the candidate loop issues no global
+// load before its stores.
+template <int NMOM, int NPL>
+__global__ void __launch_bounds__(64) k_pbuild_reg(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
+                                                   const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
+                                                   int32_t* __restrict__ col_c, double* __restrict__ val_c,
+                                                   uint8_t* __restrict__ flag, int64_t cap) {
+  extern __shared__ double sh[];
+  const int M = a.M, N = a.N;
+  const int nn = a.n_x * a.n_phi;
+  const int box = blockIdx.x;
+  const int j = box / N, jp = box - j * N;
+  const int t = threadIdx.x;
+  // LDS: r1, r2, Q1, Q2 [nn], weights [NMOM][nn], phi table [n_phi][PHI_STRIDE], C [nc2][nmom],
+  // pe [M+1], base [M] (int64), pref [M+1] (int), lo [M] (int)
+  const int nc = a.nch, nc2 = nc * nc;
+  double* s_r1 = sh;
+  double* s_r2 = s_r1 + nn;
+  double* s_Q1 = s_r2 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_w = s_Q2 + nn;
+  double* s_phi = s_w + NMOM * nn;
+  double* s_C = s_phi + PHI_STRIDE * a.n_phi;
+  double* s_pe = s_C + nc2 * a.nmom;
+  int64_t* s_base = reinterpret_cast<int64_t*>(s_pe + M + 1);
+  int* s_pref = reinterpret_cast<int*>(s_base + M);
+  int* s_lo = s_pref + M + 1;
+
+  int run = 0;
+  for (int base = 0; base < M; base += 64) {
+    int i = base + t;
+    int c = (i < M) ? cnt[(size_t)box * M + i] : 0;
+    int x = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(x, o, WARP);
+      if (t >= o) x += y;
+    }
+    if (i < M) {
+      const int pref = run + x - c;
+      s_pref[i] = pref;
+      s_lo[i] = lo[(size_t)box * M + i];
+      // candidate e of row i goes to block base[i] + e of the candidate block-CSR
+      s_base[i] = c ? rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] - pref : 0;
+    }
+    run += __shfl(x, 63, WARP);
+  }
+  const int total = run;
+  if (total == 0) return;
+  if (t == 0) s_pref[M] = total;
+  for (int i = t; i <= M; i += 64) s_pe[i] = a.pe[i];
+  for (int e = t; e < nc2 * a.nmom; e += 64) s_C[e] = a.C[e];
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
+  for (int nd = t; nd < nn; nd += 64) {
+    Node n = box_node_at(a, s_phi, nd);
+    s_r1[nd] = n.r1;
+    s_r2[nd] = n.r2;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
+    for (int m = 0; m < a.nmom; ++m) s_w[m * nn + nd] = moment_weight(n, a.keys + 5 * m);
+  }
+  __syncthreads();
+  const int ng = t & 7, cg = t >> 3;
+  double r1[NPL], r2[NPL], Q1[NPL], Q2[NPL], w[NMOM][NPL];
+#pragma unroll
+  for (int u = 0; u < NPL; ++u) {
+    const int nd = ng + 8 * u;
+    const bool ok = nd < nn;
+    r1[u] = ok ? s_r1[nd] : 0.0;
+    r2[u] = ok ? s_r2[nd] : 0.0;
+    Q1[u] = ok ? s_Q1[nd] : 1.0;   // padding nodes: L >= 1 > 0 >= U, F = 0
+    Q2[u] = ok ? s_Q2[nd] : 0.0;
+#pragma unroll
+    for (int m = 0; m < NMOM; ++m) w[m][u] = (ok && m < a.nmom) ? s_w[m * nn + nd] : 0.0;
+  }
+  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  // row of the lane's candidate e (last i with pref[i] <= e); e only grows, so the row is advanced
+  // from the previous one, with a binary search over the rest when four steps do not reach it
+  int i = 0;
+  for (int e0 = 0; e0 < total; e0 += 8) {
+    const int e = min(e0 + cg, total - 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i < M - 1 && s_pref[i + 1] <= e) ++i;
+    if (i < M - 1 && s_pref[i + 1] <= e) {
+      int lo_i = i + 1, hi_i = M - 1;
+      while (lo_i < hi_i) {
+        int mid = (lo_i + hi_i + 1) >> 1;
+        if (s_pref[mid] <= e) lo_i = mid;
+        else hi_i = mid - 1;
+      }
+      i = lo_i;
+    }
+    const int ip = s_lo[i] + (e - s_pref[i]);
+    const double pa = s_pe[i], pb = s_pe[i + 1], ppa = s_pe[ip], ppb = s_pe[ip + 1];
+    double mom[NMOM];
+#pragma unroll
+    for (int m = 0; m < NMOM; ++m) mom[m] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NPL; ++u) {
+      const double U = fmin(Q2[u], fmin(ppb * r1[u], pb * r2[u]));
+      const double L = fmax(Q1[u], fmax(ppa * r1[u], pa * r2[u]));
+      const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+#pragma unroll
+      for (int m = 0; m < NMOM; ++m) mom[m] = fma(w[m][u], F, mom[m]);
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1)
+#pragma unroll
+      for (int m = 0; m < NMOM; ++m) mom[m] += __shfl_xor(mom[m], o, WARP);
+    const int64_t blk = s_base[i] + e;
+    // past the end, or the candidate arrays are too small (the caller sees the total and builds again)
+    if (e0 + cg >= total || blk >= cap) continue;
+    const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+    bool nz = false;
+    for (int gg = ng; gg < nc2; gg += 8) {
+      double v = 0.0;
+#pragma unroll
+      for (int m = 0; m < NMOM; ++m)
+        if (m < a.nmom) v = fma(s_C[gg * a.nmom + m], mom[m], v);
+      v *= norm;
+      val_c[blk * nc2 + gg] = v;
+      nz |= (v != 0.0);
+    }
+    // the block is nonzero if any of its channel values is: OR over the eight lanes
+    int nzi = nz ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) nzi |= __shfl_xor(nzi, o, WARP);
+    if (ng == 0) {
+      col_c[blk] = jp * M + ip;
+      flag[blk] = (uint8_t)nzi;
+    }
+  }
+}
+
 hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
-                         const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag, hipStream_t s) {
+                         const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag, int64_t cap,
+                         hipStream_t s) {
   int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > PB_MAXNODES || a.nmom < 1 || a.nmom > PB_MAXMOM || a.nch < 1) return hipErrorInvalidValue;
   size_t shmem = (size_t)nn * (4 + (a.nmom <= 1 ? 1 : (a.nmom <= 2 ? 2 : (a.nmom <= 4 ? 4 : 8)))) * sizeof(double) +
-                 (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
+                 (size_t)PHI_STRIDE * a.n_phi * sizeof(double) + (a.M + 1) * sizeof(double) +
+                 (2 * a.M + 1) * sizeof(int);
   dim3 g(a.N * a.N), b(64);
+  const size_t shreg = (size_t)nn * (4 + (a.nmom <= 1 ? 1 : (a.nmom <= 2 ? 2 : 4))) * sizeof(double) +
+                       (size_t)(PHI_STRIDE * a.n_phi + a.nch * a.nch * a.nmom + a.M + 1) * sizeof(double) +
+                       (size_t)a.M * sizeof(int64_t) + (2 * a.M + 1) * sizeof(int);
+  if (nn <= 64 && a.nmom <= 4 && shreg <= 64 * 1024) {
+    const size_t shmem = shreg;
+    // node data in registers (8 nodes per lane)
+    if (a.nmom <= 1)
+      hipLaunchKernelGGL((k_pbuild_reg<1, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+    else if (a.nmom <= 2)
+      hipLaunchKernelGGL((k_pbuild_reg<2, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+    else
+      hipLaunchKernelGGL((k_pbuild_reg<4, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+    return hipGetLastError();
+  }
   if (a.nmom <= 1)
-    hipLaunchKernelGGL(k_pbuild<1>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+    hipLaunchKernelGGL(k_pbuild<1>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
   else if (a.nmom <= 2)
-    hipLaunchKernelGGL(k_pbuild<2>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+    hipLaunchKernelGGL(k_pbuild<2>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
   else if (a.nmom <= 4)
-    hipLaunchKernelGGL(k_pbuild<4>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+    hipLaunchKernelGGL(k_pbuild<4>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
   else
-    hipLaunchKernelGGL(k_pbuild<8>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag);
+    hipLaunchKernelGGL(k_pbuild<8>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ compaction
 
 __global__ void __launch_bounds__(256) k_rowcount(int64_t rows, const int64_t* __restrict__ rowptr_c,
-                                                  const uint8_t* __restrict__ flag, int64_t* __restrict__ rowcnt) {
+                                                  const uint8_t* __restrict__ flag, int64_t* __restrict__ rowcnt,
+                                                  int64_t cap) {
   int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (row >= rows) return;
-  int64_t b0 = rowptr_c[row], b1 = rowptr_c[row + 1];
+  // candidates at or past cap were not written (too small arrays; the caller builds again)
+  int64_t b0 = min(rowptr_c[row], cap), b1 = min(rowptr_c[row + 1], cap);
   int64_t c = 0;
   for (int64_t e = b0 + lane; e < b1; e += 64) c += flag[e];
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, WARP);
   if (lane == 0) rowcnt[row] = c;
 }
 
-hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_rowcount, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, rowptr_c, flag, rowcnt);
+hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt, int64_t cap,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rowcount, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, rowptr_c, flag, rowcnt, cap);
   return hipGetLastError();
 }
 
@@ -430,18 +857,21 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
                                                  const int32_t* __restrict__ col_c, const double* __restrict__ val_c,
                                                  const uint8_t* __restrict__ flag, const int64_t* __restrict__ rowptr,
                                                  int32_t* __restrict__ col, double* __restrict__ val64,
-                                                 float* __restrict__ val32) {
+                                                 float* __restrict__ val32, int64_t cap_c, int64_t cap_b) {
   int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (row >= rows) return;
   const int nc2 = nch * nch;
-  int64_t b0 = rowptr_c[row], b1 = rowptr_c[row + 1];
+  // reads stay below cap_c (candidate arrays) and writes below cap_b (P0 arrays); a build that
+  // outgrew either is run again by the caller
+  int64_t b0 = min(rowptr_c[row], cap_c), b1 = min(rowptr_c[row + 1], cap_c);
   int64_t out = rowptr[row];
   for (int64_t base = b0; base < b1; base += 64) {
     int64_t e = base + lane;
-    bool f = (e < b1) && flag[e];
-    unsigned long long mask = __ballot(f);
+    const bool kept = (e < b1) && flag[e];
+    unsigned long long mask = __ballot(kept);
     int before = __popcll(mask & ((1ull << lane) - 1ull));
+    const bool f = kept && out + before < cap_b;
     if (f) col[out + before] = col_c[e];
     if (nc2 <= 16) {   // a lane copies its own block
       if (f) {
@@ -461,6 +891,7 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
         m &= m - 1ull;
         const int64_t es = base + src, d = out + k;
         ++k;
+        if (d >= cap_b) break;
         for (int t = lane; t < nc2; t += 64) {
           const int gp = t / nch, g = t - gp * nch;
           const double v = val_c[es * nc2 + g * nch + gp];
@@ -475,9 +906,9 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
 
 hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c, const double* val_c,
                           const uint8_t* flag, const int64_t* rowptr, int32_t* col, double* val64, float* val32,
-                          hipStream_t s) {
+                          int64_t cap_c, int64_t cap_b, hipStream_t s) {
   hipLaunchKernelGGL(k_compact, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, rowptr_c, col_c, val_c,
-                     flag, rowptr, col, val64, val32);
+                     flag, rowptr, col, val64, val32, cap_c, cap_b);
   return hipGetLastError();
 }
 
@@ -1005,6 +1436,115 @@ __global__ void __launch_bounds__(256) k_step64m(RotArgs r, const double* __rest
   }
 }
 
+// Small grids (one energy): one workgroup per 8 complex columns with one wavefront per 16-row
+// output tile, so that all row tiles run at once. Each lane first loads its whole A-operand
+// fragment (row kt*16 + l%16 of O, then of v O^T, every fourth column from l/16) into registers,
+// so a product is one chain of Mp/4 MFMAs with no memory waits inside.
+#define STEP64R_MAXK 32   // Mp / 4 for Mp <= 128: at most 8 wavefronts, so 256 VGPRs per lane
+// NK = Mp / 4 is a template argument so that the fragment loads and the MFMA chains are straight-line
+// code. Out-of-range fragment entries are loaded from a clamped address and kept: they meet only the
+// zero rows (i, k >= M) of the LDS tiles or produce output rows that are never stored, and every
+// entry of O and v O^T is finite, so they add exact zeros. Masking them instead would make the
+// compiler wrap each load in a branch that waits for it.
+template <int NK>
+__global__ void __launch_bounds__(512) k_step64r(RotArgs r, const double* __restrict__ Wm,
+                                                 const double2* __restrict__ y, double2* __restrict__ s_out) {
+  extern __shared__ double shd[];
+  constexpr int RCP = 17;   // 16 real columns + pad
+  constexpr int Mp = 4 * NK;
+  const int M = r.M, B = r.B, nch = r.nch;
+  const int ncol = r.N * B;
+  const int g = blockIdx.y;
+  const size_t woff = (size_t)r.wave[g] * M * M;
+  const double* O = r.A + woff;
+  const double* W = Wm + woff;
+  const int col0 = blockIdx.x * 8;
+  double* YT = shd;              // [Mp][RCP]
+  double* TT = shd + Mp * RCP;   // [Mp][RCP]
+  const int tid = threadIdx.x, lane = tid & 63, kt = tid >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4, part = r16 & 1;
+  const int row = kt * 16 + r16;
+  const int rowc = row < M ? row : M - 1;
+  // every global load of the kernel is issued here, so that their latencies overlap:
+  // the A fragments of O and of v O^T for this wavefront's row tile,
+  double af[NK], bf[NK];
+  {
+    const double* Ok = O + (size_t)rowc * M;
+    const double* Wi = W + (size_t)rowc * M;
+#pragma unroll
+    for (int st = 0; st < NK; ++st) {
+      const int ic = 4 * st + q4;
+      af[st] = Ok[ic < M ? ic : M - 1];
+      bf[st] = Wi[ic < M ? ic : M - 1];
+    }
+  }
+  // the two entries of the y tile that this thread stages (blockDim = 4 Mp, tile = 8 Mp entries),
+  double2 yv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * 4 * Mp;
+    const int cc = e / Mp, i = e - cc * Mp;
+    const int col = col0 + cc;
+    yv[h] = make_double2(0.0, 0.0);
+    if (i < M && col < ncol) {
+      const int jj = col / B, cb = col - jj * B;
+      yv[h] = y[(((size_t)jj * M + i) * nch + g) * B + cb];
+    }
+  }
+  // and the G1 values of the four output rows this lane owns in the first product
+  const int cc_out = r16 >> 1;
+  const int col_out = col0 + cc_out;
+  const bool live = col_out < ncol;
+  const int jj_out = live ? col_out / B : 0, cb_out = live ? col_out - jj_out * B : 0;
+  double2 gv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = kt * 16 + q4 + 4 * v;
+    gv[v] = r.G[(((size_t)jj_out * M + (k < M ? k : M - 1)) * nch + g) * B + cb_out];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = tid + h * 4 * Mp;
+    const int cc = e / Mp, i = e - cc * Mp;
+    YT[i * RCP + 2 * cc] = yv[h].x;
+    YT[i * RCP + 2 * cc + 1] = yv[h].y;
+  }
+  __syncthreads();
+  d4v acc = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < NK; ++st)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[st], YT[(4 * st + q4) * RCP + r16], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = kt * 16 + q4 + 4 * v;
+    const double val = acc[v];
+    const double other = __shfl_xor(val, 1, WARP);
+    const double re = part ? other : val, im = part ? val : other;
+    double out = 0.0;
+    if (live && k < M) {
+      if (r.acap && k == 0 && part == 0 && jj_out == r.j0[cb_out]) {
+        for (int f = 0; f < r.nfin; ++f)
+          if (r.finals[f] == g) r.acap[r.acap_off + (int64_t)cb_out * r.nfin + f] = make_double2(re, im);
+      }
+      out = part ? (re * gv[v].y + im * gv[v].x) : (re * gv[v].x - im * gv[v].y);
+    }
+    TT[k * RCP + r16] = out;
+  }
+  __syncthreads();
+  acc = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < NK; ++st)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[st], TT[(4 * st + q4) * RCP + r16], acc, 0, 0, 0);
+  if (live) {
+    double* so = reinterpret_cast<double*>(s_out);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = kt * 16 + q4 + 4 * v;
+      if (i < M) so[2 * ((((size_t)jj_out * M + i) * nch + g) * B + cb_out) + part] = acc[v];
+    }
+  }
+}
+
 static size_t step64m_lds(int Mp, int ct) { return (size_t)2 * Mp * (16 * ct + 1) * sizeof(double); }
 
 hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s) {
@@ -1018,6 +1558,23 @@ hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, do
     int ct = (step64m_lds(Mp, 2) <= lim && (int64_t)((ncol + 15) / 16) * r.nch >= 256) ? 2 : 1;
     // a small grid (one energy on few channels) stays with the VALU version, whose wavefronts
     // run their rows in parallel instead of one MFMA chain per tile
+    if (step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch < 256 && Mp / 4 <= STEP64R_MAXK &&
+        step64m_lds(Mp, 1) <= lim) {
+      // small grid: all row tiles of a column tile at once, A fragments preloaded
+      dim3 grid((ncol + 7) / 8, r.nch), block(64 * (Mp / 16));
+      const size_t sh = step64m_lds(Mp, 1);
+      switch (Mp / 16) {
+        case 1: hipLaunchKernelGGL(k_step64r<4>, grid, block, sh, s, r, W, y, s_out); break;
+        case 2: hipLaunchKernelGGL(k_step64r<8>, grid, block, sh, s, r, W, y, s_out); break;
+        case 3: hipLaunchKernelGGL(k_step64r<12>, grid, block, sh, s, r, W, y, s_out); break;
+        case 4: hipLaunchKernelGGL(k_step64r<16>, grid, block, sh, s, r, W, y, s_out); break;
+        case 5: hipLaunchKernelGGL(k_step64r<20>, grid, block, sh, s, r, W, y, s_out); break;
+        case 6: hipLaunchKernelGGL(k_step64r<24>, grid, block, sh, s, r, W, y, s_out); break;
+        case 7: hipLaunchKernelGGL(k_step64r<28>, grid, block, sh, s, r, W, y, s_out); break;
+        default: hipLaunchKernelGGL(k_step64r<32>, grid, block, sh, s, r, W, y, s_out); break;
+      }
+      return hipGetLastError();
+    }
     if (step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch >= 256) {
       dim3 grid((ncol + 8 * ct - 1) / (8 * ct), r.nch);
       if (ct == 2) hipLaunchKernelGGL(k_step64m<2>, grid, dim3(256), step64m_lds(Mp, 2), s, r, W, y, s_out, Mp);
@@ -1230,7 +1787,8 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
   double* s_Q1 = s_r2 + nn;
   double* s_Q2 = s_Q1 + nn;
   double* s_w = s_Q2 + nn;            // [MCH][nn]
-  double* s_pe = s_w + MCH * nn;      // M + 1
+  double* s_phi = s_w + MCH * nn;     // [n_phi][PHI_STRIDE]
+  double* s_pe = s_phi + PHI_STRIDE * a.n_phi;   // M + 1
   int* s_pref = reinterpret_cast<int*>(s_pe + M + 1);
   int* s_lo = s_pref + M + 1;
   __shared__ int s_total;
@@ -1248,8 +1806,10 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
   const int total = s_total;
   if (total == 0) return;
   for (int i = t; i <= M; i += blockDim.x) s_pe[i] = a.pe[i];
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
   for (int nd = t; nd < nn; nd += blockDim.x) {
-    Node n = box_node(a, j, jp, nd);
+    Node n = box_node_at(a, s_phi, nd);
     s_r1[nd] = n.r1;
     s_r2[nd] = n.r2;
     s_Q1[nd] = n.Q1;
@@ -1262,7 +1822,7 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
     __syncthreads();
     for (int e = t; e < mc * nn; e += blockDim.x) {
       const int m = e / nn, nd = e - m * nn;
-      Node n = box_node(a, j, jp, nd);
+      Node n = box_node_at(a, s_phi, nd);
       s_w[m * nn + nd] = moment_weight(n, a.keys + 5 * (m0 + m));
     }
     __syncthreads();
@@ -1340,7 +1900,8 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
                                  double* val_c, uint8_t* flag, hipStream_t s) {
   const int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > PB_MAXNODES || a.nmom < 1 || a.nch < 1) return hipErrorInvalidValue;
-  const size_t sh1 = (size_t)nn * (4 + MCH) * sizeof(double) + (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
+  const size_t sh1 = (size_t)nn * (4 + MCH) * sizeof(double) + (size_t)PHI_STRIDE * a.n_phi * sizeof(double) +
+                     (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
   if (sh1 > 64 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pbuild_mom, dim3(a.N * a.N), dim3(256), sh1, s, a, cnt, lo, segoff, rowptr_c, col_c, mom, norm);
   const size_t sh2 = (size_t)NBT * a.nmom * sizeof(double);

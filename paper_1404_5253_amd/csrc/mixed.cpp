@@ -118,13 +118,14 @@ wp_status wpcd::MixedWork::make(wp_lattice* Lp, int B_, int m_, bool split_) {
   D = R * L->nch;
   DB = D * B;
   fused = B >= 16 && L->nch <= 4;
+  // grow-only, so that a work object kept by the lattice is reused by later calls
   DevAlloc* al = &L->al;
-  if (!dG64.make(al, DB) || !db.make(al, DB) || !dy.make(al, DB) || !dr.make(al, DB) || !dKy.make(al, DB) ||
-      !ds64.make(al, DB) || !dcap.make(al, (size_t)B * nfin) || !dcoef.make(al, (size_t)(m + 1) * B) ||
-      !H.make(al, (size_t)m * (m + 1) * B) || !part.make(al, (size_t)kNblk * ARN_NV * B) || !nrm.make(al, B) ||
-      !dG32.make(al, DB) || !V.make(al, (size_t)(m + 1) * DB) || !t32.make(al, DB) ||
-      (!fused && !kv32.make(al, DB)) || !scl.make(al, (size_t)(m + 1) * B) || !dj0.make(al, B) ||
-      !dfin.make(al, nfin))
+  if (!grow(dG64, al, DB) || !grow(db, al, DB) || !grow(dy, al, DB) || !grow(dr, al, DB) || !grow(dKy, al, DB) ||
+      !grow(ds64, al, DB) || !grow(dcap, al, (size_t)B * nfin) || !grow(dcoef, al, (size_t)(m + 1) * B) ||
+      !grow(H, al, (size_t)m * (m + 1) * B) || !grow(part, al, (size_t)kNblk * ARN_NV * B) || !grow(nrm, al, B) ||
+      !grow(dG32, al, DB) || !grow(V, al, (size_t)(m + 1) * DB) || !grow(t32, al, DB) ||
+      (!fused && !grow(kv32, al, DB)) || !grow(scl, al, (size_t)(m + 1) * B) || !grow(dj0, al, B) ||
+      !grow(dfin, al, nfin))
     return fail(WP_ENOMEM, "device allocation (mixed solve)");
   hc.resize((size_t)B * nfin);
   hH.resize((size_t)m * (m + 1) * B);
@@ -234,15 +235,20 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
     }
   }
   if (wp_status st = ensure_mixed(L, s)) return st;
-  if (wp_status so = ensure_order(L)) return so;
+  if (wp_status so = ensure_order(L, s)) return so;
   const int m = std::max(2, std::min(ARN_NV, o.refine_every > 0 ? o.refine_every : 8));
   const int max_outer = std::max(2, std::min(100, o.max_iter / (m + 1)));
-  MixedWork w;
+  // the lattice's work object when no other call holds it, else one of this call's own
+  std::unique_lock<std::mutex> ws_lock(L->ws_mu, std::try_to_lock);
+  MixedWork own;
+  if (ws_lock.owns_lock() && !L->mws) L->mws = std::make_shared<MixedWork>();
+  MixedWork& w = ws_lock.owns_lock() ? *L->mws : own;
+  StreamDrain drain{s};   // idle stream before the work object is released or handed on
   if (wp_status st = w.make(L, B, m, o.mode == WP_SOLVE_MIXED_SPLIT)) return st;
-  DBuf<int> dg0;
-  DBuf<double> dE;
-  DBuf<int64_t> g1w;
-  if (!dg0.make(&L->al, B) || !dE.make(&L->al, nE) || !g1_work(L, nE, g1w))
+  DBuf<int>& dg0 = w.dg0;
+  DBuf<double>& dE = w.dE;
+  DBuf<int64_t>& g1w = w.g1w;
+  if (!grow(dg0, &L->al, B) || !grow(dE, &L->al, nE) || !g1_work(L, nE, g1w))
     return fail(WP_ENOMEM, "device allocation (mixed solve)");
   const int64_t DB = w.DB, R = w.R;
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * 8, hipMemcpyHostToDevice, s));

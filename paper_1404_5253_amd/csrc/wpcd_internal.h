@@ -77,6 +77,19 @@ struct DBuf {
   DBuf& operator=(const DBuf&) = delete;
 };
 
+// Grow-only: keeps b when it holds at least n elements, else reallocates it for n.
+template <class T>
+inline bool grow(DBuf<T>& b, DevAlloc* al, size_t n) {
+  return (b.p && b.n >= n) || b.make(al, n);
+}
+
+// Waits for the stream when the scope ends, so that memory its work used may be released or
+// handed to another call.
+struct StreamDrain {
+  hipStream_t s;
+  ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 // ------------------------------------------------------------------ kernel launchers
 // (defined in kernels.hip; every launcher checks its shapes and returns hipError_t)
 struct PBuildArgs {
@@ -99,19 +112,26 @@ hipError_t launch_rowseg(int M, int N, const int* cnt, int* segoff, int64_t* row
 size_t scan_tmp_size(int64_t n);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 // Quadrature (step 3) into the candidate block-CSR (values in FP64, per-block nonzero flag).
+// Candidate blocks at or past cap are not written (the caller checks the total and builds again).
 hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
                          const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag,
-                         hipStream_t s);
+                         int64_t cap, hipStream_t s);
 // Many moments: moments of every candidate pair, then values = norm * (moments x C^T).
 // Ct is [nmom][nch*nch]; mom [ncand][nmom] and norm [ncand] are scratch.
 hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const int* cnt, const int* lo, const int* segoff,
                                  const int64_t* rowptr_c, int64_t ncand, int32_t* col_c, double* mom, double* norm,
                                  double* val_c, uint8_t* flag, hipStream_t s);
 hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt,
-                           hipStream_t s);
+                           int64_t cap, hipStream_t s);
+// Reads candidates below cap_c, writes kept blocks below cap_b.
 hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c,
                           const double* val_c, const uint8_t* flag, const int64_t* rowptr,
-                          int32_t* col, double* val64, float* val32, hipStream_t s);
+                          int32_t* col, double* val64, float* val32, int64_t cap_c, int64_t cap_b,
+                          hipStream_t s);
+// SpMV work order of R block rows: by decreasing length (ties in any order).
+hipError_t launch_row_order(int64_t R, const int64_t* rowptr, int32_t* order, hipStream_t s);
+// host[0] = *a, host[1] = *b, with host in pinned host memory.
+hipError_t launch_totals(const int64_t* a, const int64_t* b, int64_t* host, hipStream_t s);
 
 // Solve kernels. Vector layout: x[((j*M + i)*nch + g)*B + c] complex (double2 / float2).
 struct RotArgs {

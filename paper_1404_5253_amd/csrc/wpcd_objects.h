@@ -2,11 +2,15 @@
 #pragma once
 
 #include <cmath>
+#include <memory>
 #include <mutex>
 #include <string>
 
 #include "wpcd_internal.h"
 
+namespace wpcd {
+struct MixedWork;
+}
 using namespace wpcd;
 
 #define HIPCHECK(expr)                                                                                     \
@@ -53,14 +57,31 @@ struct wp_lattice {
   int64_t blocks = 0;
   DBuf<int64_t> d_rowptr;
   DBuf<int32_t> d_col;
-  DBuf<int32_t> d_order;   // block rows by decreasing length (ties by index): SpMV work order
+  DBuf<int32_t> d_order;   // block rows by decreasing length: SpMV work order
+  bool order_ok = false;   // d_order holds the order of the resident P0 (or it is enqueued)
+  hipEvent_t order_ev = nullptr;   // recorded after the order kernel
+  std::mutex order_mu;
   DBuf<char> scratch_sel, scratch_cand;   // P0 build scratch kept between builds (grow-only)
+  // Solve workspaces reused across calls (grow-only) by the call that holds ws_mu; a call that
+  // finds it held (another thread on this lattice) allocates its own.
+  std::mutex ws_mu;
+  struct Solve64WS {
+    DBuf<double2> dG, dy, dt, ds, dacap;
+    DBuf<int> dj0, dg0, dfin;
+    DBuf<double> dE;
+    DBuf<int64_t> g1w;
+  } ws64;
+  std::shared_ptr<wpcd::MixedWork> mws;
+  int64_t cand_cap = 0;                   // candidate blocks scratch_cand holds
+  int64_t* h_tot = nullptr;               // pinned: the two totals of the last build
   // pinned host staging of the captured series terms (FP64 solve), reused across calls
   std::mutex pin_mu;
   double2* pin = nullptr;
   size_t pin_cap = 0;
   ~wp_lattice() {
     if (pin) (void)hipHostFree(pin);
+    if (h_tot) (void)hipHostFree(h_tot);
+    if (order_ev) (void)hipEventDestroy(order_ev);
   }
   DBuf<double> d_val64;
   DBuf<float> d_val32;
@@ -102,7 +123,7 @@ struct ProfScope {
 wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
 wp_status ensure_mixed(wp_lattice* L, hipStream_t s);   // bf16 blocks + FP32 copy of P0
-wp_status ensure_order(wp_lattice* L);                  // SpMV row order of the resident P0
+wp_status ensure_order(wp_lattice* L, hipStream_t s);   // SpMV row order of the resident P0 (on s)
 
 // ------------------------------------------------------------------ mixed path (mixed.cpp)
 constexpr int kNblk = 512;   // workgroups of the column reductions
@@ -115,7 +136,9 @@ struct MixedWork {
   DBuf<double2> dG64, db, dy, dr, dKy, ds64, dcap, dcoef, H, part, nrm;
   DBuf<float2> dG32, V, t32, kv32;
   DBuf<double> scl;
-  DBuf<int> dj0, dfin;
+  DBuf<int> dj0, dfin, dg0;
+  DBuf<double> dE;        // energies, G1 work list: used by solve_mixed only
+  DBuf<int64_t> g1w;
   std::vector<double2> hc, hH, hn, coef;
   std::vector<double> hsc;
   wp_status make(wp_lattice* L, int B, int m, bool split);
