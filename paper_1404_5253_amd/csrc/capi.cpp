@@ -583,10 +583,20 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   // stage's total instead (two host round trips).
   const size_t kKeepScratch = (size_t)512 << 20;
   const size_t nbox = (size_t)N * N * M;
+  // node tables of every q-box in HBM, shared by selection and quadrature, when the moment count
+  // allows it (weights padded to AS entries per node)
+  const int nn = L->n_x * L->n_phi, nmom = (int)L->keys.size();
+  const bool use_tab = nmom <= 4 && nn <= 128 && 9 * M + 1 <= 8192;
+  const int AS = ((nmom <= 1 ? 1 : nmom <= 2 ? 2 : 4) + 2) & ~1;
+  double *geo = nullptr, *aux = nullptr;
   int *cnt, *lo, *segoff;
   int64_t *rowcnt, *rowptr_c, *tmp;
   auto sel_layout = [&](char* base) {
     Carve c{base};
+    if (use_tab) {
+      geo = c.take<double>((size_t)N * N * nn * 4);
+      aux = c.take<double>((size_t)N * N * nn * AS);
+    }
     cnt = c.take<int>(nbox);
     lo = c.take<int>(nbox);
     segoff = c.take<int>(nbox);
@@ -636,7 +646,16 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   HIPCHECK(hipEventCreate(&e1));
   EventGuard eg1{e1};
   HIPCHECK(hipEventRecord(e0, s));
-  WP_LAUNCH("select", s, launch_select(a, cnt, lo, s));
+  if (use_tab) {
+    WP_LAUNCH("node_table", s, launch_node_table(a, geo, aux, AS, s));
+    WP_LAUNCH("select", s, launch_select_tab(a, geo, aux, AS, cnt, lo, s));
+  } else {
+    WP_LAUNCH("select", s, launch_select(a, cnt, lo, s));
+  }
+  auto pbuild = [&]() -> hipError_t {
+    return use_tab ? launch_pbuild_tab(a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s)
+                   : launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s);
+  };
   WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt, segoff, rowcnt, s));
   WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr_c, R, tmp, s));
   int64_t ncand = -1, nblk = -1;
@@ -646,7 +665,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     cand_layout(L->scratch_cand.p, (size_t)L->cand_cap);
     val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
     val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
-    WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s));
+    WP_LAUNCH("pbuild", s, pbuild());
     WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
     WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
     WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p, val64,
@@ -681,7 +700,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
       WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c,
                                                            mom, nrm, val_c, flag, s));
     } else if (ncand > 0) {
-      WP_LAUNCH("pbuild", s, launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s));
+      WP_LAUNCH("pbuild", s, pbuild());
     }
     if (ncand > 0) {
       WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));

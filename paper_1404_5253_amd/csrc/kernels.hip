@@ -1,20 +1,24 @@
 // gfx950 kernels of the WPCD hot path.
 //
 // P0 build (steps 2 and 3 of the paper's Sec. V.A; Appendix, final formula):
-//   k_select   one workgroup per q-box (j, j'): node tables in LDS, lanes over p rows i; the
-//              p' range with F > 0 at any node is bracketed by the extreme node bounds and
-//              located by binary search: one hull [lo, lo + cnt) per (box, i).
+//   k_node_table  the (x, phi) quadrature nodes of every q-box (j, j') and their moment weights,
+//              once per build, into HBM for the two kernels below.
+//   k_select_tab / k_select  per q-box, lanes over p rows i: the p' range with F > 0 at any node
+//              is bracketed by the extreme node bounds and located by binary search: one hull
+//              [lo, lo + cnt) per (box, i) (k_select builds its node table itself).
 //   k_rowseg   per lattice row (j, i): offsets of the box segments and the row total.
 //   k_scan_*   exclusive scans (row offsets of the candidate and of the final block-CSR).
-//   k_pbuild   one wavefront per q-box: node tables and moment weights in LDS, one candidate
-//              cell pair per lane, F and the moments accumulated in registers, channel values
-//              sum_m C[g][g'][m] mom_m written straight into the candidate block-CSR.
+//   k_pbuild_tab / k_pbuild  one wavefront per q-box, one candidate cell pair per lane, F and
+//              the moments accumulated in registers, channel values sum_m C[g][g'][m] mom_m
+//              written straight into the candidate block-CSR.
 //   k_rowcount / k_compact  ballot + popcount compaction of the nonzero blocks into the
 //              final block-CSR (deterministic, no atomics on the output path).
+//   k_row_order  SpMV work order of the final block rows (longest first).
 // Solve (step 5):
 //   k_g1       G1(E) (eqs. dg1a, dg1b) in FP64, straight into the iteration layout.
-//   k_step64   per channel and column tile: t = O y, capture of e0^T O y, t *= G1,
-//              s = (v O^T) t (FP64; the mixed-precision MFMA version is in kernels_mixed.hip).
+//   k_step64 / k_step64m / k_step64r  per channel and column tile: t = O y, capture of
+//              e0^T O y, t *= G1, s = (v O^T) t in FP64, on the VALU or on FP64 MFMA tiles (the
+//              mixed-precision BF16 MFMA version is in kernels_mixed.hip).
 //   k_spmm / k_spmv / k_spmv_gen  block-CSR P0 times complex vectors (lanes over energies,
 //              over blocks, or over channel rows for large blocks).
 #include <hip/hip_runtime.h>
@@ -167,47 +171,79 @@ __global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ 
   }
 }
 
-// The same selection with the node data held in registers: one wavefront per q-box, lane l takes
-// the nodes nd = (l mod 8) + 8u and the rows i = (l / 8) + 8k; the per-row hull bounds are reduced
-// over the eight lanes that share a row, then the binary searches run with lanes over rows. min and
-// max are exact, so the hull is the same as node-by-node in one lane.
-// Rows are first restricted exactly: node n can be active in row i only if p_{i-1} r2 < Q2 and
-// p_i r2 > Q1 (A >= p_{i-1} r2, B <= p_i r2), and with a positive factor r2 the rounded products are
-// nondecreasing in i, so these rows form an interval [i0(n), i1(n)) found by binary search with the
-// same products; rows outside the union's hull have no active node and get an empty p' range.
+// ------------------------------------------------------------------ node tables in HBM
+__device__ double moment_weight(const Node& n, const int* key);
+// The quadrature nodes of every q-box, computed once per build for both the selection and the
+// quadrature: geo[box][nd] = (r1, r2, Q1, Q2) and aux[box][nd] = (z1, moment weights w_0 .. w_{nmom-1},
+// padded to AS entries). One wavefront per box, four boxes per workgroup (BPW), lanes over nodes.
+#define BPW 4
+__global__ void __launch_bounds__(64 * BPW) k_node_table(PBuildArgs a, double* __restrict__ geo,
+                                                         double* __restrict__ aux, int AS) {
+  extern __shared__ double sh[];
+  const int nn = a.n_x * a.n_phi;
+  const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int box = blockIdx.x * BPW + wv;
+  const bool live = box < a.N * a.N;
+  double* s_phi = sh + wv * PHI_STRIDE * a.n_phi;
+  const int j = live ? box / a.N : 0, jp = live ? box - j * a.N : 0;
+  if (live)
+    for (int ib = t; ib < a.n_phi; ib += 64) box_phi_row(a, j, jp, ib, s_phi);
+  __syncthreads();
+  if (!live) return;
+  for (int nd = t; nd < nn; nd += 64) {
+    const Node n = box_node_at(a, s_phi, nd);
+    double* g = geo + ((size_t)box * nn + nd) * 4;
+    g[0] = n.r1;
+    g[1] = n.r2;
+    g[2] = n.Q1;
+    g[3] = n.Q2;
+    double* x = aux + ((size_t)box * nn + nd) * AS;
+    x[0] = n.z1;
+    for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? moment_weight(n, a.keys + 5 * m) : 0.0;
+  }
+}
+
+hipError_t launch_node_table(const PBuildArgs& a, double* geo, double* aux, int AS, hipStream_t s) {
+  const int nn = a.n_x * a.n_phi;
+  if (nn < 1 || nn > 256 || a.n_phi > 256 || AS < 1 + a.nmom) return hipErrorInvalidValue;
+  const int nbox = a.N * a.N;
+  hipLaunchKernelGGL(k_node_table, dim3((nbox + BPW - 1) / BPW), dim3(64 * BPW),
+                     (size_t)BPW * PHI_STRIDE * a.n_phi * sizeof(double), s, a, geo, aux, AS);
+  return hipGetLastError();
+}
+
+// Selection from the node tables, with the arithmetic of k_select: one wavefront per q-box, BPW
+// boxes per workgroup (the p edges shared in LDS). Rows are first restricted exactly: node n can
+// be active in row i only if p_{i-1} r2 < Q2 and p_i r2 > Q1 (A >= p_{i-1} r2, B <= p_i r2), and
+// with a positive factor r2 the rounded products are nondecreasing in i, so these rows form an
+// interval [i0(n), i1(n)) found by binary search with the same products; rows outside the hull of
+// the union have no active node and get an empty p' range. Inside it, lane l holds the nodes
+// nd = (l mod 8) + 8u in registers and takes the rows (l / 8) + 8k; the bounds of a row are reduced
+// over the eight lanes that share it (min and max are exact, so the hull is the same as node by
+// node in one lane), then the binary searches run with lanes over rows.
 template <int NPL>
-__global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict__ cnt, int* __restrict__ lo_out) {
+__global__ void __launch_bounds__(64 * BPW) k_select_tab(PBuildArgs a, const double* __restrict__ geo,
+                                                         const double* __restrict__ aux, int AS,
+                                                         int* __restrict__ cnt, int* __restrict__ lo_out) {
   extern __shared__ double sh[];
   const int M = a.M;
   const int nn = a.n_x * a.n_phi;
-  double* spe = sh;              // M + 1
-  double* s_r2 = spe + M + 1;    // nn
-  double* s_z1 = s_r2 + nn;
-  double* s_Q1 = s_z1 + nn;
-  double* s_Q2 = s_Q1 + nn;
-  double* s_phi = s_Q2 + nn;     // n_phi * PHI_STRIDE
-  double* s_xlo = s_phi + PHI_STRIDE * a.n_phi;   // M
-  double* s_xhi = s_xlo + M;                      // M
-  const int box = blockIdx.x;
-  const int j = box / a.N, jp = box - j * a.N;
-  const int t = threadIdx.x;
-  for (int i = t; i <= M; i += 64) spe[i] = a.pe[i];
-  fill_phi_table(a, j, jp, s_phi);
-  __syncthreads();
-  for (int nd = t; nd < nn; nd += 64) {
-    Node n = box_node_at(a, s_phi, nd);
-    s_r2[nd] = n.r2;
-    s_z1[nd] = n.z1;
-    s_Q1[nd] = n.Q1;
-    s_Q2[nd] = n.Q2;
-  }
+  const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int box = blockIdx.x * BPW + wv;
+  const bool live = box < a.N * a.N;
+  double* spe = sh;                                 // M + 1, shared
+  double* s_xlo = spe + M + 1 + wv * 2 * M;         // M per wavefront
+  double* s_xhi = s_xlo + M;                        // M per wavefront
+  const double* G = geo + (size_t)(live ? box : 0) * nn * 4;
+  const double* X = aux + (size_t)(live ? box : 0) * nn * AS;
+  for (int i = threadIdx.x; i <= M; i += 64 * BPW) spe[i] = a.pe[i];
   __syncthreads();
   // hull [ilo, ihi) of the rows where any node can be active
   int ilo = M, ihi = 0;
   for (int nd = t; nd < nn; nd += 64) {
-    const double r2n = s_r2[nd], Q1n = s_Q1[nd], Q2n = s_Q2[nd];
+    const double r2n = G[nd * 4 + 1], Q1n = G[nd * 4 + 2], Q2n = G[nd * 4 + 3];
     if (!(Q1n < Q2n)) continue;
-    int lo = 0, hi = M;   // i1: smallest i in [0, M] with p_{i-1} r2 >= Q2 (pe[M] r2 treated as >= Q2)
+    int lo = 0, hi = M;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (spe[mid] * r2n >= Q2n) hi = mid;
@@ -215,7 +251,7 @@ __global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict
     }
     const int i1 = lo;
     lo = 0;
-    hi = M;               // i0: smallest i in [0, M] with p_i r2 > Q1 (i = M: none)
+    hi = M;
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
       if (spe[mid + 1] * r2n > Q1n) hi = mid;
@@ -240,10 +276,11 @@ __global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict
   for (int u = 0; u < NPL; ++u) {
     const int nd = ng + 8 * u;
     const bool ok = nd < nn;
-    r2[u] = ok ? s_r2[nd] : 0.0;
-    z1[u] = ok ? s_z1[nd] : 0.0;
-    Q1[u] = ok ? s_Q1[nd] : 1.0;   // padding nodes: A >= 1 > 0 >= B, never active
-    Q2[u] = ok ? s_Q2[nd] : 0.0;
+    const int ndc = ok ? nd : 0;
+    r2[u] = ok ? G[ndc * 4 + 1] : 0.0;
+    z1[u] = ok ? X[(size_t)ndc * AS] : 0.0;
+    Q1[u] = ok ? G[ndc * 4 + 2] : 1.0;   // padding nodes: A >= 1 > 0 >= B, never active
+    Q2[u] = ok ? G[ndc * 4 + 3] : 0.0;
   }
   for (int i0 = ilo; i0 < ihi; i0 += 8) {
     const int i = i0 + rg;
@@ -270,6 +307,7 @@ __global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict
     }
   }
   __syncthreads();
+  if (!live) return;
   for (int i = t; i < M; i += 64) {
     const double xlo = s_xlo[i], xhi = s_xhi[i];
     int c = 0, l2 = 0;
@@ -300,20 +338,23 @@ __global__ void __launch_bounds__(64) k_select_reg(PBuildArgs a, int* __restrict
   }
 }
 
+hipError_t launch_select_tab(const PBuildArgs& a, const double* geo, const double* aux, int AS, int* cnt, int* lo,
+                             hipStream_t s) {
+  const int nn = a.n_x * a.n_phi;
+  if (nn < 1 || nn > 128 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
+  const size_t sh = (size_t)(a.M + 1 + BPW * 2 * a.M) * sizeof(double);
+  if (sh > 64 * 1024) return hipErrorInvalidValue;
+  const int npl = (nn + 7) / 8;
+  const dim3 g((a.N * a.N + BPW - 1) / BPW), b(64 * BPW);
+  if (npl <= 4) hipLaunchKernelGGL(k_select_tab<4>, g, b, sh, s, a, geo, aux, AS, cnt, lo);
+  else if (npl <= 8) hipLaunchKernelGGL(k_select_tab<8>, g, b, sh, s, a, geo, aux, AS, cnt, lo);
+  else hipLaunchKernelGGL(k_select_tab<16>, g, b, sh, s, a, geo, aux, AS, cnt, lo);
+  return hipGetLastError();
+}
+
 hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) {
   int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > 256 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
-  if (nn <= 128) {
-    // node data in registers: 8 lanes per row, nn / 8 nodes per lane
-    const size_t sh = (a.M + 1) * sizeof(double) + (4 * nn + PHI_STRIDE * a.n_phi + 2 * a.M) * sizeof(double);
-    if (sh <= 64 * 1024) {
-      const int npl = (nn + 7) / 8;
-      if (npl <= 4) hipLaunchKernelGGL(k_select_reg<4>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
-      else if (npl <= 8) hipLaunchKernelGGL(k_select_reg<8>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
-      else hipLaunchKernelGGL(k_select_reg<16>, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo);
-      return hipGetLastError();
-    }
-  }
   size_t shmem = (a.M + 1) * sizeof(double) + (4 * nn + PHI_STRIDE * a.n_phi) * sizeof(double);
   hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(128), shmem, s, a, cnt, lo);
   return hipGetLastError();
@@ -430,18 +471,24 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
 
 size_t scan_tmp_size(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1); }
 
-// Up to SCAN1_MAX entries: one workgroup of 1024 threads, thread t scanning its own run of
-// consecutive entries, the run totals scanned across the workgroup (one launch instead of three).
+// Up to SCAN1_MAX entries below 2^31 each (row counts of a lattice with M, N <= 1024): one
+// workgroup of 1024 threads. The entries are loaded coalesced into LDS as int32, thread t sums its
+// run of consecutive entries from LDS, the run totals are scanned across the workgroup, and each
+// thread writes its run's offsets (one launch instead of three).
 #define SCAN1_T 1024
-#define SCAN1_MAX (SCAN1_T * 32)
+#define SCAN1_MAX 16384
 __global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restrict__ in, int64_t* __restrict__ out,
                                                         int64_t n) {
+  __shared__ int32_t v[SCAN1_MAX];
   __shared__ int64_t wsum[SCAN1_T / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int64_t per = (n + SCAN1_T - 1) / SCAN1_T;
-  const int64_t b0 = min(n, (int64_t)t * per), b1 = min(n, b0 + per);
+  const int nn = (int)n;
+  for (int k = t; k < nn; k += SCAN1_T) v[k] = (int32_t)in[k];
+  __syncthreads();
+  const int per = (nn + SCAN1_T - 1) / SCAN1_T;
+  const int b0 = min(nn, t * per), b1 = min(nn, b0 + per);
   int64_t loc = 0;
-  for (int64_t k = b0; k < b1; ++k) loc += in[k];
+  for (int k = b0; k < b1; ++k) loc += v[k];
   int64_t x = loc;   // inclusive scan over the wavefront
   for (int o = 1; o < 64; o <<= 1) {
     const int64_t y = __shfl_up(x, o, WARP);
@@ -451,15 +498,14 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restri
   __syncthreads();
   int64_t before = 0, total = 0;
   for (int w = 0; w < SCAN1_T / 64; ++w) {
-    const int64_t v = wsum[w];
-    if (w < wv) before += v;
-    total += v;
+    const int64_t ws = wsum[w];
+    if (w < wv) before += ws;
+    total += ws;
   }
   int64_t run = before + x - loc;
-  for (int64_t k = b0; k < b1; ++k) {
-    const int64_t v = in[k];
+  for (int k = b0; k < b1; ++k) {
     out[k] = run;
-    run += v;
+    run += v[k];
   }
   if (t == 0) out[n] = total;
 }
@@ -656,42 +702,41 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
   }
 }
 
-// The same quadrature with the node data in registers: lane l holds nodes nd = (l mod 8) + 8u and
-// works on candidate (l / 8) + 8k; the moments are summed over the eight lanes of a candidate, which
-// then write its channel values (lane l mod 8 takes the channel pairs gg = l mod 8, + 8, ...).
-// Everything a candidate needs besides its own nodes is staged in LDS first (the output position of
-// the row's first candidate, the channel coefficients), so that the candidate loop issues no global
-// load before its stores.
-template <int NMOM, int NPL>
-__global__ void __launch_bounds__(64) k_pbuild_reg(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
-                                                   const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
-                                                   int32_t* __restrict__ col_c, double* __restrict__ val_c,
-                                                   uint8_t* __restrict__ flag, int64_t cap) {
+// Quadrature from the node tables: one wavefront per q-box, one candidate per lane. Every lane
+// reads the same node at the same time (wave-uniform loads, kept in scalar registers), so the
+// per-node work is the arithmetic alone. Moment weights past nmom are zero in the table.
+// One wavefront per box, BPW boxes per workgroup (coefficients and p edges shared in LDS).
+template <int NMOM>
+__global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const double* __restrict__ geo,
+                                                         const double* __restrict__ aux, int AS,
+                                                         const int* __restrict__ cnt, const int* __restrict__ lo,
+                                                         const int* __restrict__ segoff,
+                                                         const int64_t* __restrict__ rowptr_c,
+                                                         int32_t* __restrict__ col_c, double* __restrict__ val_c,
+                                                         uint8_t* __restrict__ flag, int64_t cap) {
   extern __shared__ double sh[];
   const int M = a.M, N = a.N;
   const int nn = a.n_x * a.n_phi;
-  const int box = blockIdx.x;
-  const int j = box / N, jp = box - j * N;
-  const int t = threadIdx.x;
-  // LDS: r1, r2, Q1, Q2 [nn], weights [NMOM][nn], phi table [n_phi][PHI_STRIDE], C [nc2][nmom],
-  // pe [M+1], base [M] (int64), pref [M+1] (int), lo [M] (int)
+  const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int box = blockIdx.x * BPW + wv;
+  const bool live = box < N * N;
+  const int j = live ? box / N : 0, jp = live ? box - j * N : 0;
   const int nc = a.nch, nc2 = nc * nc;
-  double* s_r1 = sh;
-  double* s_r2 = s_r1 + nn;
-  double* s_Q1 = s_r2 + nn;
-  double* s_Q2 = s_Q1 + nn;
-  double* s_w = s_Q2 + nn;
-  double* s_phi = s_w + NMOM * nn;
-  double* s_C = s_phi + PHI_STRIDE * a.n_phi;
+  // LDS: C [nc2][nmom] and pe [M+1] shared; per wavefront the node table [nn][4 + AS], base [M]
+  // (int64), pref [M+1], lo [M] (int)
+  double* s_C = sh;
   double* s_pe = s_C + nc2 * a.nmom;
-  int64_t* s_base = reinterpret_cast<int64_t*>(s_pe + M + 1);
+  const int RS = 4 + AS;
+  const size_t per_wave = (size_t)nn * RS * sizeof(double) + (size_t)M * sizeof(int64_t) + (2 * M + 1) * sizeof(int);
+  char* wbase = reinterpret_cast<char*>(s_pe + M + 1) + wv * ((per_wave + 7) & ~(size_t)7);
+  double* s_nd = reinterpret_cast<double*>(wbase);
+  int64_t* s_base = reinterpret_cast<int64_t*>(s_nd + (size_t)nn * RS);
   int* s_pref = reinterpret_cast<int*>(s_base + M);
   int* s_lo = s_pref + M + 1;
-
   int run = 0;
   for (int base = 0; base < M; base += 64) {
     int i = base + t;
-    int c = (i < M) ? cnt[(size_t)box * M + i] : 0;
+    int c = (live && i < M) ? cnt[(size_t)box * M + i] : 0;
     int x = c;
     for (int o = 1; o < 64; o <<= 1) {
       int y = __shfl_up(x, o, WARP);
@@ -700,82 +745,55 @@ __global__ void __launch_bounds__(64) k_pbuild_reg(PBuildArgs a, const int* __re
     if (i < M) {
       const int pref = run + x - c;
       s_pref[i] = pref;
-      s_lo[i] = lo[(size_t)box * M + i];
+      s_lo[i] = live ? lo[(size_t)box * M + i] : 0;
       // candidate e of row i goes to block base[i] + e of the candidate block-CSR
       s_base[i] = c ? rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] - pref : 0;
     }
     run += __shfl(x, 63, WARP);
   }
-  const int total = run;
-  if (total == 0) return;
+  const int total = run;   // 0 for a box past the end
   if (t == 0) s_pref[M] = total;
-  for (int i = t; i <= M; i += 64) s_pe[i] = a.pe[i];
-  for (int e = t; e < nc2 * a.nmom; e += 64) s_C[e] = a.C[e];
-  fill_phi_table(a, j, jp, s_phi);
-  __syncthreads();
-  for (int nd = t; nd < nn; nd += 64) {
-    Node n = box_node_at(a, s_phi, nd);
-    s_r1[nd] = n.r1;
-    s_r2[nd] = n.r2;
-    s_Q1[nd] = n.Q1;
-    s_Q2[nd] = n.Q2;
-    for (int m = 0; m < a.nmom; ++m) s_w[m * nn + nd] = moment_weight(n, a.keys + 5 * m);
+  for (int i = threadIdx.x; i <= M; i += 64 * BPW) s_pe[i] = a.pe[i];
+  for (int e = threadIdx.x; e < nc2 * a.nmom; e += 64 * BPW) s_C[e] = a.C[e];
+  if (total > 0) {   // this box's node table, row nd = (r1, r2, Q1, Q2, z1, w ...)
+    const double* Gg = geo + (size_t)box * nn * 4;
+    const double* Xg = aux + (size_t)box * nn * AS;
+    for (int e = t; e < nn * 4; e += 64) s_nd[(e >> 2) * RS + (e & 3)] = Gg[e];
+    for (int e = t; e < nn * AS; e += 64) s_nd[(e / AS) * RS + 4 + e % AS] = Xg[e];
   }
   __syncthreads();
-  const int ng = t & 7, cg = t >> 3;
-  double r1[NPL], r2[NPL], Q1[NPL], Q2[NPL], w[NMOM][NPL];
-#pragma unroll
-  for (int u = 0; u < NPL; ++u) {
-    const int nd = ng + 8 * u;
-    const bool ok = nd < nn;
-    r1[u] = ok ? s_r1[nd] : 0.0;
-    r2[u] = ok ? s_r2[nd] : 0.0;
-    Q1[u] = ok ? s_Q1[nd] : 1.0;   // padding nodes: L >= 1 > 0 >= U, F = 0
-    Q2[u] = ok ? s_Q2[nd] : 0.0;
-#pragma unroll
-    for (int m = 0; m < NMOM; ++m) w[m][u] = (ok && m < a.nmom) ? s_w[m * nn + nd] : 0.0;
-  }
+  if (total == 0) return;
   const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
-  // row of the lane's candidate e (last i with pref[i] <= e); e only grows, so the row is advanced
-  // from the previous one, with a binary search over the rest when four steps do not reach it
-  int i = 0;
-  for (int e0 = 0; e0 < total; e0 += 8) {
-    const int e = min(e0 + cg, total - 1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i < M - 1 && s_pref[i + 1] <= e) ++i;
-    if (i < M - 1 && s_pref[i + 1] <= e) {
-      int lo_i = i + 1, hi_i = M - 1;
-      while (lo_i < hi_i) {
-        int mid = (lo_i + hi_i + 1) >> 1;
-        if (s_pref[mid] <= e) lo_i = mid;
-        else hi_i = mid - 1;
-      }
-      i = lo_i;
+  for (int e0 = 0; e0 < total; e0 += 64) {
+    const int e = min(e0 + t, total - 1);
+    int lo_i = 0, hi_i = M - 1;   // row: last i with pref[i] <= e
+    while (lo_i < hi_i) {
+      int mid = (lo_i + hi_i + 1) >> 1;
+      if (s_pref[mid] <= e) lo_i = mid;
+      else hi_i = mid - 1;
     }
+    const int i = lo_i;
     const int ip = s_lo[i] + (e - s_pref[i]);
     const double pa = s_pe[i], pb = s_pe[i + 1], ppa = s_pe[ip], ppb = s_pe[ip + 1];
     double mom[NMOM];
 #pragma unroll
     for (int m = 0; m < NMOM; ++m) mom[m] = 0.0;
-#pragma unroll
-    for (int u = 0; u < NPL; ++u) {
-      const double U = fmin(Q2[u], fmin(ppb * r1[u], pb * r2[u]));
-      const double L = fmax(Q1[u], fmax(ppa * r1[u], pa * r2[u]));
+#pragma unroll 4
+    for (int nd = 0; nd < nn; ++nd) {
+      const double* q = s_nd + nd * RS;   // the same address in every lane: LDS broadcast
+      const double r1 = q[0], r2 = q[1], Q1 = q[2], Q2 = q[3];
+      const double U = fmin(Q2, fmin(ppb * r1, pb * r2));
+      const double L = fmax(Q1, fmax(ppa * r1, pa * r2));
       const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
 #pragma unroll
-      for (int m = 0; m < NMOM; ++m) mom[m] = fma(w[m][u], F, mom[m]);
+      for (int m = 0; m < NMOM; ++m) mom[m] = fma(q[5 + m], F, mom[m]);
     }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1)
-#pragma unroll
-      for (int m = 0; m < NMOM; ++m) mom[m] += __shfl_xor(mom[m], o, WARP);
     const int64_t blk = s_base[i] + e;
     // past the end, or the candidate arrays are too small (the caller sees the total and builds again)
-    if (e0 + cg >= total || blk >= cap) continue;
+    if (e0 + t >= total || blk >= cap) continue;
     const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
     bool nz = false;
-    for (int gg = ng; gg < nc2; gg += 8) {
+    for (int gg = 0; gg < nc2; ++gg) {
       double v = 0.0;
 #pragma unroll
       for (int m = 0; m < NMOM; ++m)
@@ -784,15 +802,28 @@ __global__ void __launch_bounds__(64) k_pbuild_reg(PBuildArgs a, const int* __re
       val_c[blk * nc2 + gg] = v;
       nz |= (v != 0.0);
     }
-    // the block is nonzero if any of its channel values is: OR over the eight lanes
-    int nzi = nz ? 1 : 0;
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) nzi |= __shfl_xor(nzi, o, WARP);
-    if (ng == 0) {
-      col_c[blk] = jp * M + ip;
-      flag[blk] = (uint8_t)nzi;
-    }
+    col_c[blk] = jp * M + ip;
+    flag[blk] = nz ? 1 : 0;
   }
+}
+
+hipError_t launch_pbuild_tab(const PBuildArgs& a, const double* geo, const double* aux, int AS, const int* cnt,
+                             const int* lo, const int* segoff, const int64_t* rowptr_c, int32_t* col_c,
+                             double* val_c, uint8_t* flag, int64_t cap, hipStream_t s) {
+  if (a.nmom < 1 || a.nmom > 4 || AS < 1 + a.nmom || a.nch < 1) return hipErrorInvalidValue;
+  const int nn = a.n_x * a.n_phi;
+  const size_t per_wave = ((size_t)nn * (4 + AS) * sizeof(double) + (size_t)a.M * sizeof(int64_t) +
+                           (2 * a.M + 1) * sizeof(int) + 7) & ~(size_t)7;
+  const size_t sh = (size_t)(a.nch * a.nch * a.nmom + a.M + 1) * sizeof(double) + BPW * per_wave;
+  if (sh > 64 * 1024) return hipErrorInvalidValue;
+  dim3 g((a.N * a.N + BPW - 1) / BPW), b(64 * BPW);
+  if (a.nmom <= 1)
+    hipLaunchKernelGGL(k_pbuild_tab<1>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+  else if (a.nmom <= 2)
+    hipLaunchKernelGGL(k_pbuild_tab<2>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+  else
+    hipLaunchKernelGGL(k_pbuild_tab<4>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+  return hipGetLastError();
 }
 
 hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
@@ -804,20 +835,6 @@ hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, con
                  (size_t)PHI_STRIDE * a.n_phi * sizeof(double) + (a.M + 1) * sizeof(double) +
                  (2 * a.M + 1) * sizeof(int);
   dim3 g(a.N * a.N), b(64);
-  const size_t shreg = (size_t)nn * (4 + (a.nmom <= 1 ? 1 : (a.nmom <= 2 ? 2 : 4))) * sizeof(double) +
-                       (size_t)(PHI_STRIDE * a.n_phi + a.nch * a.nch * a.nmom + a.M + 1) * sizeof(double) +
-                       (size_t)a.M * sizeof(int64_t) + (2 * a.M + 1) * sizeof(int);
-  if (nn <= 64 && a.nmom <= 4 && shreg <= 64 * 1024) {
-    const size_t shmem = shreg;
-    // node data in registers (8 nodes per lane)
-    if (a.nmom <= 1)
-      hipLaunchKernelGGL((k_pbuild_reg<1, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
-    else if (a.nmom <= 2)
-      hipLaunchKernelGGL((k_pbuild_reg<2, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
-    else
-      hipLaunchKernelGGL((k_pbuild_reg<4, 8>), g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
-    return hipGetLastError();
-  }
   if (a.nmom <= 1)
     hipLaunchKernelGGL(k_pbuild<1>, g, b, shmem, s, a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
   else if (a.nmom <= 2)

@@ -108,10 +108,18 @@ struct PBuildArgs {
 hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s);
 // Per lattice row, offsets of each box segment and the row total.
 hipError_t launch_rowseg(int M, int N, const int* cnt, int* segoff, int64_t* rowcnt, hipStream_t s);
-// Exclusive scan of n int64 values into out[n+1] (tmp: scan_tmp_size(n) int64).
+// Exclusive scan of n int64 values, each below 2^31, into out[n+1] (tmp: scan_tmp_size(n) int64).
 size_t scan_tmp_size(int64_t n);
 hipError_t launch_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
 // Quadrature (step 3) into the candidate block-CSR (values in FP64, per-block nonzero flag).
+// Node tables of all q-boxes: geo[box][nd] = (r1, r2, Q1, Q2), aux[box][nd] = (z1, w_0 .. w_{nmom-1},
+// zeros up to AS entries); selection and quadrature reading them.
+hipError_t launch_node_table(const PBuildArgs& a, double* geo, double* aux, int AS, hipStream_t s);
+hipError_t launch_select_tab(const PBuildArgs& a, const double* geo, const double* aux, int AS, int* cnt, int* lo,
+                             hipStream_t s);
+hipError_t launch_pbuild_tab(const PBuildArgs& a, const double* geo, const double* aux, int AS, const int* cnt,
+                             const int* lo, const int* segoff, const int64_t* rowptr_c, int32_t* col_c,
+                             double* val_c, uint8_t* flag, int64_t cap, hipStream_t s);
 // Candidate blocks at or past cap are not written (the caller checks the total and builds again).
 hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
                          const int64_t* rowptr_c, int32_t* col_c, double* val_c, uint8_t* flag,

@@ -56,6 +56,9 @@ SPECS = {
     "quartet_yam_24": pipeline.Spec(M=24, N=24, two_J=3, pot="yamaguchi"),
     "doublet_mt_20": pipeline.Spec(M=20, N=20, two_J=1, pot="mt"),
     "quartet_yam_ragged_17x13": pipeline.Spec(M=17, N=13, two_J=3, pot="yamaguchi", n_x=6, n_phi=10),
+    # 144 nodes per box: past the node-table path, the selection and quadrature that build their
+    # own node tables per q-box
+    "doublet_mt_nodes144": pipeline.Spec(M=9, N=8, two_J=1, pot="mt", n_x=12, n_phi=12),
 }
 
 
