@@ -173,31 +173,36 @@ __global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ 
 
 // ------------------------------------------------------------------ node tables in HBM
 __device__ double moment_weight(const Node& n, const int* key);
+
 // The quadrature nodes of every q-box, computed once per build for both the selection and the
 // quadrature: geo[box][nd] = (r1, r2, Q1, Q2) and aux[box][nd] = (z1, moment weights w_0 .. w_{nmom-1},
-// padded to AS entries). One wavefront per box, four boxes per workgroup (BPW), lanes over nodes.
+// zeros up to AS entries). A workgroup takes BB consecutive boxes: first the phi rows of all of
+// them (threads over (box, phi node), so that the arc tangents and sines fill the lanes), then
+// their nodes (threads over (box, node), consecutive threads writing consecutive nodes).
 #define BPW 4
-__global__ void __launch_bounds__(64 * BPW) k_node_table(PBuildArgs a, double* __restrict__ geo,
-                                                         double* __restrict__ aux, int AS) {
-  extern __shared__ double sh[];
+__global__ void __launch_bounds__(256) k_node_table(PBuildArgs a, double* __restrict__ geo, double* __restrict__ aux,
+                                                    int AS, int BB) {
+  extern __shared__ double sh[];   // [BB][n_phi][PHI_STRIDE]
   const int nn = a.n_x * a.n_phi;
-  const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int box = blockIdx.x * BPW + wv;
-  const bool live = box < a.N * a.N;
-  double* s_phi = sh + wv * PHI_STRIDE * a.n_phi;
-  const int j = live ? box / a.N : 0, jp = live ? box - j * a.N : 0;
-  if (live)
-    for (int ib = t; ib < a.n_phi; ib += 64) box_phi_row(a, j, jp, ib, s_phi);
+  const int nbox = a.N * a.N;
+  const int box0 = blockIdx.x * BB;
+  const int nb = min(BB, nbox - box0);
+  for (int e = threadIdx.x; e < nb * a.n_phi; e += 256) {
+    const int b = e / a.n_phi, ib = e - b * a.n_phi;
+    const int box = box0 + b, j = box / a.N, jp = box - j * a.N;
+    box_phi_row(a, j, jp, ib, sh + (size_t)b * a.n_phi * PHI_STRIDE);
+  }
   __syncthreads();
-  if (!live) return;
-  for (int nd = t; nd < nn; nd += 64) {
-    const Node n = box_node_at(a, s_phi, nd);
-    double* g = geo + ((size_t)box * nn + nd) * 4;
+  for (int e = threadIdx.x; e < nb * nn; e += 256) {
+    const int b = e / nn, nd = e - b * nn;
+    const Node n = box_node_at(a, sh + (size_t)b * a.n_phi * PHI_STRIDE, nd);
+    const size_t k = (size_t)(box0 + b) * nn + nd;
+    double* g = geo + k * 4;
     g[0] = n.r1;
     g[1] = n.r2;
     g[2] = n.Q1;
     g[3] = n.Q2;
-    double* x = aux + ((size_t)box * nn + nd) * AS;
+    double* x = aux + k * AS;
     x[0] = n.z1;
     for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? moment_weight(n, a.keys + 5 * m) : 0.0;
   }
@@ -207,8 +212,9 @@ hipError_t launch_node_table(const PBuildArgs& a, double* geo, double* aux, int 
   const int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > 256 || a.n_phi > 256 || AS < 1 + a.nmom) return hipErrorInvalidValue;
   const int nbox = a.N * a.N;
-  hipLaunchKernelGGL(k_node_table, dim3((nbox + BPW - 1) / BPW), dim3(64 * BPW),
-                     (size_t)BPW * PHI_STRIDE * a.n_phi * sizeof(double), s, a, geo, aux, AS);
+  const size_t row = (size_t)a.n_phi * PHI_STRIDE * sizeof(double);
+  const int BB = (int)std::max<size_t>(1, std::min<size_t>(32, (32 * 1024) / row));
+  hipLaunchKernelGGL(k_node_table, dim3((nbox + BB - 1) / BB), dim3(256), BB * row, s, a, geo, aux, AS, BB);
   return hipGetLastError();
 }
 
