@@ -543,14 +543,6 @@ static wp_status upload_tables(wp_lattice* L) {
   return WP_OK;
 }
 
-// Destroys an event when the scope ends.
-struct EventGuard {
-  hipEvent_t e;
-  ~EventGuard() {
-    if (e) (void)hipEventDestroy(e);
-  }
-};
-
 // Sub-allocations of one device buffer (256-byte aligned); with base = nullptr it only sizes.
 struct Carve {
   char* base;
@@ -640,11 +632,9 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   };
   double* val64 = nullptr;
   float* val32 = nullptr;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHECK(hipEventCreate(&e0));
-  EventGuard eg0{e0};
-  HIPCHECK(hipEventCreate(&e1));
-  EventGuard eg1{e1};
+  for (hipEvent_t& e : L->build_ev)
+    if (!e) HIPCHECK(hipEventCreate(&e));
+  hipEvent_t e0 = L->build_ev[0], e1 = L->build_ev[1];
   HIPCHECK(hipEventRecord(e0, s));
   if (use_tab) {
     WP_LAUNCH("node_table", s, launch_node_table(a, geo, aux, AS, s));

@@ -379,8 +379,10 @@ __global__ void k_rowseg(int M, int N, const int* __restrict__ cnt, int* __restr
   const int j = live ? (int)(r / M) : 0, i = live ? (int)(r - (int64_t)j * M) : 0;
   const int q = (N + 3) / 4, jp0 = min(N, h * q), jp1 = min(N, jp0 + q);
   int64_t part = 0;
-  if (live)
+  if (live) {
+#pragma unroll 8
     for (int jp = jp0; jp < jp1; ++jp) part += cnt[((size_t)j * N + jp) * M + i];
+  }
   // exclusive prefix over the four quarters of the row (lanes 4k .. 4k+3 of the wavefront)
   const int lane = threadIdx.x & 63, base = lane & ~3;
   int64_t before = 0, total = 0;
@@ -391,6 +393,7 @@ __global__ void k_rowseg(int M, int N, const int* __restrict__ cnt, int* __restr
   }
   if (!live) return;
   int64_t run = before;
+#pragma unroll 8
   for (int jp = jp0; jp < jp1; ++jp) {
     const size_t idx = ((size_t)j * N + jp) * M + i;
     segoff[idx] = (int)run;
@@ -489,6 +492,7 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restri
   __shared__ int64_t wsum[SCAN1_T / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nn = (int)n;
+#pragma unroll 16
   for (int k = t; k < nn; k += SCAN1_T) v[k] = (int32_t)in[k];
   __syncthreads();
   const int per = (nn + SCAN1_T - 1) / SCAN1_T;

@@ -74,6 +74,7 @@ struct wp_lattice {
   std::shared_ptr<wpcd::MixedWork> mws;
   int64_t cand_cap = 0;                   // candidate blocks scratch_cand holds
   int64_t* h_tot = nullptr;               // pinned: the two totals of the last build
+  hipEvent_t build_ev[2] = {nullptr, nullptr};   // start and end of a build (device time)
   // pinned host staging of the captured series terms (FP64 solve), reused across calls
   std::mutex pin_mu;
   double2* pin = nullptr;
@@ -82,6 +83,8 @@ struct wp_lattice {
     if (pin) (void)hipHostFree(pin);
     if (h_tot) (void)hipHostFree(h_tot);
     if (order_ev) (void)hipEventDestroy(order_ev);
+    for (hipEvent_t e : build_ev)
+      if (e) (void)hipEventDestroy(e);
   }
   DBuf<double> d_val64;
   DBuf<float> d_val32;
