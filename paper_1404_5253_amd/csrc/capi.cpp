@@ -890,8 +890,19 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   } ev_guard{ev};
   int launched = 0;   // iterations enqueued
   int T_of[2] = {0, 0};
-  auto enqueue = [&](int slot) -> wp_status {
-    const int T = std::min(chunk, max_iter - launched);
+  // Terms still needed by the slowest unfinished column after the chunks read so far, predicted
+  // from the geometric rate of its relative change over the last chunk (-1: unknown). With
+  // overlap, the chunk enqueued while chunk k is read gets only that many terms beyond chunk k
+  // (at least 2), so that little work runs past convergence. Only the schedule depends on it:
+  // the terms are read in order and the stop rule ends every column at the same term.
+  int need = -1;
+  std::vector<double> r_prev(B, INFINITY);
+  auto next_size = [&](int in_flight) {
+    if (need < 0) return chunk;
+    return std::max(2, std::min(chunk, need - in_flight + 1));
+  };
+  auto enqueue = [&](int slot, int want) -> wp_status {
+    const int T = std::min(want, max_iter - launched);
     for (int t = 0; t < T; ++t) {
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin,
                  (int64_t)(launched + t) * B * nfin};
@@ -908,7 +919,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   };
   int pending = -1;   // slot of a chunk enqueued and not yet read
   if (overlap) {
-    if (wp_status st0 = enqueue(0)) return st0;
+    if (wp_status st0 = enqueue(0, chunk)) return st0;
     pending = 0;
   }
   for (int k = 0;; ++k) {
@@ -917,13 +928,14 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
       cur = pending;
       pending = -1;
       if (launched < max_iter) {
-        if (wp_status st1 = enqueue(cur ^ 1)) return st1;   // runs while chunk `cur` is read
+        // runs while chunk `cur` is read
+        if (wp_status st1 = enqueue(cur ^ 1, next_size(T_of[cur]))) return st1;
         pending = cur ^ 1;
       }
     } else {
       if (launched >= max_iter) break;
       cur = k & 1;
-      if (wp_status st1 = enqueue(cur)) return st1;
+      if (wp_status st1 = enqueue(cur, chunk)) return st1;
     }
     HIPCHECK(hipEventSynchronize(ev[cur]));
     const double2* hcap = pin + cur * per_chunk;
@@ -939,6 +951,21 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
       }
       all_done &= cs[c].done;
     }
+    need = 0;
+    for (int c = 0; c < B && need >= 0; ++c) {
+      const ColState& q = cs[c];
+      if (q.done) continue;
+      const double r = q.r_last, r0 = r_prev[c];
+      if (r <= o.tol) {
+        need = std::max(need, 1);
+      } else if (r > 0 && r < r0 && std::isfinite(r0)) {
+        const double rate = std::pow(r / r0, 1.0 / std::max(1, T_of[cur]));   // per term, < 1
+        need = std::max(need, (int)std::ceil(std::log(o.tol / r) / std::log(rate)) + 1);
+      } else {
+        need = -1;   // not (yet) contracting: no prediction
+      }
+    }
+    for (int c = 0; c < B; ++c) r_prev[c] = cs[c].r_last;
     if (all_done || (overlap && pending < 0)) break;
   }
   HIPCHECK(hipStreamSynchronize(s));

@@ -190,6 +190,7 @@ struct ColState {
   std::vector<Wynn> w;      // per final
   std::vector<cplx> S, last, best;
   double best_r = INFINITY;
+  double r_last = INFINITY;   // relative change at the newest term
   int best_n = 0, streak = 0, n = 0, plateau = 24;
   bool done = false, ok = false;
   double err = 0.0;
@@ -208,6 +209,7 @@ inline bool column_push(ColState& cs, const cplx* a, int nfin, double tol, doubl
   if (cs.n > 0) {
     double r = 0.0;
     for (int f = 0; f < nfin; ++f) r = std::max(r, std::abs(est[f] - cs.last[f]) / std::max(std::abs(est[f]), 1e-300));
+    cs.r_last = r;
     if (r < cs.best_r) {
       cs.best_r = r;
       cs.best = est;
