@@ -908,7 +908,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
                  (int64_t)(launched + t) * B * nfin};
       WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
       WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1,
-                                             L->d_order.p));
+                                             B >= 16 ? nullptr : L->d_order.p));
     }
     HIPCHECK(hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)launched * B * nfin,
                             (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, s));
