@@ -141,9 +141,12 @@ wp_status twobody_pseudostates(wp_lattice* lat, const wp_potential_desc* pot, do
  * formula): steps 2 (selection of the nonzero cell pairs) and 3 (their (x, phi) Gauss
  * quadrature with the analytic Q integral F) of Sec. V.A, on the GPU. The result stays
  * resident as block-CSR: block rows and columns are lattice cells r = j*M + i (q bin j, p bin i),
- * each stored block holds the n_ch x n_ch channel values (row-major in (gamma, gamma')).
+ * each stored block holds the n_ch x n_ch channel values (column-major in (gamma, gamma') on the
+ * device; perm_matrix_export returns them row-major).
  * Values are computed in FP64 and stored in FP64 (WP_P_FP64) or rounded to FP32 (WP_P_FP32).
- * Blocks whose values are all exactly zero are omitted. Energy independent: build once.
+ * Blocks whose values are all exactly zero are omitted. Energy independent: build once. A
+ * rebuild of the same lattice reuses the device buffers of the previous build (no allocation)
+ * and waits for the device once, at the end; the call returns after the build has finished.
  * stats (may be NULL): blocks = stored cell pairs, nnz = stored scalar entries (blocks times
  * channel pairs with a nonzero coefficient), candidates = selected cell pairs before
  * compaction, bytes = device bytes of the stored matrix, device_ms = GPU time of the build.

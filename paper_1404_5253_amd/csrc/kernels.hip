@@ -175,8 +175,9 @@ __global__ void __launch_bounds__(128) k_select(PBuildArgs a, int* __restrict__ 
 __device__ double moment_weight(const Node& n, const int* key);
 
 // The quadrature nodes of every q-box, computed once per build for both the selection and the
-// quadrature: geo[box][nd] = (r1, r2, Q1, Q2) and aux[box][nd] = (z1, moment weights w_0 .. w_{nmom-1},
-// zeros up to AS entries). A workgroup takes BB consecutive boxes: first the phi rows of all of
+// quadrature: geo[box][nd] = (r1, r2, Q1, Q2) and aux[box][nd] = (z1, halved moment weights
+// w_0 / 2 .. w_{nmom-1} / 2, zeros up to AS entries; halving is exact, and the quadrature takes the
+// 1/2 of F from the weight). A workgroup takes BB consecutive boxes: first the phi rows of all of
 // them (threads over (box, phi node), so that the arc tangents and sines fill the lanes), then
 // their nodes (threads over (box, node), consecutive threads writing consecutive nodes).
 #define BPW 4
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__(256) k_node_table(PBuildArgs a, double* __rest
     g[3] = n.Q2;
     double* x = aux + k * AS;
     x[0] = n.z1;
-    for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? moment_weight(n, a.keys + 5 * m) : 0.0;
+    for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? 0.5 * moment_weight(n, a.keys + 5 * m) : 0.0;
   }
 }
 
@@ -712,9 +713,11 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
   }
 }
 
-// Quadrature from the node tables: one wavefront per q-box, one candidate per lane. Every lane
-// reads the same node at the same time (wave-uniform loads, kept in scalar registers), so the
-// per-node work is the arithmetic alone. Moment weights past nmom are zero in the table.
+// Quadrature from the node tables: one wavefront per q-box, one candidate per lane, the box's
+// node table staged in LDS and read by broadcast. Moment weights past nmom are zero in the table.
+// Per node, w F = (w / 2) (U - L) (U + L) for U > L, else 0, is taken as
+// fma(w / 2, max(U - L, 0) (U + L), mom): U + L > 0, and scaling by 1/2 commutes with rounding,
+// so this is the same number as fma(w, F, mom) with one compare and two selects fewer.
 // One wavefront per box, BPW boxes per workgroup (coefficients and p edges shared in LDS).
 template <int NMOM>
 __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const double* __restrict__ geo,
@@ -794,9 +797,9 @@ __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const dou
       const double r1 = q[0], r2 = q[1], Q1 = q[2], Q2 = q[3];
       const double U = fmin(Q2, fmin(ppb * r1, pb * r2));
       const double L = fmax(Q1, fmax(ppa * r1, pa * r2));
-      const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+      const double F2 = fmax(U - L, 0.0) * (U + L);   // 2 F
 #pragma unroll
-      for (int m = 0; m < NMOM; ++m) mom[m] = fma(q[5 + m], F, mom[m]);
+      for (int m = 0; m < NMOM; ++m) mom[m] = fma(q[5 + m], F2, mom[m]);
     }
     const int64_t blk = s_base[i] + e;
     // past the end, or the candidate arrays are too small (the caller sees the total and builds again)
