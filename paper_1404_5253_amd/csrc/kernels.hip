@@ -746,10 +746,19 @@ __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const dou
   int64_t* s_base = reinterpret_cast<int64_t*>(s_nd + (size_t)nn * RS);
   int* s_pref = reinterpret_cast<int*>(s_base + M);
   int* s_lo = s_pref + M + 1;
+  // per row: the candidate count, the first candidate column, and the output position of the
+  // row's first candidate (all loaded at once from in-range addresses; box 0 stands in for a box
+  // past the end, whose counts are taken as zero)
+  const size_t bx = live ? (size_t)box : 0;
   int run = 0;
   for (int base = 0; base < M; base += 64) {
-    int i = base + t;
-    int c = (live && i < M) ? cnt[(size_t)box * M + i] : 0;
+    const int i = base + t;
+    const int ic = i < M ? i : M - 1;
+    const int c_ld = cnt[bx * M + ic];
+    const int lo_ld = lo[bx * M + ic];
+    const int64_t rp = rowptr_c[(size_t)j * M + ic];
+    const int sg = segoff[bx * M + ic];
+    const int c = (live && i < M) ? c_ld : 0;
     int x = c;
     for (int o = 1; o < 64; o <<= 1) {
       int y = __shfl_up(x, o, WARP);
@@ -758,9 +767,9 @@ __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const dou
     if (i < M) {
       const int pref = run + x - c;
       s_pref[i] = pref;
-      s_lo[i] = live ? lo[(size_t)box * M + i] : 0;
+      s_lo[i] = live ? lo_ld : 0;
       // candidate e of row i goes to block base[i] + e of the candidate block-CSR
-      s_base[i] = c ? rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] - pref : 0;
+      s_base[i] = c ? rp + sg - pref : 0;
     }
     run += __shfl(x, 63, WARP);
   }
