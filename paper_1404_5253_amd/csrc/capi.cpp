@@ -818,7 +818,13 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const int max_iter = std::max(4, std::min(1000, o.max_iter));
   const int chunk = 8;
   if (wp_status us = upload_waves(L)) return us;
-  if (wp_status so = ensure_order(L, s)) return so;
+  // SpMV row order: lattice order for few channels (rows of one q bin share their columns, and
+  // the short rows finish together), longest rows first for many channels (measured both ways)
+  const int32_t* order = nullptr;
+  if (nch > 4) {
+    if (wp_status so = ensure_order(L, s)) return so;
+    order = L->d_order.p;
+  }
   // the lattice's workspace when no other call holds it, else one of this call's own
   std::unique_lock<std::mutex> ws_lock(L->ws_mu, std::try_to_lock);
   wp_lattice::Solve64WS own_ws;
@@ -842,7 +848,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const double* val = L->d_val64.p;
   if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
-  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, L->d_order.p));
+  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, order));
   std::vector<ColState> cs(B);
   for (auto& c : cs) {
     c.w.resize(nfin);
@@ -908,7 +914,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
                  (int64_t)(launched + t) * B * nfin};
       WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
       WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1,
-                                             B >= 16 ? nullptr : L->d_order.p));
+                                             order));
     }
     HIPCHECK(hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)launched * B * nfin,
                             (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, s));
