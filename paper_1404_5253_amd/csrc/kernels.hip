@@ -1716,15 +1716,15 @@ __global__ void __launch_bounds__(256) k_spmm(int64_t rows, int B, int cb0, int 
   for (int g = 0; g < NC; ++g) y[((size_t)row * NC + g) * B + c] = make_x<XT, AT>(ar[g], ai[g]);
 }
 
-// Half a wavefront per row (32 lanes over its blocks, two rows per wavefront, eight per
-// workgroup), reduction within the half; for few columns. Rows have ~25 blocks at M = N = 100,
-// so the halves are about as full as a whole wavefront would be, with half as many wavefronts.
-template <typename VT, typename XT, typename AT, int NC>
+// LPR lanes per row (half a wavefront as launched, 256 / LPR rows per workgroup), reduction
+// within those lanes; for few columns. Rows have ~25 blocks at
+// M = N = 100, so a few lanes per row keep the lanes busy with fewer wavefronts.
+template <typename VT, typename XT, typename AT, int NC, int LPR>
 __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int cb1, const int64_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, const VT* __restrict__ val,
                                               const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t w = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 5);
-  const int hl = threadIdx.x & 31;
+  const int64_t w = (int64_t)blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
+  const int hl = threadIdx.x & (LPR - 1);
   const bool live = w < rows;
   const int64_t row = live ? (order ? order[w] : w) : 0;
   const int64_t b0 = live ? rowptr[row] : 0, b1 = live ? rowptr[row + 1] : 0;
@@ -1732,7 +1732,7 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int 
     AT ar[NC], ai[NC];
 #pragma unroll
     for (int g = 0; g < NC; ++g) ar[g] = ai[g] = AT(0);
-    for (int64_t e = b0 + hl; e < b1; e += 32) {
+    for (int64_t e = b0 + hl; e < b1; e += LPR) {
       const int cc = col[e];
       const VT* v = val + e * NC * NC;
 #pragma unroll
@@ -1750,7 +1750,7 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t rows, int B, int cb0, int 
     for (int g = 0; g < NC; ++g) {
       AT sr = ar[g], si = ai[g];
 #pragma unroll
-      for (int o = 16; o > 0; o >>= 1) {   // within the 32 lanes of the half
+      for (int o = LPR / 2; o > 0; o >>= 1) {   // within the LPR lanes of the row
         sr += __shfl_xor(sr, o, WARP);
         si += __shfl_xor(si, o, WARP);
       }
@@ -1769,8 +1769,9 @@ static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* 
     dim3 grid((unsigned)spmv_blocks(rows, order), (cb1 - cb0 + 63) / 64);
     hipLaunchKernelGGL((k_spmm<VT, XT, AT, NC>), grid, dim3(256), 0, s, rows, B, cb0, cb1, rowptr, col, val, x, y, order);
   } else {
-    hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC>), dim3((unsigned)((rows + 7) / 8)), dim3(256), 0, s, rows, B, cb0, cb1,
-                       rowptr, col, val, x, y, order);
+    // 32 lanes per row (16 measured slower at M = N = 100)
+    hipLaunchKernelGGL((k_spmv<VT, XT, AT, NC, 32>), dim3((unsigned)((rows + 7) / 8)), dim3(256), 0, s, rows, B, cb0,
+                       cb1, rowptr, col, val, x, y, order);
   }
 }
 
