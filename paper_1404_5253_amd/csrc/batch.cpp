@@ -24,7 +24,7 @@ struct wp_batch {
   int slots = 0, nfin = 0, B = 0, max_terms = 0, m = 0;
   int64_t D = 0;
   // FP64 path
-  DBuf<double2> dG, dy, dt, ds, dacap;
+  DBuf<double2> dG, dy, ds, dacap;
   DBuf<int> dj0, dfin;
   // mixed path
   MixedWork mw;
@@ -65,7 +65,7 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   b->m = std::max(2, std::min(ARN_NV, o->refine_every > 0 ? o->refine_every : 8));
   const size_t per_slot =
       b->mixed ? (size_t)b->nfin * mixed_bytes_per_column(L, b->m)
-               : (size_t)b->nfin * (4 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
+               : (size_t)b->nfin * (3 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
   int cap = (int)std::min<size_t>((size_t)max_slots, hbm_budget / std::max<size_t>(per_slot, 1));
   if (cap < 1) return fail(WP_EBUDGET, "hbm_budget smaller than one slot");
   b->slots = cap;
@@ -87,11 +87,11 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
     HIPCHECK(hipMemcpy(w.dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(w.dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
   } else {
-    if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) || !b->dt.make(al, b->D * B) ||
+    if (!b->dG.make(al, b->D * B) || !b->dy.make(al, b->D * B) ||
         !b->ds.make(al, b->D * B) || !b->dacap.make(al, (size_t)b->max_terms * B * b->nfin) || !b->dj0.make(al, B) ||
         !b->dfin.make(al, b->nfin))
       return fail(WP_ENOMEM, "device allocation (batch)");
-    for (auto* p : {&b->dG, &b->dy, &b->dt, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
+    for (auto* p : {&b->dG, &b->dy, &b->ds}) HIPCHECK(launch_fill0(p->p, b->D * B, nullptr));
     HIPCHECK(hipMemcpy(b->dj0.p, b->j0.data(), B * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->dfin.p, L->opens.data(), b->nfin * sizeof(int), hipMemcpyHostToDevice));
     b->hcap.resize((size_t)b->max_terms * B * b->nfin);
@@ -137,7 +137,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0,
                                c0 + nf));
     HIPCHECK(launch_spmv_f32v_f64x(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, st, c0,
-                                   c0 + nf, L->d_order.p));
+                                   c0 + nf, spmv_order(L)));
     HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c0 + nf, st));
     S.mc.assign(nf, MixedCol());
   } else {
@@ -146,7 +146,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
                                c0 + nf));
     HIPCHECK(launch_spmv_f64(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st, c0, c0 + nf,
-                             L->d_order.p));
+                             spmv_order(L)));
     S.cs.resize(nf);
     for (auto& c : S.cs) {
       c.w.resize(nf);
@@ -230,7 +230,7 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
     WP_LAUNCH("step64", st, launch_step64(ro, L->d_W.p, b->dy.p, b->ds.p, st));
     WP_LAUNCH("spmv64", st, launch_spmv_f64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
-                                            b->dy.p, st, 0, -1, L->d_order.p));
+                                            b->dy.p, st, 0, -1, spmv_order(L)));
   }
   HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
                           st));

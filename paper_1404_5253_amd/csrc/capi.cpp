@@ -779,7 +779,7 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
 // lattice order in one contiguous chunk per XCD, was slower.
 // Computed on the device on stream s after each build; a call on another stream waits for it.
 wp_status wpcd::ensure_order(wp_lattice* L, hipStream_t s) {
-  if (!L->have_P) return WP_OK;
+  if (!L->have_P || L->nch <= 4) return WP_OK;   // lattice order (spmv_order)
   std::lock_guard<std::mutex> lk(L->order_mu);
   if (!L->order_ev) HIPCHECK(hipEventCreateWithFlags(&L->order_ev, hipEventDisableTiming));
   if (L->order_ok) {
@@ -818,25 +818,20 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const int max_iter = std::max(4, std::min(1000, o.max_iter));
   const int chunk = 8;
   if (wp_status us = upload_waves(L)) return us;
-  // SpMV row order: lattice order for few channels (rows of one q bin share their columns, and
-  // the short rows finish together), longest rows first for many channels (measured both ways)
-  const int32_t* order = nullptr;
-  if (nch > 4) {
-    if (wp_status so = ensure_order(L, s)) return so;
-    order = L->d_order.p;
-  }
+  if (wp_status so = ensure_order(L, s)) return so;
+  const int32_t* order = spmv_order(L);
   // the lattice's workspace when no other call holds it, else one of this call's own
   std::unique_lock<std::mutex> ws_lock(L->ws_mu, std::try_to_lock);
   wp_lattice::Solve64WS own_ws;
   wp_lattice::Solve64WS& ws = ws_lock.owns_lock() ? L->ws64 : own_ws;
   StreamDrain drain{s};   // idle stream before the workspace is released or handed on
-  DBuf<double2>&dG = ws.dG, &dy = ws.dy, &dt = ws.dt, &ds = ws.ds, &dacap = ws.dacap;
+  DBuf<double2>&dG = ws.dG, &dy = ws.dy, &ds = ws.ds, &dacap = ws.dacap;
   DBuf<int>&dj0 = ws.dj0, &dg0 = ws.dg0, &dfin = ws.dfin;
   DBuf<double>& dE = ws.dE;
   DBuf<int64_t>& g1w = ws.g1w;
   DevAlloc* al = &L->al;
   if (!g1_work(L, nE, g1w)) return fail(WP_ENOMEM, "device allocation (G1 work list)");
-  if (!grow(dG, al, D * B) || !grow(dy, al, D * B) || !grow(dt, al, D * B) || !grow(ds, al, D * B) ||
+  if (!grow(dG, al, D * B) || !grow(dy, al, D * B) || !grow(ds, al, D * B) ||
       !grow(dacap, al, (size_t)(max_iter + chunk) * B * nfin) || !grow(dj0, al, B) || !grow(dg0, al, B) ||
       !grow(dfin, al, nfin) || !grow(dE, al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");

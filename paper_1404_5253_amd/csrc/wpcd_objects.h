@@ -66,7 +66,7 @@ struct wp_lattice {
   // finds it held (another thread on this lattice) allocates its own.
   std::mutex ws_mu;
   struct Solve64WS {
-    DBuf<double2> dG, dy, dt, ds, dacap;
+    DBuf<double2> dG, dy, ds, dacap;
     DBuf<int> dj0, dg0, dfin;
     DBuf<double> dE;
     DBuf<int64_t> g1w;
@@ -127,6 +127,9 @@ wp_status fail(wp_status st, const std::string& msg);
 wp_status upload_waves(wp_lattice* L);
 wp_status ensure_mixed(wp_lattice* L, hipStream_t s);   // bf16 blocks + FP32 copy of P0
 wp_status ensure_order(wp_lattice* L, hipStream_t s);   // SpMV row order of the resident P0 (on s)
+// Row order the SpMV kernels take: longest rows first for many channels (the LDS-staged kernels),
+// lattice order for few (rows of one q bin share their columns; measured faster at 1 to 64 columns).
+inline const int32_t* spmv_order(const wp_lattice* L) { return L->nch > 4 ? L->d_order.p : nullptr; }
 
 // ------------------------------------------------------------------ mixed path (mixed.cpp)
 constexpr int kNblk = 512;   // workgroups of the column reductions
