@@ -481,25 +481,25 @@ __global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* 
 
 size_t scan_tmp_size(int64_t n) { return (size_t)((n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1); }
 
-// Up to SCAN1_MAX entries below 2^31 each (row counts of a lattice with M, N <= 1024): one
-// workgroup of 1024 threads. The entries are loaded coalesced into LDS as int32, thread t sums its
-// run of consecutive entries from LDS, the run totals are scanned across the workgroup, and each
-// thread writes its run's offsets (one launch instead of three).
+// Up to SCAN1_MAX entries: one workgroup of 1024 threads, thread t holding its run of at most 16
+// consecutive entries in registers (all loads issued at once); the run totals are scanned across
+// the workgroup and each thread writes its run's offsets (one launch instead of three).
 #define SCAN1_T 1024
-#define SCAN1_MAX 16384
+#define SCAN1_MAX (SCAN1_T * 16)
 __global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restrict__ in, int64_t* __restrict__ out,
                                                         int64_t n) {
-  __shared__ int32_t v[SCAN1_MAX];
   __shared__ int64_t wsum[SCAN1_T / 64];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nn = (int)n;
-#pragma unroll 16
-  for (int k = t; k < nn; k += SCAN1_T) v[k] = (int32_t)in[k];
-  __syncthreads();
   const int per = (nn + SCAN1_T - 1) / SCAN1_T;
-  const int b0 = min(nn, t * per), b1 = min(nn, b0 + per);
+  const int b0 = t * per;
+  int64_t v[16];
   int64_t loc = 0;
-  for (int k = b0; k < b1; ++k) loc += v[k];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = (k < per && b0 + k < nn) ? in[b0 + k] : 0;
+    loc += v[k];
+  }
   int64_t x = loc;   // inclusive scan over the wavefront
   for (int o = 1; o < 64; o <<= 1) {
     const int64_t y = __shfl_up(x, o, WARP);
@@ -514,8 +514,9 @@ __global__ void __launch_bounds__(SCAN1_T) k_scan_single(const int64_t* __restri
     total += ws;
   }
   int64_t run = before + x - loc;
-  for (int k = b0; k < b1; ++k) {
-    out[k] = run;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < per && b0 + k < nn) out[b0 + k] = run;
     run += v[k];
   }
   if (t == 0) out[n] = total;
