@@ -130,6 +130,25 @@ def test_p0_rebuild_is_bit_identical():
         assert np.array_equal(x, y)
 
 
+def test_rebuild_and_reused_work_spaces_give_identical_solves():
+    """The lattice keeps its build scratch, P0 arrays and solve work spaces between calls (grow-only,
+    reused at other widths): a rebuild after a mixed solve (which adds an FP32 copy of P0), and
+    solves at 1, 3 and 1 energies, reproduce the first results bit for bit."""
+    spec = SPECS["doublet_mt_20"]
+    L = _lib_lattice(spec)
+    Es = [2.0, 7.5, 14.1]
+    first = L.solve([Es[0]], "fp64").amplitude(0)["A"]
+    mixed_first = L.solve(Es, "mixed_split", tol=1e-9, accept=1e-6).amplitude(1)["A"]
+    st0 = dict(L.perm_stats)
+    L.build_perm("fp64")
+    assert L.perm_stats["blocks"] == st0["blocks"] and L.perm_stats["candidates"] == st0["candidates"]
+    assert np.array_equal(L.solve([Es[0]], "fp64").amplitude(0)["A"], first)
+    many = L.solve(Es, "fp64")
+    assert np.array_equal(many.amplitude(0)["A"], first)
+    assert np.array_equal(L.solve([Es[0]], "fp64").amplitude(0)["A"], first)
+    assert np.array_equal(L.solve(Es, "mixed_split", tol=1e-9, accept=1e-6).amplitude(1)["A"], mixed_first)
+
+
 @pytest.mark.parametrize("name,E", [("pw10_mt_8", 3.0), ("pw10_mt_8", 22.7), ("pw18_mt_6", 3.0),
                                     ("quartet_yam_24", 1.0), ("quartet_yam_24", 3.0), ("quartet_yam_24", 10.0),
                                     ("doublet_mt_20", 3.0), ("doublet_mt_20", 14.1),
