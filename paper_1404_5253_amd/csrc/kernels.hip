@@ -1135,7 +1135,10 @@ __device__ __forceinline__ double g1_pint(double k2, double pa, double pb, doubl
 // [h pa^2, h pb^2]; with q_s its point nearest to the q bin, the 16-point Gauss-Legendre rule is
 // exact to rounding when the Bernstein ellipse parameter rho(q_s) of the bin is at least 3
 // (error ~ rho^-32). Returns false (element left to the wavefront rule) otherwise.
-__device__ bool g1_continuum_lane(const G1Args& g, double pa, double pb, double qa, double qb, double E,
+// Four lanes per element (sub = 0 .. 3, aligned groups of four): each sums the Gauss nodes
+// n = sub, sub + 4, ..., and the four partial sums are added by shuffles; the test before the sum
+// depends on the element only, so the four lanes of a group always take the same branch.
+__device__ bool g1_continuum_lane(const G1Args& g, int sub, double pa, double pb, double qa, double qb, double E,
                                   double2* out) {
   const double h = g.h2m, b3 = 0.75 * g.h2m;
   const double L2 = (E - h * pb * pb) / b3, U2 = (E - h * pa * pa) / b3;   // singular set in q^2
@@ -1162,10 +1165,13 @@ __device__ bool g1_continuum_lane(const G1Args& g, double pa, double pb, double 
   if (fmax(r1, r2) < 3.0) return false;
   const double sh = sqrt(h);
   double acc = 0.0;
-  for (int n = 0; n < 16; ++n) {
+#pragma unroll
+  for (int n = sub; n < 16; n += 4) {
     const double q = mid + half * g.gl16_x[n];
     acc += g.gl16_w[n] * g1_pint(E - b3 * q * q, pa, pb, sh);
   }
+  acc += __shfl_xor(acc, 1, WARP);
+  acc += __shfl_xor(acc, 2, WARP);
   const double d = (pb - pa) * (qb - qa);
   *out = make_double2(acc * half / d, 0.0);   // no shell point inside: real
   return true;
@@ -1174,7 +1180,9 @@ __device__ bool g1_continuum_lane(const G1Args& g, double pa, double pb, double 
 // One lane per element: bound-continuum elements and the continuum elements the lane rule
 // accepts are written; the others are appended to a work list for k_g1_wave.
 __global__ void __launch_bounds__(256) k_g1_lane(G1Args g) {
-  const int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t el = tid >> 2;   // four lanes per element
+  const int sub = (int)(tid & 3);
   const int lane = threadIdx.x & 63;
   const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
   bool defer = false;
@@ -1188,10 +1196,10 @@ __global__ void __launch_bounds__(256) k_g1_lane(G1Args g) {
       v = g1_bound_dev(g.qe[d.j], g.qe[d.j + 1], E, g.eps_b[d.w], g.h2m);
     } else {
       const double* bins = g.bins + (size_t)d.w * (g.M + 1);
-      ok = g1_continuum_lane(g, bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1], E, &v);
+      ok = g1_continuum_lane(g, sub, bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1], E, &v);
     }
-    if (ok) g1_store(g, d, v, 0, 1);
-    defer = !ok;
+    if (ok && sub == 0) g1_store(g, d, v, 0, 1);
+    defer = !ok && sub == 0;
   }
   const unsigned long long mask = __ballot(defer);
   if (mask) {
@@ -1228,7 +1236,7 @@ hipError_t launch_g1(const G1Args& g, hipStream_t s) {
   if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
   const int64_t n = g1_work_elems(g.nwave, g.M, g.N, g.nE);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, g.wl_n);
-  hipLaunchKernelGGL(k_g1_lane, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(k_g1_lane, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s, g);
   const int64_t wblocks = std::min<int64_t>(2048, std::max<int64_t>(1, (n + 3) / 4));
   hipLaunchKernelGGL(k_g1_wave, dim3((unsigned)wblocks), dim3(256), 0, s, g);
   return hipGetLastError();
