@@ -368,17 +368,17 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
     for (int g = 0; g < NC; ++g) ar[g] = ai[g] = 0.f;
     const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
     int64_t e = b0;
-    for (; e + 4 <= b1; e += 4) {
-      int cc[4];
+    for (; e + 8 <= b1; e += 8) {   // eight blocks' gathers in flight; sums in block order
+      int cc[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) cc[u] = col[e + u];
-      float2 xv[4][NC];
+      for (int u = 0; u < 8; ++u) cc[u] = col[e + u];
+      float2 xv[8][NC];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int gp = 0; gp < NC; ++gp) xv[u][gp] = t[((size_t)cc[u] * NC + gp) * B + cl];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const float* v = val + (e + u) * NC * NC;
 #pragma unroll
         for (int gp = 0; gp < NC; ++gp)
