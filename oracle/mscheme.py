@@ -136,3 +136,42 @@ def G_mscheme(ch, chp, two_J, q, qp, x):
         tot += p ** l * pp ** lp * acc / (two_J + 1)
     val = 8.0 * np.pi ** 2 * tot
     return val.real, val.imag
+
+
+def G_polynomial(ch, chp, two_J, n_x=16, check=4, seed=0):
+    """G_{gamma gamma'}(q, q', x) as an exact polynomial rebuilt from m-scheme samples.
+
+    G is homogeneous of degree L = l + l' in (q, q') (the factors p^l p'^l' turn the spherical
+    harmonics of p-hat and p'-hat into solid harmonics) and a polynomial in x, so
+    G = sum_{a=0..L} q^a q'^(L-a) h_a(x). The h_a are recovered from G_mscheme on L + 1 ratios
+    q/q' times n_x Chebyshev nodes in x; the structure is then checked against G_mscheme itself
+    at ``check`` random points (a failure raises). Nothing from eq. gal is used.
+
+    Returns a vectorised callable G(q, q', x).
+    """
+    from numpy.polynomial import chebyshev as _ch
+    L = ch[0] + chp[0]
+    r = np.linspace(0.45, 2.2, L + 1)
+    xs = np.cos(np.pi * (np.arange(n_x) + 0.5) / n_x)
+    S = np.array([[G_mscheme(ch, chp, two_J, rr, 1.0, xx)[0] for xx in xs] for rr in r])
+    V = np.vander(r, L + 1, increasing=True)
+    H = np.linalg.solve(V, S)                      # H[a, m] = h_a(x_m)
+    coef = [_ch.chebfit(xs, H[a], n_x - 1) for a in range(L + 1)]
+
+    def G(q, qp, x):
+        q, qp, x = np.broadcast_arrays(np.asarray(q, float), np.asarray(qp, float), np.asarray(x, float))
+        out = np.zeros(q.shape)
+        for a in range(L + 1):
+            out = out + q ** a * qp ** (L - a) * _ch.chebval(x, coef[a])
+        return out
+
+    rng = np.random.default_rng(seed)
+    scale = max(np.abs(S).max(), 1.0)
+    for _ in range(check):
+        q, qp, x = rng.uniform(0.2, 3.0), rng.uniform(0.2, 3.0), rng.uniform(-1.0, 1.0)
+        ref = G_mscheme(ch, chp, two_J, q, qp, x)[0]
+        got = float(G(q, qp, x))
+        tol = 1e-10 * scale * max(q, qp, 1.0) ** L
+        if abs(got - ref) > tol:
+            raise AssertionError(f"G is not the assumed polynomial for {ch}, {chp}: {got} vs {ref}")
+    return G

@@ -20,11 +20,16 @@ evaluated with an n_x-point Gauss-Legendre rule in x on [-1, 1] and an n_phi-poi
 on an empty Q range) and written 0.5 (U - L)(U + L); (a, b) = (l1 + l1', l2 + l2') (pinned by
 the m-scheme evaluation of G in ``mscheme``); atan of x/0 is pi/2.
 
-(ii) SEMI-ANALYTIC (s-wave, l = l' = 0): the 3D (q, q', x) form before the polar substitution
-with x traded for pi1 (dx = 2 pi1 dpi1 / (q q'), pi2^2 = pi1^2 + 3/4 (q'^2 - q^2)); the inner
-integral is 2 ln(pi1 + pi2) on one exact pi1 interval and the (q, q') box is done adaptively.
+(ii) SEMI-ANALYTIC: the 3D (q, q', x) form before the polar substitution with x traded for pi1
+(dx = 2 pi1 dpi1 / (q q'), pi2^2 = pi1^2 + 3/4 (q'^2 - q^2)). For s-wave the inner integral is
+2 ln(pi1 + pi2) on one exact pi1 interval and the (q, q') box is done adaptively
+(``element_semianalytic_s``). For any channel pair the inner integral of G / (pi1^l' pi2^l) is a
+smooth integral in w = ln(pi1 + pi2) on the same exact interval, with G supplied by the caller
+(the tests pass the m-scheme G, which shares nothing with the moment decomposition of the rule)
+and the box done by a composite Gauss rule (``element_semianalytic``).
 
-(iii) BRUTE FORCE: midpoint sums of the 3D theta form on tiny lattices.
+(iii) BRUTE FORCE: midpoint sums of the 3D theta form on tiny lattices (``element_bruteforce_s``,
+``element_bruteforce``).
 
 Layout used by the oracle: a lattice row/column index is (j, i) -> j * M + i.
 """
@@ -246,6 +251,88 @@ def element_bruteforce_s(p_edges, q_edges, i, j, ip, jp, n):
     pi2 = np.sqrt(0.25 * Q * Q + QP * QP + Q * QP * X)
     th = ((pi1 > p_edges[ip]) & (pi1 <= p_edges[ip + 1]) & (pi2 > p_edges[i]) & (pi2 <= p_edges[i + 1]))
     f = np.where(th, Q * QP / (pi1 * pi2), 0.0)
+    vol = (qb - qa) * (qpb - qpa) * 2.0 / n ** 3
+    dp = np.diff(p_edges)
+    dq = np.diff(q_edges)
+    return f.sum() * vol / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
+
+
+# --------------------------------------------------------------------------- pins (any channel pair)
+
+def element_rule_channel(p_edges, q_edges, i, j, ip, jp, keys, Cab, n_x, n_phi):
+    """Channel-pair element sum_m C[g, g', m] * moment_m of one cell pair by the rule."""
+    return float(sum(c * element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi)
+                     for key, c in zip(keys, Cab) if c != 0.0))
+
+
+def element_semianalytic(p_edges, q_edges, i, j, ip, jp, G, l, lp, n_w=24, n_sub=96, n_g=6):
+    """Channel-pair element of P0 from the 3D kernel, for any l, l' (eq. P_kern before the polar step).
+
+    With the kernel delta(p' - pi1) delta(p - pi2) G(q, q', x) / (p'^(l'+2) p^(l+2)) and the unit
+    momentum weights, the element is
+
+        (d_i dq_j d_i' dq_j')^(-1/2) int dq int dq' int dx q q' G / (pi1^(l'+1) pi2^(l+1))
+                                          * theta(pi1 in D_i') theta(pi2 in D_i).
+
+    x -> pi1 (dx = 2 pi1 dpi1 / (q q')) and then w = ln(pi1 + pi2) (dpi1 / pi2 = dw, which
+    removes the 1/pi2 end singularity) turn the x integral into
+
+        2 int dw G(q, q', x(w)) / (pi1^l' pi2^l),  pi1 = (e^w - c e^-w)/2, pi2 = (e^w + c e^-w)/2,
+
+    c = 3/4 (q'^2 - q^2), over the exact pi1 interval [|q - q'/2|, q + q'/2] cap D_i' cap
+    {pi2 in D_i}. That smooth integral takes an n_w-point Gauss rule. The result is a continuous
+    function of (q, q') with kinks where the interval ends switch, integrated over the box by a
+    composite Gauss rule (n_sub panels of n_g points per axis; error O(n_sub^-2) at the kinks).
+    G is any vectorised callable (for the pin: the m-scheme polynomial).
+    """
+    pa, pb = p_edges[i], p_edges[i + 1]
+    ppa, ppb = p_edges[ip], p_edges[ip + 1]
+    tg, tw = _leg.leggauss(n_w)
+    gg, gw = _leg.leggauss(n_g)
+
+    def composite(a, b):
+        h = (b - a) / n_sub
+        mids = a + h * (np.arange(n_sub) + 0.5)
+        return (mids[:, None] + 0.5 * h * gg[None, :]).ravel(), np.tile(0.5 * h * gw, n_sub)
+
+    q, wq = composite(q_edges[j], q_edges[j + 1])
+    qp, wqp = composite(q_edges[jp], q_edges[jp + 1])
+    Q, QP = np.meshgrid(q, qp, indexing="ij")
+    W2 = np.outer(wq, wqp)
+    Q, QP, W2 = Q.ravel(), QP.ravel(), W2.ravel()
+    c = 0.75 * (QP * QP - Q * Q)
+    lo = np.maximum(np.maximum(np.abs(Q - 0.5 * QP), ppa), np.sqrt(np.maximum(0.0, pa * pa - c)))
+    hi = np.minimum(np.minimum(Q + 0.5 * QP, ppb), np.sqrt(np.maximum(0.0, pb * pb - c)))
+    ok = (pb * pb - c > 0.0) & (hi > lo)
+    Q, QP, W2, c, lo, hi = Q[ok], QP[ok], W2[ok], c[ok], lo[ok], hi[ok]
+    w0 = np.log(lo + np.sqrt(np.maximum(0.0, lo * lo + c)))
+    w1 = np.log(hi + np.sqrt(np.maximum(0.0, hi * hi + c)))
+    w = 0.5 * (w0 + w1)[:, None] + 0.5 * (w1 - w0)[:, None] * tg[None, :]
+    e, ei = np.exp(w), np.exp(-w)
+    pi1 = 0.5 * (e - c[:, None] * ei)
+    pi2 = 0.5 * (e + c[:, None] * ei)
+    Qb, QPb = Q[:, None], QP[:, None]
+    x = np.clip((pi1 * pi1 - Qb * Qb - 0.25 * QPb * QPb) / (Qb * QPb), -1.0, 1.0)
+    f = G(Qb, QPb, x) / (pi1 ** lp * pi2 ** l)
+    inner = 2.0 * 0.5 * (w1 - w0) * (f @ tw)
+    dp = np.diff(p_edges)
+    dq = np.diff(q_edges)
+    return float(np.dot(W2, inner)) / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
+
+
+def element_bruteforce(p_edges, q_edges, i, j, ip, jp, G, l, lp, n):
+    """Midpoint sum with n^3 points of the 3D (q, q', x) theta form for any channel pair."""
+    qa, qb = q_edges[j], q_edges[j + 1]
+    qpa, qpb = q_edges[jp], q_edges[jp + 1]
+    t = (np.arange(n) + 0.5) / n
+    q = qa + (qb - qa) * t
+    qp = qpa + (qpb - qpa) * t
+    x = -1.0 + 2.0 * t
+    Q, QP, X = np.meshgrid(q, qp, x, indexing="ij")
+    pi1 = np.sqrt(Q * Q + 0.25 * QP * QP + Q * QP * X)
+    pi2 = np.sqrt(0.25 * Q * Q + QP * QP + Q * QP * X)
+    th = ((pi1 > p_edges[ip]) & (pi1 <= p_edges[ip + 1]) & (pi2 > p_edges[i]) & (pi2 <= p_edges[i + 1]))
+    f = np.where(th, Q * QP * G(Q, QP, X) / (pi1 ** (lp + 1) * pi2 ** (l + 1)), 0.0)
     vol = (qb - qa) * (qpb - qpa) * 2.0 / n ** 3
     dp = np.diff(p_edges)
     dq = np.diff(q_edges)
