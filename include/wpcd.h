@@ -212,6 +212,17 @@ wp_status faddeev_solve(wp_lattice* lat, int n_E, const double* E_lab, const wp_
 wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, double* A, double* S,
                     double* delta_deg, double* eta, double* err_est, int* n_iter);
 
+/*
+ * On-shell series of the FP64 path (Sec. II.A; Sec. V.A step 5): the terms
+ * a_n[f] = e_f^T O y_n, y_n = K^n b, that the Pade summation of energy e_idx and initial
+ * channel `initial` (0 <= initial < n_open, the order of amplitude()'s columns) consumed, in
+ * order, for every final channel f. *n_terms in: capacity of a in terms; out: number of terms.
+ * a (may be NULL to query *n_terms): n_terms * n_open complex numbers, term-major
+ * (a[2 * (n * n_open + f) + {0, 1}] = re/im of a_n[f]). Solutions of the mixed modes hold no
+ * series (*n_terms = 0). WP_EINVAL if the capacity is too small.
+ */
+wp_status faddeev_series(const wp_solution* sol, int e_idx, int initial, int* n_terms, double* a);
+
 void wp_solution_free(wp_solution* sol);
 
 /*

@@ -133,7 +133,7 @@ def solve_energy(sysm: System, E_lab, tol=1e-12, n_max=200, direct=False, P0full
     K = kernel(sysm, E, P0full)
     opens = initial_channels(sysm)
     U = np.zeros((len(opens), len(opens)), dtype=complex)
-    iters, conv, errs = [], [], []
+    iters, conv, errs, series = [], [], [], []
     for b, g0 in enumerate(opens):
         if direct:
             U[:, b] = solve.direct_solve(K, g0, j0, opens)
@@ -141,7 +141,8 @@ def solve_energy(sysm: System, E_lab, tol=1e-12, n_max=200, direct=False, P0full
             conv.append(True)
             errs.append(0.0)
         else:
-            est, n, ok, _, err = solve.iterate_pade(K, g0, j0, opens, tol=tol, n_max=n_max)
+            est, n, ok, terms, err = solve.iterate_pade(K, g0, j0, opens, tol=tol, n_max=n_max)
+            series.append(terms)
             U[:, b] = est
             errs.append(np.max(err / np.maximum(np.abs(est), 1e-300)))
             iters.append(n)
@@ -150,4 +151,4 @@ def solve_energy(sysm: System, E_lab, tol=1e-12, n_max=200, direct=False, P0full
     A = amp.amplitude_matrix(U, q0, dq0, sysm.spec.h2m)
     S = amp.s_matrix(A)
     return dict(E=E, q0=q0, j0=j0, U=U, A=A, S=S, iters=iters, converged=all(conv), rel_err=max(errs),
-                delta=amp.phase_deg(S), eta=amp.inelasticity(S))
+                delta=amp.phase_deg(S), eta=amp.inelasticity(S), series=series)

@@ -14,9 +14,16 @@ G_kj: the p integral is done in closed form for fixed q (log or arctangent), the
 adaptive quadrature with breakpoints at the singular points; for E > 0 the imaginary part is
 -(pi / (d*_k dq_j)) (1 / (2 sqrt(h b3))) times the polar angle of the energy ellipse inside the
 rectangle (p = sqrt(E/h) cos t, q = sqrt(E/b3) sin t).
+Where the energy shell crosses the box or passes within one bin width of it, the q integrand
+has endpoint singularities (an inverse square root where E - b3 q^2 changes sign, logarithms
+where the pole of the p integrand meets a p-bin edge) that limit double-precision adaptive
+quadrature to about 1e-10; those elements are integrated in 30-digit arithmetic (mpmath
+tanh-sinh, the same formula and breakpoints). Every other element has a smooth integrand and
+is done in double precision.
 """
 from __future__ import annotations
 
+import mpmath
 import numpy as np
 from scipy import integrate
 
@@ -61,9 +68,54 @@ def _arc_inside(pa, pb, qa, qb, E, h, b3):
     return max(0.0, min(hi_p, hi_q) - max(lo_p, lo_q))
 
 
+def _inner_p_mp(q, pa, pb, E, h, b3):
+    """_inner_p in mpmath arithmetic."""
+    c2 = E - b3 * q * q
+    sh = mpmath.sqrt(h)
+    if c2 > 0:
+        c = mpmath.sqrt(c2)
+        g = lambda p: mpmath.log(abs((c + sh * p) / (c - sh * p)))
+        return (g(pb) - g(pa)) / (2 * c * sh)
+    if c2 < 0:
+        k = mpmath.sqrt(-c2)
+        return -(mpmath.atan(sh * pb / k) - mpmath.atan(sh * pa / k)) / (sh * k)
+    return 1 / (h * pb) - 1 / (h * pa)
+
+
+def _near_shell(pa, pb, qa, qb, E, h, b3):
+    """True if the q set where the p bin holds the pole (h pa^2 <= E - b3 q^2 <= h pb^2) lies within
+    one bin width of [qa, qb]."""
+    hi2 = (E - h * pa * pa) / b3
+    if E <= 0.0 or hi2 <= 0.0:
+        return False
+    lo = np.sqrt(max((E - h * pb * pb) / b3, 0.0))
+    w = qb - qa
+    return lo <= qb + w and np.sqrt(hi2) >= qa - w
+
+
+def _real_part_mp(pa, pb, qa, qb, E, h2m):
+    mp = mpmath.mpf
+    with mpmath.workdps(30):
+        h = mp(h2m)
+        b3 = mp(3) / 4 * h
+        pa_, pb_, qa_, qb_, E_ = mp(pa), mp(pb), mp(qa), mp(qb), mp(E)
+        pts = [qa_, qb_]
+        for c2 in (E_, E_ - h * pa_ * pa_, E_ - h * pb_ * pb_):
+            if c2 > 0:
+                qs = mpmath.sqrt(c2 / b3)
+                if qa_ < qs < qb_:
+                    pts.append(qs)
+        re = mpmath.quad(lambda q: _inner_p_mp(q, pa_, pb_, E_, h, b3), sorted(set(pts)))
+        return float(re)
+
+
 def continuum_element(pa, pb, qa, qb, E, h2m=H2M, epsabs=1e-15, epsrel=1e-13):
     h = h2m
     b3 = 0.75 * h2m
+    if _near_shell(pa, pb, qa, qb, E, h, b3):
+        re = _real_part_mp(pa, pb, qa, qb, E, h2m)
+        im = -np.pi / (2.0 * np.sqrt(h * b3)) * _arc_inside(pa, pb, qa, qb, E, h, b3)
+        return (re + 1j * im) / ((pb - pa) * (qb - qa))
     pts = []
     for c2 in (E, E - h * pa * pa, E - h * pb * pb):
         if c2 > 0:

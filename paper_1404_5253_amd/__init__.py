@@ -85,6 +85,7 @@ _SIGS = {
     "perm_matrix_export": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _D]),
     "faddeev_solve": (C.c_int, [_P, C.c_int, _D, C.POINTER(_SolveOpts), _P, C.POINTER(_P)]),
     "amplitude": (C.c_int, [_P, C.c_int, _I, _D, _D, _D, _D, _D, _I]),
+    "faddeev_series": (C.c_int, [_P, C.c_int, C.c_int, _I, _D]),
     "wp_solution_free": (None, [_P]),
     "faddeev_batch_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_SolveOpts), C.POINTER(_P)]),
     "faddeev_batch_admit": (C.c_int, [_P, C.c_double, _I]),
@@ -205,6 +206,17 @@ def amplitude(sol, e_idx):
                 delta=dl, eta=et, err=er, iters=np.array(list(it)))
 
 
+def faddeev_series(sol, e_idx, initial=0):
+    """Series terms a_n of the FP64 path: complex array (n_terms, n_open)."""
+    n = C.c_int(0)
+    _check(_lib.faddeev_series(sol, e_idx, initial, C.byref(n), None))
+    nopen = C.c_int()
+    _check(_lib.amplitude(sol, e_idx, C.byref(nopen), None, None, None, None, None, None))
+    a = np.zeros(2 * n.value * nopen.value)
+    _check(_lib.faddeev_series(sol, e_idx, initial, C.byref(n), _dptr(a)))
+    return (a[0::2] + 1j * a[1::2]).reshape(n.value, nopen.value)
+
+
 def wp_profile_enable(on=True):
     _check(_lib.wp_profile_enable(1 if on else 0))
 
@@ -237,6 +249,9 @@ class Solution:
 
     def amplitude(self, e_idx=0):
         return amplitude(self.h, e_idx)
+
+    def series(self, e_idx=0, initial=0):
+        return faddeev_series(self.h, e_idx, initial)
 
     def __del__(self, _lib=_lib):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -175,6 +175,7 @@ static void finish_slot(wp_batch* b, wp_batch::Slot& S) {
       for (int f = 0; f < nf; ++f) S.r.U[f * nf + f0] = est[f];
       S.r.err[f0] = cs.err;
       S.r.iters[f0] = cs.n;
+      S.r.series[f0] = std::move(cs.terms);
       S.r.ok &= cs.ok;
     }
   }

@@ -410,8 +410,8 @@ wp_status wpcd::upload_waves(wp_lattice* L) {
   }
   // tanh-sinh rule on [-1, 1]: t = k h, x = tanh(pi/2 sinh t), with the node position kept as a
   // fraction of the interval measured from the nearer end
-  const double hts = 1.0 / 6.0;   // t in [-3.33, 3.33]: end weights below 1e-18
-  const int K = 20;
+  const double hts = 1.0 / 12.0;   // t in [-3.33, 3.33]: end weights below 1e-18
+  const int K = 40;
   std::vector<double> tu, tv, tw;
   for (int k = -K; k <= K; ++k) {
     double t = k * hts, sarg = 0.5 * M_PI * std::sinh(t);
@@ -983,6 +983,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
       for (int f = 0; f < nfin; ++f) r.U[f * nfin + b] = est[f];
       r.err[b] = c.err;
       r.iters[b] = c.n;
+      r.series[b] = std::move(c.terms);
       r.ok &= c.ok;
     }
     allok &= r.ok;
@@ -1044,6 +1045,25 @@ extern "C" wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, d
     if (err) err[a] = r.err[a];
     if (n_iter) n_iter[a] = r.iters[a];
   }
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_series(const wp_solution* sol, int e_idx, int initial, int* n_terms, double* a) {
+  if (!sol || !n_terms) return fail(WP_EINVAL, "NULL argument");
+  if (e_idx < 0 || e_idx >= (int)sol->res.size()) return fail(WP_EINVAL, "energy index out of range");
+  const EnergyResult& r = sol->res[e_idx];
+  if (initial < 0 || initial >= r.n_open) return fail(WP_EINVAL, "initial channel out of range");
+  static const std::vector<cplx> none;
+  const std::vector<cplx>& t = r.series.size() > (size_t)initial ? r.series[initial] : none;
+  const int n = r.n_open > 0 ? (int)(t.size() / r.n_open) : 0;
+  if (a) {
+    if (*n_terms < n) return fail(WP_EINVAL, "faddeev_series: output holds fewer terms than the series");
+    for (size_t k = 0; k < t.size(); ++k) {
+      a[2 * k] = t[k].real();
+      a[2 * k + 1] = t[k].imag();
+    }
+  }
+  *n_terms = n;
   return WP_OK;
 }
 

@@ -1006,9 +1006,30 @@ namespace wpcd {
 
 // ------------------------------------------------------------------ step 4: channel resolvent G1
 
+// 1 - r(t)^2 on one edge of the box in the polar variables p = P r cos t, q = Q r sin t:
+//   p edge (value v): r = v / (P cos t),  q edge: r = v / (Q sin t).
+// ts is the angle at which the energy shell r = 1 meets the edge (acos(v/P) or asin(v/Q); < 0 when
+// it does not). Near ts the difference is formed from the node's offset to the segment end it was
+// placed from (t - ts = (base - ts) + off, exact when base is ts itself), using
+// cos^2 t - cos^2 ts = -sin(t - ts) sin(t + ts) and sin^2 t - sin^2 ts = sin(t - ts) sin(t + ts),
+// so that the logarithm keeps full relative accuracy next to its singular point.
+__device__ __forceinline__ double g1_omr2(bool pedge, double v, double PQ, double ts, double t, double base,
+                                          double off, double st, double ct) {
+  if (ts < 0.0) {
+    const double r = v / (PQ * (pedge ? ct : st));
+    return 1.0 - r * r;
+  }
+  const double d = (base - ts) + off;
+  const double num = sin(d) * sin(t + ts);
+  return pedge ? -num / (ct * ct) : num / (st * st);
+}
+
 // Continuum element (1/(dp dq)) int int dp dq / (E + i0 - h p^2 - b3 q^2) (eq. dg1b, unit weights),
 // evaluated by one wavefront: lanes share the quadrature nodes, a shuffle reduction sums them.
-// E < 0: p integral in closed form (arctangent), q integral by two 20-point Gauss panels.
+// E < 0: p integral in closed form (arctangent), then q = kappa sinh u with kappa^2 = -E/b3, which
+// turns dq / sqrt(b3 q^2 - E) into du / sqrt(b3) and leaves a smooth integrand also when E is
+// just below the breakup threshold (the branch points q = +-i kappa then nearly touch q = 0);
+// two 20-point Gauss panels in u.
 // E > 0: p = P r cos t, q = Q r sin t (P = sqrt(E/h), Q = sqrt(E/b3)) gives
 //   Re = (1/sqrt(h b3)) int dt [-1/2 ln|1 - r^2|]_{r_lo(t)}^{r_hi(t)},
 // split at the box corners and where the energy shell r = 1 crosses a box edge (log
@@ -1018,29 +1039,33 @@ __device__ double2 g1_continuum_wave(const G1Args& g, int lane, double pa, doubl
   const double h = g.h2m, b3 = 0.75 * g.h2m;
   double re = 0.0, im = 0.0;
   if (E <= 0.0) {
-    const double sh = sqrt(h);
-    const double mid = 0.5 * (qa + qb);
+    const double sh = sqrt(h), sb = sqrt(b3);
+    const double kap = sqrt(-E / b3), sE = sqrt(-E);
+    // E = 0 exactly (the breakup threshold): plain q, dq / (sb q)
+    const double ua = E < 0.0 ? asinh(qa / kap) : qa, ub = E < 0.0 ? asinh(qb / kap) : qb;
+    const double mid = 0.5 * (ua + ub);
     double part = 0.0;
     for (int idx = lane; idx < 2 * g.ngl; idx += 64) {
       const int panel = idx / g.ngl, n = idx - panel * g.ngl;
-      const double a = panel ? mid : qa, b = panel ? qb : mid;
-      const double q = 0.5 * (a + b) + 0.5 * (b - a) * g.gl_x[n];
-      const double k = sqrt(b3 * q * q - E);
-      part += 0.5 * (b - a) * g.gl_w[n] * (-atan2(sh * (pb - pa) * k, k * k + h * pa * pb) / (sh * k));
+      const double a = panel ? mid : ua, b = panel ? ub : mid;
+      const double u = 0.5 * (a + b) + 0.5 * (b - a) * g.gl_x[n];
+      // k = sqrt(b3 q^2 - E) at q = kappa sinh u, and dq / k = du / sb
+      const double k = E < 0.0 ? sE * cosh(u) : sb * u;
+      const double jac = E < 0.0 ? 1.0 / sb : 1.0 / k;
+      part += 0.5 * (b - a) * g.gl_w[n] * (-atan2(sh * (pb - pa) * k, k * k + h * pa * pb) / sh) * jac;
     }
     re = wave_sum(part);
   } else {
     const double P = sqrt(E / h), Q = sqrt(E / b3);
     const double t0 = atan2(qa / Q, pb / P), t1 = atan2(qb / Q, pa / P);
+    // shell crossings of the four edges (-1: none)
+    const double tpa = pa / P < 1.0 ? acos(pa / P) : -1.0, tpb = pb / P < 1.0 ? acos(pb / P) : -1.0;
+    const double tqa = qa / Q < 1.0 ? asin(qa / Q) : -1.0, tqb = qb / Q < 1.0 ? asin(qb / Q) : -1.0;
     double pts[8];
     int np = 0;
     pts[np++] = t0;
     pts[np++] = t1;
-    double cand[6] = {atan2(qa / Q, pa / P), atan2(qb / Q, pb / P), -1, -1, -1, -1};
-    if (pa / P < 1.0) cand[2] = acos(pa / P);
-    if (pb / P < 1.0) cand[3] = acos(pb / P);
-    if (qa / Q < 1.0) cand[4] = asin(qa / Q);
-    if (qb / Q < 1.0) cand[5] = asin(qb / Q);
+    const double cand[6] = {atan2(qa / Q, pa / P), atan2(qb / Q, pb / P), tpa, tpb, tqa, tqb};
     for (int c = 0; c < 6; ++c)
       if (cand[c] > t0 && cand[c] < t1) pts[np++] = cand[c];
     for (int x = 1; x < np; ++x)  // insertion sort (np <= 8)
@@ -1056,15 +1081,36 @@ __device__ double2 g1_continuum_wave(const G1Args& g, int lane, double pa, doubl
       const double a = pts[sgi], b = pts[sgi + 1];
       if (!(b > a)) continue;
       const double u = g.ts_u[n];
-      const double t = (u <= 0.5) ? a + (b - a) * u : b - (b - a) * g.ts_v[n];
+      // node placed from the nearer end: t = base + off
+      const double base = (u <= 0.5) ? a : b;
+      const double off = (u <= 0.5) ? (b - a) * u : -(b - a) * g.ts_v[n];
+      const double t = base + off;
       double st, ct;
       sincos(t, &st, &ct);
+      // r_lo = max(pa / (P cos t), qa / (Q sin t)), r_hi = min(pb / (P cos t), qb / (Q sin t)),
+      // remembering which edge gives each
       double rlo = 0.0;
-      if (pa > 0.0) rlo = pa / (P * ct);
-      if (qa > 0.0) rlo = fmax(rlo, qa / (Q * st));
-      const double rhi = fmin(pb / (P * ct), qb / (Q * st));
+      int elo = -1;   // 0: p edge pa, 1: q edge qa
+      if (pa > 0.0) {
+        rlo = pa / (P * ct);
+        elo = 0;
+      }
+      if (qa > 0.0 && qa / (Q * st) > rlo) {
+        rlo = qa / (Q * st);
+        elo = 1;
+      }
+      const double rp = pb / (P * ct), rq = qb / (Q * st);
+      const bool hp = rp <= rq;
+      const double rhi = hp ? rp : rq;
       if (rhi > rlo) {
-        const double f = -0.5 * log(fabs(1.0 - rhi * rhi)) + 0.5 * log(fabs(1.0 - rlo * rlo));
+        const double xh = hp ? g1_omr2(true, pb, P, tpb, t, base, off, st, ct)
+                             : g1_omr2(false, qb, Q, tqb, t, base, off, st, ct);
+        double f = -0.5 * log(fabs(xh));
+        if (elo >= 0) {
+          const double xl = elo == 0 ? g1_omr2(true, pa, P, tpa, t, base, off, st, ct)
+                                     : g1_omr2(false, qa, Q, tqa, t, base, off, st, ct);
+          f += 0.5 * log(fabs(xl));
+        }
         if (isfinite(f)) part += 0.5 * (b - a) * g.ts_w[n] * f;   // a node on the shell carries no weight
       }
     }

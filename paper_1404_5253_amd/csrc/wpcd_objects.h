@@ -98,6 +98,8 @@ struct EnergyResult {
   std::vector<cplx> U;      // [final][initial]
   std::vector<double> err;  // per initial column
   std::vector<int> iters;
+  // FP64 path: the on-shell series terms a_n read for each initial column b, series[b][n * n_open + f]
+  std::vector<std::vector<cplx>> series;
   bool ok = true;
 };
 
@@ -181,6 +183,7 @@ inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {
   r.U.assign(r.n_open * r.n_open, cplx(0, 0));
   r.err.assign(r.n_open, 0.0);
   r.iters.assign(r.n_open, 0);
+  r.series.assign(r.n_open, std::vector<cplx>());
   r.ok = true;
   return true;
 }
@@ -197,6 +200,7 @@ struct ColState {
   int best_n = 0, streak = 0, n = 0, plateau = 24;
   bool done = false, ok = false;
   double err = 0.0;
+  std::vector<cplx> terms;    // every term pushed, [n][final]
 };
 constexpr int PLATEAU = 24;
 
@@ -204,6 +208,7 @@ constexpr int PLATEAU = 24;
 inline bool column_push(ColState& cs, const cplx* a, int nfin, double tol, double accept) {
   std::vector<cplx> est(nfin);
   double Smax = 0.0;
+  cs.terms.insert(cs.terms.end(), a, a + nfin);
   for (int f = 0; f < nfin; ++f) {
     cs.S[f] += a[f];
     est[f] = cs.w[f].push(cs.S[f]);

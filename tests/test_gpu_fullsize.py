@@ -4,9 +4,12 @@
   pairs against the oracle's count (exact), 64 seeded P0 elements recomputed one by one with the
   oracle's rule, and the on-shell amplitudes at 14.1 MeV against the oracle's FP64 solve
   (tests/golden/swave_mt_100.json, written by tests/golden/make_golden.py from the oracle only).
-* 18-channel Malfliet-Tjon, M = N = 150 (J = 1/2+, j <= 2): sampled P0 blocks against the
-  oracle's rule for every moment contracted with the oracle's recoupling coefficients; the 2 x 2
-  S matrix at 3 MeV (below breakup) unitary; both mixed paths against the FP64 path.
+* 18-channel Malfliet-Tjon, M = N = 150 (J = 1/2+, j <= 2): the number of stored blocks and of
+  stored entries against the oracle's (exact), sampled P0 blocks against the oracle's rule for
+  every moment contracted with the oracle's recoupling coefficients; the FP64 solve of 3 and
+  22.7 MeV in one call (4 columns: the kernels the bench times) against the oracle's series
+  terms (1e-10, growing linearly after ten terms) and amplitudes (tests/golden/pw_mt_150.json); the 2 x 2 S matrix at 3 MeV
+  (below breakup) unitary; both mixed paths against the oracle's amplitudes (1e-6).
 """
 import json
 import os
@@ -24,6 +27,7 @@ if gpu_available():
 import workloads
 from oracle import pipeline, recoupling
 from oracle.perm import channel_terms, element_rule
+from parity_util import amplitude_tolerance, series_mismatch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -73,9 +77,12 @@ def test_swave_mt_100_against_oracle(golden, two_J):
         assert np.max(np.abs(blk - C[:, :, 0] * v)) <= 1e-12 * scale, (i, j, ip, jp)
     ref = g["results"]["14.1"]
     Ar = ref["A_re"] + 1j * ref["A_im"]
-    a = L.solve([14.1], "fp64").amplitude(0)
-    bound = 1e-10 * abs(Ar) + 30 * max(a["err"][0], ref["rel_err"]) * abs(Ar)
-    assert abs(a["A"][0, 0] - Ar) <= bound, (abs(a["A"][0, 0] - Ar) / abs(Ar), a["err"])
+    sol = L.solve([14.1], "fp64")
+    a = sol.amplitude(0)
+    terms = (np.array(ref["series_re"]) + 1j * np.array(ref["series_im"]))[:, None]
+    assert series_mismatch(sol.series(0, 0), terms) <= 1e-10
+    tol = amplitude_tolerance([terms])
+    assert abs(a["A"][0, 0] - Ar) <= tol * abs(Ar), (tol, abs(a["A"][0, 0] - Ar) / abs(Ar), a["err"])
     for mode in ("mixed", "mixed_split"):
         m = L.solve([14.1], mode, tol=1e-8).amplitude(0)
         assert abs(m["A"][0, 0] - Ar) <= 1e-6, (mode, abs(m["A"][0, 0] - Ar))
@@ -116,16 +123,47 @@ def test_pw_mt_150_sampled_blocks(pw150):
         assert np.max(np.abs(val[b] - ref)) <= 1e-12 * scale, (i, j, ip, jp, np.max(np.abs(val[b] - ref)) / scale)
 
 
-def test_pw_mt_150_unitarity_and_mixed(pw150):
+@pytest.fixture(scope="module")
+def golden150():
+    with open(os.path.join(HERE, "golden", "pw_mt_150.json")) as f:
+        return json.load(f)
+
+
+def test_pw_mt_150_pattern_counts(pw150, golden150):
+    """Stored blocks and stored scalar entries equal the oracle's counts at full size."""
+    L, st, spec, wl = pw150
+    assert [list(c) for c in L.channels] == golden150["channels"]
+    assert st["blocks"] == golden150["blocks"]
+    assert st["nnz"] == golden150["nnz"]
+
+
+def test_pw_mt_150_fp64_against_oracle(pw150, golden150):
     L, st, spec, wl = pw150
     E_lo, E_hi = wl["E_lab"]
-    ref = L.solve([E_lo, E_hi], "fp64", tol=1e-10, max_iter=400)
-    lo = ref.amplitude(0)
-    S = lo["S"]
+    sol = L.solve([E_lo, E_hi], "fp64", tol=1e-12, accept=1e-6, max_iter=400)
+    assert sol.converged
+    for k, E in enumerate((E_lo, E_hi)):
+        g = golden150["results"][str(E)]
+        got = sol.amplitude(k)
+        refs = [np.array(g["series_re"][b]) + 1j * np.array(g["series_im"][b]) for b in range(2)]
+        for b in range(2):
+            d = series_mismatch(sol.series(k, b), refs[b])
+            assert d <= 1e-10, (E, b, d)
+        Ar = np.array(g["A_re"]) + 1j * np.array(g["A_im"])
+        tol = amplitude_tolerance(refs)
+        assert np.max(np.abs(got["A"] - Ar)) <= tol * np.max(np.abs(Ar)), (E, tol, np.max(np.abs(got["A"] - Ar)))
+    S = sol.amplitude(0)["S"]
     assert S.shape == (2, 2)
     assert np.max(np.abs(S @ S.conj().T - np.eye(2))) <= 1e-6      # two open channels below breakup
-    for mode in ("mixed", "mixed_split"):
-        mix = L.solve([E_lo, E_hi], mode, tol=1e-8)
-        for k in range(2):
-            d = np.max(np.abs(mix.amplitude(k)["A"] - ref.amplitude(k)["A"]))
-            assert d <= 1e-6, (mode, k, d)
+
+
+@pytest.mark.parametrize("mode", ["mixed", "mixed_split"])
+def test_pw_mt_150_mixed_against_oracle(pw150, golden150, mode):
+    L, st, spec, wl = pw150
+    E_lo, E_hi = wl["E_lab"]
+    mix = L.solve([E_lo, E_hi], mode, tol=1e-8)
+    for k, E in enumerate((E_lo, E_hi)):
+        g = golden150["results"][str(E)]
+        Ar = np.array(g["A_re"]) + 1j * np.array(g["A_im"])
+        d = np.max(np.abs(mix.amplitude(k)["A"] - Ar))
+        assert d <= 1e-6, (mode, E, d)

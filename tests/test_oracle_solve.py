@@ -78,6 +78,52 @@ def test_continuum_element_vs_swapped_order(E):
         assert g == pytest.approx(ref, rel=1e-9, abs=1e-12), (pa, pb, qa, qb)
 
 
+def _energy_route_ref(pa, pb, qa, qb, E):
+    """A third route to the continuum element, in 30-digit arithmetic: with eps = h p^2 + b3 q^2 and
+    the polar angle of the ellipse as second variable (dp dq = d eps dt / (2 sqrt(h b3))),
+    int int dp dq / (E + i0 - eps) = (1 / (2 sqrt(h b3))) int d eps theta(eps) / (E + i0 - eps),
+    theta(eps) = angle of the ellipse eps inside the box (closed form). The principal value is
+    taken by subtracting theta(E); the imaginary part is -pi theta(E) / (2 sqrt(h b3)).
+    Breakpoints: the four corner energies (kinks of theta) and E."""
+    with mpmath.workdps(30):
+        h = mpmath.mpf(H)
+        b3 = h * 3 / 4
+        pa, pb, qa, qb, E = [mpmath.mpf(x) for x in (pa, pb, qa, qb, E)]
+
+        def theta(e):
+            if e <= 0:
+                return mpmath.mpf(0)
+            P, Q = mpmath.sqrt(e / h), mpmath.sqrt(e / b3)
+            lo = max(mpmath.acos(min(1, pb / P)), mpmath.asin(min(1, qa / Q)))
+            hi = min(mpmath.acos(min(1, pa / P)), mpmath.asin(min(1, qb / Q)))
+            return max(mpmath.mpf(0), hi - lo)
+        corners = sorted({h * pa * pa + b3 * qa * qa, h * pb * pb + b3 * qa * qa, h * pa * pa + b3 * qb * qb,
+                          h * pb * pb + b3 * qb * qb})
+        lo, hi = corners[0], corners[-1]
+        inside = lo < E < hi
+        tE = theta(E) if inside else 0
+        re = mpmath.quad(lambda e: (theta(e) - tE) / (E - e), sorted(set(corners + ([E] if inside else []))))
+        if inside:
+            re += tE * mpmath.log((E - lo) / (hi - E))
+        c = 1 / (2 * mpmath.sqrt(h * b3))
+        return complex(c * re, -mpmath.pi * c * tE) / float((pb - pa) * (qb - qa))
+
+
+@pytest.mark.parametrize("E_lab", [3.0, 3.336, 3.34, 14.1, 28.1, 45.0])
+def test_continuum_elements_vs_energy_route(E_lab):
+    """Every continuum element of a small MT doublet lattice (both pair waves), below and above the
+    breakup threshold (E_lab = 3.337 MeV) and next to it, against the energy route to 1e-13."""
+    s = pipeline.build_system(pipeline.Spec(M=6, N=7, two_J=1, pot="mt"))
+    E = lattice.total_energy(E_lab, s.eps0)
+    for d in s.pair.values():
+        G = resolvent.channel_diagonal(s.q_edges, E, list(d["eps"][:d["nb"]]), d["bins"])
+        bins, nb = d["bins"], d["nb"]
+        for k in range(len(bins) - 1):
+            for j in range(len(s.q_edges) - 1):
+                ref = _energy_route_ref(bins[k], bins[k + 1], s.q_edges[j], s.q_edges[j + 1], E)
+                assert abs(G[nb + k, j] - ref) <= 1e-13 * abs(ref), (E_lab, k, j, G[nb + k, j], ref)
+
+
 def test_wynn_known_series():
     # alternating series for ln 2
     est, _ = solve.pade_sum([(-1) ** n / (n + 1) for n in range(24)])
