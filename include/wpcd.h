@@ -107,9 +107,26 @@ wp_status wp_lattice_pseudostates(const wp_lattice* lat, int channel, int* n_bou
 /*
  * Step-4 result: the diagonal of G1(E) (eqs. dg1a, dg1b) for one channel at E = eps0 + (2/3) E_lab,
  * G[2*(k*N + j) + {0,1}] = re/im of G_kj, k = pseudostate (bound states first), j = q bin;
- * G holds 2*M*N doubles. Host FP64 only (no device work).
+ * G holds 2*M*N doubles. Computed on the device by the solve's G1 kernels (FP64; device memory
+ * for the values of every channel and a work list is allocated per call), then copied to G.
  */
 wp_status wp_lattice_resolvent(const wp_lattice* lat, double E_lab, int channel, double* G);
+
+/*
+ * wp_lattice_resolvent without device allocation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, hosts that forbid hipMalloc after set-up).
+ * Same arguments and result as wp_lattice_resolvent (bit for bit: the same kernels). Its device
+ * scratch (G1 of every channel, the energy and the near-shell work list) is a fixed array of
+ * WP_NOALLOC_SCRATCH (16 MiB) per GPU, held until the process ends; a lattice needing more
+ * (about 16 M N (n_ch + 1) + 8 n_waves M N bytes; M = N = 150 with 18 channels needs 8.7 MB) is
+ * rejected with WP_EINVAL. The lattice's device
+ * tables must already be resident (after perm_matrix_build, faddeev_solve or
+ * wp_lattice_resolvent), else WP_ENOTREADY. Runs on the null stream and returns when G is
+ * written. Calls on one GPU share the scratch array: calls that overlap in time on the same GPU
+ * race, so callers must not overlap them.
+ */
+#define WP_NOALLOC_SCRATCH ((size_t)16 << 20)
+wp_status wp_lattice_resolvent_noalloc(const wp_lattice* lat, double E_lab, int channel, double* G);
 
 void wp_lattice_free(wp_lattice* lat);
 

@@ -79,6 +79,7 @@ _SIGS = {
     "wp_lattice_edges": (C.c_int, [_P, _D, _D]),
     "wp_lattice_pseudostates": (C.c_int, [_P, C.c_int, _I, _D, _D, _D]),
     "wp_lattice_resolvent": (C.c_int, [_P, C.c_double, C.c_int, _D]),
+    "wp_lattice_resolvent_noalloc": (C.c_int, [_P, C.c_double, C.c_int, _D]),
     "wp_lattice_free": (None, [_P]),
     "twobody_pseudostates": (C.c_int, [_P, C.POINTER(_PotDesc), _D, _D]),
     "perm_matrix_build": (C.c_int, [_P, C.c_int, _P, C.POINTER(_PermStats)]),
@@ -127,6 +128,7 @@ class TorchAllocator:
         self._torch = torch
         self.device = device
         self.live = {}
+        self.n_alloc = 0   # allocations served so far
         self._a = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)(self._alloc)
         self._r = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)(self._release)
         self.struct = _Alloc(self._a, self._r, None)
@@ -138,6 +140,7 @@ class TorchAllocator:
             return None
         p = t.data_ptr()
         self.live[p] = t
+        self.n_alloc += 1
         return p
 
     def _release(self, ptr, ctx):
@@ -304,6 +307,12 @@ class Lattice:
     def resolvent(self, E_lab, channel):
         G = np.zeros(2 * self.M * self.N)
         _check(_lib.wp_lattice_resolvent(self.h, E_lab, channel, _dptr(G)))
+        return (G[0::2] + 1j * G[1::2]).reshape(self.M, self.N)
+
+    def resolvent_noalloc(self, E_lab, channel):
+        """As resolvent(), through the entry point that allocates no device memory."""
+        G = np.zeros(2 * self.M * self.N)
+        _check(_lib.wp_lattice_resolvent_noalloc(self.h, E_lab, channel, _dptr(G)))
         return (G[0::2] + 1j * G[1::2]).reshape(self.M, self.N)
 
     def build_perm(self, precision="fp64", stream=None):

@@ -131,7 +131,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
   if (b->mixed) {
     MixedWork& w = b->mw;
-    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, w.dG64.p, b->g1w), st));
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, w.dG64.p, b->g1w.p), st));
     HIPCHECK(launch_cvt_d2f_cols(b->D, B, c0, c0 + nf, w.dG64.p, w.dG32.p, st));
     HIPCHECK(hipMemcpyAsync(w.dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0,
@@ -141,7 +141,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
     HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c0 + nf, st));
     S.mc.assign(nf, MixedCol());
   } else {
-    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, b->dG.p, b->g1w), st));
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, b->dG.p, b->g1w.p), st));
     HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
                                c0 + nf));

@@ -445,7 +445,7 @@ bool wpcd::g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w) {
 }
 
 G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G,
-                     DBuf<int64_t>& work) {
+                     int64_t* work) {
   G1Args g{};
   g.M = L->M;
   g.N = L->N;
@@ -472,8 +472,8 @@ G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, in
   g.gl16_w = L->d_gl_w.p + 20;
   g.h2m = L->h2m;
   g.G = G;
-  g.wl_n = reinterpret_cast<int*>(work.p);
-  g.wl = work.p ? work.p + 1 : nullptr;
+  g.wl_n = reinterpret_cast<int*>(work);
+  g.wl = work ? work + 1 : nullptr;
   return g;
 }
 
@@ -507,7 +507,7 @@ extern "C" wp_status wp_lattice_resolvent(const wp_lattice* Lc, double E_lab, in
     return fail(WP_ENOMEM, "device allocation (resolvent)");
   const double E = L->eps0 + 2.0 * E_lab / 3.0;
   HIPCHECK(hipMemcpy(dE.p, &E, 8, hipMemcpyHostToDevice));
-  WP_LAUNCH("g1", nullptr, launch_g1(g1_args(L, dE.p, 1, 1, 0, 1, dG.p, g1w), nullptr));
+  WP_LAUNCH("g1", nullptr, launch_g1(g1_args(L, dE.p, 1, 1, 0, 1, dG.p, g1w.p), nullptr));
   std::vector<double2> h(rows);
   HIPCHECK(hipMemcpy(h.data(), dG.p, rows * sizeof(double2), hipMemcpyDeviceToHost));
   for (int k = 0; k < L->M; ++k)
@@ -836,7 +836,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
       !grow(dfin, al, nfin) || !grow(dE, al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
-  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p, g1w), s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, dG.p, g1w.p), s));
   HIPCHECK(hipMemcpyAsync(dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));

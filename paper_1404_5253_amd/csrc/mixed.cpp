@@ -255,7 +255,7 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
   HIPCHECK(hipMemcpyAsync(w.dj0.p, j0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(dg0.p, g0.data(), B * sizeof(int), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(w.dfin.p, L->opens.data(), nfin * sizeof(int), hipMemcpyHostToDevice, s));
-  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, w.dG64.p, g1w), s));
+  WP_LAUNCH("g1", s, launch_g1(g1_args(L, dE.p, nE, nfin, 0, B, w.dG64.p, g1w.p), s));
   HIPCHECK(launch_cvt_d2f(DB, w.dG64.p, w.dG32.p, s));
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, dg0.p, w.ds64.p, s));
   WP_LAUNCH("spmv_f32v_f64x", s,

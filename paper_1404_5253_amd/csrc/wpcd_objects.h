@@ -164,9 +164,10 @@ wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_s
                       wp_solution* sol);
 // Device work list of the G1 kernels for nE energies (element list plus counter in slot 0).
 bool g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w);
-// G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns)
+// G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns); work: the
+// work list (counter in slot 0, then g1_work_elems entries)
 G1Args g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, int col0, int B, double2* G,
-               DBuf<int64_t>& work);
+               int64_t* work);
 
 // Kinematics of one energy: E, q0, on-shell bin j0 ((q_{j-1}, q_j] convention), its width.
 inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {

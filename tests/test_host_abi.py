@@ -74,3 +74,19 @@ def test_pseudostates_match_oracle(pot, two_J):
         assert np.allclose(np.abs(O), np.abs(d["O"]), atol=1e-10)      # eigenvector signs are free
         assert np.allclose(O @ O.T, np.eye(M), atol=1e-13)
         assert np.allclose(bins, d["bins"], rtol=1e-12)
+
+
+def test_noalloc_resolvent_host_checks():
+    """wp_lattice_resolvent_noalloc rejects, before any device work, a lattice whose scratch need
+    exceeds the fixed array (WP_EINVAL) and a lattice whose device tables are not resident yet
+    (WP_ENOTREADY)."""
+    L = wp.Lattice(12, 12, two_J=1, torch_alloc=False)
+    L.pseudostates(kind="mt", V_R=1438.72)
+    G = np.zeros(2 * 12 * 12)
+    st = wp._lib.wp_lattice_resolvent_noalloc(L.h, 14.1, 0, G.ctypes.data_as(C.POINTER(C.c_double)))
+    assert st == wp.WP_ENOTREADY and b"not resident" in wp._lib.wp_last_error()
+    big = wp.Lattice(600, 600, two_J=1, torch_alloc=False)
+    big.pseudostates(kind="mt", V_R=1438.72)
+    G = np.zeros(2 * 600 * 600)
+    st = wp._lib.wp_lattice_resolvent_noalloc(big.h, 14.1, 0, G.ctypes.data_as(C.POINTER(C.c_double)))
+    assert st == wp.WP_EINVAL and b"scratch" in wp._lib.wp_last_error()
