@@ -1,19 +1,25 @@
 """Benchmark of the WPCD hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 
-Workload (the s-wave Malfliet-Tjon lattice pair, M = N = 100): the doublet (J = 1/2+, 1S0 + 3S1,
-D = 20000) and quartet (J = 3/2+, D = 10000) systems with V_R drawn from seed 0, V_A tuned to
-the deuteron, 8 x 8 (x, phi) nodes per cell pair, E_lab = 14.1 MeV. Inputs (lattice tables,
-pseudostates) are resident before timing.
+Headline workload (the 18-channel lattice, `pw_mt_150`): J = 1/2+ nd channels with pair waves
+j <= 2 (18 channels, 10 pair waves), Malfliet-Tjon form in every pair wave (V_R drawn from seed 0,
+V_A tuned to the deuteron, singlet 0.82 V_A), M = N = 150 tangent-mapped bins up to 10 fm^-1,
+8 x 8 (x, phi) nodes per cell pair, E_lab = 3 MeV (below breakup) and 22.7 MeV (above).
+Lattice tables and pseudostates are resident before timing.
 
-One step = the whole hot path for both systems: P0 build (selection, quadrature, compaction;
-FP64) and one FP64 solve at 14.1 MeV (G1, Neumann iteration, Pade). The JSON line reports
-  value        P-elements/s of the P0 build phase (stored channel entries / wall time of the
-               synchronised build calls inside the timed region);
-  ms_per_step  wall time per step (build + solves);
-plus solves/s, the roofline of the dominant kernel (HIP events around every launch, inside the
-timed region) and the oracle timed on the host (cpu_baseline).
+One step = the whole hot path on that lattice: the P0 build (selection, quadrature, compaction;
+FP64 arithmetic, FP32 storage) and one mixed-precision solve of both energies in one call (G1 in
+FP64, FP32 P0, BF16 v1/O blocks on MFMA with FP32 accumulation as hi + lo pairs, FP64 residual
+refinement; 2 energies x 2 open channels = 4 solves). The JSON line reports
+  value        P-elements/s of the build (stored channel entries / wall time of the synchronised
+               build call inside the timed region);
+  ms_per_step  wall time per step (build + solve);
+plus solves/s, the largest amplitude error against the oracle's values of the same lattice
+(tests/golden/pw_mt_150.json), the roofline of the dominant kernel (HIP events around every
+launch, inside the timed region) and the oracle timed on the host cores (cpu_baseline, run first,
+before the GPU is touched). Extras: the s-wave M = N = 100 lattice pair, 64 batched energies,
+the continuous-batching service, and (--sweep) the s-wave build for M = N = 40..400.
 """
 from __future__ import annotations
 
@@ -30,7 +36,7 @@ import numpy as np  # noqa: E402
 
 import workloads  # noqa: E402
 
-WORKLOAD = "swave_mt_100"
+WORKLOAD = "pw_mt_150"
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # FP64 VALU lane-ops/s (one op per lane per clock)
 FP64_PEAK_TFLOPS = 78.6
@@ -38,6 +44,7 @@ FP64_PEAK_TFLOPS = 78.6
 # Algorithmic work per unit (measurement section)
 PBUILD_OPS_PER_NODE = 14          # FP64 VALU ops per (cell pair, quadrature node)
 AMP_TARGET = 1e-6                 # amplitude error at which the solve paths are compared
+HEADLINE_MODE, HEADLINE_TOL = "mixed_split", 1e-8   # the headline solve: split-BF16 mixed path
 
 
 def measured_traffic(workload, kernel):
@@ -64,10 +71,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched-energy and serving measurements")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-extras", action="store_true", help="skip the s-wave, batched and serving sections")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured length of the serving stream")
+    ap.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up length of the serving stream")
     ap.add_argument("--sweep", action="store_true", help="also time the s-wave P0 build for M = N in 40..400")
-    ap.add_argument("--only", choices=["batched", "serving", "pw150"], default=None,
+    ap.add_argument("--only", choices=["batched", "serving", "swave", "sweep"], default=None,
                     help="run only this extra section (no headline step); for profiling runs")
     return ap.parse_args()
 
@@ -122,11 +130,12 @@ SERVING_MODES = (("fp64", dict(tol=3e-7, accept=1e-7, refine_every=0)),
                  ("mixed_split", dict(tol=1e-5, accept=1e-5, refine_every=8)))
 
 
-def serving_section(wp, torch, V_R, seconds, lats_by_key=None):
-    """Poisson stream (200 req/s, seed 2026) over four resident lattices, continuous batching, once
-    with FP64 batches and once with split-BF16 mixed batches, each at a stop tolerance that keeps
-    the amplitude error below 1e-6; afterwards every served amplitude is compared with a converged
-    FP64 solve of the same energy (outside the timing)."""
+def serving_section(wp, torch, V_R, seconds, warmup, lats_by_key=None, n_check=200):
+    """Poisson stream (200 req/s, seed 2026; `warmup` s served but not counted, then `seconds` s
+    measured) over four resident lattices, continuous batching, once with FP64 batches and once
+    with split-BF16 mixed batches, each at a stop tolerance that keeps the amplitude error below
+    1e-6; afterwards a seeded sample of n_check served amplitudes per mode is compared with a
+    converged FP64 solve of the same energy (outside the timing). Every request must be served."""
     from paper_1404_5253_amd.serve import BatchBackend, run_stream
     lats = []
     for (M, two_J, j_max, sw) in SERVING_LATTICES:
@@ -136,101 +145,56 @@ def serving_section(wp, torch, V_R, seconds, lats_by_key=None):
             L.pseudostates(kind="mt", V_R=V_R)
             L.build_perm("fp64")
         lats.append(L)
-    reqs = workloads.serving_requests(len(lats), rate=200.0, duration=seconds)
+    reqs = workloads.serving_requests(len(lats), rate=200.0, duration=warmup + seconds)
     # saturation: the same kind of stream at 10x the rate, so that solves/s is the service rate
-    sat = workloads.serving_requests(len(lats), rate=2000.0, duration=0.25, seed=7)
+    sat = workloads.serving_requests(len(lats), rate=2000.0, duration=1.0, seed=7)
     out = {"lattices": [f"M=N={M}, {L.nch} ch" for (M, *_), L in zip(SERVING_LATTICES, lats)], "requests": len(reqs),
-           "saturation_requests": len(sat)}
+           "warmup_s": warmup, "measured_s": seconds, "saturation_requests": len(sat),
+           "P0_bytes": [L.perm_stats["bytes"] for L in lats]}
     served = {}
+
+    def backends(mode, kw):
+        out_ = []
+        for L in lats:
+            st = torch.cuda.Stream()
+            b = BatchBackend(L, slots=32, hbm_budget=16 << 30, terms=8, stream=wp.C.c_void_p(st.cuda_stream),
+                             mode=mode, max_iter=400, **kw)
+            b._torch_stream = st
+            out_.append(b)
+        return out_
+
     for mode, kw in SERVING_MODES:
-        backs = []
-        for L in lats:
-            st = torch.cuda.Stream()
-            b = BatchBackend(L, slots=32, hbm_budget=16 << 30, terms=8, stream=wp.C.c_void_p(st.cuda_stream),
-                             mode=mode, max_iter=400, **kw)
-            b._torch_stream = st
-            backs.append(b)
-        _, sstats = run_stream(backs, sat)
+        backs = backends(mode, kw)
+        done, sstats = run_stream(backs, sat)
         for b in backs:
             b.close()
+        assert sstats["n_served"] == len(sat), (mode, sstats["n_served"], len(sat))
         out[f"saturated_{mode}"] = {k: sstats[k] for k in ("n", "p50_ms", "p99_ms", "solves_per_s", "wall_s")}
-        backs = []
-        for L in lats:
-            st = torch.cuda.Stream()
-            b = BatchBackend(L, slots=32, hbm_budget=16 << 30, terms=8, stream=wp.C.c_void_p(st.cuda_stream),
-                             mode=mode, max_iter=400, **kw)
-            b._torch_stream = st
-            backs.append(b)
-        done, stats = run_stream(backs, reqs)
+        backs = backends(mode, kw)
+        done, stats = run_stream(backs, reqs, measure_from=warmup)
         for b in backs:
             b.close()
+        assert stats["n_served"] == len(reqs), (mode, stats["n_served"], len(reqs))
         stats["accepted"] = sum(1 for r in done if r.result.get("accepted", True))
         out[mode] = stats
         served[mode] = {r.rid: (r.lattice, r.E_lab, r.result["A"]) for r in done}
-    # accuracy of every served amplitude against a converged FP64 solve (batched per lattice)
+    # accuracy of a seeded sample of served amplitudes against converged FP64 solves
     for mode in served:
+        rids = sorted(served[mode])
+        pick = set(np.random.default_rng(3).choice(rids, min(n_check, len(rids)), replace=False).tolist())
         worst = 0.0
         for li, L in enumerate(lats):
-            items = [(rid, E, A) for rid, (l, E, A) in served[mode].items() if l == li]
+            items = [(E, A) for rid, (l, E, A) in served[mode].items() if l == li and rid in pick]
             for k0 in range(0, len(items), 64):
                 chunk = items[k0:k0 + 64]
-                ref = L.solve([E for _, E, _ in chunk], "fp64", tol=1e-12, max_iter=400, allow_noconv=True)
-                for k, (_, _, A) in enumerate(chunk):
+                ref = L.solve([E for E, _ in chunk], "fp64", tol=1e-12, max_iter=400, accept=1e-6)
+                for k, (_, A) in enumerate(chunk):
                     worst = max(worst, float(np.max(np.abs(A - ref.amplitude(k)["A"]))))
         out[mode]["max_abs_dA_vs_converged_fp64"] = worst
+        out[mode]["checked"] = len(pick)
     out["speedup_mixed_split_over_fp64_solves_per_s"] = out["mixed_split"]["solves_per_s"] / out["fp64"]["solves_per_s"]
     out["speedup_mixed_split_over_fp64_saturated"] = (out["saturated_mixed_split"]["solves_per_s"]
                                                       / out["saturated_fp64"]["solves_per_s"])
-    return out
-
-
-def pw150_section(wp, torch, V_R, reps=3):
-    """18-channel J = 1/2+ lattice (j <= 2), M = N = 150: P0 build rate, the FP64 SpMV against the
-    HBM roofline, and the FP64 and mixed solves of E_lab = 3 and 22.7 MeV (one call each)."""
-    wl = workloads.WORKLOADS["pw_mt_150"]
-    sysd = wl["systems"][0]
-    M = wl["M"]
-    L = wp.Lattice(M, M, two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"], n_x=wl["n_x"],
-                   n_phi=wl["n_phi"])
-    L.pseudostates(kind="mt", V_R=V_R)
-    L.build_perm("fp64")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        st = L.build_perm("fp64")
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    out = dict(channels=L.nch, P_elements=st["nnz"], P_blocks=st["blocks"], P_bytes=st["bytes"],
-               build_ms=dt * 1e3, build_device_ms=st["device_ms"], P_elements_per_s=st["nnz"] / dt)
-    Es = wl["E_lab"]
-    amps = {}
-    for mode, tol in (("fp64", 1e-10), ("mixed", 1e-8), ("mixed_split", 1e-8)):
-        L.solve(Es, mode, tol=tol, max_iter=400, allow_noconv=True)
-        torch.cuda.synchronize()
-        wp.wp_profile_reset()
-        wp.wp_profile_enable(True)
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            sol = L.solve(Es, mode, tol=tol, max_iter=400, allow_noconv=True)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        wp.wp_profile_enable(False)
-        prof = wp.wp_profile_read()
-        amps[mode] = np.array([sol.amplitude(k)["A"] for k in range(len(Es))])
-        out[f"ms_per_call_{mode}"] = dt * 1e3
-        out[f"solves_per_s_{mode}"] = len(Es) / dt
-        out[f"kernels_ms_per_call_{mode}"] = {k: round(v[1] / reps, 3) for k, v in prof.items()}
-        if mode == "fp64":
-            n, ms = prof["spmv64"]
-            us = ms / n * 1e3
-            byts = st["bytes"] + 2 * 16 * M * M * L.nch * len(Es) * 2
-            out["spmv64_roofline"] = dict(bound="hbm", achieved=byts / us / 1e3, peak=HBM_PEAK_GBS, unit="GB/s",
-                                          frac=byts / us / 1e3 / HBM_PEAK_GBS, avg_us=us, bytes_per_launch=byts)
-    for mode in ("mixed", "mixed_split"):
-        out[f"max_abs_dA_{mode}_vs_fp64"] = float(np.max(np.abs(amps[mode] - amps["fp64"])))
-        out[f"speedup_{mode}_over_fp64"] = out[f"solves_per_s_{mode}"] / out["solves_per_s_fp64"]
-    S = L.solve([Es[0]], "fp64", tol=1e-10, max_iter=400).amplitude(0)["S"]
-    out["unitarity_defect_3MeV"] = float(np.max(np.abs(S @ S.conj().T - np.eye(len(S)))))
     return out
 
 
@@ -262,48 +226,11 @@ def sweep_section(wp, torch, V_R, sizes=(40, 100, 200, 400), reps=3):
     return out
 
 
-def cpu_baseline(V_R, M, N, budget_s=25.0):
-    """The oracle as it stands, on a bounded sample: the doublet P0 over a subset of q-boxes
-    (rows j < n_rows) and one oracle solve of a smaller lattice; scaled to P-elements/s."""
-    from oracle import channels, recoupling
-    from oracle.perm import P0Lattice, box_nodes, candidate_pairs, F_values, moment_weight
-    import oracle.lattice as olat
-    pe = olat.tangent_edges(M)
-    qe = olat.tangent_edges(N)
-    ch = channels.swave_doublet()
-    t0 = time.perf_counter()
-    n_el = 0
-    boxes = 0
-    dp, dq = np.diff(pe), np.diff(qe)
-    key = (0, 0, 0, 0, 0)
-    for j in range(N):
-        for jp in range(N):
-            nodes = box_nodes(qe, j, jp, 8, 8)
-            ii, iip = candidate_pairs(pe, nodes)
-            if len(ii):
-                F = F_values(pe, nodes, ii, iip)
-                mom = F @ moment_weight(nodes, key) / np.sqrt(dp[ii] * dq[j] * dp[iip] * dq[jp])
-                n_el += int(np.count_nonzero(mom)) * len(ch) ** 2
-            boxes += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=n_el / dt, unit="P-elements/s", cores=1, kind="oracle",
-                sample=f"oracle P0 rule (numpy, 1 thread) for the doublet lattice M=N={M}: {boxes} of {N * N} "
-                       f"q-boxes ({n_el} stored elements) in {dt:.1f} s")
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    import torch
-    import paper_1404_5253_amd as wp
-
-    torch.cuda.set_device(0)
-    wl = workloads.WORKLOADS[WORKLOAD]
-    V_R = workloads.mt_repulsion(wl["V_R_seed"])
+def swave_section(wp, torch, V_R, reps=10):
+    """The s-wave Malfliet-Tjon lattice pair at M = N = 100 (doublet J = 1/2+, 2 channels, and
+    quartet J = 3/2+, 1 channel; V_R seed 0): P0 build in FP64 and one FP64 solve at 14.1 MeV each,
+    per step."""
+    wl = workloads.WORKLOADS["swave_mt_100"]
     M, N = wl["M"], wl["N"]
     E = wl["E_lab"][0]
     lats = []
@@ -312,34 +239,243 @@ def main():
                        n_x=wl["n_x"], n_phi=wl["n_phi"])
         L.pseudostates(kind="mt", V_R=V_R)
         lats.append(L)
-    if args.only:
-        if args.only == "pw150":
-            res = pw150_section(wp, torch, V_R)
-        else:
-            for L in lats:
-                L.build_perm("fp64")
-            res = (batched_energies_section(wp, torch, lats[0]) if args.only == "batched"
-                   else serving_section(wp, torch, V_R, args.serve_seconds, {(M, 1, 1, True): lats[0]}))
-        print(json.dumps({"section": args.only, "result": res}))
-        return
+    times = dict(build=0.0, solve=0.0)
 
-    def step(times):
+    def step(acc):
         for L in lats:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             L.build_perm("fp64")
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            sol = L.solve([E], "fp64")
+            L.solve([E], "fp64")
             torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            times["build"] += t1 - t0
-            times["solve"] += t2 - t1
-            times["amps"].append(sol.amplitude(0)["A"][0, 0])
+            acc["build"] += t1 - t0
+            acc["solve"] += time.perf_counter() - t1
+
+    step(dict(build=0.0, solve=0.0))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step(times)
+    dt = (time.perf_counter() - t0) / reps
+    wp.wp_profile_reset()
+    wp.wp_profile_enable(True)
+    step(dict(build=0.0, solve=0.0))
+    torch.cuda.synchronize()
+    wp.wp_profile_enable(False)
+    prof = wp.wp_profile_read()
+    elems = sum(L.perm_stats["nnz"] for L in lats)
+    return dict(M=M, N=N, E_lab=E, systems=["doublet J=1/2+ (2 ch)", "quartet J=3/2+ (1 ch)"],
+                P_elements=elems, P_elements_per_s=elems * reps / times["build"], ms_per_step=dt * 1e3,
+                build_ms_per_step=times["build"] / reps * 1e3, solve_ms_per_step=times["solve"] / reps * 1e3,
+                solves_per_s_fp64=2 * reps / times["solve"],
+                kernels_ms_per_step={k: round(v[1], 4) for k, v in prof.items()}), lats
+
+
+# ---------------------------------------------------------------- oracle timed on the host
+
+def _oracle_p0_rows(task):
+    """Worker: the oracle's P0 rule for every q-box (j, j') of the rows j given, contracted with the
+    coefficient table; returns (stored entries, stored blocks) of those rows."""
+    from threadpoolctl import threadpool_limits
+    from oracle.perm import box_nodes, candidate_pairs, F_values, moment_weight
+    rows, pe, qe, keys, C, n_x, n_phi = task
+    with threadpool_limits(1):   # one process per core
+        return _oracle_p0_rows_1(rows, pe, qe, keys, C, n_x, n_phi)
+
+
+def _oracle_p0_rows_1(rows, pe, qe, keys, C, n_x, n_phi):
+    from oracle.perm import box_nodes, candidate_pairs, F_values, moment_weight
+    dp, dq = np.diff(pe), np.diff(qe)
+    entries = blocks = 0
+    for j in rows:
+        for jp in range(len(qe) - 1):
+            nodes = box_nodes(qe, j, jp, n_x, n_phi)
+            ii, iip = candidate_pairs(pe, nodes)
+            if not len(ii):
+                continue
+            F = F_values(pe, nodes, ii, iip)
+            Wm = np.stack([moment_weight(nodes, key) for key in keys], axis=1)
+            mom = (F @ Wm) / np.sqrt(dp[ii] * dq[j] * dp[iip] * dq[jp])[:, None]
+            mom = mom[np.any(mom != 0.0, axis=1)]
+            vals = np.einsum("abm,nm->nab", C, mom)
+            entries += int(np.count_nonzero(vals))
+            blocks += len(mom)
+    return entries, blocks
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle as it stands on the host cores, on bounded samples of the headline workload:
+    P0 rows (q bins j in a fixed shuffled order, one process per core, until budget_s of wall time
+    has passed or every row is done), a sample of G1 elements, and per-stage times. Runs before the
+    GPU is touched (the worker processes are forked)."""
+    import multiprocessing as mp
+    import platform
+    from oracle import lattice as olat, pipeline, potential, pseudostates, recoupling, resolvent
+    from oracle.perm import channel_terms
+    wl = workloads.WORKLOADS[WORKLOAD]
+    sysd = wl["systems"][0]
+    V_R = workloads.mt_repulsion(wl["V_R_seed"])
+    M, N = wl["M"], wl["N"]
+    spec = pipeline.Spec(M=M, N=N, two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"], pot="mt",
+                         V_R=V_R, n_x=wl["n_x"], n_phi=wl["n_phi"])
+    stages = {}
+    t0 = time.perf_counter()
+    pe, qe = olat.tangent_edges(M), olat.tangent_edges(N)
+    chans = pipeline.channel_list(spec)
+    gt = {(a, b): recoupling.g_table(chans[a], chans[b], spec.two_J) for a in range(len(chans))
+          for b in range(len(chans))}
+    keys, C = channel_terms(chans, gt)
+    stages["lattice_channels_coefficients_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    strength = potential.tune_mt(pe, V_R, spec.mu_R, spec.mu_A, spec.target_BE)
+    waves = {}
+    for c in chans:
+        if (c[0], c[1]) not in waves:
+            v = pipeline.pair_potential(spec, pe, c[0], c[1], strength)
+            eps, O = pseudostates.diagonalize(pe, v)
+            nb = int(np.sum(eps < 0))
+            waves[(c[0], c[1])] = (eps, nb, pseudostates.scattering_bins(eps[nb:]))
+    stages["pseudostates_s"] = time.perf_counter() - t0
+    eps0 = float(waves[(0, 1)][0][0])
+    # P0: rows in a fixed shuffled order, all cores
+    cores = max(1, min(16, os.cpu_count() or 1))
+    order = list(np.random.default_rng(0).permutation(N))
+    ctx = mp.get_context("fork")
+    entries = blocks = done = 0
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        while done < N and time.perf_counter() - t0 < budget_s:
+            batch = order[done:done + cores]
+            tasks = [([j], pe, qe, keys, C, spec.n_x, spec.n_phi) for j in batch]
+            for e, b in pool.map(_oracle_p0_rows, tasks):
+                entries += e
+                blocks += b
+            done += len(batch)
+    t_p0 = time.perf_counter() - t0
+    stages["P0_rows_sampled"] = done
+    stages["P0_sample_s"] = t_p0
+    stages["P0_full_lattice_estimate_s"] = t_p0 * N / done
+    # G1: a seeded sample of continuum elements of every pair wave at 22.7 MeV, one core
+    E = olat.total_energy(wl["E_lab"][1], eps0)
+    rng = np.random.default_rng(1)
+    t0 = time.perf_counter()
+    n_el = 0
+    for key, (eps, nb, bins) in waves.items():
+        for _ in range(20):
+            k, j = int(rng.integers(0, len(bins) - 1)), int(rng.integers(0, N))
+            resolvent.continuum_element(bins[k], bins[k + 1], qe[j], qe[j + 1], E)
+            n_el += 1
+    t_g1 = time.perf_counter() - t0
+    stages["G1_elements_per_s_1core"] = n_el / t_g1
+    stages["G1_one_energy_estimate_s_1core"] = len(waves) * M * N / (n_el / t_g1)
+    # a whole oracle solve where it finishes in seconds: the quartet Yamaguchi lattice M = N = 40
+    t0 = time.perf_counter()
+    s1 = pipeline.build_system(pipeline.Spec(M=40, N=40, two_J=3, pot="yamaguchi"))
+    t1 = time.perf_counter()
+    pipeline.solve_energy(s1, 10.0)
+    t2 = time.perf_counter()
+    stages["oracle_quartet_40"] = dict(build_s=t1 - t0, solve_s=t2 - t1, solves_per_s=1.0 / (t2 - t1))
+    try:
+        model = next((ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")),
+                     platform.processor())
+    except OSError:
+        model = platform.processor()
+    return dict(value=entries / t_p0, unit="P-elements/s", cores=cores, kind="oracle",
+                sample=f"oracle P0 rule (numpy) for the 18-channel lattice M=N={M}: {done} of {N} q-bin rows "
+                       f"({blocks} blocks, {entries} stored entries) in {t_p0:.1f} s on {cores} processes; "
+                       f"host {model}, os.cpu_count()={os.cpu_count()}, "
+                       f"OPENBLAS_NUM_THREADS={os.environ.get('OPENBLAS_NUM_THREADS', 'unset')}",
+                stages=stages)
+
+
+def roofline(label, avg_s, L, B, nodes):
+    """Algorithmic work of one launch of the kernel behind `label` over its average duration,
+    against the peak of the resource that bounds it (the per-unit figures are in the design doc)."""
+    st = L.perm_stats
+    M, N, nch = L.M, L.N, L.nch
+    R = M * N
+    D = R * nch
+    idx = st["blocks"] * 4 + (R + 1) * 8          # block column indices and row pointer
+    if label in ("spmv_f32", "spmm_arnoldi"):      # FP32 P0, complex FP32 vectors in and out
+        byts = st["nnz"] * 4 + idx + 2 * D * B * 8
+    elif label == "spmv_f32v_f64x":                # FP32 P0, complex FP64 vectors
+        byts = st["nnz"] * 4 + idx + 2 * D * B * 16
+    elif label == "spmv64":                        # FP64 P0, complex FP64 vectors
+        byts = st["nnz"] * 8 + idx + 2 * D * B * 16
+    else:
+        byts = None
+    if byts is not None:
+        return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                    bytes_per_launch=byts)
+    if label == "step64":                          # two complex-by-real M x M products per column
+        flops = 8.0 * M * M * N * nch * B
+        return dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    flops_per_launch=flops)
+    if label in ("pbuild", "pbuild_mom"):          # FP64 VALU ops over the candidates' nodes
+        nmom = getattr(L, "nmom", None)
+        ops = st["candidates"] * nodes * (PBUILD_OPS_PER_NODE + 2 * (nmom or 1))
+        return dict(bound="alu", achieved=ops / avg_s / 1e12, peak=FP64_VALU_PEAK_TOPS, unit="Tops/s",
+                    ops_per_launch=ops)
+    if label == "combine":                         # candidate values written once (FP64)
+        byts = st["candidates"] * (nch * nch * 8 + 1)
+        return dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                    bytes_per_launch=byts)
+    return dict(bound="alu", achieved=None, peak=None, unit=None)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    # the oracle first, in forked worker processes, before anything touches the GPU
+    cpu = None if (args.no_cpu_baseline or args.only) else cpu_baseline()
+    import torch
+    import paper_1404_5253_amd as wp
+
+    torch.cuda.set_device(0)
+    V_R = workloads.mt_repulsion(0)
+    if args.only:
+        if args.only == "swave":
+            res, _ = swave_section(wp, torch, V_R)
+        elif args.only == "sweep":
+            res = sweep_section(wp, torch, V_R)
+        else:
+            L = wp.Lattice(100, 100, two_J=1)
+            L.pseudostates(kind="mt", V_R=V_R)
+            L.build_perm("fp64")
+            res = (batched_energies_section(wp, torch, L) if args.only == "batched"
+                   else serving_section(wp, torch, V_R, args.serve_seconds, args.serve_warmup,
+                                        {(100, 1, 1, True): L}))
+        print(json.dumps({"section": args.only, "result": res}))
+        return
+
+    wl = workloads.WORKLOADS[WORKLOAD]
+    sysd = wl["systems"][0]
+    M, N = wl["M"], wl["N"]
+    Es = list(wl["E_lab"])
+    nodes = wl["n_x"] * wl["n_phi"]
+    L = wp.Lattice(M, N, two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"], n_x=wl["n_x"],
+                   n_phi=wl["n_phi"])
+    L.pseudostates(kind="mt", V_R=V_R)
+    B = len(Es) * 2                               # columns: energies x open channels
+
+    def step(acc):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.build_perm("fp32")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol = L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL)
+        torch.cuda.synchronize()
+        acc["build"] += t1 - t0
+        acc["solve"] += time.perf_counter() - t1
+        acc["sol"] = sol
 
     for _ in range(args.warmup):
-        step(dict(build=0.0, solve=0.0, amps=[]))
-    times = dict(build=0.0, solve=0.0, amps=[])
+        step(dict(build=0.0, solve=0.0))
+    times = dict(build=0.0, solve=0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -351,40 +487,30 @@ def main():
     wp.wp_profile_reset()
     wp.wp_profile_enable(True)
     for _ in range(args.steps):
-        step(dict(build=0.0, solve=0.0, amps=[]))
+        step(dict(build=0.0, solve=0.0))
     torch.cuda.synchronize()
     wp.wp_profile_enable(False)
     prof = wp.wp_profile_read()
     K = args.steps
-    elems = sum(L.perm_stats["nnz"] for L in lats)
-    cand = sum(L.perm_stats["candidates"] for L in lats)
-    blocks = sum(L.perm_stats["blocks"] for L in lats)
+    st = L.perm_stats
     ms_per_step = (t1 - t0) / K * 1e3
-    value = elems * K / times["build"]
-
-    # dominant kernel by total event time inside the timed region
+    value = st["nnz"] * K / times["build"]
+    # amplitudes against the oracle's values of the same lattice
+    with open(os.path.join(ROOT, "tests", "golden", "pw_mt_150.json")) as f:
+        gold = json.load(f)
+    dA = 0.0
+    for k, E in enumerate(Es):
+        g = gold["results"][str(E)]
+        Ar = np.array(g["A_re"]) + 1j * np.array(g["A_im"])
+        dA = max(dA, float(np.max(np.abs(times["sol"].amplitude(k)["A"] - Ar))))
     dom = max(prof, key=lambda k: prof[k][1])
     n_launch, tot_ms = prof[dom]
     avg_s = tot_ms / n_launch / 1e3
-    nodes = wl["n_x"] * wl["n_phi"]
-    if dom == "pbuild":
-        work = cand / len(lats) * nodes * PBUILD_OPS_PER_NODE   # per launch (average over systems)
-        roof = dict(bound="alu", achieved=work / avg_s / 1e12, peak=FP64_VALU_PEAK_TOPS, unit="Tops/s")
-    elif dom == "select":
-        work = N * N * nodes * M * 12 / 1.0
-        roof = dict(bound="alu", achieved=work / avg_s / 1e12, peak=FP64_VALU_PEAK_TOPS, unit="Tops/s")
-    elif dom == "step64":
-        # two complex-by-real M x M products per column (j, channel): 2 x 4 M^2 flops
-        flops = np.mean([8.0 * M * M * N * L.nch for L in lats])
-        roof = dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
-    elif dom == "g1":
-        roof = dict(bound="alu", achieved=None, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s")
-    else:   # spmv64: block values + column index + row pointer + vector in/out
-        byts = np.mean([L.perm_stats["bytes"] + 2 * 16 * M * N * L.nch for L in lats])
-        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] is not None else None
+    roof = roofline(dom, avg_s, L, B, nodes)
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") is not None else None
     roof["kernel"] = dom
     roof["avg_us"] = avg_s * 1e6
+    roof["launches_per_step"] = n_launch / K
     roof["traffic"] = measured_traffic(WORKLOAD, dom)
     out = {
         "metric": "P-elements/s; nd solves/s + p50/p99 latency vs FP64 path at 1e-6 amp error",
@@ -399,24 +525,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "M": M, "N": N, "systems": ["doublet J=1/2+ (2 ch)", "quartet J=3/2+ (1 ch)"],
-                   "potential": f"MT V_R={V_R:.3f} (seed 0), V_A tuned", "E_lab": E, "nodes_per_pair": nodes,
-                   "P_elements_per_step": elems, "P_blocks_per_step": blocks, "candidates_per_step": cand},
-        "solves_per_s_fp64": 2 * K / times["solve"],
+        "config": {"workload": WORKLOAD, "M": M, "N": N, "channels": L.nch, "J": "1/2+", "j_max": sysd["j_max"],
+                   "potential": f"MT V_R={V_R:.3f} (seed 0), V_A tuned", "E_lab": Es, "nodes_per_pair": nodes,
+                   "P0_storage": "f32 (computed in f64)",
+                   "solve": f"{HEADLINE_MODE} (bf16 hi+lo MFMA, fp32 P0 and vectors, fp64 G1 and refinement), "
+                            f"tol {HEADLINE_TOL}",
+                   "P_elements_per_step": st["nnz"], "P_blocks_per_step": st["blocks"],
+                   "candidates_per_step": st["candidates"], "P0_bytes": st["bytes"]},
+        "solves_per_s": B * K / times["solve"],
         "build_ms_per_step": times["build"] / K * 1e3,
         "solve_ms_per_step": times["solve"] / K * 1e3,
-        "amplitudes": [f"{a.real:.12f}{a.imag:+.12f}j" for a in times["amps"][:2]],
+        "max_abs_dA_vs_oracle": dA,
         "kernels_ms_per_step": {k: round(v[1] / K, 4) for k, v in prof.items()},
+        "launches_per_step": {k: v[0] // K for k, v in prof.items()},
         "roofline": roof,
     }
     if not args.no_extras:
-        out["batched_64_energies"] = batched_energies_section(wp, torch, lats[0])
-        out["serving"] = serving_section(wp, torch, V_R, args.serve_seconds, {(M, 1, 1, True): lats[0]})
-        out["pw_mt_150"] = pw150_section(wp, torch, V_R)
+        sw, sw_lats = swave_section(wp, torch, V_R)
+        out["swave_mt_100"] = sw
+        out["batched_64_energies"] = batched_energies_section(wp, torch, sw_lats[0])
+        out["serving"] = serving_section(wp, torch, V_R, args.serve_seconds, args.serve_warmup,
+                                         {(100, 1, 1, True): sw_lats[0]})
     if args.sweep:
         out["swave_sweep"] = sweep_section(wp, torch, V_R)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(V_R, M, N)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

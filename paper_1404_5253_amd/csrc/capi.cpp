@@ -687,8 +687,8 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
       for (int gg = 0; gg < nc2; ++gg)
         for (int m = 0; m < nm; ++m) ct[(size_t)m * nc2 + gg] = L->C[(size_t)gg * nm + m];
       HIPCHECK(hipMemcpyAsync(Ct, ct.data(), ct.size() * 8, hipMemcpyHostToDevice, s));
-      WP_LAUNCH("pbuild_general", s, launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c,
-                                                           mom, nrm, val_c, flag, s));
+      // profiled inside, per kernel (pbuild_mom, combine)
+      HIPCHECK(launch_pbuild_general(a, Ct, cnt, lo, segoff, rowptr_c, ncand, col_c, mom, nrm, val_c, flag, s));
     } else if (ncand > 0) {
       WP_LAUNCH("pbuild", s, pbuild());
     }

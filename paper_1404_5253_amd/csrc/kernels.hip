@@ -2006,11 +2006,17 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
   const size_t sh1 = (size_t)nn * (4 + MCH) * sizeof(double) + (size_t)PHI_STRIDE * a.n_phi * sizeof(double) +
                      (a.M + 1) * sizeof(double) + (2 * a.M + 1) * sizeof(int);
   if (sh1 > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pbuild_mom, dim3(a.N * a.N), dim3(256), sh1, s, a, cnt, lo, segoff, rowptr_c, col_c, mom, norm);
   const size_t sh2 = (size_t)NBT * a.nmom * sizeof(double);
   if (sh2 > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_combine, dim3((unsigned)((ncand + NBT - 1) / NBT)), dim3(256), sh2, s, ncand, a.nmom,
-                     a.nch * a.nch, Ct, mom, norm, val_c, flag);
+  {
+    ProfScope ps("pbuild_mom", s);
+    hipLaunchKernelGGL(k_pbuild_mom, dim3(a.N * a.N), dim3(256), sh1, s, a, cnt, lo, segoff, rowptr_c, col_c, mom, norm);
+  }
+  {
+    ProfScope ps("combine", s);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((ncand + NBT - 1) / NBT)), dim3(256), sh2, s, ncand, a.nmom,
+                       a.nch * a.nch, Ct, mom, norm, val_c, flag);
+  }
   return hipGetLastError();
 }
 

@@ -541,6 +541,7 @@ hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2*
     return hipErrorInvalidValue;
   const int64_t rows = a.cells * a.nch;
   if (a.B >= 16 && a.nch <= 4) {
+    ProfScope ps("spmm_arnoldi", s);
     const dim3 grid = arn_grid(a.cells, a.B, a.nblk);
     switch (a.nch) {
       case 1: spmm_arn_launch<1>(grid, s, a.cells, a.B, a.rowptr, a.col, a.val, a.order, t, a.V, a.vstride, a.j, a.scl, a.part); break;
@@ -553,8 +554,12 @@ hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2*
                        a.H + (size_t)a.j * (a.m + 1) * a.B, nullptr, 0);
   } else {
     if (!kv_scratch) return hipErrorInvalidValue;
-    hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s, 0, -1, a.order);
-    if (e != hipSuccess) return e;
+    {
+      ProfScope ps("spmv_f32", s);
+      hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s, 0, -1, a.order);
+      if (e != hipSuccess) return e;
+    }
+    ProfScope ps("arnoldi_dots", s);
     const dim3 grid = arn_grid(rows, a.B, a.nblk);
     hipLaunchKernelGGL(k_sub_dots, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl, a.part);
     hipLaunchKernelGGL(k_arn_finish, dim3(((a.j + 1) * a.B + 3) / 4), dim3(256), 0, s, (int)grid.x, a.B, a.j + 1,

@@ -163,7 +163,7 @@ wp_status wpcd::mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const s
     aa.j = j;
     rm.yscale = w.scl.p + (size_t)j * B;
     WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, w.V.p + (size_t)j * DB, w.t32.p, s));
-    WP_LAUNCH("arnoldi_product", s, launch_arnoldi_product(aa, w.t32.p, w.kv32.p, s));
+    HIPCHECK(launch_arnoldi_product(aa, w.t32.p, w.kv32.p, s));   // profiled inside, per kernel
     WP_LAUNCH("arnoldi_orth", s, launch_arnoldi_orth(aa, s));
   }
   HIPCHECK(hipMemcpyAsync(w.hH.data(), w.H.p, w.hH.size() * sizeof(double2), hipMemcpyDeviceToHost, s));

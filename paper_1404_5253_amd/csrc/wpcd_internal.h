@@ -13,6 +13,18 @@
 #include "../../include/wpcd.h"
 
 namespace wpcd {
+// Launch profiling (wp_profile_*): records a pair of events around the launches of its scope on
+// their stream when profiling is enabled (defined in capi.cpp).
+struct ProfScope {
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t s);
+  ~ProfScope();
+};
+}  // namespace wpcd
+
+namespace wpcd {
 
 using cplx = std::complex<double>;
 

@@ -111,14 +111,6 @@ struct wp_solution {
 
 namespace wpcd {
 
-// Launch profiling (wp_profile_*): records a pair of events around a launch on its stream.
-struct ProfScope {
-  const char* name;
-  hipStream_t st;
-  hipEvent_t a = nullptr;
-  ProfScope(const char* n, hipStream_t s);
-  ~ProfScope();
-};
 #define WP_LAUNCH(name, stream, expr)        \
   do {                                       \
     wpcd::ProfScope ps_(name, stream);       \

@@ -101,6 +101,12 @@ class LatticeWorker:
         with self.lock:
             self.queue.append(req)
 
+    def busy(self):
+        """True while a submitted request has not retired (read under the lock, so that a request
+        between the queue and the in-flight table is still seen)."""
+        with self.lock:
+            return bool(self.queue or self.inflight)
+
     def pump(self):
         """Admit what fits, then one step. Returns True if any work was done."""
         with self.lock:
@@ -114,19 +120,23 @@ class LatticeWorker:
         if not self.inflight:
             return False
         for sl, res in self.b.step():
-            req = self.inflight.pop(sl)
+            req = self.inflight[sl]
             req.t_done = self.clock()
             req.result = res
-            self.finished.append(req)
+            with self.lock:   # finished before it leaves the in-flight table
+                self.finished.append(req)
+                del self.inflight[sl]
         self.steps += 1
         return True
 
 
-def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, threaded=True):
+def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, threaded=True, measure_from=0.0):
     """Serve (t_arrival, lattice, E_lab) requests in arrival order; returns finished Requests and stats.
 
     With threaded=True each lattice is stepped by its own thread; with False a single loop
-    round-robins the lattices (deterministic, used with a virtual clock).
+    round-robins the lattices (deterministic, used with a virtual clock). The stats cover the
+    requests arriving at or after measure_from (seconds into the stream: the warm-up before it
+    is served but not counted).
     """
     reqs = [Request(k, t, lat, E) for k, (t, lat, E) in enumerate(sorted(requests))]
     t0 = clock()
@@ -149,7 +159,7 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
         threads = [threading.Thread(target=worker_loop, args=(w,), daemon=True) for w in workers]
         for t in threads:
             t.start()
-        while pending or any(w.queue or w.inflight for w in workers):
+        while pending or any(w.busy() for w in workers):
             feed()
             wait = pending[0].t_arrival - now() if pending else 0.0
             sleep(min(0.001, wait) if wait > 0 else 0.0005)
@@ -157,7 +167,7 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
         for t in threads:
             t.join()
     else:
-        while pending or any(w.queue or w.inflight for w in workers):
+        while pending or any(w.busy() for w in workers):
             feed()
             busy = False
             for w in workers:
@@ -167,15 +177,17 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
     t_end = now()
     done = [r for w in workers for r in w.finished]
     done.sort(key=lambda r: r.rid)
-    lat = sorted(r.t_done - r.t_arrival for r in done)
+    counted = [r for r in done if r.t_arrival >= measure_from]
+    lat = sorted(r.t_done - r.t_arrival for r in counted)
 
     def pct(p):
         if not lat:
             return float("nan")
         k = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
         return lat[k]
-    span = (max(r.t_done for r in done) - min(r.t_arrival for r in done)) if done else 0.0
-    stats = dict(n=len(done), p50_ms=pct(50) * 1e3, p99_ms=pct(99) * 1e3, mean_ms=(sum(lat) / len(lat) * 1e3) if lat else 0,
-                 solves_per_s=len(done) / span if span > 0 else 0.0, wall_s=t_end,
+    span = (max(r.t_done for r in counted) - min(r.t_arrival for r in counted)) if counted else 0.0
+    stats = dict(n=len(counted), n_served=len(done), n_requests=len(reqs), p50_ms=pct(50) * 1e3,
+                 p99_ms=pct(99) * 1e3, mean_ms=(sum(lat) / len(lat) * 1e3) if lat else 0,
+                 solves_per_s=len(counted) / span if span > 0 else 0.0, wall_s=t_end,
                  steps=[w.steps for w in workers])
     return done, stats

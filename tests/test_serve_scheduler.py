@@ -78,3 +78,56 @@ def test_arrivals_wait_for_free_slots():
     done, _ = run_stream([back], reqs, clock=clk, sleep=clk.sleep, threaded=False)
     first, second = sorted(done, key=lambda r: r.t_admit)
     assert second.t_admit >= first.t_done
+
+
+class ThreadedFakeBackend:
+    """Real-time fake for the threaded scheduler: slots finish after ceil(E) steps of step_s
+    seconds; admission yields the GIL between taking the slot and returning (widening the window
+    in which a request is neither queued nor in flight, had the scheduler not held the lock)."""
+
+    def __init__(self, slots, step_s=0.0002):
+        import threading
+        import time
+        self.time = time
+        self.slots = [None] * slots
+        self.step_s = step_s
+        self.mu = threading.Lock()
+
+    def admit(self, E):
+        with self.mu:
+            for k, s in enumerate(self.slots):
+                if s is None:
+                    self.slots[k] = [E, int(E) + 1]
+                    self.time.sleep(0)
+                    return k
+        return None
+
+    def live(self):
+        return sum(s is not None for s in self.slots)
+
+    def step(self):
+        self.time.sleep(self.step_s)
+        out = []
+        with self.mu:
+            for k, s in enumerate(self.slots):
+                if s is None:
+                    continue
+                s[1] -= 1
+                if s[1] <= 0:
+                    out.append((k, {"E": s[0]}))
+                    self.slots[k] = None
+        return out
+
+
+def test_threaded_stream_serves_every_request():
+    """Threaded run_stream (one thread per lattice, as the bench runs it): every request is served
+    exactly once with its own result, also the last ones of the stream, and the warm-up window is
+    served but not counted."""
+    backs = [ThreadedFakeBackend(3), ThreadedFakeBackend(4), ThreadedFakeBackend(2)]
+    reqs = [(0.0004 * k, k % 3, 1.0 + (k % 5)) for k in range(300)]
+    done, st = run_stream(backs, reqs, threaded=True, measure_from=0.04)
+    assert st["n_served"] == st["n_requests"] == 300
+    assert sorted(r.rid for r in done) == list(range(300))
+    for r in done:
+        assert r.result["E"] == r.E_lab and r.t_arrival <= r.t_admit <= r.t_done
+    assert st["n"] == sum(1 for r in done if r.t_arrival >= 0.04) < 300
