@@ -209,10 +209,24 @@ extern "C" wp_status wp_lattice_build(const wp_lattice_desc* d, const wp_allocat
   if (L->keys.empty()) L->keys.push_back({0, 0, 0, 0, 0});
   L->C.assign((size_t)L->nch * L->nch * nm, 0.0);
   for (auto& e : ent) L->C[((size_t)std::get<0>(e) * L->nch + std::get<1>(e)) * nm + std::get<2>(e)] += std::get<3>(e);
+  std::vector<char> nzp((size_t)L->nch * L->nch, 0);
   for (int p = 0; p < L->nch * L->nch; ++p) {
     bool nz = false;
     for (int m = 0; m < nm; ++m) nz |= L->C[(size_t)p * nm + m] != 0.0;
+    nzp[p] = nz;
     L->nz_pairs += nz;
+  }
+  // many channels: blocks stored packed (the channel pairs without a coefficient are left out)
+  L->vpb = L->nch * L->nch;
+  if (L->nch > 4) {
+    L->pk = make_pack(L->nch, nzp);
+    const int nc = L->nch;
+    for (int u = 0; u < nc; ++u)
+      for (int r = L->pk.lo[u]; r < L->pk.hi[u]; ++r) {
+        L->pk_src.push_back(L->pk.perm[r] * nc + L->pk.perm[u]);
+        L->pk_pos.push_back(u * nc + r);
+      }
+    L->vpb = L->pk.npk;
   }
   *out = L.release();
   return WP_OK;
@@ -540,6 +554,22 @@ static wp_status upload_tables(wp_lattice* L) {
   HIPCHECK(hipMemcpy(L->d_gwp.p, gwp.data(), gwp.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_C.p, L->C.data(), L->C.size() * 8, hipMemcpyHostToDevice));
   HIPCHECK(hipMemcpy(L->d_keys.p, keys.data(), keys.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (L->nch > 4) {
+    const int nc = L->nch;
+    std::vector<int> pkt(4 * nc);
+    for (int u = 0; u < nc; ++u) {
+      pkt[u] = L->pk.perm[u];
+      pkt[nc + u] = L->pk.lo[u];
+      pkt[2 * nc + u] = L->pk.hi[u];
+      pkt[3 * nc + u] = L->pk.off[u];
+    }
+    if (!L->d_pkt.make(&L->al, pkt.size()) || !L->d_pkpos.make(&L->al, L->pk_pos.size()) ||
+        !L->d_pksrc.make(&L->al, L->pk_src.size()))
+      return fail(WP_ENOMEM, "device allocation (packing tables)");
+    HIPCHECK(hipMemcpy(L->d_pkt.p, pkt.data(), pkt.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_pkpos.p, L->pk_pos.data(), L->pk_pos.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_pksrc.p, L->pk_src.data(), L->pk_src.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   return WP_OK;
 }
 
@@ -628,7 +658,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   };
   auto blk_cap = [&]() -> int64_t {
     const size_t nv = precision == WP_P_FP64 ? L->d_val64.n : L->d_val32.n;
-    return (int64_t)std::min(L->d_col.n, nv / (size_t)nc2);
+    return (int64_t)std::min(L->d_col.n, nv / (size_t)L->vpb);
   };
   double* val64 = nullptr;
   float* val32 = nullptr;
@@ -659,7 +689,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
     WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
     WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p, val64,
-                                           val32, L->cand_cap, bcap0, s));
+                                           val32, L->cand_cap, bcap0, L->d_pksrc.p, L->vpb, s));
     WP_LAUNCH("totals", s, launch_totals(rowptr_c + R, L->d_rowptr.p + R, L->h_tot, s));
     HIPCHECK(hipEventRecord(e1, s));
     HIPCHECK(hipEventSynchronize(e1));
@@ -708,21 +738,21 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
       if (!L->d_col.make(&L->al, nb1)) return fail(WP_ENOMEM, "device allocation (P0 columns)");
     }
     if (precision == WP_P_FP64) {
-      if (L->d_val64.n < nb1 * nc2) {
+      if (L->d_val64.n < nb1 * L->vpb) {
         L->d_val64.reset();
-        if (!L->d_val64.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+        if (!L->d_val64.make(&L->al, nb1 * L->vpb)) return fail(WP_ENOMEM, "device allocation (P0)");
       }
     } else {
-      if (L->d_val32.n < nb1 * nc2) {
+      if (L->d_val32.n < nb1 * L->vpb) {
         L->d_val32.reset();
-        if (!L->d_val32.make(&L->al, nb1 * nc2)) return fail(WP_ENOMEM, "device allocation (P0)");
+        if (!L->d_val32.make(&L->al, nb1 * L->vpb)) return fail(WP_ENOMEM, "device allocation (P0)");
       }
     }
     val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
     val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
     if (ncand > 0)
       WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p,
-                                             val64, val32, L->cand_cap, blk_cap(), s));
+                                             val64, val32, L->cand_cap, blk_cap(), L->d_pksrc.p, L->vpb, s));
     HIPCHECK(hipEventRecord(e1, s));
     HIPCHECK(hipEventSynchronize(e1));
   }
@@ -740,7 +770,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   L->stats.blocks = nblk;
   L->stats.nnz = nblk * L->nz_pairs;
   L->stats.candidates = ncand;
-  L->stats.bytes = (R + 1) * 8 + nblk * 4 + nblk * nc2 * (precision == WP_P_FP64 ? 8 : 4);
+  L->stats.bytes = (R + 1) * 8 + nblk * 4 + nblk * (int64_t)L->vpb * (precision == WP_P_FP64 ? 8 : 4);
   L->stats.device_ms = ms;
   if (stats) *stats = L->stats;
   return WP_OK;
@@ -754,8 +784,10 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
   if (rowptr) HIPCHECK(hipMemcpy(rowptr, L->d_rowptr.p, (R + 1) * 8, hipMemcpyDeviceToHost));
   if (col) HIPCHECK(hipMemcpy(col, L->d_col.p, L->blocks * 4, hipMemcpyDeviceToHost));
   if (val) {
-    // device blocks are column-major; the export is row-major: val[(blk * nch + g) * nch + g']
-    std::vector<double> d(L->blocks * nc2);
+    // device blocks are column-major (few channels) or packed (many channels); the export is
+    // row-major: val[(blk * nch + g) * nch + g']
+    const int vpb = L->vpb;
+    std::vector<double> d(L->blocks * vpb);
     if (L->prec == WP_P_FP64) {
       HIPCHECK(hipMemcpy(d.data(), L->d_val64.p, d.size() * 8, hipMemcpyDeviceToHost));
     } else {
@@ -764,9 +796,15 @@ extern "C" wp_status perm_matrix_export(const wp_lattice* L, int64_t* rowptr, in
       for (size_t e = 0; e < f.size(); ++e) d[e] = f[e];
     }
     const int nch = L->nch;
-    for (int64_t b = 0; b < L->blocks; ++b)
-      for (int g = 0; g < nch; ++g)
-        for (int gp = 0; gp < nch; ++gp) val[b * nc2 + g * nch + gp] = d[b * nc2 + gp * nch + g];
+    if (nch > 4) {
+      std::fill(val, val + L->blocks * nc2, 0.0);
+      for (int64_t b = 0; b < L->blocks; ++b)
+        for (int t = 0; t < vpb; ++t) val[b * nc2 + L->pk_src[t]] = d[b * vpb + t];
+    } else {
+      for (int64_t b = 0; b < L->blocks; ++b)
+        for (int g = 0; g < nch; ++g)
+          for (int gp = 0; gp < nch; ++gp) val[b * nc2 + g * nch + gp] = d[b * nc2 + gp * nch + g];
+    }
   }
   return WP_OK;
 }
@@ -843,7 +881,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const double* val = L->d_val64.p;
   if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
-  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, order));
+  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, order, pk_view(L)));
   std::vector<ColState> cs(B);
   for (auto& c : cs) {
     c.w.resize(nfin);
@@ -909,7 +947,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
                  (int64_t)(launched + t) * B * nfin};
       WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
       WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1,
-                                             order));
+                                             order, pk_view(L)));
     }
     HIPCHECK(hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)launched * B * nfin,
                             (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, s));

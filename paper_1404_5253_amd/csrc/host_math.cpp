@@ -467,3 +467,72 @@ cplx Wynn::push(cplx S) {
 }
 
 }  // namespace wpcd
+
+namespace wpcd {
+
+PackDesc make_pack(int nc, const std::vector<char>& nz) {
+  // groups of channels with equal rows of the pattern (canonical order within a group)
+  std::vector<std::vector<int>> groups;
+  for (int g = 0; g < nc; ++g) {
+    bool placed = false;
+    for (auto& grp : groups) {
+      const int h = grp[0];
+      bool same = true;
+      for (int gp = 0; gp < nc && same; ++gp) same = nz[g * nc + gp] == nz[h * nc + gp];
+      if (same) {
+        grp.push_back(g);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) groups.push_back({g});
+  }
+  const int align = (nc % 2 == 0) ? 2 : 1;
+  auto evaluate = [&](const std::vector<int>& perm, PackDesc* out) {
+    PackDesc d;
+    d.nc = nc;
+    int total = 0;
+    for (int u = 0; u < nc; ++u) {
+      const int cu = perm[u];
+      int lo = nc, hi = 0;
+      for (int r = 0; r < nc; ++r)
+        if (nz[perm[r] * nc + cu]) {
+          lo = std::min(lo, r);
+          hi = std::max(hi, r + 1);
+        }
+      if (hi <= lo) lo = hi = 0;   // an all-zero column stores nothing
+      lo = lo / align * align;
+      hi = std::min(nc, (hi + align - 1) / align * align);
+      d.perm[u] = cu;
+      d.lo[u] = lo;
+      d.hi[u] = hi;
+      d.off[u] = total;
+      total += hi - lo;
+    }
+    d.npk = total;
+    if (out) *out = d;
+    return total;
+  };
+  std::vector<int> gorder(groups.size());
+  for (size_t k = 0; k < gorder.size(); ++k) gorder[k] = (int)k;
+  auto perm_of = [&](const std::vector<int>& go) {
+    std::vector<int> perm;
+    for (int k : go) perm.insert(perm.end(), groups[k].begin(), groups[k].end());
+    return perm;
+  };
+  PackDesc best;
+  int best_n = evaluate(perm_of(gorder), &best);
+  if (groups.size() <= 8) {
+    while (std::next_permutation(gorder.begin(), gorder.end())) {
+      PackDesc d;
+      const int n = evaluate(perm_of(gorder), &d);
+      if (n < best_n) {
+        best_n = n;
+        best = d;
+      }
+    }
+  }
+  return best;
+}
+
+}  // namespace wpcd

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "wpcd_internal.h"
 
@@ -897,7 +898,8 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
                                                  const int32_t* __restrict__ col_c, const double* __restrict__ val_c,
                                                  const uint8_t* __restrict__ flag, const int64_t* __restrict__ rowptr,
                                                  int32_t* __restrict__ col, double* __restrict__ val64,
-                                                 float* __restrict__ val32, int64_t cap_c, int64_t cap_b) {
+                                                 float* __restrict__ val32, int64_t cap_c, int64_t cap_b,
+                                                 const int* __restrict__ pk_src, int vpb) {
   int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   int lane = threadIdx.x & 63;
   if (row >= rows) return;
@@ -923,7 +925,7 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
             if (val32) val32[d * nc2 + gp * nch + g] = (float)v;
           }
       }
-    } else {           // the wave copies each kept block, lanes over its entries
+    } else {           // the wave copies each kept block, lanes over its packed values
       unsigned long long m = mask;
       int k = 0;
       while (m) {
@@ -932,11 +934,10 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
         const int64_t es = base + src, d = out + k;
         ++k;
         if (d >= cap_b) break;
-        for (int t = lane; t < nc2; t += 64) {
-          const int gp = t / nch, g = t - gp * nch;
-          const double v = val_c[es * nc2 + g * nch + gp];
-          if (val64) val64[d * nc2 + t] = v;
-          if (val32) val32[d * nc2 + t] = (float)v;
+        for (int t = lane; t < vpb; t += 64) {
+          const double v = val_c[es * nc2 + pk_src[t]];
+          if (val64) val64[d * vpb + t] = v;
+          if (val32) val32[d * vpb + t] = (float)v;
         }
       }
     }
@@ -946,9 +947,10 @@ __global__ void __launch_bounds__(256) k_compact(int64_t rows, int nch, const in
 
 hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c, const double* val_c,
                           const uint8_t* flag, const int64_t* rowptr, int32_t* col, double* val64, float* val32,
-                          int64_t cap_c, int64_t cap_b, hipStream_t s) {
+                          int64_t cap_c, int64_t cap_b, const int* pk_src, int vpb, hipStream_t s) {
+  if (nch > 4 && (!pk_src || vpb < 1 || vpb > nch * nch)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_compact, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, nch, rowptr_c, col_c, val_c,
-                     flag, rowptr, col, val64, val32, cap_c, cap_b);
+                     flag, rowptr, col, val64, val32, cap_c, cap_b, pk_src, vpb);
   return hipGetLastError();
 }
 
@@ -1832,14 +1834,16 @@ static void spmv_dispatch(int64_t rows, int B, int cb0, int cb1, const int64_t* 
 
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order);
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk);
 
 template <typename VT, typename XT, typename AT>
 static hipError_t spmv_any(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk) {
   if (cb1 < 0) cb1 = B;
   if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1) return hipErrorInvalidValue;
-  if (nch > 4) return launch_spmv_gen<VT, XT, AT>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
+  if (nch > 4) return launch_spmv_gen<VT, XT, AT>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order, pk);
   switch (nch) {
     case 1: spmv_dispatch<VT, XT, AT, 1>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
     case 2: spmv_dispatch<VT, XT, AT, 2>(rows, B, cb0, cb1, rowptr, col, val, x, y, s, order); break;
@@ -1851,17 +1855,19 @@ static hipError_t spmv_any(int64_t rows, int nch, int B, const int64_t* rowptr, 
 }
 
 hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
-                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
-  return spmv_any<double, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
+                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk) {
+  return spmv_any<double, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order, pk);
 }
 hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
-                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
-  return spmv_any<float, float2, float>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
+                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk) {
+  return spmv_any<float, float2, float>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order, pk);
 }
 hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
                                  const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1,
-                                 const int32_t* order) {
-  return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order);
+                                 const int32_t* order, const PackView& pk) {
+  return spmv_any<float, double2, double>(rows, nch, B, rowptr, col, val, x, y, s, cb0, cb1, order, pk);
 }
 
 }  // namespace wpcd
@@ -2021,162 +2027,169 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
 }
 
 // ------------------------------------------------------------------ block-CSR product, many channels
-// Few columns (B < 16): one wavefront per block row, lanes over (slot, g) with 64 / NC slots, so
-// that a wavefront takes that many blocks at once; for each g' the lanes of a slot read the
-// contiguous column g' of their (column-major) block and the slot's x entries are broadcast.
-// The slots of a row are summed by shuffles in a fixed order.
-template <typename VT, typename XT, typename AT, int CT>
-__global__ void __launch_bounds__(256) k_spmv_gen(int64_t rows, int NC, int B, int cb0, int cb1,
-                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y, const int32_t* __restrict__ order) {
-  const int64_t row = spmv_row(rows, order);
-  const int lane = threadIdx.x & 63;
-  if (row < 0) return;
-  const int SL = 64 / NC;
-  const int s = lane / NC, g = lane - s * NC;
-  const bool act = s < SL;
-  const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
-  const int nc2 = NC * NC;
-  for (int c0 = cb0; c0 < cb1; c0 += CT) {
-    AT ar[CT], ai[CT];
-#pragma unroll
-    for (int q = 0; q < CT; ++q) ar[q] = ai[q] = AT(0);
-    for (int64_t e0 = b0; e0 < b1; e0 += SL) {
-      const int64_t e = e0 + s;
-      const bool ok = act && e < b1;
-      const int cc = ok ? col[e] : 0;
-      const VT* v = val + (ok ? e : b0) * nc2 + g;
-      const XT* xr = x + (size_t)cc * NC * B;
-      int gp = 0;
-      for (; gp + 4 <= NC; gp += 4) {
-        AT a[4];
-        XT xv[4][CT];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          a[u] = ok ? (AT)v[(gp + u) * NC] : AT(0);
-#pragma unroll
-          for (int q = 0; q < CT; ++q) xv[u][q] = xr[(size_t)(gp + u) * B + min(c0 + q, cb1 - 1)];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int q = 0; q < CT; ++q) {
-            ar[q] = fma(a[u], (AT)xv[u][q].x, ar[q]);
-            ai[q] = fma(a[u], (AT)xv[u][q].y, ai[q]);
-          }
-      }
-      for (; gp < NC; ++gp) {
-        const AT a = ok ? (AT)v[gp * NC] : AT(0);
-#pragma unroll
-        for (int q = 0; q < CT; ++q) {
-          const XT xv = xr[(size_t)gp * B + min(c0 + q, cb1 - 1)];
-          ar[q] = fma(a, (AT)xv.x, ar[q]);
-          ai[q] = fma(a, (AT)xv.y, ai[q]);
-        }
-      }
-    }
-    // sum over the slots: lane (0, g) collects (s, g), s = 1 .. SL - 1, in order
-#pragma unroll
-    for (int q = 0; q < CT; ++q) {
-      AT sr = ar[q], si = ai[q];
-      for (int t = 1; t < SL; ++t) {
-        const AT r2 = __shfl(ar[q], min(lane + t * NC, 63), WARP);
-        const AT i2 = __shfl(ai[q], min(lane + t * NC, 63), WARP);
-        if (s == 0) {
-          sr += r2;
-          si += i2;
-        }
-      }
-      if (s == 0 && c0 + q < cb1) {
-        XT out;
-        out.x = sr;
-        out.y = si;
-        y[((size_t)row * NC + g) * B + c0 + q] = out;
-      }
-    }
-  }
-}
+// P0 blocks of many channels are stored packed (PackDesc): pkt[0, NC) = perm (position ->
+// canonical channel), pkt[NC, 2NC) = lo, pkt[2NC, 3NC) = hi, pkt[3NC, 4NC) = off of each block
+// column u (position), npk values per block. x and y keep the canonical channel order.
 
-// Even NC, few columns: lanes over (slot, h) own the channel pair g = 2h, 2h + 1 and read it as
-// one vector per g' (16 bytes in FP64) from the column-major block, so a wavefront streams
-// SL = 128 / NC blocks per pass with fully used cache lines. The x entries the pass needs
-// (SL slots x NC x CT) are loaded once, coalesced, into the wavefront's LDS and read from there
-// by broadcast; the column indices of up to 63 blocks are loaded once and passed by shuffles;
-// UN values of g' are loaded ahead of their use. Blocks past the row end load nothing.
-template <typename V2, typename XT, typename AT, int CT, int UN>
-__global__ void __launch_bounds__(256) k_spmv_lds(int64_t rows, int NC, int B, int cb0, int cb1,
-                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                  const V2* __restrict__ val2, const XT* __restrict__ x,
-                                                  XT* __restrict__ y, const int32_t* __restrict__ order) {
-  __shared__ XT xs_all[4][128 * CT];
+template <typename VT, int RPL> struct VecR;
+template <> struct VecR<double, 1> { using T = double; };
+template <> struct VecR<float, 1> { using T = float; };
+template <> struct VecR<double, 2> { using T = double2; };
+template <> struct VecR<float, 2> { using T = float2; };
+template <typename T> __device__ __forceinline__ T vzero();
+template <> __device__ __forceinline__ double vzero<double>() { return 0.0; }
+template <> __device__ __forceinline__ float vzero<float>() { return 0.f; }
+template <> __device__ __forceinline__ double2 vzero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 vzero<float2>() { return make_float2(0.f, 0.f); }
+template <typename T> __device__ __forceinline__ T xzero();
+template <> __device__ __forceinline__ double2 xzero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float2 xzero<float2>() { return make_float2(0.f, 0.f); }
+template <typename T> __device__ __forceinline__ T szero() { return xzero<T>(); }
+template <> __device__ __forceinline__ float4 szero<float4>() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+template <typename VR> __device__ __forceinline__ float vget(const VR& v, int k);
+__device__ __forceinline__ double vget(const double2& v, int k) { return k ? v.y : v.x; }
+__device__ __forceinline__ float vget(const float2& v, int k) { return k ? v.y : v.x; }
+__device__ __forceinline__ double vget(const double& v, int) { return v; }
+__device__ __forceinline__ float vget(const float& v, int) { return v; }
+
+// Few columns (B < 16): one wavefront per block row (rows in the order given, longest first).
+// Lanes over (slot s, h): a slot takes one block of the pass (SL blocks per pass), lane h of the
+// slot owns the RPL channel rows RPL h .. RPL h + RPL - 1 (positions) and reads, for every block
+// column u whose stored interval holds them, RPL consecutive values. The x entries of the pass's
+// blocks (SL x NC x CT) are staged in the wavefront's LDS and read back by broadcast; the x loads
+// of the next pass are issued into registers before the current pass computes, and the column
+// indices one pass further ahead. The values of a pass are loaded UN block columns at a time (all
+// of them before the staging when UN = NC). The slots of a row are summed by shuffles in a fixed
+// order.
+template <int NC, int CT, int UN, bool P2, typename VT, typename XT, typename AT>
+__global__ void __launch_bounds__(256) k_spmv_pk(int64_t rows, int B, int cb0, int cb1,
+                                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                 const VT* __restrict__ val, int npk, const int* __restrict__ pkt,
+                                                 const XT* __restrict__ x, XT* __restrict__ y,
+                                                 const int32_t* __restrict__ order) {
+  constexpr int RPL = (NC % 2 == 0) ? 2 : 1;
+  // staging unit: one complex entry, or (P2) two adjacent columns as one 16-byte entry
+  using ST = typename std::conditional<P2, float4, XT>::type;
+  constexpr int SPC = P2 ? CT / 2 : CT;   // staging units per (slot, column u)
+  constexpr int NH = NC / RPL, SL = 64 / NH, PER = NC * SPC, NST = (SL * PER + 63) / 64;
+  static_assert(NC % UN == 0, "UN must divide NC");
+  static_assert(!P2 || (CT % 2 == 0 && sizeof(XT) == 8), "pairs of complex FP32 columns only");
+  using VR = typename VecR<VT, RPL>::T;
+  __shared__ ST xs_all[4][SL * PER];
   const int64_t row = spmv_row(rows, order);
   const int lane = threadIdx.x & 63;
-  XT* xs = xs_all[threadIdx.x >> 6];
+  ST* xs = xs_all[threadIdx.x >> 6];
   if (row < 0) return;
-  const int NH = NC >> 1;            // lanes per block column
-  const int SL = 64 / NH;            // blocks per pass
-  const int CH = SL * (64 / SL);     // blocks per column-index chunk (<= 64)
   const int s = lane / NH, h = lane - s * NH;
   const bool act = s < SL;
-  const int per = NC * CT;           // staged x entries per slot
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
-  const int64_t nh2 = (int64_t)NC * NH;   // V2 entries per block
-  for (int c0 = cb0; c0 < cb1; c0 += CT) {
-    AT ar[2][CT], ai[2][CT];
+  const VR* vr = reinterpret_cast<const VR*>(val);
+  const ST* xst = reinterpret_cast<const ST*>(x);
+  const int npr = npk / RPL;   // VR entries per block
+  const int bst = P2 ? B / 2 : B;   // staging units per (cell, channel)
+  // block columns holding this lane's rows (bit u); column u's values start at (off_u - lo_u) / RPL + h
+  unsigned inmask = 0;
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+  for (int u = 0; u < NC; ++u)
+    if (RPL * h >= pkt[NC + u] && RPL * h < pkt[2 * NC + u]) inmask |= 1u << u;
+  for (int c0 = cb0; c0 < cb1; c0 += CT) {
+    // staging entry t = k 64 + lane -> (slot, column position u, unit q): its offset within the cell
+    int xo[NST];
+#pragma unroll
+    for (int k = 0; k < NST; ++k) {
+      const int t = k * 64 + lane;
+      const int sl = t / PER, off = t - sl * PER, u = off / SPC, q = off - u * SPC;
+      xo[k] = t < SL * PER ? pkt[u] * bst + (P2 ? (c0 / 2 + q) : min(c0 + q, cb1 - 1)) : 0;
+    }
+    AT ar[RPL][CT], ai[RPL][CT];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
 #pragma unroll
       for (int q = 0; q < CT; ++q) ar[k][q] = ai[k][q] = AT(0);
-    for (int64_t cb = b0; cb < b1; cb += CH) {
-      const int colreg = (lane < CH && cb + lane < b1) ? col[cb + lane] : 0;
-      for (int k0 = 0; k0 < CH && cb + k0 < b1; k0 += SL) {
-        const int nsl = (int)min((int64_t)SL, b1 - (cb + k0));
-        for (int t0 = 0; t0 < SL * per; t0 += 64) {   // uniform trip count: all lanes shuffle
-          const int t = t0 + lane;
-          const int sl = min(t / per, SL - 1), off = t - sl * per;
-          const int gp = off / CT, q = off - gp * CT;
-          const int c2 = __shfl(colreg, min(k0 + sl, 63), WARP);
-          if (t < SL * per && sl < nsl) xs[t] = x[((size_t)c2 * NC + gp) * B + min(c0 + q, cb1 - 1)];
+    ST xreg[NST];
+    auto load_x = [&](int64_t cb, int colv) {
+      const int nsl = (int)min((int64_t)SL, b1 - cb);
+#pragma unroll
+      for (int k = 0; k < NST; ++k) {
+        const int t = k * 64 + lane, sl = t / PER;
+        const int c2 = __shfl(colv, min(sl, SL - 1), WARP);
+        // slots past the row end get zeros: their lanes multiply them by zero values
+        xreg[k] = (t < SL * PER && sl < nsl) ? xst[(size_t)c2 * NC * bst + xo[k]] : szero<ST>();
+      }
+    };
+    // x of the next pass ahead in registers for complex FP32 vectors; complex FP64 vectors are
+    // staged within the pass (register budget)
+    constexpr bool XA = sizeof(XT) == 8;
+    int colreg = (lane < SL && b0 + lane < b1) ? col[b0 + lane] : 0;
+    if (XA && b0 < b1) load_x(b0, colreg);
+    int colnext = (lane < SL && b0 + SL + lane < b1) ? col[b0 + SL + lane] : 0;
+    for (int64_t cb = b0; cb < b1; cb += SL) {
+      if (!XA) load_x(cb, colreg);
+#pragma unroll
+      for (int k = 0; k < NST; ++k) {
+        const int t = k * 64 + lane;
+        if (t < SL * PER) xs[t] = xreg[k];
+      }
+      const int64_t e = cb + s;
+      const bool ok = act && e < b1;
+      const VR* v = vr + (ok ? e : 0) * npr + h;
+      auto ld = [&](int u) -> VR {
+        return (ok && ((inmask >> u) & 1u)) ? v[(pkt[3 * NC + u] - pkt[NC + u]) / RPL] : vzero<VR>();
+      };
+      VR a[UN];
+      if (UN == NC) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u) a[u] = ld(u);
+      }
+      const int64_t nb = cb + SL;
+      if (XA) {
+        if (nb < b1) load_x(nb, colnext);
+        colnext = (lane < SL && nb + SL + lane < b1) ? col[nb + SL + lane] : 0;
+      } else {
+        colreg = colnext;
+        colnext = (lane < SL && nb + SL + lane < b1) ? col[nb + SL + lane] : 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      const ST* xr = xs + s * PER;
+      // column groups of UN (a rolled loop when UN < NC keeps the register count down)
+#pragma nounroll
+      for (int u0 = 0; u0 < NC; u0 += UN) {
+        if (UN < NC) {
+#pragma unroll
+          for (int w = 0; w < UN; ++w) a[w] = ld(u0 + w);
         }
-        __builtin_amdgcn_wave_barrier();
-        const int64_t e = cb + k0 + s;
-        if (act && e < b1) {
-          const V2* v = val2 + e * nh2 + h;
-          const XT* xr = xs + s * per;
-          int gp = 0;
-          for (; gp + UN <= NC; gp += UN) {
-            V2 a[UN];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) a[u] = v[(size_t)(gp + u) * NH];
+        for (int w = 0; w < UN; ++w) {
+          XT xv[CT];
+          if constexpr (P2) {
 #pragma unroll
-            for (int u = 0; u < UN; ++u)
+            for (int qq = 0; qq < CT / 2; ++qq) {
+              const float4 p = xr[(u0 + w) * SPC + qq];
+              xv[2 * qq].x = p.x;
+              xv[2 * qq].y = p.y;
+              xv[2 * qq + 1].x = p.z;
+              xv[2 * qq + 1].y = p.w;
+            }
+          } else {
 #pragma unroll
-              for (int q = 0; q < CT; ++q) {
-                const XT xv = xr[(gp + u) * CT + q];
-                ar[0][q] = fma((AT)a[u].x, (AT)xv.x, ar[0][q]);
-                ai[0][q] = fma((AT)a[u].x, (AT)xv.y, ai[0][q]);
-                ar[1][q] = fma((AT)a[u].y, (AT)xv.x, ar[1][q]);
-                ai[1][q] = fma((AT)a[u].y, (AT)xv.y, ai[1][q]);
-              }
+            for (int q = 0; q < CT; ++q) xv[q] = xr[(u0 + w) * SPC + q];
           }
-          for (; gp < NC; ++gp) {
-            const V2 a = v[(size_t)gp * NH];
 #pragma unroll
-            for (int q = 0; q < CT; ++q) {
-              const XT xv = xr[gp * CT + q];
-              ar[0][q] = fma((AT)a.x, (AT)xv.x, ar[0][q]);
-              ai[0][q] = fma((AT)a.x, (AT)xv.y, ai[0][q]);
-              ar[1][q] = fma((AT)a.y, (AT)xv.x, ar[1][q]);
-              ai[1][q] = fma((AT)a.y, (AT)xv.y, ai[1][q]);
+          for (int q = 0; q < CT; ++q) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+              ar[k][q] = fma((AT)vget(a[w], k), (AT)xv[q].x, ar[k][q]);
+              ai[k][q] = fma((AT)vget(a[w], k), (AT)xv[q].y, ai[k][q]);
             }
           }
         }
-        __builtin_amdgcn_wave_barrier();
       }
+      __builtin_amdgcn_wave_barrier();
     }
     // sum over the slots: lane (0, h) collects (s, h), s = 1 .. SL - 1, in order
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < RPL; ++k) {
+      const int g = pkt[RPL * h + k];   // canonical channel of the lane's row k
 #pragma unroll
       for (int q = 0; q < CT; ++q) {
         AT sr = ar[k][q], si = ai[k][q];
@@ -2192,26 +2205,24 @@ __global__ void __launch_bounds__(256) k_spmv_lds(int64_t rows, int NC, int B, i
           XT out;
           out.x = sr;
           out.y = si;
-          y[((size_t)row * NC + 2 * h + k) * B + c0 + q] = out;
+          y[((size_t)row * NC + g) * B + c0 + q] = out;
         }
       }
+    }
   }
 }
 
-template <typename VT> struct Vec2;
-template <> struct Vec2<double> { using T = double2; };
-template <> struct Vec2<float> { using T = float2; };
-
 // Many columns (B >= 16): lanes over columns, up to NCMAX channel accumulators per lane. The
-// wavefront stages each block's NC x NC entries in its own LDS slice with coalesced loads (one
-// global read per entry instead of one scalar load per entry and column block) and reads them
-// back by broadcast, two channels g per read.
+// wavefront stages each block's packed values into a full NC x NC block (positions, column-major)
+// in its own LDS slice, whose never-stored entries are zeroed once, and reads them back by
+// broadcast, two rows per read.
 #define NCMAX 24
 template <typename VT, typename XT, typename AT>
-__global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, int cb0, int cb1,
-                                                  const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                  const VT* __restrict__ val, const XT* __restrict__ x, XT* __restrict__ y,
-                                                  const int32_t* __restrict__ order) {
+__global__ void __launch_bounds__(256) k_spmm_pk(int64_t rows, int NC, int B, int cb0, int cb1,
+                                                 const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                 const VT* __restrict__ val, int npk, const int* __restrict__ pkt,
+                                                 const int* __restrict__ pk_pos, const XT* __restrict__ x,
+                                                 XT* __restrict__ y, const int32_t* __restrict__ order) {
   __shared__ VT vs_all[4][NCMAX * NCMAX + 2];
   VT* vs = vs_all[threadIdx.x >> 6];
   const int64_t row = spmv_row(rows, order);
@@ -2222,26 +2233,26 @@ __global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, i
   const int cl = live ? c : cb1 - 1;
   const int64_t b0 = rowptr[row], b1 = rowptr[row + 1];
   const int nc2 = NC * NC;
+  for (int t = lane; t < nc2 + 2; t += 64) vs[t] = VT(0);
   AT ar[NCMAX], ai[NCMAX];
 #pragma unroll
   for (int g = 0; g < NCMAX; ++g) ar[g] = ai[g] = AT(0);
   for (int64_t e = b0; e < b1; ++e) {
     const int cc = col[e];
-    const VT* v = val + e * nc2;
+    const VT* v = val + e * npk;
     __builtin_amdgcn_wave_barrier();
-    for (int t = lane; t < nc2; t += 64) vs[t] = v[t];
-    if (lane == 0 && (nc2 & 1)) vs[nc2] = VT(0);   // pad for the paired reads of an odd NC
+    for (int t = lane; t < npk; t += 64) vs[pk_pos[t]] = v[t];
     __builtin_amdgcn_wave_barrier();
     for (int gp0 = 0; gp0 < NC; gp0 += 6) {   // six x loads in flight, then their products
       XT xg[6];
 #pragma unroll
       for (int u = 0; u < 6; ++u)
-        if (gp0 + u < NC) xg[u] = x[((size_t)cc * NC + gp0 + u) * B + cl];
+        if (gp0 + u < NC) xg[u] = x[((size_t)cc * NC + pkt[gp0 + u]) * B + cl];
 #pragma unroll
       for (int u = 0; u < 6; ++u) {
         if (gp0 + u >= NC) break;
         const XT xv = xg[u];
-        const VT* vg = vs + (gp0 + u) * NC;   // column g' of the block: entries g = 0 .. NC - 1
+        const VT* vg = vs + (gp0 + u) * NC;   // column u of the block: rows r = 0 .. NC - 1
 #pragma unroll
         for (int g = 0; g < NCMAX; g += 2) {
           if (g < NC) {
@@ -2264,62 +2275,88 @@ __global__ void __launch_bounds__(256) k_spmm_gen(int64_t rows, int NC, int B, i
       XT out;
       out.x = ar[g];
       out.y = ai[g];
-      y[((size_t)row * NC + g) * B + c] = out;
+      y[((size_t)row * NC + pkt[g]) * B + c] = out;
     }
   }
 }
 
+// values loaded UN block columns at a time: all NC ahead for FP32 values and vectors, else the
+// largest of 6, 5, 4, 3, 2, 1 that divides NC (register budget of FP64 data)
+template <int NC, typename VT, typename XT>
+constexpr int spmv_pk_un() {
+  if (sizeof(VT) == 4 && sizeof(XT) == 8) return NC;
+  return NC % 6 == 0 ? 6 : NC % 5 == 0 ? 5 : NC % 4 == 0 ? 4 : NC % 3 == 0 ? 3 : NC % 2 == 0 ? 2 : 1;
+}
+
+template <int NC, int CT, bool P2, typename VT, typename XT, typename AT>
+static void launch_spmv_pk_ct(const dim3& grid, int64_t rows, int B, int cb0, int cb1, const int64_t* rowptr,
+                              const int32_t* col, const VT* val, int npk, const int* pkt, const XT* x, XT* y,
+                              hipStream_t s, const int32_t* order) {
+  hipLaunchKernelGGL((k_spmv_pk<NC, CT, spmv_pk_un<NC, VT, XT>(), P2, VT, XT, AT>), grid, dim3(256), 0, s, rows, B, cb0,
+                     cb1, rowptr, col, val, npk, pkt, x, y, order);
+}
+
+template <int NC, typename VT, typename XT, typename AT>
+static void launch_spmv_pk_nc(const dim3& grid, int64_t rows, int B, int cb0, int cb1, const int64_t* rowptr,
+                              const int32_t* col, const VT* val, int npk, const int* pkt, const XT* x, XT* y,
+                              hipStream_t s, const int32_t* order) {
+  const int ncols = cb1 - cb0;
+  // pairs of complex FP32 columns as 16-byte loads when every chunk of 4 is whole and aligned
+  const bool p2 = sizeof(XT) == 8 && B % 2 == 0 && cb0 % 2 == 0 && ncols % 4 == 0;
+  if constexpr (NC > NCMAX) {   // more than NCMAX channels: four columns per pass only
+    launch_spmv_pk_ct<NC, 4, false, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, npk, pkt, x, y, s, order);
+  } else {
+    if (ncols >= 4 && p2 && sizeof(XT) == 8)
+      launch_spmv_pk_ct<NC, 4, sizeof(XT) == 8, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, npk, pkt, x, y,
+                                                             s, order);
+    else if (ncols >= 4)
+      launch_spmv_pk_ct<NC, 4, false, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, npk, pkt, x, y, s, order);
+    else if (ncols >= 2)
+      launch_spmv_pk_ct<NC, 2, false, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, npk, pkt, x, y, s, order);
+    else
+      launch_spmv_pk_ct<NC, 1, false, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, npk, pkt, x, y, s, order);
+  }
+}
 
 template <typename VT, typename XT, typename AT>
 hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const VT* val,
-                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order) {
+                           const XT* x, XT* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk) {
   if (cb1 < 0) cb1 = B;
-  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 1 || nch > 64) return hipErrorInvalidValue;
+  if (cb0 < 0 || cb1 > B || cb0 >= cb1 || rows < 1 || nch < 5 || nch > PK_MAX || !pk.pkt || !pk.pos ||
+      pk.npk < 1 || pk.npk > nch * nch)
+    return hipErrorInvalidValue;
   // the choice depends on B and nch only, so every launch on a given batch width sums in one order
-  if (B >= 16 && nch <= NCMAX) {
-    dim3 grid((unsigned)spmv_blocks(rows, order), (cb1 - cb0 + 63) / 64);
-    hipLaunchKernelGGL((k_spmm_gen<VT, XT, AT>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, val, x, y, order);
-  } else if (nch % 2 == 0 && nch >= 4) {
-    using V2 = typename Vec2<VT>::T;
-    const V2* v2 = reinterpret_cast<const V2*>(val);
-    const dim3 grid((unsigned)spmv_blocks(rows, order));
-    const int ncols = cb1 - cb0;
-    if (nch % 9 == 0) {
-      if (ncols >= 4)
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 4, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-      else if (ncols >= 2)
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 2, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-      else
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 1, 9>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-    } else {
-      if (ncols >= 4)
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 4, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-      else if (ncols >= 2)
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 2, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-      else
-        hipLaunchKernelGGL((k_spmv_lds<V2, XT, AT, 1, 6>), grid, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, v2, x, y, order);
-    }
-  } else if (B >= 4) {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 4>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
-                       cb0, cb1, rowptr, col, val, x, y, order);
-  } else if (B >= 2) {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 2>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
-                       cb0, cb1, rowptr, col, val, x, y, order);
-  } else {
-    hipLaunchKernelGGL((k_spmv_gen<VT, XT, AT, 1>), dim3((unsigned)spmv_blocks(rows, order)), dim3(256), 0, s, rows, nch, B,
-                       cb0, cb1, rowptr, col, val, x, y, order);
+  const dim3 grid((unsigned)spmv_blocks(rows, order));
+  if (B >= 16 && nch <= NCMAX) {   // wider blocks take the few-column kernel, four columns per pass
+    dim3 g2 = grid;
+    g2.y = (cb1 - cb0 + 63) / 64;
+    hipLaunchKernelGGL((k_spmm_pk<VT, XT, AT>), g2, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, val, pk.npk,
+                       pk.pkt, pk.pos, x, y, order);
+    return hipGetLastError();
+  }
+  switch (nch) {
+#define WP_PK_CASE(n) \
+  case n: launch_spmv_pk_nc<n, VT, XT, AT>(grid, rows, B, cb0, cb1, rowptr, col, val, pk.npk, pk.pkt, x, y, s, order); break;
+    WP_PK_CASE(5) WP_PK_CASE(6) WP_PK_CASE(7) WP_PK_CASE(8) WP_PK_CASE(9) WP_PK_CASE(10) WP_PK_CASE(11)
+    WP_PK_CASE(12) WP_PK_CASE(13) WP_PK_CASE(14) WP_PK_CASE(15) WP_PK_CASE(16) WP_PK_CASE(17) WP_PK_CASE(18)
+    WP_PK_CASE(19) WP_PK_CASE(20) WP_PK_CASE(21) WP_PK_CASE(22) WP_PK_CASE(23) WP_PK_CASE(24)
+    WP_PK_CASE(25) WP_PK_CASE(26) WP_PK_CASE(27) WP_PK_CASE(28) WP_PK_CASE(29) WP_PK_CASE(30) WP_PK_CASE(31)
+    WP_PK_CASE(32)
+#undef WP_PK_CASE
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_spmv_gen<double, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
                                                              const double*, const double2*, double2*, hipStream_t, int, int,
-                                                             const int32_t*);
+                                                             const int32_t*, const PackView&);
 template hipError_t launch_spmv_gen<float, float2, float>(int64_t, int, int, const int64_t*, const int32_t*,
                                                           const float*, const float2*, float2*, hipStream_t, int, int,
-                                                          const int32_t*);
+                                                          const int32_t*, const PackView&);
 template hipError_t launch_spmv_gen<float, double2, double>(int64_t, int, int, const int64_t*, const int32_t*,
                                                             const float*, const double2*, double2*, hipStream_t, int, int,
-                                                            const int32_t*);
+                                                            const int32_t*, const PackView&);
 
 }  // namespace wpcd

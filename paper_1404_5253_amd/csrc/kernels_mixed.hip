@@ -556,7 +556,7 @@ hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2*
     if (!kv_scratch) return hipErrorInvalidValue;
     {
       ProfScope ps("spmv_f32", s);
-      hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s, 0, -1, a.order);
+      hipError_t e = launch_spmv_f32(a.cells, a.nch, a.B, a.rowptr, a.col, a.val, t, kv_scratch, s, 0, -1, a.order, a.pk);
       if (e != hipSuccess) return e;
     }
     ProfScope ps("arnoldi_dots", s);

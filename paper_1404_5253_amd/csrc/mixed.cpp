@@ -66,7 +66,7 @@ wp_status wpcd::ensure_mixed(wp_lattice* L, hipStream_t s) {
     L->Mp = Mp;
   }
   if (!L->d_val32.p) {
-    const int64_t n = L->blocks * L->nch * L->nch;
+    const int64_t n = L->blocks * L->vpb;
     if (!L->d_val32.make(&L->al, std::max<int64_t>(n, 1))) return fail(WP_ENOMEM, "device allocation (FP32 P0)");
     if (n > 0) HIPCHECK(launch_cvt_scalar(n, L->d_val64.p, L->d_val32.p, s));
   }
@@ -149,14 +149,14 @@ wp_status wpcd::mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const s
     WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, w.dy.p, w.ds64.p, s));
     WP_LAUNCH("spmv_f32v_f64x", s,
               launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.dKy.p, s, 0, -1,
-                                    spmv_order(L)));
+                                    spmv_order(L), pk_view(L)));
     WP_LAUNCH("residual", s, launch_residual(DB, w.db.p, w.dy.p, w.dKy.p, w.dr.p, s));
   }
   HIPCHECK(launch_norm2_f64(D, B, w.dr.p, w.part.p, kNblk, w.nrm.p, s));
   HIPCHECK(launch_scale_d2f(D, B, w.nrm.p, w.dr.p, w.V.p, w.scl.p, s));
   HIPCHECK(hipMemcpyAsync(w.hn.data(), w.nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
   ArnoldiArgs aa{R,         nch,     B,      m,    0,          L->d_rowptr.p, L->d_col.p, L->d_val32.p,
-                 spmv_order(L), w.V.p, DB,    w.scl.p, w.H.p, w.part.p, kNblk};
+                 spmv_order(L), w.V.p, DB,    w.scl.p, w.H.p, w.part.p, kNblk, pk_view(L)};
   RotArgsMixed rm{M,          N, nch, B, L->d_Ob.p, w.split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p,
                   w.split ? L->d_Wb_lo.p : nullptr, L->Mp, L->d_wave.p, w.dG32.p, nullptr};
   for (int j = 0; j < m; ++j) {
@@ -260,7 +260,7 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, dg0.p, w.ds64.p, s));
   WP_LAUNCH("spmv_f32v_f64x", s,
             launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, s, 0, -1,
-                                  spmv_order(L)));
+                                  spmv_order(L), pk_view(L)));
   HIPCHECK(launch_fill0(w.dy.p, DB, s));
   std::vector<MixedCol> col(B);
   std::vector<char> active(B, 1);

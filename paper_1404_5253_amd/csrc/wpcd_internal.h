@@ -51,6 +51,21 @@ struct MomKey { int k, a, b, l, lp; };
 struct GTerm { int l1, l1p, k; double g; };
 std::vector<GTerm> g_table(const Chan& c, const Chan& cp, int two_J);
 
+// Packed storage of the channel blocks of P0 for many channels. The channel pairs whose
+// recoupling coefficients all vanish (eq. gal) are zero in every block, so a block stores only
+// the others: channels are taken in a permuted order (position r -> canonical channel perm[r])
+// chosen so that the stored rows of each block column u form one interval [lo[u], hi[u]) (even
+// ends when nc is even, for two-row loads), stored at off[u] within the block's npk values.
+constexpr int PK_MAX = 32;
+struct PackDesc {
+  int nc = 0, npk = 0;
+  int perm[PK_MAX], lo[PK_MAX], hi[PK_MAX], off[PK_MAX];
+};
+// nz[g * nc + gp]: the pair (g, g') has a nonzero coefficient. Returns the packing with the
+// fewest stored values among the orders of the groups of channels with equal rows (exhaustive up
+// to 8 groups, else the canonical order of groups).
+PackDesc make_pack(int nc, const std::vector<char>& nz);
+
 // Wynn epsilon accumulator with the stop rule of faddeev_solve.
 struct Wynn {
   std::vector<cplx> diag;
@@ -144,10 +159,13 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
 hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt,
                            int64_t cap, hipStream_t s);
 // Reads candidates below cap_c, writes kept blocks below cap_b.
+// Many channels (nch > 4): the kept blocks are written packed, value t of a block taken from the
+// candidate block's row-major entry pk_src[t] (vpb values per block); few channels: full
+// column-major blocks (vpb = nch^2, pk_src unused).
 hipError_t launch_compact(int64_t rows, int nch, const int64_t* rowptr_c, const int32_t* col_c,
                           const double* val_c, const uint8_t* flag, const int64_t* rowptr,
                           int32_t* col, double* val64, float* val32, int64_t cap_c, int64_t cap_b,
-                          hipStream_t s);
+                          const int* pk_src, int vpb, hipStream_t s);
 // SpMV work order of R block rows: by decreasing length (ties in any order).
 hipError_t launch_row_order(int64_t R, const int64_t* rowptr, int32_t* order, hipStream_t s);
 // host[0] = *a, host[1] = *b, with host in pinned host memory.
@@ -172,18 +190,27 @@ hipError_t launch_init_rhs64(int M, int N, int nch, int B, const double* W, cons
                              const int* j0, const int* g0, double2* s0, hipStream_t st, int cb0 = 0,
                              int cb1 = -1);
 hipError_t launch_fill0(double2* p, int64_t n, hipStream_t st);
+// Device view of the packed block storage (many channels, PackDesc): npk values per block;
+// pkt[4 nc] = perm, lo, hi, off; pos[npk] = position (u nc + r) of each packed value in the full
+// column-major block of positions.
+struct PackView {
+  int npk = 0;
+  const int* pkt = nullptr;
+  const int* pos = nullptr;
+};
 // Block-CSR products for any storage/vector precision: lanes over columns when all B >= 16
-// columns are requested, else lanes over blocks with a wave reduction.
+// columns are requested, else lanes over blocks with a wave reduction. Few channels (<= 4): full
+// column-major blocks; many channels: the packed blocks described by pk.
 // order: the block rows in the sequence the wavefronts take them (longest first), or nullptr
 hipError_t launch_spmv_f64(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const double* val,
-                           const double2* x, double2* y, hipStream_t s, int cb0 = 0, int cb1 = -1,
-                           const int32_t* order = nullptr);
+                           const double2* x, double2* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk);
 hipError_t launch_spmv_f32(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col, const float* val,
-                           const float2* x, float2* y, hipStream_t s, int cb0 = 0, int cb1 = -1,
-                           const int32_t* order = nullptr);
+                           const float2* x, float2* y, hipStream_t s, int cb0, int cb1, const int32_t* order,
+                           const PackView& pk);
 hipError_t launch_spmv_f32v_f64x(int64_t rows, int nch, int B, const int64_t* rowptr, const int32_t* col,
-                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0 = 0,
-                                 int cb1 = -1, const int32_t* order = nullptr);
+                                 const float* val, const double2* x, double2* y, hipStream_t s, int cb0, int cb1,
+                                 const int32_t* order, const PackView& pk);
 // zero the columns [cb0, cb1) of a rows x B array
 hipError_t launch_fill0_cols(double2* p, int64_t rows, int B, int cb0, int cb1, hipStream_t st);
 
@@ -254,6 +281,7 @@ struct ArnoldiArgs {
   double2* H;           // [m][m + 1][B]
   double2* part;        // [nblk][ARN_NV][B] partial sums
   int nblk;
+  PackView pk;          // packed blocks (many channels)
 };
 // w = V_j - P0 t into slot j + 1 and H column j (rows 0..j); kv_scratch ([rows][B]) is used when
 // the fused kernel does not apply (B < 16 or nch > 4)

@@ -89,7 +89,14 @@ struct wp_lattice {
   DBuf<double> d_val64;
   DBuf<float> d_val32;
   wp_perm_stats stats{};
+  // packed block storage for many channels (nch > 4): vpb values per stored block; per packed
+  // value its candidate-block entry (row-major g * nch + g') and its block position (u * nch + r)
+  PackDesc pk;
+  int vpb = 0;
+  std::vector<int> pk_src, pk_pos;
+  DBuf<int> d_pkt, d_pkpos, d_pksrc;
 };
+inline PackView pk_view(const wp_lattice* L) { return PackView{L->pk.npk, L->d_pkt.p, L->d_pkpos.p}; }
 
 struct EnergyResult {
   double E_lab, E, q0, dq0;

@@ -65,6 +65,8 @@ SPECS = {
     # 144 nodes per box: past the node-table path, the selection and quadrature that build their
     # own node tables per q-box
     "doublet_mt_nodes144": pipeline.Spec(M=9, N=8, two_J=1, pot="mt", n_x=12, n_phi=12),
+    # J = 3/2+ with j <= 2: 30 channels, more than the wide-batch kernel holds per lane
+    "pw30_mt_4": pipeline.Spec(M=4, N=5, two_J=3, j_max=2, swave_only=False, pot="mt"),
 }
 
 

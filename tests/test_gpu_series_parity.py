@@ -14,12 +14,16 @@ The solve kernels are chosen by the grid a call makes (columns = energies x open
 |---|---|---|---|
 | doublet_mt_20, 1 energy | 1 | k_step64r (MFMA, all row tiles per workgroup) | k_spmv, 2 channels |
 | doublet_mt_20, 64 energies | 64 | k_step64m<1> (MFMA, >= 256 workgroups) | k_spmm, 2 channels |
-| pw18_mt_6, 1 energy | 2 | k_step64r | k_spmv_lds<2 columns, 9> |
-| pw18_mt_6, 2 energies | 4 | k_step64r | k_spmv_lds<4 columns, 9> |
-| pw18_mt_6, 20 energies | 40 | k_step64m<2> | k_spmm_gen |
-| pw10_mt_8, 2 energies | 4 | k_step64r | k_spmv_lds<4 columns, 6> |
+| pw18_mt_6, 1 energy | 2 | k_step64r | k_spmv_pk<18, 2 columns> |
+| pw18_mt_6, 2 energies | 4 | k_step64r | k_spmv_pk<18, 4 columns> |
+| pw18_mt_6, 20 energies | 40 | k_step64m<2> | k_spmm_pk |
+| pw10_mt_8, 2 energies | 4 | k_step64r | k_spmv_pk<10, 4 columns> |
 | doublet_mt_136x8, 1 energy | 1 | k_step64 (VALU, M > 128) | k_spmv, 2 channels |
 | quartet_yam_24, 3 energies | 3 | k_step64r | k_spmv, 1 channel |
+| pw30_mt_4, 3 and 12 energies | 3 x open channels | k_step64r / k_step64m | k_spmv_pk<30, 4> (more than 24 channels) |
+
+Many-channel P0 (more than 4 channels) is stored packed: only the channel pairs with a nonzero
+recoupling coefficient, in a permuted channel order (k_spmv_pk, k_spmm_pk).
 """
 import numpy as np
 import pytest
@@ -40,6 +44,7 @@ SPECS = {
     "pw10_mt_8": pipeline.Spec(M=8, N=8, two_J=1, j_max=1, swave_only=False, pot="mt"),
     "doublet_mt_136x8": pipeline.Spec(M=136, N=8, two_J=1, pot="mt"),
     "quartet_yam_24": pipeline.Spec(M=24, N=24, two_J=3, pot="yamaguchi"),
+    "pw30_mt_4": pipeline.Spec(M=4, N=5, two_J=3, j_max=2, swave_only=False, pot="mt"),
 }
 
 CASES = {
@@ -51,6 +56,8 @@ CASES = {
     "pw10_mt_8-E2": ("pw10_mt_8", [3.0, 22.7]),
     "doublet_mt_136x8-E1": ("doublet_mt_136x8", [14.1]),
     "quartet_yam_24-E3": ("quartet_yam_24", [1.0, 3.0, 10.0]),
+    "pw30_mt_4-E3": ("pw30_mt_4", [3.0, 14.1, 22.7]),
+    "pw30_mt_4-E12": ("pw30_mt_4", list(np.random.default_rng(3).uniform(4.0, 50.0, 12))),
 }
 
 _systems = {}
