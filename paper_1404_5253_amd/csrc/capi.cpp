@@ -570,6 +570,62 @@ static wp_status upload_tables(wp_lattice* L) {
     HIPCHECK(hipMemcpy(L->d_pkpos.p, L->pk_pos.data(), L->pk_pos.size() * sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(L->d_pksrc.p, L->pk_src.data(), L->pk_src.size() * sizeof(int), hipMemcpyHostToDevice));
   }
+  // fused build tables (more than 8 moments)
+  const int nm = (int)L->keys.size(), nc = L->nch;
+  bool has_k0 = false;
+  FusedArgs& fz = L->fz;
+  fz.KM = fz.EA = fz.EB = fz.LL = fz.LP = 1;
+  for (auto& k : L->keys) {
+    has_k0 = has_k0 || k.k == 0;
+    fz.KM = std::max(fz.KM, k.k + 1);
+    fz.EA = std::max(fz.EA, k.a + 1);
+    fz.EB = std::max(fz.EB, k.b + 1);
+    fz.LL = std::max(fz.LL, k.l + 1);
+    fz.LP = std::max(fz.LP, k.lp + 1);
+  }
+  fz.vpb = L->vpb;
+  fz.ncoef = 0;
+  for (int t = 0; t < L->vpb; ++t) {
+    const int gg = nc > 4 ? L->pk_src[t] : (t % nc) * nc + t / nc;
+    for (int m = 0; m < nm; ++m) fz.ncoef += L->C[(size_t)gg * nm + m] != 0.0;
+  }
+  fz.ncoef = std::max(fz.ncoef, 1);
+  PBuildArgs shape{L->M, L->N, nc, nm, L->n_x, L->n_phi};
+  // the stored set of the fused build equals that of the two-pass build when some moment has k = 0
+  L->fz_ok = nm > 8 && has_k0 && fused_build_fits(shape, fz);
+  if (L->fz_ok) {
+    std::vector<int> fkey, cptr{0}, cm;
+    std::vector<double> cv;
+    for (auto& k : L->keys) fkey.insert(fkey.end(), {k.k, k.a * fz.EB + k.b, k.l * fz.LP + k.lp});
+    for (int t = 0; t < L->vpb; ++t) {
+      // canonical pair (g, g') of stored value t: packed (pk_src), or full column-major (t = g' nc + g)
+      const int gg = nc > 4 ? L->pk_src[t] : (t % nc) * nc + t / nc;
+      for (int m = 0; m < nm; ++m) {
+        const double c = L->C[(size_t)gg * nm + m];
+        if (c != 0.0) {
+          cm.push_back(m);
+          cv.push_back(c);
+        }
+      }
+      cptr.push_back((int)cm.size());
+    }
+    if (cm.empty()) {   // all coefficients zero: keep the arrays non-empty
+      cm.push_back(0);
+      cv.push_back(0.0);
+    }
+    if ((int)cm.size() != fz.ncoef) return fail(WP_EINVAL, "fused build tables: coefficient count mismatch");
+    if (!L->d_fkey.make(&L->al, fkey.size()) || !L->d_fcptr.make(&L->al, cptr.size()) ||
+        !L->d_fcm.make(&L->al, cm.size()) || !L->d_fcv.make(&L->al, cv.size()))
+      return fail(WP_ENOMEM, "device allocation (fused build tables)");
+    HIPCHECK(hipMemcpy(L->d_fkey.p, fkey.data(), fkey.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_fcptr.p, cptr.data(), cptr.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_fcm.p, cm.data(), cm.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L->d_fcv.p, cv.data(), cv.size() * sizeof(double), hipMemcpyHostToDevice));
+    fz.fkey = L->d_fkey.p;
+    fz.cptr = L->d_fcptr.p;
+    fz.cm = L->d_fcm.p;
+    fz.cv = L->d_fcv.p;
+  }
   return WP_OK;
 }
 
@@ -610,7 +666,8 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   const int nn = L->n_x * L->n_phi, nmom = (int)L->keys.size();
   const bool use_tab = nmom <= 4 && nn <= 128 && 9 * M + 1 <= 8192;
   const int AS = ((nmom <= 1 ? 1 : nmom <= 2 ? 2 : 4) + 2) & ~1;
-  double *geo = nullptr, *aux = nullptr;
+  double *geo = nullptr, *aux = nullptr, *fgeo = nullptr;
+  const bool fused = L->keys.size() > 8 && L->fz_ok;
   int *cnt, *lo, *segoff;
   int64_t *rowcnt, *rowptr_c, *tmp;
   auto sel_layout = [&](char* base) {
@@ -619,6 +676,7 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
       geo = c.take<double>((size_t)N * N * nn * 4);
       aux = c.take<double>((size_t)N * N * nn * AS);
     }
+    if (fused) fgeo = c.take<double>((size_t)N * N * fused_geo_doubles(a));
     cnt = c.take<int>(nbox);
     lo = c.take<int>(nbox);
     segoff = c.take<int>(nbox);
@@ -643,14 +701,19 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   else L->d_val64.reset();
   const bool general = L->keys.size() > 8;
   const int nm = (int)L->keys.size();
-  int32_t* col_c;
-  double *val_c, *mom, *nrm, *Ct;
-  uint8_t* flag;
+  int32_t* col_c = nullptr;
+  double *val_c = nullptr, *mom = nullptr, *nrm = nullptr, *Ct = nullptr;
+  uint8_t* flag = nullptr;
+  int64_t* dest = nullptr;
   auto cand_layout = [&](char* base, size_t nc) {
     Carve c{base};
+    flag = c.take<uint8_t>(nc);
+    if (fused) {   // per candidate: kept flag and final block index
+      dest = c.take<int64_t>(nc);
+      return c.off;
+    }
     col_c = c.take<int32_t>(nc);
     val_c = c.take<double>(nc * nc2);
-    flag = c.take<uint8_t>(nc);
     mom = general ? c.take<double>(nc * nm) : nullptr;
     nrm = general ? c.take<double>(nc) : nullptr;
     Ct = general ? c.take<double>((size_t)nm * nc2) : nullptr;
@@ -676,20 +739,39 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     return use_tab ? launch_pbuild_tab(a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s)
                    : launch_pbuild(a, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, L->cand_cap, s);
   };
+  // fused build: kept flags, then the final row pointer from them
+  auto fused_flags = [&]() -> wp_status {
+    WP_LAUNCH("pflag", s, launch_pflag(a, cnt, lo, segoff, rowptr_c, flag, L->cand_cap, fgeo, s));
+    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
+    WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
+    return WP_OK;
+  };
+  // fused build: final block index per candidate, then the values of every kept block
+  auto fused_values = [&](int64_t cap_b) -> wp_status {
+    WP_LAUNCH("cand_dest", s, launch_cand_dest(R, rowptr_c, flag, L->d_rowptr.p, dest, L->cand_cap, s));
+    WP_LAUNCH("pbuild_fused", s, launch_pbuild_fused(a, L->fz, cnt, lo, segoff, rowptr_c, fgeo, dest, L->cand_cap,
+                                                     L->d_col.p, val64, val32, cap_b, s));
+    return WP_OK;
+  };
   WP_LAUNCH("rowseg", s, launch_rowseg(M, N, cnt, segoff, rowcnt, s));
   WP_LAUNCH("scan", s, launch_scan(rowcnt, rowptr_c, R, tmp, s));
   int64_t ncand = -1, nblk = -1;
   bool done = false;
   const int64_t bcap0 = blk_cap();
-  if (!general && L->cand_cap > 0 && bcap0 > 0) {
+  if ((!general || fused) && L->cand_cap > 0 && bcap0 > 0) {
     cand_layout(L->scratch_cand.p, (size_t)L->cand_cap);
     val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
     val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
-    WP_LAUNCH("pbuild", s, pbuild());
-    WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
-    WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
-    WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p, val64,
-                                           val32, L->cand_cap, bcap0, L->d_pksrc.p, L->vpb, s));
+    if (fused) {
+      if (wp_status st = fused_flags()) return st;
+      if (wp_status st = fused_values(bcap0)) return st;
+    } else {
+      WP_LAUNCH("pbuild", s, pbuild());
+      WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
+      WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
+      WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p, val64,
+                                             val32, L->cand_cap, bcap0, L->d_pksrc.p, L->vpb, s));
+    }
     WP_LAUNCH("totals", s, launch_totals(rowptr_c + R, L->d_rowptr.p + R, L->h_tot, s));
     HIPCHECK(hipEventRecord(e1, s));
     HIPCHECK(hipEventSynchronize(e1));
@@ -711,7 +793,9 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
       L->cand_cap = (int64_t)nc;
     }
     cand_layout(L->scratch_cand.p, (size_t)L->cand_cap);
-    if (ncand > 0 && general) {
+    if (ncand > 0 && fused) {
+      if (wp_status st = fused_flags()) return st;
+    } else if (ncand > 0 && general) {
       // transposed coefficient table [nmom][nch*nch] for the combine contraction
       std::vector<double> ct((size_t)nm * nc2);
       for (int gg = 0; gg < nc2; ++gg)
@@ -722,12 +806,14 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     } else if (ncand > 0) {
       WP_LAUNCH("pbuild", s, pbuild());
     }
-    if (ncand > 0) {
-      WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
-    } else {
-      HIPCHECK(hipMemsetAsync(rowcnt, 0, R * sizeof(int64_t), s));
+    if (!(ncand > 0 && fused)) {
+      if (ncand > 0) {
+        WP_LAUNCH("rowcount", s, launch_rowcount(R, rowptr_c, flag, rowcnt, L->cand_cap, s));
+      } else {
+        HIPCHECK(hipMemsetAsync(rowcnt, 0, R * sizeof(int64_t), s));
+      }
+      WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
     }
-    WP_LAUNCH("scan", s, launch_scan(rowcnt, L->d_rowptr.p, R, tmp, s));
     HIPCHECK(hipMemcpyAsync(L->h_tot + 1, L->d_rowptr.p + R, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     nblk = L->h_tot[1];
@@ -750,9 +836,12 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
     }
     val64 = precision == WP_P_FP64 ? L->d_val64.p : nullptr;
     val32 = precision == WP_P_FP64 ? nullptr : L->d_val32.p;
-    if (ncand > 0)
+    if (ncand > 0 && fused) {
+      if (wp_status st = fused_values(blk_cap())) return st;
+    } else if (ncand > 0) {
       WP_LAUNCH("compact", s, launch_compact(R, nch, rowptr_c, col_c, val_c, flag, L->d_rowptr.p, L->d_col.p,
                                              val64, val32, L->cand_cap, blk_cap(), L->d_pksrc.p, L->vpb, s));
+    }
     HIPCHECK(hipEventRecord(e1, s));
     HIPCHECK(hipEventSynchronize(e1));
   }

@@ -63,12 +63,13 @@ struct Node {
 // box_phi_table, and box_node_at completes node nd = a * n_phi + b from that table; the values are
 // the same, operation by operation, as evaluating every node from scratch.
 #define PHI_STRIDE 5   // c, s, Q1, Q2, phi-weight factor per phi node
-// phi node ib of the box into tab[ib * PHI_STRIDE ...]
-__device__ void box_phi_row(const PBuildArgs& a, int j, int jp, int ib, double* tab) {
-  const double qa = a.qe[j], qb = a.qe[j + 1], qpa = a.qe[jp], qpb = a.qe[jp + 1];
+static_assert(PHI_STRIDE == 5, "fused_geo_doubles assumes 5 doubles per phi node");
+// phi node ib of the box into tab[ib * PHI_STRIDE ...] (q edges qe, Gauss nodes gp on [-1, 1])
+__device__ void box_phi_row_p(const double* qe, const double* gp, int j, int jp, int ib, double* tab) {
+  const double qa = qe[j], qb = qe[j + 1], qpa = qe[jp], qpb = qe[jp + 1];
   const double phi1 = atan2(qpa, qb), phi2 = atan2(qpb, qa);
   const double hphi = 0.5 * (phi2 - phi1);
-  const double phi = 0.5 * (phi1 + phi2) + hphi * a.gp[ib];
+  const double phi = 0.5 * (phi1 + phi2) + hphi * gp[ib];
   double c, sn;
   sincos(phi, &sn, &c);
   double* t = tab + ib * PHI_STRIDE;
@@ -78,22 +79,30 @@ __device__ void box_phi_row(const PBuildArgs& a, int j, int jp, int ib, double* 
   t[3] = fmin(qb / c, qpb / sn);
   t[4] = hphi;
 }
-__device__ Node box_node_at(const PBuildArgs& a, const double* tab, int nd) {
+__device__ __forceinline__ void box_phi_row(const PBuildArgs& a, int j, int jp, int ib, double* tab) {
+  box_phi_row_p(a.qe, a.gp, j, jp, ib, tab);
+}
+// node nd = ia * n_phi + ib from the phi table (x rule gx, gwx; phi weights gwp)
+__device__ Node box_node_at_p(const double* gx, const double* gwx, const double* gwp, int n_phi, const double* tab,
+                              int nd) {
   Node n;
-  const int ia = nd / a.n_phi, ib = nd - ia * a.n_phi;
+  const int ia = nd / n_phi, ib = nd - ia * n_phi;
   const double* t = tab + ib * PHI_STRIDE;
   n.c = t[0];
   n.s = t[1];
   n.Q1 = t[2];
   n.Q2 = t[3];
-  n.w = a.gwx[ia] * t[4] * a.gwp[ib];
-  n.x = a.gx[ia];
+  n.w = gwx[ia] * t[4] * gwp[ib];
+  n.x = gx[ia];
   const double cs = n.c * n.s;
   n.z1 = sqrt(n.c * n.c + 0.25 * n.s * n.s + n.x * cs);
   const double z2 = sqrt(0.25 * n.c * n.c + n.s * n.s + n.x * cs);
   n.r1 = 1.0 / n.z1;
   n.r2 = 1.0 / z2;
   return n;
+}
+__device__ __forceinline__ Node box_node_at(const PBuildArgs& a, const double* tab, int nd) {
+  return box_node_at_p(a.gx, a.gwx, a.gwp, a.n_phi, tab, nd);
 }
 // the phi table of box (j, jp) in LDS, filled by the first n_phi threads of the workgroup
 __device__ __forceinline__ void fill_phi_table(const PBuildArgs& a, int j, int jp, double* tab) {
@@ -2024,6 +2033,612 @@ hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const in
                        a.nch * a.nch, Ct, mom, norm, val_c, flag);
   }
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ step 3 fused (many moments)
+// The stored set is decided from the geometry alone: a candidate pair is kept when F > 0 at one of
+// its nodes. With a moment of k = 0 among the keys (its weight is positive at every node) that is
+// exactly the rule "some moment integral is nonzero" of the two-pass build above.
+
+// Row prefix of q-box `box` (all threads of the workgroup): s_pref[i] = candidates of the rows
+// before i (s_pref[M] = the box total, returned), s_lo[i] = first p' of row i, s_cb[i] = candidate
+// index of (row i, p' = s_lo[i]). s_w holds one int per wavefront.
+__device__ int box_rows(const PBuildArgs& a, int box, const int* __restrict__ cnt, const int* __restrict__ lo,
+                        const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c, int* s_pref,
+                        int* s_lo, int64_t* s_cb, int* s_w) {
+  const int M = a.M, j = box / a.N;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  int carry = 0;
+  for (int base = 0; base < M; base += blockDim.x) {
+    const int i = base + t;
+    int c = 0;
+    if (i < M) {
+      c = cnt[(size_t)box * M + i];
+      s_lo[i] = lo[(size_t)box * M + i];
+      s_cb[i] = rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i];
+    }
+    int v = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, WARP);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) s_w[wv] = v;
+    __syncthreads();
+    int off = carry, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wv) off += s_w[w];
+      tot += s_w[w];
+    }
+    if (i < M) s_pref[i] = off + v - c;
+    carry += tot;
+    __syncthreads();
+  }
+  if (t == 0) s_pref[M] = carry;
+  __syncthreads();
+  return carry;
+}
+// the row i of the box's candidate e: the last row with s_pref[i] <= e (a row with candidates)
+__device__ __forceinline__ int cand_row(const int* s_pref, int M, int e) {
+  int lo_i = 0, hi_i = M - 1;
+  while (lo_i < hi_i) {
+    const int mid = (lo_i + hi_i + 1) >> 1;
+    if (s_pref[mid] <= e) lo_i = mid;
+    else hi_i = mid - 1;
+  }
+  return lo_i;
+}
+
+// Also stores the box's node geometry for k_pbuild_fused: geo[box][4 nn + PHI_STRIDE n_phi] =
+// r1, r2, Q1, Q2 of every node, then the phi table (boxes without candidates are not written).
+__global__ void __launch_bounds__(256) k_pflag(PBuildArgs a, const int* __restrict__ cnt, const int* __restrict__ lo,
+                                               const int* __restrict__ segoff, const int64_t* __restrict__ rowptr_c,
+                                               uint8_t* __restrict__ flag, int64_t cap, double* __restrict__ geo) {
+  extern __shared__ double sh[];
+  const int M = a.M, nn = a.n_x * a.n_phi;
+  const int box = blockIdx.x, j = box / a.N, jp = box - j * a.N;
+  double* s_r1 = sh;
+  double* s_r2 = s_r1 + nn;
+  double* s_Q1 = s_r2 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_phi = s_Q2 + nn;
+  int64_t* s_cb = reinterpret_cast<int64_t*>(s_phi + PHI_STRIDE * a.n_phi);
+  int* s_pref = reinterpret_cast<int*>(s_cb + M);
+  int* s_lo = s_pref + M + 1;
+  __shared__ int s_w[4];
+  const int total = box_rows(a, box, cnt, lo, segoff, rowptr_c, s_pref, s_lo, s_cb, s_w);
+  if (total == 0) return;
+  fill_phi_table(a, j, jp, s_phi);
+  __syncthreads();
+  for (int nd = threadIdx.x; nd < nn; nd += blockDim.x) {
+    const Node n = box_node_at(a, s_phi, nd);
+    s_r1[nd] = n.r1;
+    s_r2[nd] = n.r2;
+    s_Q1[nd] = n.Q1;
+    s_Q2[nd] = n.Q2;
+  }
+  __syncthreads();
+  const int GS = 4 * nn + PHI_STRIDE * a.n_phi;   // s_r1 .. s_phi are contiguous
+  for (int x = threadIdx.x; x < GS; x += blockDim.x) geo[(size_t)box * GS + x] = sh[x];
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = cand_row(s_pref, M, e);
+    const int off = e - s_pref[i];
+    const int64_t cand = s_cb[i] + off;
+    if (cand >= cap) continue;
+    const int ip = s_lo[i] + off;
+    const double pa = a.pe[i], pb = a.pe[i + 1], ppa = a.pe[ip], ppb = a.pe[ip + 1];
+    bool f = false;
+    for (int nd = 0; nd < nn && !f; ++nd) {
+      const double r1 = s_r1[nd], r2 = s_r2[nd];
+      const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
+      const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
+      f = U > L;
+    }
+    flag[cand] = f ? 1 : 0;
+  }
+}
+
+// dest[e] = final block index of candidate e (rows of the final block-CSR at rowptr), -1 if dropped
+__global__ void __launch_bounds__(256) k_cand_dest(int64_t rows, const int64_t* __restrict__ rowptr_c,
+                                                   const uint8_t* __restrict__ flag, const int64_t* __restrict__ rowptr,
+                                                   int64_t* __restrict__ dest, int64_t cap_c) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  const int64_t b0 = min(rowptr_c[row], cap_c), b1 = min(rowptr_c[row + 1], cap_c);
+  int64_t out = rowptr[row];
+  for (int64_t base = b0; base < b1; base += 64) {
+    const int64_t e = base + lane;
+    const bool kept = e < b1 && flag[e];
+    const unsigned long long mask = __ballot(kept);
+    const int before = __popcll(mask & ((1ull << lane) - 1ull));
+    if (e < b1) dest[e] = kept ? out + before : -1;
+    out += __popcll(mask);
+  }
+}
+
+__device__ __forceinline__ double legendre_p(int k, double x) {
+  double p0 = 1.0, p1 = x, pk = (k == 0) ? 1.0 : x;
+  for (int m = 2; m <= k; ++m) {
+    const double p2 = ((2.0 * m - 1.0) * x * p1 - (m - 1.0) * p0) / m;
+    p0 = p1;
+    p1 = p2;
+    pk = p2;
+  }
+  return pk;
+}
+
+// One workgroup (4 wavefronts) per q-box. The moment weight of node nd and moment m is the product
+// of three small per-box tables, w_x P_k(x) * w_phi c^(a+1) s^(b+1) * zeta1^-(l'+1) zeta2^-(l+1); a
+// wavefront keeps the weights of its moment tiles (tiles wv, wv + 4, ...) for all nodes in
+// registers, as the B operand of v_mfma_f64_16x16x4f64. The kept candidates of the box are taken
+// 16 at a time: their F at every node into LDS (the A operand), the 16 x (16 NTW per wavefront)
+// moment integrals into LDS, then threads over (stored value t, 4 candidates) contract them with
+// t's nonzero coefficients and write norm * sum to the final arrays (consecutive threads,
+// consecutive values of a block). With CL the coefficient lists are staged in LDS once per box.
+// LDS: the weight tables and the F / moment tiles share one region (the tables are dead once the
+// weights are in registers).
+#define FZ_KS 16    // node steps of 4: up to 64 nodes
+#define FZ_LCH 256  // candidates listed per pass
+#define FZ_MT 18    // LDS row of one moment: 16 candidates + 2 (16-byte aligned, spreads the banks)
+struct alignas(16) FusedCoef {
+  double cv;
+  int m, pad;
+};
+// LDS layout of k_pbuild_fused (byte offsets). Per workgroup: p and q edges, the Gauss rules, the
+// w_x P_k(x) table and (cl) the coefficient lists; per box: the phi and node tables, then one
+// region used first for the weight tables (cos/sin powers, 1/zeta powers, node offsets) and then
+// for the candidate tiles (F [16][FST], moments [ntl 16][FZ_MT]), the candidate list and the row
+// prefix.
+struct FusedLds {
+  int nn, ntl, FST, EAB, LLP;
+  unsigned o_pe, o_qe, o_g, o_PW, o_nof, o_ce, o_cp, o_geo, o_uni, o_mom, o_nrm, o_ld, o_cb, o_pref, o_lo, o_li, o_lip;
+  int GS;   // node geometry doubles per box (as k_pflag stores them)
+  unsigned total;
+};
+struct LdsCursor {   // LDS offsets are 32-bit
+  unsigned o = 0;
+  __host__ __device__ unsigned take(unsigned bytes, unsigned al) {
+    o = (o + al - 1) / al * al;
+    const unsigned r = o;
+    o += bytes;
+    return r;
+  }
+};
+__host__ __device__ inline FusedLds fused_layout(const PBuildArgs& a, const FusedArgs& f, bool cl) {
+  FusedLds L;
+  L.nn = a.n_x * a.n_phi;
+  L.ntl = (a.nmom + 15) >> 4;
+  L.FST = 4 * FZ_KS + 1;
+  L.EAB = f.EA * f.EB;
+  L.LLP = f.LL * f.LP;
+  LdsCursor c;
+  L.o_pe = c.take((unsigned)(a.M + 1) * 8, 16);
+  L.o_qe = c.take((unsigned)(a.N + 1) * 8, 8);
+  L.o_g = c.take((unsigned)(2 * a.n_x + 2 * a.n_phi) * 8, 8);
+  L.o_PW = c.take((unsigned)a.n_x * f.KM * 8, 8);
+  L.o_nof = c.take((unsigned)L.nn * 8, 8);
+  L.GS = 4 * L.nn + PHI_STRIDE * a.n_phi;
+  L.o_ce = cl ? c.take((unsigned)f.ncoef * sizeof(FusedCoef), 16) : 0;
+  L.o_cp = cl ? c.take((unsigned)f.vpb * 8, 8) : 0;
+  L.o_geo = c.take((unsigned)L.GS * 8, 8);
+  const unsigned setup = (unsigned)(a.n_phi * L.EAB + L.nn * L.LLP) * 8;
+  const unsigned tiles = (unsigned)(16 * L.FST + L.ntl * 16 * FZ_MT) * 8;
+  L.o_uni = c.take(setup > tiles ? setup : tiles, 16);
+  L.o_mom = L.o_uni + (unsigned)(16 * L.FST) * 8;
+  L.o_nrm = c.take(FZ_LCH * 8, 8);
+  L.o_ld = c.take(FZ_LCH * 4, 16);
+  L.o_cb = c.take((unsigned)a.M * 8, 8);
+  L.o_pref = c.take((unsigned)(a.M + 1) * 4, 4);
+  L.o_lo = c.take((unsigned)a.M * 4, 4);
+  L.o_li = c.take(FZ_LCH * 4, 4);
+  L.o_lip = c.take(FZ_LCH * 4, 4);
+  L.total = c.o;
+  return L;
+}
+
+// Persistent: workgroup b takes the q-boxes b, b + gridDim.x, ... (4 wavefronts each). The moment
+// weight of node nd and moment m is the product of three tables, w_x P_k(x) (per workgroup) times
+// w_phi c^(a+1) s^(b+1) times zeta1^-(l'+1) zeta2^-(l+1) (per box); a wavefront keeps the weights
+// of its moment tiles (tiles wv, wv + 4, ...) for all nodes in registers, as the B operand of
+// v_mfma_f64_16x16x4f64. The kept candidates of the box are taken 16 at a time: their F at every
+// node into LDS (the A operand), the 16 x 16 NTW moment integrals of each wavefront into LDS
+// (moment-major), then threads over (stored value t, 4 candidates) contract them with t's nonzero
+// coefficients and write norm * sum to the final arrays (consecutive threads, consecutive values of
+// a block). The row data of the next box are loaded while the current box is computed.
+template <int NTW, bool CL, typename OT>
+__global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs f, const int* __restrict__ cnt,
+                                                      const int* __restrict__ lo, const int* __restrict__ segoff,
+                                                      const int64_t* __restrict__ rowptr_c,
+                                                      const double* __restrict__ geo,
+                                                      const int64_t* __restrict__ dest, int64_t cap_c,
+                                                      int32_t* __restrict__ col, OT* __restrict__ out, int64_t cap_b) {
+  extern __shared__ __align__(16) unsigned char shb[];
+  const FusedLds G = fused_layout(a, f, CL);
+  const int GS = G.GS;
+  const int M = a.M, N = a.N, nn = G.nn, nmom = a.nmom, ntl = G.ntl, FST = G.FST, EAB = G.EAB, LLP = G.LLP;
+  const int n_x = a.n_x, n_phi = a.n_phi, vpb = f.vpb;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, r16 = lane & 15, q4 = lane >> 4;
+  double* s_pe = reinterpret_cast<double*>(shb + G.o_pe);
+  double* s_qe = reinterpret_cast<double*>(shb + G.o_qe);
+  double* s_gx = reinterpret_cast<double*>(shb + G.o_g);
+  double* s_gwx = s_gx + n_x;
+  double* s_gp = s_gwx + n_x;
+  double* s_gwp = s_gp + n_phi;
+  double* s_PW = reinterpret_cast<double*>(shb + G.o_PW);          // [n_x][KM]
+  FusedCoef* s_ce = reinterpret_cast<FusedCoef*>(shb + G.o_ce);    // [ncoef]  (CL)
+  int2* s_cp = reinterpret_cast<int2*>(shb + G.o_cp);              // [vpb]    (CL)
+  int2* s_nof = reinterpret_cast<int2*>(shb + G.o_nof);            // [nn] table offsets of a node
+  double* s_r1 = reinterpret_cast<double*>(shb + G.o_geo);         // node geometry of the box, as
+  double* s_r2 = s_r1 + nn;                                         // k_pflag stored it
+  double* s_Q1 = s_r2 + nn;
+  double* s_Q2 = s_Q1 + nn;
+  double* s_phi = s_Q2 + nn;                                        // [n_phi][PHI_STRIDE]
+  double* s_CS = reinterpret_cast<double*>(shb + G.o_uni);         // [n_phi][EA EB]  (set-up)
+  double* s_RR = s_CS + n_phi * EAB;                                // [nn][LL LP]     (set-up)
+  double* s_F = reinterpret_cast<double*>(shb + G.o_uni);          // [16][FST]       (tiles)
+  double* s_mom = reinterpret_cast<double*>(shb + G.o_mom);        // [ntl 16][FZ_MT] (tiles)
+  double* s_nrm = reinterpret_cast<double*>(shb + G.o_nrm);
+  int* s_ld = reinterpret_cast<int*>(shb + G.o_ld);   // final block index (< cap_b < 2^31)
+  int64_t* s_cb = reinterpret_cast<int64_t*>(shb + G.o_cb);
+  int* s_pref = reinterpret_cast<int*>(shb + G.o_pref);
+  int* s_lo = reinterpret_cast<int*>(shb + G.o_lo);
+  int* s_li = reinterpret_cast<int*>(shb + G.o_li);
+  int* s_lip = reinterpret_cast<int*>(shb + G.o_lip);
+  __shared__ int s_w[4];
+  // box-independent tables, once per workgroup
+  for (int x = tid; x <= M; x += 256) s_pe[x] = a.pe[x];
+  for (int x = tid; x <= N; x += 256) s_qe[x] = a.qe[x];
+  for (int x = tid; x < n_x; x += 256) {
+    s_gx[x] = a.gx[x];
+    s_gwx[x] = a.gwx[x];
+  }
+  for (int x = tid; x < n_phi; x += 256) {
+    s_gp[x] = a.gp[x];
+    s_gwp[x] = a.gwp[x];
+  }
+  for (int x = tid; x < n_x * f.KM; x += 256) {
+    const int ia = x / f.KM, k = x - ia * f.KM;
+    s_PW[x] = a.gwx[ia] * legendre_p(k, a.gx[ia]);
+  }
+  if (CL) {
+    for (int x = tid; x < f.ncoef; x += 256) {
+      FusedCoef e;
+      e.cv = f.cv[x];
+      e.m = f.cm[x];
+      e.pad = 0;
+      s_ce[x] = e;
+    }
+    for (int x = tid; x < vpb; x += 256) s_cp[x] = make_int2(f.cptr[x], f.cptr[x + 1]);
+  }
+  for (int nd = tid; nd < nn; nd += 256) {
+    const int ia = nd / n_phi, ib = nd - ia * n_phi;
+    s_nof[nd] = make_int2(ia * f.KM, ib * EAB);
+  }
+  // moment keys of the wavefront's tiles
+  int fk[NTW], fe[NTW], fl[NTW];
+  bool fok[NTW];
+#pragma unroll
+  for (int nt = 0; nt < NTW; ++nt) {
+    const int m = (wv + 4 * nt) * 16 + r16;
+    fok[nt] = m < nmom;
+    fk[nt] = fok[nt] ? f.fkey[3 * m] : 0;
+    fe[nt] = fok[nt] ? f.fkey[3 * m + 1] : 0;
+    fl[nt] = fok[nt] ? f.fkey[3 * m + 2] : 0;
+  }
+  const int nbox = N * N;
+  // row data (thread = row; M <= 256) and node geometry (GS <= 3 * 256) of the first box
+  int rc = 0, rl = 0;
+  int64_t rb = 0;
+  double rg[3] = {0.0, 0.0, 0.0};
+  int box = blockIdx.x;
+  if (box < nbox && tid < M) {
+    rc = cnt[(size_t)box * M + tid];
+    rl = lo[(size_t)box * M + tid];
+    rb = rowptr_c[(size_t)(box / N) * M + tid] + segoff[(size_t)box * M + tid];
+  }
+  if (box < nbox) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (tid + 256 * k < GS) rg[k] = geo[(size_t)box * GS + tid + 256 * k];
+  }
+  __syncthreads();
+  for (; box < nbox; box += gridDim.x) {
+    const int j = box / N, jp = box - j * N;
+    // row prefix of this box from the registers
+    if (tid < M) {
+      s_lo[tid] = rl;
+      s_cb[tid] = rb;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (tid + 256 * k < GS) s_r1[tid + 256 * k] = rg[k];
+    int v = rc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, WARP);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) s_w[wv] = v;
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+      if (w < wv) off += s_w[w];
+      total += s_w[w];
+    }
+    if (tid < M) s_pref[tid] = off + v - rc;
+    if (tid == 0) s_pref[M] = total;
+    // the next box's row data and node geometry, in flight while this box is computed
+    {
+      const int nb = box + gridDim.x;
+      rc = 0;
+      rl = 0;
+      rb = 0;
+      if (nb < nbox && tid < M) {
+        rc = cnt[(size_t)nb * M + tid];
+        rl = lo[(size_t)nb * M + tid];
+        rb = rowptr_c[(size_t)(nb / N) * M + tid] + segoff[(size_t)nb * M + tid];
+      }
+      if (nb < nbox) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (tid + 256 * k < GS) rg[k] = geo[(size_t)nb * GS + tid + 256 * k];
+      }
+    }
+    if (total == 0) {   // uniform; the next box writes LDS only after a barrier
+      __syncthreads();
+      continue;
+    }
+    // 1/zeta powers of every (node, l, l') over all threads
+    for (int y = tid; y < nn * LLP; y += 256) {
+      const int nd = y / LLP, x = y - nd * LLP, l = x / f.LP, lp = x - l * f.LP;
+      const double r1 = s_r1[nd], r2 = s_r2[nd];
+      double w = 1.0;
+      for (int e = 0; e <= lp; ++e) w *= r1;
+      for (int e = 0; e <= l; ++e) w *= r2;
+      s_RR[y] = w;
+    }
+    for (int x = tid; x < n_phi * EAB; x += 256) {
+      const int ib = x / EAB, r = x - ib * EAB, ea = r / f.EB, eb = r - ea * f.EB;
+      const double* t = s_phi + ib * PHI_STRIDE;
+      double w = t[4] * s_gwp[ib];
+      for (int e = 0; e <= ea; ++e) w *= t[0];
+      for (int e = 0; e <= eb; ++e) w *= t[1];
+      s_CS[x] = w;
+    }
+    __syncthreads();
+    // B operands: wr[ks][nt] = weight of node 4 ks + q4, moment (wv + 4 nt) 16 + r16
+    double wr[FZ_KS][NTW];
+#pragma unroll
+    for (int ks = 0; ks < FZ_KS; ++ks) {   // branch-free: reads in range, padding selected to zero
+      const int nd = 4 * ks + q4;
+      const bool nok = nd < nn;
+      const int ndc = nok ? nd : 0;
+      const int2 no = s_nof[ndc];
+      const double* rr = s_RR + ndc * LLP;
+#pragma unroll
+      for (int nt = 0; nt < NTW; ++nt) {
+        const double w = s_PW[no.x + fk[nt]] * s_CS[no.y + fe[nt]] * rr[fl[nt]];
+        wr[ks][nt] = (nok && fok[nt]) ? w : 0.0;
+      }
+      __builtin_amdgcn_sched_barrier(0);   // bounds the table reads in flight (registers)
+    }
+    __syncthreads();   // the weight tables are overwritten by the candidate tiles below
+    const double dq = s_qe[j + 1] - s_qe[j], dqp = s_qe[jp + 1] - s_qe[jp];
+    for (int c0 = 0; c0 < total; c0 += FZ_LCH) {
+      // the kept candidates among [c0, c0 + FZ_LCH), in candidate order
+      const int e = c0 + tid;
+      bool kept = false;
+      int i = 0, ip = 0;
+      int64_t d = -1;
+      if (tid < FZ_LCH && e < total) {
+        i = cand_row(s_pref, M, e);
+        const int o = e - s_pref[i];
+        const int64_t cand = s_cb[i] + o;
+        ip = s_lo[i] + o;
+        if (cand < cap_c) {
+          d = dest[cand];
+          kept = d >= 0 && d < cap_b;
+        }
+      }
+      const unsigned long long mask = __ballot(kept);
+      if (lane == 0) s_w[wv] = __popcll(mask);
+      __syncthreads();
+      int pos = __popcll(mask & ((1ull << lane) - 1ull)), nf = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (w < wv) pos += s_w[w];
+        nf += s_w[w];
+      }
+      if (kept) {
+        s_li[pos] = i;
+        s_lip[pos] = ip;
+        s_ld[pos] = (int)d;
+        s_nrm[pos] = 1.0 / sqrt((s_pe[i + 1] - s_pe[i]) * dq * (s_pe[ip + 1] - s_pe[ip]) * dqp);
+        col[d] = jp * M + ip;
+      }
+      __syncthreads();
+      for (int r0 = 0; r0 < nf; r0 += 16) {
+        const int nr = min(16, nf - r0);
+        {  // F of candidate row tid / 16 at nodes tid % 16 + 16 k; nodes past nn stay zero
+          const int r = tid >> 4;
+          double pa = 0.0, pb = 0.0, ppa = 0.0, ppb = 0.0;
+          if (r < nr) {
+            const int ii = s_li[r0 + r], iip = s_lip[r0 + r];
+            pa = s_pe[ii];
+            pb = s_pe[ii + 1];
+            ppa = s_pe[iip];
+            ppb = s_pe[iip + 1];
+          }
+          for (int nd = tid & 15; nd < 4 * FZ_KS; nd += 16) {
+            double F = 0.0;
+            if (r < nr && nd < nn) {
+              const double r1 = s_r1[nd], r2 = s_r2[nd];
+              const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
+              const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
+              F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+            }
+            s_F[r * FST + nd] = F;
+          }
+        }
+        __syncthreads();
+        // branch-free: every node step and every tile of the wavefront (a tile past the last
+        // moment has zero weights), so that the accumulators stay in place between instructions
+        d4v acc[NTW];
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt) acc[nt] = d4v{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < FZ_KS; ++ks) {
+          const double av = s_F[r16 * FST + 4 * ks + q4];
+#pragma unroll
+          for (int nt = 0; nt < NTW; ++nt)
+            acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, wr[ks][nt], acc[nt], 0, 0, 0);
+        }
+        // moments times the block norm (rows past nr: F = 0, any norm)
+        double nrm4[4];
+#pragma unroll
+        for (int v4 = 0; v4 < 4; ++v4) nrm4[v4] = s_nrm[r0 + q4 + 4 * v4];
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt) {
+          const int tg = wv + 4 * nt;
+          if (tg < ntl) {
+#pragma unroll
+            for (int v4 = 0; v4 < 4; ++v4) s_mom[(tg * 16 + r16) * FZ_MT + q4 + 4 * v4] = acc[nt][v4] * nrm4[v4];
+          }
+        }
+        __syncthreads();
+        // items (rq, t) = rq * vpb + t over (4 candidates rq, stored value t), stepped without division
+        const int nq = (nr + 3) >> 2;
+        int rq = 0, t = tid;
+        while (t >= vpb) {
+          t -= vpb;
+          ++rq;
+        }
+        while (rq < nq) {
+          const int2 ce = CL ? s_cp[t] : make_int2(f.cptr[t], f.cptr[t + 1]);
+          const double* mb = s_mom + 4 * rq;
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+          for (int c = ce.x; c < ce.y; ++c) {
+            double cv;
+            int m;
+            if (CL) {
+              const FusedCoef ec = s_ce[c];
+              cv = ec.cv;
+              m = ec.m;
+            } else {
+              cv = f.cv[c];
+              m = f.cm[c];
+            }
+            const double2 x01 = *reinterpret_cast<const double2*>(mb + m * FZ_MT);
+            const double2 x23 = *reinterpret_cast<const double2*>(mb + m * FZ_MT + 2);
+            s0 = fma(cv, x01.x, s0);
+            s1 = fma(cv, x01.y, s1);
+            s2 = fma(cv, x23.x, s2);
+            s3 = fma(cv, x23.y, s3);
+          }
+          const int r = 4 * rq;
+          const int4 d4 = *reinterpret_cast<const int4*>(s_ld + r0 + r);
+          if (r < nr) out[(int64_t)d4.x * vpb + t] = (OT)s0;
+          if (r + 1 < nr) out[(int64_t)d4.y * vpb + t] = (OT)s1;
+          if (r + 2 < nr) out[(int64_t)d4.z * vpb + t] = (OT)s2;
+          if (r + 3 < nr) out[(int64_t)d4.w * vpb + t] = (OT)s3;
+          t += 256;
+          while (t >= vpb) {
+            t -= vpb;
+            ++rq;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+static size_t pflag_lds(const PBuildArgs& a) {
+  const int nn = a.n_x * a.n_phi;
+  return ((size_t)4 * nn + PHI_STRIDE * a.n_phi) * 8 + (size_t)a.M * 8 + (2 * (size_t)a.M + 1) * 4;
+}
+
+bool fused_build_fits(const PBuildArgs& a, const FusedArgs& f) {
+  const int nn = a.n_x * a.n_phi;
+  if (nn < 4 || nn > 4 * FZ_KS || nn % 4 != 0 || a.M < 1 || a.M > 256 || 4 * nn + PHI_STRIDE * a.n_phi > 768)
+    return false;
+  if (a.nmom < 1 || a.nmom > 256 || f.vpb < 1 || f.ncoef < 1) return false;
+  if (f.KM < 1 || f.EA < 1 || f.EB < 1 || f.LL < 1 || f.LP < 1) return false;
+  return fused_layout(a, f, false).total <= 64 * 1024 && pflag_lds(a) <= 64 * 1024;
+}
+
+hipError_t launch_pflag(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff, const int64_t* rowptr_c,
+                        uint8_t* flag, int64_t cap, double* geo, hipStream_t s) {
+  const size_t sh = pflag_lds(a);
+  if (sh > 64 * 1024 || !geo) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pflag, dim3(a.N * a.N), dim3(256), sh, s, a, cnt, lo, segoff, rowptr_c, flag, cap, geo);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_dest(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, const int64_t* rowptr,
+                            int64_t* dest, int64_t cap_c, hipStream_t s) {
+  hipLaunchKernelGGL(k_cand_dest, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, s, rows, rowptr_c, flag, rowptr,
+                     dest, cap_c);
+  return hipGetLastError();
+}
+
+template <int NTW, bool CL, typename OT>
+static hipError_t launch_fused_k(const PBuildArgs& a, const FusedArgs& f, const int* cnt, const int* lo,
+                                 const int* segoff, const int64_t* rowptr_c, const double* geo, const int64_t* dest,
+                                 int64_t cap_c, int32_t* col, OT* out, int64_t cap_b, size_t sh, hipStream_t s) {
+  auto kern = k_pbuild_fused<NTW, CL, OT>;
+  if (sh > 64 * 1024 &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) !=
+          hipSuccess)
+    return hipErrorInvalidValue;
+  // persistent: as many workgroups as fit on the device at once, at most one per box
+  int dev = 0, ncu = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), 256, sh) != hipSuccess)
+    return hipErrorInvalidValue;
+  const int nbox = a.N * a.N;
+  const int grid = std::max(1, std::min(nbox, std::max(1, occ) * ncu));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), sh, s, a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out,
+                     cap_b);
+  return hipGetLastError();
+}
+
+template <bool CL, typename OT>
+static hipError_t launch_fused_t(const PBuildArgs& a, const FusedArgs& f, const int* cnt, const int* lo,
+                                 const int* segoff, const int64_t* rowptr_c, const double* geo, const int64_t* dest,
+                                 int64_t cap_c, int32_t* col, OT* out, int64_t cap_b, hipStream_t s) {
+  const int ntw = ((a.nmom + 15) / 16 + 3) / 4;
+  const size_t sh = fused_layout(a, f, CL).total;
+  switch (ntw) {
+    case 1: return launch_fused_k<1, CL>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, sh, s);
+    case 2: return launch_fused_k<2, CL>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, sh, s);
+    case 3: return launch_fused_k<3, CL>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, sh, s);
+    case 4: return launch_fused_k<4, CL>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, sh, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename OT>
+static hipError_t launch_fused_o(const PBuildArgs& a, const FusedArgs& f, const int* cnt, const int* lo,
+                                 const int* segoff, const int64_t* rowptr_c, const double* geo, const int64_t* dest,
+                                 int64_t cap_c, int32_t* col, OT* out, int64_t cap_b, hipStream_t s) {
+  // the coefficient lists go to LDS when the device gives a workgroup enough of it
+  int dev = 0, maxsh = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return hipErrorInvalidValue;
+  const bool cl = fused_layout(a, f, true).total <= (size_t)maxsh;
+  return cl ? launch_fused_t<true>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, s)
+            : launch_fused_t<false>(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, out, cap_b, s);
+}
+
+hipError_t launch_pbuild_fused(const PBuildArgs& a, const FusedArgs& f, const int* cnt, const int* lo,
+                               const int* segoff, const int64_t* rowptr_c, const double* geo, const int64_t* dest,
+                               int64_t cap_c, int32_t* col, double* val64, float* val32, int64_t cap_b,
+                               hipStream_t s) {
+  if (!fused_build_fits(a, f) || (!val64 == !val32) || !geo || cap_b > 0x7fffffff)
+    return hipErrorInvalidValue;
+  return val64 ? launch_fused_o(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, val64, cap_b, s)
+               : launch_fused_o(a, f, cnt, lo, segoff, rowptr_c, geo, dest, cap_c, col, val32, cap_b, s);
 }
 
 // ------------------------------------------------------------------ block-CSR product, many channels

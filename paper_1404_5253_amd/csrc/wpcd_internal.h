@@ -156,6 +156,35 @@ hipError_t launch_pbuild(const PBuildArgs& a, const int* cnt, const int* lo, con
 hipError_t launch_pbuild_general(const PBuildArgs& a, const double* Ct, const int* cnt, const int* lo, const int* segoff,
                                  const int64_t* rowptr_c, int64_t ncand, int32_t* col_c, double* mom, double* norm,
                                  double* val_c, uint8_t* flag, hipStream_t s);
+// Fused many-moment quadrature. The stored set is decided first from the node geometry alone
+// (launch_pflag: a candidate is kept when F > 0 at one of its nodes), the final block-CSR offsets
+// follow from it (rowcount, scan, launch_cand_dest: the final block index of every kept
+// candidate, -1 otherwise), and launch_pbuild_fused then computes each kept block once, per
+// q-box: the moment integrals on FP64 MFMA tiles (F of 16 candidates x 4 nodes times the moment
+// weights of 4 nodes x 16 moments), contracted with the nonzero recoupling coefficients of every
+// stored value, written to col / val of the final arrays.
+struct FusedArgs {
+  int KM, EA, EB, LL, LP;   // factor tables: P_k (k < KM), cos^(a+1) sin^(b+1) (a < EA, b < EB),
+                            // zeta1^-(l'+1) zeta2^-(l+1) (l < LL, l' < LP)
+  const int* fkey;          // [nmom][3]: k, a * EB + b, l * LP + l' of every moment
+  const int* cptr;          // [vpb + 1]: coefficients of stored value t at [cptr[t], cptr[t + 1])
+  const int* cm;            // moment index of each coefficient, ascending within a value
+  const double* cv;         // the coefficient C[g][g'][m]
+  int ncoef;                // entries of cm / cv
+  int vpb;                  // stored values per block
+};
+// Shape limits of the fused kernel (nodes a multiple of 4 up to 64, up to 256 moments, LDS).
+bool fused_build_fits(const PBuildArgs& a, const FusedArgs& f);
+// geo [N N][fused_geo_doubles(a)]: node geometry of every box with candidates, for the fused kernel.
+hipError_t launch_pflag(const PBuildArgs& a, const int* cnt, const int* lo, const int* segoff,
+                        const int64_t* rowptr_c, uint8_t* flag, int64_t cap, double* geo, hipStream_t s);
+inline int fused_geo_doubles(const PBuildArgs& a) { return 4 * a.n_x * a.n_phi + 5 * a.n_phi; }
+hipError_t launch_cand_dest(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, const int64_t* rowptr,
+                            int64_t* dest, int64_t cap_c, hipStream_t s);
+hipError_t launch_pbuild_fused(const PBuildArgs& a, const FusedArgs& f, const int* cnt, const int* lo,
+                               const int* segoff, const int64_t* rowptr_c, const double* geo, const int64_t* dest,
+                               int64_t cap_c, int32_t* col, double* val64, float* val32, int64_t cap_b,
+                               hipStream_t s);
 hipError_t launch_rowcount(int64_t rows, const int64_t* rowptr_c, const uint8_t* flag, int64_t* rowcnt,
                            int64_t cap, hipStream_t s);
 // Reads candidates below cap_c, writes kept blocks below cap_b.

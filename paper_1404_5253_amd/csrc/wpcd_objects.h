@@ -95,6 +95,12 @@ struct wp_lattice {
   int vpb = 0;
   std::vector<int> pk_src, pk_pos;
   DBuf<int> d_pkt, d_pkpos, d_pksrc;
+  // fused many-moment build (FusedArgs): factor-table extents, per moment its table offsets, per
+  // stored value its nonzero coefficients; fz_ok when the shape fits the fused kernel
+  FusedArgs fz{};
+  bool fz_ok = false;
+  DBuf<int> d_fkey, d_fcptr, d_fcm;
+  DBuf<double> d_fcv;
 };
 inline PackView pk_view(const wp_lattice* L) { return PackView{L->pk.npk, L->d_pkt.p, L->d_pkpos.p}; }
 
