@@ -87,28 +87,35 @@ def batched_energies_section(wp, torch, L, reps=3):
     tolerance (and Arnoldi cycle length) is chosen by the autotuner on a separate calibration
     draw of 64 energies (seed 4321) against the converged FP64 amplitudes, then timed on the
     bench energies, where the error against the converged FP64 amplitudes is reported."""
-    from paper_1404_5253_amd.tune import tune
+    from paper_1404_5253_amd.tune import LAUNCH_DEFAULTS, solve_amplitudes, tune
     Es = workloads.batched_energies()
     Ecal = workloads.batched_energies(seed=4321)
     best, _ = tune(L, Ecal, target=AMP_TARGET, sync=torch.cuda.synchronize)
     out = {"autotuned": {k: {kk: (float(vv) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                          for k, v in best.items()}}
     amps = {}
-    runs = [("fp64", "fp64", 1e-12, 0)] + [(f"{m}_at_1e-6", m, v["tol"], v["refine_every"]) for m, v in best.items()]
-    for label, mode, tol, cyc in runs:
-        L.solve(Es, mode, tol=tol, refine_every=cyc, allow_noconv=True)   # warm-up
+    runs = [("fp64", "fp64", dict(LAUNCH_DEFAULTS, tol=1e-12, refine_every=0))] + \
+           [(f"{m}_at_1e-6", m, v) for m, v in best.items()]
+    for label, mode, cfg in runs:
+        launch = {k: cfg[k] for k in ("graph", "step_tile", "spmm_cols")}
+        run = lambda it=False: solve_amplitudes(L, Es, mode, cfg["tol"], cfg["refine_every"], cfg["width"], iters=it,
+                                                **launch)
+        run()   # warm-up (and graph capture)
         torch.cuda.synchronize()
-        wp.wp_profile_reset()
-        wp.wp_profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(reps):
-            sol = L.solve(Es, mode, tol=tol, refine_every=cyc, allow_noconv=True)
+            A, it = run(True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        # kernel breakdown from one more pass with events around every launch (launched, not replayed)
+        wp.wp_profile_reset()
+        wp.wp_profile_enable(True)
+        run()
+        torch.cuda.synchronize()
         wp.wp_profile_enable(False)
-        out[f"kernels_ms_per_batch_{label}"] = {k: round(v[1] / reps, 3) for k, v in wp.wp_profile_read().items()}
-        out[f"iters_{label}"] = int(np.max([sol.amplitude(k)["iters"][0] for k in range(len(Es))]))
-        amps[label] = np.array([sol.amplitude(k)["A"][0, 0] for k in range(len(Es))])
+        out[f"kernels_ms_per_batch_{label}"] = {k: round(v[1], 3) for k, v in wp.wp_profile_read().items()}
+        out[f"iters_{label}"] = int(it)
+        amps[label] = A[:, 0]
         out[f"solves_per_s_{label}"] = len(Es) / dt
         out[f"ms_per_batch_{label}"] = dt * 1e3
     out["n_energies"] = len(Es)
@@ -264,8 +271,21 @@ def swave_section(wp, torch, V_R, reps=10):
     torch.cuda.synchronize()
     wp.wp_profile_enable(False)
     prof = wp.wp_profile_read()
+    # the single-energy FP64 solves again, launched and replayed from HIP graphs (term chunks)
+    graph_cmp = {}
+    for g in (False, True):
+        for L in lats:
+            L.solve([E], "fp64", graph=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for L in lats:
+                L.solve([E], "fp64", graph=g)
+        torch.cuda.synchronize()
+        graph_cmp["graph" if g else "launched"] = 2 * reps / (time.perf_counter() - t0)
     elems = sum(L.perm_stats["nnz"] for L in lats)
     return dict(M=M, N=N, E_lab=E, systems=["doublet J=1/2+ (2 ch)", "quartet J=3/2+ (1 ch)"],
+                solves_per_s_fp64_launched_vs_graph=graph_cmp,
                 P_elements=elems, P_elements_per_s=elems * reps / times["build"], ms_per_step=dt * 1e3,
                 build_ms_per_step=times["build"] / reps * 1e3, solve_ms_per_step=times["solve"] / reps * 1e3,
                 solves_per_s_fp64=2 * reps / times["solve"],

@@ -204,14 +204,28 @@ wp_status perm_matrix_export(const wp_lattice* lat, int64_t* row_ptr, int32_t* c
  *                        one correction gains about as much as the FP32 data allow.
  * max_iter: operator applications per solve (<= 1000). Returns WP_ENOCONV (solution still
  * returned) if any solve was not accepted.
+ * Launch choices (all 0: the library's defaults; none changes what is computed, only the kernel
+ * variant or how launches are issued, so results of one choice are reproducible bit for bit):
+ *   graph:     1 replays every full chunk of 8 FP64 terms (FP64 mode) and every refinement
+ *              cycle's Arnoldi sweep (mixed modes) from a HIP graph captured once per call
+ *              shape and kept by the lattice; ignored while wp_profile is enabled and by the
+ *              batch API.
+ *   step_tile: FP64 step kernel, one of WP_STEP_*; a choice whose tiles do not fit the lattice
+ *              (LDS, rows) falls back to the default.
+ *   spmm_cols: more than 4 channels: the column count of a call from which the block-CSR
+ *              products run lanes over the columns instead of passes of 4 (default 16).
  */
 enum { WP_SOLVE_FP64 = 0, WP_SOLVE_MIXED = 1, WP_SOLVE_MIXED_SPLIT = 2 };
+enum { WP_STEP_AUTO = 0, WP_STEP_MFMA8 = 1, WP_STEP_MFMA16 = 2, WP_STEP_VALU = 3, WP_STEP_ROWS = 4 };
 typedef struct {
   int mode;
   double tol;
   double accept;
   int max_iter;
   int refine_every;
+  int graph;
+  int step_tile;
+  int spmm_cols;
 } wp_solve_opts;
 
 wp_status faddeev_solve(wp_lattice* lat, int n_E, const double* E_lab, const wp_solve_opts* opts,

@@ -65,7 +65,13 @@ class _PermStats(C.Structure):
 
 class _SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("accept", C.c_double),
-                ("max_iter", C.c_int), ("refine_every", C.c_int)]
+                ("max_iter", C.c_int), ("refine_every", C.c_int), ("graph", C.c_int), ("step_tile", C.c_int),
+                ("spmm_cols", C.c_int)]
+
+
+WP_STEP_AUTO, WP_STEP_MFMA8, WP_STEP_MFMA16, WP_STEP_VALU, WP_STEP_ROWS = 0, 1, 2, 3, 4
+STEP_TILES = {"auto": WP_STEP_AUTO, "mfma8": WP_STEP_MFMA8, "mfma16": WP_STEP_MFMA16, "valu": WP_STEP_VALU,
+              "rows": WP_STEP_ROWS}
 
 
 _P = C.c_void_p
@@ -184,9 +190,9 @@ def perm_matrix_build(lat, precision=WP_P_FP64, stream=None):
 
 
 def faddeev_solve(lat, E_lab, mode=WP_SOLVE_FP64, tol=1e-12, accept=1e-7, max_iter=200, refine_every=0,
-                  stream=None, allow_noconv=False):
+                  stream=None, allow_noconv=False, graph=0, step_tile=0, spmm_cols=0):
     E = np.ascontiguousarray(np.atleast_1d(E_lab), dtype=np.float64)
-    o = _SolveOpts(mode, tol, accept, max_iter, refine_every)
+    o = _SolveOpts(mode, tol, accept, max_iter, refine_every, graph, step_tile, spmm_cols)
     h = _P()
     st = _lib.faddeev_solve(lat, len(E), _dptr(E), C.byref(o), stream, C.byref(h))
     if st == WP_ENOCONV and allow_noconv and h.value:
@@ -332,11 +338,12 @@ class Lattice:
         return rp, col[:nb], val[:nb * self.nch * self.nch].reshape(nb, self.nch, self.nch)
 
     def solve(self, E_lab, mode="fp64", tol=1e-12, accept=1e-7, max_iter=200, refine_every=0, stream=None,
-              allow_noconv=False):
+              allow_noconv=False, graph=False, step_tile="auto", spmm_cols=0):
         m = SOLVE_MODES[mode]
         E = np.atleast_1d(E_lab)
         h, ok = faddeev_solve(self.h, E, m, tol, accept, max_iter, refine_every,
-                              stream if stream is not None else current_stream(), allow_noconv)
+                              stream if stream is not None else current_stream(), allow_noconv,
+                              int(bool(graph)), STEP_TILES[step_tile], int(spmm_cols))
         return Solution(h, len(E), ok)
 
     def __del__(self, _lib=_lib):

@@ -81,6 +81,9 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   if (b->mixed) {
     if (wp_status st = ensure_mixed(L, nullptr)) return st;
     if (wp_status st = b->mw.make(L, B, b->m, o->mode == WP_SOLVE_MIXED_SPLIT)) return st;
+    b->mw.step_tile = o->step_tile;
+    b->mw.spmm_cols = o->spmm_cols;
+    b->mw.graph = false;   // the batch's active columns change between cycles
     MixedWork& w = b->mw;
     for (auto* p : {&w.dG64, &w.db, &w.dy}) HIPCHECK(hipMemset(p->p, 0, w.DB * sizeof(double2)));
     HIPCHECK(hipMemset(w.dG32.p, 0, w.DB * sizeof(float2)));
@@ -137,7 +140,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0,
                                c0 + nf));
     HIPCHECK(launch_spmv_f32v_f64x(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, st, c0,
-                                   c0 + nf, spmv_order(L), pk_view(L)));
+                                   c0 + nf, spmv_order(L), pk_view(L, b->o.spmm_cols)));
     HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c0 + nf, st));
     S.mc.assign(nf, MixedCol());
   } else {
@@ -146,7 +149,7 @@ extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
     HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
                                c0 + nf));
     HIPCHECK(launch_spmv_f64(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st, c0, c0 + nf,
-                             spmv_order(L), pk_view(L)));
+                             spmv_order(L), pk_view(L, b->o.spmm_cols)));
     S.cs.resize(nf);
     for (auto& c : S.cs) {
       c.w.resize(nf);
@@ -229,9 +232,10 @@ extern "C" wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, in
   if (b->mixed) return step_mixed(b, st, n_done, done_slots);
   for (int t = 0; t < terms; ++t) {
     RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, b->dG.p, b->dacap.p, b->dj0.p, b->dfin.p, nf, (int64_t)t * B * nf};
+    ro.tile = b->o.step_tile;
     WP_LAUNCH("step64", st, launch_step64(ro, L->d_W.p, b->dy.p, b->ds.p, st));
     WP_LAUNCH("spmv64", st, launch_spmv_f64((int64_t)M * N, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p,
-                                            b->dy.p, st, 0, -1, spmv_order(L), pk_view(L)));
+                                            b->dy.p, st, 0, -1, spmv_order(L), pk_view(L, b->o.spmm_cols)));
   }
   HIPCHECK(hipMemcpyAsync(b->hcap.data(), b->dacap.p, (size_t)terms * B * nf * sizeof(double2), hipMemcpyDeviceToHost,
                           st));

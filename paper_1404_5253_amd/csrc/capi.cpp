@@ -76,6 +76,8 @@ wpcd::ProfScope::~ProfScope() {
   p.recs.push_back({name, a, b});
 }
 
+bool wpcd::profiling_enabled() { return prof().on; }
+
 extern "C" wp_status wp_profile_enable(int on) {
   prof().on = on != 0;
   return WP_OK;
@@ -959,7 +961,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   DevAlloc* al = &L->al;
   if (!g1_work(L, nE, g1w)) return fail(WP_ENOMEM, "device allocation (G1 work list)");
   if (!grow(dG, al, D * B) || !grow(dy, al, D * B) || !grow(ds, al, D * B) ||
-      !grow(dacap, al, (size_t)(max_iter + chunk) * B * nfin) || !grow(dj0, al, B) || !grow(dg0, al, B) ||
+      !grow(dacap, al, (size_t)2 * chunk * B * nfin) || !grow(dj0, al, B) || !grow(dg0, al, B) ||
       !grow(dfin, al, nfin) || !grow(dE, al, nE))
     return fail(WP_ENOMEM, "device allocation (solve vectors)");
   HIPCHECK(hipMemcpyAsync(dE.p, Etot.data(), nE * sizeof(double), hipMemcpyHostToDevice, s));
@@ -970,7 +972,7 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
   const double* val = L->d_val64.p;
   if (!val) return fail(WP_ENOTREADY, "FP64 solve needs P0 built with WP_P_FP64");
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, dj0.p, dg0.p, ds.p, s));
-  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, order, pk_view(L)));
+  HIPCHECK(launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1, order, pk_view(L, o.spmm_cols)));
   std::vector<ColState> cs(B);
   for (auto& c : cs) {
     c.w.resize(nfin);
@@ -1029,17 +1031,43 @@ static wp_status solve_fp64(wp_lattice* L, const std::vector<double>& Elab, cons
     if (need < 0) return chunk;
     return std::max(2, std::min(chunk, need - in_flight + 1));
   };
-  auto enqueue = [&](int slot, int want) -> wp_status {
-    const int T = std::min(want, max_iter - launched);
+  // T terms into capture slot `slot` (rows slot * chunk + t of dacap), then their copy to the
+  // slot's pinned staging
+  auto record_chunk = [&](hipStream_t st, int slot, int T) -> hipError_t {
     for (int t = 0; t < T; ++t) {
       RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, dG.p, dacap.p, dj0.p, dfin.p, nfin,
-                 (int64_t)(launched + t) * B * nfin};
-      WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, dy.p, ds.p, s));
-      WP_LAUNCH("spmv64", s, launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, s, 0, -1,
-                                             order, pk_view(L)));
+                 (int64_t)(slot * chunk + t) * B * nfin};
+      ro.tile = o.step_tile;
+      hipError_t e;
+      {
+        ProfScope ps("step64", st);
+        e = launch_step64(ro, L->d_W.p, dy.p, ds.p, st);
+      }
+      if (e != hipSuccess) return e;
+      {
+        ProfScope ps("spmv64", st);
+        e = launch_spmv_f64(R, nch, B, L->d_rowptr.p, L->d_col.p, val, ds.p, dy.p, st, 0, -1, order,
+                            pk_view(L, o.spmm_cols));
+      }
+      if (e != hipSuccess) return e;
     }
-    HIPCHECK(hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)launched * B * nfin,
-                            (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, s));
+    return hipMemcpyAsync(pin + slot * per_chunk, dacap.p + (size_t)slot * per_chunk,
+                          (size_t)T * B * nfin * sizeof(double2), hipMemcpyDeviceToHost, st);
+  };
+  // full chunks replayed from a graph (o.graph), kept by the work space between calls
+  const bool use_graph = o.graph == 1 && !profiling_enabled();
+  auto enqueue = [&](int slot, int want) -> wp_status {
+    const int T = std::min(want, max_iter - launched);
+    if (use_graph && T == chunk) {
+      const std::vector<int64_t> key{slot, M, N, nch, B, nfin, chunk, o.step_tile, o.spmm_cols,
+                                     (int64_t)dG.p, (int64_t)dy.p, (int64_t)ds.p, (int64_t)dacap.p, (int64_t)dj0.p,
+                                     (int64_t)dfin.p, (int64_t)pin, (int64_t)L->d_O.p, (int64_t)L->d_W.p,
+                                     (int64_t)L->d_wave.p, (int64_t)L->d_rowptr.p, (int64_t)L->d_col.p,
+                                     (int64_t)val, (int64_t)order, (int64_t)L->d_pkt.p, (int64_t)L->d_pkpos.p};
+      HIPCHECK(graph_run(L, ws.chunk_graph[slot], key, s, [&](hipStream_t st) { return record_chunk(st, slot, T); }));
+    } else {
+      HIPCHECK(record_chunk(s, slot, T));
+    }
     HIPCHECK(hipEventRecord(ev[slot], s));
     T_of[slot] = T;
     launched += T;

@@ -1661,10 +1661,24 @@ hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, do
     const int Mp = (r.M + 15) / 16 * 16;
     const size_t lim = 64 * 1024;
     int ct = (step64m_lds(Mp, 2) <= lim && (int64_t)((ncol + 15) / 16) * r.nch >= 256) ? 2 : 1;
-    // a small grid (one energy on few channels) stays with the VALU version, whose wavefronts
-    // run their rows in parallel instead of one MFMA chain per tile
-    if (step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch < 256 && Mp / 4 <= STEP64R_MAXK &&
-        step64m_lds(Mp, 1) <= lim) {
+    // an explicit choice (WP_STEP_*) that fits the lattice replaces the choice by grid size
+    const bool rows_fit = Mp / 4 <= STEP64R_MAXK && step64m_lds(Mp, 1) <= lim;
+    bool use_rows = (int64_t)((ncol + 7) / 8) * r.nch < 256 && rows_fit && step64m_lds(Mp, ct) <= lim;
+    bool use_m = !use_rows && step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch >= 256;
+    if (r.tile == WP_STEP_ROWS && rows_fit) {
+      use_rows = true;
+      use_m = false;
+    } else if ((r.tile == WP_STEP_MFMA8 || r.tile == WP_STEP_MFMA16) &&
+               step64m_lds(Mp, r.tile == WP_STEP_MFMA16 ? 2 : 1) <= lim) {
+      use_rows = false;
+      use_m = true;
+      ct = r.tile == WP_STEP_MFMA16 ? 2 : 1;
+    } else if (r.tile == WP_STEP_VALU && (size_t)2 * r.M * 2 * sizeof(double2) <= lim) {
+      use_rows = use_m = false;
+    }
+    // a small grid (one energy on few channels) takes k_step64r, whose wavefronts run the row
+    // tiles of a column tile in parallel instead of one MFMA chain per tile
+    if (use_rows) {
       // small grid: all row tiles of a column tile at once, A fragments preloaded
       dim3 grid((ncol + 7) / 8, r.nch), block(64 * (Mp / 16));
       const size_t sh = step64m_lds(Mp, 1);
@@ -1680,7 +1694,7 @@ hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, do
       }
       return hipGetLastError();
     }
-    if (step64m_lds(Mp, ct) <= lim && (int64_t)((ncol + 7) / 8) * r.nch >= 256) {
+    if (use_m) {
       dim3 grid((ncol + 8 * ct - 1) / (8 * ct), r.nch);
       if (ct == 2) hipLaunchKernelGGL(k_step64m<2>, grid, dim3(256), step64m_lds(Mp, 2), s, r, W, y, s_out, Mp);
       else hipLaunchKernelGGL(k_step64m<1>, grid, dim3(256), step64m_lds(Mp, 1), s, r, W, y, s_out, Mp);
@@ -1692,6 +1706,7 @@ hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, do
   // wavefront then share fewer rows of O, so its loads hit fewer cache lines)
   int tc = 16;
   while (tc > 2 && ((size_t)2 * r.M * tc * sizeof(double2) > 64 * 1024 || (int64_t)(ncol / tc) * r.nch < 256)) tc >>= 1;
+  // (the large-M branch is also the one an explicit WP_STEP_VALU takes)
   const size_t shmem = (size_t)2 * r.M * tc * sizeof(double2);
   if (shmem > 64 * 1024) return hipErrorInvalidValue;
   dim3 grid((ncol + tc - 1) / tc, r.nch);
@@ -2943,7 +2958,7 @@ hipError_t launch_spmv_gen(int64_t rows, int nch, int B, const int64_t* rowptr, 
     return hipErrorInvalidValue;
   // the choice depends on B and nch only, so every launch on a given batch width sums in one order
   const dim3 grid((unsigned)spmv_blocks(rows, order));
-  if (B >= 16 && nch <= NCMAX) {   // wider blocks take the few-column kernel, four columns per pass
+  if (B >= pk.spmm_min && nch <= NCMAX) {   // wide calls: lanes over the columns
     dim3 g2 = grid;
     g2.y = (cb1 - cb0 + 63) / 64;
     hipLaunchKernelGGL((k_spmm_pk<VT, XT, AT>), g2, dim3(256), 0, s, rows, nch, B, cb0, cb1, rowptr, col, val, pk.npk,

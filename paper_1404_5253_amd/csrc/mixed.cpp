@@ -142,30 +142,70 @@ wp_status wpcd::mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const s
   wp_lattice* L = w.L;
   const int M = L->M, N = L->N, nch = L->nch, B = w.B, m = w.m, nfin = w.nfin;
   const int64_t D = w.D, DB = w.DB, R = w.R;
-  if (y_is_zero) {
-    HIPCHECK(hipMemcpyAsync(w.dr.p, w.db.p, DB * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  // the Arnoldi sweep: residual (b itself on the first cycle), its norm and scaling, m Arnoldi
+  // steps; replayed from a graph when the call asks for one
+  auto record_sweep = [&](hipStream_t st) -> hipError_t {
+    hipError_t e = hipSuccess;
+    if (y_is_zero) {
+      e = hipMemcpyAsync(w.dr.p, w.db.p, DB * sizeof(double2), hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    } else {
+      RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, w.dG64.p, nullptr, w.dj0.p, w.dfin.p, nfin, 0};
+      ro.tile = w.step_tile;
+      {
+        ProfScope ps("step64", st);
+        e = launch_step64(ro, L->d_W.p, w.dy.p, w.ds64.p, st);
+      }
+      if (e != hipSuccess) return e;
+      {
+        ProfScope ps("spmv_f32v_f64x", st);
+        e = launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.dKy.p, st, 0, -1,
+                                  spmv_order(L), pk_view(L, w.spmm_cols));
+      }
+      if (e != hipSuccess) return e;
+      {
+        ProfScope ps("residual", st);
+        e = launch_residual(DB, w.db.p, w.dy.p, w.dKy.p, w.dr.p, st);
+      }
+      if (e != hipSuccess) return e;
+    }
+    if ((e = launch_norm2_f64(D, B, w.dr.p, w.part.p, kNblk, w.nrm.p, st)) != hipSuccess) return e;
+    if ((e = launch_scale_d2f(D, B, w.nrm.p, w.dr.p, w.V.p, w.scl.p, st)) != hipSuccess) return e;
+    ArnoldiArgs aa{R,         nch,     B,      m,    0,          L->d_rowptr.p, L->d_col.p, L->d_val32.p,
+                   spmv_order(L), w.V.p, DB,    w.scl.p, w.H.p, w.part.p, kNblk, pk_view(L, w.spmm_cols)};
+    RotArgsMixed rm{M,          N, nch, B, L->d_Ob.p, w.split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p,
+                    w.split ? L->d_Wb_lo.p : nullptr, L->Mp, L->d_wave.p, w.dG32.p, nullptr};
+    for (int j = 0; j < m; ++j) {
+      aa.j = j;
+      rm.yscale = w.scl.p + (size_t)j * B;
+      {
+        ProfScope ps("step_bf16", st);
+        e = launch_step_bf16(rm, w.V.p + (size_t)j * DB, w.t32.p, st);
+      }
+      if (e != hipSuccess) return e;
+      if ((e = launch_arnoldi_product(aa, w.t32.p, w.kv32.p, st)) != hipSuccess) return e;   // profiled inside
+      {
+        ProfScope ps("arnoldi_orth", st);
+        e = launch_arnoldi_orth(aa, st);
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  if (w.graph && !profiling_enabled()) {
+    const std::vector<int64_t> key{
+        y_is_zero,          M, N, nch, B, m, w.split, w.step_tile, w.spmm_cols, (int64_t)w.dr.p, (int64_t)w.db.p,
+        (int64_t)w.dy.p,    (int64_t)w.ds64.p, (int64_t)w.dKy.p, (int64_t)w.dG64.p, (int64_t)w.dG32.p,
+        (int64_t)w.dj0.p,   (int64_t)w.dfin.p, (int64_t)w.part.p, (int64_t)w.nrm.p, (int64_t)w.V.p,
+        (int64_t)w.scl.p,   (int64_t)w.H.p, (int64_t)w.t32.p, (int64_t)w.kv32.p, (int64_t)L->d_O.p,
+        (int64_t)L->d_W.p,  (int64_t)L->d_wave.p, (int64_t)L->d_Ob.p, (int64_t)L->d_Ob_lo.p, (int64_t)L->d_Wb.p,
+        (int64_t)L->d_Wb_lo.p, (int64_t)L->d_rowptr.p, (int64_t)L->d_col.p, (int64_t)L->d_val32.p,
+        (int64_t)spmv_order(L), (int64_t)L->d_pkt.p, (int64_t)L->d_pkpos.p};
+    HIPCHECK(graph_run(L, w.sweep_graph[y_is_zero ? 0 : 1], key, s, record_sweep));
   } else {
-    RotArgs ro{M, N, nch, B, L->d_O.p, L->d_wave.p, w.dG64.p, nullptr, w.dj0.p, w.dfin.p, nfin, 0};
-    WP_LAUNCH("step64", s, launch_step64(ro, L->d_W.p, w.dy.p, w.ds64.p, s));
-    WP_LAUNCH("spmv_f32v_f64x", s,
-              launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.dKy.p, s, 0, -1,
-                                    spmv_order(L), pk_view(L)));
-    WP_LAUNCH("residual", s, launch_residual(DB, w.db.p, w.dy.p, w.dKy.p, w.dr.p, s));
+    HIPCHECK(record_sweep(s));
   }
-  HIPCHECK(launch_norm2_f64(D, B, w.dr.p, w.part.p, kNblk, w.nrm.p, s));
-  HIPCHECK(launch_scale_d2f(D, B, w.nrm.p, w.dr.p, w.V.p, w.scl.p, s));
   HIPCHECK(hipMemcpyAsync(w.hn.data(), w.nrm.p, B * sizeof(double2), hipMemcpyDeviceToHost, s));
-  ArnoldiArgs aa{R,         nch,     B,      m,    0,          L->d_rowptr.p, L->d_col.p, L->d_val32.p,
-                 spmv_order(L), w.V.p, DB,    w.scl.p, w.H.p, w.part.p, kNblk, pk_view(L)};
-  RotArgsMixed rm{M,          N, nch, B, L->d_Ob.p, w.split ? L->d_Ob_lo.p : nullptr, L->d_Wb.p,
-                  w.split ? L->d_Wb_lo.p : nullptr, L->Mp, L->d_wave.p, w.dG32.p, nullptr};
-  for (int j = 0; j < m; ++j) {
-    aa.j = j;
-    rm.yscale = w.scl.p + (size_t)j * B;
-    WP_LAUNCH("step_bf16", s, launch_step_bf16(rm, w.V.p + (size_t)j * DB, w.t32.p, s));
-    HIPCHECK(launch_arnoldi_product(aa, w.t32.p, w.kv32.p, s));   // profiled inside, per kernel
-    WP_LAUNCH("arnoldi_orth", s, launch_arnoldi_orth(aa, s));
-  }
   HIPCHECK(hipMemcpyAsync(w.hH.data(), w.H.p, w.hH.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipMemcpyAsync(w.hsc.data(), w.scl.p, w.hsc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
@@ -245,6 +285,9 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
   MixedWork& w = ws_lock.owns_lock() ? *L->mws : own;
   StreamDrain drain{s};   // idle stream before the work object is released or handed on
   if (wp_status st = w.make(L, B, m, o.mode == WP_SOLVE_MIXED_SPLIT)) return st;
+  w.step_tile = o.step_tile;
+  w.spmm_cols = o.spmm_cols;
+  w.graph = o.graph == 1;
   DBuf<int>& dg0 = w.dg0;
   DBuf<double>& dE = w.dE;
   DBuf<int64_t>& g1w = w.g1w;
@@ -260,7 +303,7 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
   HIPCHECK(launch_init_rhs64(M, N, nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, dg0.p, w.ds64.p, s));
   WP_LAUNCH("spmv_f32v_f64x", s,
             launch_spmv_f32v_f64x(R, nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, s, 0, -1,
-                                  spmv_order(L), pk_view(L)));
+                                  spmv_order(L), pk_view(L, w.spmm_cols)));
   HIPCHECK(launch_fill0(w.dy.p, DB, s));
   std::vector<MixedCol> col(B);
   std::vector<char> active(B, 1);

@@ -211,6 +211,7 @@ struct RotArgs {
   const int* finals;     // [nfin] channels captured
   int nfin;
   int64_t acap_off;      // offset (in double2) of this term's capture row: acap[acap_off + c*nfin + f]
+  int tile = 0;          // WP_STEP_* choice of kernel (0: by shape)
 };
 // fused s = W (G1 * (O y)) with capture; r.A = O, W = v O^T (same wave layout), r.G required
 hipError_t launch_step64(const RotArgs& r, const double* W, const double2* y, double2* s_out, hipStream_t s);
@@ -226,6 +227,7 @@ struct PackView {
   int npk = 0;
   const int* pkt = nullptr;
   const int* pos = nullptr;
+  int spmm_min = 16;   // column count from which lanes run over the columns
 };
 // Block-CSR products for any storage/vector precision: lanes over columns when all B >= 16
 // columns are requested, else lanes over blocks with a wave reduction. Few channels (<= 4): full

@@ -10,6 +10,22 @@
 
 namespace wpcd {
 struct MixedWork;
+
+// A HIP graph captured once and replayed while its key (every pointer, size and choice the
+// captured launches depend on) is unchanged.
+struct GraphCache {
+  std::vector<int64_t> key;
+  hipGraphExec_t exec = nullptr;
+  GraphCache() = default;
+  GraphCache(const GraphCache&) = delete;
+  GraphCache& operator=(const GraphCache&) = delete;
+  ~GraphCache() { reset(); }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
 }
 using namespace wpcd;
 
@@ -70,7 +86,10 @@ struct wp_lattice {
     DBuf<int> dj0, dg0, dfin;
     DBuf<double> dE;
     DBuf<int64_t> g1w;
+    wpcd::GraphCache chunk_graph[2];   // one full chunk of terms per capture slot
   } ws64;
+  hipStream_t cap_stream = nullptr;   // graph capture (default priority, non-blocking)
+  std::mutex cap_mu;
   std::shared_ptr<wpcd::MixedWork> mws;
   int64_t cand_cap = 0;                   // candidate blocks scratch_cand holds
   int64_t* h_tot = nullptr;               // pinned: the two totals of the last build
@@ -85,6 +104,9 @@ struct wp_lattice {
     if (order_ev) (void)hipEventDestroy(order_ev);
     for (hipEvent_t e : build_ev)
       if (e) (void)hipEventDestroy(e);
+    ws64.chunk_graph[0].reset();
+    ws64.chunk_graph[1].reset();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
   DBuf<double> d_val64;
   DBuf<float> d_val32;
@@ -102,7 +124,9 @@ struct wp_lattice {
   DBuf<int> d_fkey, d_fcptr, d_fcm;
   DBuf<double> d_fcv;
 };
-inline PackView pk_view(const wp_lattice* L) { return PackView{L->pk.npk, L->d_pkt.p, L->d_pkpos.p}; }
+inline PackView pk_view(const wp_lattice* L, int spmm_cols = 0) {
+  return PackView{L->pk.npk, L->d_pkt.p, L->d_pkpos.p, spmm_cols > 0 ? spmm_cols : 16};
+}
 
 struct EnergyResult {
   double E_lab, E, q0, dq0;
@@ -154,8 +178,19 @@ struct MixedWork {
   DBuf<int64_t> g1w;
   std::vector<double2> hc, hH, hn, coef;
   std::vector<double> hsc;
+  // launch choices of the current call (wp_solve_opts) and the graphs of the Arnoldi sweep
+  // (index: the first cycle, whose residual is b, or a later one)
+  int step_tile = 0, spmm_cols = 0;
+  bool graph = false;
+  GraphCache sweep_graph[2];
   wp_status make(wp_lattice* L, int B, int m, bool split);
 };
+// Enqueues record(stream) on s as a HIP graph: captured on the lattice's capture stream when the
+// cache is empty or its key differs, then launched on s. record must only enqueue work (no host
+// synchronisation) and return hipSuccess.
+template <typename F>
+hipError_t graph_run(wp_lattice* L, GraphCache& g, const std::vector<int64_t>& key, hipStream_t s, F record);
+bool profiling_enabled();
 // per-column state of the refinement's stop rule
 struct MixedCol {
   std::vector<cplx> U;
@@ -243,6 +278,36 @@ inline bool column_push(ColState& cs, const cplx* a, int nfin, double tol, doubl
   cs.last = est;
   cs.n++;
   return cs.done;
+}
+
+
+template <typename F>
+hipError_t graph_run(wp_lattice* L, GraphCache& g, const std::vector<int64_t>& key, hipStream_t s, F record) {
+  if (!g.exec || g.key != key) {
+    g.reset();
+    std::lock_guard<std::mutex> lk(L->cap_mu);   // one capture at a time on the lattice's stream
+    if (!L->cap_stream) {
+      const hipError_t e = hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipStreamBeginCapture(L->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t er = record(L->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(L->cap_stream, &graph);
+    if (er != hipSuccess || e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return er != hipSuccess ? er : e;
+    }
+    e = hipGraphInstantiateWithFlags(&g.exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec = nullptr;
+      return e;
+    }
+    g.key = key;
+  }
+  return hipGraphLaunch(g.exec, s);
 }
 
 }  // namespace wpcd

@@ -43,7 +43,7 @@ class BatchBackend:
         self.L = lattice
         self.terms = terms
         self.mode = mode
-        o = wp._SolveOpts(wp.SOLVE_MODES[mode], tol, accept, max_iter, refine_every)
+        o = wp._SolveOpts(wp.SOLVE_MODES[mode], tol, accept, max_iter, refine_every, 0, 0, 0)
         self.h = C.c_void_p()
         wp._check(wp._lib.faddeev_batch_create(lattice.h, slots, hbm_budget, C.byref(o), C.byref(self.h)))
         self.slots = slots
