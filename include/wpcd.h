@@ -271,6 +271,21 @@ void wp_solution_free(wp_solution* sol);
 wp_status faddeev_batch_create(wp_lattice* lat, int max_slots, size_t hbm_budget,
                                const wp_solve_opts* opts, wp_batch** out);
 wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot);
+/*
+ * Admission of several energies on a stream (serving): E_lab[0 .. n) in order go into free
+ * slots, in runs of adjacent free slots, each run served by one G1 launch and one right-hand
+ * side product P0 (v O^T) e0 over its columns (so k requests cost one P0 pass, not k). The work is
+ * enqueued on `stream` (give the stream the batch is stepped on) and the call does not wait for
+ * it. *n_admitted = how many were admitted (fewer than n, possibly 0, when the batch runs out of
+ * free slots: not an error); slots[k] = the slot of E_lab[k]. WP_EINVAL for E_lab <= 0 or an
+ * on-shell momentum outside the lattice (nothing of that run is admitted). faddeev_batch_admit
+ * is the one-energy form on the null stream, synchronous, WP_EBUDGET when no slot is free.
+ */
+wp_status faddeev_batch_admit_many(wp_batch* b, int n, const double* E_lab, void* stream, int* slots,
+                                   int* n_admitted);
+/* Device bytes one slot of a batch with these options takes on this lattice: the unit in which
+ * serving divides one device-memory budget among the lattices' batches (hbm_budget of each). */
+wp_status faddeev_batch_slot_bytes(const wp_lattice* lat, const wp_solve_opts* opts, size_t* bytes);
 wp_status faddeev_batch_step(wp_batch* b, void* stream, int terms, int* n_done, int* done_slots);
 wp_status faddeev_batch_take(wp_batch* b, int slot, wp_solution** out);
 wp_status faddeev_batch_live(const wp_batch* b, int* n_live);

@@ -96,6 +96,8 @@ _SIGS = {
     "wp_solution_free": (None, [_P]),
     "faddeev_batch_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_SolveOpts), C.POINTER(_P)]),
     "faddeev_batch_admit": (C.c_int, [_P, C.c_double, _I]),
+    "faddeev_batch_admit_many": (C.c_int, [_P, C.c_int, _D, _P, _I, _I]),
+    "faddeev_batch_slot_bytes": (C.c_int, [_P, C.POINTER(_SolveOpts), C.POINTER(C.c_size_t)]),
     "faddeev_batch_step": (C.c_int, [_P, _P, C.c_int, _I, _I]),
     "faddeev_batch_take": (C.c_int, [_P, C.c_int, C.POINTER(_P)]),
     "faddeev_batch_live": (C.c_int, [_P, _I]),

@@ -41,7 +41,31 @@ struct wp_batch {
   };
   std::vector<Slot> s;
   std::vector<double2> hcap;
+  // pinned staging of each slot's energy and on-shell bins (written only when the slot is
+  // admitted again, by which time its previous copy has run)
+  double* hE = nullptr;
+  int* hj0 = nullptr;
+  size_t per_slot = 0;
+  ~wp_batch() {
+    if (hE) (void)hipHostFree(hE);
+    if (hj0) (void)hipHostFree(hj0);
+  }
 };
+
+// Device bytes one slot of a batch takes (its columns of every solve vector).
+static size_t slot_bytes(const wp_lattice* L, const wp_solve_opts& o, int m, int max_terms) {
+  const int nfin = (int)L->opens.size();
+  const int64_t D = (int64_t)L->M * L->N * L->nch;
+  return o.mode != WP_SOLVE_FP64 ? (size_t)nfin * mixed_bytes_per_column(L, m)
+                                 : (size_t)nfin * (3 * D * sizeof(double2) + max_terms * nfin * sizeof(double2));
+}
+
+extern "C" wp_status faddeev_batch_slot_bytes(const wp_lattice* L, const wp_solve_opts* o, size_t* bytes) {
+  if (!L || !o || !bytes) return fail(WP_EINVAL, "NULL argument");
+  const int m = std::max(2, std::min(ARN_NV, o->refine_every > 0 ? o->refine_every : 8));
+  *bytes = slot_bytes(L, *o, m, 64);
+  return WP_OK;
+}
 
 extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t hbm_budget, const wp_solve_opts* o,
                                           wp_batch** out) {
@@ -63,17 +87,18 @@ extern "C" wp_status faddeev_batch_create(wp_lattice* L, int max_slots, size_t h
   b->D = (int64_t)L->M * L->N * L->nch;
   b->max_terms = 64;
   b->m = std::max(2, std::min(ARN_NV, o->refine_every > 0 ? o->refine_every : 8));
-  const size_t per_slot =
-      b->mixed ? (size_t)b->nfin * mixed_bytes_per_column(L, b->m)
-               : (size_t)b->nfin * (3 * b->D * sizeof(double2) + b->max_terms * b->nfin * sizeof(double2));
+  const size_t per_slot = slot_bytes(L, *o, b->m, b->max_terms);
+  b->per_slot = per_slot;
   int cap = (int)std::min<size_t>((size_t)max_slots, hbm_budget / std::max<size_t>(per_slot, 1));
   if (cap < 1) return fail(WP_EBUDGET, "hbm_budget smaller than one slot");
   b->slots = cap;
   b->B = cap * b->nfin;
   const int B = b->B;
   DevAlloc* al = &L->al;
-  if (!b->dg0.make(al, B) || !b->dE.make(al, cap) || !g1_work(L, 1, b->g1w))
+  if (!b->dg0.make(al, B) || !b->dE.make(al, cap) || !g1_work(L, cap, b->g1w))
     return fail(WP_ENOMEM, "device allocation (batch)");
+  HIPCHECK(hipHostMalloc((void**)&b->hE, cap * sizeof(double), hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&b->hj0, B * sizeof(int), hipHostMallocDefault));
   b->j0.assign(B, 0);
   b->g0.assign(B, 0);
   for (int c = 0; c < B; ++c) b->g0[c] = L->opens[c % b->nfin];
@@ -113,52 +138,94 @@ extern "C" wp_status faddeev_batch_live(const wp_batch* b, int* n) {
   return WP_OK;
 }
 
+// Admits E_lab[0 .. n) in order into the first run of adjacent free slots (as many as it
+// holds), with one G1 launch and one right-hand-side product for all of them, on stream st.
+static wp_status admit_run(wp_batch* b, int n, const double* E_lab, hipStream_t st, int* slots, int* n_admitted) {
+  *n_admitted = 0;
+  int sl0 = -1;
+  for (int k = 0; k < b->slots; ++k)
+    if (!b->s[k].live) {
+      sl0 = k;
+      break;
+    }
+  if (sl0 < 0 || n < 1) return WP_OK;
+  int k = 0;
+  while (k < n && sl0 + k < b->slots && !b->s[sl0 + k].live) ++k;
+  wp_lattice* L = b->L;
+  // kinematics first: a bad energy admits nothing
+  std::vector<EnergyResult> rs(k);
+  for (int e = 0; e < k; ++e)
+    if (!kinematics(L, E_lab[e], rs[e])) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
+  const int nf = b->nfin, c0 = sl0 * nf, c1 = (sl0 + k) * nf, B = b->B;
+  const int64_t R = (int64_t)L->M * L->N;
+  for (int e = 0; e < k; ++e) {
+    auto& S = b->s[sl0 + e];
+    S = wp_batch::Slot();
+    S.r = rs[e];
+    b->hE[sl0 + e] = S.r.E;
+    for (int f = 0; f < nf; ++f) b->j0[c0 + e * nf + f] = b->hj0[c0 + e * nf + f] = S.r.j0;
+  }
+  HIPCHECK(hipMemcpyAsync(b->dE.p + sl0, b->hE + sl0, k * sizeof(double), hipMemcpyHostToDevice, st));
+  if (b->mixed) {
+    MixedWork& w = b->mw;
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl0, k, nf, c0, B, w.dG64.p, b->g1w.p), st));
+    HIPCHECK(launch_cvt_d2f_cols(b->D, B, c0, c1, w.dG64.p, w.dG32.p, st));
+    HIPCHECK(hipMemcpyAsync(w.dj0.p + c0, b->hj0 + c0, (c1 - c0) * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0, c1));
+    WP_LAUNCH("spmv_f32v_f64x", st,
+              launch_spmv_f32v_f64x(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, st, c0,
+                                    c1, spmv_order(L), pk_view(L, b->o.spmm_cols)));
+    HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c1, st));
+    for (int e = 0; e < k; ++e) b->s[sl0 + e].mc.assign(nf, MixedCol());
+  } else {
+    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl0, k, nf, c0, B, b->dG.p, b->g1w.p), st));
+    HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->hj0 + c0, (c1 - c0) * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0, c1));
+    WP_LAUNCH("spmv64", st,
+              launch_spmv_f64(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st, c0, c1,
+                              spmv_order(L), pk_view(L, b->o.spmm_cols)));
+    for (int e = 0; e < k; ++e) {
+      auto& S = b->s[sl0 + e];
+      S.cs.resize(nf);
+      for (auto& c : S.cs) {
+        c.w.resize(nf);
+        c.S.assign(nf, cplx(0, 0));
+      }
+    }
+  }
+  for (int e = 0; e < k; ++e) {
+    b->s[sl0 + e].live = true;
+    slots[e] = sl0 + e;
+  }
+  *n_admitted = k;
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_batch_admit_many(wp_batch* b, int n, const double* E_lab, void* stream, int* slots,
+                                              int* n_admitted) {
+  if (!b || !E_lab || !slots || !n_admitted || n < 0) return fail(WP_EINVAL, "NULL argument");
+  *n_admitted = 0;
+  for (int e = 0; e < n; ++e)
+    if (!(E_lab[e] > 0)) return fail(WP_EINVAL, "E_lab must be positive");
+  hipStream_t st = (hipStream_t)stream;
+  int done = 0;
+  while (done < n) {   // one run of adjacent free slots per pass
+    int got = 0;
+    if (wp_status s = admit_run(b, n - done, E_lab + done, st, slots + done, &got)) return s;
+    if (got == 0) break;
+    done += got;
+  }
+  *n_admitted = done;
+  return WP_OK;
+}
+
 extern "C" wp_status faddeev_batch_admit(wp_batch* b, double E_lab, int* slot) {
   if (!b || !slot) return fail(WP_EINVAL, "NULL argument");
   if (!(E_lab > 0)) return fail(WP_EINVAL, "E_lab must be positive");
-  int sl = -1;
-  for (int k = 0; k < b->slots; ++k)
-    if (!b->s[k].live) {
-      sl = k;
-      break;
-    }
-  if (sl < 0) return fail(WP_EBUDGET, "no free slot within the batch's device-memory budget");
-  wp_lattice* L = b->L;
-  auto& S = b->s[sl];
-  S = wp_batch::Slot();
-  if (!kinematics(L, E_lab, S.r)) return fail(WP_EINVAL, "on-shell momentum outside the q lattice");
-  const int nf = b->nfin, c0 = sl * nf, B = b->B;
-  const int64_t R = (int64_t)L->M * L->N;
-  hipStream_t st = nullptr;
-  for (int f = 0; f < nf; ++f) b->j0[c0 + f] = S.r.j0;
-  HIPCHECK(hipMemcpyAsync(b->dE.p + sl, &S.r.E, sizeof(double), hipMemcpyHostToDevice, st));
-  if (b->mixed) {
-    MixedWork& w = b->mw;
-    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, w.dG64.p, b->g1w.p), st));
-    HIPCHECK(launch_cvt_d2f_cols(b->D, B, c0, c0 + nf, w.dG64.p, w.dG32.p, st));
-    HIPCHECK(hipMemcpyAsync(w.dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, w.dj0.p, b->dg0.p, w.ds64.p, st, c0,
-                               c0 + nf));
-    HIPCHECK(launch_spmv_f32v_f64x(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val32.p, w.ds64.p, w.db.p, st, c0,
-                                   c0 + nf, spmv_order(L), pk_view(L, b->o.spmm_cols)));
-    HIPCHECK(launch_fill0_cols(w.dy.p, b->D, B, c0, c0 + nf, st));
-    S.mc.assign(nf, MixedCol());
-  } else {
-    WP_LAUNCH("g1", st, launch_g1(g1_args(L, b->dE.p + sl, 1, nf, c0, B, b->dG.p, b->g1w.p), st));
-    HIPCHECK(hipMemcpyAsync(b->dj0.p + c0, b->j0.data() + c0, nf * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHECK(launch_init_rhs64(L->M, L->N, L->nch, B, L->d_W.p, L->d_wave.p, b->dj0.p, b->dg0.p, b->ds.p, st, c0,
-                               c0 + nf));
-    HIPCHECK(launch_spmv_f64(R, L->nch, B, L->d_rowptr.p, L->d_col.p, L->d_val64.p, b->ds.p, b->dy.p, st, c0, c0 + nf,
-                             spmv_order(L), pk_view(L, b->o.spmm_cols)));
-    S.cs.resize(nf);
-    for (auto& c : S.cs) {
-      c.w.resize(nf);
-      c.S.assign(nf, cplx(0, 0));
-    }
-  }
-  HIPCHECK(hipStreamSynchronize(st));
-  S.live = true;
-  *slot = sl;
+  int got = 0;
+  if (wp_status s = admit_run(b, 1, &E_lab, nullptr, slot, &got)) return s;
+  if (got == 0) return fail(WP_EBUDGET, "no free slot within the batch's device-memory budget");
+  HIPCHECK(hipStreamSynchronize(nullptr));
   return WP_OK;
 }
 

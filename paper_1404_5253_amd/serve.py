@@ -8,8 +8,14 @@ overlap on the GPU (ctypes releases the GIL inside library calls). A request
 between two steps of that batch, advances with every step of the batch and retires as soon as
 its Pade estimate is accepted; latency = retirement time - arrival time.
 
-The scheduler only talks to a backend object with admit(E) -> slot | None, step() -> list of
-(slot, result) and live(), so it is tested on the CPU with a fake backend and a virtual clock.
+Admission takes every queued request that fits in one call (admit_many: runs of adjacent free
+slots, one G1 launch and one right-hand-side product per run, enqueued on the lattice's own
+stream). One device-memory budget is divided among the lattices' batches (divide_budget), in
+units of each lattice's slot size.
+
+The scheduler only talks to a backend object with admit(E) -> slot | None (or admit_many(Es) ->
+slots), step() -> list of (slot, result) and live(), so it is tested on the CPU with a fake
+backend and a virtual clock.
 """
 from __future__ import annotations
 
@@ -50,13 +56,20 @@ class BatchBackend:
         self.stream = stream
         self._done = (C.c_int * slots)()
 
+    def admit_many(self, Es):
+        """Slots of the first len(result) energies of Es (fewer when the batch is full)."""
+        n = len(Es)
+        if n == 0:
+            return []
+        E = (C.c_double * n)(*Es)
+        sl = (C.c_int * n)()
+        got = C.c_int()
+        self.wp._check(self.wp._lib.faddeev_batch_admit_many(self.h, n, E, self.stream, sl, C.byref(got)))
+        return list(sl[:got.value])
+
     def admit(self, E_lab):
-        sl = C.c_int()
-        st = self.wp._lib.faddeev_batch_admit(self.h, E_lab, C.byref(sl))
-        if st == self.wp.WP_EBUDGET:
-            return None
-        self.wp._check(st)
-        return sl.value
+        got = self.admit_many([E_lab])
+        return got[0] if got else None
 
     def live(self):
         n = C.c_int()
@@ -110,13 +123,21 @@ class LatticeWorker:
     def pump(self):
         """Admit what fits, then one step. Returns True if any work was done."""
         with self.lock:
-            while self.queue:
-                sl = self.b.admit(self.queue[0].E_lab)
-                if sl is None:
-                    break
-                req = self.queue.popleft()
-                req.t_admit = self.clock()
-                self.inflight[sl] = req
+            if hasattr(self.b, "admit_many"):
+                slots = self.b.admit_many([r.E_lab for r in self.queue]) if self.queue else []
+                t = self.clock()
+                for sl in slots:
+                    req = self.queue.popleft()
+                    req.t_admit = t
+                    self.inflight[sl] = req
+            else:
+                while self.queue:
+                    sl = self.b.admit(self.queue[0].E_lab)
+                    if sl is None:
+                        break
+                    req = self.queue.popleft()
+                    req.t_admit = self.clock()
+                    self.inflight[sl] = req
         if not self.inflight:
             return False
         for sl, res in self.b.step():
@@ -191,3 +212,37 @@ def run_stream(backends, requests, clock=time.perf_counter, sleep=time.sleep, th
                  solves_per_s=len(counted) / span if span > 0 else 0.0, wall_s=t_end,
                  steps=[w.steps for w in workers])
     return done, stats
+
+
+def slot_bytes(lattice, mode="fp64", refine_every=0):
+    """Device bytes one batch slot takes on this lattice (faddeev_batch_slot_bytes)."""
+    import paper_1404_5253_amd as wp
+    o = wp._SolveOpts(wp.SOLVE_MODES[mode], 1e-8, 1e-8, 200, refine_every, 0, 0, 0)
+    b = C.c_size_t()
+    wp._check(wp._lib.faddeev_batch_slot_bytes(lattice.h, C.byref(o), C.byref(b)))
+    return b.value
+
+
+def divide_budget(total_bytes, slot_bytes, weights, max_slots):
+    """Slots per lattice from one device-memory budget: proportional to the weights (each
+    lattice's share of the expected load), at least one and at most max_slots each, with
+    sum(slots[i] * slot_bytes[i]) <= total_bytes. Raises if not even one slot each fits."""
+    n = len(slot_bytes)
+    if sum(slot_bytes) > total_bytes:
+        raise ValueError("budget smaller than one slot per lattice")
+    wsum = float(sum(weights))
+
+    def slots_at(scale):
+        return [min(max_slots, max(1, int(scale * w / wsum))) for w in weights]
+
+    def cost(sl):
+        return sum(k * b for k, b in zip(sl, slot_bytes))
+
+    lo, hi = 0.0, float(max_slots) * n * 4 + 1.0
+    for _ in range(100):   # largest scale whose slots fit
+        mid = 0.5 * (lo + hi)
+        if cost(slots_at(mid)) <= total_bytes:
+            lo = mid
+        else:
+            hi = mid
+    return slots_at(lo)

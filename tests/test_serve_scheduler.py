@@ -131,3 +131,52 @@ def test_threaded_stream_serves_every_request():
     for r in done:
         assert r.result["E"] == r.E_lab and r.t_arrival <= r.t_admit <= r.t_done
     assert st["n"] == sum(1 for r in done if r.t_arrival >= 0.04) < 300
+
+
+def test_divide_budget_is_proportional_and_fits():
+    from paper_1404_5253_amd.serve import divide_budget
+    sb = [10, 20, 40, 80]
+    sl = divide_budget(1000, sb, [1, 1, 1, 1], max_slots=32)
+    assert sum(k * b for k, b in zip(sl, sb)) <= 1000
+    assert all(1 <= k <= 32 for k in sl)
+    assert sl[0] == sl[1] == sl[2] == sl[3]          # equal weights: equal slot counts
+    big = divide_budget(10 ** 9, sb, [1, 1, 1, 1], max_slots=32)
+    assert big == [32, 32, 32, 32]                   # capped
+    w = divide_budget(4000, [10, 10], [3, 1], max_slots=1000)
+    assert w[0] == 3 * w[1] or abs(w[0] - 3 * w[1]) <= 3
+    import pytest
+    with pytest.raises(ValueError):
+        divide_budget(100, [60, 60], [1, 1], max_slots=4)
+
+
+def test_worker_admits_the_queue_in_one_call():
+    """With admit_many the worker hands the whole queue to the backend at once and admits the
+    first len(slots) requests in order."""
+    from paper_1404_5253_amd.serve import LatticeWorker, Request
+
+    class Many:
+        def __init__(self, free):
+            self.free = list(range(free))
+            self.calls = []
+
+        def admit_many(self, Es):
+            self.calls.append(list(Es))
+            k = min(len(Es), len(self.free))
+            got, self.free = self.free[:k], self.free[k:]
+            return got
+
+        def step(self):
+            return []
+
+        def live(self):
+            return 0
+
+    b = Many(3)
+    w = LatticeWorker(b, clock=lambda: 1.0)
+    for i in range(5):
+        w.submit(Request(i, 0.0, 0, 10.0 + i))
+    w.pump()
+    assert b.calls == [[10.0, 11.0, 12.0, 13.0, 14.0]]
+    assert sorted(w.inflight) == [0, 1, 2]
+    assert [r.E_lab for r in w.queue] == [13.0, 14.0]
+    assert [w.inflight[k].E_lab for k in (0, 1, 2)] == [10.0, 11.0, 12.0]
