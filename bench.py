@@ -440,6 +440,10 @@ def roofline(label, avg_s, L, B, nodes):
         flops = 8.0 * M * M * N * nch * B
         return dict(bound="alu", achieved=flops / avg_s / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                     flops_per_launch=flops)
+    if label == "pbuild_fused":                    # FP64 MFMA: moments of the kept pairs at every node
+        flops = 2.0 * st["blocks"] * nodes * L.nmom
+        return dict(bound="mfma", achieved=flops / avg_s / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    flops_per_launch=flops)
     if label in ("pbuild", "pbuild_mom"):          # FP64 VALU ops over the candidates' nodes
         nmom = getattr(L, "nmom", None)
         ops = st["candidates"] * nodes * (PBUILD_OPS_PER_NODE + 2 * (nmom or 1))

@@ -93,6 +93,11 @@ wp_status wp_lattice_build(const wp_lattice_desc* desc, const wp_allocator* allo
  * (l, s, j, lam, 2I, t) as int[6]. */
 wp_status wp_lattice_channels(const wp_lattice* lat, int* n_ch, int* table);
 
+/* Sizes of the P0 rule and storage (Appendix, final formula): *n_moments = distinct moment
+ * integrals (k, a, b, l, l') per cell pair, *n_stored = values stored per P0 block (n_ch^2, or
+ * the packed count for more than 4 channels); either pointer may be NULL. */
+wp_status wp_lattice_info(const wp_lattice* lat, int* n_moments, int* n_stored);
+
 /* Lattice edges (host copies): p_edges[M+1], q_edges[N+1]; either may be NULL. */
 wp_status wp_lattice_edges(const wp_lattice* lat, double* p_edges, double* q_edges);
 

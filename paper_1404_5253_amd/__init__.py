@@ -82,6 +82,7 @@ _SIGS = {
     "wp_last_error": (C.c_char_p, []),
     "wp_lattice_build": (C.c_int, [C.POINTER(_LatDesc), C.POINTER(_Alloc), C.POINTER(_P)]),
     "wp_lattice_channels": (C.c_int, [_P, _I, _I]),
+    "wp_lattice_info": (C.c_int, [_P, _I, _I]),
     "wp_lattice_edges": (C.c_int, [_P, _D, _D]),
     "wp_lattice_pseudostates": (C.c_int, [_P, C.c_int, _I, _D, _D, _D]),
     "wp_lattice_resolvent": (C.c_int, [_P, C.c_double, C.c_int, _D]),
@@ -292,6 +293,9 @@ class Lattice:
         _check(_lib.wp_lattice_channels(self.h, C.byref(n), tab))
         self.channels = [tuple(tab[6 * a: 6 * a + 6]) for a in range(n.value)]
         self.nch = n.value
+        nm, npk = C.c_int(), C.c_int()
+        _check(_lib.wp_lattice_info(self.h, C.byref(nm), C.byref(npk)))
+        self.nmom, self.n_stored = nm.value, npk.value
         self.perm_stats = None
 
     def edges(self):

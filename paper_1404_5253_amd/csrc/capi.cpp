@@ -246,6 +246,13 @@ extern "C" wp_status wp_lattice_channels(const wp_lattice* L, int* n_ch, int* ta
   return WP_OK;
 }
 
+extern "C" wp_status wp_lattice_info(const wp_lattice* L, int* n_moments, int* n_stored) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (n_moments) *n_moments = (int)L->keys.size();
+  if (n_stored) *n_stored = L->vpb;
+  return WP_OK;
+}
+
 extern "C" wp_status wp_lattice_edges(const wp_lattice* L, double* p, double* q) {
   if (!L) return fail(WP_EINVAL, "NULL lattice");
   if (p) std::copy(L->pe.begin(), L->pe.end(), p);

@@ -90,3 +90,16 @@ def test_noalloc_resolvent_host_checks():
     G = np.zeros(2 * 600 * 600)
     st = wp._lib.wp_lattice_resolvent_noalloc(big.h, 14.1, 0, G.ctypes.data_as(C.POINTER(C.c_double)))
     assert st == wp.WP_EINVAL and b"scratch" in wp._lib.wp_last_error()
+
+
+def test_lattice_info_matches_the_oracle_rule():
+    """Moment count of the P0 rule and stored values per block: the oracle's distinct moment keys,
+    and the channel pairs with a nonzero recoupling coefficient (all n_ch^2 for <= 4 channels)."""
+    for spec in (pipeline.Spec(M=6, N=7, two_J=1, j_max=2, swave_only=False, pot="mt"),
+                 pipeline.Spec(M=6, N=6, two_J=1, pot="mt")):
+        s = pipeline.build_system(spec)
+        L = wp.Lattice(spec.M, spec.N, two_J=spec.two_J, j_max=spec.j_max, swave_only=spec.swave_only,
+                       torch_alloc=False)
+        assert L.nmom == len(s.P0geo.keys)
+        nz = int(np.any(s.C != 0.0, axis=2).sum())
+        assert L.n_stored == (nz if L.nch > 4 else L.nch ** 2), (L.n_stored, nz)
