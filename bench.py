@@ -241,6 +241,32 @@ def sweep_section(wp, torch, V_R, sizes=(40, 100, 200, 400), reps=3):
     return out
 
 
+def breakup_section(wp, torch, L, Es, reps=5):
+    """Breakup transition elements of the headline solve (the same U projected onto every
+    energy-shell cell of the three-body continuum): cells per energy and the cost of the
+    projections on top of the solve."""
+    def run(bu):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sol = L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL, breakup=bu)
+        torch.cuda.synchronize()
+        return sol, (time.perf_counter() - t0) / reps
+    run(True)
+    _, t_plain = run(False)
+    sol, t_bu = run(True)
+    wp.wp_profile_reset()
+    wp.wp_profile_enable(True)
+    L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL, breakup=True)
+    torch.cuda.synchronize()
+    wp.wp_profile_enable(False)
+    prof = wp.wp_profile_read()
+    cells = [int(sol.breakup(k, 0)[0].shape[0]) for k in range(len(Es))]
+    return dict(E_lab=list(Es), cells_per_energy=cells, solve_ms=t_plain * 1e3, solve_ms_with_breakup=t_bu * 1e3,
+                projection_kernel_ms=round(prof.get("breakup", (0, 0.0))[1], 4),
+                max_abs_element=[float(np.max(np.abs(sol.breakup(k, 0)[1]), initial=0.0)) for k in range(len(Es))])
+
+
 def swave_section(wp, torch, V_R, reps=10):
     """The s-wave Malfliet-Tjon lattice pair at M = N = 100 (doublet J = 1/2+, 2 channels, and
     quartet J = 3/2+, 1 channel; V_R seed 0): P0 build in FP64 and one FP64 solve at 14.1 MeV each,
@@ -573,6 +599,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_extras:
+        out["breakup"] = breakup_section(wp, torch, L, Es)
         sw, sw_lats = swave_section(wp, torch, V_R)
         out["swave_mt_100"] = sw
         out["batched_64_energies"] = batched_energies_section(wp, torch, sw_lats[0])

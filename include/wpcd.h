@@ -231,6 +231,7 @@ typedef struct {
   int graph;
   int step_tile;
   int spmm_cols;
+  int breakup;   /* mixed modes: 1 also projects each solution onto the breakup cells */
 } wp_solve_opts;
 
 wp_status faddeev_solve(wp_lattice* lat, int n_E, const double* E_lab, const wp_solve_opts* opts,
@@ -258,6 +259,20 @@ wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, double* A, d
  * series (*n_terms = 0). WP_EINVAL if the capacity is too small.
  */
 wp_status faddeev_series(const wp_solution* sol, int e_idx, int initial, int* n_terms, double* a);
+
+/*
+ * Breakup transition elements (Sec. II.A; Sec. II.B.4, end: breakup is an inelastic transition
+ * into the discretised two-body continuum, read from the same U): for energy e_idx and initial
+ * open channel `initial`, <Z_kj^g| U |Z_0j0> for every channel g, continuum pseudostate k of g's
+ * pair wave (k >= its number of bound states) and q bin j whose cell holds the three-body energy
+ * (h2m p_a^2 + (3/4) h2m q_a^2 < E < h2m p_b^2 + (3/4) h2m q_b^2 over the pseudostate's momentum
+ * bin [p_a, p_b] and q bin [q_a, q_b]: the cells where Im G1 != 0). The transition element is
+ * (O y)_{g k j} of the solution y (y = O^T U e0). cells: *n_cells rows of (g, k, j) as int[3];
+ * U: *n_cells complex numbers (re, im). Either may be NULL to query *n_cells. Only solutions of
+ * the mixed modes asked for it (wp_solve_opts.breakup = 1) hold cells; others report 0. The
+ * normalisation of these elements to a physical breakup amplitude is not given in the paper.
+ */
+wp_status faddeev_breakup(const wp_solution* sol, int e_idx, int initial, int* n_cells, int* cells, double* U);
 
 void wp_solution_free(wp_solution* sol);
 

@@ -152,3 +152,32 @@ def solve_energy(sysm: System, E_lab, tol=1e-12, n_max=200, direct=False, P0full
     S = amp.s_matrix(A)
     return dict(E=E, q0=q0, j0=j0, U=U, A=A, S=S, iters=iters, converged=all(conv), rel_err=max(errs),
                 delta=amp.phase_deg(S), eta=amp.inelasticity(S), series=series)
+
+
+def breakup_elements(sysm: System, E_lab, P0full=None):
+    """Breakup transition elements (Sec. II.A; Sec. II.B.4, end): breakup is an inelastic
+    transition into the discretised two-body continuum, so its elements are components of the
+    same solution, z = U e0 = O y, on the cells of the three-body continuum the energy shell
+    crosses: continuum pseudostates k of each channel's pair wave (after its bound states) and q
+    bins j where the resolvent G1 has an imaginary part. y from the dense solve (small lattices).
+
+    Returns (cells, {initial b: elements}) with cells a list of (g, k, j) in (g, k, j) order."""
+    E = lattice.total_energy(E_lab, sysm.eps0)
+    q0 = lattice.q_onshell(E_lab, sysm.spec.h2m)
+    j0 = lattice.onshell_bin(sysm.q_edges, q0)
+    K = kernel(sysm, E, P0full)
+    G1 = g1_lists(sysm, E)
+    cells = []
+    for g, c in enumerate(sysm.chans):
+        nb = sysm.pair[(c[0], c[1])]["nb"]
+        G = G1[(c[0], c[1])]
+        for k in range(nb, G.shape[0]):
+            for j in range(G.shape[1]):
+                if G[k, j].imag != 0.0:
+                    cells.append((g, k, j))
+    out = {}
+    for b, g0 in enumerate(initial_channels(sysm)):
+        t = K.rotate(solve.direct_solution(K, g0, j0))   # t[g, j, k]
+        out[b] = np.array([t[g, j, k] for (g, k, j) in cells])
+    return cells, out
+

@@ -20,8 +20,15 @@ from .lattice import H2M, h0_diagonal
 
 
 def diagonalize(edges, v, h2m=H2M):
+    """Eigenpairs of h1 = h0 + v1. Each eigenvector is fixed up to its sign by the eigensolver;
+    the convention here makes its component of largest magnitude positive, so that projections
+    onto single pseudostates (the breakup elements) are defined."""
     eps, vec = np.linalg.eigh(np.diag(h0_diagonal(edges, h2m)) + v)
-    return eps, vec.T.copy()
+    O = vec.T.copy()
+    for k in range(O.shape[0]):
+        if O[k, np.argmax(np.abs(O[k]))] < 0.0:
+            O[k] = -O[k]
+    return eps, O
 
 
 def scattering_bins(eps_cont, h2m=H2M):

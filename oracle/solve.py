@@ -143,11 +143,15 @@ def iterate_pade(K: FactorizedKernel, g0, j0, finals, tol=1e-12, n_max=200, acce
     return best, len(terms), ok, np.array(terms), best_r * np.abs(best)
 
 
-def direct_solve(K: FactorizedKernel, g0, j0, finals):
-    """U_{a0} = e_a^T O (I - K)^{-1} b by dense LU (small lattices only)."""
+def direct_solution(K: FactorizedKernel, g0, j0):
+    """y = (I - K)^{-1} b by dense LU (small lattices only)."""
     import scipy.linalg as sl
     Kd = K.dense()
     b = K.rhs(g0, j0)
-    y = sl.solve(np.eye(Kd.shape[0]) - Kd, b)
-    t = K.rotate(y)
+    return sl.solve(np.eye(Kd.shape[0]) - Kd, b)
+
+
+def direct_solve(K: FactorizedKernel, g0, j0, finals):
+    """U_{a0} = e_a^T O (I - K)^{-1} b by dense LU (small lattices only)."""
+    t = K.rotate(direct_solution(K, g0, j0))
     return np.array([t[f, j0, 0] for f in finals])

@@ -66,7 +66,7 @@ class _PermStats(C.Structure):
 class _SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_int), ("tol", C.c_double), ("accept", C.c_double),
                 ("max_iter", C.c_int), ("refine_every", C.c_int), ("graph", C.c_int), ("step_tile", C.c_int),
-                ("spmm_cols", C.c_int)]
+                ("spmm_cols", C.c_int), ("breakup", C.c_int)]
 
 
 WP_STEP_AUTO, WP_STEP_MFMA8, WP_STEP_MFMA16, WP_STEP_VALU, WP_STEP_ROWS = 0, 1, 2, 3, 4
@@ -94,6 +94,7 @@ _SIGS = {
     "faddeev_solve": (C.c_int, [_P, C.c_int, _D, C.POINTER(_SolveOpts), _P, C.POINTER(_P)]),
     "amplitude": (C.c_int, [_P, C.c_int, _I, _D, _D, _D, _D, _D, _I]),
     "faddeev_series": (C.c_int, [_P, C.c_int, C.c_int, _I, _D]),
+    "faddeev_breakup": (C.c_int, [_P, C.c_int, C.c_int, _I, _I, _D]),
     "wp_solution_free": (None, [_P]),
     "faddeev_batch_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_SolveOpts), C.POINTER(_P)]),
     "faddeev_batch_admit": (C.c_int, [_P, C.c_double, _I]),
@@ -193,9 +194,9 @@ def perm_matrix_build(lat, precision=WP_P_FP64, stream=None):
 
 
 def faddeev_solve(lat, E_lab, mode=WP_SOLVE_FP64, tol=1e-12, accept=1e-7, max_iter=200, refine_every=0,
-                  stream=None, allow_noconv=False, graph=0, step_tile=0, spmm_cols=0):
+                  stream=None, allow_noconv=False, graph=0, step_tile=0, spmm_cols=0, breakup=0):
     E = np.ascontiguousarray(np.atleast_1d(E_lab), dtype=np.float64)
-    o = _SolveOpts(mode, tol, accept, max_iter, refine_every, graph, step_tile, spmm_cols)
+    o = _SolveOpts(mode, tol, accept, max_iter, refine_every, graph, step_tile, spmm_cols, breakup)
     h = _P()
     st = _lib.faddeev_solve(lat, len(E), _dptr(E), C.byref(o), stream, C.byref(h))
     if st == WP_ENOCONV and allow_noconv and h.value:
@@ -264,6 +265,16 @@ class Solution:
 
     def series(self, e_idx=0, initial=0):
         return faddeev_series(self.h, e_idx, initial)
+
+    def breakup(self, e_idx=0, initial=0):
+        """Breakup cells (n, 3) int array of (channel, pseudostate, q bin) and their complex
+        transition elements (faddeev_breakup)."""
+        n = C.c_int()
+        _check(_lib.faddeev_breakup(self.h, e_idx, initial, C.byref(n), None, None))
+        cells = np.zeros(max(n.value, 1) * 3, dtype=np.int32)
+        U = np.zeros(max(n.value, 1) * 2)
+        _check(_lib.faddeev_breakup(self.h, e_idx, initial, C.byref(n), cells.ctypes.data_as(_I), _dptr(U)))
+        return cells[:3 * n.value].reshape(n.value, 3), U[0:2 * n.value:2] + 1j * U[1:2 * n.value:2]
 
     def __del__(self, _lib=_lib):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -344,12 +355,12 @@ class Lattice:
         return rp, col[:nb], val[:nb * self.nch * self.nch].reshape(nb, self.nch, self.nch)
 
     def solve(self, E_lab, mode="fp64", tol=1e-12, accept=1e-7, max_iter=200, refine_every=0, stream=None,
-              allow_noconv=False, graph=False, step_tile="auto", spmm_cols=0):
+              allow_noconv=False, graph=False, step_tile="auto", spmm_cols=0, breakup=False):
         m = SOLVE_MODES[mode]
         E = np.atleast_1d(E_lab)
         h, ok = faddeev_solve(self.h, E, m, tol, accept, max_iter, refine_every,
                               stream if stream is not None else current_stream(), allow_noconv,
-                              int(bool(graph)), STEP_TILES[step_tile], int(spmm_cols))
+                              int(bool(graph)), STEP_TILES[step_tile], int(spmm_cols), int(bool(breakup)))
         return Solution(h, len(E), ok)
 
     def __del__(self, _lib=_lib):

@@ -360,6 +360,16 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
         std::vector<double> A(pw.v);
         for (int i = 0; i < M; ++i) A[(size_t)i * M + i] += h0[i];
         sym_eigen(M, A, pw.eps, &pw.O);
+        // sign convention of each pseudostate: its component of largest magnitude is positive
+        // (projections onto single pseudostates, the breakup elements, depend on it)
+        for (int k = 0; k < M; ++k) {
+          double* row = pw.O.data() + (size_t)k * M;
+          int im = 0;
+          for (int i = 1; i < M; ++i)
+            if (std::fabs(row[i]) > std::fabs(row[im])) im = i;
+          if (row[im] < 0.0)
+            for (int i = 0; i < M; ++i) row[i] = -row[i];
+        }
         pw.nb = 0;
         while (pw.nb < M && pw.eps[pw.nb] < 0.0) ++pw.nb;
         nbound += pw.nb;
@@ -1226,6 +1236,25 @@ extern "C" wp_status faddeev_series(const wp_solution* sol, int e_idx, int initi
     }
   }
   *n_terms = n;
+  return WP_OK;
+}
+
+extern "C" wp_status faddeev_breakup(const wp_solution* sol, int e_idx, int initial, int* n_cells, int* cells,
+                                     double* U) {
+  if (!sol || !n_cells) return fail(WP_EINVAL, "NULL argument");
+  if (e_idx < 0 || e_idx >= (int)sol->res.size()) return fail(WP_EINVAL, "energy index out of range");
+  const EnergyResult& r = sol->res[e_idx];
+  if (initial < 0 || initial >= r.n_open) return fail(WP_EINVAL, "initial channel out of range");
+  const int n = (int)(r.bu_cells.size() / 3);
+  if (cells) std::copy(r.bu_cells.begin(), r.bu_cells.end(), cells);
+  if (U && n > 0) {
+    const std::vector<cplx>& v = r.bu[initial];
+    for (int t = 0; t < n; ++t) {
+      U[2 * t] = v[t].real();
+      U[2 * t + 1] = v[t].imag();
+    }
+  }
+  *n_cells = n;
   return WP_OK;
 }
 

@@ -601,6 +601,36 @@ __global__ void __launch_bounds__(256) k_capture64(int M, int nch, int B, int nf
   if (lane == 0) out[t] = make_double2(sr, si);
 }
 
+// Breakup projections (one wavefront per cell): out[t] = sum_i O[wave(g)][k][i] y[((j M + i) nch + g) B + c]
+// for cell t = (c, g, k, j), the pair pseudostate k of channel g at spectator bin j.
+__global__ void __launch_bounds__(256) k_project_cells(int M, int nch, int B, const double* __restrict__ O,
+                                                       const int* __restrict__ wave, const int4* __restrict__ cells,
+                                                       int n, const double2* __restrict__ y,
+                                                       double2* __restrict__ out) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= n) return;
+  const int4 cl = cells[t];
+  const int c = cl.x, g = cl.y, k = cl.z, j = cl.w;
+  const double* o = O + ((size_t)wave[g] * M + k) * M;
+  double sr = 0.0, si = 0.0;
+  for (int i = lane; i < M; i += 64) {
+    const double2 v = y[(((size_t)j * M + i) * nch + g) * B + c];
+    sr += o[i] * v.x;
+    si += o[i] * v.y;
+  }
+  sr = wsum64(sr);
+  si = wsum64(si);
+  if (lane == 0) out[t] = make_double2(sr, si);
+}
+
+hipError_t launch_project_cells(int M, int nch, int B, const double* O, const int* wave, const int4* cells, int n,
+                                const double2* y, double2* out, hipStream_t s) {
+  if (M < 1 || B < 1 || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_project_cells, dim3((n + 3) / 4), dim3(256), 0, s, M, nch, B, O, wave, cells, n, y, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_capture64(int M, int nch, int B, int nfin, const double* O, const int* wave, const int* j0,
                             const int* finals, const double2* y, double2* out, hipStream_t s) {
   if (M < 1 || B < 1 || nfin < 1) return hipErrorInvalidValue;

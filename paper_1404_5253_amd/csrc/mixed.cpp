@@ -256,6 +256,26 @@ bool wpcd::MixedCol::update(const double2* u_new, int nfin, double tol) {
   return err <= tol;
 }
 
+// Breakup cells of three-body energy E: (g, k, j) for every channel g, continuum pseudostate k of
+// its pair wave and q bin j whose energy range h2m [p_a^2, p_b^2] + (3/4) h2m [q_a^2, q_b^2] holds
+// E strictly inside (the cells where Im G1 != 0).
+std::vector<int> wpcd::shell_cells(const wp_lattice* L, double E) {
+  std::vector<int> out;
+  const double h = L->h2m, b3 = 0.75 * L->h2m;
+  for (int g = 0; g < L->nch; ++g) {
+    const PairWave& w = L->waves[L->wave_of[g]];
+    for (int k = w.nb; k < L->M; ++k) {
+      const double pa = w.bins[k - w.nb], pb = w.bins[k - w.nb + 1];
+      for (int j = 0; j < L->N; ++j) {
+        const double lo = h * pa * pa + b3 * L->qe[j] * L->qe[j];
+        const double hi = h * pb * pb + b3 * L->qe[j + 1] * L->qe[j + 1];
+        if (lo < E && E < hi) out.insert(out.end(), {g, k, j});
+      }
+    }
+  }
+  return out;
+}
+
 wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                             wp_solution* sol) {
   const int M = L->M, N = L->N, nch = L->nch;
@@ -317,6 +337,41 @@ wp_status wpcd::solve_mixed(wp_lattice* L, const std::vector<double>& Elab, cons
       all &= !active[c];
     }
     if (all) break;
+  }
+  if (o.breakup == 1) {
+    // breakup: (O y) on every energy-shell cell of every column
+    std::vector<int4> cells;
+    std::vector<int> first(B + 1, 0);
+    for (int e = 0; e < nE; ++e) {
+      sol->res[e].bu_cells = shell_cells(L, Etot[e]);
+      const std::vector<int>& sc = sol->res[e].bu_cells;
+      for (int b = 0; b < nfin; ++b) {
+        const int c = e * nfin + b;
+        first[c] = (int)cells.size();
+        for (size_t t = 0; t + 2 < sc.size(); t += 3) cells.push_back(make_int4(c, sc[t], sc[t + 1], sc[t + 2]));
+      }
+    }
+    first[B] = (int)cells.size();
+    if (!cells.empty()) {
+      DBuf<int4> dcells;
+      DBuf<double2> dout;
+      if (!dcells.make(&L->al, cells.size()) || !dout.make(&L->al, cells.size()))
+        return fail(WP_ENOMEM, "device allocation (breakup cells)");
+      std::vector<double2> h(cells.size());
+      HIPCHECK(hipMemcpyAsync(dcells.p, cells.data(), cells.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      WP_LAUNCH("breakup", s, launch_project_cells(M, nch, B, L->d_O.p, L->d_wave.p, dcells.p, (int)cells.size(),
+                                                  w.dy.p, dout.p, s));
+      HIPCHECK(hipMemcpyAsync(h.data(), dout.p, h.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      for (int e = 0; e < nE; ++e) {
+        sol->res[e].bu.assign(nfin, {});
+        for (int b = 0; b < nfin; ++b) {
+          const int c = e * nfin + b;
+          auto& v = sol->res[e].bu[b];
+          for (int t = first[c]; t < first[c + 1]; ++t) v.emplace_back(h[t].x, h[t].y);
+        }
+      }
+    }
   }
   bool allok = true;
   for (int e = 0; e < nE; ++e) {

@@ -323,6 +323,9 @@ int arn_blocks(int64_t rows, int B, int nblk);
 // U[c][f] = e0^T O y at (g = finals[f], j = j0[c], k = 0), FP64
 hipError_t launch_capture64(int M, int nch, int B, int nfin, const double* O, const int* wave, const int* j0,
                             const int* finals, const double2* y, double2* out, hipStream_t s);
+// out[t] = (O y) of cell t = (column c, channel g, pseudostate k, q bin j), n cells
+hipError_t launch_project_cells(int M, int nch, int B, const double* O, const int* wave, const int4* cells, int n,
+                                const double2* y, double2* out, hipStream_t s);
 hipError_t launch_norm2_f64(int64_t rows, int B, const double2* x, double2* part, int nblk, double2* out, hipStream_t s);
 // out = x / |x| per column (FP64 in, FP32 out); scl0[c] = 1 when given
 hipError_t launch_scale_d2f(int64_t rows, int B, const double2* nrm2, const double2* x, float2* out, double* scl0,

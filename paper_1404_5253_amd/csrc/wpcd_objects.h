@@ -137,6 +137,10 @@ struct EnergyResult {
   std::vector<int> iters;
   // FP64 path: the on-shell series terms a_n read for each initial column b, series[b][n * n_open + f]
   std::vector<std::vector<cplx>> series;
+  // breakup (mixed modes, on request): the energy-shell cells (g, k, j) and, per initial
+  // column, the transition element of each cell
+  std::vector<int> bu_cells;
+  std::vector<std::vector<cplx>> bu;
   bool ok = true;
 };
 
@@ -202,6 +206,7 @@ size_t mixed_bytes_per_column(const wp_lattice* L, int m);
 wp_status mixed_cycle(MixedWork& w, hipStream_t s, bool y_is_zero, const std::vector<char>& active);
 wp_status solve_mixed(wp_lattice* L, const std::vector<double>& Elab, const wp_solve_opts& o, hipStream_t s,
                       wp_solution* sol);
+std::vector<int> shell_cells(const wp_lattice* L, double E);   // breakup cells (g, k, j) at energy E
 // Device work list of the G1 kernels for nE energies (element list plus counter in slot 0).
 bool g1_work(wp_lattice* L, int nE, DBuf<int64_t>& w);
 // G1 arguments for energies dE[nE] written to columns col0 + e*nrep + f of G (B columns); work: the

@@ -71,7 +71,8 @@ def test_pseudostates_match_oracle(pot, two_J):
         d = s.pair[(ch[0], ch[1])]
         assert nb == d["nb"]
         assert np.allclose(eps, d["eps"], rtol=1e-11, atol=1e-11)
-        assert np.allclose(np.abs(O), np.abs(d["O"]), atol=1e-10)      # eigenvector signs are free
+        # signs fixed by the same convention on both sides (largest component positive)
+        assert np.allclose(O, d["O"], atol=1e-10)
         assert np.allclose(O @ O.T, np.eye(M), atol=1e-13)
         assert np.allclose(bins, d["bins"], rtol=1e-12)
 
