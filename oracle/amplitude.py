@@ -14,6 +14,14 @@ def amplitude_matrix(U, q0, dq0, h2m):
     return (2.0 / (3.0 * h2m * q0)) * np.asarray(U) / dq0
 
 
+def amplitude_matrix_energy(U, B0):
+    """Energy-weight packets: A = U / B_j0 with B_j0 the energy width of the on-shell q bin. The
+    on-shell factor |f(q0)|^2 / B_j0 replaces 1/dq_j0 and |f(q0)|^2 = (3/2) H2M q0 cancels the
+    prefactor 2 / (3 H2M q0); G1 has the single imaginary entry -i pi / B_j0 below breakup, so the
+    same S = 1 - 2 pi i A is exactly unitary there."""
+    return np.asarray(U) / B0
+
+
 def s_matrix(A):
     A = np.atleast_2d(A)
     return np.eye(A.shape[0]) - 2j * np.pi * A

@@ -38,6 +38,24 @@ def h0_diagonal(edges: np.ndarray, h2m: float = H2M) -> np.ndarray:
     return h2m * (b ** 3 - a ** 3) / (3.0 * (b - a))
 
 
+# ---- energy weights (Sec. III.B, the footnote to eqs. dg1a, dg1b) ----
+#
+# A packet with weight w(p) ~ sqrt(p) is |p_i> = C_i^(-1/2) int_{D_i} w(p) |p> dp with
+# |w(p)|^2 = d eps / dp: the weight is flat in the energy eps = H2M p^2, and C_i is the energy
+# width H2M (p_i^2 - p_{i-1}^2). For the third nucleon, |f(q)|^2 = d eps_q / dq with
+# eps_q = (3/4) H2M q^2 and B_j = (3/4) H2M (q_j^2 - q_{j-1}^2).
+
+def energy_widths(edges: np.ndarray, scale: float) -> np.ndarray:
+    """scale * (p_i^2 - p_{i-1}^2): C_i with scale = H2M, B_j with scale = (3/4) H2M."""
+    return scale * (edges[1:] ** 2 - edges[:-1] ** 2)
+
+
+def h0_diagonal_energy(edges: np.ndarray, h2m: float = H2M) -> np.ndarray:
+    """<p_i | H2M p^2 | p_i> for energy-weight packets: (1/C_i) int eps d eps, the bin's mean energy."""
+    a, b = edges[:-1], edges[1:]
+    return 0.5 * h2m * (a * a + b * b)
+
+
 # ---- kinematics (nd elastic: deuteron at rest, neutron with lab energy E_lab) ----
 
 def e_cm(E_lab: float) -> float:

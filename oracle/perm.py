@@ -31,6 +31,22 @@ and the box done by a composite Gauss rule (``element_semianalytic``).
 (iii) BRUTE FORCE: midpoint sums of the 3D theta form on tiny lattices (``element_bruteforce_s``,
 ``element_bruteforce``).
 
+(iv) ENERGY WEIGHTS (Sec. III.B, footnote: packets with w(p) ~ sqrt(p), f(q) ~ sqrt(q)). The
+plane-wave projection gains the factor w(p) f(q) / sqrt(C_i B_j) in place of 1/sqrt(d_i dq_j),
+with |w|^2 = 2 H2M p, |f|^2 = (3/2) H2M q, C_i = H2M (p_i^2 - p_{i-1}^2) and
+B_j = (3/4) H2M (q_j^2 - q_{j-1}^2). In the integrand of the Appendix this multiplies by
+w(pi2) w(pi1) f(q) f(q') = 3 H2M^2 sqrt(pi1 pi2 q q') = 3 H2M^2 Q^2 sqrt(cos sin zeta1 zeta2),
+so the Q integral becomes int Q^3 dQ = (U^4 - L^4)/4, and with the constants
+
+  [P0]^{gg'}_{ij,i'j'} = sum g / sqrt(dp2_i dq2_j dp2_i' dq2_j')
+        * int dx P_k(x) int dphi (U^4 - L^4) sqrt(cos sin zeta1 zeta2)
+          cos^(a+1) sin^(b+1) / (zeta1^(l'+1) zeta2^(l+1)),
+
+dp2_i = p_i^2 - p_{i-1}^2, dq2_j = q_j^2 - q_{j-1}^2: the same rule with F = U^4 - L^4 (written
+(U - L)(U + L)(U^2 + L^2)), one more node factor and another norm. The brute force
+(``element_bruteforce`` with weights="energy") applies the weights and widths as defined, in
+MeV units, so the reduction of the constants is checked too.
+
 Layout used by the oracle: a lattice row/column index is (j, i) -> j * M + i.
 """
 from __future__ import annotations
@@ -63,25 +79,41 @@ def box_nodes(q_edges, j, jp, n_x, n_phi):
     z2 = np.sqrt(0.25 * c * c + s * s + X * c * s)
     Q1 = np.maximum(qa / c, qpa / s)
     Q2 = np.minimum(qb / c, qpb / s)
-    return dict(x=X, c=c, s=s, z1=z1, z2=z2, Q1=Q1, Q2=Q2, w=W)
+    return dict(x=X, c=c, s=s, z1=z1, z2=z2, Q1=Q1, Q2=Q2, w=W, ew=np.sqrt(c * s * z1 * z2))
 
 
-def moment_weight(nodes, key):
-    """Node weight of moment key = (k, a, b, l, l'): w P_k(x) c^(a+1) s^(b+1) / (z1^(l'+1) z2^(l+1))."""
+def moment_weight(nodes, key, weights="unit"):
+    """Node weight of moment key = (k, a, b, l, l'): w P_k(x) c^(a+1) s^(b+1) / (z1^(l'+1) z2^(l+1)),
+    times sqrt(c s z1 z2) for energy weights."""
     k, a, b, l, lp = key
     Pk = _leg.legval(nodes["x"], [0.0] * k + [1.0])
-    return (nodes["w"] * Pk * nodes["c"] ** (a + 1) * nodes["s"] ** (b + 1)
-            / (nodes["z1"] ** (lp + 1) * nodes["z2"] ** (l + 1)))
+    wt = (nodes["w"] * Pk * nodes["c"] ** (a + 1) * nodes["s"] ** (b + 1)
+          / (nodes["z1"] ** (lp + 1) * nodes["z2"] ** (l + 1)))
+    return wt * nodes["ew"] if weights == "energy" else wt
 
 
-def F_values(p_edges, nodes, ii, iip):
-    """F at every node for the cell pairs (i, i') given as index arrays -> (npairs, nnodes)."""
+def pair_norm(p_edges, q_edges, ii, j, iip, jp, weights="unit"):
+    """1/sqrt(d_i dq_j d_i' dq_j') (unit) or 1/sqrt(dp2_i dq2_j dp2_i' dq2_j') (energy weights)."""
+    if weights == "energy":
+        dp = p_edges[1:] ** 2 - p_edges[:-1] ** 2
+        dq = q_edges[1:] ** 2 - q_edges[:-1] ** 2
+    else:
+        dp = np.diff(p_edges)
+        dq = np.diff(q_edges)
+    return 1.0 / np.sqrt(dp[ii] * dq[j] * dp[iip] * dq[jp])
+
+
+def F_values(p_edges, nodes, ii, iip, weights="unit"):
+    """F at every node for the cell pairs (i, i') given as index arrays -> (npairs, nnodes):
+    (U^2 - L^2)/2 for unit weights, U^4 - L^4 for energy weights, 0 where U <= L."""
     z1 = nodes["z1"][None, :]
     z2 = nodes["z2"][None, :]
     U = np.minimum(np.minimum(nodes["Q2"][None, :], p_edges[iip + 1][:, None] / z1),
                    p_edges[ii + 1][:, None] / z2)
     L = np.maximum(np.maximum(nodes["Q1"][None, :], p_edges[iip][:, None] / z1),
                    p_edges[ii][:, None] / z2)
+    if weights == "energy":
+        return np.where(U > L, (U - L) * (U + L) * (U * U + L * L), 0.0)
     return np.where(U > L, 0.5 * (U - L) * (U + L), 0.0)
 
 
@@ -143,15 +175,14 @@ def channel_terms(chans, gtabs):
 class P0Lattice:
     """Geometric P0 data: for every q-box, the stored cell pairs and their moment integrals."""
 
-    def __init__(self, p_edges, q_edges, keys, n_x=8, n_phi=8, exhaustive=False):
+    def __init__(self, p_edges, q_edges, keys, n_x=8, n_phi=8, exhaustive=False, weights="unit"):
         self.p_edges = np.asarray(p_edges, float)
         self.q_edges = np.asarray(q_edges, float)
         self.M = len(p_edges) - 1
         self.N = len(q_edges) - 1
         self.keys = list(keys)
         self.n_x, self.n_phi = n_x, n_phi
-        dp = np.diff(self.p_edges)
-        dq = np.diff(self.q_edges)
+        self.weights = weights
         rows, cols, moms = [], [], []
         M, N = self.M, self.N
         for j in range(N):
@@ -164,10 +195,10 @@ class P0Lattice:
                     ii, iip = candidate_pairs(self.p_edges, nodes)
                 if len(ii) == 0:
                     continue
-                F = F_values(self.p_edges, nodes, ii, iip)
-                Wm = np.stack([moment_weight(nodes, key) for key in self.keys], axis=1)
+                F = F_values(self.p_edges, nodes, ii, iip, weights)
+                Wm = np.stack([moment_weight(nodes, key, weights) for key in self.keys], axis=1)
                 mom = F @ Wm
-                norm = 1.0 / np.sqrt(dp[ii] * dq[j] * dp[iip] * dq[jp])
+                norm = pair_norm(self.p_edges, self.q_edges, ii, j, iip, jp, weights)
                 mom *= norm[:, None]
                 keep = np.any(mom != 0.0, axis=1)
                 rows.append(j * M + ii[keep])
@@ -197,13 +228,12 @@ class P0Lattice:
         return sp.bmat(blocks, format="csr")
 
 
-def element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi):
+def element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi, weights="unit"):
     """One moment integral of one cell pair by the rule (for sampled checks at full size)."""
-    nodes = box_nodes(np.asarray(q_edges, float), j, jp, n_x, n_phi)
-    F = F_values(np.asarray(p_edges, float), nodes, np.array([i]), np.array([ip]))[0]
-    dp = np.diff(p_edges)
-    dq = np.diff(q_edges)
-    return float(F @ moment_weight(nodes, key)) / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
+    p_edges, q_edges = np.asarray(p_edges, float), np.asarray(q_edges, float)
+    nodes = box_nodes(q_edges, j, jp, n_x, n_phi)
+    F = F_values(p_edges, nodes, np.array([i]), np.array([ip]), weights)[0]
+    return float(F @ moment_weight(nodes, key, weights)) * float(pair_norm(p_edges, q_edges, i, j, ip, jp, weights))
 
 
 # --------------------------------------------------------------------------- pins (s-wave)
@@ -259,13 +289,14 @@ def element_bruteforce_s(p_edges, q_edges, i, j, ip, jp, n):
 
 # --------------------------------------------------------------------------- pins (any channel pair)
 
-def element_rule_channel(p_edges, q_edges, i, j, ip, jp, keys, Cab, n_x, n_phi):
+def element_rule_channel(p_edges, q_edges, i, j, ip, jp, keys, Cab, n_x, n_phi, weights="unit"):
     """Channel-pair element sum_m C[g, g', m] * moment_m of one cell pair by the rule."""
-    return float(sum(c * element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi)
+    return float(sum(c * element_rule(p_edges, q_edges, i, j, ip, jp, key, n_x, n_phi, weights)
                      for key, c in zip(keys, Cab) if c != 0.0))
 
 
-def element_semianalytic(p_edges, q_edges, i, j, ip, jp, G, l, lp, n_w=24, n_sub=96, n_g=6):
+def element_semianalytic(p_edges, q_edges, i, j, ip, jp, G, l, lp, n_w=24, n_sub=96, n_g=6, weights="unit",
+                         h2m=41.471):
     """Channel-pair element of P0 from the 3D kernel, for any l, l' (eq. P_kern before the polar step).
 
     With the kernel delta(p' - pi1) delta(p - pi2) G(q, q', x) / (p'^(l'+2) p^(l+2)) and the unit
@@ -284,6 +315,9 @@ def element_semianalytic(p_edges, q_edges, i, j, ip, jp, G, l, lp, n_w=24, n_sub
     function of (q, q') with kinks where the interval ends switch, integrated over the box by a
     composite Gauss rule (n_sub panels of n_g points per axis; error O(n_sub^-2) at the kinks).
     G is any vectorised callable (for the pin: the m-scheme polynomial).
+
+    weights="energy": the integrand gains w(pi2) w(pi1) f(q) f(q') (|w|^2 = 2 h2m p, |f|^2 =
+    (3/2) h2m q) and the widths are the energy widths C_i, B_j (MeV), as defined.
     """
     pa, pb = p_edges[i], p_edges[i + 1]
     ppa, ppb = p_edges[ip], p_edges[ip + 1]
@@ -314,14 +348,25 @@ def element_semianalytic(p_edges, q_edges, i, j, ip, jp, G, l, lp, n_w=24, n_sub
     Qb, QPb = Q[:, None], QP[:, None]
     x = np.clip((pi1 * pi1 - Qb * Qb - 0.25 * QPb * QPb) / (Qb * QPb), -1.0, 1.0)
     f = G(Qb, QPb, x) / (pi1 ** lp * pi2 ** l)
+    if weights == "energy":
+        f = f * np.sqrt(2.0 * h2m * pi2) * np.sqrt(2.0 * h2m * pi1)
+        W2 = W2 * np.sqrt(1.5 * h2m * Q) * np.sqrt(1.5 * h2m * QP)
     inner = 2.0 * 0.5 * (w1 - w0) * (f @ tw)
+    if weights == "energy":
+        C = h2m * (p_edges[1:] ** 2 - p_edges[:-1] ** 2)
+        B = 0.75 * h2m * (q_edges[1:] ** 2 - q_edges[:-1] ** 2)
+        return float(np.dot(W2, inner)) / np.sqrt(C[i] * B[j] * C[ip] * B[jp])
     dp = np.diff(p_edges)
     dq = np.diff(q_edges)
     return float(np.dot(W2, inner)) / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])
 
 
-def element_bruteforce(p_edges, q_edges, i, j, ip, jp, G, l, lp, n):
-    """Midpoint sum with n^3 points of the 3D (q, q', x) theta form for any channel pair."""
+def element_bruteforce(p_edges, q_edges, i, j, ip, jp, G, l, lp, n, weights="unit", h2m=41.471):
+    """Midpoint sum with n^3 points of the 3D (q, q', x) theta form for any channel pair.
+
+    weights="energy": the integrand is multiplied by w(pi2) w(pi1) f(q) f(q') with |w(p)|^2 =
+    2 h2m p and |f(q)|^2 = (3/2) h2m q, and divided by sqrt(C_i B_j C_i' B_j') (energy widths)
+    instead of the momentum widths."""
     qa, qb = q_edges[j], q_edges[j + 1]
     qpa, qpb = q_edges[jp], q_edges[jp + 1]
     t = (np.arange(n) + 0.5) / n
@@ -334,6 +379,11 @@ def element_bruteforce(p_edges, q_edges, i, j, ip, jp, G, l, lp, n):
     th = ((pi1 > p_edges[ip]) & (pi1 <= p_edges[ip + 1]) & (pi2 > p_edges[i]) & (pi2 <= p_edges[i + 1]))
     f = np.where(th, Q * QP * G(Q, QP, X) / (pi1 ** (lp + 1) * pi2 ** (l + 1)), 0.0)
     vol = (qb - qa) * (qpb - qpa) * 2.0 / n ** 3
+    if weights == "energy":
+        wgt = np.sqrt(2.0 * h2m * pi2) * np.sqrt(2.0 * h2m * pi1) * np.sqrt(1.5 * h2m * Q) * np.sqrt(1.5 * h2m * QP)
+        C = h2m * (p_edges[1:] ** 2 - p_edges[:-1] ** 2)
+        B = 0.75 * h2m * (q_edges[1:] ** 2 - q_edges[:-1] ** 2)
+        return (f * wgt).sum() * vol / np.sqrt(C[i] * B[j] * C[ip] * B[jp])
     dp = np.diff(p_edges)
     dq = np.diff(q_edges)
     return f.sum() * vol / np.sqrt(dp[i] * dq[j] * dp[ip] * dq[jp])

@@ -40,6 +40,7 @@ class Spec:
     target_BE: float = BE_DEUTERON
     h2m: float = lattice.H2M
     exhaustive: bool = False
+    weights: str = "unit"            # or "energy" (w(p) ~ sqrt(p), f(q) ~ sqrt(q); Sec. III.B footnote)
 
 
 @dataclass
@@ -67,8 +68,10 @@ def pair_potential(spec, pe, l, s, strength, YR=None):
     if spec.pot == "yamaguchi":
         if (l, s) != (0, 1):
             return np.zeros((len(pe) - 1, len(pe) - 1))
+        if spec.weights == "energy":
+            return potential.yamaguchi_wp_energy(pe, spec.beta, strength)
         return potential.yamaguchi_wp(pe, spec.beta, strength)
-    YR_, YA_ = potential.mt_parts(pe, l, spec.mu_R, spec.mu_A)
+    YR_, YA_ = potential.mt_parts(pe, l, spec.mu_R, spec.mu_A, spec.weights)
     VA = strength if s == 1 else spec.singlet_ratio * strength
     return spec.V_R * YR_ - VA * YA_
 
@@ -80,11 +83,11 @@ def build_system(spec: Spec) -> System:
     gt = {(a, b): recoupling.g_table(chans[a], chans[b], spec.two_J)
           for a in range(len(chans)) for b in range(len(chans))}
     keys, C = channel_terms(chans, gt)
-    P = P0Lattice(pe, qe, keys, spec.n_x, spec.n_phi, exhaustive=spec.exhaustive)
+    P = P0Lattice(pe, qe, keys, spec.n_x, spec.n_phi, exhaustive=spec.exhaustive, weights=spec.weights)
     if spec.pot == "yamaguchi":
-        strength = potential.tune_yamaguchi(pe, spec.beta, spec.target_BE, spec.h2m)
+        strength = potential.tune_yamaguchi(pe, spec.beta, spec.target_BE, spec.h2m, spec.weights)
     else:
-        strength = potential.tune_mt(pe, spec.V_R, spec.mu_R, spec.mu_A, spec.target_BE, spec.h2m)
+        strength = potential.tune_mt(pe, spec.V_R, spec.mu_R, spec.mu_A, spec.target_BE, spec.h2m, spec.weights)
     sysm = System(spec, pe, qe, chans, C, keys, P, strength=strength)
     nbound = 0
     for c in chans:
@@ -92,9 +95,12 @@ def build_system(spec: Spec) -> System:
         if key in sysm.pair:
             continue
         v = pair_potential(spec, pe, c[0], c[1], strength)
-        eps, O = pseudostates.diagonalize(pe, v, spec.h2m)
+        eps, O = pseudostates.diagonalize(pe, v, spec.h2m, h0=potential.h0_of(pe, spec.h2m, spec.weights))
         nb = int(np.sum(eps < 0))
-        bins = pseudostates.scattering_bins(eps[nb:], spec.h2m)
+        if spec.weights == "energy":
+            bins = pseudostates.scattering_bins_energy(eps[nb:], spec.h2m)
+        else:
+            bins = pseudostates.scattering_bins(eps[nb:], spec.h2m)
         sysm.pair[key] = dict(eps=eps, O=O, v=v, W=v @ O.T, nb=nb, bins=bins)
         nbound += nb
     if sysm.pair.get((0, 1), {}).get("nb", 0) != 1 or nbound != 1:
@@ -112,7 +118,8 @@ def g1_lists(sysm: System, E):
     out = {}
     for key, d in sysm.pair.items():
         bound = list(d["eps"][:d["nb"]])
-        out[key] = resolvent.channel_diagonal(sysm.q_edges, E, bound, d["bins"], sysm.spec.h2m)
+        diag = resolvent.channel_diagonal_energy if sysm.spec.weights == "energy" else resolvent.channel_diagonal
+        out[key] = diag(sysm.q_edges, E, bound, d["bins"], sysm.spec.h2m)
     return out
 
 
@@ -147,8 +154,12 @@ def solve_energy(sysm: System, E_lab, tol=1e-12, n_max=200, direct=False, P0full
             errs.append(np.max(err / np.maximum(np.abs(est), 1e-300)))
             iters.append(n)
             conv.append(ok)
-    dq0 = sysm.q_edges[j0 + 1] - sysm.q_edges[j0]
-    A = amp.amplitude_matrix(U, q0, dq0, sysm.spec.h2m)
+    if sysm.spec.weights == "energy":
+        B0 = 0.75 * sysm.spec.h2m * (sysm.q_edges[j0 + 1] ** 2 - sysm.q_edges[j0] ** 2)
+        A = amp.amplitude_matrix_energy(U, B0)
+    else:
+        dq0 = sysm.q_edges[j0 + 1] - sysm.q_edges[j0]
+        A = amp.amplitude_matrix(U, q0, dq0, sysm.spec.h2m)
     S = amp.s_matrix(A)
     return dict(E=E, q0=q0, j0=j0, U=U, A=A, S=S, iters=iters, converged=all(conv), rel_err=max(errs),
                 delta=amp.phase_deg(S), eta=amp.inelasticity(S), series=series)

@@ -144,3 +144,66 @@ def channel_diagonal(q_edges, E, eps_bound, cont_bins, h2m=H2M):
         rows.append(np.array([continuum_element(pa, pb, q_edges[j], q_edges[j + 1], E, h2m)
                               for j in range(N)]))
     return np.array(rows)
+
+
+# --------------------------------------------------------------------------- energy weights
+#
+# With the weights w(p) ~ sqrt(p), f(q) ~ sqrt(q) of the footnote in Sec. III.B (|w|^2 dp = d eps,
+# |f|^2 dq = d eps_q), eqs. dg1a and dg1b are integrals over energy intervals and come out in
+# closed form:
+#
+#   G_0j = (1/B_j) int_{y1}^{y2} dy / (E + i0 - eps_n - y) = (1/B_j) [ln(z1) - ln(z2)],
+#          z_b = E - eps_n - y_b;
+#   G_kj = (1/(C_k B_j)) int_{x1}^{x2} dx int_{y1}^{y2} dy / (E + i0 - x - y)
+#        = (1/(C_k B_j)) [phi(z11) - phi(z21) - phi(z12) + phi(z22)],
+#          z_ab = E - x_a - y_b, phi(z) = z ln(z + i0) (phi(0) = 0),
+#
+# with x = H2M p^2 over the pseudostate's energy bin (width C_k), y = (3/4) H2M q^2 over the q bin
+# (width B_j) and ln(z + i0) = ln|z| + i pi for z < 0. The four-term difference cancels heavily
+# when the bins are small next to |z|, so it is evaluated in 40-digit arithmetic here.
+
+def _log_i0(z):
+    return mpmath.log(abs(z)) + (1j * mpmath.pi if z < 0 else 0)
+
+
+def _phi_re(z):
+    """Real part of phi(z) = z ln(z + i0)."""
+    return mpmath.mpf(0) if z == 0 else z * mpmath.log(abs(z))
+
+
+def bound_continuum_energy(q_edges, E, eps0, h2m=H2M):
+    out = np.empty(len(q_edges) - 1, dtype=complex)
+    with mpmath.workdps(40):
+        b3 = mpmath.mpf(3) / 4 * mpmath.mpf(h2m)
+        for j in range(len(q_edges) - 1):
+            y1 = b3 * mpmath.mpf(q_edges[j]) ** 2
+            y2 = b3 * mpmath.mpf(q_edges[j + 1]) ** 2
+            z1 = mpmath.mpf(E) - mpmath.mpf(eps0) - y1
+            z2 = mpmath.mpf(E) - mpmath.mpf(eps0) - y2
+            out[j] = complex((_log_i0(z1) - _log_i0(z2)) / (y2 - y1))
+    return out
+
+
+def continuum_element_energy(pa, pb, qa, qb, E, h2m=H2M):
+    with mpmath.workdps(40):
+        h = mpmath.mpf(h2m)
+        b3 = mpmath.mpf(3) / 4 * h
+        x1, x2 = h * mpmath.mpf(pa) ** 2, h * mpmath.mpf(pb) ** 2
+        y1, y2 = b3 * mpmath.mpf(qa) ** 2, b3 * mpmath.mpf(qb) ** 2
+        E_ = mpmath.mpf(E)
+        re = (_phi_re(E_ - x1 - y1) - _phi_re(E_ - x2 - y1) - _phi_re(E_ - x1 - y2) + _phi_re(E_ - x2 - y2))
+        # the imaginary parts pi z [z < 0] of the four terms add up to -pi times the length of the
+        # segment x + y = E inside the box (exactly 0 off the shell)
+        C, B, s0 = x2 - x1, y2 - y1, x1 + y1
+        ell = max(mpmath.mpf(0), min(E_ - s0, C, B, s0 + C + B - E_))
+        return complex(re / (C * B), -mpmath.pi * ell / (C * B))
+
+
+def channel_diagonal_energy(q_edges, E, eps_bound, cont_bins, h2m=H2M):
+    """channel_diagonal for energy-weight packets (cont_bins: momentum edges of the energy bins)."""
+    N = len(q_edges) - 1
+    rows = [bound_continuum_energy(q_edges, E, eb, h2m) for eb in eps_bound]
+    for k in range(len(cont_bins) - 1):
+        rows.append(np.array([continuum_element_energy(cont_bins[k], cont_bins[k + 1], q_edges[j], q_edges[j + 1],
+                                                       E, h2m) for j in range(N)]))
+    return np.array(rows)

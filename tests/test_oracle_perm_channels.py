@@ -68,7 +68,7 @@ def test_rule_converges_to_kernel_integral(a, b):
 
 def _planted(monkeypatch, fn):
     orig = perm.moment_weight
-    monkeypatch.setattr(perm, "moment_weight", lambda nodes, key: orig(nodes, fn(key)))
+    monkeypatch.setattr(perm, "moment_weight", lambda nodes, key, weights="unit": orig(nodes, fn(key), weights))
 
 
 @pytest.mark.parametrize("mistake", ["zeta_powers_swapped", "cos_sin_powers_swapped"])
