@@ -102,6 +102,22 @@ wp_status wp_lattice_info(const wp_lattice* lat, int* n_moments, int* n_stored);
 wp_status wp_lattice_edges(const wp_lattice* lat, double* p_edges, double* q_edges);
 
 /*
+ * Packet weights (Sec. III.B, the footnote to eqs. dg1a, dg1b). WP_WEIGHTS_UNIT (the default):
+ * unit momentum weights as above. WP_WEIGHTS_ENERGY: weights w(p) ~ sqrt(p), f(q) ~ sqrt(q),
+ * flat in the energies eps = (hbar^2/m) p^2 and eps_q = (3/4) (hbar^2/m) q^2: a packet is
+ * C_i^(-1/2) int_{D_i} w(p) |p> dp with |w|^2 = d eps / dp and C_i the energy width of D_i. Then
+ * h0 is the bin's mean energy; the potential and P0 elements carry the weights (the P0 rule
+ * takes F = U^4 - L^4, the node factor sqrt(cos phi sin phi zeta1 zeta2) and the norm
+ * 1 / sqrt(dp2_i dq2_j dp2_i' dq2_j'), dp2_i = p_i^2 - p_{i-1}^2); the continuum pseudostate bins
+ * are energy intervals (edges at midpoints of neighbouring eps_k, mirrored last edge; reported
+ * by wp_lattice_pseudostates as momenta sqrt(e / (hbar^2/m))); G1 is evaluated in closed form;
+ * the amplitude is A = U / B_j0 with B_j0 the energy width of the on-shell q bin.
+ * Set it before twobody_pseudostates and perm_matrix_build; once either has run, WP_EINVAL.
+ */
+enum { WP_WEIGHTS_UNIT = 0, WP_WEIGHTS_ENERGY = 1 };
+wp_status wp_lattice_weights(wp_lattice* lat, int kind);
+
+/*
  * Step-1 results for one channel's pair wave (after twobody_pseudostates): number of bound
  * states, pseudostate energies eps[M] (ascending), O[M*M] (row k = eigenvector k in the free WP
  * basis, eq. exp_z) and the continuum bin edges bins[M - n_bound + 1]. Pointers may be NULL.

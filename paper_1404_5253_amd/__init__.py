@@ -27,6 +27,8 @@ C = C   # ctypes, re-exported for callers that pass raw stream handles
 WP_OK, WP_EINVAL, WP_ENOMEM, WP_EDEVICE, WP_ENOTREADY, WP_ENOCONV, WP_EBUDGET, WP_EINTERNAL = range(8)
 WP_P_FP64, WP_P_FP32 = 0, 1
 WP_SOLVE_FP64, WP_SOLVE_MIXED, WP_SOLVE_MIXED_SPLIT = 0, 1, 2
+WP_WEIGHTS_UNIT, WP_WEIGHTS_ENERGY = 0, 1
+WEIGHTS = {"unit": WP_WEIGHTS_UNIT, "energy": WP_WEIGHTS_ENERGY}
 SOLVE_MODES = {"fp64": WP_SOLVE_FP64, "mixed": WP_SOLVE_MIXED, "mixed_split": WP_SOLVE_MIXED_SPLIT}
 H2M = 41.471
 
@@ -83,6 +85,7 @@ _SIGS = {
     "wp_lattice_build": (C.c_int, [C.POINTER(_LatDesc), C.POINTER(_Alloc), C.POINTER(_P)]),
     "wp_lattice_channels": (C.c_int, [_P, _I, _I]),
     "wp_lattice_info": (C.c_int, [_P, _I, _I]),
+    "wp_lattice_weights": (C.c_int, [_P, C.c_int]),
     "wp_lattice_edges": (C.c_int, [_P, _D, _D]),
     "wp_lattice_pseudostates": (C.c_int, [_P, C.c_int, _I, _D, _D, _D]),
     "wp_lattice_resolvent": (C.c_int, [_P, C.c_double, C.c_int, _D]),
@@ -286,7 +289,8 @@ class Lattice:
     """One lattice: channels, pseudostates, resident P0 (device memory from torch)."""
 
     def __init__(self, M, N, two_J=1, parity=1, j_max=1, swave_only=True, n_x=8, n_phi=8, alpha=1.0,
-                 p_max=10.0, q_max=10.0, hbar2_over_m=H2M, p_edges=None, q_edges=None, torch_alloc=True):
+                 p_max=10.0, q_max=10.0, hbar2_over_m=H2M, p_edges=None, q_edges=None, torch_alloc=True,
+                 weights="unit"):
         self.alloc = None
         if torch_alloc:
             try:
@@ -298,6 +302,11 @@ class Lattice:
         self.M, self.N = M, N
         self.h = wp_lattice_build(M, N, two_J, parity, j_max, swave_only, n_x, n_phi, alpha, p_max, q_max,
                                   hbar2_over_m, p_edges, q_edges, self.alloc)
+        if weights not in WEIGHTS:
+            raise ValueError(f"weights must be one of {sorted(WEIGHTS)}")
+        self.weights = weights
+        if weights != "unit":
+            _check(_lib.wp_lattice_weights(self.h, WEIGHTS[weights]))
         n = C.c_int()
         _check(_lib.wp_lattice_channels(self.h, C.byref(n), None))
         tab = (C.c_int * (6 * n.value))()

@@ -260,6 +260,15 @@ extern "C" wp_status wp_lattice_edges(const wp_lattice* L, double* p, double* q)
   return WP_OK;
 }
 
+extern "C" wp_status wp_lattice_weights(wp_lattice* L, int kind) {
+  if (!L) return fail(WP_EINVAL, "NULL lattice");
+  if (kind != WP_WEIGHTS_UNIT && kind != WP_WEIGHTS_ENERGY) return fail(WP_EINVAL, "unknown weight kind");
+  if (L->pseudo || L->have_P)
+    return fail(WP_EINVAL, "wp_lattice_weights: set the weights before twobody_pseudostates and perm_matrix_build");
+  L->weights = kind;
+  return WP_OK;
+}
+
 extern "C" void wp_lattice_free(wp_lattice* L) { delete L; }
 
 // ------------------------------------------------------------------ pseudostates
@@ -275,16 +284,17 @@ static double ground_energy(const std::vector<double>& h0, const std::vector<dou
 static std::vector<double> wave_potential(const wp_lattice* L, const wp_potential_desc* p, int l, int s, double strength) {
   const int M = L->M;
   std::vector<double> v((size_t)M * M, 0.0);
+  const bool ew = L->weights == WP_WEIGHTS_ENERGY;
   if (p->kind == 0) {
     if (l == 0 && s == 1) {
-      auto G = yamaguchi_form(L->pe, p->beta);
+      auto G = ew ? yamaguchi_form_energy(L->pe, p->beta) : yamaguchi_form(L->pe, p->beta);
       for (int i = 0; i < M; ++i)
         for (int k = 0; k < M; ++k) v[(size_t)i * M + k] = -strength * G[i] * G[k];
     }
     return v;
   }
-  auto YR = yukawa_wp(L->pe, l, p->mu_R);
-  auto YA = yukawa_wp(L->pe, l, p->mu_A);
+  auto YR = ew ? yukawa_wp_energy(L->pe, l, p->mu_R) : yukawa_wp(L->pe, l, p->mu_R);
+  auto YA = ew ? yukawa_wp_energy(L->pe, l, p->mu_A) : yukawa_wp(L->pe, l, p->mu_A);
   double VA = s == 1 ? strength : p->singlet_ratio * strength;
   for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];
   return v;
@@ -321,12 +331,13 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
   if (p->kind != 0 && p->kind != 1) return fail(WP_EINVAL, "potential kind must be 0 (Yamaguchi) or 1 (MT)");
   try {
     const int M = L->M;
-    auto h0 = h0_diagonal(L->pe, L->h2m);
+    const bool ew = L->weights == WP_WEIGHTS_ENERGY;
+    auto h0 = ew ? h0_diagonal_energy(L->pe, L->h2m) : h0_diagonal(L->pe, L->h2m);
     double str = p->kind == 0 ? p->lambda : p->V_A;
     if (p->tune) {
       if (p->target_BE <= 0) return fail(WP_EINVAL, "target_BE must be positive");
       if (p->kind == 0) {
-        auto G = yamaguchi_form(L->pe, p->beta);
+        auto G = ew ? yamaguchi_form_energy(L->pe, p->beta) : yamaguchi_form(L->pe, p->beta);
         auto f = [&](double lam) {
           std::vector<double> v((size_t)M * M);
           for (int i = 0; i < M; ++i)
@@ -335,8 +346,8 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
         };
         str = find_root(f, 1.0, 2000.0, 1e-15);
       } else {
-        auto YR = yukawa_wp(L->pe, 0, p->mu_R);
-        auto YA = yukawa_wp(L->pe, 0, p->mu_A);
+        auto YR = ew ? yukawa_wp_energy(L->pe, 0, p->mu_R) : yukawa_wp(L->pe, 0, p->mu_R);
+        auto YA = ew ? yukawa_wp_energy(L->pe, 0, p->mu_A) : yukawa_wp(L->pe, 0, p->mu_A);
         auto f = [&](double VA) {
           std::vector<double> v(YR.size());
           for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];
@@ -373,13 +384,21 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
         pw.nb = 0;
         while (pw.nb < M && pw.eps[pw.nb] < 0.0) ++pw.nb;
         nbound += pw.nb;
-        // continuum bins: 0, midpoints of neighbouring p*_k, mirrored last edge
+        // continuum bins: 0, midpoints of neighbouring p*_k, mirrored last edge (unit weights);
+        // the same in energy, as momenta sqrt(e / h2m) (energy weights)
         int K = M - pw.nb;
         pw.bins.assign(K + 1, 0.0);
-        std::vector<double> ps(K);
-        for (int k = 0; k < K; ++k) ps[k] = std::sqrt(pw.eps[pw.nb + k] / L->h2m);
-        for (int k = 1; k < K; ++k) pw.bins[k] = 0.5 * (ps[k - 1] + ps[k]);
-        pw.bins[K] = 2.0 * ps[K - 1] - pw.bins[K - 1];
+        if (ew) {
+          std::vector<double> eb(K + 1, 0.0);
+          for (int k = 1; k < K; ++k) eb[k] = 0.5 * (pw.eps[pw.nb + k - 1] + pw.eps[pw.nb + k]);
+          eb[K] = 2.0 * pw.eps[pw.nb + K - 1] - eb[K - 1];
+          for (int k = 0; k <= K; ++k) pw.bins[k] = std::sqrt(eb[k] / L->h2m);
+        } else {
+          std::vector<double> ps(K);
+          for (int k = 0; k < K; ++k) ps[k] = std::sqrt(pw.eps[pw.nb + k] / L->h2m);
+          for (int k = 1; k < K; ++k) pw.bins[k] = 0.5 * (ps[k - 1] + ps[k]);
+          pw.bins[K] = 2.0 * ps[K - 1] - pw.bins[K - 1];
+        }
         // W = v O^T
         pw.W.assign((size_t)M * M, 0.0);
         for (int i = 0; i < M; ++i)
@@ -507,6 +526,7 @@ G1Args wpcd::g1_args(const wp_lattice* L, const double* dE, int nE, int nrep, in
   g.G = G;
   g.wl_n = reinterpret_cast<int*>(work);
   g.wl = work ? work + 1 : nullptr;
+  g.ew = L->weights == WP_WEIGHTS_ENERGY ? 1 : 0;
   return g;
 }
 
@@ -670,7 +690,8 @@ extern "C" wp_status perm_matrix_build(wp_lattice* L, int precision, void* strea
   const int M = L->M, N = L->N, nch = L->nch, nc2 = nch * nch;
   const int64_t R = (int64_t)M * N;
   PBuildArgs a{M, N, nch, (int)L->keys.size(), L->n_x, L->n_phi, L->d_pe.p, L->d_qe.p, L->d_gx.p,
-               L->d_gwx.p, L->d_gp.p, L->d_gwp.p, L->d_keys.p, L->d_C.p};
+               L->d_gwx.p, L->d_gp.p, L->d_gwp.p, L->d_keys.p, L->d_C.p,
+               L->weights == WP_WEIGHTS_ENERGY ? 1 : 0};
   // Scratch is carved from two grow-only buffers of the lattice (the selection arrays, sized by
   // the lattice, and the candidate arrays, sized by the candidate count), so that a rebuild
   // allocates nothing; a buffer above kKeepScratch is released when the build ends.
@@ -1199,8 +1220,8 @@ extern "C" wp_status amplitude(const wp_solution* sol, int e_idx, int* n_open, d
   const int n = r.n_open;
   *n_open = n;
   if (!A && !S && !delta && !eta && !err && !n_iter) return WP_OK;
-  // A = (2 / (3 h2m q0)) U / dq_j0,  S = 1 - 2 pi i A
-  const double fac = 2.0 / (3.0 * sol->h2m * r.q0) / r.dq0;
+  // A = (2 / (3 h2m q0)) U / dq_j0 (unit weights) or U / B_j0 (energy weights),  S = 1 - 2 pi i A
+  const double fac = r.afac;
   std::vector<cplx> Am(n * n), Sm(n * n);
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b) {

@@ -175,6 +175,82 @@ std::vector<double> yukawa_wp(const std::vector<double>& e, int l, double mu) {
   return v;
 }
 
+// Energy-weight packets (weight w(p) = sqrt(2 h2m p), |w|^2 = d eps/dp; norm C_i = h2m dp2_i,
+// dp2_i = p_i^2 - p_{i-1}^2; Sec. III.B, footnote). Integrals over a bin are taken in t = sqrt(p)
+// (p = t^2, sqrt(p) dp = 2 t^2 dt), where the integrands are smooth at p = 0.
+
+std::vector<double> h0_diagonal_energy(const std::vector<double>& e, double h2m) {
+  // (1/C_i) int eps d eps over the bin: its mean energy
+  size_t M = e.size() - 1;
+  std::vector<double> h(M);
+  for (size_t i = 0; i < M; ++i) h[i] = 0.5 * h2m * (e[i] * e[i] + e[i + 1] * e[i + 1]);
+  return h;
+}
+
+static void sqrt_nodes(const std::vector<double>& e, int ng, std::vector<double>& P, std::vector<double>& W) {
+  // per bin: nodes p = t^2 and weights of int sqrt(p) f(p) dp = int 2 t^2 f(t^2) dt
+  std::vector<double> gx(ng), gw(ng);
+  gauss_legendre(ng, gx.data(), gw.data());
+  size_t M = e.size() - 1;
+  P.assign(M * ng, 0.0);
+  W.assign(M * ng, 0.0);
+  for (size_t i = 0; i < M; ++i) {
+    const double ta = std::sqrt(e[i]), tb = std::sqrt(e[i + 1]);
+    const double h = 0.5 * (tb - ta), m = 0.5 * (tb + ta);
+    for (int a = 0; a < ng; ++a) {
+      const double t = m + h * gx[a];
+      P[i * ng + a] = t * t;
+      W[i * ng + a] = h * gw[a] * 2.0 * t * t;
+    }
+  }
+}
+
+std::vector<double> yamaguchi_form_energy(const std::vector<double>& e, double beta) {
+  // G_i = C_i^{-1/2} int w(p) p / (p^2 + beta^2) dp = sqrt(2 / dp2_i) int p^{3/2} / (p^2 + beta^2) dp
+  const int ng = 32;
+  std::vector<double> P, W;
+  sqrt_nodes(e, ng, P, W);
+  size_t M = e.size() - 1;
+  std::vector<double> G(M);
+  for (size_t i = 0; i < M; ++i) {
+    double s = 0.0;
+    for (int a = 0; a < ng; ++a) {
+      const double p = P[i * ng + a];
+      s += W[i * ng + a] * p / (p * p + beta * beta);
+    }
+    G[i] = s * std::sqrt(2.0 / (e[i + 1] * e[i + 1] - e[i] * e[i]));
+  }
+  return G;
+}
+
+std::vector<double> yukawa_wp_energy(const std::vector<double>& e, int l, double mu) {
+  // v_ii' = 2 (dp2_i dp2_i')^{-1/2} int int sqrt(p p') Q_l(z) / pi dp dp'
+  const int ng = 32;
+  std::vector<double> P, W;
+  sqrt_nodes(e, ng, P, W);
+  size_t M = e.size() - 1;
+  std::vector<double> v(M * M);
+  for (size_t i = 0; i < M; ++i)
+    for (size_t k = i; k < M; ++k) {
+      double s = 0.0;
+      for (int a = 0; a < ng; ++a) {
+        const double p = P[i * ng + a];
+        double acc = 0.0;
+        for (int b = 0; b < ng; ++b) {
+          const double pp = P[k * ng + b];
+          const double z = (p * p + pp * pp + mu * mu) / (2.0 * p * pp);
+          acc += W[k * ng + b] * legendre_q(l, z);
+        }
+        s += W[i * ng + a] * acc;
+      }
+      const double d2i = e[i + 1] * e[i + 1] - e[i] * e[i], d2k = e[k + 1] * e[k + 1] - e[k] * e[k];
+      s *= 2.0 / (M_PI * std::sqrt(d2i * d2k));
+      v[i * M + k] = s;
+      v[k * M + i] = s;
+    }
+  return v;
+}
+
 // ------------------------------------------------------------------ symmetric eigenproblem
 
 void sym_eigen(int n, std::vector<double>& A, std::vector<double>& d, std::vector<double>* Zout) {

@@ -84,7 +84,7 @@ __device__ __forceinline__ void box_phi_row(const PBuildArgs& a, int j, int jp, 
 }
 // node nd = ia * n_phi + ib from the phi table (x rule gx, gwx; phi weights gwp)
 __device__ Node box_node_at_p(const double* gx, const double* gwx, const double* gwp, int n_phi, const double* tab,
-                              int nd) {
+                              int nd, bool ew = false) {
   Node n;
   const int ia = nd / n_phi, ib = nd - ia * n_phi;
   const double* t = tab + ib * PHI_STRIDE;
@@ -99,10 +99,19 @@ __device__ Node box_node_at_p(const double* gx, const double* gwx, const double*
   const double z2 = sqrt(0.25 * n.c * n.c + n.s * n.s + n.x * cs);
   n.r1 = 1.0 / n.z1;
   n.r2 = 1.0 / z2;
+  if (ew) n.w *= sqrt(cs * n.z1 * z2);   // energy weights: Q^2 sqrt(c s zeta1 zeta2) per node
   return n;
 }
 __device__ __forceinline__ Node box_node_at(const PBuildArgs& a, const double* tab, int nd) {
-  return box_node_at_p(a.gx, a.gwx, a.gwp, a.n_phi, tab, nd);
+  return box_node_at_p(a.gx, a.gwx, a.gwp, a.n_phi, tab, nd, a.ew != 0);
+}
+// F of one node and cell pair for U > L: (U^2 - L^2) / 2 (unit weights) or U^4 - L^4 (energy)
+__device__ __forceinline__ double f_of(double U, double L, bool ew) {
+  return ew ? (U - L) * (U + L) * fma(U, U, L * L) : 0.5 * (U - L) * (U + L);
+}
+// a bin's width in the norm of a P0 element: p_i - p_{i-1}, or p_i^2 - p_{i-1}^2 (energy weights)
+__device__ __forceinline__ double bin_w(double lo, double hi, bool ew) {
+  return ew ? (hi - lo) * (hi + lo) : hi - lo;
 }
 // the phi table of box (j, jp) in LDS, filled by the first n_phi threads of the workgroup
 __device__ __forceinline__ void fill_phi_table(const PBuildArgs& a, int j, int jp, double* tab) {
@@ -215,7 +224,8 @@ __global__ void __launch_bounds__(256) k_node_table(PBuildArgs a, double* __rest
     g[3] = n.Q2;
     double* x = aux + k * AS;
     x[0] = n.z1;
-    for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? 0.5 * moment_weight(n, a.keys + 5 * m) : 0.0;
+    const double half = a.ew ? 1.0 : 0.5;   // energy weights: no 1/2 in F
+    for (int m = 0; m < AS - 1; ++m) x[1 + m] = m < a.nmom ? half * moment_weight(n, a.keys + 5 * m) : 0.0;
   }
 }
 
@@ -681,7 +691,7 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
   }
   __syncthreads();
 
-  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  const double dq = bin_w(a.qe[j], a.qe[j + 1], a.ew), dqp = bin_w(a.qe[jp], a.qe[jp + 1], a.ew);
   const int nc = a.nch, nc2 = nc * nc;
   for (int e = t; e < total; e += 64) {
     // row i: last i with pref[i] <= e
@@ -701,12 +711,12 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
       const double r1 = s_r1[nd], r2 = s_r2[nd];
       const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
       const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
-      const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+      const double F = (U > L) ? f_of(U, L, a.ew != 0) : 0.0;
 #pragma unroll
       for (int m = 0; m < NMOM; ++m)
         if (m < a.nmom) mom[m] = fma(s_w[m * nn + nd], F, mom[m]);
     }
-    const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+    const double norm = 1.0 / sqrt(bin_w(pa, pb, a.ew) * dq * bin_w(ppa, ppb, a.ew) * dqp);
     const int64_t blk = rowptr_c[(size_t)j * M + i] + segoff[(size_t)box * M + i] + (ip - s_lo[i]);
     if (blk >= cap) continue;   // the candidate arrays are too small: the caller sees the total and builds again
     col_c[blk] = jp * M + ip;
@@ -730,7 +740,7 @@ __global__ void __launch_bounds__(64) k_pbuild(PBuildArgs a, const int* __restri
 // fma(w / 2, max(U - L, 0) (U + L), mom): U + L > 0, and scaling by 1/2 commutes with rounding,
 // so this is the same number as fma(w, F, mom) with one compare and two selects fewer.
 // One wavefront per box, BPW boxes per workgroup (coefficients and p edges shared in LDS).
-template <int NMOM>
+template <int NMOM, bool EW>
 __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const double* __restrict__ geo,
                                                          const double* __restrict__ aux, int AS,
                                                          const int* __restrict__ cnt, const int* __restrict__ lo,
@@ -796,7 +806,7 @@ __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const dou
   }
   __syncthreads();
   if (total == 0) return;
-  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  const double dq = bin_w(a.qe[j], a.qe[j + 1], a.ew), dqp = bin_w(a.qe[jp], a.qe[jp + 1], a.ew);
   for (int e0 = 0; e0 < total; e0 += 64) {
     const int e = min(e0 + t, total - 1);
     int lo_i = 0, hi_i = M - 1;   // row: last i with pref[i] <= e
@@ -817,14 +827,15 @@ __global__ void __launch_bounds__(64 * BPW) k_pbuild_tab(PBuildArgs a, const dou
       const double r1 = q[0], r2 = q[1], Q1 = q[2], Q2 = q[3];
       const double U = fmin(Q2, fmin(ppb * r1, pb * r2));
       const double L = fmax(Q1, fmax(ppa * r1, pa * r2));
-      const double F2 = fmax(U - L, 0.0) * (U + L);   // 2 F
+      double F2 = fmax(U - L, 0.0) * (U + L);   // 2 F (unit weights), with the unhalved weight:
+      if (EW) F2 *= fma(U, U, L * L);           // U^4 - L^4 (energy weights)
 #pragma unroll
       for (int m = 0; m < NMOM; ++m) mom[m] = fma(q[5 + m], F2, mom[m]);
     }
     const int64_t blk = s_base[i] + e;
     // past the end, or the candidate arrays are too small (the caller sees the total and builds again)
     if (e0 + t >= total || blk >= cap) continue;
-    const double norm = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+    const double norm = 1.0 / sqrt(bin_w(pa, pb, EW) * dq * bin_w(ppa, ppb, EW) * dqp);
     bool nz = false;
     for (int gg = 0; gg < nc2; ++gg) {
       double v = 0.0;
@@ -850,12 +861,18 @@ hipError_t launch_pbuild_tab(const PBuildArgs& a, const double* geo, const doubl
   const size_t sh = (size_t)(a.nch * a.nch * a.nmom + a.M + 1) * sizeof(double) + BPW * per_wave;
   if (sh > 64 * 1024) return hipErrorInvalidValue;
   dim3 g((a.N * a.N + BPW - 1) / BPW), b(64 * BPW);
-  if (a.nmom <= 1)
-    hipLaunchKernelGGL(k_pbuild_tab<1>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
-  else if (a.nmom <= 2)
-    hipLaunchKernelGGL(k_pbuild_tab<2>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
-  else
-    hipLaunchKernelGGL(k_pbuild_tab<4>, g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, flag, cap);
+#define WP_TAB(NM, EW) \
+  hipLaunchKernelGGL((k_pbuild_tab<NM, EW>), g, b, sh, s, a, geo, aux, AS, cnt, lo, segoff, rowptr_c, col_c, val_c, \
+                     flag, cap)
+  const bool ew = a.ew != 0;
+  if (a.nmom <= 1) {
+    if (ew) WP_TAB(1, true); else WP_TAB(1, false);
+  } else if (a.nmom <= 2) {
+    if (ew) WP_TAB(2, true); else WP_TAB(2, false);
+  } else {
+    if (ew) WP_TAB(4, true); else WP_TAB(4, false);
+  }
+#undef WP_TAB
   return hipGetLastError();
 }
 
@@ -1282,6 +1299,95 @@ __global__ void __launch_bounds__(256) k_g1_wave(G1Args g) {
   }
 }
 
+// Energy-weight packets (Sec. III.B, footnote to eqs. dg1a, dg1b): with |w|^2 dp = d eps and
+// |f|^2 dq = d eps_q both elements are integrals over energy intervals, x = h p^2 over the
+// pseudostate bin (width C), y = b3 q^2 over the q bin (width B).
+// Bound-continuum: (1/B) int dy / (E + i0 - eps_n - y) = (1/B) [ln(z1) - ln(z2)],
+// z_b = E - eps_n - y_b; Im = -pi / B where z1 > 0 >= z2 (the on-shell bin).
+__device__ double2 g1_bound_energy(double qa, double qb, double E, double eps0, double h2m) {
+  const double b3 = 0.75 * h2m;
+  const double B = b3 * (qb - qa) * (qb + qa);
+  const double z1 = (E - eps0) - b3 * qa * qa, z2 = z1 - B;
+  const bool on = z1 > 0.0 && z2 <= 0.0;
+  const double re = on ? log(z1 / -z2) : log1p(B / z2);   // ln|z1 / z2| = ln|1 + B / z2|
+  return make_double2(re / B, on ? -M_PI / B : 0.0);
+}
+// Continuum: (1/(C B)) int int dx dy / (E + i0 - x - y). The x + y cross-sections of the box have
+// the trapezoidal length l(s) (rising over min(C, B), flat, falling), so the element is the mean of
+// 1 / (E + i0 - s) under the density l(s) / (C B) of s = X + Y, X, Y uniform on the two bins.
+// Im = -pi l(E) / (C B). Re: away from the box (|E - s_c| > 2 (C + B), s_c its centre) the
+// expansion 1/(d - u) = sum_n u^n / d^(n+1) over the even central moments of X + Y,
+//   mu_n = sum_{k even} binom(n, k) (C/2)^k / (k + 1) (B/2)^(n-k) / (n - k + 1),
+// converges by a factor below 1/16 per term; nearer, the closed form, the sum of +-z ln|z| over
+// the corners z = E - x_a - y_b, taken as psi_s(z_s) - psi_s(z_s - l) with s = min(C, B), l the other
+// width, z_s the corner z11 - s and psi_s(u) = (u + s) ln|u + s| - u ln|u| = s ln|u + s| +
+// u ln|1 + s/u| (log1p where u and u + s have one sign): the difference over the small width is
+// formed without cancellation, and the one over the large width cancels at most a few digits.
+__device__ __forceinline__ double g1_psi(double u, double s) {
+  const double v = u + s;
+  if (u == 0.0) return s * log(s);
+  if (v == 0.0) return s * log(s);
+  if ((u > 0.0) == (v > 0.0)) return s * log(fabs(v)) + u * log1p(s / u);
+  return v * log(fabs(v)) - u * log(fabs(u));
+}
+__device__ double2 g1_continuum_energy(double pa, double pb, double qa, double qb, double E, double h2m) {
+  const double h = h2m, b3 = 0.75 * h2m;
+  const double x1 = h * pa * pa, y1 = b3 * qa * qa;
+  const double C = h * (pb - pa) * (pb + pa), B = b3 * (qb - qa) * (qb + qa);
+  const double s0 = x1 + y1;
+  const double ell = fmax(0.0, fmin(fmin(E - s0, s0 + C + B - E), fmin(C, B)));
+  const double im = -M_PI * ell / (C * B);
+  const double d = E - (s0 + 0.5 * (C + B));
+  double re;
+  if (fabs(d) > 2.0 * (C + B)) {
+    const double a = 0.5 * C / d, b = 0.5 * B / d;
+    // sum over even n of sum over even k of binom(n, k) a^k / (k + 1) b^(n-k) / (n - k + 1)
+    double sum = 0.0;
+    double ak[32], bk[32];   // a^k / (k + 1), b^k / (k + 1)
+    ak[0] = 1.0;
+    bk[0] = 1.0;
+    double pa_ = 1.0, pb_ = 1.0;
+    for (int k = 1; k < 32; ++k) {
+      pa_ *= a;
+      pb_ *= b;
+      ak[k] = pa_ / (k + 1);
+      bk[k] = pb_ / (k + 1);
+    }
+    for (int n = 30; n >= 0; n -= 2) {   // smallest terms first
+      double t = 0.0, binom = 1.0;       // binom(n, k) for k = 0, 2, ...
+      for (int k = 0; k <= n; k += 2) {
+        t += binom * ak[k] * bk[n - k];
+        binom *= (double)(n - k) * (n - k - 1) / ((k + 1.0) * (k + 2.0));
+      }
+      sum += t;
+    }
+    re = sum / d;
+  } else {
+    const double sw = fmin(C, B), lw = fmax(C, B);
+    const double zs = (E - x1 - y1) - sw;
+    re = (g1_psi(zs, sw) - g1_psi(zs - lw, sw)) / (C * B);
+  }
+  return make_double2(re, im);
+}
+
+// One lane per element, energy-weight packets.
+__global__ void __launch_bounds__(256) k_g1_energy(G1Args g) {
+  const int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
+  if (el >= n) return;
+  const G1Elem d = g1_decode(g, el);
+  const double E = g.E[d.e];
+  const int nb = g.nb[d.w];
+  double2 v;
+  if (d.k < nb) {
+    v = g1_bound_energy(g.qe[d.j], g.qe[d.j + 1], E, g.eps_b[d.w], g.h2m);
+  } else {
+    const double* bins = g.bins + (size_t)d.w * (g.M + 1);
+    v = g1_continuum_energy(bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1], E, g.h2m);
+  }
+  g1_store(g, d, v, 0, 1);
+}
+
 __global__ void k_zero_i32(int* p) {
   if (threadIdx.x == 0) p[0] = 0;
 }
@@ -1292,6 +1398,10 @@ hipError_t launch_g1(const G1Args& g, hipStream_t s) {
   if (g.M < 1 || g.N < 1 || g.nE < 1 || g.nwave < 1 || g.nrep < 1 || !g.wl || !g.wl_n) return hipErrorInvalidValue;
   if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
   const int64_t n = g1_work_elems(g.nwave, g.M, g.N, g.nE);
+  if (g.ew) {
+    hipLaunchKernelGGL(k_g1_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, g.wl_n);
   hipLaunchKernelGGL(k_g1_lane, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s, g);
   const int64_t wblocks = std::min<int64_t>(2048, std::max<int64_t>(1, (n + 3) / 4));
@@ -1949,7 +2059,7 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
     s_Q2[nd] = n.Q2;
   }
   __syncthreads();
-  const double dq = a.qe[j + 1] - a.qe[j], dqp = a.qe[jp + 1] - a.qe[jp];
+  const double dq = bin_w(a.qe[j], a.qe[j + 1], a.ew), dqp = bin_w(a.qe[jp], a.qe[jp + 1], a.ew);
   for (int m0 = 0; m0 < a.nmom; m0 += MCH) {
     const int mc = min(MCH, a.nmom - m0);
     __syncthreads();
@@ -1976,7 +2086,7 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
         const double r1 = s_r1[nd], r2 = s_r2[nd];
         const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
         const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
-        const double F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+        const double F = (U > L) ? f_of(U, L, a.ew != 0) : 0.0;
         if (F != 0.0) {
 #pragma unroll
           for (int m = 0; m < MCH; ++m) acc[m] = fma(s_w[m * nn + nd], F, acc[m]);
@@ -1986,7 +2096,7 @@ __global__ void __launch_bounds__(256) k_pbuild_mom(PBuildArgs a, const int* __r
       for (int m = 0; m < mc; ++m) mom[blk * a.nmom + m0 + m] = acc[m];
       if (m0 == 0) {
         col_c[blk] = jp * M + ip;
-        norm[blk] = 1.0 / sqrt((pb - pa) * dq * (ppb - ppa) * dqp);
+        norm[blk] = 1.0 / sqrt(bin_w(pa, pb, a.ew) * dq * bin_w(ppa, ppb, a.ew) * dqp);
       }
     }
   }
@@ -2402,11 +2512,16 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
       __syncthreads();
       continue;
     }
-    // 1/zeta powers of every (node, l, l') over all threads
+    // 1/zeta powers of every (node, l, l') over all threads (energy weights: times the node
+    // factor sqrt(c s zeta1 zeta2))
     for (int y = tid; y < nn * LLP; y += 256) {
       const int nd = y / LLP, x = y - nd * LLP, l = x / f.LP, lp = x - l * f.LP;
       const double r1 = s_r1[nd], r2 = s_r2[nd];
       double w = 1.0;
+      if (a.ew) {
+        const double* t = s_phi + (nd % n_phi) * PHI_STRIDE;
+        w = sqrt(t[0] * t[1] / (r1 * r2));
+      }
       for (int e = 0; e <= lp; ++e) w *= r1;
       for (int e = 0; e <= l; ++e) w *= r2;
       s_RR[y] = w;
@@ -2437,7 +2552,7 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
       __builtin_amdgcn_sched_barrier(0);   // bounds the table reads in flight (registers)
     }
     __syncthreads();   // the weight tables are overwritten by the candidate tiles below
-    const double dq = s_qe[j + 1] - s_qe[j], dqp = s_qe[jp + 1] - s_qe[jp];
+    const double dq = bin_w(s_qe[j], s_qe[j + 1], a.ew), dqp = bin_w(s_qe[jp], s_qe[jp + 1], a.ew);
     for (int c0 = 0; c0 < total; c0 += FZ_LCH) {
       // the kept candidates among [c0, c0 + FZ_LCH), in candidate order
       const int e = c0 + tid;
@@ -2466,7 +2581,7 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
         s_li[pos] = i;
         s_lip[pos] = ip;
         s_ld[pos] = (int)d;
-        s_nrm[pos] = 1.0 / sqrt((s_pe[i + 1] - s_pe[i]) * dq * (s_pe[ip + 1] - s_pe[ip]) * dqp);
+        s_nrm[pos] = 1.0 / sqrt(bin_w(s_pe[i], s_pe[i + 1], a.ew) * dq * bin_w(s_pe[ip], s_pe[ip + 1], a.ew) * dqp);
         col[d] = jp * M + ip;
       }
       __syncthreads();
@@ -2488,7 +2603,7 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
               const double r1 = s_r1[nd], r2 = s_r2[nd];
               const double U = fmin(s_Q2[nd], fmin(ppb * r1, pb * r2));
               const double L = fmax(s_Q1[nd], fmax(ppa * r1, pa * r2));
-              F = (U > L) ? 0.5 * (U - L) * (U + L) : 0.0;
+              F = (U > L) ? f_of(U, L, a.ew != 0) : 0.0;
             }
             s_F[r * FST + nd] = F;
           }

@@ -38,6 +38,10 @@ std::vector<double> h0_diagonal(const std::vector<double>& edges, double h2m);
 // NN potential in the free WP basis (M x M, row-major).
 std::vector<double> yamaguchi_form(const std::vector<double>& edges, double beta);
 std::vector<double> yukawa_wp(const std::vector<double>& edges, int l, double mu);
+// energy-weight packets (weight sqrt(2 h2m p), norm h2m (p_i^2 - p_{i-1}^2))
+std::vector<double> h0_diagonal_energy(const std::vector<double>& edges, double h2m);
+std::vector<double> yamaguchi_form_energy(const std::vector<double>& edges, double beta);
+std::vector<double> yukawa_wp_energy(const std::vector<double>& edges, int l, double mu);
 
 // Symmetric eigenproblem: Householder tridiagonalisation + implicit QL.
 // a (n x n row-major, destroyed) -> eigenvalues ascending in d, eigenvectors as ROWS of z.
@@ -129,6 +133,8 @@ struct PBuildArgs {
   const double* gwp;   // weights [n_phi]
   const int* keys;     // device [nmom][5]
   const double* C;     // device [nch][nch][nmom]
+  int ew = 0;          // energy-weight packets: F = U^4 - L^4, node factor sqrt(c s zeta1 zeta2),
+                       // widths p_i^2 - p_{i-1}^2 in the norm (unit weights otherwise)
 };
 
 // Selection (step 2): per q-box and p-row the hull [lo, lo + cnt) of possibly nonzero p' bins.
@@ -270,6 +276,7 @@ struct G1Args {
   double2* G;
   int64_t* wl;          // work list (g1_work_elems entries) and its counter
   int* wl_n;
+  int ew = 0;           // energy-weight packets: closed forms, one lane per element (no work list)
 };
 int64_t g1_work_elems(int nwave, int M, int N, int nE);
 hipError_t launch_g1(const G1Args& g, hipStream_t s);

@@ -46,6 +46,7 @@ struct wp_lattice {
   DevAlloc al;
   int M = 0, N = 0, nch = 0, two_J = 1, n_x = 8, n_phi = 8;
   double h2m = 41.471;
+  int weights = WP_WEIGHTS_UNIT;
   std::vector<double> pe, qe;
   std::vector<Chan> ch;
   std::vector<MomKey> keys;
@@ -130,6 +131,7 @@ inline PackView pk_view(const wp_lattice* L, int spmm_cols = 0) {
 
 struct EnergyResult {
   double E_lab, E, q0, dq0;
+  double afac;   // A = afac U: 2 / (3 h2m q0 dq_j0) (unit weights) or 1 / B_j0 (energy weights)
   int j0;
   int n_open;
   std::vector<cplx> U;      // [final][initial]
@@ -225,6 +227,9 @@ inline bool kinematics(const wp_lattice* L, double E_lab, EnergyResult& r) {
   if (jj < 0) return false;
   r.j0 = jj;
   r.dq0 = L->qe[jj + 1] - L->qe[jj];
+  r.afac = L->weights == WP_WEIGHTS_ENERGY
+               ? 1.0 / (0.75 * L->h2m * (L->qe[jj + 1] * L->qe[jj + 1] - L->qe[jj] * L->qe[jj]))
+               : 2.0 / (3.0 * L->h2m * r.q0) / r.dq0;
   r.n_open = (int)L->opens.size();
   r.U.assign(r.n_open * r.n_open, cplx(0, 0));
   r.err.assign(r.n_open, 0.0);

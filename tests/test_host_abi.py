@@ -104,3 +104,33 @@ def test_lattice_info_matches_the_oracle_rule():
         assert L.nmom == len(s.P0geo.keys)
         nz = int(np.any(s.C != 0.0, axis=2).sum())
         assert L.n_stored == (nz if L.nch > 4 else L.nch ** 2), (L.n_stored, nz)
+
+
+@pytest.mark.parametrize("pot,two_J", [("yamaguchi", 3), ("mt", 1)])
+def test_energy_weight_pseudostates_match_oracle(pot, two_J):
+    """Energy-weight packets (Sec. III.B footnote): h0, potential, strength tuning, pseudostates and
+    the energy bins against the oracle."""
+    M = 16
+    L = wp.Lattice(M, M, two_J=two_J, torch_alloc=False, weights="energy")
+    eps0, strength = L.pseudostates(kind=pot)
+    s = pipeline.build_system(pipeline.Spec(M=M, N=M, two_J=two_J, pot=pot, weights="energy"))
+    assert strength == pytest.approx(s.strength, rel=1e-11)
+    assert eps0 == pytest.approx(-2.2246, abs=1e-12)
+    for a, ch in enumerate(L.channels):
+        nb, eps, O, bins = L.pseudostate_data(a)
+        d = s.pair[(ch[0], ch[1])]
+        assert nb == d["nb"]
+        assert np.allclose(eps, d["eps"], rtol=1e-10, atol=1e-10)
+        assert np.allclose(O, d["O"], atol=1e-9)
+        assert np.allclose(bins, d["bins"], rtol=1e-11)
+
+
+def test_weights_call_order():
+    L = wp.Lattice(8, 8, two_J=3, torch_alloc=False)
+    assert wp._lib.wp_lattice_weights(L.h, 7) == wp.WP_EINVAL
+    assert wp._lib.wp_lattice_weights(L.h, wp.WP_WEIGHTS_ENERGY) == wp.WP_OK
+    L.pseudostates(kind="yamaguchi")
+    assert wp._lib.wp_lattice_weights(L.h, wp.WP_WEIGHTS_UNIT) == wp.WP_EINVAL
+    assert b"before twobody_pseudostates" in wp._lib.wp_last_error()
+    with pytest.raises(ValueError):
+        wp.Lattice(8, 8, torch_alloc=False, weights="momentum")
