@@ -18,8 +18,9 @@ refinement; 2 energies x 2 open channels = 4 solves). The JSON line reports
 plus solves/s, the largest amplitude error against the oracle's values of the same lattice
 (tests/golden/pw_mt_150.json), the roofline of the dominant kernel (HIP events around every
 launch, inside the timed region) and the oracle timed on the host cores (cpu_baseline, run first,
-before the GPU is touched). Extras: the s-wave M = N = 100 lattice pair, 64 batched energies,
-the continuous-batching service, and (--sweep) the s-wave build for M = N = 40..400.
+before the GPU is touched). Extras: breakup elements, energy-weight packets on the same lattice,
+the s-wave M = N = 100 lattice pair, 64 batched energies, the continuous-batching service, and
+(--sweep) the s-wave build for M = N = 40..400.
 """
 from __future__ import annotations
 
@@ -75,7 +76,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured length of the serving stream")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up length of the serving stream")
     ap.add_argument("--sweep", action="store_true", help="also time the s-wave P0 build for M = N in 40..400")
-    ap.add_argument("--only", choices=["batched", "serving", "swave", "sweep"], default=None,
+    ap.add_argument("--only", choices=["batched", "serving", "swave", "sweep", "energy"], default=None,
                     help="run only this extra section (no headline step); for profiling runs")
     return ap.parse_args()
 
@@ -265,6 +266,63 @@ def breakup_section(wp, torch, L, Es, reps=5):
     return dict(E_lab=list(Es), cells_per_energy=cells, solve_ms=t_plain * 1e3, solve_ms_with_breakup=t_bu * 1e3,
                 projection_kernel_ms=round(prof.get("breakup", (0, 0.0))[1], 4),
                 max_abs_element=[float(np.max(np.abs(sol.breakup(k, 0)[1]), initial=0.0)) for k in range(len(Es))])
+
+
+def energy_weights_section(wp, torch, V_R, Es, unit_lat, unit_g1_ms, reps=3):
+    """Energy-weight packets (weights ~ sqrt(p), sqrt(q); closed-form G1) on the headline lattice:
+    one step (build + the headline solve) against the unit-weight step, the G1 launch of each,
+    and both weightings' amplitudes. Then the quartet s-wave phase (Yamaguchi, 1 and 3 MeV) of
+    both weightings as the lattice grows: the result is independent of the partition only in the
+    limit, and how fast each weighting gets there is the accuracy comparison."""
+    wl = workloads.WORKLOADS[WORKLOAD]
+    sysd = wl["systems"][0]
+    L = wp.Lattice(wl["M"], wl["N"], two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"],
+                   n_x=wl["n_x"], n_phi=wl["n_phi"], weights="energy")
+    L.pseudostates(kind="mt", V_R=V_R)
+
+    def step(acc):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.build_perm("fp32")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sol = L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL)
+        torch.cuda.synchronize()
+        acc["build"] += t1 - t0
+        acc["solve"] += time.perf_counter() - t1
+        acc["sol"] = sol
+    step(dict(build=0.0, solve=0.0))
+    acc = dict(build=0.0, solve=0.0)
+    for _ in range(reps):
+        step(acc)
+    wp.wp_profile_reset()
+    wp.wp_profile_enable(True)
+    step(dict(build=0.0, solve=0.0))
+    torch.cuda.synchronize()
+    wp.wp_profile_enable(False)
+    prof = wp.wp_profile_read()
+    unit = unit_lat.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL)
+    amps = {}
+    for k, E in enumerate(Es):
+        Ae, Au = acc["sol"].amplitude(k), unit.amplitude(k)
+        amps[str(E)] = dict(delta_deg_energy=[float(x) for x in Ae["delta"]],
+                            delta_deg_unit=[float(x) for x in Au["delta"]],
+                            max_abs_dA_energy_vs_unit=float(np.max(np.abs(Ae["A"] - Au["A"]))))
+    conv = []
+    for Mq in (24, 48, 64, 100, 150):
+        row = dict(M=Mq)
+        for w in ("unit", "energy"):
+            Lq = wp.Lattice(Mq, Mq, two_J=3, weights=w)
+            Lq.pseudostates(kind="yamaguchi")
+            Lq.build_perm("fp64")
+            sq = Lq.solve([1.0, 3.0], "fp64", accept=1e-6)
+            row[w] = [float(sq.amplitude(k)["delta"][0]) for k in range(2)]
+        conv.append(row)
+    return dict(step_ms_build=acc["build"] / reps * 1e3, step_ms_solve=acc["solve"] / reps * 1e3,
+                P_elements=L.perm_stats["nnz"], P_elements_per_s=L.perm_stats["nnz"] * reps / acc["build"],
+                g1_ms_per_call_energy=round(prof.get("g1", (1, 0.0))[1] / max(1, prof.get("g1", (1, 0.0))[0]), 4),
+                g1_ms_per_call_unit=unit_g1_ms, kernels_ms_per_step={k: round(v[1], 4) for k, v in prof.items()},
+                amplitudes=amps, quartet_phase_deg_1_and_3_MeV_vs_M=conv)
 
 
 def swave_section(wp, torch, V_R, reps=10):
@@ -499,6 +557,22 @@ def main():
             res, _ = swave_section(wp, torch, V_R)
         elif args.only == "sweep":
             res = sweep_section(wp, torch, V_R)
+        elif args.only == "energy":
+            wl = workloads.WORKLOADS[WORKLOAD]
+            sysd = wl["systems"][0]
+            L = wp.Lattice(wl["M"], wl["N"], two_J=sysd["two_J"], j_max=sysd["j_max"], swave_only=sysd["swave"],
+                           n_x=wl["n_x"], n_phi=wl["n_phi"])
+            L.pseudostates(kind="mt", V_R=V_R)
+            L.build_perm("fp32")
+            Es = list(wl["E_lab"])
+            L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL)
+            wp.wp_profile_reset()
+            wp.wp_profile_enable(True)
+            L.solve(Es, HEADLINE_MODE, tol=HEADLINE_TOL)
+            torch.cuda.synchronize()
+            wp.wp_profile_enable(False)
+            g1u = wp.wp_profile_read().get("g1", (1, 0.0))
+            res = energy_weights_section(wp, torch, V_R, Es, L, round(g1u[1] / max(1, g1u[0]), 4))
         else:
             L = wp.Lattice(100, 100, two_J=1)
             L.pseudostates(kind="mt", V_R=V_R)
@@ -600,6 +674,8 @@ def main():
     }
     if not args.no_extras:
         out["breakup"] = breakup_section(wp, torch, L, Es)
+        g1u = prof.get("g1", (1, 0.0))
+        out["energy_weights"] = energy_weights_section(wp, torch, V_R, Es, L, round(g1u[1] / max(1, g1u[0]), 4))
         sw, sw_lats = swave_section(wp, torch, V_R)
         out["swave_mt_100"] = sw
         out["batched_64_energies"] = batched_energies_section(wp, torch, sw_lats[0])

@@ -1316,8 +1316,7 @@ __device__ double2 g1_bound_energy(double qa, double qb, double E, double eps0, 
 // the trapezoidal length l(s) (rising over min(C, B), flat, falling), so the element is the mean of
 // 1 / (E + i0 - s) under the density l(s) / (C B) of s = X + Y, X, Y uniform on the two bins.
 // Im = -pi l(E) / (C B). Re: away from the box (|E - s_c| > 2 (C + B), s_c its centre) the
-// expansion 1/(d - u) = sum_n u^n / d^(n+1) over the even central moments of X + Y,
-//   mu_n = sum_{k even} binom(n, k) (C/2)^k / (k + 1) (B/2)^(n-k) / (n - k + 1),
+// expansion 1/(d - u) = sum_n u^n / d^(n+1) over the even central moments mu_n of X + Y
 // converges by a factor below 1/16 per term; nearer, the closed form, the sum of +-z ln|z| over
 // the corners z = E - x_a - y_b, taken as psi_s(z_s) - psi_s(z_s - l) with s = min(C, B), l the other
 // width, z_s the corner z11 - s and psi_s(u) = (u + s) ln|u + s| - u ln|u| = s ln|u + s| +
@@ -1340,28 +1339,26 @@ __device__ double2 g1_continuum_energy(double pa, double pb, double qa, double q
   const double d = E - (s0 + 0.5 * (C + B));
   double re;
   if (fabs(d) > 2.0 * (C + B)) {
-    const double a = 0.5 * C / d, b = 0.5 * B / d;
-    // sum over even n of sum over even k of binom(n, k) a^k / (k + 1) b^(n-k) / (n - k + 1)
+    // mu_n = 2 (P^(n+2) - Q^(n+2)) / ((n + 1)(n + 2) C B), P = (C + B)/2, Q = (C - B)/2 (n even), so
+    // re = (2 d / (C B)) sum_{n even} D_(n+2) / ((n + 1)(n + 2)) with D_m = p^m - q^m, p = P/d,
+    // q = Q/d, from D_1 = B/d, D_2 = B C / d^2 and D_(m+2) = (p + q) D_(m+1) - p q D_m (the
+    // differences are never formed from the powers themselves)
+    const double sc = C / d, tb = B / d;
+    const double pq = 0.25 * (sc - tb) * (sc + tb);
+    double dm = tb, dm1 = tb * sc;
+    double t[16];
+#pragma unroll
+    for (int h2 = 0; h2 < 16; ++h2) {   // n = 2 h2
+      t[h2] = dm1 * (1.0 / ((2.0 * h2 + 1.0) * (2.0 * h2 + 2.0)));   // a constant once unrolled
+      const double d3 = fma(sc, dm1, -pq * dm);
+      const double d4 = fma(sc, d3, -pq * dm1);
+      dm = d3;
+      dm1 = d4;
+    }
     double sum = 0.0;
-    double ak[32], bk[32];   // a^k / (k + 1), b^k / (k + 1)
-    ak[0] = 1.0;
-    bk[0] = 1.0;
-    double pa_ = 1.0, pb_ = 1.0;
-    for (int k = 1; k < 32; ++k) {
-      pa_ *= a;
-      pb_ *= b;
-      ak[k] = pa_ / (k + 1);
-      bk[k] = pb_ / (k + 1);
-    }
-    for (int n = 30; n >= 0; n -= 2) {   // smallest terms first
-      double t = 0.0, binom = 1.0;       // binom(n, k) for k = 0, 2, ...
-      for (int k = 0; k <= n; k += 2) {
-        t += binom * ak[k] * bk[n - k];
-        binom *= (double)(n - k) * (n - k - 1) / ((k + 1.0) * (k + 2.0));
-      }
-      sum += t;
-    }
-    re = sum / d;
+#pragma unroll
+    for (int h2 = 15; h2 >= 0; --h2) sum += t[h2];   // smallest terms first
+    re = 2.0 * d / (C * B) * sum;
   } else {
     const double sw = fmin(C, B), lw = fmax(C, B);
     const double zs = (E - x1 - y1) - sw;
@@ -1370,22 +1367,30 @@ __device__ double2 g1_continuum_energy(double pa, double pb, double qa, double q
   return make_double2(re, im);
 }
 
-// One lane per element, energy-weight packets.
+// Energy-weight packets: one thread per output G[row * B + col0 + c], row = (j M + k) nch + ch,
+// c = e nrep + f, consecutive threads writing consecutive addresses; the closed forms are cheap
+// enough to evaluate again for every channel of a pair wave and every column of an energy.
 __global__ void __launch_bounds__(256) k_g1_energy(G1Args g) {
-  const int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)g.nwave * g.M * g.N * g.nE;
-  if (el >= n) return;
-  const G1Elem d = g1_decode(g, el);
-  const double E = g.E[d.e];
-  const int nb = g.nb[d.w];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int W = g.nE * g.nrep;
+  const int64_t n = (int64_t)g.M * g.N * g.nch * W;
+  if (t >= n) return;
+  const int64_t row = t / W;
+  const int c = (int)(t - row * W);
+  const int ch = (int)(row % g.nch);
+  const int64_t jk = row / g.nch;
+  const int k = (int)(jk % g.M), j = (int)(jk / g.M);
+  const int w = g.wave[ch];
+  const double E = g.E[c / g.nrep];
+  const int nb = g.nb[w];
   double2 v;
-  if (d.k < nb) {
-    v = g1_bound_energy(g.qe[d.j], g.qe[d.j + 1], E, g.eps_b[d.w], g.h2m);
+  if (k < nb) {
+    v = g1_bound_energy(g.qe[j], g.qe[j + 1], E, g.eps_b[w], g.h2m);
   } else {
-    const double* bins = g.bins + (size_t)d.w * (g.M + 1);
-    v = g1_continuum_energy(bins[d.k - nb], bins[d.k - nb + 1], g.qe[d.j], g.qe[d.j + 1], E, g.h2m);
+    const double* bins = g.bins + (size_t)w * (g.M + 1);
+    v = g1_continuum_energy(bins[k - nb], bins[k - nb + 1], g.qe[j], g.qe[j + 1], E, g.h2m);
   }
-  g1_store(g, d, v, 0, 1);
+  g.G[row * g.B + g.col0 + c] = v;
 }
 
 __global__ void k_zero_i32(int* p) {
@@ -1399,7 +1404,8 @@ hipError_t launch_g1(const G1Args& g, hipStream_t s) {
   if (g.col0 < 0 || g.col0 + (int64_t)g.nE * g.nrep > g.B) return hipErrorInvalidValue;
   const int64_t n = g1_work_elems(g.nwave, g.M, g.N, g.nE);
   if (g.ew) {
-    hipLaunchKernelGGL(k_g1_energy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g);
+    const int64_t nout = (int64_t)g.M * g.N * g.nch * g.nE * g.nrep;
+    hipLaunchKernelGGL(k_g1_energy, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, g);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, g.wl_n);
