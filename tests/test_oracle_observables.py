@@ -132,3 +132,40 @@ def test_eigenphases_reconstruct_s():
         d, O = ob.eigenphases(S)
         assert np.allclose(O @ np.diag(np.exp(2j * d)) @ O.T, S, atol=1e-13)
         assert np.allclose(O.T @ O, np.eye(len(d)), atol=1e-13)
+
+
+def _spin_free_blocks(s_lam, two_J_max=9):
+    """Blocks whose channel-spin S is s_lam[lam] on the diagonal for every J and Sigma (scattering
+    that does not see the spins), returned in the jj basis (S_jj = T^T S_Sigma T)."""
+    out = []
+    for two_J in range(1, two_J_max + 1, 2):
+        for par in (1, -1):
+            chans = [(c[3], c[4]) for c in channels.enumerate_channels(two_J, par, 1)
+                     if c[0] == 0 and c[1] == 1 and c[2] == 1]
+            sig, T = ob.sigma_transform(two_J, chans)
+            Ss = np.diag([s_lam[lam] for lam, _ in sig])
+            out.append((two_J, chans, T.T @ Ss @ T))
+    return out
+
+
+def spinless_cross_section(s_lam, k, theta):
+    """|f|^2 with f = sum_lam (2 lam + 1) (s_lam - 1) / (2 i k) P_lam(cos theta)."""
+    from numpy.polynomial import legendre
+    c = [(2 * l + 1) * (s_lam[l] - 1.0) / (2j * k) for l in range(len(s_lam))]
+    return np.abs(legendre.legval(np.cos(theta), c)) ** 2
+
+
+def test_spin_free_scattering_has_no_analysing_power():
+    """S independent of Sigma and J (per lam): the amplitude is spin-independent, A_y = 0 and
+    dsigma/dOmega is the spinless |f|^2."""
+    rng = np.random.default_rng(4)
+    # lam <= 3 scatter: up to J = 9/2 every (lam, Sigma, J) of these lam is present; higher lam
+    # (incomplete shells) do not scatter
+    s_lam = np.ones(8, dtype=complex)
+    s_lam[:4] = np.exp(2j * rng.uniform(-1.2, 1.2, 4)) * rng.uniform(0.6, 1.0, 4)
+    blocks = _spin_free_blocks(s_lam)
+    th = np.linspace(0.0, np.pi, 11)
+    k = 0.8
+    ds, ay = ob.observables(blocks, k, th)
+    assert np.max(np.abs(ay)) <= 1e-12
+    assert np.allclose(ds, spinless_cross_section(s_lam, k, th), rtol=1e-11)
