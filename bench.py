@@ -19,6 +19,7 @@ plus solves/s, the largest amplitude error against the oracle's values of the sa
 (tests/golden/pw_mt_150.json), the roofline of the dominant kernel (HIP events around every
 launch, inside the timed region) and the oracle timed on the host cores (cpu_baseline, run first,
 before the GPU is touched). Extras: breakup elements, energy-weight packets on the same lattice,
+elastic observables summed over 18 J^pi blocks,
 the s-wave M = N = 100 lattice pair, 64 batched energies, the continuous-batching service, and
 (--sweep) the s-wave build for M = N = 40..400.
 """
@@ -76,7 +77,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="measured length of the serving stream")
     ap.add_argument("--serve-warmup", type=float, default=5.0, help="warm-up length of the serving stream")
     ap.add_argument("--sweep", action="store_true", help="also time the s-wave P0 build for M = N in 40..400")
-    ap.add_argument("--only", choices=["batched", "serving", "swave", "sweep", "energy"], default=None,
+    ap.add_argument("--only", choices=["batched", "serving", "swave", "sweep", "energy", "jsum"], default=None,
                     help="run only this extra section (no headline step); for profiling runs")
     return ap.parse_args()
 
@@ -325,6 +326,43 @@ def energy_weights_section(wp, torch, V_R, Es, unit_lat, unit_g1_ms, reps=3):
                 amplitudes=amps, quartet_phase_deg_1_and_3_MeV_vs_M=conv)
 
 
+def jsum_section(wp, torch, V_R, M=100, two_J_max=17):
+    """Elastic nd observables over J^pi blocks (Sec. IV): every block 2J = 1 .. two_J_max of both
+    parities is a lattice of its own (pair waves j <= 1, 10-14 channels, M = N = 100, MT), built
+    and solved in FP64 at 13 and 35 MeV; dsigma/dOmega and A_y from the blocks' elastic S. Then the
+    channel-spin eigenphases of the J = 1/2+ and 3/2+ blocks at 3 MeV (below breakup)."""
+    from paper_1404_5253_amd.jsum import JBlocks
+    blocks = [(tJ, p) for tJ in range(1, two_J_max + 1, 2) for p in (1, -1)]
+    Es = [13.0, 35.0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    jb = JBlocks(blocks, M, M, j_max=1, kind="mt", V_R=V_R)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per_E, q0 = jb.solve(Es, "fp64", accept=1e-6)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    th_deg = np.array([10.0, 30.0, 60.0, 90.0, 120.0, 150.0, 170.0])
+    obs = {}
+    t3 = time.perf_counter()
+    for e, E in enumerate(Es):
+        ds, ay = wp.nd_elastic_observables(per_E[e], q0[e], np.radians(th_deg))
+        obs[str(E)] = dict(theta_deg=th_deg.tolist(), dsigma_dOmega_mb_sr=(10.0 * ds).tolist(), A_y=ay.tolist())
+    t4 = time.perf_counter()
+    low = JBlocks([(1, 1), (3, 1)], M, M, j_max=1, kind="mt", V_R=V_R)
+    lowE, _ = low.solve([3.0], "fp64", accept=1e-6)
+    eig = {}
+    for two_J, chans, S in lowE[0]:
+        sig, Ss = wp.nd_sigma_rep(two_J, chans, S)
+        d, _ = wp.nd_eigenphases(Ss)
+        eig[f"{two_J}/2+"] = dict(channels_lam_2Sigma=sig, eigenphases_deg=np.degrees(d).tolist())
+    n_ch = [L.nch for _, L in jb.lats]
+    return dict(blocks=len(blocks), M=M, N=M, j_max=1, channels_per_block=n_ch, E_lab=Es,
+                build_s=t1 - t0, solve_s=t2 - t1, solves=len(blocks) * len(Es),
+                solves_per_s=len(blocks) * len(Es) / (t2 - t1), observables_host_ms=(t4 - t3) * 1e3,
+                observables=obs, eigenphases_3MeV=eig)
+
+
 def swave_section(wp, torch, V_R, reps=10):
     """The s-wave Malfliet-Tjon lattice pair at M = N = 100 (doublet J = 1/2+, 2 channels, and
     quartet J = 3/2+, 1 channel; V_R seed 0): P0 build in FP64 and one FP64 solve at 14.1 MeV each,
@@ -557,6 +595,8 @@ def main():
             res, _ = swave_section(wp, torch, V_R)
         elif args.only == "sweep":
             res = sweep_section(wp, torch, V_R)
+        elif args.only == "jsum":
+            res = jsum_section(wp, torch, V_R)
         elif args.only == "energy":
             wl = workloads.WORKLOADS[WORKLOAD]
             sysd = wl["systems"][0]
@@ -676,6 +716,7 @@ def main():
         out["breakup"] = breakup_section(wp, torch, L, Es)
         g1u = prof.get("g1", (1, 0.0))
         out["energy_weights"] = energy_weights_section(wp, torch, V_R, Es, L, round(g1u[1] / max(1, g1u[0]), 4))
+        out["jsum_observables"] = jsum_section(wp, torch, V_R)
         sw, sw_lats = swave_section(wp, torch, V_R)
         out["swave_mt_100"] = sw
         out["batched_64_energies"] = batched_energies_section(wp, torch, sw_lats[0])

@@ -290,6 +290,40 @@ wp_status faddeev_series(const wp_solution* sol, int e_idx, int initial, int* n_
  */
 wp_status faddeev_breakup(const wp_solution* sol, int e_idx, int initial, int* n_cells, int* cells, double* U);
 
+/*
+ * Elastic nd observables from several J^pi blocks (Sec. IV). The elastic S of a block (amplitude(),
+ * n_open x n_open) is over its open channels (lam, I), the channels of wp_lattice_channels with the
+ * deuteron (l, s, j) = (0, 1, 1) as pair state, in that order: J = j (x) I, I = lam (x) 1/2.
+ *
+ * nd_sigma_rep: S in the channel-spin representation Sigma = s + sigma (Sec. IV, the I -> Sigma
+ * transformation, T[(lam, Sigma), (lam, I)] = sqrt((2I+1)(2Sigma+1)) (-1)^(J-I) {lam 1/2 I; j J Sigma},
+ * S_Sigma = T S T^T); the Sigma channels are, for each lam in ascending order, the Sigma in
+ * {1/2, 3/2} that couple to J (lam_s[n], two_Sigma[n]). In: two_J (odd), n (1..8), lam[n],
+ * two_I[n], S[2 n n] (re/im, row-major). Out (each may be NULL): lam_s, two_Sigma, S_sigma[2 n n].
+ * WP_EINVAL if the channels of a lam do not come as a whole shell (the count must match).
+ *
+ * nd_eigenphases: below breakup S is symmetric and unitary, S = O diag(exp(2 i delta)) O^T with O
+ * real orthogonal; delta[n] in radians and O[n n] (column k = eigenvector k, its largest component
+ * positive), ordered by the eigenvalues of Re S + 0.618 Im S. Either output may be NULL. Above
+ * breakup S is not unitary and the result only approximately diagonalises it.
+ *
+ * nd_elastic_observables: differential cross section (fm^2/sr) and neutron vector analysing power
+ * A_y at n_theta c.m. angles theta[] (radians), summed over n_blocks blocks: two_J[b], n_open[b],
+ * the blocks' lam, two_I and S (as above) concatenated in block order, k the nd relative momentum
+ * (fm^-1, the on-shell q0 of the solve). Amplitude in the channel-spin basis
+ * |Sigma nu, lam m; J M> = sum <Sigma nu lam m|J M> <j m_d 1/2 sigma|Sigma nu> (the states the
+ * printed transformation maps to), beam along z, outgoing direction (theta, phi = 0):
+ * M = (sqrt(pi)/(i k)) sum sqrt(2 lam + 1) <Sigma nu lam 0|J nu> <Sigma' nu' lam' nu-nu'|J nu>
+ * (S - 1) Y_lam'^(nu-nu'); dsdo = Tr(M M^+)/6, Ay = Tr(M sigma_y M^+)/Tr(M M^+) with sigma_y on the
+ * incoming neutron and y along k_in x k_out. Host FP64. Outputs may be NULL.
+ */
+wp_status nd_sigma_rep(int two_J, int n, const int* lam, const int* two_I, const double* S, int* lam_s,
+                       int* two_Sigma, double* S_sigma);
+wp_status nd_eigenphases(int n, const double* S, double* delta, double* O);
+wp_status nd_elastic_observables(int n_blocks, const int* two_J, const int* n_open, const int* lam, const int* two_I,
+                                 const double* S, double k, int n_theta, const double* theta, double* dsdo,
+                                 double* Ay);
+
 void wp_solution_free(wp_solution* sol);
 
 /*

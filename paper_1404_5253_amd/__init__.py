@@ -99,6 +99,9 @@ _SIGS = {
     "faddeev_series": (C.c_int, [_P, C.c_int, C.c_int, _I, _D]),
     "faddeev_breakup": (C.c_int, [_P, C.c_int, C.c_int, _I, _I, _D]),
     "wp_solution_free": (None, [_P]),
+    "nd_sigma_rep": (C.c_int, [C.c_int, C.c_int, _I, _I, _D, _I, _I, _D]),
+    "nd_eigenphases": (C.c_int, [C.c_int, _D, _D, _D]),
+    "nd_elastic_observables": (C.c_int, [C.c_int, _I, _I, _I, _I, _D, C.c_double, C.c_int, _D, _D, _D]),
     "faddeev_batch_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_SolveOpts), C.POINTER(_P)]),
     "faddeev_batch_admit": (C.c_int, [_P, C.c_double, _I]),
     "faddeev_batch_admit_many": (C.c_int, [_P, C.c_int, _D, _P, _I, _I]),
@@ -124,6 +127,62 @@ def _check(st):
 
 def _dptr(a):
     return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _iarr(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.int32))
+    return a, a.ctypes.data_as(_I)
+
+
+def _carr(S):
+    """Complex matrix -> contiguous re/im doubles."""
+    a = np.ascontiguousarray(np.asarray(S, dtype=np.complex128))
+    return a, a.ctypes.data_as(_D)
+
+
+def open_channels(channels):
+    """(lam, 2I) of a lattice's open elastic channels (deuteron (l, s, j) = (0, 1, 1)), in the order
+    of the amplitude matrices."""
+    return [(c[3], c[4]) for c in channels if c[0] == 0 and c[1] == 1 and c[2] == 1]
+
+
+def nd_sigma_rep(two_J, chans, S):
+    """(lam, 2 Sigma) channels and S in the channel-spin representation."""
+    n = len(chans)
+    lam, pl = _iarr([c[0] for c in chans])
+    tI, pI = _iarr([c[1] for c in chans])
+    Sa, pS = _carr(S)
+    ls, pls = _iarr(np.zeros(n))
+    ts, pts = _iarr(np.zeros(n))
+    out = np.zeros((n, n), dtype=np.complex128)
+    _check(_lib.nd_sigma_rep(two_J, n, pl, pI, pS, pls, pts, out.ctypes.data_as(_D)))
+    return list(zip(ls.tolist(), ts.tolist())), out
+
+
+def nd_eigenphases(S):
+    """Eigenphases (radians) and the real orthogonal O with S = O diag(exp(2 i delta)) O^T."""
+    Sa, pS = _carr(S)
+    n = Sa.shape[0]
+    d = np.zeros(n)
+    O = np.zeros((n, n))
+    _check(_lib.nd_eigenphases(n, pS, _dptr(d), _dptr(O)))
+    return d, O
+
+
+def nd_elastic_observables(blocks, k, thetas):
+    """dsigma/dOmega (fm^2/sr) and A_y at the angles thetas (radians) from blocks = [(two_J, chans, S)]
+    with chans the (lam, 2I) of S's rows (open_channels of the block's lattice)."""
+    tJ, ptJ = _iarr([b[0] for b in blocks])
+    no, pno = _iarr([len(b[1]) for b in blocks])
+    lam, pl = _iarr([c[0] for b in blocks for c in b[1]])
+    tI, pI = _iarr([c[1] for b in blocks for c in b[1]])
+    Sa, pS = _carr(np.concatenate([np.asarray(b[2], dtype=np.complex128).ravel() for b in blocks]))
+    th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64))
+    ds = np.zeros(len(th))
+    ay = np.zeros(len(th))
+    _check(_lib.nd_elastic_observables(len(blocks), ptJ, pno, pl, pI, pS, float(k), len(th), _dptr(th), _dptr(ds),
+                                       _dptr(ay)))
+    return ds, ay
 
 
 def exported_symbols():

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwpcd.so")
-SOURCES = ["host_math.cpp", "capi.cpp", "mixed.cpp", "batch.cpp", "kernels.hip", "kernels_mixed.hip", "noalloc.hip"]
+SOURCES = ["host_math.cpp", "capi.cpp", "mixed.cpp", "batch.cpp", "observables.cpp", "kernels.hip", "kernels_mixed.hip",
+           "noalloc.hip"]
 
 
 def hipcc() -> str:

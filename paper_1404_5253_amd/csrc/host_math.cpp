@@ -409,7 +409,7 @@ static double cg2(int j1, int m1, int j2, int m2, int J, int M) {
   return (double)(pre * s);
 }
 
-static double sixj2(int a, int b, int c, int d, int e, int f) {
+double sixj2(int a, int b, int c, int d, int e, int f) {
   // {a b c; d e f} by the Racah formula.
   if (!tri2(a, b, c) || !tri2(a, e, f) || !tri2(d, b, f) || !tri2(d, e, c)) return 0.0;
   long double pre = delta2(a, b, c) * delta2(a, e, f) * delta2(d, b, f) * delta2(d, e, c);

@@ -43,6 +43,9 @@ std::vector<double> h0_diagonal_energy(const std::vector<double>& edges, double 
 std::vector<double> yamaguchi_form_energy(const std::vector<double>& edges, double beta);
 std::vector<double> yukawa_wp_energy(const std::vector<double>& edges, int l, double mu);
 
+// Wigner 6j symbol {a b c; d e f} with doubled arguments (Racah formula).
+double sixj2(int a, int b, int c, int d, int e, int f);
+
 // Symmetric eigenproblem: Householder tridiagonalisation + implicit QL.
 // a (n x n row-major, destroyed) -> eigenvalues ascending in d, eigenvectors as ROWS of z.
 void sym_eigen(int n, std::vector<double>& a, std::vector<double>& d, std::vector<double>* z);
