@@ -73,7 +73,10 @@ typedef struct wp_batch wp_batch;
  *   grid_kind 1: explicit edges p_edges[M+1], q_edges[N+1], [0] = 0, strictly increasing.
  * Channels: l + s + t odd, T = 1/2 (two_T must be 1), (-1)^(l+lam) = parity, j <= j_max;
  * swave_only keeps l = lam = 0. Canonical order: sorted by (j, l, s, lam, 2I).
- * n_x, n_phi: Gauss-Legendre points of the (x, phi) rule of the P0 elements, 1..16 each.
+ * n_x, n_phi: Gauss-Legendre points of the (x, phi) rule of the P0 elements, 1..64 each with
+ * n_x * n_phi <= 256 (nodes per cell pair). Lattices with more than 8 moment integrals and more
+ * than 64 nodes (or a node count not a multiple of 4) take the moment + combine build, whose LDS
+ * holds about 220 nodes: above that perm_matrix_build fails.
  * Limits: 2 <= M, N <= 1024; at most 32 channels.
  */
 typedef struct {

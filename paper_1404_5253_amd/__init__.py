@@ -263,6 +263,8 @@ def faddeev_solve(lat, E_lab, mode=WP_SOLVE_FP64, tol=1e-12, accept=1e-7, max_it
     st = _lib.faddeev_solve(lat, len(E), _dptr(E), C.byref(o), stream, C.byref(h))
     if st == WP_ENOCONV and allow_noconv and h.value:
         return h, False
+    if st != WP_OK and h.value:   # the library hands back a solution with WP_ENOCONV; not wanted here
+        _lib.wp_solution_free(h)
     _check(st)
     return h, True
 

@@ -152,8 +152,9 @@ extern "C" wp_status wp_lattice_build(const wp_lattice_desc* d, const wp_allocat
   *out = nullptr;
   if (d->M < 2 || d->M > 1024 || d->N < 2 || d->N > 1024) return fail(WP_EINVAL, "M, N must be in [2, 1024]");
   if (d->two_T != 1) return fail(WP_EINVAL, "only T = 1/2 (two_T = 1) is supported");
-  if (d->n_x < 1 || d->n_x > 16 || d->n_phi < 1 || d->n_phi > 16)
-    return fail(WP_EINVAL, "n_x, n_phi must be in [1, 16]");
+  // the per-box quadrature kernels hold up to 256 nodes per cell pair
+  if (d->n_x < 1 || d->n_x > 64 || d->n_phi < 1 || d->n_phi > 64 || d->n_x * d->n_phi > 256)
+    return fail(WP_EINVAL, "n_x, n_phi must be in [1, 64] with n_x * n_phi <= 256");
   if (d->hbar2_over_m <= 0) return fail(WP_EINVAL, "hbar2_over_m must be positive");
   if (d->two_J < 1 || d->two_J % 2 == 0) return fail(WP_EINVAL, "two_J must be odd and positive");
   std::unique_ptr<wp_lattice> L(new (std::nothrow) wp_lattice());

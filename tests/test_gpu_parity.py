@@ -67,6 +67,10 @@ SPECS = {
     "doublet_mt_nodes144": pipeline.Spec(M=9, N=8, two_J=1, pot="mt", n_x=12, n_phi=12),
     # J = 3/2+ with j <= 2: 30 channels, more than the wide-batch kernel holds per lane
     "pw30_mt_4": pipeline.Spec(M=4, N=5, two_J=3, j_max=2, swave_only=False, pot="mt"),
+    # the largest rules: 64 x 4 = 256 nodes per pair (per-box node tables), and 48 x 4 nodes with
+    # 10 channels (the moment + combine build)
+    "quartet_yam_nodes64x4": pipeline.Spec(M=10, N=9, two_J=3, pot="yamaguchi", n_x=64, n_phi=4),
+    "pw10_mt_6_nodes48x4": pipeline.Spec(M=6, N=6, two_J=1, j_max=1, swave_only=False, pot="mt", n_x=48, n_phi=4),
 }
 
 

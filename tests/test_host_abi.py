@@ -134,3 +134,13 @@ def test_weights_call_order():
     assert b"before twobody_pseudostates" in wp._lib.wp_last_error()
     with pytest.raises(ValueError):
         wp.Lattice(8, 8, torch_alloc=False, weights="momentum")
+
+
+def test_rule_size_limits():
+    """n_x, n_phi in [1, 64] with at most 256 nodes per cell pair (the per-box kernels' limit)."""
+    wp.Lattice(6, 6, n_x=64, n_phi=4, torch_alloc=False)
+    wp.Lattice(6, 6, n_x=16, n_phi=16, torch_alloc=False)
+    for nx, nphi in ((65, 1), (20, 20), (0, 8)):
+        with pytest.raises(wp.WpError) as e:
+            wp.Lattice(6, 6, n_x=nx, n_phi=nphi, torch_alloc=False)
+        assert e.value.status == wp.WP_EINVAL
