@@ -282,6 +282,37 @@ static double ground_energy(const std::vector<double>& h0, const std::vector<dou
   return d[0];
 }
 
+// Unit-strength Yukawa matrices in the WP basis depend only on the p edges, l, mu and the weights,
+// not on the three-body block: lattices of several J^pi on one grid share them. A process-wide
+// cache (bounded; keyed by the exact edge values) saves recomputing them per lattice.
+static std::vector<double> yukawa_cached(const std::vector<double>& pe, int l, double mu, bool ew) {
+  struct Key {
+    std::vector<double> pe;
+    int l;
+    double mu;
+    bool ew;
+    bool operator<(const Key& o) const {
+      if (l != o.l) return l < o.l;
+      if (mu != o.mu) return mu < o.mu;
+      if (ew != o.ew) return ew < o.ew;
+      return pe < o.pe;
+    }
+  };
+  static std::mutex mu_cache;
+  static std::map<Key, std::vector<double>> cache;
+  Key k{pe, l, mu, ew};
+  {
+    std::lock_guard<std::mutex> lk(mu_cache);
+    auto it = cache.find(k);
+    if (it != cache.end()) return it->second;
+  }
+  std::vector<double> v = ew ? yukawa_wp_energy(pe, l, mu) : yukawa_wp(pe, l, mu);
+  std::lock_guard<std::mutex> lk(mu_cache);
+  if (cache.size() >= 64) cache.clear();
+  cache.emplace(std::move(k), v);
+  return v;
+}
+
 static std::vector<double> wave_potential(const wp_lattice* L, const wp_potential_desc* p, int l, int s, double strength) {
   const int M = L->M;
   std::vector<double> v((size_t)M * M, 0.0);
@@ -294,8 +325,8 @@ static std::vector<double> wave_potential(const wp_lattice* L, const wp_potentia
     }
     return v;
   }
-  auto YR = ew ? yukawa_wp_energy(L->pe, l, p->mu_R) : yukawa_wp(L->pe, l, p->mu_R);
-  auto YA = ew ? yukawa_wp_energy(L->pe, l, p->mu_A) : yukawa_wp(L->pe, l, p->mu_A);
+  auto YR = yukawa_cached(L->pe, l, p->mu_R, ew);
+  auto YA = yukawa_cached(L->pe, l, p->mu_A, ew);
   double VA = s == 1 ? strength : p->singlet_ratio * strength;
   for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];
   return v;
@@ -347,8 +378,8 @@ extern "C" wp_status twobody_pseudostates(wp_lattice* L, const wp_potential_desc
         };
         str = find_root(f, 1.0, 2000.0, 1e-15);
       } else {
-        auto YR = ew ? yukawa_wp_energy(L->pe, 0, p->mu_R) : yukawa_wp(L->pe, 0, p->mu_R);
-        auto YA = ew ? yukawa_wp_energy(L->pe, 0, p->mu_A) : yukawa_wp(L->pe, 0, p->mu_A);
+        auto YR = yukawa_cached(L->pe, 0, p->mu_R, ew);
+        auto YA = yukawa_cached(L->pe, 0, p->mu_A, ew);
         auto f = [&](double VA) {
           std::vector<double> v(YR.size());
           for (size_t e = 0; e < v.size(); ++e) v[e] = p->V_R * YR[e] - VA * YA[e];

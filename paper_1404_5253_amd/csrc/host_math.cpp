@@ -7,7 +7,9 @@
 #include <map>
 #include <queue>
 #include <stdexcept>
+#include <thread>
 #include <tuple>
+#include <vector>
 
 #include "wpcd_internal.h"
 
@@ -124,6 +126,23 @@ static double legendre_q(int l, double z) {
   return pref * sum / std::pow(2.0 * z, l + 1);
 }
 
+// Rows i = 0 .. M-1 on up to 16 host threads, interleaved (row i has M - i bin pairs); each row
+// writes only its own pairs (i, k >= i) and their mirror images, so the rows do not race.
+static void rows_parallel(size_t M, const std::function<void(size_t)>& row) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const size_t T = std::min<size_t>(hw, M);
+  if (T <= 1) {
+    for (size_t i = 0; i < M; ++i) row(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (size_t t = 0; t < T; ++t)
+    th.emplace_back([&, t] {
+      for (size_t i = t; i < M; i += T) row(i);
+    });
+  for (auto& x : th) x.join();
+}
+
 std::vector<double> yukawa_wp(const std::vector<double>& e, int l, double mu) {
   // Unit-strength Yukawa e^{-mu r}/r in partial wave l, free WP basis:
   // v_ii' = (d_i d_i')^{-1/2} int int p p' v_l(p,p') dp dp',  p p' v_l = Q_l(z) / pi,
@@ -155,7 +174,7 @@ std::vector<double> yukawa_wp(const std::vector<double>& e, int l, double mu) {
       W[i * ng + a] = h * gw[a];
     }
   }
-  for (size_t i = 0; i < M; ++i)
+  rows_parallel(M, [&](size_t i) {
     for (size_t k = i; k < M; ++k) {
       double s = 0.0;
       for (int a = 0; a < ng; ++a) {
@@ -172,6 +191,7 @@ std::vector<double> yukawa_wp(const std::vector<double>& e, int l, double mu) {
       v[i * M + k] = s;
       v[k * M + i] = s;
     }
+  });
   return v;
 }
 
@@ -230,7 +250,7 @@ std::vector<double> yukawa_wp_energy(const std::vector<double>& e, int l, double
   sqrt_nodes(e, ng, P, W);
   size_t M = e.size() - 1;
   std::vector<double> v(M * M);
-  for (size_t i = 0; i < M; ++i)
+  rows_parallel(M, [&](size_t i) {
     for (size_t k = i; k < M; ++k) {
       double s = 0.0;
       for (int a = 0; a < ng; ++a) {
@@ -248,6 +268,7 @@ std::vector<double> yukawa_wp_energy(const std::vector<double>& e, int l, double
       v[i * M + k] = s;
       v[k * M + i] = s;
     }
+  });
   return v;
 }
 
