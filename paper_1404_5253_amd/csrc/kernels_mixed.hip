@@ -295,12 +295,14 @@ __device__ __forceinline__ ArnLanes arn_lanes(int B) {
 
 // Sums the per-lane partials (hr, hi)[0 .. nv) of equal column over the lanes and waves of the
 // block (fixed order: wave, then row offset) into part[blk][i][c].
-__device__ __forceinline__ void arn_block_reduce(const double (&hr)[ARN_NV], const double (&hi)[ARN_NV], int nv,
+template <int NV>
+__device__ __forceinline__ void arn_block_reduce(const double (&hr)[NV], const double (&hi)[NV], int nv,
                                                  const ArnLanes& ln, int B, double2* __restrict__ part) {
   __shared__ double2 red[4][4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  static_assert(NV % 4 == 0, "partials are reduced four at a time");
 #pragma unroll
-  for (int i0 = 0; i0 < ARN_NV; i0 += 4) {
+  for (int i0 = 0; i0 < NV; i0 += 4) {
     if (i0 < nv) {   // uniform over the block
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wv][q][lane] = make_double2(hr[i0 + q], hi[i0 + q]);
@@ -321,10 +323,11 @@ __device__ __forceinline__ void arn_block_reduce(const double (&hr)[ARN_NV], con
   }
 }
 
+template <int NV>
 __device__ __forceinline__ void arn_dot_row(const float2* __restrict__ V, int64_t vstride, int nv, size_t idx,
-                                            float wr, float wi, double (&hr)[ARN_NV], double (&hi)[ARN_NV]) {
+                                            float wr, float wi, double (&hr)[NV], double (&hi)[NV]) {
 #pragma unroll
-  for (int q = 0; q < ARN_NV; ++q) {
+  for (int q = 0; q < NV; ++q) {
     if (q < nv) {
       const float2 v = V[(size_t)q * vstride + idx];
       hr[q] += (double)v.x * wr + (double)v.y * wi;
@@ -417,6 +420,9 @@ __global__ void __launch_bounds__(256) k_spmm_arn(int64_t cells, int B, const in
 }
 
 // Unfused variant (any B, any nch): w = V_j - kv with kv = P0 t from the general SpMM.
+// NV: basis slots held per lane (8 when the cycle has at most 8 Arnoldi steps, else ARN_NV): fewer
+// registers, more waves in flight for these bandwidth-bound passes.
+template <int NV>
 __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const float2* __restrict__ kv,
                                                   float2* __restrict__ V, int64_t vstride, int j,
                                                   const double* __restrict__ scl, double2* __restrict__ part) {
@@ -427,9 +433,9 @@ __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const flo
   float2* Wo = V + (size_t)(j + 1) * vstride;
   const float sj = (float)scl[(size_t)j * B + cl];
   const int nv = j + 1;
-  double hr[ARN_NV], hi[ARN_NV];
+  double hr[NV], hi[NV];
 #pragma unroll
-  for (int q = 0; q < ARN_NV; ++q) hr[q] = hi[q] = 0.0;
+  for (int q = 0; q < NV; ++q) hr[q] = hi[q] = 0.0;
   const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
   for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
     const size_t idx = (size_t)d * B + cl;
@@ -443,6 +449,7 @@ __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const flo
 
 // w -= sum_{i <= j} h_i V_i (FP64 arithmetic, FP32 storage) in basis slot j + 1, with the partial
 // sums of |w|^2 of the stored values.
+template <int NV>
 __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* __restrict__ V, int64_t vstride, int j,
                                                    const double2* __restrict__ h, const double* __restrict__ scl,
                                                    double2* __restrict__ part) {
@@ -450,9 +457,9 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
   const ArnLanes ln = arn_lanes(B);
   const int cl = ln.live ? ln.c : B - 1;
   const int nv = j + 1;
-  double cr[ARN_NV], ci[ARN_NV];
+  double cr[NV], ci[NV];
 #pragma unroll
-  for (int q = 0; q < ARN_NV; ++q) {
+  for (int q = 0; q < NV; ++q) {
     cr[q] = ci[q] = 0.0;
     if (q < nv) {
       const double sc = scl[(size_t)q * B + cl];
@@ -461,9 +468,9 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
     }
   }
   float2* Wo = V + (size_t)(j + 1) * vstride;
-  double acc[ARN_NV], dummy[ARN_NV];
+  double acc[4], dummy[4];
 #pragma unroll
-  for (int q = 0; q < ARN_NV; ++q) acc[q] = dummy[q] = 0.0;
+  for (int q = 0; q < 4; ++q) acc[q] = dummy[q] = 0.0;
   const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
   for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
     if (!ln.live) continue;
@@ -471,7 +478,7 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
     const float2 w = Wo[idx];
     double xr = w.x, xi = w.y;
 #pragma unroll
-    for (int q = 0; q < ARN_NV; ++q) {
+    for (int q = 0; q < NV; ++q) {
       if (q < nv) {
         const float2 v = V[(size_t)q * vstride + idx];
         xr -= cr[q] * v.x - ci[q] * v.y;
@@ -537,7 +544,7 @@ static void spmm_arn_launch(dim3 grid, hipStream_t s, int64_t cells, int B, cons
 }
 
 hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2* kv_scratch, hipStream_t s) {
-  if (a.j < 0 || a.j + 1 >= ARN_NV + 1 || a.B < 1 || a.nch < 1 || a.vstride < a.cells * a.nch * a.B)
+  if (a.j < 0 || a.j + 1 >= ARN_NV + 1 || a.j >= a.m || a.B < 1 || a.nch < 1 || a.vstride < a.cells * a.nch * a.B)
     return hipErrorInvalidValue;
   const int64_t rows = a.cells * a.nch;
   if (a.B >= 16 && a.nch <= 4) {
@@ -561,7 +568,11 @@ hipError_t launch_arnoldi_product(const ArnoldiArgs& a, const float2* t, float2*
     }
     ProfScope ps("arnoldi_dots", s);
     const dim3 grid = arn_grid(rows, a.B, a.nblk);
-    hipLaunchKernelGGL(k_sub_dots, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl, a.part);
+    if (a.m <= 8)
+      hipLaunchKernelGGL(k_sub_dots<8>, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl, a.part);
+    else
+      hipLaunchKernelGGL(k_sub_dots<ARN_NV>, grid, dim3(256), 0, s, rows, a.B, kv_scratch, a.V, a.vstride, a.j, a.scl,
+                         a.part);
     hipLaunchKernelGGL(k_arn_finish, dim3(((a.j + 1) * a.B + 3) / 4), dim3(256), 0, s, (int)grid.x, a.B, a.j + 1,
                        a.part, a.scl, a.H + (size_t)a.j * (a.m + 1) * a.B, nullptr, 0);
   }
@@ -573,7 +584,10 @@ hipError_t launch_arnoldi_orth(const ArnoldiArgs& a, hipStream_t s) {
   const int64_t rows = a.cells * a.nch;
   const dim3 grid = arn_grid(rows, a.B, a.nblk);
   const double2* hcol = a.H + (size_t)a.j * (a.m + 1) * a.B;
-  hipLaunchKernelGGL(k_orth_norm, grid, dim3(256), 0, s, rows, a.B, a.V, a.vstride, a.j, hcol, a.scl, a.part);
+  if (a.m <= 8)
+    hipLaunchKernelGGL(k_orth_norm<8>, grid, dim3(256), 0, s, rows, a.B, a.V, a.vstride, a.j, hcol, a.scl, a.part);
+  else
+    hipLaunchKernelGGL(k_orth_norm<ARN_NV>, grid, dim3(256), 0, s, rows, a.B, a.V, a.vstride, a.j, hcol, a.scl, a.part);
   hipLaunchKernelGGL(k_arn_finish, dim3((a.B + 3) / 4), dim3(256), 0, s, (int)grid.x, a.B, 1, a.part, a.scl,
                      a.H + ((size_t)a.j * (a.m + 1) + a.j + 1) * a.B, a.scl + (size_t)(a.j + 1) * a.B, 1);
   return hipGetLastError();
@@ -644,9 +658,9 @@ __global__ void __launch_bounds__(256) k_norm2_f64(int64_t rows, int B, const do
                                                    double2* __restrict__ part) {
   const int wv = threadIdx.x >> 6;
   const ArnLanes ln = arn_lanes(B);
-  double acc[ARN_NV], dummy[ARN_NV];
+  double acc[4], dummy[4];
 #pragma unroll
-  for (int q = 0; q < ARN_NV; ++q) acc[q] = dummy[q] = 0.0;
+  for (int q = 0; q < 4; ++q) acc[q] = dummy[q] = 0.0;
   const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
   if (ln.live)
     for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {

@@ -169,7 +169,7 @@ wp_status ensure_order(wp_lattice* L, hipStream_t s);   // SpMV row order of the
 inline const int32_t* spmv_order(const wp_lattice* L) { return L->nch > 4 ? L->d_order.p : nullptr; }
 
 // ------------------------------------------------------------------ mixed path (mixed.cpp)
-constexpr int kNblk = 512;   // workgroups of the column reductions
+constexpr int kNblk = 1024;   // workgroups of the column reductions (4 per CU)
 // device and host work space of the mixed refinement for B columns
 struct MixedWork {
   wp_lattice* L = nullptr;
