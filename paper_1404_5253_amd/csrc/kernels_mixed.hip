@@ -37,13 +37,21 @@ __global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const float2*
   constexpr int CC = 8 * CT;      // complex columns per block
   const int M = r.M, Mp = r.Mp, B = r.B, nch = r.nch;
   const int ncol = r.N * B;
-  const int g = blockIdx.y;
+  // Workgroups are dispatched round robin to the 8 XCDs by linear id. Each XCD is given a
+  // contiguous range of (channel, column tile) pairs instead, so that it reads the O and vO^T
+  // tables of two or three channels (which then stay in its L2) rather than those of every
+  // channel; the map is a bijection over the grid.
+  const int ntx = gridDim.x, T = ntx * gridDim.y;
+  const int lin = blockIdx.x + ntx * blockIdx.y;
+  const int xcd = lin & 7, per = T >> 3, extra = T & 7;
+  const int idx = xcd * per + min(xcd, extra) + (lin >> 3);
+  const int g = idx / ntx, tile = idx - g * ntx;
   const size_t woff = (size_t)r.wave[g] * Mp * Mp;
   const uint16_t* Oh = r.A + woff;
   const uint16_t* Ol = SPLIT ? r.A_lo + woff : nullptr;
   const uint16_t* Wh = r.W + woff;
   const uint16_t* Wl = SPLIT ? r.W_lo + woff : nullptr;
-  const int col0 = blockIdx.x * CC;
+  const int col0 = tile * CC;
   uint16_t* YT = shb;                      // [NP][RC][Mp], real column rc = 2 cc + part
   uint16_t* TT = shb + NP * RC * Mp;       // [NP][RC][Mp]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
