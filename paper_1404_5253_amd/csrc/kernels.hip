@@ -1531,11 +1531,18 @@ __global__ void __launch_bounds__(256) k_step64m(RotArgs r, const double* __rest
   constexpr int RC = 16 * CT, CC = 8 * CT, RCP = RC + 1;
   const int M = r.M, B = r.B, nch = r.nch;
   const int ncol = r.N * B;
-  const int g = blockIdx.y;
+  // XCD-aware order (workgroups go round robin to the 8 XCDs by linear id): each XCD takes a
+  // contiguous range of (channel, column tile) pairs, so it reads the O and vO^T tables of a few
+  // channels, which stay in its L2; the map is a bijection over the grid
+  const int ntx = gridDim.x, T = ntx * gridDim.y;
+  const int lin = blockIdx.x + ntx * blockIdx.y;
+  const int xcd = lin & 7, per = T >> 3, extra = T & 7;
+  const int idx = xcd * per + min(xcd, extra) + (lin >> 3);
+  const int g = idx / ntx, tile = idx - g * ntx;
   const size_t woff = (size_t)r.wave[g] * M * M;
   const double* O = r.A + woff;
   const double* W = Wm + woff;
-  const int col0 = blockIdx.x * CC;
+  const int col0 = tile * CC;
   double* YT = shd;              // [Mp][RCP]
   double* TT = shd + Mp * RCP;   // [Mp][RCP]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
