@@ -91,11 +91,18 @@ __global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const float2*
     f32x4 acc[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the A operand of the next tile is read while the current one is multiplied (the index is
+    // clamped at the last tile, so every read stays in the table)
+    const size_t arow = (size_t)(kt * 16 + rc) * Mp + 4 * quad;
+    bf16x4 ah_n = *reinterpret_cast<const bf16x4*>(Oh + arow), al_n;
+    if (SPLIT) al_n = *reinterpret_cast<const bf16x4*>(Ol + arow);
     for (int it = 0; it < nt; ++it) {
-      const size_t ao = (size_t)(kt * 16 + rc) * Mp + it * 16 + 4 * quad;
-      const bf16x4 ah = *reinterpret_cast<const bf16x4*>(Oh + ao);
+      const bf16x4 ah = ah_n;
       bf16x4 al;
-      if (SPLIT) al = *reinterpret_cast<const bf16x4*>(Ol + ao);
+      if (SPLIT) al = al_n;
+      const size_t an = arow + (size_t)min(it + 1, nt - 1) * 16;
+      ah_n = *reinterpret_cast<const bf16x4*>(Oh + an);
+      if (SPLIT) al_n = *reinterpret_cast<const bf16x4*>(Ol + an);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int bo = (ct * 16 + rc) * Mp + it * 16 + 4 * quad;
@@ -137,11 +144,16 @@ __global__ void __launch_bounds__(256) k_step_bf16(RotArgsMixed r, const float2*
     f32x4 acc[CT];
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const size_t wrow = (size_t)(itl * 16 + rc) * Mp + 4 * quad;
+    bf16x4 ah_n = *reinterpret_cast<const bf16x4*>(Wh + wrow), al_n;
+    if (SPLIT) al_n = *reinterpret_cast<const bf16x4*>(Wl + wrow);
     for (int kt = 0; kt < nt; ++kt) {
-      const size_t ao = (size_t)(itl * 16 + rc) * Mp + kt * 16 + 4 * quad;
-      const bf16x4 ah = *reinterpret_cast<const bf16x4*>(Wh + ao);
+      const bf16x4 ah = ah_n;
       bf16x4 al;
-      if (SPLIT) al = *reinterpret_cast<const bf16x4*>(Wl + ao);
+      if (SPLIT) al = al_n;
+      const size_t an = wrow + (size_t)min(kt + 1, nt - 1) * 16;
+      ah_n = *reinterpret_cast<const bf16x4*>(Wh + an);
+      if (SPLIT) al_n = *reinterpret_cast<const bf16x4*>(Wl + an);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const int bo = (ct * 16 + rc) * Mp + kt * 16 + 4 * quad;
