@@ -457,12 +457,40 @@ __global__ void __launch_bounds__(256) k_sub_dots(int64_t rows, int B, const flo
 #pragma unroll
   for (int q = 0; q < NV; ++q) hr[q] = hi[q] = 0.0;
   const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
-  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
-    const size_t idx = (size_t)d * B + cl;
-    const float2 v = Vj[idx], k = kv[idx];
-    const float wr = sj * v.x - k.x, wi = sj * v.y - k.y;
-    if (ln.live) Wo[idx] = make_float2(wr, wi);
-    if (ln.live) arn_dot_row(V, vstride, nv, idx, wr, wi, hr, hi);
+  // two rows per pass, all their reads issued before the store (the output slot shares the basis
+  // buffer, so the reads of a later row could not move above it); the sums take the rows in the
+  // same order as one row per pass
+  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += 2 * step) {
+    const bool two = d + step < rows;
+    const size_t i1 = (size_t)d * B + cl, i2 = (size_t)(two ? d + step : d) * B + cl;
+    const float2 v1 = Vj[i1], k1 = kv[i1], v2 = Vj[i2], k2 = kv[i2];
+    float2 b1[NV], b2[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (q < nv) {
+        b1[q] = V[(size_t)q * vstride + i1];
+        b2[q] = V[(size_t)q * vstride + i2];
+      }
+    const float w1r = sj * v1.x - k1.x, w1i = sj * v1.y - k1.y;
+    const float w2r = sj * v2.x - k2.x, w2i = sj * v2.y - k2.y;
+    if (ln.live) {
+      Wo[i1] = make_float2(w1r, w1i);
+      if (two) Wo[i2] = make_float2(w2r, w2i);
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+        if (q < nv) {
+          hr[q] += (double)b1[q].x * w1r + (double)b1[q].y * w1i;
+          hi[q] += (double)b1[q].x * w1i - (double)b1[q].y * w1r;
+        }
+      if (two) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+          if (q < nv) {
+            hr[q] += (double)b2[q].x * w2r + (double)b2[q].y * w2i;
+            hi[q] += (double)b2[q].x * w2i - (double)b2[q].y * w2r;
+          }
+      }
+    }
   }
   arn_block_reduce(hr, hi, nv, ln, B, part);
 }
@@ -492,22 +520,36 @@ __global__ void __launch_bounds__(256) k_orth_norm(int64_t rows, int B, float2* 
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = dummy[q] = 0.0;
   const int64_t step = (int64_t)gridDim.x * 4 * ln.R;
-  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += step) {
+  // two rows per pass, their reads before the stores, sums in row order (as in k_sub_dots)
+  for (int64_t d = ((int64_t)blockIdx.x * 4 + wv) * ln.R + ln.rsub; d < rows; d += 2 * step) {
     if (!ln.live) continue;
-    const size_t idx = (size_t)d * B + cl;
-    const float2 w = Wo[idx];
-    double xr = w.x, xi = w.y;
+    const bool two = d + step < rows;
+    const size_t i1 = (size_t)d * B + cl, i2 = (size_t)(two ? d + step : d) * B + cl;
+    const float2 w1 = Wo[i1], w2 = Wo[i2];
+    float2 b1[NV], b2[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (q < nv) {
+        b1[q] = V[(size_t)q * vstride + i1];
+        b2[q] = V[(size_t)q * vstride + i2];
+      }
+    double x1r = w1.x, x1i = w1.y, x2r = w2.x, x2i = w2.y;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       if (q < nv) {
-        const float2 v = V[(size_t)q * vstride + idx];
-        xr -= cr[q] * v.x - ci[q] * v.y;
-        xi -= cr[q] * v.y + ci[q] * v.x;
+        x1r -= cr[q] * b1[q].x - ci[q] * b1[q].y;
+        x1i -= cr[q] * b1[q].y + ci[q] * b1[q].x;
+        x2r -= cr[q] * b2[q].x - ci[q] * b2[q].y;
+        x2i -= cr[q] * b2[q].y + ci[q] * b2[q].x;
       }
     }
-    const float2 o = make_float2((float)xr, (float)xi);
-    Wo[idx] = o;
-    acc[0] += (double)o.x * o.x + (double)o.y * o.y;
+    const float2 o1 = make_float2((float)x1r, (float)x1i), o2 = make_float2((float)x2r, (float)x2i);
+    Wo[i1] = o1;
+    acc[0] += (double)o1.x * o1.x + (double)o1.y * o1.y;
+    if (two) {
+      Wo[i2] = o2;
+      acc[0] += (double)o2.x * o2.x + (double)o2.y * o2.y;
+    }
   }
   arn_block_reduce(acc, dummy, 1, ln, B, part);
 }
