@@ -32,3 +32,21 @@ def test_noalloc_resolvent_matches_allocating_entry_point():
             assert np.array_equal(got[a], ref[a]), (L.M, a)
     # the scratch array keeps the last call's contents: the big lattice again after the small one
     assert np.array_equal(big.resolvent_noalloc(14.1, 3), big.resolvent(14.1, 3))
+
+
+def test_noalloc_resolvent_energy_weights():
+    """The same with energy-weight packets (the closed-form G1 kernel, no work list), after a
+    unit-weight call has left its values in the scratch array."""
+    unit = _lattice(16, 3, 1, True)
+    L = wp.Lattice(20, 20, two_J=1, j_max=1, swave_only=False, weights="energy")
+    L.pseudostates(kind="mt", V_R=1438.72)
+    L.build_perm("fp64")
+    ref_unit = unit.resolvent(3.0, 0)   # makes the G1 tables resident (a documented precondition)
+    assert np.array_equal(unit.resolvent_noalloc(3.0, 0), ref_unit)
+    L.resolvent(3.0, 0)
+    for E_lab in (3.0, 22.7):
+        for a in (0, 4, 9):
+            n0 = L.alloc.n_alloc
+            got = L.resolvent_noalloc(E_lab, a)
+            assert L.alloc.n_alloc == n0
+            assert np.array_equal(got, L.resolvent(E_lab, a)), (E_lab, a)
