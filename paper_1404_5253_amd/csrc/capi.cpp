@@ -284,7 +284,8 @@ static double ground_energy(const std::vector<double>& h0, const std::vector<dou
 
 // Unit-strength Yukawa matrices in the WP basis depend only on the p edges, l, mu and the weights,
 // not on the three-body block: lattices of several J^pi on one grid share them. A process-wide
-// cache (bounded; keyed by the exact edge values) saves recomputing them per lattice.
+// cache (keyed by the exact edge values; emptied when it would exceed 256 MB of matrices) saves
+// recomputing them per lattice.
 static std::vector<double> yukawa_cached(const std::vector<double>& pe, int l, double mu, bool ew) {
   struct Key {
     std::vector<double> pe;
@@ -300,6 +301,8 @@ static std::vector<double> yukawa_cached(const std::vector<double>& pe, int l, d
   };
   static std::mutex mu_cache;
   static std::map<Key, std::vector<double>> cache;
+  static size_t cached_bytes = 0;
+  constexpr size_t kMaxBytes = (size_t)256 << 20;
   Key k{pe, l, mu, ew};
   {
     std::lock_guard<std::mutex> lk(mu_cache);
@@ -307,9 +310,14 @@ static std::vector<double> yukawa_cached(const std::vector<double>& pe, int l, d
     if (it != cache.end()) return it->second;
   }
   std::vector<double> v = ew ? yukawa_wp_energy(pe, l, mu) : yukawa_wp(pe, l, mu);
+  const size_t bytes = v.size() * sizeof(double);
+  if (bytes > kMaxBytes) return v;
   std::lock_guard<std::mutex> lk(mu_cache);
-  if (cache.size() >= 64) cache.clear();
-  cache.emplace(std::move(k), v);
+  if (cached_bytes + bytes > kMaxBytes) {
+    cache.clear();
+    cached_bytes = 0;
+  }
+  if (cache.emplace(std::move(k), v).second) cached_bytes += bytes;
   return v;
 }
 
