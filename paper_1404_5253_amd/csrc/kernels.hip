@@ -2647,14 +2647,14 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
           }
         }
         __syncthreads();
-        // items (rq, t) = rq * vpb + t over (4 candidates rq, stored value t), stepped without division
+        // items (t, rq) = t * nq + rq over (stored value t, 4 candidates rq): the lanes of one value
+        // are adjacent, so they read its coefficients once (broadcast) and its moments as one
+        // contiguous 128-byte row segment, and a wavefront walks 16 coefficient lists, not 64
         const int nq = (nr + 3) >> 2;
-        int rq = 0, t = tid;
-        while (t >= vpb) {
-          t -= vpb;
-          ++rq;
-        }
-        while (rq < nq) {
+        const int nitems = nq * vpb;
+        for (int item = tid; item < nitems; item += 256) {
+          const int t = nq == 4 ? item >> 2 : item / nq;
+          const int rq = item - t * nq;
           const int2 ce = CL ? s_cp[t] : make_int2(f.cptr[t], f.cptr[t + 1]);
           const double* mb = s_mom + 4 * rq;
           double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -2682,11 +2682,6 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
           if (r + 1 < nr) out[(int64_t)d4.y * vpb + t] = (OT)s1;
           if (r + 2 < nr) out[(int64_t)d4.z * vpb + t] = (OT)s2;
           if (r + 3 < nr) out[(int64_t)d4.w * vpb + t] = (OT)s3;
-          t += 256;
-          while (t >= vpb) {
-            t -= vpb;
-            ++rq;
-          }
         }
         __syncthreads();
       }
