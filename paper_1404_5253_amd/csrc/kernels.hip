@@ -2647,17 +2647,19 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
           }
         }
         __syncthreads();
-        // items (t, rq) = t * nq + rq over (stored value t, 4 candidates rq): the lanes of one value
+        // items (t, rq) = t * nq + rq over (stored value t, 8 candidates rq): the lanes of one value
         // are adjacent, so they read its coefficients once (broadcast) and its moments as one
-        // contiguous 128-byte row segment, and a wavefront walks 16 coefficient lists, not 64
-        const int nq = (nr + 3) >> 2;
+        // contiguous 128-byte row segment, and a wavefront walks 32 coefficient lists
+        const int nq = (nr + 7) >> 3;
         const int nitems = nq * vpb;
         for (int item = tid; item < nitems; item += 256) {
-          const int t = nq == 4 ? item >> 2 : item / nq;
+          const int t = nq == 2 ? item >> 1 : item;
           const int rq = item - t * nq;
           const int2 ce = CL ? s_cp[t] : make_int2(f.cptr[t], f.cptr[t + 1]);
-          const double* mb = s_mom + 4 * rq;
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+          const double* mb = s_mom + 8 * rq;
+          double sacc[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sacc[u] = 0.0;
           for (int c = ce.x; c < ce.y; ++c) {
             double cv;
             int m;
@@ -2669,19 +2671,17 @@ __global__ void __launch_bounds__(256, 2) k_pbuild_fused(PBuildArgs a, FusedArgs
               cv = f.cv[c];
               m = f.cm[c];
             }
-            const double2 x01 = *reinterpret_cast<const double2*>(mb + m * FZ_MT);
-            const double2 x23 = *reinterpret_cast<const double2*>(mb + m * FZ_MT + 2);
-            s0 = fma(cv, x01.x, s0);
-            s1 = fma(cv, x01.y, s1);
-            s2 = fma(cv, x23.x, s2);
-            s3 = fma(cv, x23.y, s3);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const double2 x = *reinterpret_cast<const double2*>(mb + m * FZ_MT + 2 * u);
+              sacc[2 * u] = fma(cv, x.x, sacc[2 * u]);
+              sacc[2 * u + 1] = fma(cv, x.y, sacc[2 * u + 1]);
+            }
           }
-          const int r = 4 * rq;
-          const int4 d4 = *reinterpret_cast<const int4*>(s_ld + r0 + r);
-          if (r < nr) out[(int64_t)d4.x * vpb + t] = (OT)s0;
-          if (r + 1 < nr) out[(int64_t)d4.y * vpb + t] = (OT)s1;
-          if (r + 2 < nr) out[(int64_t)d4.z * vpb + t] = (OT)s2;
-          if (r + 3 < nr) out[(int64_t)d4.w * vpb + t] = (OT)s3;
+          const int r = 8 * rq;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (r + u < nr) out[(int64_t)s_ld[r0 + r + u] * vpb + t] = (OT)sacc[u];
         }
         __syncthreads();
       }
