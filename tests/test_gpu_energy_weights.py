@@ -9,6 +9,8 @@ w(p) ~ sqrt(p), f(q) ~ sqrt(q)) through the C ABI, against the oracle.
 * FP64 solve: series terms and amplitudes to the unit-weight tolerances (tests/parity_util.py);
   S unitary below breakup.
 * Mixed path against the FP64 path: |dA| <= 1e-6.
+* Continuous batching (G1 per slot at admission): bit-identical alone and in a mix, FP64 and
+  split-BF16.
 """
 import numpy as np
 import pytest
@@ -130,3 +132,21 @@ def test_energy_mixed_matches_fp64(mode):
         assert np.max(np.abs(a["A"] - b["A"])) <= 1e-6, (mode, Es[k])
         compared += 1
     assert compared >= 2
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed_split"])
+def test_energy_batch_alone_equals_in_mix(mode):
+    """Continuous batching with energy-weight packets (each slot's closed-form G1 computed at
+    admission): a request's amplitude is bit-identical alone or among seven others, and agrees with
+    the plain solve."""
+    from test_gpu_parity import _run_batch
+    L = _lib_lattice(SPECS["doublet_mt_20"])
+    mix = [3.0, 14.1, 2.5, 40.0, 9.0, 22.7, 1.5, 33.0]
+    tol = 1e-12 if mode == "fp64" else 1e-8
+    together = _run_batch(L, mix, slots=8, mode=mode, tol=tol)
+    assert len(together) == len(mix)
+    for E in (3.0, 22.7):
+        alone = _run_batch(L, [E], slots=8, mode=mode, tol=tol)[E]
+        assert np.array_equal(alone["A"], together[E]["A"]), (mode, E)
+        solo = L.solve([E], mode, tol=tol, accept=1e-6).amplitude(0)
+        assert np.max(np.abs(alone["A"] - solo["A"])) <= (1e-8 if mode == "fp64" else 1e-6), (mode, E)
