@@ -581,7 +581,7 @@ def roofline(label, avg_s, L, B, nodes):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     # the oracle first, in forked worker processes, before anything touches the GPU
     cpu = None if (args.no_cpu_baseline or args.only) else cpu_baseline()
