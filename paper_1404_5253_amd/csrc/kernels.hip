@@ -383,7 +383,7 @@ hipError_t launch_select(const PBuildArgs& a, int* cnt, int* lo, hipStream_t s) 
   int nn = a.n_x * a.n_phi;
   if (nn < 1 || nn > 256 || a.M < 1 || a.M > 1024 || a.N < 1 || a.N > 1024) return hipErrorInvalidValue;
   size_t shmem = (a.M + 1) * sizeof(double) + (4 * nn + PHI_STRIDE * a.n_phi) * sizeof(double);
-  hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(128), shmem, s, a, cnt, lo);
+  hipLaunchKernelGGL(k_select, dim3(a.N * a.N), dim3(64), shmem, s, a, cnt, lo);
   return hipGetLastError();
 }
 
@@ -2707,7 +2707,7 @@ hipError_t launch_pflag(const PBuildArgs& a, const int* cnt, const int* lo, cons
                         uint8_t* flag, int64_t cap, double* geo, hipStream_t s) {
   const size_t sh = pflag_lds(a);
   if (sh > 64 * 1024 || !geo) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pflag, dim3(a.N * a.N), dim3(256), sh, s, a, cnt, lo, segoff, rowptr_c, flag, cap, geo);
+  hipLaunchKernelGGL(k_pflag, dim3(a.N * a.N), dim3(64), sh, s, a, cnt, lo, segoff, rowptr_c, flag, cap, geo);
   return hipGetLastError();
 }
 
